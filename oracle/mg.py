@@ -1,0 +1,126 @@
+"""Time-parallel multigrid with the damped block-Jacobi slab smoother.
+
+Oracle module (test infrastructure only).
+
+Section 3.1 (time-parallel multigrid): coarsening in time combines two
+consecutive slabs into one; the smoother is damped block Jacobi
+    u <- u + omega D^{-1} (f - L_h u),   D = diag(A_n),  omega = 1/2.
+The paper defers the remaining multigrid details to its references.  The
+readings used (and listed as such in the design notes):
+  * V(nu1, nu2) cycle, coarsening in time only, down to one slab (or an odd
+    slab count, which is then solved exactly by forward substitution);
+  * a coarse slab covers two fine slabs with the same number of time
+    elements and the same degree; prolongation P is the exact embedding of
+    the coarse slab space into the two fine slabs, computed here by an L2
+    projection (exact because the spaces are nested), restriction R = P^T;
+  * the coarse operator is the Galerkin product R L P, formed block-wise
+    from the fine A and B (all slabs of a level are identical);
+  * D^{-1} is applied exactly by sparse LU (the paper's "Direct" variant).
+The residual norm is the Euclidean norm of the coefficient vector, relative
+to ||f|| (zero initial guess), stopping at 1e-8 as in Section 4.4.
+"""
+import numpy as np
+import scipy.sparse as sp
+
+from . import bspline as bs
+from .spacetime import Axis
+from .solve import SlabSystem
+
+
+def time_prolongation(tau, n_el, p):
+    """P_t (2 N_t x N_t): coarse slab [0, 2 tau] -> fine slabs [0, tau] and
+    [tau, 2 tau], each with n_el elements of degree p.  Column j holds the
+    fine coefficients of coarse basis function j, found by solving the fine
+    mass-matrix system M_f c = (fine, coarse) with Gauss quadrature on the
+    fine elements (exact: coarse functions are polynomials there)."""
+    q = p + 2
+    coarse = bs.open_uniform_knots(0.0, 2 * tau, n_el, p)
+    blocks = []
+    for (a, b) in [(0.0, tau), (tau, 2 * tau)]:
+        ax = Axis(a, b, n_el, p, q)
+        N = ax.N
+        Mf = np.zeros((N, N))
+        rhs = np.zeros((N, bs.n_basis(coarse, p)))
+        for e in range(n_el):
+            g = ax.gidx[e]
+            Mf[np.ix_(g, g)] += np.einsum("q,qi,qj->ij", ax.W[e], ax.V[e], ax.V[e])
+            cvals = bs.basis_all(coarse, p, ax.X[e], 0)                  # (q, Nc)
+            rhs[g] += np.einsum("q,qi,qj->ij", ax.W[e], ax.V[e], cvals)
+        blocks.append(np.linalg.solve(Mf, rhs))
+    return np.vstack(blocks)
+
+
+class Level:
+    def __init__(self, system):
+        self.sys = system
+
+    @property
+    def S(self):
+        return self.sys.S
+
+
+class MultigridOracle:
+    def __init__(self, prob, nu1=1, nu2=1, omega=0.5, system=None):
+        self.prob = prob
+        self.nu1, self.nu2, self.omega = nu1, nu2, omega
+        fine = system if system is not None else SlabSystem.assemble(prob)
+        self.levels = [fine]
+        self.P = []
+        tau = prob.tau
+        Nx = prob.N_x
+        while self.levels[-1].S > 1 and self.levels[-1].S % 2 == 0:
+            lev = self.levels[-1]
+            Pt = time_prolongation(tau, prob.n_elem_t, prob.degree)
+            P = sp.kron(sp.csr_matrix(Pt), sp.identity(Nx), format="csr")
+            A, B = lev.A, lev.B
+            Z = sp.csr_matrix(A.shape)
+            Lpair = sp.bmat([[A, Z], [-B, A]], format="csr")
+            Epair = sp.bmat([[Z, B], [Z, Z]], format="csr")
+            Ac = (P.T @ Lpair @ P).tocsc()
+            Bc = (P.T @ Epair @ P).tocsr()
+            self.levels.append(SlabSystem(Ac, Bc, lev.S // 2))
+            self.P.append(P)
+            tau *= 2
+
+    # grid transfers --------------------------------------------------
+    def restrict(self, lvl, r):
+        P = self.P[lvl]
+        S = self.levels[lvl].S
+        R = r.reshape(S // 2, P.shape[0])
+        return (P.T @ R.T).T.ravel()
+
+    def prolong(self, lvl, e):
+        P = self.P[lvl]
+        S = self.levels[lvl + 1].S
+        E = e.reshape(S, P.shape[1])
+        return (P @ E.T).T.ravel()
+
+    # smoother -----------------------------------------------------------
+    def smooth(self, lvl, f, u, steps):
+        sysl = self.levels[lvl]
+        for _ in range(steps):
+            u = u + self.omega * sysl.slab_solve(sysl.residual(f, u))
+        return u
+
+    def vcycle(self, f, u, lvl=0):
+        sysl = self.levels[lvl]
+        if lvl == len(self.levels) - 1:
+            return sysl.forward_substitution(f)
+        u = self.smooth(lvl, f, u, self.nu1)
+        rc = self.restrict(lvl, sysl.residual(f, u))
+        ec = self.vcycle(rc, np.zeros_like(rc), lvl + 1)
+        u = u + self.prolong(lvl, ec)
+        u = self.smooth(lvl, f, u, self.nu2)
+        return u
+
+    def solve(self, f, rtol=1e-8, maxit=100, u0=None):
+        """Returns (u, iterations, history of relative residual norms)."""
+        u = np.zeros_like(f) if u0 is None else u0.copy()
+        fn = np.linalg.norm(f)
+        hist = [np.linalg.norm(self.levels[0].residual(f, u)) / fn]
+        it = 0
+        while hist[-1] > rtol and it < maxit:
+            u = self.vcycle(f, u)
+            it += 1
+            hist.append(np.linalg.norm(self.levels[0].residual(f, u)) / fn)
+        return u, it, hist
