@@ -1,0 +1,213 @@
+/*
+ * sth.h - C ABI of the MI355X (gfx950) space-time heat-equation slab solver.
+ *
+ * The library implements the hot path of the time-parallel multigrid of
+ * Hofer, Langer and Neumueller, "Robust Preconditioning for Space-Time
+ * Isogeometric Analysis of Parabolic Evolution Problems" (arXiv 1802.09277):
+ * the space-time dG-IgA system L_h u = f of the heat equation on the unit
+ * square or cube (eq. equ_linear_system: block lower bidiagonal, diagonal
+ * blocks A_n = K_t (x) M_x + M_t (x) K_x, sub-diagonal blocks -B_n with
+ * B_n = N_t (x) M_x, eq. structureAn), its residual, the damped block-Jacobi
+ * slab smoother (Section 3.1) whose slab inverses A_n^{-1} are applied
+ * through the decomposition eq. equ:ST:generalDecompA with the temporal
+ * generalized eigen decomposition (Section 3.3, in real 2x2-block form) and
+ * fast diagonalisation of the spatial spline pencils, time restriction and
+ * prolongation (two slabs -> one), the V-cycle and the solve loop.
+ *
+ * Conventions for every entry point:
+ *  - Vectors are caller-owned, contiguous FP64 device buffers of
+ *    sth_vector_len(h) elements, laid out u[slab][t][z][y][x] (x fastest;
+ *    the time index is the slower Kronecker index of eq. structureAn; only
+ *    the interior spatial B-splines are unknowns, u = 0 on the lateral
+ *    boundary).  The library never frees them.
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls are
+ *    stream-ordered and asynchronous unless stated otherwise.
+ *  - Every call returns an sth_status; on failure sth_last_error() gives a
+ *    thread-local message.  Invalid arguments return STH_EINVAL before any
+ *    allocation or launch.  Nothing throws across the ABI.
+ *  - Calls on one handle must not overlap in time (they share workspaces).
+ */
+#ifndef STH_H
+#define STH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sth_handle sth_handle;
+
+typedef enum {
+    STH_OK = 0,
+    STH_EINVAL = -1,    /* invalid argument or unsupported shape */
+    STH_ENOMEM = -2,    /* device allocation failed */
+    STH_EHIP = -3,      /* a HIP runtime call failed */
+    STH_ENOTPOS = -4,   /* M_t not positive, or a temporal eigenvalue with
+                           Re(lambda) <= 0 (the a-posteriori check of Section
+                           3.2: reduce theta) */
+    STH_ECOND = -5,     /* temporal eigenvector matrix too ill-conditioned
+                           for the diagonalisation path (Section 3.3, last
+                           paragraph; Table 1) */
+    STH_ENOCONV = -6,   /* NaN/Inf, residual growth, or maxit reached */
+    STH_ENODEV = -7     /* no usable GPU */
+} sth_status;
+
+typedef enum {
+    STH_FP64 = 0,       /* spatial eigenbasis transforms in FP64 (MFMA f64) */
+    STH_FP32 = 1,       /* transforms in FP32 MFMA, FP32 accumulation */
+    STH_BF16X3 = 2      /* transforms as 3 BF16 MFMA products (hi*hi, hi*lo,
+                           lo*hi), FP32 accumulation */
+} sth_prec;
+
+/* The discrete problem (Sections 2.1-2.3): unit square (dim 2) or cube
+ * (dim 3), open uniform knot vectors, degree `degree` in space and time,
+ * n_slabs equal slabs on (0,T), n_elem_t time elements per slab, SUPG
+ * parameter sigma = theta * (T / n_slabs / n_elem_t).  The multigrid
+ * coarsens in time only (two slabs -> one) while the slab count is even;
+ * the coarsest level is solved exactly by slab-wise forward substitution.
+ * omega is the damping of the block-Jacobi smoother (Section 3.1: 1/2),
+ * nu_pre / nu_post the smoothing steps of the V-cycle. */
+typedef struct {
+    int dim;            /* 2 or 3 */
+    int n_elem;         /* spatial elements per axis, >= 2 */
+    int degree;         /* 1..4 */
+    int n_slabs;        /* >= 1 */
+    int n_elem_t;       /* >= 1; N_t = n_elem_t + degree <= 8 */
+    double T;           /* > 0 */
+    double theta;       /* >= 0 */
+    double omega;       /* (0, 1] */
+    int nu_pre;         /* >= 0 */
+    int nu_post;        /* >= 0 */
+    int transform_prec; /* sth_prec */
+} sth_problem;
+
+/* Right-hand side as a sum of separable modes (host arrays):
+ *   f(x,t) = sum_m amp[m] prod_a sin(k[m*dim+a] pi x_a) cos(omega[m] pi t + phase[m]),
+ * zero initial data.  The load vector is l_h(phi_i) (Section 2.2) with a
+ * Gauss rule of degree+3 points per direction and element. */
+typedef struct {
+    int n_modes;
+    const double* amp;
+    const int* k;
+    const double* omega;
+    const double* phase;
+} sth_rhs_modes;
+
+/* Fills p with the defaults of Section 4.4: theta 0.01, omega 1/2, T 1,
+ * V(1,1), FP64 transforms (the shape fields are left at zero). */
+void sth_problem_default(sth_problem* p);
+
+/* Device bytes that sth_setup would allocate for this problem (factors,
+ * coarse-level vectors and workspaces; not the caller's vectors).  Host
+ * only, no allocation: used for admission by memory footprint. */
+int sth_workspace_bytes(const sth_problem* p, size_t* bytes);
+
+/* Host FP64 setup (1-D spline matrices, temporal pencils of every level,
+ * their eigen decompositions with the Re(lambda) > 0 and cond(V) guards,
+ * spatial fast-diagonalisation factors) and upload on `stream`.  On success
+ * *out owns device memory until sth_destroy.  Synchronises `stream`. */
+int sth_setup(const sth_problem* p, void* stream, sth_handle** out);
+
+/* n_slabs * N_t * n^dim (n = n_elem + degree - 2), or 0 for NULL. */
+size_t sth_vector_len(const sth_handle* h);
+
+/* Number of multigrid levels (1 + number of time coarsenings). */
+int sth_num_levels(const sth_handle* h);
+
+/* f <- load vector of the given modes (host 1-D quadrature, device outer
+ * products). */
+int sth_load_rhs(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream);
+
+/* y <- L_h u  (eq. equ_linear_system). */
+int sth_apply(sth_handle* h, const double* u, double* y, void* stream);
+
+/* r <- f - L_h u, i.e. r_n = f_n - A_n u_n + B_n u_{n-1} for all slabs. */
+int sth_residual(sth_handle* h, const double* f, const double* u, double* r, void* stream);
+
+/* z <- D^{-1} r with D = diag(A_n): every slab inverted independently by
+ * eq. equ:ST:generalDecompA (exact up to rounding for FP64 transforms). */
+int sth_block_solve(sth_handle* h, const double* r, double* z, void* stream);
+
+/* `steps` damped block-Jacobi steps u <- u + omega D^{-1}(f - L_h u). */
+int sth_smooth(sth_handle* h, const double* f, double* u, int steps, void* stream);
+
+/* One V(nu_pre, nu_post) cycle on the finest level, u updated in place. */
+int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream);
+
+/* V-cycles from the initial guess in u until ||f - L_h u||_2 <= rtol ||f||_2
+ * or maxit cycles.  Blocks the host (one scalar read per cycle).  iters and
+ * relres (may be NULL) receive the cycle count and the final relative
+ * residual.  Returns STH_ENOCONV on NaN, on growth over 3 consecutive
+ * cycles or when maxit is reached. */
+int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
+              int* iters, double* relres, void* stream);
+
+/* Level transfers (Section 3.1, time coarsening by combining two slabs):
+ * rc <- (P_t^T (x) I) r on slab pairs of `level` (rc has the slab count of
+ * level+1), and u <- u + (P_t (x) I) ec.  Vectors of a coarse level have
+ * sth_level_len(h, level) elements. */
+int sth_restrict(sth_handle* h, int level, const double* r, double* rc, void* stream);
+int sth_prolong_add(sth_handle* h, int level, const double* ec, double* u, void* stream);
+size_t sth_level_len(const sth_handle* h, int level);
+
+/* ||v||_2 of a level-0 vector with a reduction order fixed by the vector
+ * length only; the result is written to *out (host) after a stream sync. */
+int sth_norm(sth_handle* h, const double* v, double* out, void* stream);
+
+int sth_destroy(sth_handle* h);
+
+/* Thread-local message of the last failure in this thread. */
+const char* sth_last_error(void);
+
+/* ---- host-side introspection (no GPU needed) ------------------------- */
+
+/* Setup quantities of one level, copied into caller-provided host arrays
+ * (any pointer may be NULL).  n = interior functions per axis, N_t time
+ * functions per slab.
+ *   M1, K1  : n*n   1-D spatial mass / stiffness (row-major)
+ *   U, mu   : n*n, n  K1 U = M1 U diag(mu), U^T M1 U = I
+ *   Kt, Mt  : N_t*N_t temporal matrices of eq. TimeMatrices on this level
+ *   Pt      : 2N_t*N_t prolongation level -> level+1 (if level < levels-1)
+ *   V, W    : N_t*N_t real eigenvector block form, W = (M_t V)^{-1}, so
+ *             that W K_t V = Z (block diagonal) and W M_t V = I
+ *   eig_re, eig_im : N_t; a complex pair occupies two consecutive entries
+ *             with eig_im = +beta, -beta and Z block [[a, b], [-b, a]].
+ * Also returns cond(V) (2-norm) and the number of levels. */
+typedef struct {
+    int n, N_t, n_levels;
+    double cond_V;
+    double *M1, *K1, *U, *mu, *Kt, *Mt, *Pt, *V, *W, *eig_re, *eig_im;
+} sth_factors;
+int sth_host_factors(const sth_problem* p, int level, sth_factors* out);
+
+/* 1-D load vectors used by sth_load_rhs for one mode: time part per slab
+ * (n_slabs*N_t, test functions psi + sigma psi') and spatial part per axis
+ * (n, interior functions). */
+int sth_host_load_1d(const sth_problem* p, double omega, double phase, int k,
+                     double* time_part, double* space_part);
+
+/* ---- kernel timing (measurement support) ----------------------------- */
+
+/* Kernel classes timed with HIP events when timing is enabled. */
+typedef enum {
+    STH_K_RESIDUAL = 0, STH_K_XFORM_X = 1, STH_K_XFORM_S = 2, STH_K_TIMEMIX = 3,
+    STH_K_RESTRICT = 4, STH_K_PROLONG = 5, STH_K_NORM = 6, STH_K_OTHER = 7,
+    STH_K_COUNT = 8
+} sth_kernel_class;
+
+/* Start (enable=1) or stop (0) recording an event pair around every launch
+ * on this handle; starting clears previous records. */
+int sth_timing(sth_handle* h, int enable);
+
+/* Totals over the recorded launches of one class: launches, summed kernel
+ * time in ms, summed algorithmic FLOPs and HBM bytes (the minimum traffic
+ * of the operation: every input read once, every output written once).
+ * Synchronises on the recorded events. */
+int sth_timing_report(sth_handle* h, int kclass, int* launches, double* ms,
+                      double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STH_H */

@@ -1,0 +1,559 @@
+// gfx950 kernels of the space-time slab solver.
+//
+//  * k_residual  : r_n = f_n - A_n u_n + B_n u_{n-1} (eq. equ_linear_system,
+//                  A_n = K_t (x) M_x + M_t (x) K_x, B_n = N_t (x) M_x with
+//                  N_t = e_1 e_{N_t}^T, eq. structureAn) by sum factorisation:
+//                  banded 1-D passes of M_1/K_1 through LDS per time row,
+//                  then the dense N_t x N_t contraction in registers.
+//  * k_xform_x / k_xform_s : the spatial eigenbasis transforms of the slab
+//                  inverse (eq. equ:ST:generalDecompA with fast
+//                  diagonalisation of K_x + lambda M_x) as FP64 MFMA GEMMs
+//                  (v_mfma_f64_16x16x4), contiguous or strided axis.
+//  * k_timemix   : per spatial mode, W, the shifted 1x1 / 2x2 divide by
+//                  (Z + mu I), and V (Section 3.3 in real block form).
+//  * k_restrict / k_prolong : time transfers between two fine slabs and one
+//                  coarse slab (Section 3.1).
+//  * k_norm2_*   : fixed-order two-stage sum of squares.
+#include "kernels.hpp"
+
+namespace sth {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// residual
+// ---------------------------------------------------------------------------
+template <int DIM> struct ResTile;
+template <> struct ResTile<2> { static constexpr int TX = 32, TY = 8, TZ = 1; };
+template <> struct ResTile<3> { static constexpr int TX = 8, TY = 8, TZ = 4; };
+
+constexpr int kMaxP = 4;
+constexpr int kBand = 2 * kMaxP + 1;
+
+template <int DIM, int NT>
+__global__ __launch_bounds__(256) void k_residual(int p, int n, const double* __restrict__ M1b,
+                                                  const double* __restrict__ K1b, TimeOp op,
+                                                  const double* __restrict__ f,
+                                                  const double* __restrict__ u, double* __restrict__ r,
+                                                  long s0, double sign, int tiles_x, int tiles_y) {
+    using Tl = ResTile<DIM>;
+    constexpr int TX = Tl::TX, TY = Tl::TY, TZ = Tl::TZ;
+    constexpr int HXM = TX + 2 * kMaxP, HYM = TY + 2 * kMaxP, HZM = (DIM == 3) ? TZ + 2 * kMaxP : 1;
+    __shared__ double Us[HZM * HYM * HXM];
+    __shared__ double As[HZM * HYM * TX];
+    __shared__ double Bs[HZM * HYM * TX];
+    __shared__ double Cs[(DIM == 3) ? HZM * TY * TX : 1];
+    __shared__ double Ds[(DIM == 3) ? HZM * TY * TX : 1];
+    __shared__ double bxM[TX * kBand], bxK[TX * kBand], byM[TY * kBand], byK[TY * kBand];
+    __shared__ double bzM[TZ * kBand], bzK[TZ * kBand];
+
+    const int tid = threadIdx.x;
+    const int B = 2 * p + 1;
+    const int HX = TX + 2 * p, HY = TY + 2 * p, HZ = (DIM == 3) ? TZ + 2 * p : 1;
+    int tile = blockIdx.x;
+    const int tx = tile % tiles_x;
+    tile /= tiles_x;
+    const int ty = tile % tiles_y;
+    const int tz = tile / tiles_y;
+    const int gx0 = tx * TX, gy0 = ty * TY, gz0 = tz * TZ;
+    const long s = s0 + blockIdx.y;
+    long Nx = (long)n * n;
+    if (DIM == 3) Nx *= n;
+    const long slab_len = NT * Nx;
+
+    // band rows of the tile
+    for (int i = tid; i < TX * B; i += 256) {
+        int lx = i / B, k = i % B, gx = gx0 + lx;
+        bxM[lx * kBand + k] = (gx < n) ? M1b[(long)gx * B + k] : 0.0;
+        bxK[lx * kBand + k] = (gx < n) ? K1b[(long)gx * B + k] : 0.0;
+    }
+    for (int i = tid; i < TY * B; i += 256) {
+        int ly = i / B, k = i % B, gy = gy0 + ly;
+        byM[ly * kBand + k] = (gy < n) ? M1b[(long)gy * B + k] : 0.0;
+        byK[ly * kBand + k] = (gy < n) ? K1b[(long)gy * B + k] : 0.0;
+    }
+    if (DIM == 3) {
+        for (int i = tid; i < TZ * B; i += 256) {
+            int lz = i / B, k = i % B, gz = gz0 + lz;
+            bzM[lz * kBand + k] = (gz < n) ? M1b[(long)gz * B + k] : 0.0;
+            bzK[lz * kBand + k] = (gz < n) ? K1b[(long)gz * B + k] : 0.0;
+        }
+    }
+
+    const int lx = tid % TX, ly = (tid / TX) % TY, lz = tid / (TX * TY);
+    const int gx = gx0 + lx, gy = gy0 + ly, gz = gz0 + lz;
+    const bool own = gx < n && gy < n && (DIM == 2 || gz < n);
+
+    double acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+
+    for (int tr = 0; tr <= NT; ++tr) {
+        const double* src;
+        if (tr < NT) {
+            src = u + s * slab_len + (long)tr * Nx;
+        } else {
+            if (s == 0) break;
+            src = u + (s - 1) * slab_len + (long)(NT - 1) * Nx;   // end trace of slab n-1
+        }
+        __syncthreads();
+        for (int i = tid; i < HZ * HY * HX; i += 256) {
+            int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+            int x = gx0 - p + hx, y = gy0 - p + hy, z = gz0 - p + hz;
+            double v = 0.0;
+            if (x >= 0 && x < n && y >= 0 && y < n && (DIM == 2 || (z >= 0 && z < n))) {
+                long off = (DIM == 3) ? ((long)z * n + y) * n + x : (long)y * n + x;
+                v = src[off];
+            }
+            Us[(hz * HYM + hy) * HXM + hx] = v;
+        }
+        __syncthreads();
+        // x pass: A = M1 u, B = K1 u along x
+        for (int i = tid; i < HZ * HY * TX; i += 256) {
+            int ix = i % TX, hy = (i / TX) % HY, hz = i / (TX * HY);
+            const double* row = &Us[(hz * HYM + hy) * HXM + ix];
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < B; ++k) {
+                a += bxM[ix * kBand + k] * row[k];
+                b += bxK[ix * kBand + k] * row[k];
+            }
+            As[(hz * HYM + hy) * TX + ix] = a;
+            Bs[(hz * HYM + hy) * TX + ix] = b;
+        }
+        __syncthreads();
+        double Mu = 0.0, Ku = 0.0;
+        if (DIM == 2) {
+            for (int k = 0; k < B; ++k) {
+                double a = As[(ly + k) * TX + lx], b = Bs[(ly + k) * TX + lx];
+                Mu += byM[ly * kBand + k] * a;
+                Ku += byK[ly * kBand + k] * a + byM[ly * kBand + k] * b;
+            }
+        } else {
+            // y pass: C = M1y A, D = K1y A + M1y B
+            for (int i = tid; i < HZ * TY * TX; i += 256) {
+                int ix = i % TX, iy = (i / TX) % TY, hz = i / (TX * TY);
+                double c = 0.0, d = 0.0;
+                for (int k = 0; k < B; ++k) {
+                    double a = As[(hz * HYM + iy + k) * TX + ix], b = Bs[(hz * HYM + iy + k) * TX + ix];
+                    c += byM[iy * kBand + k] * a;
+                    d += byK[iy * kBand + k] * a + byM[iy * kBand + k] * b;
+                }
+                Cs[(hz * TY + iy) * TX + ix] = c;
+                Ds[(hz * TY + iy) * TX + ix] = d;
+            }
+            __syncthreads();
+            for (int k = 0; k < B; ++k) {
+                double c = Cs[((lz + k) * TY + ly) * TX + lx], d = Ds[((lz + k) * TY + ly) * TX + lx];
+                Mu += bzM[lz * kBand + k] * c;
+                Ku += bzK[lz * kBand + k] * c + bzM[lz * kBand + k] * d;
+            }
+        }
+        if (tr < NT) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] -= op.Kt[t * kNt + tr] * Mu + op.Mt[t * kNt + tr] * Ku;
+        } else {
+            acc[0] += Mu;
+        }
+    }
+    if (!own) return;
+    long pt = (DIM == 3) ? ((long)gz * n + gy) * n + gx : (long)gy * n + gx;
+    double* rs = r + s * slab_len + pt;
+    const double* fs = f ? f + s * slab_len + pt : nullptr;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) rs[(long)t * Nx] = (fs ? fs[(long)t * Nx] : 0.0) + sign * acc[t];
+}
+
+template <int DIM>
+static hipError_t residual_dim(int Nt, int p, int n, const double* M1b, const double* K1b,
+                               const TimeOp& op, const double* f, const double* u, double* r,
+                               long s0, long ns, double sign, hipStream_t st) {
+    using Tl = ResTile<DIM>;
+    int tiles_x = (n + Tl::TX - 1) / Tl::TX, tiles_y = (n + Tl::TY - 1) / Tl::TY;
+    int tiles_z = (DIM == 3) ? (n + Tl::TZ - 1) / Tl::TZ : 1;
+    dim3 grid(tiles_x * tiles_y * tiles_z, (unsigned)ns);
+#define STH_RES_CASE(NTV)                                                                          \
+    case NTV:                                                                                      \
+        hipLaunchKernelGGL((k_residual<DIM, NTV>), grid, dim3(256), 0, st, p, n, M1b, K1b, op, f, \
+                           u, r, s0, sign, tiles_x, tiles_y);                                      \
+        break;
+    switch (Nt) {
+        STH_RES_CASE(2) STH_RES_CASE(3) STH_RES_CASE(4) STH_RES_CASE(5)
+        STH_RES_CASE(6) STH_RES_CASE(7) STH_RES_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_RES_CASE
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
+                           const TimeOp& op, const double* f, const double* u, double* r,
+                           long s0, long ns, double sign, hipStream_t st) {
+    if (ns <= 0) return hipSuccess;
+    if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
+    if (dim == 2) return residual_dim<2>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+    if (dim == 3) return residual_dim<3>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// spatial eigenbasis transforms (FP64 MFMA 16x16x4)
+//   lane l supplies A[l%16][l/16] and B[l/16][l%16]; the 4 accumulator
+//   values of lane l hold D[l/16 + 4r][l%16], r = 0..3.
+// ---------------------------------------------------------------------------
+template <int EPI>
+__global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, double* __restrict__ out,
+                                                 const double* __restrict__ T, int n, int np, long lines,
+                                                 double alpha) {
+    __shared__ double in_s[64][17];
+    __shared__ double T_s[16][130];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long line0 = (long)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 128;
+    const int njt = min(8, (np - j0) / 16);
+    d4 acc[8];
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) acc[jt] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+            int l = i >> 4, kk = i & 15;
+            long line = line0 + l;
+            int k = k0 + kk;
+            in_s[l][kk] = (line < lines && k < n) ? in[line * n + k] : 0.0;
+        }
+        for (int i = threadIdx.x; i < 16 * 128; i += 256) {
+            int kk = i >> 7, jj = i & 127;
+            int j = j0 + jj;
+            T_s[kk][jj] = (j < np) ? T[(long)(k0 + kk) * np + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            double a = in_s[wave * 16 + (lane & 15)][kq * 4 + (lane >> 4)];
+#pragma unroll
+            for (int jt = 0; jt < 8; ++jt) {
+                if (jt < njt) {
+                    double b = T_s[kq * 4 + (lane >> 4)][jt * 16 + (lane & 15)];
+                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) {
+        if (jt >= njt) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            long line = line0 + wave * 16 + (lane >> 4) + 4 * rr;
+            int j = j0 + jt * 16 + (lane & 15);
+            if (line < lines && j < n) {
+                double v = acc[jt][rr];
+                double* o = out + line * n + j;
+                if (EPI == 0) *o = v;
+                else if (EPI == 1) *o += alpha * v;
+                else *o = alpha * v;
+            }
+        }
+    }
+}
+
+hipError_t launch_xform_x(int epi, const double* in, double* out, const double* T, int n, int np,
+                          long lines, double alpha, hipStream_t st) {
+    if (lines <= 0) return hipSuccess;
+    dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
+    if (epi == 0) hipLaunchKernelGGL(k_xform_x<0>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    else if (epi == 1) hipLaunchKernelGGL(k_xform_x<1>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    else hipLaunchKernelGGL(k_xform_x<2>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, double* __restrict__ out,
+                                                 const double* __restrict__ T, int n, int np, long inner,
+                                                 int nib, int njb) {
+    __shared__ double in_s[16][66];
+    __shared__ double T_s[16][66];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    long bid = blockIdx.x;
+    const int ib = (int)(bid % nib);
+    bid /= nib;
+    const int jb = (int)(bid % njb);
+    const long b = bid / njb;
+    const long i0 = (long)ib * 64;
+    const int j0 = jb * 64;
+    const double* inb = in + b * (long)n * inner;
+    double* outb = out + b * (long)n * inner;
+    const bool active = (j0 + wave * 16) < np;
+    d4 acc[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) acc[it] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        for (int i = threadIdx.x; i < 16 * 64; i += 256) {
+            int kk = i >> 6, ii = i & 63;
+            int k = k0 + kk;
+            long ig = i0 + ii;
+            in_s[kk][ii] = (k < n && ig < inner) ? inb[(long)k * inner + ig] : 0.0;
+            int j = j0 + ii;
+            T_s[kk][ii] = (j < np) ? T[(long)k * np + j] : 0.0;
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) {
+                double a = T_s[kq * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+                for (int it = 0; it < 4; ++it) {
+                    double bb = in_s[kq * 4 + (lane >> 4)][it * 16 + (lane & 15)];
+                    acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[it], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            int j = j0 + wave * 16 + (lane >> 4) + 4 * rr;
+            long ig = i0 + it * 16 + (lane & 15);
+            if (j < n && ig < inner) outb[(long)j * inner + ig] = acc[it][rr];
+        }
+    }
+}
+
+hipError_t launch_xform_s(const double* in, double* out, const double* T, int n, int np,
+                          long nbatch, long inner, hipStream_t st) {
+    if (nbatch <= 0) return hipSuccess;
+    int nib = (int)((inner + 63) / 64), njb = (np + 63) / 64;
+    long blocks = nbatch * nib * njb;
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_xform_s, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner, nib, njb);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// temporal transform and shifted divide
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
+                                                 long Nx, const double* __restrict__ in,
+                                                 double* __restrict__ out, long total) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    int jx = (int)(m % n);
+    long rest = m / n;
+    int jy = (int)(rest % n);
+    double mu = mu1[jx] + mu1[jy];
+    if (dim == 3) mu += mu1[rest / n];
+    const double* g = in + s * NT * Nx + m;
+    double h[NT], y[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) h[t] = 0.0;
+#pragma unroll
+    for (int t2 = 0; t2 < NT; ++t2) {
+        double v = g[(long)t2 * Nx];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) h[t] += tm.W[t * kNt + t2] * v;
+    }
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        if (tm.kind[k] == 0) {
+            y[k] = h[k] / (tm.re[k] + mu);
+        } else if (tm.kind[k] == 1 && k + 1 < NT) {
+            double a = tm.re[k] + mu, b = tm.im[k];
+            double det = a * a + b * b;
+            y[k] = (a * h[k] - b * h[k + 1]) / det;
+            y[k + 1] = (b * h[k] + a * h[k + 1]) / det;
+        }
+    }
+    double* o = out + s * NT * Nx + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double z = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) z += tm.V[t * kNt + k] * y[k];
+        o[(long)t * Nx] = z;
+    }
+}
+
+hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
+                          const double* in, double* out, long S, hipStream_t st) {
+    long Nx = (long)n * n * (dim == 3 ? n : 1);
+    long total = S * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+#define STH_TM_CASE(NTV)                                                                         \
+    case NTV:                                                                                    \
+        hipLaunchKernelGGL(k_timemix<NTV>, grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out, \
+                           total);                                                               \
+        break;
+    switch (Nt) {
+        STH_TM_CASE(2) STH_TM_CASE(3) STH_TM_CASE(4) STH_TM_CASE(5)
+        STH_TM_CASE(6) STH_TM_CASE(7) STH_TM_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_TM_CASE
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// time transfers
+// ---------------------------------------------------------------------------
+template <int NT>
+__global__ __launch_bounds__(256) void k_restrict(Transfer tr, const double* __restrict__ r,
+                                                  double* __restrict__ rc, long Sc, long Nx) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= Sc * Nx) return;
+    long m = idx / Nx, x = idx % Nx;
+    const double* a = r + (2 * m) * NT * Nx + x;    // slabs 2m and 2m+1 are contiguous
+    double acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2 * NT; ++t) {
+        double v = a[(long)t * Nx];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] += tr.P[t * kNt + c] * v;
+    }
+    double* o = rc + m * NT * Nx + x;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) o[(long)c * Nx] = acc[c];
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_prolong(Transfer tr, const double* __restrict__ e,
+                                                 double* __restrict__ u, long Sc, long Nx) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= Sc * Nx) return;
+    long m = idx / Nx, x = idx % Nx;
+    const double* ec = e + m * NT * Nx + x;
+    double c[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) c[k] = ec[(long)k * Nx];
+    double* o = u + (2 * m) * NT * Nx + x;
+#pragma unroll
+    for (int t = 0; t < 2 * NT; ++t) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) v += tr.P[t * kNt + k] * c[k];
+        o[(long)t * Nx] += v;
+    }
+}
+
+#define STH_TR_SWITCH(KER, ...)                                                        \
+    switch (Nt) {                                                                      \
+        case 2: hipLaunchKernelGGL(KER<2>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        case 3: hipLaunchKernelGGL(KER<3>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        case 4: hipLaunchKernelGGL(KER<4>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        case 5: hipLaunchKernelGGL(KER<5>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        case 6: hipLaunchKernelGGL(KER<6>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        case 7: hipLaunchKernelGGL(KER<7>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        case 8: hipLaunchKernelGGL(KER<8>, grid, dim3(256), 0, st, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                          \
+    }
+
+hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,
+                           long Nx, hipStream_t st) {
+    long total = Sc * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_TR_SWITCH(k_restrict, tr, r, rc, Sc, Nx)
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u, long Sc,
+                          long Nx, hipStream_t st) {
+    long total = Sc * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_TR_SWITCH(k_prolong, tr, e, u, Sc, Nx)
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// misc
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill(double* v, long len, double val) {
+    long stride = (long)gridDim.x * 256;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) v[i] = val;
+}
+
+hipError_t launch_fill(double* v, long len, double val, hipStream_t st) {
+    if (len <= 0) return hipSuccess;
+    long blocks = (len + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, v, len, val);
+    return hipGetLastError();
+}
+
+__device__ inline double block_sum_256(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_norm2_partial(const double* __restrict__ v, long len, long chunk,
+                                                       double* __restrict__ partial) {
+    __shared__ double sh[256];
+    long beg = (long)blockIdx.x * chunk;
+    long end = beg + chunk < len ? beg + chunk : len;
+    double s = 0.0;
+    for (long i = beg + threadIdx.x; i < end; i += 256) s += v[i] * v[i];
+    double tot = block_sum_256(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_norm2_final(const double* __restrict__ partial, double* out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < kNormBlocks; i += 256) s += partial[i];
+    double tot = block_sum_256(s, sh);
+    if (threadIdx.x == 0) out[0] = tot;
+}
+
+hipError_t launch_norm2(const double* v, long len, double* partial, double* out, hipStream_t st) {
+    long chunk = (len + kNormBlocks - 1) / kNormBlocks;
+    if (chunk < 1) chunk = 1;
+    hipLaunchKernelGGL(k_norm2_partial, dim3(kNormBlocks), dim3(256), 0, st, v, len, chunk, partial);
+    hipLaunchKernelGGL(k_norm2_final, dim3(1), dim3(256), 0, st, partial, out);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_rhs(int dim, int Nt, int n, int n_modes,
+                                             const double* __restrict__ Tpart,
+                                             const double* __restrict__ Xpart, double* __restrict__ f,
+                                             long S, long Nx) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    long total = S * Nt * Nx;
+    if (idx >= total) return;
+    long st = idx / Nx, m = idx % Nx;        // st = s*Nt + t
+    int jx = (int)(m % n);
+    long rest = m / n;
+    int jy = (int)(rest % n);
+    int jz = (int)(rest / n);
+    double v = 0.0;
+    for (int q = 0; q < n_modes; ++q) {
+        const double* X = Xpart + (long)q * 3 * n;
+        double term = Tpart[(long)q * S * Nt + st] * X[jx] * X[n + jy];
+        if (dim == 3) term *= X[2 * n + jz];
+        v += term;
+    }
+    f[idx] = v;
+}
+
+hipError_t launch_rhs(int dim, int Nt, int n, int n_modes, const double* Tpart, const double* Xpart,
+                      double* f, long S, hipStream_t st) {
+    long Nx = (long)n * n * (dim == 3 ? n : 1);
+    long total = S * Nt * Nx;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, dim, Nt, n,
+                       n_modes, Tpart, Xpart, f, S, Nx);
+    return hipGetLastError();
+}
+
+}  // namespace sth

@@ -1,0 +1,65 @@
+// Launchers of the gfx950 kernels.  All pointers are device pointers; every
+// launcher returns the HIP error of its launch.  Vectors use the layout
+// v[slab][t][z][y][x] (x fastest); n is the number of interior spline
+// functions per spatial axis, np = n rounded up to a multiple of 16.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace sth {
+
+constexpr int kNt = 8;          // maximum time functions per slab
+
+struct TimeOp {                 // residual: temporal matrices of the level
+    double Kt[kNt * kNt];
+    double Mt[kNt * kNt];
+};
+struct TimeMix {                // slab inverse: temporal eigen data of the level
+    double W[kNt * kNt];
+    double V[kNt * kNt];
+    double re[kNt];
+    double im[kNt];
+    int kind[kNt];              // 0 real, 1 first of a pair, 2 second of a pair
+};
+struct Transfer {               // 2Nt x Nt prolongation
+    double P[2 * kNt * kNt];
+};
+
+// r = f + sign * (-(A u)_n + (B u)_{n-1}) for slabs [s0, s0+ns) of a vector
+// with slab length Nt*n^dim; the coupling uses slab s-1 of the same vector
+// when s > 0.  f may be null (treated as zero).  M1b/K1b: bands [n][2p+1].
+hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
+                           const TimeOp& op, const double* f, const double* u, double* r,
+                           long s0, long ns, double sign, hipStream_t st);
+
+// out[line][j] (EPI) sum_k in[line][k] T[k][j] for `lines` contiguous lines
+// of length n.  EPI 0: store, 1: out += alpha*acc, 2: out = alpha*acc.
+hipError_t launch_xform_x(int epi, const double* in, double* out, const double* T, int n, int np,
+                          long lines, double alpha, hipStream_t st);
+
+// Strided axis: in[b][k][i] (k stride `inner`), out[b][j][i] = sum_k T[k][j] in[b][k][i].
+hipError_t launch_xform_s(const double* in, double* out, const double* T, int n, int np,
+                          long nbatch, long inner, hipStream_t st);
+
+// Per slab and spatial mode: out[:, m] = V (Z + mu_m I)^{-1} W in[:, m].
+hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
+                          const double* in, double* out, long S, hipStream_t st);
+
+// rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
+hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,
+                           long Nx, hipStream_t st);
+// u[2m..2m+1] += (P (x) I) e[m]
+hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u, long Sc,
+                          long Nx, hipStream_t st);
+
+hipError_t launch_fill(double* v, long len, double val, hipStream_t st);
+
+// Two-stage deterministic sum of squares: partial sums over a fixed number
+// of blocks, then one block; result in out[0].
+constexpr int kNormBlocks = 1024;
+hipError_t launch_norm2(const double* v, long len, double* partial, double* out, hipStream_t st);
+
+// f[s][t][z][y][x] = sum_m T[m][s*Nt+t] * X[m][0][x] * X[m][1][y] (* X[m][2][z])
+hipError_t launch_rhs(int dim, int Nt, int n, int n_modes, const double* Tpart, const double* Xpart,
+                      double* f, long S, hipStream_t st);
+
+}  // namespace sth

@@ -1,0 +1,628 @@
+// C ABI of the slab solver: handle, device data, smoother, V-cycle, solve.
+//
+// The multigrid follows Section 3.1: damped block-Jacobi smoothing
+//   u <- u + omega D^{-1}(f - L_h u),  D = diag(A_n),
+// coarsening in time by combining two consecutive slabs (restriction
+// P_t^T, prolongation P_t, the coarse slab operators are the Galerkin
+// products, which equal a rediscretisation on the double-length slab with
+// the finest SUPG parameter), V(nu_pre, nu_post) cycles, and an exact
+// slab-wise forward substitution on the coarsest level.  D^{-1} is applied by
+// eq. equ:ST:generalDecompA: spatial eigenbasis transforms (fast
+// diagonalisation of the 1-D pencils), temporal eigenvector transform and
+// shifted divide, inverse transforms.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sth.h"
+#include "kernels.hpp"
+#include "setup.hpp"
+
+using namespace sth;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(STH_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct sth_handle {
+    Setup S;
+    int dim = 2, n = 0, np = 0, Nt = 0, p = 0, L = 0;
+    long Nx = 0;
+    double omega = 0.5;
+    int nu_pre = 1, nu_post = 1;
+    std::vector<long> lev_S;            // slabs per level
+    std::vector<TimeOp> ops;
+    std::vector<TimeMix> mixes;
+    Transfer tr{};
+    // device data
+    double* Tf = nullptr;               // np x np, U padded  (forward: r^ = U^T r)
+    double* Ti = nullptr;               // np x np, U^T padded (inverse: z = U z^)
+    double* mu1 = nullptr;
+    double* M1b = nullptr;
+    double* K1b = nullptr;
+    std::vector<double*> lu, lf;        // per level >= 1: iterate and right-hand side
+    double* buf0 = nullptr;
+    double* buf1 = nullptr;
+    double* partial = nullptr;
+    double* dnorm = nullptr;
+    double* hnorm = nullptr;            // pinned
+    // timing
+    bool timing = false;
+    struct Rec { int cls; hipEvent_t a, b; double flops, bytes; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+};
+
+static long slab_len(const sth_handle* h) { return (long)h->Nt * h->Nx; }
+
+// ---------------------------------------------------------------------------
+// timing helpers
+// ---------------------------------------------------------------------------
+struct Timed {
+    sth_handle* h;
+    int cls;
+    double flops, bytes;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(sth_handle* hh, int c, double fl, double by, hipStream_t s) : h(hh), cls(c), flops(fl), bytes(by), st(s) {
+        if (!h->timing) return;
+        if (h->pool_used + 2 > h->pool.size()) {
+            for (int i = 0; i < 256; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return;
+                h->pool.push_back(e);
+            }
+        }
+        a = h->pool[h->pool_used++];
+        b = h->pool[h->pool_used++];
+        (void)hipEventRecord(a, st);
+    }
+    ~Timed() {
+        if (!a) return;
+        (void)hipEventRecord(b, st);
+        h->recs.push_back({cls, a, b, flops, bytes});
+    }
+};
+
+// ---------------------------------------------------------------------------
+// building blocks
+// ---------------------------------------------------------------------------
+static int residual(sth_handle* h, int lvl, const double* f, const double* u, double* r, long s0, long ns,
+                    double sign, hipStream_t st) {
+    double dof = (double)ns * slab_len(h);
+    int B = 2 * h->p + 1;
+    double flops = dof * ((h->dim == 2 ? 10.0 : 16.0) * B + 4.0 * h->Nt + 2.0);
+    double bytes = dof * (f ? 24.0 : 16.0);
+    Timed tm(h, STH_K_RESIDUAL, flops, bytes, st);
+    HIPCHK(launch_residual(h->dim, h->Nt, h->p, h->n, h->M1b, h->K1b, h->ops[lvl], f, u, r, s0, ns, sign, st));
+    return STH_OK;
+}
+
+static int xform_x(sth_handle* h, int epi, const double* in, double* out, const double* T, long lines,
+                   double alpha, hipStream_t st) {
+    double dof = (double)lines * h->n;
+    Timed tm(h, STH_K_XFORM_X, 2.0 * h->n * dof, dof * (epi == 1 ? 24.0 : 16.0), st);
+    HIPCHK(launch_xform_x(epi, in, out, T, h->n, h->np, lines, alpha, st));
+    return STH_OK;
+}
+
+static int xform_s(sth_handle* h, const double* in, double* out, const double* T, long nbatch, long inner,
+                   hipStream_t st) {
+    double dof = (double)nbatch * h->n * inner;
+    Timed tm(h, STH_K_XFORM_S, 2.0 * h->n * dof, 16.0 * dof, st);
+    HIPCHK(launch_xform_s(in, out, T, h->n, h->np, nbatch, inner, st));
+    return STH_OK;
+}
+
+// u (mode 1: +=, 2: =) omega * D^{-1} in, on slabs [s0, s0+ns) of level lvl.
+// `in` may alias buf1 but not buf0.
+static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int epi, double alpha, long s0,
+                        long ns, hipStream_t st) {
+    long off = s0 * slab_len(h);
+    in += off;
+    u += off;
+    const long n = h->n;
+    const long rows = ns * h->Nt;           // time rows
+    double* b0 = h->buf0 + off;
+    double* b1 = h->buf1 + off;
+    int rc;
+    if (h->dim == 2) {
+        if ((rc = xform_x(h, 0, in, b0, h->Tf, rows * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, b0, b1, h->Tf, rows, n, st))) return rc;
+        {
+            double dof = (double)ns * slab_len(h);
+            Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
+            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b1, b0, ns, st));
+        }
+        if ((rc = xform_s(h, b0, b1, h->Ti, rows, n, st))) return rc;
+        if ((rc = xform_x(h, epi, b1, u, h->Ti, rows * n, alpha, st))) return rc;
+    } else {
+        if ((rc = xform_x(h, 0, in, b0, h->Tf, rows * n * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, b0, b1, h->Tf, rows * n, n, st))) return rc;          // y
+        if ((rc = xform_s(h, b1, b0, h->Tf, rows, n * n, st))) return rc;          // z
+        {
+            double dof = (double)ns * slab_len(h);
+            Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
+            HIPCHK(launch_timemix(3, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, st));
+        }
+        if ((rc = xform_s(h, b1, b0, h->Ti, rows, n * n, st))) return rc;          // z
+        if ((rc = xform_s(h, b0, b1, h->Ti, rows * n, n, st))) return rc;          // y
+        if ((rc = xform_x(h, epi, b1, u, h->Ti, rows * n * n, alpha, st))) return rc;
+    }
+    return STH_OK;
+}
+
+// one damped block-Jacobi step on level lvl; zero_guess: u is taken as 0
+static int smooth_step(sth_handle* h, int lvl, const double* f, double* u, bool zero_guess, hipStream_t st) {
+    long ns = h->lev_S[lvl];
+    if (zero_guess) return slab_inverse(h, lvl, f, u, 2, h->omega, 0, ns, st);
+    int rc = residual(h, lvl, f, u, h->buf1, 0, ns, 1.0, st);
+    if (rc) return rc;
+    return slab_inverse(h, lvl, h->buf1, u, 1, h->omega, 0, ns, st);
+}
+
+// exact solve of the coarsest level by slab-wise forward substitution
+static int coarse_solve(sth_handle* h, int lvl, const double* f, double* u, hipStream_t st) {
+    long S = h->lev_S[lvl];
+    if (S == 1) return slab_inverse(h, lvl, f, u, 2, 1.0, 0, 1, st);
+    {
+        Timed tm(h, STH_K_OTHER, 0, 8.0 * S * slab_len(h), st);
+        HIPCHK(launch_fill(u, S * slab_len(h), 0.0, st));
+    }
+    for (long m = 0; m < S; ++m) {
+        int rc = residual(h, lvl, f, u, h->buf1, m, 1, 1.0, st);     // f_m + B u_{m-1} (u_m = 0)
+        if (rc) return rc;
+        rc = slab_inverse(h, lvl, h->buf1, u, 1, 1.0, m, 1, st);
+        if (rc) return rc;
+    }
+    return STH_OK;
+}
+
+static int restrict_lvl(sth_handle* h, int lvl, const double* r, double* rc, hipStream_t st) {
+    long Sc = h->lev_S[lvl + 1];
+    double dof = (double)Sc * slab_len(h);
+    Timed tm(h, STH_K_RESTRICT, dof * 4.0 * h->Nt, dof * 24.0, st);
+    HIPCHK(launch_restrict(h->Nt, h->tr, r, rc, Sc, h->Nx, st));
+    return STH_OK;
+}
+
+static int prolong_lvl(sth_handle* h, int lvl, const double* e, double* u, hipStream_t st) {
+    long Sc = h->lev_S[lvl + 1];
+    double dof = (double)Sc * slab_len(h);
+    Timed tm(h, STH_K_PROLONG, dof * 4.0 * h->Nt, dof * 40.0, st);
+    HIPCHK(launch_prolong(h->Nt, h->tr, e, u, Sc, h->Nx, st));
+    return STH_OK;
+}
+
+static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool zero_guess, hipStream_t st) {
+    int rc;
+    if (lvl == h->L - 1) return coarse_solve(h, lvl, f, u, st);
+    long ns = h->lev_S[lvl];
+    if (zero_guess && h->nu_pre == 0) {
+        Timed tm(h, STH_K_OTHER, 0, 8.0 * ns * slab_len(h), st);
+        HIPCHK(launch_fill(u, ns * slab_len(h), 0.0, st));
+        zero_guess = false;
+    }
+    for (int i = 0; i < h->nu_pre; ++i) {
+        if ((rc = smooth_step(h, lvl, f, u, zero_guess && i == 0, st))) return rc;
+    }
+    if ((rc = residual(h, lvl, f, u, h->buf1, 0, ns, 1.0, st))) return rc;
+    if ((rc = restrict_lvl(h, lvl, h->buf1, h->lf[lvl + 1], st))) return rc;
+    if ((rc = vcycle_lvl(h, lvl + 1, h->lf[lvl + 1], h->lu[lvl + 1], true, st))) return rc;
+    if ((rc = prolong_lvl(h, lvl, h->lu[lvl + 1], u, st))) return rc;
+    for (int i = 0; i < h->nu_post; ++i) {
+        if ((rc = smooth_step(h, lvl, f, u, false, st))) return rc;
+    }
+    return STH_OK;
+}
+
+static int norm2_dev(sth_handle* h, const double* v, long len, hipStream_t st) {
+    Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
+    HIPCHK(launch_norm2(v, len, h->partial, h->dnorm, st));
+    return STH_OK;
+}
+
+static int read_norm(sth_handle* h, const double* v, long len, hipStream_t st, double* out) {
+    int rc = norm2_dev(h, v, len, st);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *out = std::sqrt(h->hnorm[0]);
+    return STH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+static Problem to_problem(const sth_problem* p) {
+    Problem q;
+    q.dim = p->dim;
+    q.n_elem = p->n_elem;
+    q.degree = p->degree;
+    q.n_slabs = p->n_slabs;
+    q.n_elem_t = p->n_elem_t;
+    q.T = p->T;
+    q.theta = p->theta;
+    q.omega = p->omega;
+    q.nu_pre = p->nu_pre;
+    q.nu_post = p->nu_post;
+    q.prec = p->transform_prec;
+    return q;
+}
+
+extern "C" {
+
+void sth_problem_default(sth_problem* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->T = 1.0;
+    p->theta = 0.01;
+    p->omega = 0.5;
+    p->nu_pre = 1;
+    p->nu_post = 1;
+    p->transform_prec = STH_FP64;
+}
+
+const char* sth_last_error(void) { return g_err.c_str(); }
+
+static size_t level_count(const Problem& q) {
+    size_t L = 1;
+    long S = q.n_slabs;
+    while (S > 1 && S % 2 == 0) { S /= 2; ++L; }
+    return L;
+}
+
+int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
+    if (!p || !bytes) return fail(STH_EINVAL, "null argument");
+    Problem q = to_problem(p);
+    std::string e = validate(q);
+    if (!e.empty()) return fail(STH_EINVAL, e);
+    long n = q.n(), np = (n + 15) / 16 * 16;
+    long Nx = n * n * (q.dim == 3 ? n : 1);
+    long slab = (long)q.Nt() * Nx;
+    size_t total = 0;
+    total += 2 * sizeof(double) * np * np;                   // transforms
+    total += sizeof(double) * n * (1 + 2 * (2 * q.degree + 1));
+    total += 2 * sizeof(double) * (size_t)q.n_slabs * slab;  // buf0, buf1
+    long S = q.n_slabs;
+    size_t L = level_count(q);
+    for (size_t l = 1; l < L; ++l) {
+        S /= 2;
+        total += 2 * sizeof(double) * (size_t)S * slab;
+    }
+    total += sizeof(double) * (kNormBlocks + 1);
+    *bytes = total;
+    return STH_OK;
+}
+
+int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
+    if (!p || !out) return fail(STH_EINVAL, "null argument");
+    *out = nullptr;
+    Problem q = to_problem(p);
+    std::string e = validate(q);
+    if (!e.empty()) return fail(STH_EINVAL, e);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(STH_ENODEV, "no HIP device");
+    sth_handle* h = new sth_handle();
+    int st = build_setup(q, h->S, e);
+    if (st != 0) {
+        delete h;
+        return fail(st, e);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    h->dim = q.dim;
+    h->n = h->S.n;
+    h->np = (h->n + 15) / 16 * 16;
+    h->Nt = h->S.Nt;
+    h->p = q.degree;
+    h->Nx = (long)h->n * h->n * (q.dim == 3 ? h->n : 1);
+    h->omega = q.omega;
+    h->nu_pre = q.nu_pre;
+    h->nu_post = q.nu_post;
+    h->L = (int)h->S.levels.size();
+    for (auto& lv : h->S.levels) {
+        h->lev_S.push_back(lv.S);
+        TimeOp op{};
+        TimeMix tm{};
+        for (int i = 0; i < h->Nt; ++i) {
+            for (int j = 0; j < h->Nt; ++j) {
+                op.Kt[i * kNt + j] = lv.Kt(i, j);
+                op.Mt[i * kNt + j] = lv.Mt(i, j);
+                tm.W[i * kNt + j] = lv.W(i, j);
+                tm.V[i * kNt + j] = lv.V(i, j);
+            }
+            tm.re[i] = lv.re[i];
+            tm.im[i] = lv.im[i];
+            tm.kind[i] = lv.kind[i];
+        }
+        h->ops.push_back(op);
+        h->mixes.push_back(tm);
+    }
+    if (h->L > 1) {
+        const Mat& P = h->S.levels[0].Pt;
+        for (int i = 0; i < 2 * h->Nt; ++i)
+            for (int j = 0; j < h->Nt; ++j) h->tr.P[i * kNt + j] = P(i, j);
+    }
+    // host staging of the spatial factors
+    int n = h->n, np = h->np, B = 2 * h->p + 1;
+    std::vector<double> Tf((size_t)np * np, 0.0), Ti((size_t)np * np, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            Tf[(size_t)i * np + j] = h->S.U(i, j);     // r^_j = sum_i U_ij r_i
+            Ti[(size_t)j * np + i] = h->S.U(i, j);     // z_i  = sum_j U_ij z^_j
+        }
+    std::vector<double> M1b((size_t)n * B, 0.0), K1b((size_t)n * B, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < B; ++k) {
+            int j = i - h->p + k;
+            if (j >= 0 && j < n) {
+                M1b[(size_t)i * B + k] = h->S.M1(i, j);
+                K1b[(size_t)i * B + k] = h->S.K1(i, j);
+            }
+        }
+    auto cleanup = [&](int code, const std::string& msg) {
+        sth_destroy(h);
+        return fail(code, msg);
+    };
+    auto dalloc = [&](double** ptr, size_t count) -> bool {
+        return hipMalloc((void**)ptr, std::max<size_t>(count, 1) * sizeof(double)) == hipSuccess;
+    };
+    long slab = slab_len(h);
+    if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
+        !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
+        !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 1))
+        return cleanup(STH_ENOMEM, "device allocation failed");
+    h->lu.assign(h->L, nullptr);
+    h->lf.assign(h->L, nullptr);
+    for (int l = 1; l < h->L; ++l) {
+        if (!dalloc(&h->lu[l], (size_t)h->lev_S[l] * slab) || !dalloc(&h->lf[l], (size_t)h->lev_S[l] * slab))
+            return cleanup(STH_ENOMEM, "device allocation failed");
+    }
+    if (hipHostMalloc((void**)&h->hnorm, sizeof(double), 0) != hipSuccess)
+        return cleanup(STH_ENOMEM, "pinned host allocation failed");
+    if (hipMemcpyAsync(h->Tf, Tf.data(), Tf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->Ti, Ti.data(), Ti.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->mu1, h->S.mu.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->M1b, M1b.data(), M1b.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->K1b, K1b.data(), K1b.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(STH_EHIP, "upload of the setup failed");
+    *out = h;
+    return STH_OK;
+}
+
+size_t sth_vector_len(const sth_handle* h) { return h ? (size_t)h->lev_S[0] * slab_len(h) : 0; }
+
+size_t sth_level_len(const sth_handle* h, int level) {
+    if (!h || level < 0 || level >= h->L) return 0;
+    return (size_t)h->lev_S[level] * slab_len(h);
+}
+
+int sth_num_levels(const sth_handle* h) { return h ? h->L : 0; }
+
+int sth_load_rhs(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream) {
+    if (!h || !m || !f) return fail(STH_EINVAL, "null argument");
+    if (m->n_modes < 0 || (m->n_modes > 0 && (!m->amp || !m->k || !m->omega || !m->phase)))
+        return fail(STH_EINVAL, "bad mode list");
+    hipStream_t st = (hipStream_t)stream;
+    const Problem& q = h->S.prob;
+    long S = q.n_slabs;
+    int n = h->n, Nt = h->Nt, M = m->n_modes;
+    if (M == 0) {
+        HIPCHK(launch_fill(f, S * slab_len(h), 0.0, st));
+        return STH_OK;
+    }
+    std::vector<double> T((size_t)M * S * Nt), X((size_t)M * 3 * n, 0.0), tmp;
+    for (int q2 = 0; q2 < M; ++q2) {
+        load_time(q, m->omega[q2], m->phase[q2], tmp);
+        for (size_t i = 0; i < tmp.size(); ++i) T[(size_t)q2 * S * Nt + i] = m->amp[q2] * tmp[i];
+        for (int a = 0; a < h->dim; ++a) {
+            load_space(q, m->k[q2 * h->dim + a], tmp);
+            for (int i = 0; i < n; ++i) X[(size_t)q2 * 3 * n + (size_t)a * n + i] = tmp[i];
+        }
+    }
+    double *dT = nullptr, *dX = nullptr;
+    if (hipMalloc((void**)&dT, T.size() * 8) != hipSuccess) return fail(STH_ENOMEM, "rhs staging");
+    if (hipMalloc((void**)&dX, X.size() * 8) != hipSuccess) {
+        (void)hipFree(dT);
+        return fail(STH_ENOMEM, "rhs staging");
+    }
+    hipError_t e1 = hipMemcpyAsync(dT, T.data(), T.size() * 8, hipMemcpyHostToDevice, st);
+    hipError_t e2 = hipMemcpyAsync(dX, X.data(), X.size() * 8, hipMemcpyHostToDevice, st);
+    hipError_t e3 = launch_rhs(h->dim, Nt, n, M, dT, dX, f, S, st);
+    hipError_t e4 = hipStreamSynchronize(st);
+    (void)hipFree(dT);
+    (void)hipFree(dX);
+    if (e1 || e2 || e3 || e4) return fail(STH_EHIP, "rhs assembly failed");
+    return STH_OK;
+}
+
+int sth_apply(sth_handle* h, const double* u, double* y, void* stream) {
+    if (!h || !u || !y) return fail(STH_EINVAL, "null argument");
+    return residual(h, 0, nullptr, u, y, 0, h->lev_S[0], -1.0, (hipStream_t)stream);
+}
+
+int sth_residual(sth_handle* h, const double* f, const double* u, double* r, void* stream) {
+    if (!h || !f || !u || !r) return fail(STH_EINVAL, "null argument");
+    return residual(h, 0, f, u, r, 0, h->lev_S[0], 1.0, (hipStream_t)stream);
+}
+
+int sth_block_solve(sth_handle* h, const double* r, double* z, void* stream) {
+    if (!h || !r || !z) return fail(STH_EINVAL, "null argument");
+    if (r == h->buf0 || z == h->buf0) return fail(STH_EINVAL, "aliasing");
+    return slab_inverse(h, 0, r, z, 2, 1.0, 0, h->lev_S[0], (hipStream_t)stream);
+}
+
+int sth_smooth(sth_handle* h, const double* f, double* u, int steps, void* stream) {
+    if (!h || !f || !u || steps < 0) return fail(STH_EINVAL, "bad argument");
+    for (int i = 0; i < steps; ++i) {
+        int rc = smooth_step(h, 0, f, u, false, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    return STH_OK;
+}
+
+int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream) {
+    if (!h || !f || !u) return fail(STH_EINVAL, "null argument");
+    return vcycle_lvl(h, 0, f, u, false, (hipStream_t)stream);
+}
+
+int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit, int* iters, double* relres,
+              void* stream) {
+    if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    long len = h->lev_S[0] * slab_len(h);
+    double fn = 0.0, rn = 0.0;
+    int rc = read_norm(h, f, len, st, &fn);
+    if (rc) return rc;
+    if (fn == 0.0) fn = 1.0;
+    if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
+    if ((rc = read_norm(h, h->buf1, len, st, &rn))) return rc;
+    int it = 0, growth = 0;
+    double prev = rn;
+    while (rn > rtol * fn && it < maxit) {
+        if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
+        ++it;
+        if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
+        if ((rc = read_norm(h, h->buf1, len, st, &rn))) return rc;
+        if (!std::isfinite(rn)) break;
+        growth = (rn > prev) ? growth + 1 : 0;
+        prev = rn;
+        if (growth >= 3) break;
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = rn / fn;
+    if (!std::isfinite(rn)) return fail(STH_ENOCONV, "residual is not finite");
+    if (growth >= 3) return fail(STH_ENOCONV, "residual grew over 3 consecutive cycles");
+    if (rn > rtol * fn) return fail(STH_ENOCONV, "maxit reached");
+    return STH_OK;
+}
+
+int sth_restrict(sth_handle* h, int level, const double* r, double* rc, void* stream) {
+    if (!h || !r || !rc || level < 0 || level + 1 >= h->L) return fail(STH_EINVAL, "bad argument");
+    return restrict_lvl(h, level, r, rc, (hipStream_t)stream);
+}
+
+int sth_prolong_add(sth_handle* h, int level, const double* ec, double* u, void* stream) {
+    if (!h || !ec || !u || level < 0 || level + 1 >= h->L) return fail(STH_EINVAL, "bad argument");
+    return prolong_lvl(h, level, ec, u, (hipStream_t)stream);
+}
+
+int sth_norm(sth_handle* h, const double* v, double* out, void* stream) {
+    if (!h || !v || !out) return fail(STH_EINVAL, "null argument");
+    return read_norm(h, v, h->lev_S[0] * slab_len(h), (hipStream_t)stream, out);
+}
+
+int sth_destroy(sth_handle* h) {
+    if (!h) return STH_OK;
+    double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm};
+    for (double* q : ptrs)
+        if (q) (void)hipFree(q);
+    for (double* q : h->lu)
+        if (q) (void)hipFree(q);
+    for (double* q : h->lf)
+        if (q) (void)hipFree(q);
+    if (h->hnorm) (void)hipHostFree(h->hnorm);
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    delete h;
+    return STH_OK;
+}
+
+int sth_timing(sth_handle* h, int enable) {
+    if (!h) return fail(STH_EINVAL, "null handle");
+    if (enable) {
+        h->recs.clear();
+        h->pool_used = 0;
+    }
+    h->timing = enable != 0;
+    return STH_OK;
+}
+
+int sth_timing_report(sth_handle* h, int kclass, int* launches, double* ms, double* flops, double* bytes) {
+    if (!h || kclass < 0 || kclass >= STH_K_COUNT) return fail(STH_EINVAL, "bad argument");
+    int cnt = 0;
+    double t = 0, fl = 0, by = 0;
+    for (auto& r : h->recs) {
+        if (r.cls != kclass) continue;
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(STH_EHIP, "event sync");
+        float e = 0;
+        if (hipEventElapsedTime(&e, r.a, r.b) != hipSuccess) return fail(STH_EHIP, "event time");
+        ++cnt;
+        t += e;
+        fl += r.flops;
+        by += r.bytes;
+    }
+    if (launches) *launches = cnt;
+    if (ms) *ms = t;
+    if (flops) *flops = fl;
+    if (bytes) *bytes = by;
+    return STH_OK;
+}
+
+// ---- host introspection ----------------------------------------------------
+int sth_host_factors(const sth_problem* p, int level, sth_factors* out) {
+    if (!p || !out) return fail(STH_EINVAL, "null argument");
+    Problem q = to_problem(p);
+    Setup S;
+    std::string e;
+    int st = build_setup(q, S, e);
+    if (st != 0) return fail(st, e);
+    if (level < 0 || level >= (int)S.levels.size()) return fail(STH_EINVAL, "bad level");
+    int n = S.n, Nt = S.Nt;
+    out->n = n;
+    out->N_t = Nt;
+    out->n_levels = (int)S.levels.size();
+    const TemporalLevel& L = S.levels[level];
+    out->cond_V = L.condV;
+    auto cp = [](double* dst, const std::vector<double>& src) {
+        if (dst) std::memcpy(dst, src.data(), src.size() * sizeof(double));
+    };
+    cp(out->M1, S.M1.a);
+    cp(out->K1, S.K1.a);
+    cp(out->U, S.U.a);
+    cp(out->mu, S.mu);
+    cp(out->Kt, L.Kt.a);
+    cp(out->Mt, L.Mt.a);
+    if (L.Pt.r > 0) cp(out->Pt, L.Pt.a);
+    cp(out->V, L.V.a);
+    cp(out->W, L.W.a);
+    cp(out->eig_re, L.re);
+    cp(out->eig_im, L.im);
+    return STH_OK;
+}
+
+int sth_host_load_1d(const sth_problem* p, double omega, double phase, int k, double* time_part,
+                     double* space_part) {
+    if (!p) return fail(STH_EINVAL, "null argument");
+    Problem q = to_problem(p);
+    std::string e = validate(q);
+    if (!e.empty()) return fail(STH_EINVAL, e);
+    std::vector<double> tmp;
+    if (time_part) {
+        load_time(q, omega, phase, tmp);
+        std::memcpy(time_part, tmp.data(), tmp.size() * sizeof(double));
+    }
+    if (space_part) {
+        load_space(q, k, tmp);
+        std::memcpy(space_part, tmp.data(), tmp.size() * sizeof(double));
+    }
+    return STH_OK;
+}
+
+}  // extern "C"

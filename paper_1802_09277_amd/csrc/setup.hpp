@@ -1,0 +1,90 @@
+// Host FP64 setup of the space-time slab solver: 1-D B-spline matrices,
+// temporal pencils per multigrid level, their decompositions and guards.
+// Pure C++ (no HIP); the runtime uploads the results.
+#pragma once
+#include <complex>
+#include <string>
+#include <vector>
+
+namespace sth {
+
+constexpr int kMaxNt = 8;     // N_t = n_elem_t + degree supported by the kernels
+constexpr int kMaxDeg = 4;
+
+struct Mat {
+    int r = 0, c = 0;
+    std::vector<double> a;
+    Mat() = default;
+    Mat(int rows, int cols) : r(rows), c(cols), a(size_t(rows) * cols, 0.0) {}
+    double& operator()(int i, int j) { return a[size_t(i) * c + j]; }
+    double operator()(int i, int j) const { return a[size_t(i) * c + j]; }
+};
+
+// ---- splines ---------------------------------------------------------------
+// Open uniform knot vector on [a,b] with n_el elements of degree p.
+std::vector<double> open_knots(double a, double b, int n_el, int p);
+// Gauss-Legendre nodes and weights on [-1,1] (Newton on P_q).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w);
+// Nonzero B-splines of degree p at x in knot span `span` (t[span] <= x <
+// t[span+1]) and their first derivatives: values/derivs[r] belong to basis
+// function span-p+r.
+void basis_local(const std::vector<double>& t, int p, int span, double x,
+                 double* values, double* derivs);
+int find_span(const std::vector<double>& t, int p, double x);
+
+// ---- small dense linear algebra ----------------------------------------------
+bool lu_inverse(const Mat& A, Mat& inv);                      // partial pivoting
+bool lu_solve_inplace(Mat A, std::vector<double>& b);
+bool cholesky(const Mat& A, Mat& L);
+void sym_eigen(const Mat& A, std::vector<double>& evals, Mat& evecs);   // A symmetric
+// Eigenvalues and eigenvectors of a real nonsymmetric matrix (small).
+bool nonsym_eigen(const Mat& A, std::vector<std::complex<double>>& lam,
+                  std::vector<std::vector<std::complex<double>>>& vecs);
+double cond2(const Mat& A);                                   // sigma_max / sigma_min
+
+// ---- problem quantities ------------------------------------------------------
+struct Problem {
+    int dim, n_elem, degree, n_slabs, n_elem_t;
+    double T, theta, omega;
+    int nu_pre, nu_post, prec;
+    int n() const { return n_elem + degree - 2; }
+    int Nt() const { return n_elem_t + degree; }
+    double tau() const { return T / n_slabs; }
+    double sigma() const { return theta * tau() / n_elem_t; }
+};
+
+struct TemporalLevel {
+    int S = 0;             // slabs on this level
+    double tau = 0;        // slab length
+    Mat Kt, Mt;            // eq. TimeMatrices with the finest sigma
+    Mat Pt;                // 2Nt x Nt prolongation to the next coarser level
+    Mat V, W;              // real block eigenvectors, W = (Mt V)^{-1}
+    std::vector<double> re, im;   // eigen pairs (im = +b,-b on a pair)
+    std::vector<int> kind;        // 0 real, 1 first of a pair, 2 second
+    double condV = 0;
+};
+
+struct Setup {
+    Problem prob;
+    int n = 0, Nt = 0;
+    Mat M1, K1, U;         // 1-D spatial matrices (interior), eigenvectors
+    std::vector<double> mu;
+    std::vector<TemporalLevel> levels;
+};
+
+// Validates the problem; returns an error message or "".
+std::string validate(const Problem& p);
+// Full setup.  status: 0 ok, -4 not positive, -5 ill-conditioned, -1 invalid.
+int build_setup(const Problem& p, Setup& s, std::string& err);
+
+// Spatial 1-D matrices (interior functions), banded with bandwidth p.
+void space_matrices(int n_elem, int p, Mat& M1, Mat& K1);
+// Temporal matrices on a slab of length tau with n_el elements and SUPG sigma.
+void time_matrices(double tau, int n_el, int p, double sigma, Mat& Kt, Mat& Mt);
+// Prolongation coarse slab (length 2 tau) -> two fine slabs by knot insertion.
+void time_prolongation(int n_el, int p, Mat& Pt);
+// 1-D load vectors of one separable mode.
+void load_time(const Problem& p, double omega, double phase, std::vector<double>& out);
+void load_space(const Problem& p, int k, std::vector<double>& out);
+
+}  // namespace sth

@@ -1,0 +1,125 @@
+"""Host (CPU) checks of the library's FP64 setup against the oracle and
+against properties fixed by the mathematics; no GPU is needed."""
+import re
+import os
+import ctypes
+import numpy as np
+import scipy.linalg as sl
+import pytest
+
+import paper_1802_09277_amd as sth
+from oracle.spacetime import time_matrices, space_matrices_1d, Problem as OProblem, assemble_rhs
+from oracle.mg import time_prolongation
+import workloads as W
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sth.h")
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(sth.LIB_PATH)
+    src = open(HDR).read()
+    names = set(re.findall(r"\b(sth_[a-z0-9_]+)\s*\(", src))
+    assert len(names) >= 20
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+
+
+SHAPES = [dict(dim=2, n_elem=6, degree=2, n_slabs=8, n_elem_t=2),
+          dict(dim=2, n_elem=9, degree=3, n_slabs=4, n_elem_t=2),
+          dict(dim=3, n_elem=5, degree=2, n_slabs=2, n_elem_t=1),
+          dict(dim=2, n_elem=7, degree=4, n_slabs=6, n_elem_t=2),
+          dict(dim=2, n_elem=5, degree=1, n_slabs=4, n_elem_t=3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_setup_matches_oracle_and_identities(shape):
+    theta, T = 0.01, 1.0
+    F0 = sth.host_factors(level=0, **shape)
+    p, S, net = shape["degree"], shape["n_slabs"], shape["n_elem_t"]
+    M1o, K1o = space_matrices_1d(shape["n_elem"], p)
+    assert np.allclose(F0["M1"], M1o, rtol=0, atol=1e-15)
+    assert np.allclose(F0["K1"], K1o, rtol=1e-13, atol=1e-12)
+    U, mu = F0["U"], F0["mu"]
+    assert np.allclose(U.T @ M1o @ U, np.eye(len(mu)), atol=1e-12)
+    assert np.allclose(K1o @ U, M1o @ U @ np.diag(mu), atol=1e-9 * mu.max())
+    tau = T / S
+    sig = theta * tau / net
+    levels = F0["n_levels"]
+    s_l = S
+    for lvl in range(levels):
+        F = sth.host_factors(level=lvl, **shape)
+        Kt, Mt = time_matrices(0.0, tau * 2 ** lvl, net, p, sig)     # finest sigma on every level
+        assert np.allclose(F["Kt"], Kt, atol=1e-14)
+        assert np.allclose(F["Mt"], Mt, atol=1e-15)
+        V, Wm = F["V"], F["W"]
+        Z = np.diag(F["eig_re"])
+        im = F["eig_im"]
+        for k in range(len(im)):
+            if im[k] > 0:
+                Z[k, k + 1] = im[k]
+                Z[k + 1, k] = -im[k]
+        assert np.allclose(Wm @ Kt @ V, Z, atol=1e-11 * np.abs(Z).max())
+        assert np.allclose(Wm @ Mt @ V, np.eye(len(Z)), atol=1e-11)
+        lam = sl.eigvals(Kt, Mt)
+        lam_h = F["eig_re"] + 1j * F["eig_im"]
+        key = lambda z: (round(z.real, 6), round(z.imag, 6))
+        assert np.allclose(sorted(lam, key=key), sorted(lam_h, key=key), rtol=1e-10)
+        assert np.all(lam.real > 0)
+        if lvl + 1 < levels:
+            assert np.allclose(F["Pt"], time_prolongation(tau * 2 ** lvl, net, p), atol=1e-13)
+        s_l //= 2
+
+
+def test_level_count():
+    assert sth.host_factors(level=0, dim=2, n_elem=4, degree=2, n_slabs=16, n_elem_t=2)["n_levels"] == 5
+    assert sth.host_factors(level=0, dim=2, n_elem=4, degree=2, n_slabs=12, n_elem_t=2)["n_levels"] == 3
+    assert sth.host_factors(level=0, dim=2, n_elem=4, degree=2, n_slabs=1, n_elem_t=2)["n_levels"] == 1
+
+
+def test_guard_mt_not_positive():
+    """Table 2 '*' entries: theta = 1, p >= 4 on 4 elements -> M_t has an
+    eigenvalue with negative real part; setup refuses with STH_ENOTPOS."""
+    with pytest.raises(sth.StatusError) as ei:
+        sth.host_factors(level=0, dim=2, n_elem=4, degree=4, n_slabs=1, n_elem_t=4, theta=1.0)
+    assert ei.value.name == "STH_ENOTPOS"
+    # the neighbouring entry without '*' is accepted
+    sth.host_factors(level=0, dim=2, n_elem=4, degree=3, n_slabs=1, n_elem_t=4, theta=1.0)
+
+
+@pytest.mark.parametrize("bad", [dict(dim=1), dict(degree=5), dict(n_elem=1), dict(n_slabs=0),
+                                 dict(n_elem_t=7), dict(omega=0.0), dict(nu_pre=0, nu_post=0),
+                                 dict(prec=3), dict(theta=-1.0)])
+def test_invalid_problems_rejected(bad):
+    kw = dict(dim=2, n_elem=4, degree=2, n_slabs=4, n_elem_t=2)
+    kw.update(bad)
+    with pytest.raises(sth.StatusError) as ei:
+        sth.workspace_bytes(**kw)
+    assert ei.value.name == "STH_EINVAL"
+
+
+def test_workspace_bytes_grows_with_problem():
+    a = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=16, n_elem_t=2)
+    b = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=32, n_elem_t=2)
+    vec = 32 * 4 * 16 * 16 * 8
+    assert b > a and b >= 3 * vec
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_load_vectors_match_oracle(dim):
+    shape = dict(dim=dim, n_elem=5, degree=2, n_slabs=3, n_elem_t=2)
+    prob = OProblem(**shape)
+    modes = W.random_modes(4, dim, n_modes=3)
+    f_or = assemble_rhs(prob, modes)
+    amp, k, om, ph = modes.arrays()
+    f = 0
+    for m in range(len(amp)):
+        parts = []
+        for a in range(dim):
+            tp, sp_ = sth.host_load_1d(om[m], ph[m], k[m, a], **shape)
+            parts.append(sp_)
+        tpr = tp.reshape(prob.n_slabs, prob.N_t)
+        outer = parts[0]
+        for a in range(1, dim):
+            outer = np.multiply.outer(parts[a], outer)
+        f = f + amp[m] * np.multiply.outer(tpr, outer).ravel()
+    assert np.allclose(f, f_or, rtol=1e-12, atol=1e-15)

@@ -141,3 +141,8 @@ def serving_requests(n_requests=1000, seed=0):
         S = int(rng.choice([16, 32, 64, 128, 256, 512]))
         out.append(Config(f"req{rid}", 2, ne, p, S, 2, "random", seed=rid))
     return out
+
+
+def random_vector(seed, n):
+    """Seeded standard-normal vector (iterates and residuals for parity tests)."""
+    return np.random.default_rng(seed).standard_normal(n)
