@@ -1,0 +1,178 @@
+"""Benchmark: space-time DOF/s of the multigrid solve to relative residual 1e-8.
+
+One step = one full solve L_h u = f from u = 0 (V(1,1) cycles of the
+time-parallel multigrid with the damped block-Jacobi slab smoother) until
+||f - L_h u||_2 <= 1e-8 ||f||_2, on the 2D workload: unit square, p = 3,
+64 x 64 elements, 256 slabs x 2 time elements (5,408,000 unknowns), right-hand
+side from 8 random Fourier modes (seed 2).  Inputs are resident in HBM when
+the timed region starts; setup and right-hand-side assembly are outside it.
+
+Prints one JSON line with the throughput, the roofline of the dominant
+kernel class (HIP events around its launches inside the timed region) and
+the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "space-time DOF/s to rel.res 1e-8, FP64 vs mixed; serve p50/p99 latency"
+PEAKS = {  # MI355X published peaks
+    "hbm": 8.0e12,            # bytes/s
+    "fp64": 78.6e12,          # FLOP/s, vector = matrix
+    "fp32": 157.3e12,
+    "bf16": 2.5e15,
+}
+# dominant-class roofline: which bound applies to each kernel class
+CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "timemix": "hbm",
+               "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, sample_slabs):
+    """FP64 oracle direct solve (one sparse LU of A_n, then slab-wise forward
+    substitution) on the first `sample_slabs` slabs, single-threaded, scaled
+    to the full slab count; assembly excluded as in the paper's timings."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.spacetime import Problem, assemble_rhs
+    from oracle.solve import SlabSystem
+    import scipy.sparse.linalg as spla
+
+    prob = Problem(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        sysm = SlabSystem.assemble(prob)
+        f = assemble_rhs(prob, cfg.modes(), slabs=range(sample_slabs))
+        t_asm = time.perf_counter() - t0
+        log(f"cpu baseline: oracle assembly {t_asm:.1f} s (excluded)")
+        t0 = time.perf_counter()
+        lu = spla.splu(sysm.A)
+        t_fact = time.perf_counter() - t0
+        F = f.reshape(sample_slabs, -1)
+        t0 = time.perf_counter()
+        u = lu.solve(F[0])
+        for k in range(1, sample_slabs):
+            u = lu.solve(F[k] + sysm.B @ u)
+        t_solve = (time.perf_counter() - t0) / sample_slabs
+    est = t_fact + cfg.n_slabs * t_solve
+    log(f"cpu baseline: factorization {t_fact:.2f} s, {t_solve * 1e3:.1f} ms per slab solve")
+    return {
+        "value": cfg.unknowns / est,
+        "unit": "DOF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"oracle direct solve (SuperLU factorization of the slab matrix + forward substitution) "
+                   f"timed on {sample_slabs} of {cfg.n_slabs} slabs, single thread, scaled to "
+                   f"factorization + {cfg.n_slabs} slab solves; assembly excluded "
+                   f"(factorization {t_fact:.2f} s, {t_solve * 1e3:.1f} ms/slab)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--cpu-sample-slabs", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the slab solver runs on a single MI355X; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1802_09277_amd as sth
+    import workloads as W
+
+    cfg = W.CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
+                   prec=args.prec)
+    f = s.new_vector()
+    s.load_rhs(cfg.modes(), f)
+    u = s.new_vector()
+    torch.cuda.synchronize()
+
+    # warm-up with every kernel class timed, to find the dominant class
+    s.timing(0x1FF)
+    iters = 0
+    for _ in range(max(args.warmup, 1)):
+        u.zero_()
+        iters, relres, _ = s.solve(f, u, rtol=args.rtol, maxit=200)
+    totals = {k: s.timing_report(k) for k in sth.KCLASS}
+    dominant = max(totals, key=lambda k: totals[k]["ms"])
+    log("warm-up kernel classes (ms per solve): " +
+        ", ".join(f"{k}={v['ms'] / max(args.warmup, 1):.3f}" for k, v in totals.items() if v["launches"]))
+    s.timing(1 << sth.KCLASS[dominant])
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u.zero_()
+        iters, relres, _ = s.solve(f, u, rtol=args.rtol, maxit=200)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    rep = s.timing_report(dominant)
+    s.timing(0)
+    bound = CLASS_BOUND[dominant]
+    if bound == "mfma":
+        peak_key = {"fp64": "fp64", "fp32": "fp32", "bf16x3": "bf16"}[args.prec]
+        achieved = rep["flops"] / (rep["ms"] * 1e-3)
+        peak = PEAKS[peak_key]
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+    else:
+        achieved = rep["bytes"] / (rep["ms"] * 1e-3)
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel_class"] = dominant
+    roof["launches_per_step"] = rep["launches"] / args.steps
+    roof["mean_launch_us"] = rep["ms"] * 1e3 / max(rep["launches"], 1)
+
+    out = {
+        "metric": METRIC,
+        "value": cfg.unknowns / (ms * 1e-3),
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else f"f64+{args.prec}",
+        "data": "synthetic",
+        "config": {
+            "workload": cfg.note,
+            "name": cfg.name,
+            "unknowns": cfg.unknowns,
+            "coefficients_incl_dirichlet": cfg.coefficients,
+            "theta": cfg.theta,
+            "transform_prec": args.prec,
+            "v_cycles": iters,
+            "final_relres": relres,
+            "levels": s.num_levels,
+        },
+        "roofline": roof,
+    }
+    s.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_slabs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

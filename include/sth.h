@@ -64,8 +64,10 @@ typedef enum {
  * (dim 3), open uniform knot vectors, degree `degree` in space and time,
  * n_slabs equal slabs on (0,T), n_elem_t time elements per slab, SUPG
  * parameter sigma = theta * (T / n_slabs / n_elem_t).  The multigrid
- * coarsens in time only (two slabs -> one) while the slab count is even;
- * the coarsest level is solved exactly by slab-wise forward substitution.
+ * coarsens in time only (two slabs -> one) while the slab count is even and
+ * larger than coarse_slabs; the coarsest level is solved exactly by
+ * slab-wise forward substitution (in the spatial eigenbasis, where the
+ * coupling B_n only carries the last time row of the previous slab).
  * omega is the damping of the block-Jacobi smoother (Section 3.1: 1/2),
  * nu_pre / nu_post the smoothing steps of the V-cycle. */
 typedef struct {
@@ -80,6 +82,7 @@ typedef struct {
     int nu_pre;         /* >= 0 */
     int nu_post;        /* >= 0 */
     int transform_prec; /* sth_prec */
+    int coarse_slabs;   /* >= 1: stop coarsening at this many slabs or fewer */
 } sth_problem;
 
 /* Right-hand side as a sum of separable modes (host arrays):
@@ -95,7 +98,8 @@ typedef struct {
 } sth_rhs_modes;
 
 /* Fills p with the defaults of Section 4.4: theta 0.01, omega 1/2, T 1,
- * V(1,1), FP64 transforms (the shape fields are left at zero). */
+ * V(1,1), FP64 transforms, and coarse_slabs 8 (the shape fields are left at
+ * zero). */
 void sth_problem_default(sth_problem* p);
 
 /* Device bytes that sth_setup would allocate for this problem (factors,
@@ -193,12 +197,14 @@ int sth_host_load_1d(const sth_problem* p, double omega, double phase, int k,
 typedef enum {
     STH_K_RESIDUAL = 0, STH_K_XFORM_X = 1, STH_K_XFORM_S = 2, STH_K_TIMEMIX = 3,
     STH_K_RESTRICT = 4, STH_K_PROLONG = 5, STH_K_NORM = 6, STH_K_OTHER = 7,
-    STH_K_COUNT = 8
+    STH_K_XFORM_2D = 8,     /* both axes of 2-D images in one kernel */
+    STH_K_COUNT = 9
 } sth_kernel_class;
 
-/* Start (enable=1) or stop (0) recording an event pair around every launch
- * on this handle; starting clears previous records. */
-int sth_timing(sth_handle* h, int enable);
+/* Record an event pair around every launch of the kernel classes whose bit
+ * (1 << sth_kernel_class) is set in class_mask; 0 stops recording.  A
+ * nonzero mask clears the previous records. */
+int sth_timing(sth_handle* h, unsigned class_mask);
 
 /* Totals over the recorded launches of one class: launches, summed kernel
  * time in ms, summed algorithmic FLOPs and HBM bytes (the minimum traffic

@@ -7,8 +7,10 @@ consecutive slabs into one; the smoother is damped block Jacobi
     u <- u + omega D^{-1} (f - L_h u),   D = diag(A_n),  omega = 1/2.
 The paper defers the remaining multigrid details to its references.  The
 readings used (and listed as such in the design notes):
-  * V(nu1, nu2) cycle, coarsening in time only, down to one slab (or an odd
-    slab count, which is then solved exactly by forward substitution);
+  * V(nu1, nu2) cycle, coarsening in time only while the slab count is
+    even and larger than `coarse_slabs`; the coarsest level is solved
+    exactly by forward substitution (the coarse grid solver is the third
+    ingredient Section 3.1 names without fixing it);
   * a coarse slab covers two fine slabs with the same number of time
     elements and the same degree; prolongation P is the exact embedding of
     the coarse slab space into the two fine slabs, computed here by an L2
@@ -60,7 +62,7 @@ class Level:
 
 
 class MultigridOracle:
-    def __init__(self, prob, nu1=1, nu2=1, omega=0.5, system=None):
+    def __init__(self, prob, nu1=1, nu2=1, omega=0.5, system=None, coarse_slabs=1):
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
         fine = system if system is not None else SlabSystem.assemble(prob)
@@ -68,7 +70,7 @@ class MultigridOracle:
         self.P = []
         tau = prob.tau
         Nx = prob.N_x
-        while self.levels[-1].S > 1 and self.levels[-1].S % 2 == 0:
+        while self.levels[-1].S > coarse_slabs and self.levels[-1].S % 2 == 0:
             lev = self.levels[-1]
             Pt = time_prolongation(tau, prob.n_elem_t, prob.degree)
             P = sp.kron(sp.csr_matrix(Pt), sp.identity(Nx), format="csr")

@@ -18,7 +18,7 @@ STATUS = {0: "STH_OK", -1: "STH_EINVAL", -2: "STH_ENOMEM", -3: "STH_EHIP", -4: "
           -5: "STH_ECOND", -6: "STH_ENOCONV", -7: "STH_ENODEV"}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KCLASS = {"residual": 0, "xform_x": 1, "xform_s": 2, "timemix": 3, "restrict": 4, "prolong": 5,
-          "norm": 6, "other": 7}
+          "norm": 6, "other": 7, "xform_2d": 8}
 
 
 class StatusError(RuntimeError):
@@ -32,7 +32,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int), ("degree", ctypes.c_int),
                 ("n_slabs", ctypes.c_int), ("n_elem_t", ctypes.c_int), ("T", ctypes.c_double),
                 ("theta", ctypes.c_double), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
-                ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int)]
+                ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int), ("coarse_slabs", ctypes.c_int)]
 
 
 class RhsModes(ctypes.Structure):
@@ -85,7 +85,7 @@ def load_library():
         "sth_last_error": (ctypes.c_char_p, []),
         "sth_host_factors": (i, [P(Problem), i, P(Factors)]),
         "sth_host_load_1d": (i, [P(Problem), d, d, i, _DP, _DP]),
-        "sth_timing": (i, [vp, i]),
+        "sth_timing": (i, [vp, ctypes.c_uint]),
         "sth_timing_report": (i, [vp, i, P(i), P(d), P(d), P(d)]),
     }
     for name, (res, args) in sigs.items():
@@ -103,12 +103,14 @@ def _check(code):
 
 
 def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64"):
+                 nu_post=1, prec="fp64", coarse_slabs=None):
     p = Problem()
     load_library().sth_problem_default(ctypes.byref(p))
     p.dim, p.n_elem, p.degree, p.n_slabs, p.n_elem_t = dim, n_elem, degree, n_slabs, n_elem_t
     p.T, p.theta, p.omega, p.nu_pre, p.nu_post = T, theta, omega, nu_pre, nu_post
     p.transform_prec = PREC[prec] if isinstance(prec, str) else int(prec)
+    if coarse_slabs is not None:
+        p.coarse_slabs = int(coarse_slabs)
     return p
 
 
@@ -164,14 +166,15 @@ class Solver:
     """One discrete problem on the GPU (setup factors and workspaces)."""
 
     def __init__(self, dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", stream=None):
+                 nu_post=1, prec="fp64", coarse_slabs=None, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP slab solver needs a gfx950 device")
         self.lib = load_library()
         self.problem = make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T, theta, omega, nu_pre,
-                                    nu_post, prec)
+                                    nu_post, prec, coarse_slabs)
         self.shape = dict(dim=dim, n_elem=n_elem, degree=degree, n_slabs=n_slabs, n_elem_t=n_elem_t)
+        self.coarse_slabs = self.problem.coarse_slabs
         h = ctypes.c_void_p()
         _check(self.lib.sth_setup(ctypes.byref(self.problem), _stream(stream), ctypes.byref(h)))
         self.h = h
@@ -249,8 +252,9 @@ class Solver:
         _check(self.lib.sth_norm(self.h, _ptr(v), ctypes.byref(out), _stream(stream)))
         return out.value
 
-    def timing(self, enable):
-        _check(self.lib.sth_timing(self.h, int(enable)))
+    def timing(self, class_mask):
+        """Event timing of the kernel classes in class_mask (bit per class, 0 = off)."""
+        _check(self.lib.sth_timing(self.h, int(class_mask)))
 
     def timing_report(self, kclass):
         c = ctypes.c_int()

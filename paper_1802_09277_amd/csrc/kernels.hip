@@ -88,6 +88,7 @@ __global__ __launch_bounds__(256) void k_residual(int p, int n, const double* __
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[t] = 0.0;
 
+#pragma unroll
     for (int tr = 0; tr <= NT; ++tr) {
         const double* src;
         if (tr < NT) {
@@ -185,12 +186,176 @@ static hipError_t residual_dim(int Nt, int p, int n, const double* M1b, const do
     return hipGetLastError();
 }
 
+// 2D residual with whole rows per block: thread column x (one per thread,
+// TXT >= n threads across a row), RT thread rows, RY output rows per thread.
+// Per time row of u: the (TY + 2P) x n strip is staged in LDS (x halo zero),
+// the x pass (M_1, K_1 along x) goes to LDS, the y pass and the temporal
+// contraction stay in registers.
+constexpr int kRY = 8;
+
+template <int NT, int P>
+__global__ __launch_bounds__(512) void k_residual2d(int n, int TXT, int RT, const double* __restrict__ M1b,
+                                                     const double* __restrict__ K1b, TimeOp op,
+                                                     const double* __restrict__ f,
+                                                     const double* __restrict__ u, double* __restrict__ r,
+                                                     long s0, double sign) {
+    constexpr int B = 2 * P + 1;
+    extern __shared__ double sm[];
+    const int TY = RT * kRY, HY = TY + 2 * P, W = n + 2 * P;
+    double* Us = sm;
+    double* As = Us + HY * W;
+    double* Bs = As + HY * n;
+    double* byM = Bs + HY * n;
+    double* byK = byM + TY * B;
+    const int nthreads = TXT * RT;
+    const int tid = threadIdx.x;
+    const int xr = tid % TXT, yr = tid / TXT;
+    const int y0 = blockIdx.x * TY;
+    const long s = s0 + blockIdx.y;
+    const long Nx = (long)n * n, slab = NT * Nx;
+    for (int i = tid; i < HY * 2 * P; i += nthreads) {
+        int rr = i / (2 * P), c = i % (2 * P);
+        Us[rr * W + (c < P ? c : n + c)] = 0.0;
+    }
+    for (int i = tid; i < TY * B; i += nthreads) {
+        int gy = y0 + i / B;
+        byM[i] = gy < n ? M1b[(long)gy * B + i % B] : 0.0;
+        byK[i] = gy < n ? K1b[(long)gy * B + i % B] : 0.0;
+    }
+    const bool xin = xr < n;
+    double bxM[B], bxK[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+        bxM[k] = xin ? M1b[(long)xr * B + k] : 0.0;
+        bxK[k] = xin ? K1b[(long)xr * B + k] : 0.0;
+    }
+    double acc[kRY][NT];
+#pragma unroll
+    for (int i = 0; i < kRY; ++i)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[i][t] = 0.0;
+
+#pragma unroll
+    for (int tr = 0; tr <= NT; ++tr) {
+        const double* src;
+        if (tr < NT) {
+            src = u + s * slab + (long)tr * Nx;
+        } else {
+            if (s == 0) break;
+            src = u + (s - 1) * slab + (long)(NT - 1) * Nx;   // end trace of slab n-1
+        }
+        __syncthreads();
+        if (xin) {
+            for (int rr = yr; rr < HY; rr += RT) {
+                int gy = y0 - P + rr;
+                Us[rr * W + P + xr] = (gy >= 0 && gy < n) ? src[(long)gy * n + xr] : 0.0;
+            }
+        }
+        __syncthreads();
+        if (xin) {
+            for (int rr = yr; rr < HY; rr += RT) {
+                const double* row = Us + rr * W + xr;
+                double a = 0.0, b = 0.0;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    a += bxM[k] * row[k];
+                    b += bxK[k] * row[k];
+                }
+                As[rr * n + xr] = a;
+                Bs[rr * n + xr] = b;
+            }
+        }
+        __syncthreads();
+        if (xin) {
+#pragma unroll
+            for (int i = 0; i < kRY; ++i) {
+                const int ly = yr + RT * i;
+                double Mu = 0.0, Ku = 0.0;
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    double a = As[(ly + k) * n + xr], b = Bs[(ly + k) * n + xr];
+                    double m = byM[ly * B + k];
+                    Mu += m * a;
+                    Ku += byK[ly * B + k] * a + m * b;
+                }
+                if (tr < NT) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) acc[i][t] -= op.Kt[t * kNt + tr] * Mu + op.Mt[t * kNt + tr] * Ku;
+                } else {
+                    acc[i][0] += Mu;
+                }
+            }
+        }
+    }
+    if (!xin) return;
+#pragma unroll
+    for (int i = 0; i < kRY; ++i) {
+        const int gy = y0 + yr + RT * i;
+        if (gy >= n) continue;
+        const long off = s * slab + (long)gy * n + xr;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double fv = f ? f[off + (long)t * Nx] : 0.0;
+            r[off + (long)t * Nx] = fv + sign * acc[i][t];
+        }
+    }
+}
+
+template <int NT, int P>
+static hipError_t residual2d_launch(int n, const double* M1b, const double* K1b, const TimeOp& op,
+                                    const double* f, const double* u, double* r, long s0, long ns, double sign,
+                                    hipStream_t st) {
+    int TXT = (n + 7) / 8 * 8;
+    int RT = TXT >= 256 ? 1 : 256 / TXT;
+    int TY = RT * kRY, HY = TY + 2 * P;
+    size_t shm = sizeof(double) * ((size_t)HY * (n + 2 * P) + 2 * (size_t)HY * n + 2 * (size_t)TY * (2 * P + 1));
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_residual2d<NT, P>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    dim3 grid((unsigned)((n + TY - 1) / TY), (unsigned)ns);
+    hipLaunchKernelGGL((k_residual2d<NT, P>), grid, dim3(TXT * RT), shm, st, n, TXT, RT, M1b, K1b, op, f, u, r,
+                       s0, sign);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t residual2d_nt(int Nt, int n, const double* M1b, const double* K1b, const TimeOp& op,
+                                const double* f, const double* u, double* r, long s0, long ns, double sign,
+                                hipStream_t st) {
+    switch (Nt) {
+        case 2: if (P + 1 <= 2) return residual2d_launch<2, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st); break;
+        case 3: if (P + 1 <= 3) return residual2d_launch<3, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st); break;
+        case 4: if (P + 1 <= 4) return residual2d_launch<4, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st); break;
+        case 5: return residual2d_launch<5, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        case 6: return residual2d_launch<6, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        case 7: return residual2d_launch<7, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        case 8: return residual2d_launch<8, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
                            const TimeOp& op, const double* f, const double* u, double* r,
                            long s0, long ns, double sign, hipStream_t st) {
     if (ns <= 0) return hipSuccess;
     if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
-    if (dim == 2) return residual_dim<2>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+    if (dim == 2) {
+        int TXT = (n + 7) / 8 * 8, RT = TXT >= 256 ? 1 : 256 / TXT;
+        int TY = RT * kRY, HY = TY + 2 * p;
+        size_t shm = sizeof(double) * ((size_t)HY * (n + 2 * p) + 2 * (size_t)HY * n + 2 * (size_t)TY * (2 * p + 1));
+        if (shm > 150 * 1024 || TXT * RT > 512) return residual_dim<2>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        switch (p) {
+            case 1: return residual2d_nt<1>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+            case 2: return residual2d_nt<2>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+            case 3: return residual2d_nt<3>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+            case 4: return residual2d_nt<4>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        }
+    }
     if (dim == 3) return residual_dim<3>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
     return hipErrorInvalidValue;
 }
@@ -332,29 +497,188 @@ hipError_t launch_xform_s(const double* in, double* out, const double* T, int n,
 }
 
 // ---------------------------------------------------------------------------
+// Both spatial axes of a 2-D image in one kernel: U (padded to NP x NP) and
+// one image stay in LDS; every block walks over images.  DIR 0 (forward):
+// out = U^T R U.  DIR 1 (inverse): Z = U Y U^T, then the epilogue EPI
+// (0 store, 1 out += alpha Z, 2 out = alpha Z).  Eight waves share the
+// NT16 x NT16 output tiles of each GEMM; the intermediate product goes back
+// into the image buffer.  CT is the compute type: double (MFMA f64 16x16x4)
+// or float (MFMA f32 16x16x4, FP32 accumulation); global data stay FP64.
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename CT> struct Mfma16;
+template <> struct Mfma16<double> {
+    typedef d4 acc_t;
+    // D[i][j] of lane l, register r: i = l/16 + 4r, j = l%16
+    static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma16<float> {
+    typedef f4 acc_t;
+    // D[i][j] of lane l, register r: i = 4(l/16) + r, j = l%16
+    static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename CT, int DIR, int NT16, int EPI>
+__global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, double* __restrict__ out,
+                                                 const double* __restrict__ Upad, int n, long nimg,
+                                                 double alpha) {
+    using M = Mfma16<CT>;
+    typedef typename M::acc_t acc_t;
+    constexpr int NP = NT16 * 16, LD = NP + 1;
+    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
+    extern __shared__ double sm_raw[];
+    CT* Us = reinterpret_cast<CT*>(sm_raw);   // U[k][j], row stride LD
+    CT* Is = Us + NP * LD;                    // image / intermediate, row stride LD
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int kp = (n + 3) & ~3;
+    for (int i = tid; i < NP * NP; i += 512) {
+        int r = i / NP, c = i % NP;
+        Us[r * LD + c] = (CT)Upad[i];
+    }
+    const long nn = (long)n * n;
+    for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
+        __syncthreads();
+        const double* src = in + img * nn;
+        for (int i = tid; i < NP * NP; i += 512) {
+            int r = i / NP, c = i % NP;
+            Is[r * LD + c] = (r < n && c < n) ? (CT)src[(long)r * n + c] : (CT)0;
+        }
+        __syncthreads();
+        acc_t acc[TPW];
+        // first product: T1 = R U (forward) or Y U^T (inverse)
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            acc[q] = acc_t{0, 0, 0, 0};
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+                for (int k0 = 0; k0 < kp; k0 += 4) {
+                    CT a = Is[(ti * 16 + lr) * LD + k0 + lk];
+                    CT b = (DIR == 0) ? Us[(k0 + lk) * LD + tj * 16 + lr] : Us[(tj * 16 + lr) * LD + k0 + lk];
+                    acc[q] = M::op(a, b, acc[q]);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) Is[(ti * 16 + M::row(lk, rr)) * LD + tj * 16 + lr] = acc[q][rr];
+            }
+        }
+        __syncthreads();
+        // second product: U^T T1 (forward) or U T1 (inverse)
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            acc[q] = acc_t{0, 0, 0, 0};
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+                for (int k0 = 0; k0 < kp; k0 += 4) {
+                    CT a = (DIR == 0) ? Us[(k0 + lk) * LD + ti * 16 + lr] : Us[(ti * 16 + lr) * LD + k0 + lk];
+                    CT b = Is[(k0 + lk) * LD + tj * 16 + lr];
+                    acc[q] = M::op(a, b, acc[q]);
+                }
+            }
+        }
+        double* dst = out + img * nn;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+                const int j = tj * 16 + lr;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int i = ti * 16 + M::row(lk, rr);
+                    if (i < n && j < n) {
+                        double v = (double)acc[q][rr];
+                        double* o = dst + (long)i * n + j;
+                        if (EPI == 0) *o = v;
+                        else if (EPI == 1) *o += alpha * v;
+                        else *o = alpha * v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename CT, int DIR, int NT16, int EPI>
+static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
+                                 hipStream_t st) {
+    constexpr int NP = NT16 * 16;
+    size_t shm = sizeof(CT) * 2 * (size_t)NP * (NP + 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    long blocks = nimg < 2048 ? nimg : 2048;
+    hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Upad,
+                       n, nimg, alpha);
+    return hipGetLastError();
+}
+
+template <typename CT, int DIR, int EPI>
+static hipError_t xform2d_np(const double* in, double* out, const double* Upad, int n, int np, long nimg,
+                             double alpha, hipStream_t st) {
+    switch (np / 16) {
+        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st);
+        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st);
+        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st);
+        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st);
+        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st);
+        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename CT>
+static hipError_t xform2d_prec(int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
+                               long nimg, double alpha, hipStream_t st) {
+    if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st);
+    if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st);
+    if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st);
+    return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st);
+}
+
+bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 16 == 0; }
+
+hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
+                          int np, long nimg, double alpha, hipStream_t st) {
+    if (nimg <= 0) return hipSuccess;
+    if (!xform2d_supported(np)) return hipErrorInvalidValue;
+    if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st);
+    if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
 // temporal transform and shifted divide
 // ---------------------------------------------------------------------------
 template <int NT>
-__global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
-                                                 long Nx, const double* __restrict__ in,
-                                                 double* __restrict__ out, long total) {
-    long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= total) return;
-    long s = idx / Nx, m = idx % Nx;
-    int jx = (int)(m % n);
-    long rest = m / n;
-    int jy = (int)(rest % n);
-    double mu = mu1[jx] + mu1[jy];
-    if (dim == 3) mu += mu1[rest / n];
-    const double* g = in + s * NT * Nx + m;
+__device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, const double* g, double* z) {
     double h[NT], y[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) h[t] = 0.0;
 #pragma unroll
     for (int t2 = 0; t2 < NT; ++t2) {
-        double v = g[(long)t2 * Nx];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) h[t] += tm.W[t * kNt + t2] * v;
+        for (int t = 0; t < NT; ++t) h[t] += tm.W[t * kNt + t2] * g[t2];
     }
 #pragma unroll
     for (int k = 0; k < NT; ++k) {
@@ -367,26 +691,79 @@ __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const doub
             y[k + 1] = (b * h[k] + a * h[k + 1]) / det;
         }
     }
-    double* o = out + s * NT * Nx + m;
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-        double z = 0.0;
+        double v = 0.0;
 #pragma unroll
-        for (int k = 0; k < NT; ++k) z += tm.V[t * kNt + k] * y[k];
-        o[(long)t * Nx] = z;
+        for (int k = 0; k < NT; ++k) v += tm.V[t * kNt + k] * y[k];
+        z[t] = v;
+    }
+}
+
+__device__ __forceinline__ double mode_shift(int dim, const double* mu1, int n, long m) {
+    int jx = (int)(m % n);
+    long rest = m / n;
+    int jy = (int)(rest % n);
+    double mu = mu1[jx] + mu1[jy];
+    if (dim == 3) mu += mu1[rest / n];
+    return mu;
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
+                                                 long Nx, const double* __restrict__ in,
+                                                 double* __restrict__ out, long total) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    const double* gp = in + s * NT * Nx + m;
+    double g[NT], z[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) g[t] = gp[(long)t * Nx];
+    shifted_solve<NT>(tm, mu, g, z);
+    double* o = out + s * NT * Nx + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) o[(long)t * Nx] = z[t];
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_timemix_fwdsub(int dim, TimeMix tm, const double* __restrict__ mu1,
+                                                        int n, long Nx, const double* __restrict__ in,
+                                                        double* __restrict__ out, long S) {
+    long m = (long)blockIdx.x * 256 + threadIdx.x;
+    if (m >= Nx) return;
+    double mu = mode_shift(dim, mu1, n, m);
+    double prev = 0.0;
+    for (long s = 0; s < S; ++s) {
+        const double* gp = in + s * NT * Nx + m;
+        double g[NT], z[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g[t] = gp[(long)t * Nx];
+        g[0] += prev;
+        shifted_solve<NT>(tm, mu, g, z);
+        double* o = out + s * NT * Nx + m;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) o[(long)t * Nx] = z[t];
+        prev = z[NT - 1];
     }
 }
 
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
-                          const double* in, double* out, long S, hipStream_t st) {
+                          const double* in, double* out, long S, bool fwdsub, hipStream_t st) {
     long Nx = (long)n * n * (dim == 3 ? n : 1);
     long total = S * Nx;
     if (total <= 0) return hipSuccess;
     dim3 grid((unsigned)((total + 255) / 256));
-#define STH_TM_CASE(NTV)                                                                         \
-    case NTV:                                                                                    \
-        hipLaunchKernelGGL(k_timemix<NTV>, grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out, \
-                           total);                                                               \
+    dim3 gridm((unsigned)((Nx + 255) / 256));
+#define STH_TM_CASE(NTV)                                                                              \
+    case NTV:                                                                                         \
+        if (fwdsub)                                                                                   \
+            hipLaunchKernelGGL(k_timemix_fwdsub<NTV>, gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, \
+                               out, S);                                                               \
+        else                                                                                          \
+            hipLaunchKernelGGL(k_timemix<NTV>, grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out,  \
+                               total);                                                                \
         break;
     switch (Nt) {
         STH_TM_CASE(2) STH_TM_CASE(3) STH_TM_CASE(4) STH_TM_CASE(5)

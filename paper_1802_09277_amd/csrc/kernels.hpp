@@ -40,9 +40,20 @@ hipError_t launch_xform_x(int epi, const double* in, double* out, const double* 
 hipError_t launch_xform_s(const double* in, double* out, const double* T, int n, int np,
                           long nbatch, long inner, hipStream_t st);
 
+// Both spatial axes of 2-D images (n x n each, nimg images) in one kernel:
+// dir 0: out = U^T R U; dir 1: Z = U Y U^T with epilogue epi (0 store,
+// 1 out += alpha Z, 2 out = alpha Z).  Upad is U padded to np x np; prec 0
+// computes in FP64 (MFMA f64), 1 in FP32 (MFMA f32, FP32 accumulation).
+constexpr int kXform2dMaxNp = 96;
+bool xform2d_supported(int np);
+hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
+                          long nimg, double alpha, hipStream_t st);
+
 // Per slab and spatial mode: out[:, m] = V (Z + mu_m I)^{-1} W in[:, m].
+// fwdsub: instead, one pass over the S slabs per mode with the coupling of
+// the eigenbasis, g_s = in_s + e_1 out_{s-1}[Nt-1] (forward substitution).
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
-                          const double* in, double* out, long S, hipStream_t st);
+                          const double* in, double* out, long S, bool fwdsub, hipStream_t st);
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,

@@ -44,6 +44,7 @@ struct sth_handle {
     long Nx = 0;
     double omega = 0.5;
     int nu_pre = 1, nu_post = 1;
+    int prec = 0;                       // sth_prec of the spatial transforms
     std::vector<long> lev_S;            // slabs per level
     std::vector<TimeOp> ops;
     std::vector<TimeMix> mixes;
@@ -62,6 +63,7 @@ struct sth_handle {
     double* hnorm = nullptr;            // pinned
     // timing
     bool timing = false;
+    unsigned timing_mask = 0;
     struct Rec { int cls; hipEvent_t a, b; double flops, bytes; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -80,7 +82,7 @@ struct Timed {
     hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
     Timed(sth_handle* hh, int c, double fl, double by, hipStream_t s) : h(hh), cls(c), flops(fl), bytes(by), st(s) {
-        if (!h->timing) return;
+        if (!h->timing || !((h->timing_mask >> c) & 1u)) return;
         if (h->pool_used + 2 > h->pool.size()) {
             for (int i = 0; i < 256; ++i) {
                 hipEvent_t e;
@@ -132,7 +134,7 @@ static int xform_s(sth_handle* h, const double* in, double* out, const double* T
 // u (mode 1: +=, 2: =) omega * D^{-1} in, on slabs [s0, s0+ns) of level lvl.
 // `in` may alias buf1 but not buf0.
 static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int epi, double alpha, long s0,
-                        long ns, hipStream_t st) {
+                        long ns, hipStream_t st, bool fwdsub = false) {
     long off = s0 * slab_len(h);
     in += off;
     u += off;
@@ -141,13 +143,27 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
     double* b0 = h->buf0 + off;
     double* b1 = h->buf1 + off;
     int rc;
-    if (h->dim == 2) {
+    if (h->dim == 2 && xform2d_supported(h->np)) {
+        double dof = (double)ns * slab_len(h);
+        {
+            Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, 16.0 * dof, st);
+            HIPCHK(launch_xform2d(h->prec, 0, 0, in, b0, h->Tf, h->n, h->np, rows, 1.0, st));
+        }
+        {
+            Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
+            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, fwdsub, st));
+        }
+        {
+            Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, (epi == 1 ? 24.0 : 16.0) * dof, st);
+            HIPCHK(launch_xform2d(h->prec, 1, epi, b1, u, h->Tf, h->n, h->np, rows, alpha, st));
+        }
+    } else if (h->dim == 2) {
         if ((rc = xform_x(h, 0, in, b0, h->Tf, rows * n, 1.0, st))) return rc;
         if ((rc = xform_s(h, b0, b1, h->Tf, rows, n, st))) return rc;
         {
             double dof = (double)ns * slab_len(h);
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
-            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b1, b0, ns, st));
+            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b1, b0, ns, fwdsub, st));
         }
         if ((rc = xform_s(h, b0, b1, h->Ti, rows, n, st))) return rc;
         if ((rc = xform_x(h, epi, b1, u, h->Ti, rows * n, alpha, st))) return rc;
@@ -158,7 +174,7 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
         {
             double dof = (double)ns * slab_len(h);
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
-            HIPCHK(launch_timemix(3, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, st));
+            HIPCHK(launch_timemix(3, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, fwdsub, st));
         }
         if ((rc = xform_s(h, b1, b0, h->Ti, rows, n * n, st))) return rc;          // z
         if ((rc = xform_s(h, b0, b1, h->Ti, rows * n, n, st))) return rc;          // y
@@ -176,21 +192,15 @@ static int smooth_step(sth_handle* h, int lvl, const double* f, double* u, bool 
     return slab_inverse(h, lvl, h->buf1, u, 1, h->omega, 0, ns, st);
 }
 
-// exact solve of the coarsest level by slab-wise forward substitution
+// exact solve of the coarsest level: slab-wise forward substitution
+//   u_1 = A^{-1} f_1,  u_m = A^{-1}(f_m + B u_{m-1})   (eq. equ_linear_system)
+// carried out in the spatial eigenbasis, where A = K_t (x) I + M_t (x) diag(mu)
+// and B = N_t (x) I: forward transforms of all slabs, one sequential pass over
+// the slabs per spatial mode, inverse transforms.  u is overwritten.
 static int coarse_solve(sth_handle* h, int lvl, const double* f, double* u, hipStream_t st) {
     long S = h->lev_S[lvl];
     if (S == 1) return slab_inverse(h, lvl, f, u, 2, 1.0, 0, 1, st);
-    {
-        Timed tm(h, STH_K_OTHER, 0, 8.0 * S * slab_len(h), st);
-        HIPCHK(launch_fill(u, S * slab_len(h), 0.0, st));
-    }
-    for (long m = 0; m < S; ++m) {
-        int rc = residual(h, lvl, f, u, h->buf1, m, 1, 1.0, st);     // f_m + B u_{m-1} (u_m = 0)
-        if (rc) return rc;
-        rc = slab_inverse(h, lvl, h->buf1, u, 1, 1.0, m, 1, st);
-        if (rc) return rc;
-    }
-    return STH_OK;
+    return slab_inverse(h, lvl, f, u, 2, 1.0, 0, S, st, /*fwdsub=*/true);
 }
 
 static int restrict_lvl(sth_handle* h, int lvl, const double* r, double* rc, hipStream_t st) {
@@ -262,6 +272,7 @@ static Problem to_problem(const sth_problem* p) {
     q.nu_pre = p->nu_pre;
     q.nu_post = p->nu_post;
     q.prec = p->transform_prec;
+    q.coarse_slabs = p->coarse_slabs;
     return q;
 }
 
@@ -276,6 +287,7 @@ void sth_problem_default(sth_problem* p) {
     p->nu_pre = 1;
     p->nu_post = 1;
     p->transform_prec = STH_FP64;
+    p->coarse_slabs = 8;
 }
 
 const char* sth_last_error(void) { return g_err.c_str(); }
@@ -283,7 +295,7 @@ const char* sth_last_error(void) { return g_err.c_str(); }
 static size_t level_count(const Problem& q) {
     size_t L = 1;
     long S = q.n_slabs;
-    while (S > 1 && S % 2 == 0) { S /= 2; ++L; }
+    while (S > q.coarse_slabs && S % 2 == 0) { S /= 2; ++L; }
     return L;
 }
 
@@ -334,6 +346,11 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->omega = q.omega;
     h->nu_pre = q.nu_pre;
     h->nu_post = q.nu_post;
+    h->prec = q.prec;
+    if (h->prec != STH_FP64 && !(h->dim == 2 && xform2d_supported(h->np) && h->prec == STH_FP32)) {
+        delete h;
+        return fail(STH_EINVAL, "reduced-precision transforms: FP32 needs a 2-D problem with n <= 96");
+    }
     h->L = (int)h->S.levels.size();
     for (auto& lv : h->S.levels) {
         h->lev_S.push_back(lv.S);
@@ -544,13 +561,16 @@ int sth_destroy(sth_handle* h) {
     return STH_OK;
 }
 
-int sth_timing(sth_handle* h, int enable) {
+int sth_timing(sth_handle* h, unsigned class_mask) {
     if (!h) return fail(STH_EINVAL, "null handle");
-    if (enable) {
+    if (class_mask) {
+        // wait for outstanding records before their events are reused
+        for (auto& r : h->recs) (void)hipEventSynchronize(r.b);
         h->recs.clear();
         h->pool_used = 0;
     }
-    h->timing = enable != 0;
+    h->timing = class_mask != 0;
+    h->timing_mask = class_mask;
     return STH_OK;
 }
 

@@ -579,6 +579,7 @@ std::string validate(const Problem& p) {
     if (!(p.omega > 0 && p.omega <= 1)) os << "omega must be in (0,1]; ";
     if (p.nu_pre < 0 || p.nu_post < 0 || p.nu_pre + p.nu_post < 1) os << "nu_pre, nu_post >= 0 with a positive sum; ";
     if (p.prec < 0 || p.prec > 2) os << "transform_prec must be 0, 1 or 2; ";
+    if (p.coarse_slabs < 1) os << "coarse_slabs must be >= 1; ";
     if (os.str().empty() && p.n_elem + p.degree - 2 >= 1) {
         double len = double(p.n_slabs) * (p.n_elem_t + p.degree);
         for (int a = 0; a < p.dim; ++a) len *= (p.n_elem + p.degree - 2);
@@ -757,7 +758,7 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
             err = os.str();
             return st;
         }
-        bool coarsen = (S > 1 && S % 2 == 0);
+        bool coarsen = (S > p.coarse_slabs && S % 2 == 0);
         if (coarsen) L.Pt = Pt;
         s.levels.push_back(L);
         if (!coarsen) break;

@@ -47,6 +47,7 @@ struct Problem {
     int dim, n_elem, degree, n_slabs, n_elem_t;
     double T, theta, omega;
     int nu_pre, nu_post, prec;
+    int coarse_slabs;
     int n() const { return n_elem + degree - 2; }
     int Nt() const { return n_elem_t + degree; }
     double tau() const { return T / n_slabs; }

@@ -23,19 +23,27 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 SHAPES = {
-    "2d_p2": dict(dim=2, n_elem=6, degree=2, n_slabs=4, n_elem_t=2),
-    "2d_ragged_p3": dict(dim=2, n_elem=37, degree=3, n_slabs=6, n_elem_t=2),
-    "2d_p1_net3": dict(dim=2, n_elem=20, degree=1, n_slabs=8, n_elem_t=3),
-    "2d_p4": dict(dim=2, n_elem=14, degree=4, n_slabs=2, n_elem_t=2),
-    "3d_p2": dict(dim=3, n_elem=9, degree=2, n_slabs=4, n_elem_t=2),
-    "3d_p3": dict(dim=3, n_elem=6, degree=3, n_slabs=2, n_elem_t=1),
+    "2d_p2": dict(dim=2, n_elem=6, degree=2, n_slabs=4, n_elem_t=2, coarse_slabs=1),
+    "2d_ragged_p3": dict(dim=2, n_elem=37, degree=3, n_slabs=6, n_elem_t=2, coarse_slabs=1),
+    "2d_p1_net3": dict(dim=2, n_elem=20, degree=1, n_slabs=8, n_elem_t=3, coarse_slabs=2),
+    "2d_p4": dict(dim=2, n_elem=14, degree=4, n_slabs=2, n_elem_t=2, coarse_slabs=1),
+    "2d_16slabs": dict(dim=2, n_elem=12, degree=2, n_slabs=16, n_elem_t=2, coarse_slabs=4),
+    "3d_p2": dict(dim=3, n_elem=9, degree=2, n_slabs=4, n_elem_t=2, coarse_slabs=4),
+    "3d_p3": dict(dim=3, n_elem=6, degree=3, n_slabs=2, n_elem_t=1, coarse_slabs=1),
+    "3d_8slabs": dict(dim=3, n_elem=7, degree=2, n_slabs=8, n_elem_t=2, coarse_slabs=2),
+    # n = 98 > 96: the two-kernel (per-axis) transform path of large images
+    "2d_n98_axiswise": dict(dim=2, n_elem=98, degree=2, n_slabs=2, n_elem_t=2, coarse_slabs=1),
 }
+
+
+def _shape(name):
+    return {k: v for k, v in SHAPES[name].items() if k != "coarse_slabs"}
 
 
 @functools.lru_cache(maxsize=None)
 def oracle_for(name):
-    prob = OProblem(**SHAPES[name])
-    mg = MultigridOracle(prob)
+    prob = OProblem(**_shape(name))
+    mg = MultigridOracle(prob, coarse_slabs=SHAPES[name]["coarse_slabs"])
     return prob, mg
 
 
@@ -113,7 +121,7 @@ def test_smoothing_steps(name):
     assert rel_max(host(u), mg.smooth(0, f, u0, 2)) <= 1e-11
 
 
-@pytest.mark.parametrize("name", [n for n in SHAPES if SHAPES[n]["n_slabs"] % 2 == 0])
+@pytest.mark.parametrize("name", [n for n in SHAPES if SHAPES[n]["n_slabs"] > SHAPES[n]["coarse_slabs"]])
 def test_transfers(name):
     banner(name, "transfers")
     prob, mg = oracle_for(name)

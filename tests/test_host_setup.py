@@ -71,9 +71,12 @@ def test_setup_matches_oracle_and_identities(shape):
 
 
 def test_level_count():
-    assert sth.host_factors(level=0, dim=2, n_elem=4, degree=2, n_slabs=16, n_elem_t=2)["n_levels"] == 5
-    assert sth.host_factors(level=0, dim=2, n_elem=4, degree=2, n_slabs=12, n_elem_t=2)["n_levels"] == 3
-    assert sth.host_factors(level=0, dim=2, n_elem=4, degree=2, n_slabs=1, n_elem_t=2)["n_levels"] == 1
+    kw = dict(level=0, dim=2, n_elem=4, degree=2, n_elem_t=2)
+    assert sth.host_factors(n_slabs=16, coarse_slabs=1, **kw)["n_levels"] == 5
+    assert sth.host_factors(n_slabs=12, coarse_slabs=1, **kw)["n_levels"] == 3
+    assert sth.host_factors(n_slabs=1, coarse_slabs=1, **kw)["n_levels"] == 1
+    assert sth.host_factors(n_slabs=256, **kw)["n_levels"] == 6          # default: coarsest <= 8 slabs
+    assert sth.host_factors(n_slabs=8, **kw)["n_levels"] == 1
 
 
 def test_guard_mt_not_positive():
@@ -88,7 +91,7 @@ def test_guard_mt_not_positive():
 
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(degree=5), dict(n_elem=1), dict(n_slabs=0),
                                  dict(n_elem_t=7), dict(omega=0.0), dict(nu_pre=0, nu_post=0),
-                                 dict(prec=3), dict(theta=-1.0)])
+                                 dict(prec=3), dict(theta=-1.0), dict(coarse_slabs=0)])
 def test_invalid_problems_rejected(bad):
     kw = dict(dim=2, n_elem=4, degree=2, n_slabs=4, n_elem_t=2)
     kw.update(bad)
