@@ -147,6 +147,13 @@ int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream);
 int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
               int* iters, double* relres, void* stream);
 
+/* Graph replay of the solve iterations (default on): on a non-default
+ * stream sth_solve captures one iteration (V-cycle, residual, norm, scalar
+ * read) into a HIP graph for the given (f, u, stream) and replays it.
+ * enable = 0 launches every kernel individually; so does kernel timing
+ * (sth_timing), which needs events around the individual launches. */
+int sth_use_graphs(sth_handle* h, int enable);
+
 /* Level transfers (Section 3.1, time coarsening by combining two slabs):
  * rc <- (P_t^T (x) I) r on slab pairs of `level` (rc has the slab count of
  * level+1), and u <- u + (P_t (x) I) ec.  Vectors of a coarse level have

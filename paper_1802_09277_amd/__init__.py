@@ -86,6 +86,7 @@ def load_library():
         "sth_host_factors": (i, [P(Problem), i, P(Factors)]),
         "sth_host_load_1d": (i, [P(Problem), d, d, i, _DP, _DP]),
         "sth_timing": (i, [vp, ctypes.c_uint]),
+        "sth_use_graphs": (i, [vp, i]),
         "sth_timing_report": (i, [vp, i, P(i), P(d), P(d), P(d)]),
     }
     for name, (res, args) in sigs.items():
@@ -246,6 +247,10 @@ class Solver:
     def prolong_add(self, level, ec, u, stream=None):
         _check(self.lib.sth_prolong_add(self.h, level, _ptr(ec), _ptr(u), _stream(stream)))
         return u
+
+    def use_graphs(self, enable):
+        """Graph replay of solve iterations on non-default streams (default on)."""
+        _check(self.lib.sth_use_graphs(self.h, int(enable)))
 
     def norm(self, v, stream=None):
         out = ctypes.c_double()

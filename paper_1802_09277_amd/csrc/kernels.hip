@@ -191,11 +191,13 @@ static hipError_t residual_dim(int Nt, int p, int n, const double* M1b, const do
 // Per time row of u: the (TY + 2P) x n strip is staged in LDS (x halo zero),
 // the x pass (M_1, K_1 along x) goes to LDS, the y pass and the temporal
 // contraction stay in registers.
-constexpr int kRY = 8;
+constexpr int kRY = 4;
 
-template <int NT, int P>
+// MAXR: rows of the (TY + 2P)-row strip that one thread stages (RT = 1:
+// kRY + 2P; RT >= 2: at most kRY + P)
+template <int NT, int P, int MAXR>
 __global__ __launch_bounds__(512) void k_residual2d(int n, int TXT, int RT, const double* __restrict__ M1b,
-                                                     const double* __restrict__ K1b, TimeOp op,
+                                                     const double* __restrict__ K1b, const double* __restrict__ ktmt,
                                                      const double* __restrict__ f,
                                                      const double* __restrict__ u, double* __restrict__ r,
                                                      long s0, double sign) {
@@ -235,22 +237,37 @@ __global__ __launch_bounds__(512) void k_residual2d(int n, int TXT, int RT, cons
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[i][t] = 0.0;
 
+    // rows of u needed per time row: staged through registers one time row
+    // ahead, so the global loads of row tr+1 overlap the LDS passes of row tr
+    const int NR = (s > 0) ? NT + 1 : NT;
+    double pre[MAXR];
+    auto load_rows = [&](int tr) {
+        const double* src = (tr < NT) ? u + s * slab + (long)tr * Nx
+                                       : u + (s - 1) * slab + (long)(NT - 1) * Nx;   // end trace of slab n-1
 #pragma unroll
-    for (int tr = 0; tr <= NT; ++tr) {
-        const double* src;
-        if (tr < NT) {
-            src = u + s * slab + (long)tr * Nx;
-        } else {
-            if (s == 0) break;
-            src = u + (s - 1) * slab + (long)(NT - 1) * Nx;   // end trace of slab n-1
+        for (int k = 0; k < MAXR; ++k) {
+            const int rr = yr + RT * k, gy = y0 - P + rr;
+            pre[k] = (xin && rr < HY && gy >= 0 && gy < n) ? src[(long)gy * n + xr] : 0.0;
+        }
+    };
+    load_rows(0);
+#pragma unroll 1
+    for (int tr = 0; tr < NR; ++tr) {
+        // column tr of K_t and M_t: uniform loads from the device copy
+        double kc[NT], mc[NT];
+        const int trc = tr < NT ? tr : 0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            kc[t] = ktmt[t * kNt + trc];
+            mc[t] = ktmt[kNt * kNt + t * kNt + trc];
         }
         __syncthreads();
-        if (xin) {
-            for (int rr = yr; rr < HY; rr += RT) {
-                int gy = y0 - P + rr;
-                Us[rr * W + P + xr] = (gy >= 0 && gy < n) ? src[(long)gy * n + xr] : 0.0;
-            }
+#pragma unroll
+        for (int k = 0; k < MAXR; ++k) {
+            const int rr = yr + RT * k;
+            if (xin && rr < HY) Us[rr * W + P + xr] = pre[k];
         }
+        if (tr + 1 < NR) load_rows(tr + 1);
         __syncthreads();
         if (xin) {
             for (int rr = yr; rr < HY; rr += RT) {
@@ -280,7 +297,7 @@ __global__ __launch_bounds__(512) void k_residual2d(int n, int TXT, int RT, cons
                 }
                 if (tr < NT) {
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) acc[i][t] -= op.Kt[t * kNt + tr] * Mu + op.Mt[t * kNt + tr] * Ku;
+                    for (int t = 0; t < NT; ++t) acc[i][t] -= kc[t] * Mu + mc[t] * Ku;
                 } else {
                     acc[i][0] += Mu;
                 }
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(512) void k_residual2d(int n, int TXT, int RT, cons
 }
 
 template <int NT, int P>
-static hipError_t residual2d_launch(int n, const double* M1b, const double* K1b, const TimeOp& op,
+static hipError_t residual2d_launch(int n, const double* M1b, const double* K1b, const double* ktmt,
                                     const double* f, const double* u, double* r, long s0, long ns, double sign,
                                     hipStream_t st) {
     int TXT = (n + 7) / 8 * 8;
@@ -311,36 +328,43 @@ static hipError_t residual2d_launch(int n, const double* M1b, const double* K1b,
     size_t shm = sizeof(double) * ((size_t)HY * (n + 2 * P) + 2 * (size_t)HY * n + 2 * (size_t)TY * (2 * P + 1));
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_residual2d<NT, P>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_residual2d<NT, P, kRY + 2 * P>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)k_residual2d<NT, P, kRY + P>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     dim3 grid((unsigned)((n + TY - 1) / TY), (unsigned)ns);
-    hipLaunchKernelGGL((k_residual2d<NT, P>), grid, dim3(TXT * RT), shm, st, n, TXT, RT, M1b, K1b, op, f, u, r,
-                       s0, sign);
+    if (RT == 1)
+        hipLaunchKernelGGL((k_residual2d<NT, P, kRY + 2 * P>), grid, dim3(TXT * RT), shm, st, n, TXT, RT, M1b, K1b,
+                           ktmt, f, u, r, s0, sign);
+    else
+        hipLaunchKernelGGL((k_residual2d<NT, P, kRY + P>), grid, dim3(TXT * RT), shm, st, n, TXT, RT, M1b, K1b,
+                           ktmt, f, u, r, s0, sign);
     return hipGetLastError();
 }
 
 template <int P>
-static hipError_t residual2d_nt(int Nt, int n, const double* M1b, const double* K1b, const TimeOp& op,
+static hipError_t residual2d_nt(int Nt, int n, const double* M1b, const double* K1b, const double* ktmt,
                                 const double* f, const double* u, double* r, long s0, long ns, double sign,
                                 hipStream_t st) {
     switch (Nt) {
-        case 2: if (P + 1 <= 2) return residual2d_launch<2, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st); break;
-        case 3: if (P + 1 <= 3) return residual2d_launch<3, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st); break;
-        case 4: if (P + 1 <= 4) return residual2d_launch<4, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st); break;
-        case 5: return residual2d_launch<5, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
-        case 6: return residual2d_launch<6, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
-        case 7: return residual2d_launch<7, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
-        case 8: return residual2d_launch<8, P>(n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+        case 2: if (P + 1 <= 2) return residual2d_launch<2, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st); break;
+        case 3: if (P + 1 <= 3) return residual2d_launch<3, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st); break;
+        case 4: if (P + 1 <= 4) return residual2d_launch<4, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st); break;
+        case 5: return residual2d_launch<5, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
+        case 6: return residual2d_launch<6, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
+        case 7: return residual2d_launch<7, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
+        case 8: return residual2d_launch<8, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
         default: break;
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
-                           const TimeOp& op, const double* f, const double* u, double* r,
+                           const TimeOp& op, const double* ktmt, const double* f, const double* u, double* r,
                            long s0, long ns, double sign, hipStream_t st) {
     if (ns <= 0) return hipSuccess;
     if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
@@ -350,10 +374,10 @@ hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, con
         size_t shm = sizeof(double) * ((size_t)HY * (n + 2 * p) + 2 * (size_t)HY * n + 2 * (size_t)TY * (2 * p + 1));
         if (shm > 150 * 1024 || TXT * RT > 512) return residual_dim<2>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
         switch (p) {
-            case 1: return residual2d_nt<1>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
-            case 2: return residual2d_nt<2>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
-            case 3: return residual2d_nt<3>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
-            case 4: return residual2d_nt<4>(Nt, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
+            case 1: return residual2d_nt<1>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
+            case 2: return residual2d_nt<2>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
+            case 3: return residual2d_nt<3>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
+            case 4: return residual2d_nt<4>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, st);
         }
     }
     if (dim == 3) return residual_dim<3>(Nt, p, n, M1b, K1b, op, f, u, r, s0, ns, sign, st);
@@ -656,6 +680,164 @@ static hipError_t xform2d_prec(int dir, int epi, const double* in, double* out, 
     return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st);
 }
 
+// ---------------------------------------------------------------------------
+// BF16x3 variant: every operand x is split into x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi); a product is accumulated in FP32 from the three
+// MFMA bf16 products hi*hi + hi*lo + lo*hi (the lo*lo term is below the
+// FP32 accumulation error).  out = M (In M^T) per image, with M = U^T for
+// the forward and M = U for the inverse transform, so one matrix serves
+// both products.  MFMA f32 16x16x16 bf16: lane l supplies A[l%16][4(l/16)+e]
+// and B[4(l/16)+e][l%16] (e = 0..3, one 8-byte LDS read each when A is
+// stored [i][k] and B as [j][k]); D[4(l/16)+r][l%16] in register r.
+// ---------------------------------------------------------------------------
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+    unsigned u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);            // round to nearest even
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ __forceinline__ void split_bf16(double v, unsigned short* hi, unsigned short* lo) {
+    float x = (float)v;
+    unsigned short h = to_bf16(x);
+    *hi = h;
+    *lo = to_bf16(x - from_bf16(h));
+}
+
+template <int NT16, int EPI>
+__global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict__ in, double* __restrict__ out,
+                                                        const double* __restrict__ Mpad, int n, long nimg,
+                                                        double alpha) {
+    constexpr int NP = NT16 * 16, LDB = NP + 8;     // row stride in bf16 elements (keeps 8-byte alignment)
+    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
+    extern __shared__ double sm_raw[];
+    unsigned short* Mh = reinterpret_cast<unsigned short*>(sm_raw);
+    unsigned short* Ml = Mh + NP * LDB;
+    unsigned short* Ih = Ml + NP * LDB;
+    unsigned short* Il = Ih + NP * LDB;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int i = tid; i < NP * NP; i += 512) {
+        int r = i / NP, c = i % NP;
+        split_bf16(Mpad[i], &Mh[r * LDB + c], &Ml[r * LDB + c]);
+    }
+    const long nn = (long)n * n;
+    for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
+        __syncthreads();
+        const double* src = in + img * nn;
+        for (int i = tid; i < NP * NP; i += 512) {
+            int r = i / NP, c = i % NP;
+            double v = (r < n && c < n) ? src[(long)r * n + c] : 0.0;
+            split_bf16(v, &Ih[r * LDB + c], &Il[r * LDB + c]);
+        }
+        __syncthreads();
+        f4 acc[TPW];
+        // T1 = In M^T : A = In[i][k] (stored [i][k]), B[k][j] = M[j][k] (stored [j][k])
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+                for (int k0 = 0; k0 < NP; k0 += 16) {
+                    const int ao = (ti * 16 + lr) * LDB + k0 + 4 * lk, bo = (tj * 16 + lr) * LDB + k0 + 4 * lk;
+                    s4 ah = *reinterpret_cast<const s4*>(&Ih[ao]), al = *reinterpret_cast<const s4*>(&Il[ao]);
+                    s4 bh = *reinterpret_cast<const s4*>(&Mh[bo]), bl = *reinterpret_cast<const s4*>(&Ml[bo]);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+        // T1 is the B operand of the second product: store T1[k=i][j] at [j][i]
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int i = ti * 16 + 4 * lk + rr, j = tj * 16 + lr;
+                    split_bf16((double)acc[q][rr], &Ih[j * LDB + i], &Il[j * LDB + i]);
+                }
+            }
+        }
+        __syncthreads();
+        // out = M T1 : A = M[i][k] (stored [i][k]), B = T1 (stored [j][k])
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+                for (int k0 = 0; k0 < NP; k0 += 16) {
+                    const int ao = (ti * 16 + lr) * LDB + k0 + 4 * lk, bo = (tj * 16 + lr) * LDB + k0 + 4 * lk;
+                    s4 ah = *reinterpret_cast<const s4*>(&Mh[ao]), al = *reinterpret_cast<const s4*>(&Ml[ao]);
+                    s4 bh = *reinterpret_cast<const s4*>(&Ih[bo]), bl = *reinterpret_cast<const s4*>(&Il[bo]);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[q], 0, 0, 0);
+                }
+            }
+        }
+        double* dst = out + img * nn;
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+                const int j = tj * 16 + lr;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int i = ti * 16 + 4 * lk + rr;
+                    if (i < n && j < n) {
+                        double v = (double)acc[q][rr];
+                        double* o = dst + (long)i * n + j;
+                        if (EPI == 0) *o = v;
+                        else if (EPI == 1) *o += alpha * v;
+                        else *o = alpha * v;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NT16, int EPI>
+static hipError_t xform2d_bf16_launch(const double* in, double* out, const double* Mpad, int n, long nimg,
+                                      double alpha, hipStream_t st) {
+    constexpr int NP = NT16 * 16;
+    size_t shm = sizeof(unsigned short) * 4 * (size_t)NP * (NP + 8);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d_bf16x3<NT16, EPI>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    long blocks = nimg < 2048 ? nimg : 2048;
+    hipLaunchKernelGGL((k_xform2d_bf16x3<NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Mpad,
+                       n, nimg, alpha);
+    return hipGetLastError();
+}
+
+template <int EPI>
+static hipError_t xform2d_bf16_np(const double* in, double* out, const double* Mpad, int n, int np, long nimg,
+                                  double alpha, hipStream_t st) {
+    switch (np / 16) {
+        case 1: return xform2d_bf16_launch<1, EPI>(in, out, Mpad, n, nimg, alpha, st);
+        case 2: return xform2d_bf16_launch<2, EPI>(in, out, Mpad, n, nimg, alpha, st);
+        case 3: return xform2d_bf16_launch<3, EPI>(in, out, Mpad, n, nimg, alpha, st);
+        case 4: return xform2d_bf16_launch<4, EPI>(in, out, Mpad, n, nimg, alpha, st);
+        case 5: return xform2d_bf16_launch<5, EPI>(in, out, Mpad, n, nimg, alpha, st);
+        case 6: return xform2d_bf16_launch<6, EPI>(in, out, Mpad, n, nimg, alpha, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 16 == 0; }
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
@@ -665,6 +847,15 @@ hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* 
     if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st);
     if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st);
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
+                                 long nimg, double alpha, hipStream_t st) {
+    if (nimg <= 0) return hipSuccess;
+    if (!xform2d_supported(np)) return hipErrorInvalidValue;
+    if (epi == 0) return xform2d_bf16_np<0>(in, out, Mpad, n, np, nimg, 1.0, st);
+    if (epi == 1) return xform2d_bf16_np<1>(in, out, Mpad, n, np, nimg, alpha, st);
+    return xform2d_bf16_np<2>(in, out, Mpad, n, np, nimg, alpha, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -26,9 +26,10 @@ struct Transfer {               // 2Nt x Nt prolongation
 
 // r = f + sign * (-(A u)_n + (B u)_{n-1}) for slabs [s0, s0+ns) of a vector
 // with slab length Nt*n^dim; the coupling uses slab s-1 of the same vector
-// when s > 0.  f may be null (treated as zero).  M1b/K1b: bands [n][2p+1].
+// when s > 0.  f may be null (treated as zero).  M1b/K1b: bands [n][2p+1];
+// ktmt: device copy of op (K_t then M_t, kNt x kNt each).
 hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
-                           const TimeOp& op, const double* f, const double* u, double* r,
+                           const TimeOp& op, const double* ktmt, const double* f, const double* u, double* r,
                            long s0, long ns, double sign, hipStream_t st);
 
 // out[line][j] (EPI) sum_k in[line][k] T[k][j] for `lines` contiguous lines
@@ -48,6 +49,12 @@ constexpr int kXform2dMaxNp = 96;
 bool xform2d_supported(int np);
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
                           long nimg, double alpha, hipStream_t st);
+
+// BF16x3 form of the same: out = M (In M^T) per image with the products
+// accumulated in FP32 from hi*hi + hi*lo + lo*hi bf16 MFMA products; pass
+// M = U^T (padded) for the forward and M = U for the inverse transform.
+hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
+                                 long nimg, double alpha, hipStream_t st);
 
 // Per slab and spatial mode: out[:, m] = V (Z + mu_m I)^{-1} W in[:, m].
 // fwdsub: instead, one pass over the S slabs per mode with the coupling of

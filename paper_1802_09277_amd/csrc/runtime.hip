@@ -55,6 +55,7 @@ struct sth_handle {
     double* mu1 = nullptr;
     double* M1b = nullptr;
     double* K1b = nullptr;
+    double* dktmt = nullptr;            // per level: K_t then M_t (kNt x kNt each)
     std::vector<double*> lu, lf;        // per level >= 1: iterate and right-hand side
     double* buf0 = nullptr;
     double* buf1 = nullptr;
@@ -68,7 +69,27 @@ struct sth_handle {
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
+    // graph of one solve iteration (V-cycle, residual, norm, scalar read)
+    bool use_graph = true;
+    bool capturing = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    const double* gf = nullptr;
+    double* gu = nullptr;
+    hipStream_t gst = nullptr;
+    unsigned gmask = 0;
+    std::vector<Rec> grecs;
+    double gms[STH_K_COUNT] = {0}, gfl[STH_K_COUNT] = {0}, gby[STH_K_COUNT] = {0};
+    int gcnt[STH_K_COUNT] = {0};
 };
+
+static void drop_graph(sth_handle* h) {
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+    h->grecs.clear();
+}
 
 static long slab_len(const sth_handle* h) { return (long)h->Nt * h->Nx; }
 
@@ -97,7 +118,9 @@ struct Timed {
     ~Timed() {
         if (!a) return;
         (void)hipEventRecord(b, st);
-        h->recs.push_back({cls, a, b, flops, bytes});
+        // inside a graph capture the pair becomes two event-record nodes that
+        // fire on every replay; their times are summed after each replay
+        (h->capturing ? h->grecs : h->recs).push_back({cls, a, b, flops, bytes});
     }
 };
 
@@ -111,7 +134,8 @@ static int residual(sth_handle* h, int lvl, const double* f, const double* u, do
     double flops = dof * ((h->dim == 2 ? 10.0 : 16.0) * B + 4.0 * h->Nt + 2.0);
     double bytes = dof * (f ? 24.0 : 16.0);
     Timed tm(h, STH_K_RESIDUAL, flops, bytes, st);
-    HIPCHK(launch_residual(h->dim, h->Nt, h->p, h->n, h->M1b, h->K1b, h->ops[lvl], f, u, r, s0, ns, sign, st));
+    HIPCHK(launch_residual(h->dim, h->Nt, h->p, h->n, h->M1b, h->K1b, h->ops[lvl],
+                           h->dktmt + (size_t)lvl * 2 * kNt * kNt, f, u, r, s0, ns, sign, st));
     return STH_OK;
 }
 
@@ -147,7 +171,10 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
         double dof = (double)ns * slab_len(h);
         {
             Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, 16.0 * dof, st);
-            HIPCHK(launch_xform2d(h->prec, 0, 0, in, b0, h->Tf, h->n, h->np, rows, 1.0, st));
+            if (h->prec == STH_BF16X3)
+                HIPCHK(launch_xform2d_bf16x3(0, in, b0, h->Ti, h->n, h->np, rows, 1.0, st));
+            else
+                HIPCHK(launch_xform2d(h->prec, 0, 0, in, b0, h->Tf, h->n, h->np, rows, 1.0, st));
         }
         {
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
@@ -155,7 +182,10 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
         }
         {
             Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, (epi == 1 ? 24.0 : 16.0) * dof, st);
-            HIPCHK(launch_xform2d(h->prec, 1, epi, b1, u, h->Tf, h->n, h->np, rows, alpha, st));
+            if (h->prec == STH_BF16X3)
+                HIPCHK(launch_xform2d_bf16x3(epi, b1, u, h->Tf, h->n, h->np, rows, alpha, st));
+            else
+                HIPCHK(launch_xform2d(h->prec, 1, epi, b1, u, h->Tf, h->n, h->np, rows, alpha, st));
         }
     } else if (h->dim == 2) {
         if ((rc = xform_x(h, 0, in, b0, h->Tf, rows * n, 1.0, st))) return rc;
@@ -347,9 +377,9 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->nu_pre = q.nu_pre;
     h->nu_post = q.nu_post;
     h->prec = q.prec;
-    if (h->prec != STH_FP64 && !(h->dim == 2 && xform2d_supported(h->np) && h->prec == STH_FP32)) {
+    if (h->prec != STH_FP64 && !(h->dim == 2 && xform2d_supported(h->np))) {
         delete h;
-        return fail(STH_EINVAL, "reduced-precision transforms: FP32 needs a 2-D problem with n <= 96");
+        return fail(STH_EINVAL, "reduced-precision transforms (FP32, BF16x3) need a 2-D problem with n <= 96");
     }
     h->L = (int)h->S.levels.size();
     for (auto& lv : h->S.levels) {
@@ -403,8 +433,14 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
-        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 1))
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 1) ||
+        !dalloc(&h->dktmt, (size_t)h->L * 2 * kNt * kNt))
         return cleanup(STH_ENOMEM, "device allocation failed");
+    std::vector<double> ktmt((size_t)h->L * 2 * kNt * kNt);
+    for (int l = 0; l < h->L; ++l) {
+        std::memcpy(&ktmt[(size_t)l * 2 * kNt * kNt], h->ops[l].Kt, sizeof(double) * kNt * kNt);
+        std::memcpy(&ktmt[(size_t)l * 2 * kNt * kNt + kNt * kNt], h->ops[l].Mt, sizeof(double) * kNt * kNt);
+    }
     h->lu.assign(h->L, nullptr);
     h->lf.assign(h->L, nullptr);
     for (int l = 1; l < h->L; ++l) {
@@ -418,6 +454,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         hipMemcpyAsync(h->mu1, h->S.mu.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->M1b, M1b.data(), M1b.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->K1b, K1b.data(), K1b.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->dktmt, ktmt.data(), ktmt.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(STH_EHIP, "upload of the setup failed");
     *out = h;
@@ -500,6 +537,56 @@ int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream) {
     return vcycle_lvl(h, 0, f, u, false, (hipStream_t)stream);
 }
 
+// one solve iteration: V-cycle, residual into buf1, its squared norm copied
+// to the pinned host scalar (not synchronised)
+static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_t st) {
+    int rc;
+    long len = h->lev_S[0] * slab_len(h);
+    if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
+    if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
+    if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
+    HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
+    return STH_OK;
+}
+
+// Captures solve_iteration into a HIP graph for (f, u, stream); replays are
+// cheaper to launch than the individual kernels.  Not used on the legacy
+// default stream, where capture is not allowed.
+static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_t st) {
+    if (!h->gexec || h->gf != f || h->gu != u || h->gst != st || h->gmask != (h->timing ? h->timing_mask : 0u)) {
+        drop_graph(h);
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        h->capturing = true;
+        int rc = solve_iteration(h, f, u, st);
+        h->capturing = false;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            h->grecs.clear();
+            return rc;
+        }
+        HIPCHK(e);
+        h->graph = g;
+        HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+        h->gf = f;
+        h->gu = u;
+        h->gst = st;
+        h->gmask = h->timing ? h->timing_mask : 0u;
+    }
+    HIPCHK(hipGraphLaunch(h->gexec, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (auto& r : h->grecs) {
+        float e = 0;
+        HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
+        h->gms[r.cls] += e;
+        h->gfl[r.cls] += r.flops;
+        h->gby[r.cls] += r.bytes;
+        h->gcnt[r.cls] += 1;
+    }
+    return STH_OK;
+}
+
 int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit, int* iters, double* relres,
               void* stream) {
     if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
@@ -514,10 +601,16 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
     int it = 0, growth = 0;
     double prev = rn;
     while (rn > rtol * fn && it < maxit) {
-        if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
+        // kernel timing records events around individual launches, so it
+        // runs the iterations eagerly
+        if (st != nullptr && h->use_graph && !h->timing) {
+            if ((rc = graph_iteration(h, f, u, st))) return rc;
+        } else {
+            if ((rc = solve_iteration(h, f, u, st))) return rc;
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        rn = std::sqrt(h->hnorm[0]);
         ++it;
-        if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
-        if ((rc = read_norm(h, h->buf1, len, st, &rn))) return rc;
         if (!std::isfinite(rn)) break;
         growth = (rn > prev) ? growth + 1 : 0;
         prev = rn;
@@ -528,6 +621,13 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
     if (!std::isfinite(rn)) return fail(STH_ENOCONV, "residual is not finite");
     if (growth >= 3) return fail(STH_ENOCONV, "residual grew over 3 consecutive cycles");
     if (rn > rtol * fn) return fail(STH_ENOCONV, "maxit reached");
+    return STH_OK;
+}
+
+int sth_use_graphs(sth_handle* h, int enable) {
+    if (!h) return fail(STH_EINVAL, "null handle");
+    h->use_graph = enable != 0;
+    if (!h->use_graph) drop_graph(h);
     return STH_OK;
 }
 
@@ -548,13 +648,14 @@ int sth_norm(sth_handle* h, const double* v, double* out, void* stream) {
 
 int sth_destroy(sth_handle* h) {
     if (!h) return STH_OK;
-    double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm};
+    double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
     for (double* q : h->lu)
         if (q) (void)hipFree(q);
     for (double* q : h->lf)
         if (q) (void)hipFree(q);
+    drop_graph(h);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
     for (auto e : h->pool) (void)hipEventDestroy(e);
     delete h;
@@ -567,7 +668,12 @@ int sth_timing(sth_handle* h, unsigned class_mask) {
         // wait for outstanding records before their events are reused
         for (auto& r : h->recs) (void)hipEventSynchronize(r.b);
         h->recs.clear();
+        drop_graph(h);
         h->pool_used = 0;
+        for (int c = 0; c < STH_K_COUNT; ++c) {
+            h->gms[c] = h->gfl[c] = h->gby[c] = 0.0;
+            h->gcnt[c] = 0;
+        }
     }
     h->timing = class_mask != 0;
     h->timing_mask = class_mask;
@@ -576,8 +682,8 @@ int sth_timing(sth_handle* h, unsigned class_mask) {
 
 int sth_timing_report(sth_handle* h, int kclass, int* launches, double* ms, double* flops, double* bytes) {
     if (!h || kclass < 0 || kclass >= STH_K_COUNT) return fail(STH_EINVAL, "bad argument");
-    int cnt = 0;
-    double t = 0, fl = 0, by = 0;
+    int cnt = h->gcnt[kclass];
+    double t = h->gms[kclass], fl = h->gfl[kclass], by = h->gby[kclass];
     for (auto& r : h->recs) {
         if (r.cls != kclass) continue;
         if (hipEventSynchronize(r.b) != hipSuccess) return fail(STH_EHIP, "event sync");

@@ -1,0 +1,49 @@
+"""Writes sampled oracle values for the full-size 2D workload (unit square,
+p = 3, 64 x 64 elements, 256 slabs x 2 time elements, 8 random modes, seed
+2): the load vector and the direct solution at 4000 seeded indices, plus
+their Euclidean norms.  Calls only the oracle (slab-wise SuperLU forward
+substitution of eq. equ_linear_system); takes about 15 minutes on one core.
+
+    python tests/golden/make_fullsize_samples.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W                                   # noqa: E402
+from oracle.spacetime import Problem, assemble_rhs       # noqa: E402
+from oracle.solve import SlabSystem                      # noqa: E402
+
+
+def main(name="C2", n_samples=4000, seed=12345):
+    cfg = W.CONFIGS[name]
+    prob = Problem(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta)
+    t0 = time.time()
+    sysm = SlabSystem.assemble(prob)
+    print(f"assembly {time.time() - t0:.1f} s", flush=True)
+    f = assemble_rhs(prob, cfg.modes())
+    print(f"load vector {time.time() - t0:.1f} s", flush=True)
+    u = sysm.forward_substitution(f)
+    print(f"direct solve {time.time() - t0:.1f} s", flush=True)
+    rel = np.linalg.norm(sysm.apply(u) - f) / np.linalg.norm(f)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(prob.n_dof, size=n_samples, replace=False))
+    path = os.path.join(HERE, f"{name.lower()}_direct_samples.txt")
+    with open(path, "w") as fh:
+        fh.write(f"# oracle direct solution of the full-size workload {name}: {cfg.note}\n")
+        fh.write("# written by tests/golden/make_fullsize_samples.py (oracle only)\n")
+        fh.write(f"# unknowns {prob.n_dof} relres_of_direct_solution {rel:.3e}\n")
+        fh.write(f"# norm_f {np.linalg.norm(f):.17e} norm_u {np.linalg.norm(u):.17e}\n")
+        fh.write("# columns: index f[index] u[index]\n")
+        for i in idx:
+            fh.write(f"{i} {f[i]:.17e} {u[i]:.17e}\n")
+    print(f"wrote {path}", flush=True)
+
+
+if __name__ == "__main__":
+    main(*sys.argv[1:2])

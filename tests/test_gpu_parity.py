@@ -184,3 +184,26 @@ def test_solve_reports_nonconvergence():
     u = s.new_vector()
     it, rr, code = s.solve(dev(f), u, rtol=1e-8, maxit=5, check=False)
     assert code == -6 and it <= 1
+
+
+def test_graph_replay_matches_eager_solve():
+    """Solve on a non-default stream (graph replay of the iterations) gives
+    bit-identical iterates to the eager launches."""
+    name = "2d_16slabs"
+    banner(name, "graph")
+    prob, mg = oracle_for(name)
+    s = solver_for(name)
+    f = dev(assemble_rhs(prob, W.random_modes(8, prob.dim)))
+    stream = torch.cuda.Stream()
+    results = []
+    for graphs in (False, True, True):
+        s.use_graphs(graphs)
+        with torch.cuda.stream(stream):
+            u = s.new_vector()
+            it, rr, _ = s.solve(f, u, rtol=1e-11, maxit=60, stream=stream)
+        stream.synchronize()
+        results.append((it, rr, host(u)))
+    s.use_graphs(True)
+    assert results[0][0] == results[1][0] == results[2][0]
+    assert np.array_equal(results[0][2], results[1][2])
+    assert np.array_equal(results[1][2], results[2][2])

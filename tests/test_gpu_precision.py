@@ -26,22 +26,23 @@ def oracle():
     return prob, MultigridOracle(prob, coarse_slabs=4)
 
 
-def test_fp32_block_solve_accuracy():
+@pytest.mark.parametrize("prec,bound", [("fp32", 1e-4), ("bf16x3", 1e-3)])
+def test_reduced_precision_block_solve_accuracy(prec, bound):
     import paper_1802_09277_amd as sth
-    print(f"[gpu-precision] fp32 block_solve {SHAPE}", flush=True)
+    print(f"[gpu-precision] {prec} block_solve {SHAPE}", flush=True)
     prob, mg = oracle()
-    s = sth.Solver(**SHAPE, prec="fp32", coarse_slabs=4)
+    s = sth.Solver(**SHAPE, prec=prec, coarse_slabs=4)
     r = W.random_vector(31, prob.n_dof)
     z = s.new_vector()
     s.block_solve(torch.from_numpy(r).cuda(), z)
     torch.cuda.synchronize()
     ref = mg.levels[0].slab_solve(r)
     err = np.abs(z.cpu().numpy() - ref).max() / np.abs(ref).max()
-    print(f"  fp32 slab inverse max rel error {err:.2e}")
-    assert 1e-12 < err < 1e-4
+    print(f"  {prec} slab inverse max rel error {err:.2e}")
+    assert 1e-12 < err < bound
 
 
-@pytest.mark.parametrize("prec", ["fp32"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 def test_reduced_precision_solve(prec):
     import paper_1802_09277_amd as sth
     print(f"[gpu-precision] {prec} solve {SHAPE}", flush=True)
@@ -68,5 +69,6 @@ def test_reduced_precision_solve(prec):
 
 def test_reduced_precision_rejected_where_unsupported():
     import paper_1802_09277_amd as sth
-    with pytest.raises(sth.StatusError):
-        sth.Solver(dim=3, n_elem=6, degree=2, n_slabs=2, n_elem_t=2, prec="fp32")
+    for prec in ("fp32", "bf16x3"):
+        with pytest.raises(sth.StatusError):
+            sth.Solver(dim=3, n_elem=6, degree=2, n_slabs=2, n_elem_t=2, prec=prec)
