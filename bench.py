@@ -29,7 +29,8 @@ PEAKS = {  # MI355X published peaks
 }
 # dominant-class roofline: which bound applies to each kernel class
 CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "timemix": "hbm",
-               "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma"}
+               "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma",
+               "eig_smooth": "hbm", "eig_resid": "hbm"}
 
 
 def log(*a):
@@ -84,6 +85,8 @@ def main():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--basis", default="nodal", choices=["nodal", "eigen"],
+                    help="iterate on B-spline coefficients or in the spatial eigenbasis")
     ap.add_argument("--cpu-sample-slabs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -101,14 +104,14 @@ def main():
     stream = torch.cuda.Stream()          # non-default stream: solve iterations replay as HIP graphs
     torch.cuda.set_stream(stream)
     s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
-                   prec=args.prec)
+                   prec=args.prec, basis=args.basis)
     f = s.new_vector()
     s.load_rhs(cfg.modes(), f)
     u = s.new_vector()
     torch.cuda.synchronize()
 
     # warm-up with every kernel class timed, to find the dominant class
-    s.timing(0x1FF)
+    s.timing((1 << len(sth.KCLASS)) - 1)
     iters = 0
     for _ in range(max(args.warmup, 1)):
         u.zero_()
@@ -181,6 +184,7 @@ def main():
             "coefficients_incl_dirichlet": cfg.coefficients,
             "theta": cfg.theta,
             "transform_prec": args.prec,
+            "iterate_basis": args.basis,
             "v_cycles": iters,
             "final_relres": relres,
             "levels": s.num_levels,

@@ -83,6 +83,14 @@ typedef struct {
     int nu_post;        /* >= 0 */
     int transform_prec; /* sth_prec */
     int coarse_slabs;   /* >= 1: stop coarsening at this many slabs or fewer */
+    int iterate_basis;  /* sth_solve only: 0 iterate on the B-spline
+                           coefficients; 1 keep the iterate in the spatial
+                           eigenbasis of the smoother (u = (I (x) U_x) u^),
+                           where L_h, D^{-1} and the time transfers act
+                           pointwise over spatial modes; the spatial
+                           transforms then run once on f, once per cycle on the
+                           residual for the stopping test, and once on the
+                           result.  Same iterates in exact arithmetic. */
 } sth_problem;
 
 /* Right-hand side as a sum of separable modes (host arrays):
@@ -205,7 +213,9 @@ typedef enum {
     STH_K_RESIDUAL = 0, STH_K_XFORM_X = 1, STH_K_XFORM_S = 2, STH_K_TIMEMIX = 3,
     STH_K_RESTRICT = 4, STH_K_PROLONG = 5, STH_K_NORM = 6, STH_K_OTHER = 7,
     STH_K_XFORM_2D = 8,     /* both axes of 2-D images in one kernel */
-    STH_K_COUNT = 9
+    STH_K_EIG_SMOOTH = 9,   /* eigenbasis iteration: residual + slab inverse + update */
+    STH_K_EIG_RESID = 10,   /* eigenbasis iteration: residual (and restriction) */
+    STH_K_COUNT = 11
 } sth_kernel_class;
 
 /* Record an event pair around every launch of the kernel classes whose bit

@@ -18,7 +18,7 @@ STATUS = {0: "STH_OK", -1: "STH_EINVAL", -2: "STH_ENOMEM", -3: "STH_EHIP", -4: "
           -5: "STH_ECOND", -6: "STH_ENOCONV", -7: "STH_ENODEV"}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KCLASS = {"residual": 0, "xform_x": 1, "xform_s": 2, "timemix": 3, "restrict": 4, "prolong": 5,
-          "norm": 6, "other": 7, "xform_2d": 8}
+          "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10}
 
 
 class StatusError(RuntimeError):
@@ -32,7 +32,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_elem", ctypes.c_int), ("degree", ctypes.c_int),
                 ("n_slabs", ctypes.c_int), ("n_elem_t", ctypes.c_int), ("T", ctypes.c_double),
                 ("theta", ctypes.c_double), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
-                ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int), ("coarse_slabs", ctypes.c_int)]
+                ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int), ("coarse_slabs", ctypes.c_int),
+                ("iterate_basis", ctypes.c_int)]
 
 
 class RhsModes(ctypes.Structure):
@@ -103,8 +104,11 @@ def _check(code):
         raise StatusError(code, msg.decode() if msg else "")
 
 
+BASIS = {"nodal": 0, "eigen": 1}
+
+
 def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal"):
     p = Problem()
     load_library().sth_problem_default(ctypes.byref(p))
     p.dim, p.n_elem, p.degree, p.n_slabs, p.n_elem_t = dim, n_elem, degree, n_slabs, n_elem_t
@@ -112,6 +116,7 @@ def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omeg
     p.transform_prec = PREC[prec] if isinstance(prec, str) else int(prec)
     if coarse_slabs is not None:
         p.coarse_slabs = int(coarse_slabs)
+    p.iterate_basis = BASIS[basis] if isinstance(basis, str) else int(basis)
     return p
 
 
@@ -167,13 +172,13 @@ class Solver:
     """One discrete problem on the GPU (setup factors and workspaces)."""
 
     def __init__(self, dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None, stream=None):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP slab solver needs a gfx950 device")
         self.lib = load_library()
         self.problem = make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T, theta, omega, nu_pre,
-                                    nu_post, prec, coarse_slabs)
+                                    nu_post, prec, coarse_slabs, basis)
         self.shape = dict(dim=dim, n_elem=n_elem, degree=degree, n_slabs=n_slabs, n_elem_t=n_elem_t)
         self.coarse_slabs = self.problem.coarse_slabs
         h = ctypes.c_void_p()

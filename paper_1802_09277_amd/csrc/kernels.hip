@@ -549,6 +549,16 @@ template <> struct Mfma16<float> {
     }
 };
 
+// Grid of a persistent image loop: as many 512-thread blocks as fit on the
+// 256 compute units at once (LDS-limited), at most one per image.
+static long persistent_blocks(size_t shm, long nimg) {
+    long per_cu = shm > 0 ? (long)((160 * 1024) / shm) : 4;
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 4) per_cu = 4;                 // 4 x 512 threads = 32 waves per CU
+    long blocks = 256 * per_cu;
+    return nimg < blocks ? nimg : blocks;
+}
+
 template <typename CT, int DIR, int NT16, int EPI>
 __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, double* __restrict__ out,
                                                  const double* __restrict__ Upad, int n, long nimg,
@@ -568,13 +578,27 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         Us[r * LD + c] = (CT)Upad[i];
     }
     const long nn = (long)n * n;
+    // the next image is staged in registers while the current one is in the
+    // MFMA products (blocks are persistent over images)
+    constexpr int PER = (NP * NP + 511) / 512;
+    double pre[PER];
+    auto load_img = [&](long img) {
+        const double* src = in + img * nn;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + 512 * k, r = i / NP, c = i % NP;
+            pre[k] = (i < NP * NP && r < n && c < n) ? src[(long)r * n + c] : 0.0;
+        }
+    };
+    if (blockIdx.x < nimg) load_img(blockIdx.x);
     for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
         __syncthreads();
-        const double* src = in + img * nn;
-        for (int i = tid; i < NP * NP; i += 512) {
-            int r = i / NP, c = i % NP;
-            Is[r * LD + c] = (r < n && c < n) ? (CT)src[(long)r * n + c] : (CT)0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + 512 * k;
+            if (i < NP * NP) Is[(i / NP) * LD + i % NP] = (CT)pre[k];
         }
+        if (img + gridDim.x < nimg) load_img(img + gridDim.x);
         __syncthreads();
         acc_t acc[TPW];
         // first product: T1 = R U (forward) or Y U^T (inverse)
@@ -651,7 +675,7 @@ static hipError_t xform2d_launch(const double* in, double* out, const double* Up
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    long blocks = nimg < 2048 ? nimg : 2048;
+    long blocks = persistent_blocks(shm, nimg);
     hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Upad,
                        n, nimg, alpha);
     return hipGetLastError();
@@ -724,14 +748,25 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
         split_bf16(Mpad[i], &Mh[r * LDB + c], &Ml[r * LDB + c]);
     }
     const long nn = (long)n * n;
+    constexpr int PER = (NP * NP + 511) / 512;
+    double pre[PER];
+    auto load_img = [&](long img) {
+        const double* src = in + img * nn;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + 512 * k, r = i / NP, c = i % NP;
+            pre[k] = (i < NP * NP && r < n && c < n) ? src[(long)r * n + c] : 0.0;
+        }
+    };
+    if (blockIdx.x < nimg) load_img(blockIdx.x);
     for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
         __syncthreads();
-        const double* src = in + img * nn;
-        for (int i = tid; i < NP * NP; i += 512) {
-            int r = i / NP, c = i % NP;
-            double v = (r < n && c < n) ? src[(long)r * n + c] : 0.0;
-            split_bf16(v, &Ih[r * LDB + c], &Il[r * LDB + c]);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + 512 * k, r = i / NP, c = i % NP;
+            if (i < NP * NP) split_bf16(pre[k], &Ih[r * LDB + c], &Il[r * LDB + c]);
         }
+        if (img + gridDim.x < nimg) load_img(img + gridDim.x);
         __syncthreads();
         f4 acc[TPW];
         // T1 = In M^T : A = In[i][k] (stored [i][k]), B[k][j] = M[j][k] (stored [j][k])
@@ -818,7 +853,7 @@ static hipError_t xform2d_bf16_launch(const double* in, double* out, const doubl
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    long blocks = nimg < 2048 ? nimg : 2048;
+    long blocks = persistent_blocks(shm, nimg);
     hipLaunchKernelGGL((k_xform2d_bf16x3<NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Mpad,
                        n, nimg, alpha);
     return hipGetLastError();
@@ -964,6 +999,155 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 #undef STH_TM_CASE
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// Iteration in the spatial eigenbasis.  With u = (I (x) U_x) u^ and
+// r^ = (I (x) U_x^T) r, where U_x^T M_x U_x = I and U_x^T K_x U_x = diag(mu),
+// the slab operator A_n = K_t (x) M_x + M_t (x) K_x becomes
+// K_t (x) I + M_t (x) diag(mu) and B_n = N_t (x) M_x becomes N_t (x) I
+// (eq. structureAn), so the residual r^_n = f^_n - A^ u^_n + B^ u^_{n-1} and
+// the slab inverse are both pointwise over the spatial modes.
+// ---------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ void eig_residual_point(const double* __restrict__ ktmt, double mu, const double* u,
+                                                   double prevlast, double* g) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double a = 0.0;
+#pragma unroll
+        for (int t2 = 0; t2 < NT; ++t2) a += (ktmt[t * kNt + t2] + mu * ktmt[kNt * kNt + t * kNt + t2]) * u[t2];
+        g[t] -= a;
+    }
+    g[0] += prevlast;
+}
+
+// one damped block-Jacobi step u^out = u^in + omega A^{-1}(f^ - L^ u^in); with
+// zero_guess u^in is taken as 0 (and not read).  uin and uout must differ
+// (the coupling reads the previous slab's old iterate).
+template <int NT>
+__global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                    const double* __restrict__ mu1, int n, long Nx,
+                                                    const double* __restrict__ fh, const double* __restrict__ uin,
+                                                    double* __restrict__ uout, long total, double omega,
+                                                    int zero_guess) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    const long base = s * NT * Nx + m;
+    double g[NT], u[NT], z[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) g[t] = fh[base + (long)t * Nx];
+    if (!zero_guess) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = uin[base + (long)t * Nx];
+        double prev = s > 0 ? uin[base - Nx] : 0.0;          // last time row of slab s-1
+        eig_residual_point<NT>(ktmt, mu, u, prev, g);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = 0.0;
+    }
+    shifted_solve<NT>(tm, mu, g, z);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) uout[base + (long)t * Nx] = u[t] + omega * z[t];
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_eig_residual(const double* __restrict__ ktmt, int dim,
+                                                      const double* __restrict__ mu1, int n, long Nx,
+                                                      const double* __restrict__ fh, const double* __restrict__ uh,
+                                                      double* __restrict__ rh, long total) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    const long base = s * NT * Nx + m;
+    double g[NT], u[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        g[t] = fh[base + (long)t * Nx];
+        u[t] = uh[base + (long)t * Nx];
+    }
+    eig_residual_point<NT>(ktmt, mu, u, s > 0 ? uh[base - Nx] : 0.0, g);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) rh[base + (long)t * Nx] = g[t];
+}
+
+// residual of slabs 2m, 2m+1 restricted to coarse slab m (P_t^T (x) I)
+template <int NT>
+__global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const double* __restrict__ ktmt, int dim,
+                                                            const double* __restrict__ mu1, int n, long Nx,
+                                                            const double* __restrict__ fh,
+                                                            const double* __restrict__ uh, double* __restrict__ fc,
+                                                            long total) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long mc = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    double acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const long s = 2 * mc + h;
+        const long base = s * NT * Nx + m;
+        double g[NT], u[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            g[t] = fh[base + (long)t * Nx];
+            u[t] = uh[base + (long)t * Nx];
+        }
+        eig_residual_point<NT>(ktmt, mu, u, s > 0 ? uh[base - Nx] : 0.0, g);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g[t];
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+}
+
+#define STH_NT_SWITCH(KER, GRID, ...)                                                      \
+    switch (Nt) {                                                                           \
+        case 2: hipLaunchKernelGGL(KER<2>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 3: hipLaunchKernelGGL(KER<3>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 4: hipLaunchKernelGGL(KER<4>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 5: hipLaunchKernelGGL(KER<5>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 6: hipLaunchKernelGGL(KER<6>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 7: hipLaunchKernelGGL(KER<7>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 8: hipLaunchKernelGGL(KER<8>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        default: return hipErrorInvalidValue;                                               \
+    }
+
+hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                             const double* fh, const double* uin, double* uout, long S, double omega,
+                             bool zero_guess, hipStream_t st) {
+    long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_NT_SWITCH(k_eig_smooth, grid, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess ? 1 : 0)
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
+                               const double* uh, double* rh, long S, hipStream_t st) {
+    long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_NT_SWITCH(k_eig_residual, grid, ktmt, dim, mu1, n, Nx, fh, uh, rh, total)
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const double* ktmt, const double* mu1,
+                                     int n, const double* fh, const double* uh, double* fc, long Sc,
+                                     hipStream_t st) {
+    long Nx = (long)n * n * (dim == 3 ? n : 1), total = Sc * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_NT_SWITCH(k_eig_resid_restrict, grid, tr, ktmt, dim, mu1, n, Nx, fh, uh, fc, total)
+    return hipGetLastError();
+}
+#undef STH_NT_SWITCH
 
 // ---------------------------------------------------------------------------
 // time transfers

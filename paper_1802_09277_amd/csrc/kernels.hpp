@@ -62,6 +62,20 @@ hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const d
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
                           const double* in, double* out, long S, bool fwdsub, hipStream_t st);
 
+// Iteration in the spatial eigenbasis (all pointwise over spatial modes;
+// ktmt = device K_t then M_t of the level):
+//  uout = uin + omega A^{-1}(fh - L uin)   (uin not read when zero_guess)
+hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                             const double* fh, const double* uin, double* uout, long S, double omega,
+                             bool zero_guess, hipStream_t st);
+//  rh = fh - L uh
+hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
+                               const double* uh, double* rh, long S, hipStream_t st);
+//  fc = (P^T (x) I)(fh - L uh) on slab pairs
+hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const double* ktmt, const double* mu1,
+                                     int n, const double* fh, const double* uh, double* fc, long Sc,
+                                     hipStream_t st);
+
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,
                            long Nx, hipStream_t st);

@@ -57,6 +57,15 @@ struct sth_handle {
     double* K1b = nullptr;
     double* dktmt = nullptr;            // per level: K_t then M_t (kNt x kNt each)
     std::vector<double*> lu, lf;        // per level >= 1: iterate and right-hand side
+    // iteration in the spatial eigenbasis (iterate_basis = 1)
+    int basis = 0;
+    double* Cf = nullptr;               // np x np, C = M_1 U padded (C = U^{-T})
+    double* Ci = nullptr;               // np x np, C^T padded
+    double* e0 = nullptr;               // f^ on level 0
+    double* e1 = nullptr;               // u^ on level 0 (ping-pong with e2)
+    double* e2 = nullptr;
+    std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
+    std::vector<int> ecur;              // which buffer of the pair holds u^ per level
     double* buf0 = nullptr;
     double* buf1 = nullptr;
     double* partial = nullptr;
@@ -78,6 +87,7 @@ struct sth_handle {
     double* gu = nullptr;
     hipStream_t gst = nullptr;
     unsigned gmask = 0;
+    int gcur = 0;
     std::vector<Rec> grecs;
     double gms[STH_K_COUNT] = {0}, gfl[STH_K_COUNT] = {0}, gby[STH_K_COUNT] = {0};
     int gcnt[STH_K_COUNT] = {0};
@@ -287,6 +297,115 @@ static int read_norm(sth_handle* h, const double* v, long len, hipStream_t st, d
 }
 
 // ---------------------------------------------------------------------------
+// Iteration in the spatial eigenbasis.  The multigrid iterates are kept as
+// u^ with u = (I (x) U_x) u^; every operator of the cycle (L_h, D^{-1},
+// P_t (x) I, its transpose) maps to a pointwise operator over the spatial
+// modes, so the cycle runs without spatial transforms.  The transforms are
+// applied to f once (f^ = (I (x) U_x^T) f), to the residual once per cycle
+// for the stopping test (r = (I (x) C_x) r^, C = M_1 U = U^{-T}), and to the
+// result (u = (I (x) U_x) u^).  In exact arithmetic the iterates are those of
+// the nodal cycle.
+// ---------------------------------------------------------------------------
+enum SpatialKind { FWD_U, INV_U, FWD_C, INV_C };
+
+// out = (A^T (x) ... (x) A^T) in (FWD) or (A (x) ... (x) A) in (INV) on every
+// time row of `rows` rows; A = U or C.  FP64.  in, out and tmp (a level-0
+// sized scratch vector, used by the axis-by-axis path) must be distinct.
+static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, double* out, long rows, double* tmp,
+                         hipStream_t st) {
+    const bool fwd = (kind == FWD_U || kind == FWD_C);
+    const double* A = (kind == FWD_U || kind == INV_U) ? h->Tf : h->Cf;     // A padded
+    const double* At = (kind == FWD_U || kind == INV_U) ? h->Ti : h->Ci;    // A^T padded
+    const long n = h->n;
+    double dof = (double)rows * h->Nx;
+    if (h->dim == 2 && xform2d_supported(h->np)) {
+        Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, 16.0 * dof, st);
+        HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st));
+        return STH_OK;
+    }
+    // axis by axis: x (contiguous), then y (and z), ping-ponging tmp/out
+    const double* T = fwd ? A : At;
+    int rc;
+    if (h->dim == 2) {
+        if ((rc = xform_x(h, 0, in, tmp, T, rows * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, tmp, out, T, rows, n, st))) return rc;
+    } else {
+        if ((rc = xform_x(h, 0, in, out, T, rows * n * n, 1.0, st))) return rc;       // x
+        if ((rc = xform_s(h, out, tmp, T, rows * n, n, st))) return rc;                // y
+        if ((rc = xform_s(h, tmp, out, T, rows, n * n, st))) return rc;                // z
+    }
+    return STH_OK;
+}
+
+static double* eig_u(sth_handle* h, int lvl, int which) {
+    if (lvl == 0) return which ? h->e2 : h->e1;
+    return which ? h->lu2[lvl] : h->lu[lvl];
+}
+static double* eig_f(sth_handle* h, int lvl) { return lvl == 0 ? h->e0 : h->lf[lvl]; }
+
+static const double* level_ktmt(sth_handle* h, int lvl) { return h->dktmt + (size_t)lvl * 2 * kNt * kNt; }
+
+static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
+    long S = h->lev_S[lvl];
+    double dof = (double)S * slab_len(h);
+    int c = h->ecur[lvl];
+    Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), (zero_guess ? 16.0 : 24.0) * dof, st);
+    HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
+                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, st));
+    h->ecur[lvl] = 1 - c;
+    return STH_OK;
+}
+
+static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
+    if (lvl > 0) h->ecur[lvl] = 0;
+    long S = h->lev_S[lvl];
+    if (lvl == h->L - 1) {
+        double dof = (double)S * slab_len(h);
+        Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
+        HIPCHK(launch_timemix(h->dim, h->Nt, h->mixes[lvl], h->mu1, h->n, eig_f(h, lvl),
+                              eig_u(h, lvl, h->ecur[lvl]), S, true, st));
+        return STH_OK;
+    }
+    int rc;
+    if (zero_guess && h->nu_pre == 0) {
+        HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * slab_len(h), 0.0, st));
+        zero_guess = false;
+    }
+    for (int i = 0; i < h->nu_pre; ++i)
+        if ((rc = eig_smooth(h, lvl, zero_guess && i == 0, st))) return rc;
+    {
+        long Sc = h->lev_S[lvl + 1];
+        double dof = (double)S * slab_len(h);
+        Timed tm(h, STH_K_EIG_RESID, dof * (4.0 * h->Nt + 2.0 * h->Nt), dof * 16.0 + 0.5 * dof * 8.0, st);
+        HIPCHK(launch_eig_resid_restrict(h->dim, h->Nt, h->tr, level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
+                                         eig_u(h, lvl, h->ecur[lvl]), eig_f(h, lvl + 1), Sc, st));
+    }
+    if ((rc = eig_vcycle(h, lvl + 1, true, st))) return rc;
+    if ((rc = prolong_lvl(h, lvl, eig_u(h, lvl + 1, h->ecur[lvl + 1]), eig_u(h, lvl, h->ecur[lvl]), st))) return rc;
+    for (int i = 0; i < h->nu_post; ++i)
+        if ((rc = eig_smooth(h, lvl, false, st))) return rc;
+    return STH_OK;
+}
+
+// nodal residual of the current eigenbasis iterate into buf1, squared norm to
+// the pinned host scalar (not synchronised)
+static int eig_residual_norm(sth_handle* h, hipStream_t st) {
+    long S = h->lev_S[0];
+    long len = S * slab_len(h);
+    double dof = (double)len;
+    {
+        Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
+        HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, h->ecur[0]),
+                                   h->buf0, S, st));
+    }
+    int rc = spatial_apply(h, INV_C, h->buf0, h->buf1, S * h->Nt, eig_u(h, 0, 1 - h->ecur[0]), st);
+    if (rc) return rc;
+    if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
+    HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
+    return STH_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 static Problem to_problem(const sth_problem* p) {
@@ -303,6 +422,7 @@ static Problem to_problem(const sth_problem* p) {
     q.nu_post = p->nu_post;
     q.prec = p->transform_prec;
     q.coarse_slabs = p->coarse_slabs;
+    q.basis = p->iterate_basis;
     return q;
 }
 
@@ -318,6 +438,7 @@ void sth_problem_default(sth_problem* p) {
     p->nu_post = 1;
     p->transform_prec = STH_FP64;
     p->coarse_slabs = 8;
+    p->iterate_basis = 0;
 }
 
 const char* sth_last_error(void) { return g_err.c_str(); }
@@ -340,14 +461,17 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     size_t total = 0;
     total += 2 * sizeof(double) * np * np;                   // transforms
     total += sizeof(double) * n * (1 + 2 * (2 * q.degree + 1));
-    total += 2 * sizeof(double) * (size_t)q.n_slabs * slab;  // buf0, buf1
+    const size_t vecs0 = q.basis == 1 ? 5 : 2;               // buf0, buf1 (+ f^, u^ pair)
+    const size_t vecsl = q.basis == 1 ? 3 : 2;               // u, f (+ u^ partner) per coarse level
+    total += vecs0 * sizeof(double) * (size_t)q.n_slabs * slab;
+    if (q.basis == 1) total += 2 * sizeof(double) * np * np;  // C, C^T
     long S = q.n_slabs;
     size_t L = level_count(q);
     for (size_t l = 1; l < L; ++l) {
         S /= 2;
-        total += 2 * sizeof(double) * (size_t)S * slab;
+        total += vecsl * sizeof(double) * (size_t)S * slab;
     }
-    total += sizeof(double) * (kNormBlocks + 1);
+    total += sizeof(double) * (kNormBlocks + 1 + L * 2 * kNt * kNt);
     *bytes = total;
     return STH_OK;
 }
@@ -377,6 +501,11 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->nu_pre = q.nu_pre;
     h->nu_post = q.nu_post;
     h->prec = q.prec;
+    h->basis = q.basis;
+    if (h->basis != 0 && h->basis != 1) {
+        delete h;
+        return fail(STH_EINVAL, "iterate_basis must be 0 or 1");
+    }
     if (h->prec != STH_FP64 && !(h->dim == 2 && xform2d_supported(h->np))) {
         delete h;
         return fail(STH_EINVAL, "reduced-precision transforms (FP32, BF16x3) need a 2-D problem with n <= 96");
@@ -443,9 +572,33 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     }
     h->lu.assign(h->L, nullptr);
     h->lf.assign(h->L, nullptr);
+    h->lu2.assign(h->L, nullptr);
+    h->ecur.assign(h->L, 0);
     for (int l = 1; l < h->L; ++l) {
         if (!dalloc(&h->lu[l], (size_t)h->lev_S[l] * slab) || !dalloc(&h->lf[l], (size_t)h->lev_S[l] * slab))
             return cleanup(STH_ENOMEM, "device allocation failed");
+        if (h->basis == 1 && !dalloc(&h->lu2[l], (size_t)h->lev_S[l] * slab))
+            return cleanup(STH_ENOMEM, "device allocation failed");
+    }
+    std::vector<double> Cf, Ci;
+    if (h->basis == 1) {
+        // C = M_1 U = U^{-T} (from U^T M_1 U = I)
+        Cf.assign((size_t)np * np, 0.0);
+        Ci.assign((size_t)np * np, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double c = 0.0;
+                for (int k = std::max(0, i - h->p); k <= std::min(n - 1, i + h->p); ++k) c += h->S.M1(i, k) * h->S.U(k, j);
+                Cf[(size_t)i * np + j] = c;
+                Ci[(size_t)j * np + i] = c;
+            }
+        if (!dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
+            !dalloc(&h->e0, (size_t)q.n_slabs * slab) || !dalloc(&h->e1, (size_t)q.n_slabs * slab) ||
+            !dalloc(&h->e2, (size_t)q.n_slabs * slab))
+            return cleanup(STH_ENOMEM, "device allocation failed");
+        if (hipMemcpyAsync(h->Cf, Cf.data(), Cf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(h->Ci, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+            return cleanup(STH_EHIP, "upload of the setup failed");
     }
     if (hipHostMalloc((void**)&h->hnorm, sizeof(double), 0) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
@@ -542,6 +695,10 @@ int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream) {
 static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_t st) {
     int rc;
     long len = h->lev_S[0] * slab_len(h);
+    if (h->basis == 1) {
+        if ((rc = eig_vcycle(h, 0, false, st))) return rc;
+        return eig_residual_norm(h, st);
+    }
     if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
     if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
     if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
@@ -553,8 +710,11 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
 // cheaper to launch than the individual kernels.  Not used on the legacy
 // default stream, where capture is not allowed.
 static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_t st) {
-    if (!h->gexec || h->gf != f || h->gu != u || h->gst != st || h->gmask != (h->timing ? h->timing_mask : 0u)) {
+    const int cur0 = h->basis == 1 ? h->ecur[0] : 0;     // eigenbasis iterate buffer at entry
+    if (!h->gexec || h->gf != f || h->gu != u || h->gst != st || h->gcur != cur0 ||
+        h->gmask != (h->timing ? h->timing_mask : 0u)) {
         drop_graph(h);
+        h->gcur = cur0;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         h->capturing = true;
         int rc = solve_iteration(h, f, u, st);
@@ -573,6 +733,11 @@ static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_
         h->gu = u;
         h->gst = st;
         h->gmask = h->timing ? h->timing_mask : 0u;
+    }
+    else if (h->basis == 1) {
+        // replaying does not run the host-side bookkeeping of the capture:
+        // advance the eigenbasis buffer index by the smoothing steps of a cycle
+        if ((h->nu_pre + h->nu_post) % 2 == 1) h->ecur[0] = 1 - h->ecur[0];
     }
     HIPCHK(hipGraphLaunch(h->gexec, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -596,8 +761,19 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
     int rc = read_norm(h, f, len, st, &fn);
     if (rc) return rc;
     if (fn == 0.0) fn = 1.0;
-    if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
-    if ((rc = read_norm(h, h->buf1, len, st, &rn))) return rc;
+    const long rows = h->lev_S[0] * h->Nt;
+    if (h->basis == 1) {
+        // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
+        h->ecur[0] = 0;
+        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st))) return rc;
+        if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) return rc;
+        if ((rc = eig_residual_norm(h, st))) return rc;
+        HIPCHK(hipStreamSynchronize(st));
+        rn = std::sqrt(h->hnorm[0]);
+    } else {
+        if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
+        if ((rc = read_norm(h, h->buf1, len, st, &rn))) return rc;
+    }
     int it = 0, growth = 0;
     double prev = rn;
     while (rn > rtol * fn && it < maxit) {
@@ -615,6 +791,11 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
         growth = (rn > prev) ? growth + 1 : 0;
         prev = rn;
         if (growth >= 3) break;
+    }
+    if (h->basis == 1) {
+        // u = (I (x) U_x) u^
+        if ((rc = spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), u, rows, h->buf0, st))) return rc;
+        HIPCHK(hipStreamSynchronize(st));
     }
     if (iters) *iters = it;
     if (relres) *relres = rn / fn;
@@ -648,14 +829,15 @@ int sth_norm(sth_handle* h, const double* v, double* out, void* stream) {
 
 int sth_destroy(sth_handle* h) {
     if (!h) return STH_OK;
-    double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt};
+    // graph first: its nodes reference the buffers below
+    drop_graph(h);
+    double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt,
+                      h->Cf, h->Ci, h->e0, h->e1, h->e2};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
-    for (double* q : h->lu)
-        if (q) (void)hipFree(q);
-    for (double* q : h->lf)
-        if (q) (void)hipFree(q);
-    drop_graph(h);
+    for (auto* vec : {&h->lu, &h->lf, &h->lu2})
+        for (double* q : *vec)
+            if (q) (void)hipFree(q);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
     for (auto e : h->pool) (void)hipEventDestroy(e);
     delete h;

@@ -48,6 +48,7 @@ struct Problem {
     double T, theta, omega;
     int nu_pre, nu_post, prec;
     int coarse_slabs;
+    int basis;
     int n() const { return n_elem + degree - 2; }
     int Nt() const { return n_elem_t + degree; }
     double tau() const { return T / n_slabs; }

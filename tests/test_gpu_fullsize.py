@@ -38,14 +38,14 @@ def _samples():
     return data[:, 0].astype(np.int64), data[:, 1], data[:, 2], meta
 
 
-def _run(prec, rtol):
+def _run(prec, rtol, basis="nodal"):
     import paper_1802_09277_amd as sth
     cfg = W.CONFIGS["C2"]
-    print(f"[gpu-fullsize] C2 prec={prec} rtol={rtol}", flush=True)
+    print(f"[gpu-fullsize] C2 prec={prec} rtol={rtol} basis={basis}", flush=True)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta, prec=prec,
-                       stream=stream)
+                       basis=basis, stream=stream)
         f = s.new_vector()
         s.load_rhs(cfg.modes(), f, stream=stream)
         u = s.new_vector()
@@ -75,3 +75,11 @@ def test_fullsize_bench_tolerance(prec):
     err = np.abs(u[idx] - us).max() / np.abs(us).max()
     print(f"  {prec}: {it} cycles, relres {rr:.2e}, sampled max rel error vs direct {err:.2e}")
     assert rr <= 1e-8 and err <= 1e-6
+
+
+def test_fullsize_eigenbasis():
+    idx, fs, us, meta = _samples()
+    it, rr, f, u, nf = _run("fp64", 1e-12, basis="eigen")
+    err = np.abs(u[idx] - us).max() / np.abs(us).max()
+    print(f"  eigenbasis: {it} cycles, relres {rr:.2e}, sampled max rel error vs direct {err:.2e}")
+    assert rr <= 1e-12 and err <= 1e-9

@@ -207,3 +207,49 @@ def test_graph_replay_matches_eager_solve():
     assert results[0][0] == results[1][0] == results[2][0]
     assert np.array_equal(results[0][2], results[1][2])
     assert np.array_equal(results[1][2], results[2][2])
+
+
+@functools.lru_cache(maxsize=None)
+def eigen_solver_for(name):
+    import paper_1802_09277_amd as sth
+    return sth.Solver(**SHAPES[name], basis="eigen")
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_eigenbasis_iterates_match_oracle_cycles(name):
+    """Iterating in the spatial eigenbasis gives the multigrid iterates of the
+    oracle (k cycles from zero, mapped back to B-spline coefficients), both on
+    the default stream and with graph replay on a side stream."""
+    banner(name, "eigenbasis")
+    prob, mg = oracle_for(name)
+    s = eigen_solver_for(name)
+    f = assemble_rhs(prob, W.random_modes(3, prob.dim))
+    fd = dev(f)
+    uo = np.zeros_like(f)
+    for k in range(1, 4):
+        uo = mg.vcycle(f, uo)
+        u = s.new_vector()
+        it, rr, code = s.solve(fd, u, rtol=0.0, maxit=k, check=False)
+        assert it == k and code == -6
+        assert rel_max(host(u), uo) <= 1e-10, k
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        u = s.new_vector()
+        it, rr, code = s.solve(fd, u, rtol=0.0, maxit=3, check=False, stream=stream)
+    stream.synchronize()
+    assert rel_max(host(u), uo) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_eigenbasis_solve_matches_direct(name):
+    banner(name, "eigenbasis solve")
+    prob, mg = oracle_for(name)
+    s = eigen_solver_for(name)
+    f = assemble_rhs(prob, W.random_modes(5, prob.dim))
+    ud = mg.levels[0].forward_substitution(f)
+    u = s.new_vector()
+    it, rr, _ = s.solve(dev(f), u, rtol=1e-12, maxit=60)
+    _, it_o, _ = mg.solve(f, rtol=1e-12, maxit=60)
+    print(f"  eigenbasis: {it} cycles (oracle {it_o}), relres {rr:.2e}")
+    assert rr <= 1e-12 and abs(it - it_o) <= 1
+    assert np.linalg.norm(host(u) - ud) <= 1e-10 * np.linalg.norm(ud)
