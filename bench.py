@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--basis", default="nodal", choices=["nodal", "eigen"],
                     help="iterate on B-spline coefficients or in the spatial eigenbasis")
+    ap.add_argument("--coarse-slabs", type=int, default=None,
+                    help="coarsest multigrid level: at most this many slabs (library default 8)")
     ap.add_argument("--cpu-sample-slabs", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -104,7 +106,7 @@ def main():
     stream = torch.cuda.Stream()          # non-default stream: solve iterations replay as HIP graphs
     torch.cuda.set_stream(stream)
     s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
-                   prec=args.prec, basis=args.basis)
+                   prec=args.prec, basis=args.basis, coarse_slabs=args.coarse_slabs)
     f = s.new_vector()
     s.load_rhs(cfg.modes(), f)
     u = s.new_vector()
@@ -188,6 +190,7 @@ def main():
             "v_cycles": iters,
             "final_relres": relres,
             "levels": s.num_levels,
+            "coarse_slabs": s.coarse_slabs,
         },
         "roofline": roof,
     }

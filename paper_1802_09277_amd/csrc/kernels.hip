@@ -601,14 +601,17 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         if (img + gridDim.x < nimg) load_img(img + gridDim.x);
         __syncthreads();
         acc_t acc[TPW];
-        // first product: T1 = R U (forward) or Y U^T (inverse)
+        // first product: T1 = R U (forward) or Y U^T (inverse).  The k loop is
+        // outside the tile loop so that the MFMAs of a wave's tiles are
+        // independent and issue back to back.
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            acc[q] = acc_t{0, 0, 0, 0};
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
-                for (int k0 = 0; k0 < kp; k0 += 4) {
+        for (int q = 0; q < TPW; ++q) acc[q] = acc_t{0, 0, 0, 0};
+        for (int k0 = 0; k0 < kp; k0 += 4) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
                     CT a = Is[(ti * 16 + lr) * LD + k0 + lk];
                     CT b = (DIR == 0) ? Us[(k0 + lk) * LD + tj * 16 + lr] : Us[(tj * 16 + lr) * LD + k0 + lk];
                     acc[q] = M::op(a, b, acc[q]);
@@ -628,12 +631,13 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         __syncthreads();
         // second product: U^T T1 (forward) or U T1 (inverse)
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            acc[q] = acc_t{0, 0, 0, 0};
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
-                for (int k0 = 0; k0 < kp; k0 += 4) {
+        for (int q = 0; q < TPW; ++q) acc[q] = acc_t{0, 0, 0, 0};
+        for (int k0 = 0; k0 < kp; k0 += 4) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
                     CT a = (DIR == 0) ? Us[(k0 + lk) * LD + ti * 16 + lr] : Us[(ti * 16 + lr) * LD + k0 + lk];
                     CT b = Is[(k0 + lk) * LD + tj * 16 + lr];
                     acc[q] = M::op(a, b, acc[q]);
@@ -771,12 +775,13 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
         f4 acc[TPW];
         // T1 = In M^T : A = In[i][k] (stored [i][k]), B[k][j] = M[j][k] (stored [j][k])
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
-                for (int k0 = 0; k0 < NP; k0 += 16) {
+        for (int q = 0; q < TPW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < NP; k0 += 16) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
                     const int ao = (ti * 16 + lr) * LDB + k0 + 4 * lk, bo = (tj * 16 + lr) * LDB + k0 + 4 * lk;
                     s4 ah = *reinterpret_cast<const s4*>(&Ih[ao]), al = *reinterpret_cast<const s4*>(&Il[ao]);
                     s4 bh = *reinterpret_cast<const s4*>(&Mh[bo]), bl = *reinterpret_cast<const s4*>(&Ml[bo]);
@@ -803,12 +808,13 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
         __syncthreads();
         // out = M T1 : A = M[i][k] (stored [i][k]), B = T1 (stored [j][k])
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            acc[q] = f4{0.f, 0.f, 0.f, 0.f};
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
-                for (int k0 = 0; k0 < NP; k0 += 16) {
+        for (int q = 0; q < TPW; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < NP; k0 += 16) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
                     const int ao = (ti * 16 + lr) * LDB + k0 + 4 * lk, bo = (tj * 16 + lr) * LDB + k0 + 4 * lk;
                     s4 ah = *reinterpret_cast<const s4*>(&Mh[ao]), al = *reinterpret_cast<const s4*>(&Ml[ao]);
                     s4 bh = *reinterpret_cast<const s4*>(&Ih[bo]), bl = *reinterpret_cast<const s4*>(&Il[bo]);
@@ -874,6 +880,178 @@ static hipError_t xform2d_bf16_np(const double* in, double* out, const double* M
 }
 
 bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 16 == 0; }
+
+// ---------------------------------------------------------------------------
+// Squared Euclidean norm of the B-spline residual of an eigenbasis iterate,
+// 2-D: per image (slab s, time row t) the eigenbasis residual
+//   r^ = f^_t - sum_t' (K_t[t][t'] + mu M_t[t][t']) u^_t' + [t = 0] u^_{s-1, N_t-1}
+// is formed in LDS, mapped back by r = C r^ C^T (C = M_1 U = U^{-T}) with two
+// FP64 MFMA products, and its squares summed; r itself is never stored.  One
+// partial sum per block (fixed image order, fixed tree) -> deterministic.
+// ---------------------------------------------------------------------------
+template <int NT16, int NT>
+__global__ __launch_bounds__(512) void k_eig_resnorm2d(const double* __restrict__ fh, const double* __restrict__ uh,
+                                                       const double* __restrict__ ktmt,
+                                                       const double* __restrict__ mu1,
+                                                       const double* __restrict__ Cpad, int n, long nimg,
+                                                       double* __restrict__ partial) {
+    constexpr int NP = NT16 * 16, LD = NP + 1;
+    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
+    extern __shared__ double sm_raw[];
+    double* Cs = sm_raw;
+    double* Is = sm_raw + NP * LD;
+    double* red = Is + NP * LD;                                           // 512 entries
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int kp = (n + 3) & ~3;
+    for (int i = tid; i < NP * NP; i += 512) Cs[(i / NP) * LD + i % NP] = Cpad[i];
+    const long nn = (long)n * n;
+    double ssq = 0.0;
+    for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
+        const long s = img / NT;
+        const int t = (int)(img % NT);
+        double kr[NT], mr[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            kr[c] = ktmt[t * kNt + c];
+            mr[c] = ktmt[kNt * kNt + t * kNt + c];
+        }
+        __syncthreads();
+        const double* us = uh + s * NT * nn;
+        for (int i = tid; i < NP * NP; i += 512) {
+            const int r = i / NP, c = i % NP;
+            double v = 0.0;
+            if (r < n && c < n) {
+                const long m = (long)r * n + c;
+                const double mu = mu1[r] + mu1[c];
+                v = fh[img * nn + m];
+#pragma unroll
+                for (int t2 = 0; t2 < NT; ++t2) v -= (kr[t2] + mu * mr[t2]) * us[(long)t2 * nn + m];
+                if (t == 0 && s > 0) v += us[m - nn];                    // last row of slab s-1
+            }
+            Is[r * LD + c] = v;
+        }
+        __syncthreads();
+        d4 acc[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kp; k0 += 4) {                               // T1 = R^ C^T
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Is[(ti * 16 + lr) * LD + k0 + lk],
+                                                                  Cs[(tj * 16 + lr) * LD + k0 + lk], acc[q], 0, 0, 0);
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tq = wave + 8 * q;
+            if (tq < NTILE) {
+                const int ti = tq / NT16, tj = tq % NT16;
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) Is[(ti * 16 + lk + 4 * rr) * LD + tj * 16 + lr] = acc[q][rr];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kp; k0 += 4) {                               // r = C T1
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
+                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Cs[(ti * 16 + lr) * LD + k0 + lk],
+                                                                  Is[(k0 + lk) * LD + tj * 16 + lr], acc[q], 0, 0, 0);
+                }
+            }
+        }
+        // padded rows / columns of the product are exactly zero
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) ssq += acc[q][rr] * acc[q][rr];
+    }
+    red[tid] = ssq;
+    __syncthreads();
+    for (int w = 256; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out) {
+    __shared__ double sh[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += 256) s += partial[i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+template <int NT16, int NT>
+static hipError_t resnorm2d_launch(const double* fh, const double* uh, const double* ktmt, const double* mu1,
+                                   const double* Cpad, int n, long nimg, double* partial, int max_blocks,
+                                   double* out, hipStream_t st) {
+    constexpr int NP = NT16 * 16;
+    // C, the image and the 512-entry reduction buffer, all dynamic (the
+    // kernel has no static LDS, so the full 160 KB may be requested)
+    const size_t shm = sizeof(double) * (2 * (size_t)NP * (NP + 1) + 512);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_eig_resnorm2d<NT16, NT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    long blocks = persistent_blocks(shm, nimg);
+    if (blocks > max_blocks) blocks = max_blocks;
+    hipLaunchKernelGGL((k_eig_resnorm2d<NT16, NT>), dim3((unsigned)blocks), dim3(512), shm, st, fh, uh, ktmt, mu1,
+                       Cpad, n, nimg, partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+template <int NT16>
+static hipError_t resnorm2d_nt(int Nt, const double* fh, const double* uh, const double* ktmt, const double* mu1,
+                               const double* Cpad, int n, long nimg, double* partial, int max_blocks, double* out,
+                               hipStream_t st) {
+    switch (Nt) {
+        case 2: return resnorm2d_launch<NT16, 2>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 3: return resnorm2d_launch<NT16, 3>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 4: return resnorm2d_launch<NT16, 4>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 5: return resnorm2d_launch<NT16, 5>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 6: return resnorm2d_launch<NT16, 6>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 7: return resnorm2d_launch<NT16, 7>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 8: return resnorm2d_launch<NT16, 8>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_eig_resnorm2d(int Nt, const double* fh, const double* uh, const double* ktmt, const double* mu1,
+                                const double* Cpad, int n, int np, long S, double* partial, int max_blocks,
+                                double* out, hipStream_t st) {
+    if (!xform2d_supported(np) || S <= 0) return hipErrorInvalidValue;
+    const long nimg = S * Nt;
+    switch (np / 16) {
+        case 1: return resnorm2d_nt<1>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 2: return resnorm2d_nt<2>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 3: return resnorm2d_nt<3>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 4: return resnorm2d_nt<4>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 5: return resnorm2d_nt<5>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        case 6: return resnorm2d_nt<6>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
                           int np, long nimg, double alpha, hipStream_t st) {
@@ -1023,13 +1201,15 @@ __device__ __forceinline__ void eig_residual_point(const double* __restrict__ kt
 
 // one damped block-Jacobi step u^out = u^in + omega A^{-1}(f^ - L^ u^in); with
 // zero_guess u^in is taken as 0 (and not read).  uin and uout must differ
-// (the coupling reads the previous slab's old iterate).
-template <int NT>
+// (the coupling reads the previous slab's old iterate).  PRO: the coarse
+// correction (P_t (x) I) ec of the next coarser level is added to u^in first
+// (prolongation fused into the first post-smoothing step).
+template <int NT, bool PRO>
 __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                     const double* __restrict__ mu1, int n, long Nx,
                                                     const double* __restrict__ fh, const double* __restrict__ uin,
                                                     double* __restrict__ uout, long total, double omega,
-                                                    int zero_guess) {
+                                                    int zero_guess, const double* __restrict__ ec, Transfer tr) {
     long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     long s = idx / Nx, m = idx % Nx;
@@ -1042,6 +1222,30 @@ __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const d
 #pragma unroll
         for (int t = 0; t < NT; ++t) u[t] = uin[base + (long)t * Nx];
         double prev = s > 0 ? uin[base - Nx] : 0.0;          // last time row of slab s-1
+        if (PRO) {
+            const long mc = s / 2;
+            const int h = (int)(s % 2);
+            double c[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) c[k] = ec[mc * NT * Nx + m + (long)k * Nx];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k) v += tr.P[(h * NT + t) * kNt + k] * c[k];
+                u[t] += v;
+            }
+            if (s > 0) {
+                // last row of slab s-1: second half of coarse slab (s-1)/2
+                const long mp = (s - 1) / 2;
+                const int hp = (int)((s - 1) % 2);
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k)
+                    v += tr.P[(hp * NT + NT - 1) * kNt + k] * ec[mp * NT * Nx + m + (long)k * Nx];
+                prev += v;
+            }
+        }
         eig_residual_point<NT>(ktmt, mu, u, prev, g);
     } else {
 #pragma unroll
@@ -1119,13 +1323,32 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
         default: return hipErrorInvalidValue;                                               \
     }
 
+template <int NT>
+static void eig_smooth_launch(dim3 grid, hipStream_t st, int dim, const TimeMix& tm, const double* ktmt,
+                              const double* mu1, int n, long Nx, const double* fh, const double* uin, double* uout,
+                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr) {
+    if (ec)
+        hipLaunchKernelGGL((k_eig_smooth<NT, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
+                           uout, total, omega, zero_guess ? 1 : 0, ec, tr);
+    else
+        hipLaunchKernelGGL((k_eig_smooth<NT, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
+                           uout, total, omega, zero_guess ? 1 : 0, ec, tr);
+}
+
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, hipStream_t st) {
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st) {
     long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
     if (total <= 0) return hipSuccess;
+    if (ec && zero_guess) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
-    STH_NT_SWITCH(k_eig_smooth, grid, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess ? 1 : 0)
+    switch (Nt) {
+#define STH_ES_CASE(NTV) \
+        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr); break;
+        STH_ES_CASE(2) STH_ES_CASE(3) STH_ES_CASE(4) STH_ES_CASE(5) STH_ES_CASE(6) STH_ES_CASE(7) STH_ES_CASE(8)
+#undef STH_ES_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

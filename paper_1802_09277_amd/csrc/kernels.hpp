@@ -64,10 +64,12 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 
 // Iteration in the spatial eigenbasis (all pointwise over spatial modes;
 // ktmt = device K_t then M_t of the level):
-//  uout = uin + omega A^{-1}(fh - L uin)   (uin not read when zero_guess)
+//  uout = v + omega A^{-1}(fh - L v) with v = uin (+ (P (x) I) ec when ec is
+//  not null: the prolonged coarse correction, S/2 coarse slabs); uin is not
+//  read when zero_guess (then ec must be null)
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, hipStream_t st);
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);
@@ -75,6 +77,13 @@ hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double
 hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const double* ktmt, const double* mu1,
                                      int n, const double* fh, const double* uh, double* fc, long Sc,
                                      hipStream_t st);
+
+//  out[0] = ||(I (x) C (x) C)(fh - L uh)||^2 (2-D, np <= 96; C = M_1 U padded):
+//  the B-spline residual norm of an eigenbasis iterate without storing it;
+//  partial needs max_blocks entries
+hipError_t launch_eig_resnorm2d(int Nt, const double* fh, const double* uh, const double* ktmt, const double* mu1,
+                                const double* Cpad, int n, int np, long S, double* partial, int max_blocks,
+                                double* out, hipStream_t st);
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,

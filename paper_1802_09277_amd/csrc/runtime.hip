@@ -345,13 +345,16 @@ static double* eig_f(sth_handle* h, int lvl) { return lvl == 0 ? h->e0 : h->lf[l
 
 static const double* level_ktmt(sth_handle* h, int lvl) { return h->dktmt + (size_t)lvl * 2 * kNt * kNt; }
 
-static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
+// one smoothing step on level lvl; ec (not null): add the prolonged coarse
+// correction of level lvl+1 first
+static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st, const double* ec = nullptr) {
     long S = h->lev_S[lvl];
     double dof = (double)S * slab_len(h);
     int c = h->ecur[lvl];
-    Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), (zero_guess ? 16.0 : 24.0) * dof, st);
+    double bytes = (zero_guess ? 16.0 : 24.0) * dof + (ec ? 4.0 * dof : 0.0);
+    Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0 + (ec ? 2.0 * h->Nt : 0.0)), bytes, st);
     HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
-                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, st));
+                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, st));
     h->ecur[lvl] = 1 - c;
     return STH_OK;
 }
@@ -381,9 +384,10 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
                                          eig_u(h, lvl, h->ecur[lvl]), eig_f(h, lvl + 1), Sc, st));
     }
     if ((rc = eig_vcycle(h, lvl + 1, true, st))) return rc;
-    if ((rc = prolong_lvl(h, lvl, eig_u(h, lvl + 1, h->ecur[lvl + 1]), eig_u(h, lvl, h->ecur[lvl]), st))) return rc;
+    const double* ec = eig_u(h, lvl + 1, h->ecur[lvl + 1]);
+    if (h->nu_post == 0) return prolong_lvl(h, lvl, ec, eig_u(h, lvl, h->ecur[lvl]), st);
     for (int i = 0; i < h->nu_post; ++i)
-        if ((rc = eig_smooth(h, lvl, false, st))) return rc;
+        if ((rc = eig_smooth(h, lvl, false, st, i == 0 ? ec : nullptr))) return rc;
     return STH_OK;
 }
 
@@ -393,6 +397,16 @@ static int eig_residual_norm(sth_handle* h, hipStream_t st) {
     long S = h->lev_S[0];
     long len = S * slab_len(h);
     double dof = (double)len;
+    if (h->dim == 2 && xform2d_supported(h->np)) {
+        // fused: eigenbasis residual -> C r^ C^T -> sum of squares (nothing stored)
+        {
+            Timed tm(h, STH_K_XFORM_2D, dof * (4.0 * h->n + 4.0 * h->Nt), dof * 16.0, st);
+            HIPCHK(launch_eig_resnorm2d(h->Nt, h->e0, eig_u(h, 0, h->ecur[0]), level_ktmt(h, 0), h->mu1, h->Cf,
+                                        h->n, h->np, S, h->partial, kNormBlocks, h->dnorm, st));
+        }
+        HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
+        return STH_OK;
+    }
     {
         Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
         HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, h->ecur[0]),

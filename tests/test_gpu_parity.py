@@ -66,6 +66,12 @@ def rel_max(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
+def last_error():
+    import paper_1802_09277_amd as sth
+    msg = sth.load_library().sth_last_error()
+    return msg.decode() if msg else ""
+
+
 def banner(name, what):
     print(f"[gpu-parity] {what} shape={name} {SHAPES[name]}", flush=True)
     sys.stdout.flush()
@@ -230,13 +236,14 @@ def test_eigenbasis_iterates_match_oracle_cycles(name):
         uo = mg.vcycle(f, uo)
         u = s.new_vector()
         it, rr, code = s.solve(fd, u, rtol=0.0, maxit=k, check=False)
-        assert it == k and code == -6
+        assert (it, code) == (k, -6), last_error()
         assert rel_max(host(u), uo) <= 1e-10, k
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         u = s.new_vector()
         it, rr, code = s.solve(fd, u, rtol=0.0, maxit=3, check=False, stream=stream)
     stream.synchronize()
+    assert (it, code) == (3, -6), last_error()
     assert rel_max(host(u), uo) <= 1e-10
 
 
