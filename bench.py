@@ -7,8 +7,12 @@ time-parallel multigrid with the damped block-Jacobi slab smoother) until
 side from 8 random Fourier modes (seed 2).  Inputs are resident in HBM when
 the timed region starts; setup and right-hand-side assembly are outside it.
 
-Prints one JSON line with the throughput, the roofline of the dominant
-kernel class (HIP events around its launches inside the timed region) and
+The timed region replays the solve iterations as HIP graphs.  Prints one
+JSON line with the throughput, the roofline of the dominant kernel class
+on the finest multigrid level (HIP events on the solve's stream around each
+of its launches there, in an eager pass of the same K solves right after the
+timed region; HBM traffic from the
+committed rocprofv3 counter summary when it matches the kernel sources) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
@@ -30,7 +34,7 @@ PEAKS = {  # MI355X published peaks
 # dominant-class roofline: which bound applies to each kernel class
 CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "timemix": "hbm",
                "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma",
-               "eig_smooth": "hbm", "eig_resid": "hbm"}
+               "eig_smooth": "hbm", "eig_resid": "hbm", "resnorm": "mfma"}
 
 
 def log(*a):
@@ -77,6 +81,120 @@ def cpu_baseline(cfg, sample_slabs):
     }
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1802_09277_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(cfg_name, basis, prec, kclass):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy
+    of known size); None when there is none for this workload or when the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{cfg_name.lower()}_{basis}_{prec}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip().strip("`")] = v.strip().strip("`")
+    if fields.get("kernel_class") != kclass or fields.get("kernel_sources_sha256") != kernel_source_hash():
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def serve_bench(args):
+    """Serving workload: 2-D requests with n_elem in {32..256}, p in {2,3,4},
+    slabs in {16..512}, random-mode right-hand sides seeded by the request id,
+    rtol 1e-8.  A closed burst measures the saturation rate (after a cold
+    burst that fills the setup cache); Poisson arrivals at fractions of it
+    give p50/p99 latency (submit -> solution in the caller's buffer)."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_1802_09277_amd as sth
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    reqs = W.serving_requests(args.serve_requests, seed=0)
+    srv = sth.Server(args.serve_budget_gib << 30, args.serve_slots)
+    shape = lambda c: dict(dim=c.dim, n_elem=c.n_elem, degree=c.degree, n_slabs=c.n_slabs, n_elem_t=c.n_elem_t)
+
+    def burst():
+        t0 = time.perf_counter()
+        outs, tickets = [], []
+        for c in reqs:
+            u = torch.empty(sth.problem_vector_len(**shape(c)), dtype=torch.float64, device="cuda")
+            outs.append(u)
+            tickets.append(srv.submit(c.modes(), u, rtol=1e-8, maxit=100, basis=args.basis, **shape(c)))
+        stats = [srv.wait(t) for t in tickets]
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, stats
+
+    t_cold, _ = burst()
+    t_warm, stats = burst()
+    bad = [st["message"] for st in stats if st["status"] != 0]
+    if bad:
+        raise RuntimeError(f"serving: {len(bad)} requests failed: {bad[:3]}")
+    total_dof = sum(c.unknowns for c in reqs)
+    sat_rps = len(reqs) / t_warm
+    log(f"serve: cold burst {t_cold:.2f} s, warm burst {t_warm:.2f} s, {sat_rps:.1f} requests/s")
+    rng = np.random.default_rng(1)
+    rates = []
+    for load in (0.5, 0.8, 0.95):
+        lam = load * sat_rps
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+        tickets, outs = [None] * len(reqs), [None] * len(reqs)
+
+        def client():
+            t0 = time.perf_counter()
+            for i, c in enumerate(reqs):
+                delay = arrivals[i] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                outs[i] = torch.empty(sth.problem_vector_len(**shape(c)), dtype=torch.float64, device="cuda")
+                tickets[i] = srv.submit(c.modes(), outs[i], rtol=1e-8, maxit=100, basis=args.basis, **shape(c))
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=client)
+        th.start()
+        th.join()
+        lat = [srv.wait(t)["latency_ms"] for t in tickets]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rates.append({"load": load, "offered_rps": lam, "achieved_rps": len(reqs) / wall,
+                      "dof_per_s": total_dof / wall, "p50_ms": float(np.percentile(lat, 50)),
+                      "p99_ms": float(np.percentile(lat, 99))})
+        log(f"serve: load {load}: p50 {rates[-1]['p50_ms']:.1f} ms, p99 {rates[-1]['p99_ms']:.1f} ms")
+    resident, setups = srv.resident()
+    srv.close()
+    out = {
+        "metric": METRIC,
+        "value": total_dof / t_warm,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"serving: {len(reqs)} 2D requests, n_elem 32-256, p 2-4, 16-512 slabs x 2 "
+                               f"time elems, random modes seeded by request id, rtol 1e-8",
+                   "iterate_basis": args.basis, "streams": args.serve_slots,
+                   "hbm_budget_gib": args.serve_budget_gib, "unknowns_total": total_dof},
+        "serving": {"saturation_rps": sat_rps, "cold_burst_s": t_cold, "warm_burst_s": t_warm,
+                    "mean_cycles": float(np.mean([st["iters"] for st in stats])),
+                    "cached_setups": setups, "resident_gib": resident / 2 ** 30, "poisson": rates},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,17 +203,27 @@ def main():
     ap.add_argument("--config", default="C2")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--basis", default="nodal", choices=["nodal", "eigen"],
-                    help="iterate on B-spline coefficients or in the spatial eigenbasis")
+    ap.add_argument("--basis", default="eigen", choices=["nodal", "eigen"],
+                    help="iterate on B-spline coefficients or in the spatial eigenbasis (same iterates)")
     ap.add_argument("--coarse-slabs", type=int, default=None,
                     help="coarsest multigrid level: at most this many slabs (library default 8)")
     ap.add_argument("--cpu-sample-slabs", type=int, default=4)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB three times first (the reference "
+                         "kernel of known size that scales the HBM counters of a --pmc run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="serving workload (p50/p99 latency) instead")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-budget-gib", type=int, default=160)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the slab solver runs on a single MI355X; "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.serve:
+        return serve_bench(args)
 
     import torch
     import paper_1802_09277_amd as sth
@@ -111,16 +239,26 @@ def main():
     s.load_rhs(cfg.modes(), f)
     u = s.new_vector()
     torch.cuda.synchronize()
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {n * 8} bytes")
+        del src, dst
 
-    # warm-up with every kernel class timed, to find the dominant class
-    s.timing((1 << len(sth.KCLASS)) - 1)
+    # warm-up with every kernel class timed on the finest level, to find the
+    # dominant kernel class there (the coarser levels hold half the work)
+    s.timing((1 << len(sth.KCLASS)) - 1, level=0)
     iters = 0
     for _ in range(max(args.warmup, 1)):
         u.zero_()
         iters, relres, _ = s.solve(f, u, rtol=args.rtol, maxit=200)
     totals = {k: s.timing_report(k) for k in sth.KCLASS}
     dominant = max(totals, key=lambda k: totals[k]["ms"])
-    log("warm-up kernel classes (ms per solve): " +
+    log("warm-up kernel classes on the finest level (ms per solve): " +
         ", ".join(f"{k}={v['ms'] / max(args.warmup, 1):.3f}" for k, v in totals.items() if v["launches"]))
     s.timing(0)
 
@@ -138,8 +276,9 @@ def main():
     ms = (t1 - t0) * 1e3 / args.steps
 
     # roofline pass: the same K solves with HIP events around every launch
-    # of the dominant kernel class (events need individually launched kernels)
-    s.timing(1 << sth.KCLASS[dominant])
+    # of the dominant kernel class on the finest level (events need
+    # individually launched kernels)
+    s.timing(1 << sth.KCLASS[dominant], level=0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(args.steps):
@@ -160,8 +299,10 @@ def main():
         achieved = rep["bytes"] / (rep["ms"] * 1e-3)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["algorithmic_bytes_per_launch"] = rep["bytes"] / max(rep["launches"], 1)
+    roof["traffic"] = measured_traffic(cfg.name, args.basis, args.prec, dominant)
     roof["kernel_class"] = dominant
+    roof["level"] = 0
     roof["launches_per_step"] = rep["launches"] / args.steps
     roof["mean_launch_us"] = rep["ms"] * 1e3 / max(rep["launches"], 1)
     roof["events_pass_ms_per_step"] = ms_events

@@ -50,7 +50,8 @@ typedef enum {
                            for the diagonalisation path (Section 3.3, last
                            paragraph; Table 1) */
     STH_ENOCONV = -6,   /* NaN/Inf, residual growth, or maxit reached */
-    STH_ENODEV = -7     /* no usable GPU */
+    STH_ENODEV = -7,    /* no usable GPU */
+    STH_EAGAIN = -8     /* serving: the request has not finished yet */
 } sth_status;
 
 typedef enum {
@@ -124,6 +125,9 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out);
 /* n_slabs * N_t * n^dim (n = n_elem + degree - 2), or 0 for NULL. */
 size_t sth_vector_len(const sth_handle* h);
 
+/* The same for a problem description, without a setup (0 if invalid). */
+size_t sth_problem_vector_len(const sth_problem* p);
+
 /* Number of multigrid levels (1 + number of time coarsenings). */
 int sth_num_levels(const sth_handle* h);
 
@@ -157,7 +161,8 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
 
 /* Graph replay of the solve iterations (default on): on a non-default
  * stream sth_solve captures one iteration (V-cycle, residual, norm, scalar
- * read) into a HIP graph for the given (f, u, stream) and replays it.
+ * read) into a HIP graph for the given (f, u) and replays it (on any
+ * stream; a new f or u, or a change of the timing mask, recaptures).
  * enable = 0 launches every kernel individually; so does kernel timing
  * (sth_timing), which needs events around the individual launches. */
 int sth_use_graphs(sth_handle* h, int enable);
@@ -215,7 +220,8 @@ typedef enum {
     STH_K_XFORM_2D = 8,     /* both axes of 2-D images in one kernel */
     STH_K_EIG_SMOOTH = 9,   /* eigenbasis iteration: residual + slab inverse + update */
     STH_K_EIG_RESID = 10,   /* eigenbasis iteration: residual (and restriction) */
-    STH_K_COUNT = 11
+    STH_K_RESNORM = 11,     /* eigenbasis iteration: residual mapped to B-splines, sum of squares */
+    STH_K_COUNT = 12
 } sth_kernel_class;
 
 /* Record an event pair around every launch of the kernel classes whose bit
@@ -223,12 +229,70 @@ typedef enum {
  * nonzero mask clears the previous records. */
 int sth_timing(sth_handle* h, unsigned class_mask);
 
+/* Restrict the recording to launches on one multigrid level (0 = finest;
+ * -1, the default, records every level). */
+int sth_timing_level(sth_handle* h, int level);
+
 /* Totals over the recorded launches of one class: launches, summed kernel
  * time in ms, summed algorithmic FLOPs and HBM bytes (the minimum traffic
  * of the operation: every input read once, every output written once).
  * Synchronises on the recorded events. */
 int sth_timing_report(sth_handle* h, int kclass, int* launches, double* ms,
                       double* flops, double* bytes);
+
+/* ---- serving: continuous batching of independent solves ------------- */
+
+/* A server owns a scheduler thread and a setup thread, `max_active` HIP
+ * streams (one per request in flight) and a cache of setups keyed by the
+ * problem description.  Requests (a problem, a right-hand side given by
+ * modes, a tolerance) are admitted in arrival order as soon as a stream is
+ * free and their device footprint (sth_workspace_bytes plus the setup's own
+ * f and u) fits into hbm_budget_bytes together with every cached setup;
+ * idle cached setups are evicted, least recently used first, to make room.
+ * Admitted requests run concurrently: each solve is driven one V-cycle at a
+ * time (graph replays on its own stream), so a request that arrives while
+ * others run starts as soon as it is admitted.  The result is copied into
+ * the caller's device buffer u_out (sth_problem_vector_len elements, valid
+ * until the request finishes); the kernels are deterministic, so a result
+ * does not depend on which other requests ran beside it.  The solve starts
+ * from u = 0 and stops at ||f - L_h u|| <= rtol ||f|| or after maxit cycles
+ * (Section 4.4).  All calls are thread-safe. */
+typedef struct sth_server sth_server;
+
+typedef struct {
+    int status;             /* sth_status of the solve (STH_EAGAIN while pending) */
+    int iters;              /* V-cycles */
+    double relres;          /* final ||f - L_h u|| / ||f|| */
+    double queue_ms;        /* submit -> admitted */
+    double setup_ms;        /* admitted -> right-hand side loaded (includes a new setup) */
+    double solve_ms;        /* right-hand side loaded -> result in u_out */
+    double latency_ms;      /* submit -> result in u_out */
+    size_t footprint_bytes; /* device bytes of the setup the request used */
+    int setup_reused;       /* 1 if the setup came from the cache */
+    char message[160];      /* failure message, empty on success */
+} sth_request_stats;
+
+/* max_active >= 1 streams; fails with STH_EINVAL on a zero budget. */
+int sth_server_create(size_t hbm_budget_bytes, int max_active, sth_server** out);
+
+/* Queues a request; the mode arrays are copied.  STH_ENOMEM if its footprint
+ * alone exceeds the budget, STH_EINVAL for an invalid problem.  *ticket
+ * identifies the request in the calls below. */
+int sth_server_submit(sth_server* s, const sth_problem* p, const sth_rhs_modes* rhs, double rtol,
+                      int maxit, double* u_out, long long* ticket);
+
+/* STH_EAGAIN while the request is pending or running; otherwise STH_OK and
+ * *stats (if not NULL) filled, after which the ticket is released. */
+int sth_server_poll(sth_server* s, long long ticket, sth_request_stats* stats);
+
+/* Blocks until the request has finished, then as sth_server_poll. */
+int sth_server_wait(sth_server* s, long long ticket, sth_request_stats* stats);
+
+/* Device bytes held by cached setups (busy or idle) and their count. */
+int sth_server_resident(sth_server* s, size_t* bytes, int* setups);
+
+/* Waits for the requests in flight, then frees every setup and stream. */
+int sth_server_destroy(sth_server* s);
 
 #ifdef __cplusplus
 }

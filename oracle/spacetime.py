@@ -263,10 +263,12 @@ def assemble_coupling(prob, slab=1):
     return Bf[keep][:, keep].tocsr()
 
 
-def assemble_rhs(prob, f, u0=None, slabs=None):
+def assemble_rhs(prob, f, u0=None, slabs=None, chunk=4096):
     """Load vector l_h(phi_i) for every slab (Gauss rule, p+3 points per
     direction).  f(t, xs) takes arrays t and a list xs of spatial coordinate
-    arrays (x first).  Returns a flat vector in the slab layout."""
+    arrays (x first).  Returns a flat vector in the slab layout.  Elements
+    are visited in `chunk`-sized groups (memory only: same order of
+    accumulation as one pass)."""
     p = prob.degree
     q = p + 3
     sig = prob.sigma
@@ -277,21 +279,23 @@ def assemble_rhs(prob, f, u0=None, slabs=None):
     for s in slabs:
         ax_t, ax_x = _axes(prob, s, q)
         axes = [ax_t] + ax_x[::-1]
-        el = _element_grid(axes)
-        w = _tensor_vec([ax.W for ax in axes], el)
-        coords = [_tensor_vec([ax.X if k == j else np.ones_like(ax.X) for k, ax in enumerate(axes)], el)
-                  for j in range(len(axes))]
-        tq = coords[0]
-        xq = [coords[len(axes) - 1 - a] for a in range(prob.dim)]       # x, y, z
-        fq = f(tq, xq)
-        Vs = [ax.V for ax in axes]
-        phi = _tensor(Vs, el)
-        dt = _tensor([axes[0].D] + Vs[1:], el)
-        loc = np.einsum("eq,eq,eqi->ei", w, fq, phi + sig * dt)
-        g = _global_index(axes, el)
+        el_all = _element_grid(axes)
         n_full_slab = ax_t.N * prob.n_full ** prob.dim
         vec = np.zeros(n_full_slab)
-        np.add.at(vec, g.ravel(), loc.ravel())
+        Vs = [ax.V for ax in axes]
+        for c0 in range(0, len(el_all[0]), chunk):
+            el = [e[c0:c0 + chunk] for e in el_all]
+            w = _tensor_vec([ax.W for ax in axes], el)
+            coords = [_tensor_vec([ax.X if k == j else np.ones_like(ax.X) for k, ax in enumerate(axes)], el)
+                      for j in range(len(axes))]
+            tq = coords[0]
+            xq = [coords[len(axes) - 1 - a] for a in range(prob.dim)]       # x, y, z
+            fq = f(tq, xq)
+            phi = _tensor(Vs, el)
+            dt = _tensor([axes[0].D] + Vs[1:], el)
+            loc = np.einsum("eq,eq,eqi->ei", w, fq, phi + sig * dt)
+            g = _global_index(axes, el)
+            np.add.at(vec, g.ravel(), loc.ravel())
         if s == 0 and u0 is not None:
             vec += initial_term(prob, ax_t, u0)
         out.append(vec[keep])

@@ -15,10 +15,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsth.so")
 
 STATUS = {0: "STH_OK", -1: "STH_EINVAL", -2: "STH_ENOMEM", -3: "STH_EHIP", -4: "STH_ENOTPOS",
-          -5: "STH_ECOND", -6: "STH_ENOCONV", -7: "STH_ENODEV"}
+          -5: "STH_ECOND", -6: "STH_ENOCONV", -7: "STH_ENODEV", -8: "STH_EAGAIN"}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KCLASS = {"residual": 0, "xform_x": 1, "xform_s": 2, "timemix": 3, "restrict": 4, "prolong": 5,
-          "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10}
+          "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10, "resnorm": 11}
 
 
 class StatusError(RuntimeError):
@@ -40,6 +40,13 @@ class RhsModes(ctypes.Structure):
     _fields_ = [("n_modes", ctypes.c_int), ("amp", ctypes.POINTER(ctypes.c_double)),
                 ("k", ctypes.POINTER(ctypes.c_int)), ("omega", ctypes.POINTER(ctypes.c_double)),
                 ("phase", ctypes.POINTER(ctypes.c_double))]
+
+
+class RequestStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("relres", ctypes.c_double),
+                ("queue_ms", ctypes.c_double), ("setup_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t),
+                ("setup_reused", ctypes.c_int), ("message", ctypes.c_char * 160)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -87,8 +94,16 @@ def load_library():
         "sth_host_factors": (i, [P(Problem), i, P(Factors)]),
         "sth_host_load_1d": (i, [P(Problem), d, d, i, _DP, _DP]),
         "sth_timing": (i, [vp, ctypes.c_uint]),
+        "sth_timing_level": (i, [vp, i]),
         "sth_use_graphs": (i, [vp, i]),
         "sth_timing_report": (i, [vp, i, P(i), P(d), P(d), P(d)]),
+        "sth_problem_vector_len": (sz, [P(Problem)]),
+        "sth_server_create": (i, [sz, i, P(vp)]),
+        "sth_server_submit": (i, [vp, P(Problem), P(RhsModes), d, i, vp, P(ctypes.c_longlong)]),
+        "sth_server_poll": (i, [vp, ctypes.c_longlong, P(RequestStats)]),
+        "sth_server_wait": (i, [vp, ctypes.c_longlong, P(RequestStats)]),
+        "sth_server_resident": (i, [vp, P(sz), P(i)]),
+        "sth_server_destroy": (i, [vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -155,6 +170,23 @@ def host_load_1d(omega, phase, k, **kw):
     return tp, sp_
 
 
+def problem_vector_len(**kw):
+    """Unknowns of a problem (n_slabs * N_t * n^dim) without a setup."""
+    n = load_library().sth_problem_vector_len(ctypes.byref(make_problem(**kw)))
+    if n == 0:
+        raise StatusError(-1, "invalid problem")
+    return n
+
+
+def _modes(modes):
+    amp, k, om, ph = modes.arrays()
+    arrs = (np.ascontiguousarray(amp, dtype=np.float64), np.ascontiguousarray(k, dtype=np.int32).ravel(),
+            np.ascontiguousarray(om, dtype=np.float64), np.ascontiguousarray(ph, dtype=np.float64))
+    m = RhsModes(len(arrs[0]), arrs[0].ctypes.data_as(_DP), arrs[1].ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                 arrs[2].ctypes.data_as(_DP), arrs[3].ctypes.data_as(_DP))
+    return m, arrs          # keep the arrays alive while m is in use
+
+
 def _ptr(t):
     import torch
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
@@ -206,13 +238,7 @@ class Solver:
 
     # operations ----------------------------------------------------------
     def load_rhs(self, modes, f, stream=None):
-        amp, k, om, ph = modes.arrays()
-        amp = np.ascontiguousarray(amp, dtype=np.float64)
-        k = np.ascontiguousarray(k, dtype=np.int32).ravel()
-        om = np.ascontiguousarray(om, dtype=np.float64)
-        ph = np.ascontiguousarray(ph, dtype=np.float64)
-        m = RhsModes(len(amp), amp.ctypes.data_as(_DP), k.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
-                     om.ctypes.data_as(_DP), ph.ctypes.data_as(_DP))
+        m, _keep = _modes(modes)
         _check(self.lib.sth_load_rhs(self.h, ctypes.byref(m), _ptr(f), _stream(stream)))
         return f
 
@@ -262,8 +288,10 @@ class Solver:
         _check(self.lib.sth_norm(self.h, _ptr(v), ctypes.byref(out), _stream(stream)))
         return out.value
 
-    def timing(self, class_mask):
-        """Event timing of the kernel classes in class_mask (bit per class, 0 = off)."""
+    def timing(self, class_mask, level=-1):
+        """Event timing of the kernel classes in class_mask (bit per class, 0 = off),
+        on one multigrid level (0 = finest) or on all (-1)."""
+        _check(self.lib.sth_timing_level(self.h, int(level)))
         _check(self.lib.sth_timing(self.h, int(class_mask)))
 
     def timing_report(self, kclass):
@@ -277,6 +305,69 @@ class Solver:
         if getattr(self, "h", None) is not None and self.h.value:
             self.lib.sth_destroy(self.h)
             self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop of the library (sth_server_*): requests are admitted by
+    device footprint, run concurrently on their own streams and write their
+    solution into a caller-owned device tensor."""
+
+    def __init__(self, hbm_budget_bytes, max_active=4):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the HIP slab solver needs a gfx950 device")
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        _check(self.lib.sth_server_create(int(hbm_budget_bytes), int(max_active), ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, modes, u_out, rtol=1e-8, maxit=100, **problem):
+        """problem: the keyword arguments of make_problem; u_out: float64 CUDA
+        tensor of problem_vector_len(**problem) elements (kept alive by the
+        caller until the request has finished).  Returns the ticket."""
+        p = make_problem(**problem)
+        m, _keep = _modes(modes)
+        t = ctypes.c_longlong()
+        _check(self.lib.sth_server_submit(self.h, ctypes.byref(p), ctypes.byref(m), float(rtol), int(maxit),
+                                          _ptr(u_out), ctypes.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _stats(st):
+        return {"status": st.status, "iters": st.iters, "relres": st.relres, "queue_ms": st.queue_ms,
+                "setup_ms": st.setup_ms, "solve_ms": st.solve_ms, "latency_ms": st.latency_ms,
+                "footprint_bytes": st.footprint_bytes, "setup_reused": bool(st.setup_reused),
+                "message": st.message.decode(errors="replace")}
+
+    def poll(self, ticket):
+        """None while pending, else the request's statistics."""
+        st = RequestStats()
+        code = self.lib.sth_server_poll(self.h, ticket, ctypes.byref(st))
+        if code == -8:
+            return None
+        _check(code)
+        return self._stats(st)
+
+    def wait(self, ticket):
+        st = RequestStats()
+        _check(self.lib.sth_server_wait(self.h, ticket, ctypes.byref(st)))
+        return self._stats(st)
+
+    def resident(self):
+        b, n = ctypes.c_size_t(), ctypes.c_int()
+        _check(self.lib.sth_server_resident(self.h, ctypes.byref(b), ctypes.byref(n)))
+        return b.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.sth_server_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

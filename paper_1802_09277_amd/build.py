@@ -7,13 +7,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsth.so")
-SOURCES = ["setup.cpp", "kernels.hip", "runtime.hip"]
+SOURCES = ["setup.cpp", "kernels.hip", "runtime.hip", "server.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     # no packed FP32 instructions in any kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-pthread",
 ]
 
 

@@ -385,146 +385,12 @@ hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, con
 }
 
 // ---------------------------------------------------------------------------
-// spatial eigenbasis transforms (FP64 MFMA 16x16x4)
-//   lane l supplies A[l%16][l/16] and B[l/16][l%16]; the 4 accumulator
-//   values of lane l hold D[l/16 + 4r][l%16], r = 0..3.
-// ---------------------------------------------------------------------------
-template <int EPI>
-__global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, double* __restrict__ out,
-                                                 const double* __restrict__ T, int n, int np, long lines,
-                                                 double alpha) {
-    __shared__ double in_s[64][17];
-    __shared__ double T_s[16][130];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const long line0 = (long)blockIdx.x * 64;
-    const int j0 = blockIdx.y * 128;
-    const int njt = min(8, (np - j0) / 16);
-    d4 acc[8];
-#pragma unroll
-    for (int jt = 0; jt < 8; ++jt) acc[jt] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < np; k0 += 16) {
-        for (int i = threadIdx.x; i < 64 * 16; i += 256) {
-            int l = i >> 4, kk = i & 15;
-            long line = line0 + l;
-            int k = k0 + kk;
-            in_s[l][kk] = (line < lines && k < n) ? in[line * n + k] : 0.0;
-        }
-        for (int i = threadIdx.x; i < 16 * 128; i += 256) {
-            int kk = i >> 7, jj = i & 127;
-            int j = j0 + jj;
-            T_s[kk][jj] = (j < np) ? T[(long)(k0 + kk) * np + j] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-            double a = in_s[wave * 16 + (lane & 15)][kq * 4 + (lane >> 4)];
-#pragma unroll
-            for (int jt = 0; jt < 8; ++jt) {
-                if (jt < njt) {
-                    double b = T_s[kq * 4 + (lane >> 4)][jt * 16 + (lane & 15)];
-                    acc[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[jt], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int jt = 0; jt < 8; ++jt) {
-        if (jt >= njt) break;
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            long line = line0 + wave * 16 + (lane >> 4) + 4 * rr;
-            int j = j0 + jt * 16 + (lane & 15);
-            if (line < lines && j < n) {
-                double v = acc[jt][rr];
-                double* o = out + line * n + j;
-                if (EPI == 0) *o = v;
-                else if (EPI == 1) *o += alpha * v;
-                else *o = alpha * v;
-            }
-        }
-    }
-}
-
-hipError_t launch_xform_x(int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st) {
-    if (lines <= 0) return hipSuccess;
-    dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
-    if (epi == 0) hipLaunchKernelGGL(k_xform_x<0>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    else if (epi == 1) hipLaunchKernelGGL(k_xform_x<1>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    else hipLaunchKernelGGL(k_xform_x<2>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, double* __restrict__ out,
-                                                 const double* __restrict__ T, int n, int np, long inner,
-                                                 int nib, int njb) {
-    __shared__ double in_s[16][66];
-    __shared__ double T_s[16][66];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    long bid = blockIdx.x;
-    const int ib = (int)(bid % nib);
-    bid /= nib;
-    const int jb = (int)(bid % njb);
-    const long b = bid / njb;
-    const long i0 = (long)ib * 64;
-    const int j0 = jb * 64;
-    const double* inb = in + b * (long)n * inner;
-    double* outb = out + b * (long)n * inner;
-    const bool active = (j0 + wave * 16) < np;
-    d4 acc[4];
-#pragma unroll
-    for (int it = 0; it < 4; ++it) acc[it] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < np; k0 += 16) {
-        for (int i = threadIdx.x; i < 16 * 64; i += 256) {
-            int kk = i >> 6, ii = i & 63;
-            int k = k0 + kk;
-            long ig = i0 + ii;
-            in_s[kk][ii] = (k < n && ig < inner) ? inb[(long)k * inner + ig] : 0.0;
-            int j = j0 + ii;
-            T_s[kk][ii] = (j < np) ? T[(long)k * np + j] : 0.0;
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-            for (int kq = 0; kq < 4; ++kq) {
-                double a = T_s[kq * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
-#pragma unroll
-                for (int it = 0; it < 4; ++it) {
-                    double bb = in_s[kq * 4 + (lane >> 4)][it * 16 + (lane & 15)];
-                    acc[it] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc[it], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    if (!active) return;
-#pragma unroll
-    for (int it = 0; it < 4; ++it) {
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            int j = j0 + wave * 16 + (lane >> 4) + 4 * rr;
-            long ig = i0 + it * 16 + (lane & 15);
-            if (j < n && ig < inner) outb[(long)j * inner + ig] = acc[it][rr];
-        }
-    }
-}
-
-hipError_t launch_xform_s(const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st) {
-    if (nbatch <= 0) return hipSuccess;
-    int nib = (int)((inner + 63) / 64), njb = (np + 63) / 64;
-    long blocks = nbatch * nib * njb;
-    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_xform_s, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner, nib, njb);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Both spatial axes of a 2-D image in one kernel: U (padded to NP x NP) and
 // one image stay in LDS; every block walks over images.  DIR 0 (forward):
 // out = U^T R U.  DIR 1 (inverse): Z = U Y U^T, then the epilogue EPI
-// (0 store, 1 out += alpha Z, 2 out = alpha Z).  Eight waves share the
+// (0 store, 1 out += alpha Z, 2 out = alpha Z, 3 nothing stored: the block's
+// sum of the squares of Z over its images goes to out[blockIdx.x], in a
+// fixed order).  Eight waves share the
 // NT16 x NT16 output tiles of each GEMM; the intermediate product goes back
 // into the image buffer.  CT is the compute type: double (MFMA f64 16x16x4)
 // or float (MFMA f32 16x16x4, FP32 accumulation); global data stay FP64.
@@ -591,6 +457,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         }
     };
     if (blockIdx.x < nimg) load_img(blockIdx.x);
+    double ssq = 0.0;                          // EPI 3
     for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
         __syncthreads();
 #pragma unroll
@@ -644,7 +511,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
                 }
             }
         }
-        double* dst = out + img * nn;
+        double* dst = (EPI == 3) ? out : out + img * nn;
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tq = wave + 8 * q;
@@ -656,6 +523,10 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
                     const int i = ti * 16 + M::row(lk, rr);
                     if (i < n && j < n) {
                         double v = (double)acc[q][rr];
+                        if (EPI == 3) {
+                            ssq += v * v;
+                            continue;
+                        }
                         double* o = dst + (long)i * n + j;
                         if (EPI == 0) *o = v;
                         else if (EPI == 1) *o += alpha * v;
@@ -665,11 +536,25 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
             }
         }
     }
+    if (EPI == 3) {
+        // wave sums by butterfly shuffles, then the eight wave sums in order
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
+        __syncthreads();                        // LDS free: reuse it for the wave sums
+        double* red = sm_raw;
+        if (lane == 0) red[wave] = ssq;
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int w = 0; w < 8; ++w) t += red[w];
+            out[blockIdx.x] = t;
+        }
+    }
 }
 
 template <typename CT, int DIR, int NT16, int EPI>
 static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
-                                 hipStream_t st) {
+                                 hipStream_t st, long* nblocks = nullptr) {
     constexpr int NP = NT16 * 16;
     size_t shm = sizeof(CT) * 2 * (size_t)NP * (NP + 1);
     static bool attr_set = false;
@@ -680,6 +565,7 @@ static hipError_t xform2d_launch(const double* in, double* out, const double* Up
         attr_set = true;
     }
     long blocks = persistent_blocks(shm, nimg);
+    if (nblocks) *nblocks = blocks;
     hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Upad,
                        n, nimg, alpha);
     return hipGetLastError();
@@ -687,14 +573,14 @@ static hipError_t xform2d_launch(const double* in, double* out, const double* Up
 
 template <typename CT, int DIR, int EPI>
 static hipError_t xform2d_np(const double* in, double* out, const double* Upad, int n, int np, long nimg,
-                             double alpha, hipStream_t st) {
+                             double alpha, hipStream_t st, long* nblocks = nullptr) {
     switch (np / 16) {
-        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st);
-        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st);
-        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st);
-        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st);
-        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st);
-        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st);
+        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
+        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
+        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
+        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
+        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
+        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
         default: return hipErrorInvalidValue;
     }
 }
@@ -705,7 +591,8 @@ static hipError_t xform2d_prec(int dir, int epi, const double* in, double* out, 
     if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st);
     if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st);
     if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st);
-    return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st);
+    if (epi == 2) return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -732,6 +619,286 @@ __device__ __forceinline__ void split_bf16(double v, unsigned short* hi, unsigne
     unsigned short h = to_bf16(x);
     *hi = h;
     *lo = to_bf16(x - from_bf16(h));
+}
+
+// ---------------------------------------------------------------------------
+// Per-axis spatial transforms (any n; 3-D, and 2-D images too large for the
+// LDS-resident kernel).  CT = double: MFMA f64 16x16x4; CT = float: MFMA
+// f32 16x16x4 with FP32 accumulation (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] in both; the result rows follow Mfma16<CT>::row).
+// ---------------------------------------------------------------------------
+// out[line][j] (EPI) sum_k in[line][k] T[k][j]; blocks of 64 lines x 128 columns
+template <typename CT, int EPI>
+__global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, double* __restrict__ out,
+                                                 const double* __restrict__ T, int n, int np, long lines,
+                                                 double alpha) {
+    using M = Mfma16<CT>;
+    typedef typename M::acc_t acc_t;
+    __shared__ CT in_s[64][17];
+    __shared__ CT T_s[16][130];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long line0 = (long)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 128;
+    const int njt = min(8, (np - j0) / 16);
+    acc_t acc[8];
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+            int l = i >> 4, kk = i & 15;
+            long line = line0 + l;
+            int k = k0 + kk;
+            in_s[l][kk] = (CT)((line < lines && k < n) ? in[line * n + k] : 0.0);
+        }
+        for (int i = threadIdx.x; i < 16 * 128; i += 256) {
+            int kk = i >> 7, jj = i & 127;
+            int j = j0 + jj;
+            T_s[kk][jj] = (CT)((j < np) ? T[(long)(k0 + kk) * np + j] : 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+            CT a = in_s[wave * 16 + lr][kq * 4 + lk];
+#pragma unroll
+            for (int jt = 0; jt < 8; ++jt) {
+                if (jt < njt) acc[jt] = M::op(a, T_s[kq * 4 + lk][jt * 16 + lr], acc[jt]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) {
+        if (jt >= njt) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            long line = line0 + wave * 16 + M::row(lk, rr);
+            int j = j0 + jt * 16 + lr;
+            if (line < lines && j < n) {
+                double v = (double)acc[jt][rr];
+                double* o = out + line * n + j;
+                if (EPI == 0) *o = v;
+                else if (EPI == 1) *o += alpha * v;
+                else *o = alpha * v;
+            }
+        }
+    }
+}
+
+// strided axis: out[b][j][i] = sum_k T[k][j] in[b][k][i]; blocks of 64 j x 64 i
+template <typename CT>
+__global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, double* __restrict__ out,
+                                                 const double* __restrict__ T, int n, int np, long inner,
+                                                 int nib, int njb) {
+    using M = Mfma16<CT>;
+    typedef typename M::acc_t acc_t;
+    __shared__ CT in_s[16][66];
+    __shared__ CT T_s[16][66];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    long bid = blockIdx.x;
+    const int ib = (int)(bid % nib);
+    bid /= nib;
+    const int jb = (int)(bid % njb);
+    const long b = bid / njb;
+    const long i0 = (long)ib * 64;
+    const int j0 = jb * 64;
+    const double* inb = in + b * (long)n * inner;
+    double* outb = out + b * (long)n * inner;
+    const bool active = (j0 + wave * 16) < np;
+    acc_t acc[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) acc[it] = acc_t{0, 0, 0, 0};
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        for (int i = threadIdx.x; i < 16 * 64; i += 256) {
+            int kk = i >> 6, ii = i & 63;
+            int k = k0 + kk;
+            long ig = i0 + ii;
+            in_s[kk][ii] = (CT)((k < n && ig < inner) ? inb[(long)k * inner + ig] : 0.0);
+            int j = j0 + ii;
+            T_s[kk][ii] = (CT)((j < np) ? T[(long)k * np + j] : 0.0);
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+            for (int kq = 0; kq < 4; ++kq) {
+                CT a = T_s[kq * 4 + lk][wave * 16 + lr];
+#pragma unroll
+                for (int it = 0; it < 4; ++it) acc[it] = M::op(a, in_s[kq * 4 + lk][it * 16 + lr], acc[it]);
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            int j = j0 + wave * 16 + M::row(lk, rr);
+            long ig = i0 + it * 16 + lr;
+            if (j < n && ig < inner) outb[(long)j * inner + ig] = (double)acc[it][rr];
+        }
+    }
+}
+
+// BF16x3 forms of the same two kernels: operands split into bf16 hi/lo when
+// staged into LDS, three MFMA f32 16x16x16 bf16 products per k-chunk of 16
+// (hi*hi + hi*lo + lo*hi), FP32 accumulation.  Both operands are stored with
+// k contiguous ([row][k]) so that a lane's 4 k-values are one 8-byte read.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_xform_x_bf16x3(const double* __restrict__ in, double* __restrict__ out,
+                                                        const double* __restrict__ T, int n, int np, long lines,
+                                                        double alpha) {
+    __shared__ unsigned short ih[64][20], il[64][20];      // [line][k]
+    __shared__ unsigned short th[128][20], tl[128][20];    // [j][k]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long line0 = (long)blockIdx.x * 64;
+    const int j0 = blockIdx.y * 128;
+    const int njt = min(8, (np - j0) / 16);
+    f4 acc[8];
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) acc[jt] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        for (int i = threadIdx.x; i < 64 * 16; i += 256) {
+            int l = i >> 4, kk = i & 15;
+            long line = line0 + l;
+            int k = k0 + kk;
+            split_bf16((line < lines && k < n) ? in[line * n + k] : 0.0, &ih[l][kk], &il[l][kk]);
+        }
+        for (int i = threadIdx.x; i < 16 * 128; i += 256) {
+            int kk = i >> 7, jj = i & 127;
+            int j = j0 + jj;
+            split_bf16((j < np) ? T[(long)(k0 + kk) * np + j] : 0.0, &th[jj][kk], &tl[jj][kk]);
+        }
+        __syncthreads();
+        const s4 ah = *reinterpret_cast<const s4*>(&ih[wave * 16 + lr][4 * lk]);
+        const s4 al = *reinterpret_cast<const s4*>(&il[wave * 16 + lr][4 * lk]);
+#pragma unroll
+        for (int jt = 0; jt < 8; ++jt) {
+            if (jt < njt) {
+                const s4 bh = *reinterpret_cast<const s4*>(&th[jt * 16 + lr][4 * lk]);
+                const s4 bl = *reinterpret_cast<const s4*>(&tl[jt * 16 + lr][4 * lk]);
+                acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[jt], 0, 0, 0);
+                acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[jt], 0, 0, 0);
+                acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[jt], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int jt = 0; jt < 8; ++jt) {
+        if (jt >= njt) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            long line = line0 + wave * 16 + 4 * lk + rr;
+            int j = j0 + jt * 16 + lr;
+            if (line < lines && j < n) {
+                double v = (double)acc[jt][rr];
+                double* o = out + line * n + j;
+                if (EPI == 0) *o = v;
+                else if (EPI == 1) *o += alpha * v;
+                else *o = alpha * v;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_xform_s_bf16x3(const double* __restrict__ in, double* __restrict__ out,
+                                                        const double* __restrict__ T, int n, int np, long inner,
+                                                        int nib, int njb) {
+    __shared__ unsigned short ih[64][20], il[64][20];      // [i][k]
+    __shared__ unsigned short th[64][20], tl[64][20];      // [j][k]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    long bid = blockIdx.x;
+    const int ib = (int)(bid % nib);
+    bid /= nib;
+    const int jb = (int)(bid % njb);
+    const long b = bid / njb;
+    const long i0 = (long)ib * 64;
+    const int j0 = jb * 64;
+    const double* inb = in + b * (long)n * inner;
+    double* outb = out + b * (long)n * inner;
+    const bool active = (j0 + wave * 16) < np;
+    f4 acc[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) acc[it] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < np; k0 += 16) {
+        for (int i = threadIdx.x; i < 16 * 64; i += 256) {
+            int kk = i >> 6, ii = i & 63;
+            int k = k0 + kk;
+            long ig = i0 + ii;
+            split_bf16((k < n && ig < inner) ? inb[(long)k * inner + ig] : 0.0, &ih[ii][kk], &il[ii][kk]);
+            int j = j0 + ii;
+            split_bf16((j < np) ? T[(long)k * np + j] : 0.0, &th[ii][kk], &tl[ii][kk]);
+        }
+        __syncthreads();
+        if (active) {
+            // A[j][k] = T[k][j], B[k][i] = in[k][i]
+            const s4 ah = *reinterpret_cast<const s4*>(&th[wave * 16 + lr][4 * lk]);
+            const s4 al = *reinterpret_cast<const s4*>(&tl[wave * 16 + lr][4 * lk]);
+#pragma unroll
+            for (int it = 0; it < 4; ++it) {
+                const s4 bh = *reinterpret_cast<const s4*>(&ih[it * 16 + lr][4 * lk]);
+                const s4 bl = *reinterpret_cast<const s4*>(&il[it * 16 + lr][4 * lk]);
+                acc[it] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[it], 0, 0, 0);
+                acc[it] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[it], 0, 0, 0);
+                acc[it] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[it], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            int j = j0 + wave * 16 + 4 * lk + rr;
+            long ig = i0 + it * 16 + lr;
+            if (j < n && ig < inner) outb[(long)j * inner + ig] = (double)acc[it][rr];
+        }
+    }
+}
+
+template <typename CT>
+static void xform_x_ct(int epi, dim3 grid, hipStream_t st, const double* in, double* out, const double* T, int n,
+                       int np, long lines, double alpha) {
+    if (epi == 0) hipLaunchKernelGGL((k_xform_x<CT, 0>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    else if (epi == 1) hipLaunchKernelGGL((k_xform_x<CT, 1>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    else hipLaunchKernelGGL((k_xform_x<CT, 2>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+}
+
+hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
+                          long lines, double alpha, hipStream_t st) {
+    if (lines <= 0) return hipSuccess;
+    if (epi < 0 || epi > 2 || prec < 0 || prec > 2) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
+    if (prec == 0) xform_x_ct<double>(epi, grid, st, in, out, T, n, np, lines, alpha);
+    else if (prec == 1) xform_x_ct<float>(epi, grid, st, in, out, T, n, np, lines, alpha);
+    else if (epi == 0) hipLaunchKernelGGL(k_xform_x_bf16x3<0>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    else if (epi == 1) hipLaunchKernelGGL(k_xform_x_bf16x3<1>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    else hipLaunchKernelGGL(k_xform_x_bf16x3<2>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
+                          long nbatch, long inner, hipStream_t st) {
+    if (nbatch <= 0) return hipSuccess;
+    if (prec < 0 || prec > 2) return hipErrorInvalidValue;
+    int nib = (int)((inner + 63) / 64), njb = (np + 63) / 64;
+    long blocks = nbatch * nib * njb;
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_xform_s<double>, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner,
+                           nib, njb);
+    else if (prec == 1)
+        hipLaunchKernelGGL(k_xform_s<float>, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner,
+                           nib, njb);
+    else
+        hipLaunchKernelGGL(k_xform_s_bf16x3, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner,
+                           nib, njb);
+    return hipGetLastError();
 }
 
 template <int NT16, int EPI>
@@ -881,110 +1048,7 @@ static hipError_t xform2d_bf16_np(const double* in, double* out, const double* M
 
 bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 16 == 0; }
 
-// ---------------------------------------------------------------------------
-// Squared Euclidean norm of the B-spline residual of an eigenbasis iterate,
-// 2-D: per image (slab s, time row t) the eigenbasis residual
-//   r^ = f^_t - sum_t' (K_t[t][t'] + mu M_t[t][t']) u^_t' + [t = 0] u^_{s-1, N_t-1}
-// is formed in LDS, mapped back by r = C r^ C^T (C = M_1 U = U^{-T}) with two
-// FP64 MFMA products, and its squares summed; r itself is never stored.  One
-// partial sum per block (fixed image order, fixed tree) -> deterministic.
-// ---------------------------------------------------------------------------
-template <int NT16, int NT>
-__global__ __launch_bounds__(512) void k_eig_resnorm2d(const double* __restrict__ fh, const double* __restrict__ uh,
-                                                       const double* __restrict__ ktmt,
-                                                       const double* __restrict__ mu1,
-                                                       const double* __restrict__ Cpad, int n, long nimg,
-                                                       double* __restrict__ partial) {
-    constexpr int NP = NT16 * 16, LD = NP + 1;
-    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
-    extern __shared__ double sm_raw[];
-    double* Cs = sm_raw;
-    double* Is = sm_raw + NP * LD;
-    double* red = Is + NP * LD;                                           // 512 entries
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int kp = (n + 3) & ~3;
-    for (int i = tid; i < NP * NP; i += 512) Cs[(i / NP) * LD + i % NP] = Cpad[i];
-    const long nn = (long)n * n;
-    double ssq = 0.0;
-    for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
-        const long s = img / NT;
-        const int t = (int)(img % NT);
-        double kr[NT], mr[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            kr[c] = ktmt[t * kNt + c];
-            mr[c] = ktmt[kNt * kNt + t * kNt + c];
-        }
-        __syncthreads();
-        const double* us = uh + s * NT * nn;
-        for (int i = tid; i < NP * NP; i += 512) {
-            const int r = i / NP, c = i % NP;
-            double v = 0.0;
-            if (r < n && c < n) {
-                const long m = (long)r * n + c;
-                const double mu = mu1[r] + mu1[c];
-                v = fh[img * nn + m];
-#pragma unroll
-                for (int t2 = 0; t2 < NT; ++t2) v -= (kr[t2] + mu * mr[t2]) * us[(long)t2 * nn + m];
-                if (t == 0 && s > 0) v += us[m - nn];                    // last row of slab s-1
-            }
-            Is[r * LD + c] = v;
-        }
-        __syncthreads();
-        d4 acc[TPW];
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < kp; k0 += 4) {                               // T1 = R^ C^T
-#pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                const int tq = wave + 8 * q;
-                if (tq < NTILE) {
-                    const int ti = tq / NT16, tj = tq % NT16;
-                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Is[(ti * 16 + lr) * LD + k0 + lk],
-                                                                  Cs[(tj * 16 + lr) * LD + k0 + lk], acc[q], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) Is[(ti * 16 + lk + 4 * rr) * LD + tj * 16 + lr] = acc[q][rr];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < kp; k0 += 4) {                               // r = C T1
-#pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                const int tq = wave + 8 * q;
-                if (tq < NTILE) {
-                    const int ti = tq / NT16, tj = tq % NT16;
-                    acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Cs[(ti * 16 + lr) * LD + k0 + lk],
-                                                                  Is[(k0 + lk) * LD + tj * 16 + lr], acc[q], 0, 0, 0);
-                }
-            }
-        }
-        // padded rows / columns of the product are exactly zero
-#pragma unroll
-        for (int q = 0; q < TPW; ++q)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) ssq += acc[q][rr] * acc[q][rr];
-    }
-    red[tid] = ssq;
-    __syncthreads();
-    for (int w = 256; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-    }
-    if (tid == 0) partial[blockIdx.x] = red[0];
-}
-
+// one block: out[0] = sum of the per-block partial sums (fixed order)
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out) {
     __shared__ double sh[256];
     double s = 0.0;
@@ -998,59 +1062,15 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-template <int NT16, int NT>
-static hipError_t resnorm2d_launch(const double* fh, const double* uh, const double* ktmt, const double* mu1,
-                                   const double* Cpad, int n, long nimg, double* partial, int max_blocks,
-                                   double* out, hipStream_t st) {
-    constexpr int NP = NT16 * 16;
-    // C, the image and the 512-entry reduction buffer, all dynamic (the
-    // kernel has no static LDS, so the full 160 KB may be requested)
-    const size_t shm = sizeof(double) * (2 * (size_t)NP * (NP + 1) + 512);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_eig_resnorm2d<NT16, NT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    long blocks = persistent_blocks(shm, nimg);
-    if (blocks > max_blocks) blocks = max_blocks;
-    hipLaunchKernelGGL((k_eig_resnorm2d<NT16, NT>), dim3((unsigned)blocks), dim3(512), shm, st, fh, uh, ktmt, mu1,
-                       Cpad, n, nimg, partial);
+hipError_t launch_xform2d_norm(const double* in, const double* Cpad, int n, int np, long nimg, double* partial,
+                               int max_blocks, double* out, hipStream_t st) {
+    if (nimg <= 0 || !xform2d_supported(np)) return hipErrorInvalidValue;
+    if (persistent_blocks(sizeof(double) * 2 * (size_t)np * (np + 1), nimg) > max_blocks) return hipErrorInvalidValue;
+    long blocks = 0;
+    hipError_t e = xform2d_np<double, 1, 3>(in, partial, Cpad, n, np, nimg, 0.0, st, &blocks);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
     return hipGetLastError();
-}
-
-template <int NT16>
-static hipError_t resnorm2d_nt(int Nt, const double* fh, const double* uh, const double* ktmt, const double* mu1,
-                               const double* Cpad, int n, long nimg, double* partial, int max_blocks, double* out,
-                               hipStream_t st) {
-    switch (Nt) {
-        case 2: return resnorm2d_launch<NT16, 2>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 3: return resnorm2d_launch<NT16, 3>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 4: return resnorm2d_launch<NT16, 4>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 5: return resnorm2d_launch<NT16, 5>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 6: return resnorm2d_launch<NT16, 6>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 7: return resnorm2d_launch<NT16, 7>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 8: return resnorm2d_launch<NT16, 8>(fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_eig_resnorm2d(int Nt, const double* fh, const double* uh, const double* ktmt, const double* mu1,
-                                const double* Cpad, int n, int np, long S, double* partial, int max_blocks,
-                                double* out, hipStream_t st) {
-    if (!xform2d_supported(np) || S <= 0) return hipErrorInvalidValue;
-    const long nimg = S * Nt;
-    switch (np / 16) {
-        case 1: return resnorm2d_nt<1>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 2: return resnorm2d_nt<2>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 3: return resnorm2d_nt<3>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 4: return resnorm2d_nt<4>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 5: return resnorm2d_nt<5>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        case 6: return resnorm2d_nt<6>(Nt, fh, uh, ktmt, mu1, Cpad, n, nimg, partial, max_blocks, out, st);
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
@@ -1203,13 +1223,16 @@ __device__ __forceinline__ void eig_residual_point(const double* __restrict__ kt
 // zero_guess u^in is taken as 0 (and not read).  uin and uout must differ
 // (the coupling reads the previous slab's old iterate).  PRO: the coarse
 // correction (P_t (x) I) ec of the next coarser level is added to u^in first
-// (prolongation fused into the first post-smoothing step).
-template <int NT, bool PRO>
+// (prolongation fused into the first post-smoothing step).  RSTORE: the
+// residual f^ - L^ u^in is also stored in rh (the residual of u^in for the
+// stopping test, with the next cycle's first smoothing step done already).
+template <int NT, bool PRO, bool RSTORE>
 __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                     const double* __restrict__ mu1, int n, long Nx,
                                                     const double* __restrict__ fh, const double* __restrict__ uin,
                                                     double* __restrict__ uout, long total, double omega,
-                                                    int zero_guess, const double* __restrict__ ec, Transfer tr) {
+                                                    int zero_guess, const double* __restrict__ ec, Transfer tr,
+                                                    double* __restrict__ rh) {
     long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     long s = idx / Nx, m = idx % Nx;
@@ -1250,6 +1273,10 @@ __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const d
     } else {
 #pragma unroll
         for (int t = 0; t < NT; ++t) u[t] = 0.0;
+    }
+    if (RSTORE) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) rh[base + (long)t * Nx] = g[t];
     }
     shifted_solve<NT>(tm, mu, g, z);
 #pragma unroll
@@ -1326,25 +1353,30 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
 template <int NT>
 static void eig_smooth_launch(dim3 grid, hipStream_t st, int dim, const TimeMix& tm, const double* ktmt,
                               const double* mu1, int n, long Nx, const double* fh, const double* uin, double* uout,
-                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr) {
+                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr,
+                              double* rh) {
+    const int zg = zero_guess ? 1 : 0;
     if (ec)
-        hipLaunchKernelGGL((k_eig_smooth<NT, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
-                           uout, total, omega, zero_guess ? 1 : 0, ec, tr);
+        hipLaunchKernelGGL((k_eig_smooth<NT, true, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
+                           uin, uout, total, omega, zg, ec, tr, rh);
+    else if (rh)
+        hipLaunchKernelGGL((k_eig_smooth<NT, false, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
+                           uin, uout, total, omega, zg, ec, tr, rh);
     else
-        hipLaunchKernelGGL((k_eig_smooth<NT, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
-                           uout, total, omega, zero_guess ? 1 : 0, ec, tr);
+        hipLaunchKernelGGL((k_eig_smooth<NT, false, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
+                           uin, uout, total, omega, zg, ec, tr, rh);
 }
 
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st) {
+                             bool zero_guess, const double* ec, const Transfer& tr, double* rh, hipStream_t st) {
     long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
     if (total <= 0) return hipSuccess;
-    if (ec && zero_guess) return hipErrorInvalidValue;
+    if (ec && (zero_guess || rh)) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
     switch (Nt) {
 #define STH_ES_CASE(NTV) \
-        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr); break;
+        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr, rh); break;
         STH_ES_CASE(2) STH_ES_CASE(3) STH_ES_CASE(4) STH_ES_CASE(5) STH_ES_CASE(6) STH_ES_CASE(7) STH_ES_CASE(8)
 #undef STH_ES_CASE
         default: return hipErrorInvalidValue;

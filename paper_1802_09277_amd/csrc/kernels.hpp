@@ -34,11 +34,12 @@ hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, con
 
 // out[line][j] (EPI) sum_k in[line][k] T[k][j] for `lines` contiguous lines
 // of length n.  EPI 0: store, 1: out += alpha*acc, 2: out = alpha*acc.
-hipError_t launch_xform_x(int epi, const double* in, double* out, const double* T, int n, int np,
+// prec (sth_prec): 0 MFMA f64, 1 MFMA f32 (FP32 accumulation), 2 BF16x3.
+hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
                           long lines, double alpha, hipStream_t st);
 
 // Strided axis: in[b][k][i] (k stride `inner`), out[b][j][i] = sum_k T[k][j] in[b][k][i].
-hipError_t launch_xform_s(const double* in, double* out, const double* T, int n, int np,
+hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
                           long nbatch, long inner, hipStream_t st);
 
 // Both spatial axes of 2-D images (n x n each, nimg images) in one kernel:
@@ -66,10 +67,11 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 // ktmt = device K_t then M_t of the level):
 //  uout = v + omega A^{-1}(fh - L v) with v = uin (+ (P (x) I) ec when ec is
 //  not null: the prolonged coarse correction, S/2 coarse slabs); uin is not
-//  read when zero_guess (then ec must be null)
+//  read when zero_guess (then ec must be null); rh (not null, only without
+//  ec): also rh = fh - L v
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st);
+                             bool zero_guess, const double* ec, const Transfer& tr, double* rh, hipStream_t st);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);
@@ -78,12 +80,11 @@ hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const 
                                      int n, const double* fh, const double* uh, double* fc, long Sc,
                                      hipStream_t st);
 
-//  out[0] = ||(I (x) C (x) C)(fh - L uh)||^2 (2-D, np <= 96; C = M_1 U padded):
-//  the B-spline residual norm of an eigenbasis iterate without storing it;
-//  partial needs max_blocks entries
-hipError_t launch_eig_resnorm2d(int Nt, const double* fh, const double* uh, const double* ktmt, const double* mu1,
-                                const double* Cpad, int n, int np, long S, double* partial, int max_blocks,
-                                double* out, hipStream_t st);
+//  out[0] = sum over the nimg n x n images of ||C Y C^T||_F^2 (2-D, np <= 96;
+//  C padded to np x np): the squared B-spline norm of an eigenbasis vector
+//  without storing the mapped vector; partial needs max_blocks entries
+hipError_t launch_xform2d_norm(const double* in, const double* Cpad, int n, int np, long nimg, double* partial,
+                               int max_blocks, double* out, hipStream_t st);
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,

@@ -21,6 +21,7 @@
 #include "../../include/sth.h"
 #include "kernels.hpp"
 #include "setup.hpp"
+#include "solve_async.hpp"
 
 using namespace sth;
 
@@ -66,14 +67,18 @@ struct sth_handle {
     double* e2 = nullptr;
     std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
     std::vector<int> ecur;              // which buffer of the pair holds u^ per level
+    bool presmoothed = false;           // the other level-0 buffer holds u^ after one smoothing step
+    double nb_lo = 0.0;                 // ||(I (x) C) r^||^2 >= nb_lo ||r^||^2
     double* buf0 = nullptr;
     double* buf1 = nullptr;
     double* partial = nullptr;
-    double* dnorm = nullptr;
-    double* hnorm = nullptr;            // pinned
+    double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side, [2] eigenbasis residual
+    double* hnorm = nullptr;            // pinned host copies of dnorm
     // timing
     bool timing = false;
     unsigned timing_mask = 0;
+    int timing_level = -1;              // record only launches on this level (-1: all)
+    int tlev = 0;                       // level of the launches being enqueued
     struct Rec { int cls; hipEvent_t a, b; double flops, bytes; };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -85,12 +90,24 @@ struct sth_handle {
     hipGraphExec_t gexec = nullptr;
     const double* gf = nullptr;
     double* gu = nullptr;
-    hipStream_t gst = nullptr;
     unsigned gmask = 0;
+    bool allow_capture = true;          // cleared by the serving loop while another thread allocates
+    bool graph_launched = false;        // the last enqueued iteration was a graph replay
     int gcur = 0;
     std::vector<Rec> grecs;
     double gms[STH_K_COUNT] = {0}, gfl[STH_K_COUNT] = {0}, gby[STH_K_COUNT] = {0};
     int gcnt[STH_K_COUNT] = {0};
+    // state of the solve in progress (sth_solve and the serving loop)
+    struct SolveState {
+        const double* f = nullptr;
+        double* u = nullptr;
+        hipStream_t st = nullptr;
+        double rtol = 0.0, fn = 1.0, rn = 0.0, prev = 0.0;
+        int maxit = 0, it = 0, growth = 0;
+        // 0 initial norms enqueued, 1 iterating, 2 result enqueued, 3 exact
+        // B-spline norm of the current eigenbasis iterate enqueued
+        int phase = 0;
+    } sv;
 };
 
 static void drop_graph(sth_handle* h) {
@@ -114,6 +131,7 @@ struct Timed {
     hipEvent_t a = nullptr, b = nullptr;
     Timed(sth_handle* hh, int c, double fl, double by, hipStream_t s) : h(hh), cls(c), flops(fl), bytes(by), st(s) {
         if (!h->timing || !((h->timing_mask >> c) & 1u)) return;
+        if (h->timing_level >= 0 && h->tlev != h->timing_level) return;
         if (h->pool_used + 2 > h->pool.size()) {
             for (int i = 0; i < 256; ++i) {
                 hipEvent_t e;
@@ -139,6 +157,7 @@ struct Timed {
 // ---------------------------------------------------------------------------
 static int residual(sth_handle* h, int lvl, const double* f, const double* u, double* r, long s0, long ns,
                     double sign, hipStream_t st) {
+    h->tlev = lvl;
     double dof = (double)ns * slab_len(h);
     int B = 2 * h->p + 1;
     double flops = dof * ((h->dim == 2 ? 10.0 : 16.0) * B + 4.0 * h->Nt + 2.0);
@@ -149,19 +168,20 @@ static int residual(sth_handle* h, int lvl, const double* f, const double* u, do
     return STH_OK;
 }
 
-static int xform_x(sth_handle* h, int epi, const double* in, double* out, const double* T, long lines,
+// per-axis transforms in the precision `prec` (sth_prec)
+static int xform_x(sth_handle* h, int prec, int epi, const double* in, double* out, const double* T, long lines,
                    double alpha, hipStream_t st) {
     double dof = (double)lines * h->n;
     Timed tm(h, STH_K_XFORM_X, 2.0 * h->n * dof, dof * (epi == 1 ? 24.0 : 16.0), st);
-    HIPCHK(launch_xform_x(epi, in, out, T, h->n, h->np, lines, alpha, st));
+    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st));
     return STH_OK;
 }
 
-static int xform_s(sth_handle* h, const double* in, double* out, const double* T, long nbatch, long inner,
-                   hipStream_t st) {
+static int xform_s(sth_handle* h, int prec, const double* in, double* out, const double* T, long nbatch,
+                   long inner, hipStream_t st) {
     double dof = (double)nbatch * h->n * inner;
     Timed tm(h, STH_K_XFORM_S, 2.0 * h->n * dof, 16.0 * dof, st);
-    HIPCHK(launch_xform_s(in, out, T, h->n, h->np, nbatch, inner, st));
+    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st));
     return STH_OK;
 }
 
@@ -169,6 +189,7 @@ static int xform_s(sth_handle* h, const double* in, double* out, const double* T
 // `in` may alias buf1 but not buf0.
 static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int epi, double alpha, long s0,
                         long ns, hipStream_t st, bool fwdsub = false) {
+    h->tlev = lvl;
     long off = s0 * slab_len(h);
     in += off;
     u += off;
@@ -198,27 +219,29 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
                 HIPCHK(launch_xform2d(h->prec, 1, epi, b1, u, h->Tf, h->n, h->np, rows, alpha, st));
         }
     } else if (h->dim == 2) {
-        if ((rc = xform_x(h, 0, in, b0, h->Tf, rows * n, 1.0, st))) return rc;
-        if ((rc = xform_s(h, b0, b1, h->Tf, rows, n, st))) return rc;
+        const int pr = h->prec;
+        if ((rc = xform_x(h, pr, 0, in, b0, h->Tf, rows * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, pr, b0, b1, h->Tf, rows, n, st))) return rc;
         {
             double dof = (double)ns * slab_len(h);
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
             HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b1, b0, ns, fwdsub, st));
         }
-        if ((rc = xform_s(h, b0, b1, h->Ti, rows, n, st))) return rc;
-        if ((rc = xform_x(h, epi, b1, u, h->Ti, rows * n, alpha, st))) return rc;
+        if ((rc = xform_s(h, pr, b0, b1, h->Ti, rows, n, st))) return rc;
+        if ((rc = xform_x(h, pr, epi, b1, u, h->Ti, rows * n, alpha, st))) return rc;
     } else {
-        if ((rc = xform_x(h, 0, in, b0, h->Tf, rows * n * n, 1.0, st))) return rc;
-        if ((rc = xform_s(h, b0, b1, h->Tf, rows * n, n, st))) return rc;          // y
-        if ((rc = xform_s(h, b1, b0, h->Tf, rows, n * n, st))) return rc;          // z
+        const int pr = h->prec;
+        if ((rc = xform_x(h, pr, 0, in, b0, h->Tf, rows * n * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, pr, b0, b1, h->Tf, rows * n, n, st))) return rc;      // y
+        if ((rc = xform_s(h, pr, b1, b0, h->Tf, rows, n * n, st))) return rc;      // z
         {
             double dof = (double)ns * slab_len(h);
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
             HIPCHK(launch_timemix(3, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, fwdsub, st));
         }
-        if ((rc = xform_s(h, b1, b0, h->Ti, rows, n * n, st))) return rc;          // z
-        if ((rc = xform_s(h, b0, b1, h->Ti, rows * n, n, st))) return rc;          // y
-        if ((rc = xform_x(h, epi, b1, u, h->Ti, rows * n * n, alpha, st))) return rc;
+        if ((rc = xform_s(h, pr, b1, b0, h->Ti, rows, n * n, st))) return rc;      // z
+        if ((rc = xform_s(h, pr, b0, b1, h->Ti, rows * n, n, st))) return rc;      // y
+        if ((rc = xform_x(h, pr, epi, b1, u, h->Ti, rows * n * n, alpha, st))) return rc;
     }
     return STH_OK;
 }
@@ -244,6 +267,7 @@ static int coarse_solve(sth_handle* h, int lvl, const double* f, double* u, hipS
 }
 
 static int restrict_lvl(sth_handle* h, int lvl, const double* r, double* rc, hipStream_t st) {
+    h->tlev = lvl;
     long Sc = h->lev_S[lvl + 1];
     double dof = (double)Sc * slab_len(h);
     Timed tm(h, STH_K_RESTRICT, dof * 4.0 * h->Nt, dof * 24.0, st);
@@ -252,6 +276,7 @@ static int restrict_lvl(sth_handle* h, int lvl, const double* r, double* rc, hip
 }
 
 static int prolong_lvl(sth_handle* h, int lvl, const double* e, double* u, hipStream_t st) {
+    h->tlev = lvl;
     long Sc = h->lev_S[lvl + 1];
     double dof = (double)Sc * slab_len(h);
     Timed tm(h, STH_K_PROLONG, dof * 4.0 * h->Nt, dof * 40.0, st);
@@ -260,8 +285,16 @@ static int prolong_lvl(sth_handle* h, int lvl, const double* e, double* u, hipSt
 }
 
 static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool zero_guess, hipStream_t st) {
+    h->tlev = lvl;
     int rc;
-    if (lvl == h->L - 1) return coarse_solve(h, lvl, f, u, st);
+    if (lvl == h->L - 1) {
+        if (lvl > 0) return coarse_solve(h, lvl, f, u, st);      // zero initial guess on coarse levels
+        // a single level: correct the iterate, u += L^{-1}(f - L u), so that
+        // an inexact (reduced-precision) forward substitution still converges
+        const long S = h->lev_S[0];
+        if ((rc = residual(h, 0, f, u, h->buf1, 0, S, 1.0, st))) return rc;
+        return slab_inverse(h, 0, h->buf1, u, 1, 1.0, 0, S, st, /*fwdsub=*/S > 1);
+    }
     long ns = h->lev_S[lvl];
     if (zero_guess && h->nu_pre == 0) {
         Timed tm(h, STH_K_OTHER, 0, 8.0 * ns * slab_len(h), st);
@@ -282,6 +315,7 @@ static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool z
 }
 
 static int norm2_dev(sth_handle* h, const double* v, long len, hipStream_t st) {
+    h->tlev = 0;
     Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
     HIPCHK(launch_norm2(v, len, h->partial, h->dnorm, st));
     return STH_OK;
@@ -318,6 +352,7 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     const double* At = (kind == FWD_U || kind == INV_U) ? h->Ti : h->Ci;    // A^T padded
     const long n = h->n;
     double dof = (double)rows * h->Nx;
+    h->tlev = 0;
     if (h->dim == 2 && xform2d_supported(h->np)) {
         Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, 16.0 * dof, st);
         HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st));
@@ -327,12 +362,12 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     const double* T = fwd ? A : At;
     int rc;
     if (h->dim == 2) {
-        if ((rc = xform_x(h, 0, in, tmp, T, rows * n, 1.0, st))) return rc;
-        if ((rc = xform_s(h, tmp, out, T, rows, n, st))) return rc;
+        if ((rc = xform_x(h, STH_FP64, 0, in, tmp, T, rows * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, STH_FP64, tmp, out, T, rows, n, st))) return rc;
     } else {
-        if ((rc = xform_x(h, 0, in, out, T, rows * n * n, 1.0, st))) return rc;       // x
-        if ((rc = xform_s(h, out, tmp, T, rows * n, n, st))) return rc;                // y
-        if ((rc = xform_s(h, tmp, out, T, rows, n * n, st))) return rc;                // z
+        if ((rc = xform_x(h, STH_FP64, 0, in, out, T, rows * n * n, 1.0, st))) return rc;   // x
+        if ((rc = xform_s(h, STH_FP64, out, tmp, T, rows * n, n, st))) return rc;            // y
+        if ((rc = xform_s(h, STH_FP64, tmp, out, T, rows, n * n, st))) return rc;            // z
     }
     return STH_OK;
 }
@@ -348,18 +383,21 @@ static const double* level_ktmt(sth_handle* h, int lvl) { return h->dktmt + (siz
 // one smoothing step on level lvl; ec (not null): add the prolonged coarse
 // correction of level lvl+1 first
 static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st, const double* ec = nullptr) {
+    h->tlev = lvl;
     long S = h->lev_S[lvl];
     double dof = (double)S * slab_len(h);
     int c = h->ecur[lvl];
     double bytes = (zero_guess ? 16.0 : 24.0) * dof + (ec ? 4.0 * dof : 0.0);
     Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0 + (ec ? 2.0 * h->Nt : 0.0)), bytes, st);
     HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
-                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, st));
+                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, nullptr,
+                             st));
     h->ecur[lvl] = 1 - c;
     return STH_OK;
 }
 
 static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
+    h->tlev = lvl;
     if (lvl > 0) h->ecur[lvl] = 0;
     long S = h->lev_S[lvl];
     if (lvl == h->L - 1) {
@@ -374,8 +412,16 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * slab_len(h), 0.0, st));
         zero_guess = false;
     }
-    for (int i = 0; i < h->nu_pre; ++i)
+    int pre = h->nu_pre;
+    if (lvl == 0 && h->presmoothed) {
+        // the first smoothing step ran with the residual of the stopping test
+        h->ecur[0] = 1 - h->ecur[0];
+        h->presmoothed = false;
+        --pre;
+    }
+    for (int i = 0; i < pre; ++i)
         if ((rc = eig_smooth(h, lvl, zero_guess && i == 0, st))) return rc;
+    h->tlev = lvl;
     {
         long Sc = h->lev_S[lvl + 1];
         double dof = (double)S * slab_len(h);
@@ -384,6 +430,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
                                          eig_u(h, lvl, h->ecur[lvl]), eig_f(h, lvl + 1), Sc, st));
     }
     if ((rc = eig_vcycle(h, lvl + 1, true, st))) return rc;
+    h->tlev = lvl;
     const double* ec = eig_u(h, lvl + 1, h->ecur[lvl + 1]);
     if (h->nu_post == 0) return prolong_lvl(h, lvl, ec, eig_u(h, lvl, h->ecur[lvl]), st);
     for (int i = 0; i < h->nu_post; ++i)
@@ -391,30 +438,58 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     return STH_OK;
 }
 
-// nodal residual of the current eigenbasis iterate into buf1, squared norm to
-// the pinned host scalar (not synchronised)
-static int eig_residual_norm(sth_handle* h, hipStream_t st) {
-    long S = h->lev_S[0];
-    long len = S * slab_len(h);
-    double dof = (double)len;
-    if (h->dim == 2 && xform2d_supported(h->np)) {
-        // fused: eigenbasis residual -> C r^ C^T -> sum of squares (nothing stored)
-        {
-            Timed tm(h, STH_K_XFORM_2D, dof * (4.0 * h->n + 4.0 * h->Nt), dof * 16.0, st);
-            HIPCHK(launch_eig_resnorm2d(h->Nt, h->e0, eig_u(h, 0, h->ecur[0]), level_ktmt(h, 0), h->mu1, h->Cf,
-                                        h->n, h->np, S, h->partial, kNormBlocks, h->dnorm, st));
-        }
-        HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
-        return STH_OK;
+// Residual r^ = f^ - L u^ of the current eigenbasis iterate into buf0 and
+// ||r^||^2 to the pinned host scalar hnorm[2] (not synchronised).  With
+// pre-smoothing in the cycle and a level below, the same kernel also takes
+// the next cycle's first smoothing step from the iterate (into the other
+// buffer of the pair, adopted by the next V-cycle), so the residual pass and
+// the smoothing pass share their reads of f^ and u^.
+static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
+    h->tlev = 0;
+    const long S = h->lev_S[0];
+    const long len = S * slab_len(h);
+    const double dof = (double)len;
+    const int c = h->ecur[0];
+    if (h->nu_pre >= 1 && h->L > 1) {
+        Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), 32.0 * dof, st);
+        HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c),
+                                 eig_u(h, 0, 1 - c), S, h->omega, false, nullptr, h->tr, h->buf0, st));
+        h->presmoothed = true;
+    } else {
+        Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
+        HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c), h->buf0,
+                                   S, st));
     }
     {
-        Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
-        HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, h->ecur[0]),
-                                   h->buf0, S, st));
+        Timed tm(h, STH_K_NORM, 2.0 * dof, 8.0 * dof, st);
+        HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + 2, st));
     }
-    int rc = spatial_apply(h, INV_C, h->buf0, h->buf1, S * h->Nt, eig_u(h, 0, 1 - h->ecur[0]), st);
-    if (rc) return rc;
-    if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
+    HIPCHK(hipMemcpyAsync(h->hnorm + 2, h->dnorm + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    return STH_OK;
+}
+
+// The B-spline residual norm ||(I (x) C_x) r^||^2 (C = M_1 U = U^{-T}) of
+// r^ in buf0 to hnorm[0] (not synchronised); buf0 is consumed.
+static int eig_exact_norm(sth_handle* h, hipStream_t st) {
+    h->tlev = 0;
+    const long S = h->lev_S[0];
+    const long len = S * slab_len(h);
+    const double dof = (double)len;
+    const long rows = S * h->Nt;
+    int rc;
+    if (h->dim == 2 && xform2d_supported(h->np)) {
+        // r = C r^ C^T per image and the sum of its squares, r not stored
+        Timed tm(h, STH_K_RESNORM, dof * 4.0 * h->n, dof * 8.0, st);
+        HIPCHK(launch_xform2d_norm(h->buf0, h->Cf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm, st));
+    } else if (h->dim == 2) {
+        // per-axis transforms buf0 -> buf1 -> buf0
+        if ((rc = spatial_apply(h, INV_C, h->buf0, h->buf0, rows, h->buf1, st))) return rc;
+        if ((rc = norm2_dev(h, h->buf0, len, st))) return rc;
+    } else {
+        // x: buf0 -> buf1, y: buf1 -> buf0, z: buf0 -> buf1
+        if ((rc = spatial_apply(h, INV_C, h->buf0, h->buf1, rows, h->buf0, st))) return rc;
+        if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
+    }
     HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
     return STH_OK;
 }
@@ -485,9 +560,17 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
         S /= 2;
         total += vecsl * sizeof(double) * (size_t)S * slab;
     }
-    total += sizeof(double) * (kNormBlocks + 1 + L * 2 * kNt * kNt);
+    total += sizeof(double) * (kNormBlocks + 2 + L * 2 * kNt * kNt);
     *bytes = total;
     return STH_OK;
+}
+
+size_t sth_problem_vector_len(const sth_problem* p) {
+    if (!p) return 0;
+    Problem q = to_problem(p);
+    if (!validate(q).empty()) return 0;
+    long n = q.n();
+    return (size_t)q.n_slabs * q.Nt() * n * n * (q.dim == 3 ? n : 1);
 }
 
 int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
@@ -520,11 +603,8 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         delete h;
         return fail(STH_EINVAL, "iterate_basis must be 0 or 1");
     }
-    if (h->prec != STH_FP64 && !(h->dim == 2 && xform2d_supported(h->np))) {
-        delete h;
-        return fail(STH_EINVAL, "reduced-precision transforms (FP32, BF16x3) need a 2-D problem with n <= 96");
-    }
     h->L = (int)h->S.levels.size();
+    h->nb_lo = std::pow(h->S.m1_min, h->dim);
     for (auto& lv : h->S.levels) {
         h->lev_S.push_back(lv.S);
         TimeOp op{};
@@ -576,7 +656,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
-        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 1) ||
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 3) ||
         !dalloc(&h->dktmt, (size_t)h->L * 2 * kNt * kNt))
         return cleanup(STH_ENOMEM, "device allocation failed");
     std::vector<double> ktmt((size_t)h->L * 2 * kNt * kNt);
@@ -614,7 +694,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
             hipMemcpyAsync(h->Ci, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
             return cleanup(STH_EHIP, "upload of the setup failed");
     }
-    if (hipHostMalloc((void**)&h->hnorm, sizeof(double), 0) != hipSuccess)
+    if (hipHostMalloc((void**)&h->hnorm, 3 * sizeof(double), 0) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
     if (hipMemcpyAsync(h->Tf, Tf.data(), Tf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->Ti, Ti.data(), Ti.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -711,7 +791,7 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
     long len = h->lev_S[0] * slab_len(h);
     if (h->basis == 1) {
         if ((rc = eig_vcycle(h, 0, false, st))) return rc;
-        return eig_residual_norm(h, st);
+        return eig_residual_cheap(h, st);
     }
     if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
     if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
@@ -720,13 +800,18 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
     return STH_OK;
 }
 
-// Captures solve_iteration into a HIP graph for (f, u, stream); replays are
-// cheaper to launch than the individual kernels.  Not used on the legacy
-// default stream, where capture is not allowed.
-static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_t st) {
+// Captures solve_iteration into a HIP graph for (f, u); replays are cheaper
+// to launch than the individual kernels and may go to any stream.  Not used
+// on the legacy default stream, where capture is not allowed.  Enqueues one
+// iteration without waiting for it.
+static int graph_launch(sth_handle* h, const double* f, double* u, hipStream_t st) {
     const int cur0 = h->basis == 1 ? h->ecur[0] : 0;     // eigenbasis iterate buffer at entry
-    if (!h->gexec || h->gf != f || h->gu != u || h->gst != st || h->gcur != cur0 ||
-        h->gmask != (h->timing ? h->timing_mask : 0u)) {
+    const unsigned mask = h->timing ? h->timing_mask : 0u;
+    if (!h->gexec || h->gf != f || h->gu != u || h->gcur != cur0 || h->gmask != mask) {
+        if (!h->allow_capture) {                          // capture later; run this one eagerly
+            h->graph_launched = false;
+            return solve_iteration(h, f, u, st);
+        }
         drop_graph(h);
         h->gcur = cur0;
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -745,8 +830,7 @@ static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_
         HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
         h->gf = f;
         h->gu = u;
-        h->gst = st;
-        h->gmask = h->timing ? h->timing_mask : 0u;
+        h->gmask = mask;
     }
     else if (h->basis == 1) {
         // replaying does not run the host-side bookkeeping of the capture:
@@ -754,7 +838,12 @@ static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_
         if ((h->nu_pre + h->nu_post) % 2 == 1) h->ecur[0] = 1 - h->ecur[0];
     }
     HIPCHK(hipGraphLaunch(h->gexec, st));
-    HIPCHK(hipStreamSynchronize(st));
+    h->graph_launched = true;
+    return STH_OK;
+}
+
+// after a replay has completed: add the times of its timed launches
+static int graph_collect(sth_handle* h) {
     for (auto& r : h->grecs) {
         float e = 0;
         HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
@@ -766,57 +855,150 @@ static int graph_iteration(sth_handle* h, const double* f, double* u, hipStream_
     return STH_OK;
 }
 
+}  // extern "C"
+
+namespace sth {
+
+// Asynchronous solve, in three calls that only enqueue work on st; between
+// them the caller waits for the stream (sth_solve) or polls an event (the
+// serving loop).  solve_begin: ||f||^2 and the initial residual norm^2 to
+// the pinned host scalars.
+int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxit, hipStream_t st) {
+    if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
+    auto& v = h->sv;
+    v = sth_handle::SolveState{};
+    v.f = f;
+    v.u = u;
+    v.st = st;
+    v.rtol = rtol;
+    v.maxit = maxit;
+    h->graph_launched = false;
+    h->presmoothed = false;
+    h->tlev = 0;
+    const long len = h->lev_S[0] * slab_len(h);
+    {
+        Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
+        HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + 1, st));
+    }
+    HIPCHK(hipMemcpyAsync(h->hnorm + 1, h->dnorm + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+    int rc;
+    if (h->basis == 1) {
+        // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
+        const long rows = h->lev_S[0] * h->Nt;
+        h->ecur[0] = 0;
+        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st))) return rc;
+        if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) return rc;
+        return eig_residual_cheap(h, st);
+    }
+    if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
+    if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
+    HIPCHK(hipMemcpyAsync(h->hnorm, h->dnorm, sizeof(double), hipMemcpyDeviceToHost, st));
+    return STH_OK;
+}
+
+static bool solve_should_stop(const sth_handle::SolveState& v) {
+    return !(v.rn > v.rtol * v.fn) || v.it >= v.maxit || !std::isfinite(v.rn) || v.growth >= 3;
+}
+
+static int enqueue_iteration(sth_handle* h) {
+    auto& v = h->sv;
+    v.phase = 1;
+    // kernel timing records events around individual launches, so it runs
+    // the iterations eagerly
+    if (v.st != nullptr && h->use_graph && !h->timing) return graph_launch(h, v.f, v.u, v.st);
+    h->graph_launched = false;
+    return solve_iteration(h, v.f, v.u, v.st);
+}
+
+// Once the work enqueued by the previous call has completed: read the
+// residual norm, then enqueue either the next iteration (*more = true) or
+// the final mapping of the result into u (*more = false).
+//
+// Eigenbasis iteration: every cycle yields ||r^|| of its residual in the
+// eigenbasis; the B-spline residual satisfies ||r||^2 >= nb_lo ||r^||^2
+// (the squared singular values of I (x) C are products of eigenvalues of
+// M_1, nb_lo = lambda_min(M_1)^dim).  While sqrt(nb_lo) ||r^|| > rtol ||f|| the cycle is
+// provably not converged and the next one starts at once; otherwise the
+// exact ||r|| is evaluated and decides, as it would in every cycle, so the
+// cycle count is that of the plain stopping test.  Growth is watched on
+// ||r^||.
+int solve_continue(sth_handle* h, bool* more) {
+    auto& v = h->sv;
+    *more = false;
+    if (v.phase == 2) return STH_OK;
+    if (h->graph_launched) {
+        int rc = graph_collect(h);
+        if (rc) return rc;
+        h->graph_launched = false;
+    }
+    const bool eig = h->basis == 1;
+    if (v.phase == 3) {
+        v.rn = std::sqrt(h->hnorm[0]);
+    } else {
+        const double r = std::sqrt(h->hnorm[eig ? 2 : 0]);
+        if (v.phase == 0) {
+            v.fn = std::sqrt(h->hnorm[1]);
+            if (v.fn == 0.0) v.fn = 1.0;
+            v.prev = r;
+        } else {
+            ++v.it;
+            if (std::isfinite(r)) {
+                v.growth = (r > v.prev) ? v.growth + 1 : 0;
+                v.prev = r;
+            }
+        }
+        v.rn = r;
+        if (eig) {
+            v.rn = std::sqrt(h->nb_lo) * r;             // lower bound of ||r||
+            *more = true;
+            if (std::isfinite(r) && v.rn > v.rtol * v.fn && v.it < v.maxit && v.growth < 3)
+                return enqueue_iteration(h);
+            v.phase = 3;
+            return eig_exact_norm(h, v.st);
+        }
+    }
+    if (!solve_should_stop(v)) {
+        *more = true;
+        return enqueue_iteration(h);
+    }
+    v.phase = 2;
+    if (eig) {
+        // u = (I (x) U_x) u^
+        return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st);
+    }
+    return STH_OK;
+}
+
+// Outcome of a finished solve: STH_OK when the tolerance was met.
+int solve_result(sth_handle* h, int* iters, double* relres) {
+    const auto& v = h->sv;
+    if (iters) *iters = v.it;
+    if (relres) *relres = v.rn / v.fn;
+    if (!std::isfinite(v.rn)) return fail(STH_ENOCONV, "residual is not finite");
+    if (v.growth >= 3) return fail(STH_ENOCONV, "residual grew over 3 consecutive cycles");
+    if (v.rn > v.rtol * v.fn) return fail(STH_ENOCONV, "maxit reached");
+    return STH_OK;
+}
+
+void solve_allow_capture(sth_handle* h, bool allow) { h->allow_capture = allow; }
+
+}  // namespace sth
+
+extern "C" {
+
 int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit, int* iters, double* relres,
               void* stream) {
     if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
     hipStream_t st = (hipStream_t)stream;
-    long len = h->lev_S[0] * slab_len(h);
-    double fn = 0.0, rn = 0.0;
-    int rc = read_norm(h, f, len, st, &fn);
+    int rc = solve_begin(h, f, u, rtol, maxit, st);
+    bool more = true;
+    while (rc == STH_OK && more) {
+        HIPCHK(hipStreamSynchronize(st));
+        rc = solve_continue(h, &more);
+    }
     if (rc) return rc;
-    if (fn == 0.0) fn = 1.0;
-    const long rows = h->lev_S[0] * h->Nt;
-    if (h->basis == 1) {
-        // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
-        h->ecur[0] = 0;
-        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st))) return rc;
-        if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) return rc;
-        if ((rc = eig_residual_norm(h, st))) return rc;
-        HIPCHK(hipStreamSynchronize(st));
-        rn = std::sqrt(h->hnorm[0]);
-    } else {
-        if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
-        if ((rc = read_norm(h, h->buf1, len, st, &rn))) return rc;
-    }
-    int it = 0, growth = 0;
-    double prev = rn;
-    while (rn > rtol * fn && it < maxit) {
-        // kernel timing records events around individual launches, so it
-        // runs the iterations eagerly
-        if (st != nullptr && h->use_graph && !h->timing) {
-            if ((rc = graph_iteration(h, f, u, st))) return rc;
-        } else {
-            if ((rc = solve_iteration(h, f, u, st))) return rc;
-            HIPCHK(hipStreamSynchronize(st));
-        }
-        rn = std::sqrt(h->hnorm[0]);
-        ++it;
-        if (!std::isfinite(rn)) break;
-        growth = (rn > prev) ? growth + 1 : 0;
-        prev = rn;
-        if (growth >= 3) break;
-    }
-    if (h->basis == 1) {
-        // u = (I (x) U_x) u^
-        if ((rc = spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), u, rows, h->buf0, st))) return rc;
-        HIPCHK(hipStreamSynchronize(st));
-    }
-    if (iters) *iters = it;
-    if (relres) *relres = rn / fn;
-    if (!std::isfinite(rn)) return fail(STH_ENOCONV, "residual is not finite");
-    if (growth >= 3) return fail(STH_ENOCONV, "residual grew over 3 consecutive cycles");
-    if (rn > rtol * fn) return fail(STH_ENOCONV, "maxit reached");
-    return STH_OK;
+    HIPCHK(hipStreamSynchronize(st));
+    return solve_result(h, iters, relres);
 }
 
 int sth_use_graphs(sth_handle* h, int enable) {
@@ -873,6 +1055,12 @@ int sth_timing(sth_handle* h, unsigned class_mask) {
     }
     h->timing = class_mask != 0;
     h->timing_mask = class_mask;
+    return STH_OK;
+}
+
+int sth_timing_level(sth_handle* h, int level) {
+    if (!h || level < -1 || level >= h->L) return fail(STH_EINVAL, "bad argument");
+    h->timing_level = level;
     return STH_OK;
 }
 

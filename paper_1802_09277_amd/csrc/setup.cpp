@@ -740,6 +740,15 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
             for (int k = i; k < n; ++k) v += Linv(k, i) * Q(k, j);
             s.U(i, j) = v;
         }
+    if (p.basis == 1) {
+        // C = M1 U satisfies C C^T = M1 (U U^T = M1^{-1}), so the squared
+        // singular values of C are the eigenvalues of M1
+        std::vector<double> ev;
+        Mat Qm;
+        sym_eigen(s.M1, ev, Qm);
+        s.m1_min = *std::min_element(ev.begin(), ev.end());
+        s.m1_max = *std::max_element(ev.begin(), ev.end());
+    }
     // temporal levels
     s.levels.clear();
     int S = p.n_slabs;

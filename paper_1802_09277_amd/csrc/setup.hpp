@@ -71,6 +71,7 @@ struct Setup {
     int n = 0, Nt = 0;
     Mat M1, K1, U;         // 1-D spatial matrices (interior), eigenvectors
     std::vector<double> mu;
+    double m1_min = 0, m1_max = 0;   // extreme eigenvalues of M1 (eigenbasis iteration only)
     std::vector<TemporalLevel> levels;
 };
 

@@ -1,4 +1,4 @@
-"""Reduced-precision spatial transforms (FP32 MFMA, FP32 accumulation) with
+"""Reduced-precision spatial transforms (FP32 MFMA or BF16x3, FP32 accumulation) with
 the FP64 residual and multigrid: the slab inverse is approximate, the solve
 still reaches the FP64 tolerance and the solution matches the FP64 oracle's
 direct solution to the accuracy that tolerance allows.  (The paper states
@@ -17,21 +17,30 @@ from oracle.mg import MultigridOracle
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-SHAPE = dict(dim=2, n_elem=30, degree=3, n_slabs=16, n_elem_t=2)
+# the LDS-resident 2-D transform (n <= 96), the per-axis transforms of a
+# large 2-D image (n = 100) and of a 3-D problem
+SHAPES = {
+    "2d_fused": (dict(dim=2, n_elem=30, degree=3, n_slabs=16, n_elem_t=2), 4),
+    "2d_axiswise": (dict(dim=2, n_elem=100, degree=2, n_slabs=4, n_elem_t=2), 2),
+    "3d": (dict(dim=3, n_elem=10, degree=2, n_slabs=8, n_elem_t=2), 2),
+}
 
 
 @functools.lru_cache(maxsize=None)
-def oracle():
-    prob = OProblem(**SHAPE)
-    return prob, MultigridOracle(prob, coarse_slabs=4)
+def oracle(name):
+    shape, cs = SHAPES[name]
+    prob = OProblem(**shape)
+    return prob, MultigridOracle(prob, coarse_slabs=cs)
 
 
+@pytest.mark.parametrize("name", list(SHAPES))
 @pytest.mark.parametrize("prec,bound", [("fp32", 1e-4), ("bf16x3", 1e-3)])
-def test_reduced_precision_block_solve_accuracy(prec, bound):
+def test_reduced_precision_block_solve_accuracy(name, prec, bound):
     import paper_1802_09277_amd as sth
-    print(f"[gpu-precision] {prec} block_solve {SHAPE}", flush=True)
-    prob, mg = oracle()
-    s = sth.Solver(**SHAPE, prec=prec, coarse_slabs=4)
+    shape, cs = SHAPES[name]
+    print(f"[gpu-precision] {prec} block_solve {name} {shape}", flush=True)
+    prob, mg = oracle(name)
+    s = sth.Solver(**shape, prec=prec, coarse_slabs=cs)
     r = W.random_vector(31, prob.n_dof)
     z = s.new_vector()
     s.block_solve(torch.from_numpy(r).cuda(), z)
@@ -42,18 +51,20 @@ def test_reduced_precision_block_solve_accuracy(prec, bound):
     assert 1e-12 < err < bound
 
 
+@pytest.mark.parametrize("name", list(SHAPES))
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_reduced_precision_solve(prec):
+def test_reduced_precision_solve(name, prec):
     import paper_1802_09277_amd as sth
-    print(f"[gpu-precision] {prec} solve {SHAPE}", flush=True)
-    prob, mg = oracle()
-    f = assemble_rhs(prob, W.random_modes(6, 2))
+    shape, cs = SHAPES[name]
+    print(f"[gpu-precision] {prec} solve {name} {shape}", flush=True)
+    prob, mg = oracle(name)
+    f = assemble_rhs(prob, W.random_modes(6, prob.dim))
     ud = mg.levels[0].forward_substitution(f)
     fd = torch.from_numpy(f).cuda()
-    s64 = sth.Solver(**SHAPE, coarse_slabs=4)
+    s64 = sth.Solver(**shape, coarse_slabs=cs)
     u64 = s64.new_vector()
     it64, rr64, _ = s64.solve(fd, u64, rtol=1e-10, maxit=80)
-    s = sth.Solver(**SHAPE, prec=prec, coarse_slabs=4)
+    s = sth.Solver(**shape, prec=prec, coarse_slabs=cs)
     u = s.new_vector()
     it, rr, _ = s.solve(fd, u, rtol=1e-10, maxit=80)
     torch.cuda.synchronize()
@@ -65,10 +76,3 @@ def test_reduced_precision_solve(prec):
     assert rr <= 1e-10
     assert it <= it64 + 2
     assert e_direct <= 1e-7 and e_fp64 <= 1e-7
-
-
-def test_reduced_precision_rejected_where_unsupported():
-    import paper_1802_09277_amd as sth
-    for prec in ("fp32", "bf16x3"):
-        with pytest.raises(sth.StatusError):
-            sth.Solver(dim=3, n_elem=6, degree=2, n_slabs=2, n_elem_t=2, prec=prec)

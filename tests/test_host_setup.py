@@ -70,6 +70,22 @@ def test_setup_matches_oracle_and_identities(shape):
         s_l //= 2
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+def test_residual_norm_bound_of_the_eigenbasis(shape):
+    # C = M_1 U maps eigenbasis coefficients back to B-spline ones; since
+    # U^T M_1 U = I, C C^T = M_1, so ||(C (x) C) r^|| >= lambda_min(M_1)^(d/2)
+    # ||r^|| -- the bound that lets the eigenbasis solve skip the exact norm
+    F0 = sth.host_factors(level=0, **shape)
+    M1o, _ = space_matrices_1d(shape["n_elem"], shape["degree"])
+    C = M1o @ F0["U"]
+    assert np.allclose(C @ C.T, M1o, atol=1e-13)
+    lam = np.linalg.eigvalsh(M1o).min()
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        R = rng.standard_normal((len(C), len(C)))
+        assert np.linalg.norm(C @ R @ C.T) >= lam * np.linalg.norm(R) * (1 - 1e-12)
+
+
 def test_level_count():
     kw = dict(level=0, dim=2, n_elem=4, degree=2, n_elem_t=2)
     assert sth.host_factors(n_slabs=16, coarse_slabs=1, **kw)["n_levels"] == 5
