@@ -92,6 +92,12 @@ typedef struct {
                            transforms then run once on f, once per cycle on the
                            residual for the stopping test, and once on the
                            result.  Same iterates in exact arithmetic. */
+    int temporal_form;  /* how A_n^{-1} treats the temporal pencil (K_t, M_t),
+                           Section 3.3: 0 diagonalisation K_t V = M_t V Z
+                           (STH_ECOND when cond(V) > 1e8); 1 real Schur form
+                           M_t^{-1} K_t = Q R Q^T (orthogonal Q, a block back
+                           substitution per spatial mode); 2 diagonalisation
+                           unless cond(V) > 1e6, then real Schur (default) */
 } sth_problem;
 
 /* Right-hand side as a sum of separable modes (host arrays):
@@ -107,8 +113,8 @@ typedef struct {
 } sth_rhs_modes;
 
 /* Fills p with the defaults of Section 4.4: theta 0.01, omega 1/2, T 1,
- * V(1,1), FP64 transforms, and coarse_slabs 8 (the shape fields are left at
- * zero). */
+ * V(1,1), FP64 transforms, coarse_slabs 8 and the automatic temporal form
+ * (the shape fields are left at zero). */
 void sth_problem_default(sth_problem* p);
 
 /* Device bytes that sth_setup would allocate for this problem (factors,
@@ -202,6 +208,9 @@ typedef struct {
     int n, N_t, n_levels;
     double cond_V;
     double *M1, *K1, *U, *mu, *Kt, *Mt, *Pt, *V, *W, *eig_re, *eig_im;
+    int schur;          /* 1: real Schur form, V = Q, W = Q^T M_t^{-1} and
+                           W K_t V = R (quasi upper triangular, copied to R) */
+    double* R;          /* N_t*N_t, may be NULL */
 } sth_factors;
 int sth_host_factors(const sth_problem* p, int level, sth_factors* out);
 
@@ -221,7 +230,9 @@ typedef enum {
     STH_K_EIG_SMOOTH = 9,   /* eigenbasis iteration: residual + slab inverse + update */
     STH_K_EIG_RESID = 10,   /* eigenbasis iteration: residual (and restriction) */
     STH_K_RESNORM = 11,     /* eigenbasis iteration: residual mapped to B-splines, sum of squares */
-    STH_K_COUNT = 12
+    STH_K_EIG_CYCLE_END = 12, /* eigenbasis iteration: residual norm, next smoothing step and
+                               restriction in one pass on the finest level */
+    STH_K_COUNT = 13
 } sth_kernel_class;
 
 /* Record an event pair around every launch of the kernel classes whose bit

@@ -18,7 +18,8 @@ STATUS = {0: "STH_OK", -1: "STH_EINVAL", -2: "STH_ENOMEM", -3: "STH_EHIP", -4: "
           -5: "STH_ECOND", -6: "STH_ENOCONV", -7: "STH_ENODEV", -8: "STH_EAGAIN"}
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KCLASS = {"residual": 0, "xform_x": 1, "xform_s": 2, "timemix": 3, "restrict": 4, "prolong": 5,
-          "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10, "resnorm": 11}
+          "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10, "resnorm": 11,
+          "eig_cycle_end": 12}
 
 
 class StatusError(RuntimeError):
@@ -33,7 +34,7 @@ class Problem(ctypes.Structure):
                 ("n_slabs", ctypes.c_int), ("n_elem_t", ctypes.c_int), ("T", ctypes.c_double),
                 ("theta", ctypes.c_double), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int), ("coarse_slabs", ctypes.c_int),
-                ("iterate_basis", ctypes.c_int)]
+                ("iterate_basis", ctypes.c_int), ("temporal_form", ctypes.c_int)]
 
 
 class RhsModes(ctypes.Structure):
@@ -56,7 +57,7 @@ class Factors(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("N_t", ctypes.c_int), ("n_levels", ctypes.c_int),
                 ("cond_V", ctypes.c_double)] + [(nm, _DP) for nm in
                                                 ("M1", "K1", "U", "mu", "Kt", "Mt", "Pt", "V", "W",
-                                                 "eig_re", "eig_im")]
+                                                 "eig_re", "eig_im")] + [("schur", ctypes.c_int), ("R", _DP)]
 
 
 _lib = None
@@ -122,8 +123,11 @@ def _check(code):
 BASIS = {"nodal": 0, "eigen": 1}
 
 
+TEMPORAL = {"eigen": 0, "schur": 1, "auto": 2}
+
+
 def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal"):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto"):
     p = Problem()
     load_library().sth_problem_default(ctypes.byref(p))
     p.dim, p.n_elem, p.degree, p.n_slabs, p.n_elem_t = dim, n_elem, degree, n_slabs, n_elem_t
@@ -132,6 +136,7 @@ def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omeg
     if coarse_slabs is not None:
         p.coarse_slabs = int(coarse_slabs)
     p.iterate_basis = BASIS[basis] if isinstance(basis, str) else int(basis)
+    p.temporal_form = TEMPORAL[temporal] if isinstance(temporal, str) else int(temporal)
     return p
 
 
@@ -148,7 +153,7 @@ def host_factors(level=0, **kw):
     n = kw["n_elem"] + kw["degree"] - 2
     Nt = kw["n_elem_t"] + kw["degree"]
     arrs = {"M1": (n, n), "K1": (n, n), "U": (n, n), "mu": (n,), "Kt": (Nt, Nt), "Mt": (Nt, Nt),
-            "Pt": (2 * Nt, Nt), "V": (Nt, Nt), "W": (Nt, Nt), "eig_re": (Nt,), "eig_im": (Nt,)}
+            "Pt": (2 * Nt, Nt), "V": (Nt, Nt), "W": (Nt, Nt), "eig_re": (Nt,), "eig_im": (Nt,), "R": (Nt, Nt)}
     buf = {k: np.zeros(s) for k, s in arrs.items()}
     f = Factors()
     for k, a in buf.items():
@@ -156,6 +161,7 @@ def host_factors(level=0, **kw):
     _check(lib.sth_host_factors(ctypes.byref(p), level, ctypes.byref(f)))
     buf["cond_V"] = f.cond_V
     buf["n_levels"] = f.n_levels
+    buf["schur"] = bool(f.schur)
     return buf
 
 
@@ -204,13 +210,13 @@ class Solver:
     """One discrete problem on the GPU (setup factors and workspaces)."""
 
     def __init__(self, dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", stream=None):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP slab solver needs a gfx950 device")
         self.lib = load_library()
         self.problem = make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T, theta, omega, nu_pre,
-                                    nu_post, prec, coarse_slabs, basis)
+                                    nu_post, prec, coarse_slabs, basis, temporal)
         self.shape = dict(dim=dim, n_elem=n_elem, degree=degree, n_slabs=n_slabs, n_elem_t=n_elem_t)
         self.coarse_slabs = self.problem.coarse_slabs
         h = ctypes.c_void_p()

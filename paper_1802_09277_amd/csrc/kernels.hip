@@ -1094,7 +1094,7 @@ hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const d
 // ---------------------------------------------------------------------------
 // temporal transform and shifted divide
 // ---------------------------------------------------------------------------
-template <int NT>
+template <int NT, bool SCHUR>
 __device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, const double* g, double* z) {
     double h[NT], y[NT];
 #pragma unroll
@@ -1104,15 +1104,42 @@ __device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, cons
 #pragma unroll
         for (int t = 0; t < NT; ++t) h[t] += tm.W[t * kNt + t2] * g[t2];
     }
+    if (SCHUR) {
+        // (R + mu I) y = h, R quasi upper triangular: back substitution over
+        // its 1x1 and 2x2 diagonal blocks
 #pragma unroll
-    for (int k = 0; k < NT; ++k) {
-        if (tm.kind[k] == 0) {
-            y[k] = h[k] / (tm.re[k] + mu);
-        } else if (tm.kind[k] == 1 && k + 1 < NT) {
-            double a = tm.re[k] + mu, b = tm.im[k];
-            double det = a * a + b * b;
-            y[k] = (a * h[k] - b * h[k + 1]) / det;
-            y[k + 1] = (b * h[k] + a * h[k + 1]) / det;
+        for (int k = NT - 1; k >= 0; --k) {
+            if (tm.kind[k] == 1) continue;                       // solved with its second row
+            if (tm.kind[k] == 0) {
+                double r = h[k];
+#pragma unroll
+                for (int j = k + 1; j < NT; ++j) r -= tm.R[k * kNt + j] * y[j];
+                y[k] = r / (tm.R[k * kNt + k] + mu);
+            } else if (k >= 1) {                                 // rows k-1, k
+                double r0 = h[k - 1], r1 = h[k];
+#pragma unroll
+                for (int j = k + 1; j < NT; ++j) {
+                    r0 -= tm.R[(k - 1) * kNt + j] * y[j];
+                    r1 -= tm.R[k * kNt + j] * y[j];
+                }
+                const double a = tm.R[(k - 1) * kNt + k - 1] + mu, b = tm.R[(k - 1) * kNt + k];
+                const double c = tm.R[k * kNt + k - 1], d = tm.R[k * kNt + k] + mu;
+                const double det = a * d - b * c;
+                y[k - 1] = (d * r0 - b * r1) / det;
+                y[k] = (a * r1 - c * r0) / det;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (tm.kind[k] == 0) {
+                y[k] = h[k] / (tm.re[k] + mu);
+            } else if (tm.kind[k] == 1 && k + 1 < NT) {
+                double a = tm.re[k] + mu, b = tm.im[k];
+                double det = a * a + b * b;
+                y[k] = (a * h[k] - b * h[k + 1]) / det;
+                y[k + 1] = (b * h[k] + a * h[k + 1]) / det;
+            }
         }
     }
 #pragma unroll
@@ -1133,7 +1160,7 @@ __device__ __forceinline__ double mode_shift(int dim, const double* mu1, int n, 
     return mu;
 }
 
-template <int NT>
+template <int NT, bool SCHUR>
 __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
                                                  long Nx, const double* __restrict__ in,
                                                  double* __restrict__ out, long total) {
@@ -1145,31 +1172,67 @@ __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const doub
     double g[NT], z[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) g[t] = gp[(long)t * Nx];
-    shifted_solve<NT>(tm, mu, g, z);
+    shifted_solve<NT, SCHUR>(tm, mu, g, z);
     double* o = out + s * NT * Nx + m;
 #pragma unroll
     for (int t = 0; t < NT; ++t) o[(long)t * Nx] = z[t];
 }
 
-template <int NT>
-__global__ __launch_bounds__(256) void k_timemix_fwdsub(int dim, TimeMix tm, const double* __restrict__ mu1,
-                                                        int n, long Nx, const double* __restrict__ in,
-                                                        double* __restrict__ out, long S) {
-    long m = (long)blockIdx.x * 256 + threadIdx.x;
-    if (m >= Nx) return;
-    double mu = mode_shift(dim, mu1, n, m);
-    double prev = 0.0;
-    for (long s = 0; s < S; ++s) {
-        const double* gp = in + s * NT * Nx + m;
-        double g[NT], z[NT];
+// Exact forward substitution over S slabs in the spatial eigenbasis, parallel
+// in time.  Per mode the slab systems are A u_s = g_s + e_1 x_{s-1} with the
+// scalar x_{s-1} = u_{s-1}[N_t - 1], so u_s = a_s + x_{s-1} c with
+// a_s = A^{-1} g_s (independent over s) and c = A^{-1} e_1, and the scalars
+// obey x_s = a_s[N_t-1] + gamma x_{s-1}, gamma = c[N_t-1].  A block holds 32
+// modes x 8 slab groups: each thread solves its group's slabs (into out),
+// the groups' recurrences are chained through LDS, and a second sweep adds
+// x_{s-1} c.  in and out must differ.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
+                                                      long Nx, const double* __restrict__ in,
+                                                      double* __restrict__ out, long S) {
+    constexpr int MB = 32, G = 8;
+    __shared__ double xe_s[G][MB], gl_s[G][MB];
+    const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
+    const long m = (long)blockIdx.x * MB + ml;
+    const long L = (S + G - 1) / G;
+    const long sb = g * L, se = (sb + L < S) ? sb + L : S;
+    double c[NT], xe = 0.0, gl = 1.0, gamma = 0.0;
+    const bool active = m < Nx;
+    double mu = 0.0;
+    if (active) {
+        mu = mode_shift(dim, mu1, n, m);
+        double e1[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) g[t] = gp[(long)t * Nx];
-        g[0] += prev;
-        shifted_solve<NT>(tm, mu, g, z);
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(tm, mu, e1, c);
+        gamma = c[NT - 1];
+        for (long s = sb; s < se; ++s) {
+            const double* gp = in + s * NT * Nx + m;
+            double gv[NT], a[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) gv[t] = gp[(long)t * Nx];
+            shifted_solve<NT, SCHUR>(tm, mu, gv, a);
+            double* o = out + s * NT * Nx + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) o[(long)t * Nx] = a[t];
+            xe = a[NT - 1] + gamma * xe;          // group recurrence from x = 0
+            gl *= gamma;                          // gamma^(slabs so far)
+        }
+    }
+    xe_s[g][ml] = xe;
+    gl_s[g][ml] = gl;
+    __syncthreads();
+    if (!active) return;
+    double x = 0.0;                               // x entering the group
+    for (int h = 0; h < g; ++h) x = xe_s[h][ml] + gl_s[h][ml] * x;
+    for (long s = sb; s < se; ++s) {
         double* o = out + s * NT * Nx + m;
+        double u[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) o[(long)t * Nx] = z[t];
-        prev = z[NT - 1];
+        for (int t = 0; t < NT; ++t) u[t] = o[(long)t * Nx] + x * c[t];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) o[(long)t * Nx] = u[t];
+        x = u[NT - 1];
     }
 }
 
@@ -1178,16 +1241,23 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
     long Nx = (long)n * n * (dim == 3 ? n : 1);
     long total = S * Nx;
     if (total <= 0) return hipSuccess;
+    if (fwdsub && in == out) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
-    dim3 gridm((unsigned)((Nx + 255) / 256));
-#define STH_TM_CASE(NTV)                                                                              \
-    case NTV:                                                                                         \
-        if (fwdsub)                                                                                   \
-            hipLaunchKernelGGL(k_timemix_fwdsub<NTV>, gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, \
-                               out, S);                                                               \
-        else                                                                                          \
-            hipLaunchKernelGGL(k_timemix<NTV>, grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out,  \
-                               total);                                                                \
+    dim3 gridm((unsigned)((Nx + 31) / 32));
+#define STH_TM_LAUNCH(NTV, SC)                                                                           \
+    if (fwdsub)                                                                                          \
+        hipLaunchKernelGGL((k_timemix_scan<NTV, SC>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in,   \
+                           out, S);                                                                      \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_timemix<NTV, SC>), grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out,    \
+                           total);
+#define STH_TM_CASE(NTV)                 \
+    case NTV:                            \
+        if (tm.schur) {                  \
+            STH_TM_LAUNCH(NTV, true)     \
+        } else {                         \
+            STH_TM_LAUNCH(NTV, false)    \
+        }                                \
         break;
     switch (Nt) {
         STH_TM_CASE(2) STH_TM_CASE(3) STH_TM_CASE(4) STH_TM_CASE(5)
@@ -1195,6 +1265,7 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
         default: return hipErrorInvalidValue;
     }
 #undef STH_TM_CASE
+#undef STH_TM_LAUNCH
     return hipGetLastError();
 }
 
@@ -1223,16 +1294,13 @@ __device__ __forceinline__ void eig_residual_point(const double* __restrict__ kt
 // zero_guess u^in is taken as 0 (and not read).  uin and uout must differ
 // (the coupling reads the previous slab's old iterate).  PRO: the coarse
 // correction (P_t (x) I) ec of the next coarser level is added to u^in first
-// (prolongation fused into the first post-smoothing step).  RSTORE: the
-// residual f^ - L^ u^in is also stored in rh (the residual of u^in for the
-// stopping test, with the next cycle's first smoothing step done already).
-template <int NT, bool PRO, bool RSTORE>
+// (prolongation fused into the first post-smoothing step).
+template <int NT, bool PRO, bool SCHUR>
 __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                     const double* __restrict__ mu1, int n, long Nx,
                                                     const double* __restrict__ fh, const double* __restrict__ uin,
                                                     double* __restrict__ uout, long total, double omega,
-                                                    int zero_guess, const double* __restrict__ ec, Transfer tr,
-                                                    double* __restrict__ rh) {
+                                                    int zero_guess, const double* __restrict__ ec, Transfer tr) {
     long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     long s = idx / Nx, m = idx % Nx;
@@ -1274,11 +1342,7 @@ __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const d
 #pragma unroll
         for (int t = 0; t < NT; ++t) u[t] = 0.0;
     }
-    if (RSTORE) {
-#pragma unroll
-        for (int t = 0; t < NT; ++t) rh[base + (long)t * Nx] = g[t];
-    }
-    shifted_solve<NT>(tm, mu, g, z);
+    shifted_solve<NT, SCHUR>(tm, mu, g, z);
 #pragma unroll
     for (int t = 0; t < NT; ++t) uout[base + (long)t * Nx] = u[t] + omega * z[t];
 }
@@ -1338,6 +1402,88 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
     for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
 }
 
+// End of a cycle on the finest level, for one spatial mode and a chain of
+// `chain` consecutive slabs (chain even, starting at an even slab): the
+// residual r^ = f^ - L u^ of the iterate (its squares summed per block into
+// partial[blockIdx.x], fixed order), the next cycle's first smoothing step
+// u'^ = u^ + omega A^{-1} r^ (into uout), and the restriction of the residual
+// of u'^ to the next level, fc = (P_t^T (x) I)[r'_{2k}; r'_{2k+1}].  The last
+// time row of the previous slab (old and smoothed iterate) is carried in
+// registers along the chain; a chain after slab 0 first repeats the
+// smoothing step of its preceding slab for that row.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                       const double* __restrict__ mu1, int n, long Nx,
+                                                       const double* __restrict__ fh, const double* __restrict__ uin,
+                                                       double* __restrict__ uout, double* __restrict__ fc,
+                                                       Transfer tr, double omega, int chain, long total,
+                                                       double* __restrict__ partial) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double ssq = 0.0;
+    if (idx < total) {
+        const long q = idx / Nx, m = idx % Nx;
+        const double mu = mode_shift(dim, mu1, n, m);
+        const long s0 = q * chain;
+        double prev_old = 0.0, prev_new = 0.0;
+        if (s0 > 0) {
+            const long b = (s0 - 1) * NT * Nx + m;
+            double g[NT], u[NT], z[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                g[t] = fh[b + (long)t * Nx];
+                u[t] = uin[b + (long)t * Nx];
+            }
+            eig_residual_point<NT>(ktmt, mu, u, s0 > 1 ? uin[b - Nx] : 0.0, g);
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            prev_old = u[NT - 1];
+            prev_new = u[NT - 1] + omega * z[NT - 1];
+        }
+#pragma unroll 1
+        for (int k = 0; k < chain; k += 2) {
+            double acc[NT];
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const long b = (s0 + k + h) * NT * Nx + m;
+                double g[NT], g2[NT], u[NT], z[NT], up[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    g[t] = fh[b + (long)t * Nx];
+                    u[t] = uin[b + (long)t * Nx];
+                    g2[t] = g[t];
+                }
+                eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) ssq += g[t] * g[t];
+                shifted_solve<NT, SCHUR>(tm, mu, g, z);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    up[t] = u[t] + omega * z[t];
+                    uout[b + (long)t * Nx] = up[t];
+                }
+                eig_residual_point<NT>(ktmt, mu, up, prev_new, g2);
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g2[t];
+                prev_old = u[NT - 1];
+                prev_new = up[NT - 1];
+            }
+            const long mc = (s0 + k) / 2;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+        }
+    }
+    // block sum: butterfly within each wave, then the four wave sums in order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ssq;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 #define STH_NT_SWITCH(KER, GRID, ...)                                                      \
     switch (Nt) {                                                                           \
         case 2: hipLaunchKernelGGL(KER<2>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
@@ -1353,30 +1499,32 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
 template <int NT>
 static void eig_smooth_launch(dim3 grid, hipStream_t st, int dim, const TimeMix& tm, const double* ktmt,
                               const double* mu1, int n, long Nx, const double* fh, const double* uin, double* uout,
-                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr,
-                              double* rh) {
+                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr) {
     const int zg = zero_guess ? 1 : 0;
-    if (ec)
+    if (ec && tm.schur)
+        hipLaunchKernelGGL((k_eig_smooth<NT, true, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
+                           uout, total, omega, zg, ec, tr);
+    else if (ec)
         hipLaunchKernelGGL((k_eig_smooth<NT, true, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
-                           uin, uout, total, omega, zg, ec, tr, rh);
-    else if (rh)
+                           uin, uout, total, omega, zg, ec, tr);
+    else if (tm.schur)
         hipLaunchKernelGGL((k_eig_smooth<NT, false, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
-                           uin, uout, total, omega, zg, ec, tr, rh);
+                           uin, uout, total, omega, zg, ec, tr);
     else
         hipLaunchKernelGGL((k_eig_smooth<NT, false, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
-                           uin, uout, total, omega, zg, ec, tr, rh);
+                           uin, uout, total, omega, zg, ec, tr);
 }
 
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, const double* ec, const Transfer& tr, double* rh, hipStream_t st) {
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st) {
     long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
     if (total <= 0) return hipSuccess;
-    if (ec && (zero_guess || rh)) return hipErrorInvalidValue;
+    if (ec && zero_guess) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
     switch (Nt) {
 #define STH_ES_CASE(NTV) \
-        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr, rh); break;
+        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr); break;
         STH_ES_CASE(2) STH_ES_CASE(3) STH_ES_CASE(4) STH_ES_CASE(5) STH_ES_CASE(6) STH_ES_CASE(7) STH_ES_CASE(8)
 #undef STH_ES_CASE
         default: return hipErrorInvalidValue;
@@ -1560,6 +1708,35 @@ hipError_t launch_rhs(int dim, int Nt, int n, int n_modes, const double* Tpart, 
     if (total <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rhs, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, dim, Nt, n,
                        n_modes, Tpart, Xpart, f, S, Nx);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
+                                double omega, long S, int chain, double* partial, long max_partial, double* out,
+                                hipStream_t st) {
+    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_CE_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (tm.schur)                                                                                     \
+                hipLaunchKernelGGL((k_eig_cycle_end<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, \
+                                   Nx, fh, uin, uout, fc, tr, omega, chain, total, partial);                  \
+            else                                                                                              \
+                hipLaunchKernelGGL((k_eig_cycle_end<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,   \
+                                   n, Nx, fh, uin, uout, fc, tr, omega, chain, total, partial);               \
+            break;
+        STH_CE_CASE(2) STH_CE_CASE(3) STH_CE_CASE(4) STH_CE_CASE(5) STH_CE_CASE(6) STH_CE_CASE(7) STH_CE_CASE(8)
+#undef STH_CE_CASE
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
     return hipGetLastError();
 }
 

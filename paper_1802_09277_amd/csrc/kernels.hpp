@@ -13,12 +13,14 @@ struct TimeOp {                 // residual: temporal matrices of the level
     double Kt[kNt * kNt];
     double Mt[kNt * kNt];
 };
-struct TimeMix {                // slab inverse: temporal eigen data of the level
+struct TimeMix {                // slab inverse: temporal decomposition of the level
     double W[kNt * kNt];
     double V[kNt * kNt];
     double re[kNt];
     double im[kNt];
-    int kind[kNt];              // 0 real, 1 first of a pair, 2 second of a pair
+    int kind[kNt];              // 0 real / 1x1 block, 1 first of a pair / 2x2 block, 2 second
+    int schur;                  // 1: (R + mu I) y = W g by block back substitution
+    double R[kNt * kNt];        // real Schur form (quasi upper triangular)
 };
 struct Transfer {               // 2Nt x Nt prolongation
     double P[2 * kNt * kNt];
@@ -57,9 +59,11 @@ hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* 
 hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
                                  long nimg, double alpha, hipStream_t st);
 
-// Per slab and spatial mode: out[:, m] = V (Z + mu_m I)^{-1} W in[:, m].
-// fwdsub: instead, one pass over the S slabs per mode with the coupling of
-// the eigenbasis, g_s = in_s + e_1 out_{s-1}[Nt-1] (forward substitution).
+// Per slab and spatial mode: out[:, m] = A_m^{-1} in[:, m], A_m^{-1} =
+// V (Z + mu_m I)^{-1} W (or the real Schur form of the level).  fwdsub:
+// instead the exact solution of the S coupled slabs in the eigenbasis,
+// out_s = A_m^{-1}(in_s + e_1 out_{s-1}[Nt-1]) (forward substitution),
+// computed parallel in time (in and out must differ).
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
                           const double* in, double* out, long S, bool fwdsub, hipStream_t st);
 
@@ -67,11 +71,18 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 // ktmt = device K_t then M_t of the level):
 //  uout = v + omega A^{-1}(fh - L v) with v = uin (+ (P (x) I) ec when ec is
 //  not null: the prolonged coarse correction, S/2 coarse slabs); uin is not
-//  read when zero_guess (then ec must be null); rh (not null, only without
-//  ec): also rh = fh - L v
+//  read when zero_guess (then ec must be null)
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, const double* ec, const Transfer& tr, double* rh, hipStream_t st);
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st);
+//  end of a cycle on the finest level, in one pass over f^ and u^ (chains of
+//  `chain` slabs per thread, chain even and dividing S): out[0] = ||fh - L uin||^2,
+//  uout = uin + omega A^{-1}(fh - L uin), fc = (P^T (x) I)(fh - L uout) on slab
+//  pairs; partial needs max_partial >= ceil((S/chain) Nx / 256) entries
+hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
+                                double omega, long S, int chain, double* partial, long max_partial, double* out,
+                                hipStream_t st);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);

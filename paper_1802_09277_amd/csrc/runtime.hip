@@ -68,6 +68,9 @@ struct sth_handle {
     std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
     std::vector<int> ecur;              // which buffer of the pair holds u^ per level
     bool presmoothed = false;           // the other level-0 buffer holds u^ after one smoothing step
+                                        // and lf[1] the restriction of its residual
+    double* cpartial = nullptr;         // per-block partial sums of the cycle-end pass
+    long n_cpartial = 0;
     double nb_lo = 0.0;                 // ||(I (x) C) r^||^2 >= nb_lo ||r^||^2
     double* buf0 = nullptr;
     double* buf1 = nullptr;
@@ -258,8 +261,9 @@ static int smooth_step(sth_handle* h, int lvl, const double* f, double* u, bool 
 // exact solve of the coarsest level: slab-wise forward substitution
 //   u_1 = A^{-1} f_1,  u_m = A^{-1}(f_m + B u_{m-1})   (eq. equ_linear_system)
 // carried out in the spatial eigenbasis, where A = K_t (x) I + M_t (x) diag(mu)
-// and B = N_t (x) I: forward transforms of all slabs, one sequential pass over
-// the slabs per spatial mode, inverse transforms.  u is overwritten.
+// and B = N_t (x) I: forward transforms of all slabs, the coupled slabs of
+// every spatial mode solved parallel in time (a scalar recurrence carries the
+// coupling), inverse transforms.  u is overwritten.
 static int coarse_solve(sth_handle* h, int lvl, const double* f, double* u, hipStream_t st) {
     long S = h->lev_S[lvl];
     if (S == 1) return slab_inverse(h, lvl, f, u, 2, 1.0, 0, 1, st);
@@ -390,8 +394,7 @@ static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st, c
     double bytes = (zero_guess ? 16.0 : 24.0) * dof + (ec ? 4.0 * dof : 0.0);
     Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0 + (ec ? 2.0 * h->Nt : 0.0)), bytes, st);
     HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
-                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, nullptr,
-                             st));
+                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, st));
     h->ecur[lvl] = 1 - c;
     return STH_OK;
 }
@@ -412,17 +415,15 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * slab_len(h), 0.0, st));
         zero_guess = false;
     }
-    int pre = h->nu_pre;
     if (lvl == 0 && h->presmoothed) {
-        // the first smoothing step ran with the residual of the stopping test
+        // the cycle-end pass of the previous cycle (or of the initial
+        // residual) took the pre-smoothing step and restricted its residual
         h->ecur[0] = 1 - h->ecur[0];
         h->presmoothed = false;
-        --pre;
-    }
-    for (int i = 0; i < pre; ++i)
-        if ((rc = eig_smooth(h, lvl, zero_guess && i == 0, st))) return rc;
-    h->tlev = lvl;
-    {
+    } else {
+        for (int i = 0; i < h->nu_pre; ++i)
+            if ((rc = eig_smooth(h, lvl, zero_guess && i == 0, st))) return rc;
+        h->tlev = lvl;
         long Sc = h->lev_S[lvl + 1];
         double dof = (double)S * slab_len(h);
         Timed tm(h, STH_K_EIG_RESID, dof * (4.0 * h->Nt + 2.0 * h->Nt), dof * 16.0 + 0.5 * dof * 8.0, st);
@@ -438,29 +439,38 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     return STH_OK;
 }
 
-// Residual r^ = f^ - L u^ of the current eigenbasis iterate into buf0 and
-// ||r^||^2 to the pinned host scalar hnorm[2] (not synchronised).  With
-// pre-smoothing in the cycle and a level below, the same kernel also takes
-// the next cycle's first smoothing step from the iterate (into the other
-// buffer of the pair, adopted by the next V-cycle), so the residual pass and
-// the smoothing pass share their reads of f^ and u^.
+// ||r^||^2 of the residual r^ = f^ - L u^ of the current eigenbasis iterate
+// to the pinned host scalar hnorm[2] (not synchronised).  With one
+// pre-smoothing step in the cycle and a level below, a single pass (the
+// cycle-end kernel) also takes the next cycle's smoothing step (into the
+// other buffer of the pair) and restricts the residual of its result into
+// the next level's right-hand side; the next V-cycle adopts both.
+static int chain_length(const sth_handle* h) {
+    const long S = h->lev_S[0];
+    for (int c : {8, 4})
+        if (S % c == 0 && (S / c) * h->Nx >= 65536) return c;
+    return 2;
+}
+
 static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
     h->tlev = 0;
     const long S = h->lev_S[0];
     const long len = S * slab_len(h);
     const double dof = (double)len;
     const int c = h->ecur[0];
-    if (h->nu_pre >= 1 && h->L > 1) {
-        Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), 32.0 * dof, st);
-        HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c),
-                                 eig_u(h, 0, 1 - c), S, h->omega, false, nullptr, h->tr, h->buf0, st));
+    if (h->nu_pre == 1 && h->L > 1) {
+        const double Nt = h->Nt;
+        Timed tm(h, STH_K_EIG_CYCLE_END, dof * (12.0 * Nt + 10.0), 28.0 * dof, st);
+        HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
+                                    eig_u(h, 0, c), eig_u(h, 0, 1 - c), eig_f(h, 1), h->tr, h->omega, S,
+                                    chain_length(h), h->cpartial, h->n_cpartial, h->dnorm + 2, st));
         h->presmoothed = true;
     } else {
-        Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
-        HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c), h->buf0,
-                                   S, st));
-    }
-    {
+        {
+            Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
+            HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c),
+                                       h->buf0, S, st));
+        }
         Timed tm(h, STH_K_NORM, 2.0 * dof, 8.0 * dof, st);
         HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + 2, st));
     }
@@ -469,7 +479,8 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
 }
 
 // The B-spline residual norm ||(I (x) C_x) r^||^2 (C = M_1 U = U^{-T}) of
-// r^ in buf0 to hnorm[0] (not synchronised); buf0 is consumed.
+// the current eigenbasis iterate to hnorm[0] (not synchronised); r^ is
+// formed again in buf0.
 static int eig_exact_norm(sth_handle* h, hipStream_t st) {
     h->tlev = 0;
     const long S = h->lev_S[0];
@@ -477,6 +488,11 @@ static int eig_exact_norm(sth_handle* h, hipStream_t st) {
     const double dof = (double)len;
     const long rows = S * h->Nt;
     int rc;
+    {
+        Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
+        HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, h->ecur[0]),
+                                   h->buf0, S, st));
+    }
     if (h->dim == 2 && xform2d_supported(h->np)) {
         // r = C r^ C^T per image and the sum of its squares, r not stored
         Timed tm(h, STH_K_RESNORM, dof * 4.0 * h->n, dof * 8.0, st);
@@ -512,6 +528,7 @@ static Problem to_problem(const sth_problem* p) {
     q.prec = p->transform_prec;
     q.coarse_slabs = p->coarse_slabs;
     q.basis = p->iterate_basis;
+    q.temporal = p->temporal_form;
     return q;
 }
 
@@ -528,6 +545,7 @@ void sth_problem_default(sth_problem* p) {
     p->transform_prec = STH_FP64;
     p->coarse_slabs = 8;
     p->iterate_basis = 0;
+    p->temporal_form = 2;
 }
 
 const char* sth_last_error(void) { return g_err.c_str(); }
@@ -553,7 +571,10 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     const size_t vecs0 = q.basis == 1 ? 5 : 2;               // buf0, buf1 (+ f^, u^ pair)
     const size_t vecsl = q.basis == 1 ? 3 : 2;               // u, f (+ u^ partner) per coarse level
     total += vecs0 * sizeof(double) * (size_t)q.n_slabs * slab;
-    if (q.basis == 1) total += 2 * sizeof(double) * np * np;  // C, C^T
+    if (q.basis == 1) {
+        total += 2 * sizeof(double) * np * np;                // C, C^T
+        total += sizeof(double) * (((size_t)(q.n_slabs / 2) * (size_t)(Nx) + 255) / 256 + 1);   // cycle-end partials
+    }
     long S = q.n_slabs;
     size_t L = level_count(q);
     for (size_t l = 1; l < L; ++l) {
@@ -619,7 +640,10 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
             tm.re[i] = lv.re[i];
             tm.im[i] = lv.im[i];
             tm.kind[i] = lv.kind[i];
+            if (lv.schur)
+                for (int j = 0; j < h->Nt; ++j) tm.R[i * kNt + j] = lv.R(i, j);
         }
+        tm.schur = lv.schur ? 1 : 0;
         h->ops.push_back(op);
         h->mixes.push_back(tm);
     }
@@ -686,7 +710,9 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 Cf[(size_t)i * np + j] = c;
                 Ci[(size_t)j * np + i] = c;
             }
-        if (!dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
+        h->n_cpartial = ((q.n_slabs / 2) * h->Nx + 255) / 256;
+        if (!dalloc(&h->cpartial, (size_t)h->n_cpartial) ||
+            !dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
             !dalloc(&h->e0, (size_t)q.n_slabs * slab) || !dalloc(&h->e1, (size_t)q.n_slabs * slab) ||
             !dalloc(&h->e2, (size_t)q.n_slabs * slab))
             return cleanup(STH_ENOMEM, "device allocation failed");
@@ -1028,7 +1054,7 @@ int sth_destroy(sth_handle* h) {
     // graph first: its nodes reference the buffers below
     drop_graph(h);
     double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt,
-                      h->Cf, h->Ci, h->e0, h->e1, h->e2};
+                      h->Cf, h->Ci, h->e0, h->e1, h->e2, h->cpartial};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto* vec : {&h->lu, &h->lf, &h->lu2})
@@ -1114,6 +1140,8 @@ int sth_host_factors(const sth_problem* p, int level, sth_factors* out) {
     cp(out->W, L.W.a);
     cp(out->eig_re, L.re);
     cp(out->eig_im, L.im);
+    out->schur = L.schur ? 1 : 0;
+    if (L.schur) cp(out->R, L.R.a);
     return STH_OK;
 }
 

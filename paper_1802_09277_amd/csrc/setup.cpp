@@ -385,6 +385,113 @@ bool nonsym_eigen(const Mat& A, std::vector<cd>& lam, std::vector<std::vector<cd
     return true;
 }
 
+// Householder reflector P = I - 2 v v^T (|v| = 1) with P x = -+|x| e_1; false
+// when x is zero
+static bool householder(const double* x, int m, double* v) {
+    double nx = 0.0;
+    for (int i = 0; i < m; ++i) nx += x[i] * x[i];
+    nx = std::sqrt(nx);
+    if (nx == 0.0) return false;
+    for (int i = 0; i < m; ++i) v[i] = x[i];
+    v[0] += (x[0] >= 0 ? nx : -nx);
+    double nv = 0.0;
+    for (int i = 0; i < m; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    for (int i = 0; i < m; ++i) v[i] /= nv;
+    return true;
+}
+
+// T <- P T on rows r0..r0+m-1, columns c0..c1; T <- T P on columns r0..,
+// rows q0..q1; Q <- Q P
+static void reflect(Mat& T, Mat& Q, const double* v, int m, int r0, int c0, int c1, int q0, int q1) {
+    for (int j = c0; j <= c1; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += v[i] * T(r0 + i, j);
+        for (int i = 0; i < m; ++i) T(r0 + i, j) -= 2.0 * v[i] * s;
+    }
+    for (int i = q0; i <= q1; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += T(i, r0 + j) * v[j];
+        for (int j = 0; j < m; ++j) T(i, r0 + j) -= 2.0 * s * v[j];
+    }
+    for (int i = 0; i < Q.r; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s += Q(i, r0 + j) * v[j];
+        for (int j = 0; j < m; ++j) Q(i, r0 + j) -= 2.0 * s * v[j];
+    }
+}
+
+bool real_schur(const Mat& A, Mat& T, Mat& Q) {
+    const int n = A.r;
+    T = A;
+    Q = Mat(n, n);
+    for (int i = 0; i < n; ++i) Q(i, i) = 1.0;
+    double v[3], x[16];
+    // Hessenberg form by Householder reflections
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        for (int i = 0; i < m; ++i) x[i] = T(k + 1 + i, k);
+        double vv[16];
+        if (!householder(x, m, vv)) continue;
+        reflect(T, Q, vv, m, k + 1, 0, n - 1, 0, n - 1);
+        for (int i = k + 2; i < n; ++i) T(i, k) = 0.0;
+    }
+    double anorm = 0.0;
+    for (double a : T.a) anorm = std::max(anorm, std::fabs(a));
+    if (anorm == 0.0) return true;
+    const double eps = 1e-15;
+    int hi = n - 1, iter = 0;
+    while (hi > 0) {
+        // deflation: the active block is l..hi
+        int l = hi;
+        for (; l > 0; --l) {
+            double s = std::fabs(T(l - 1, l - 1)) + std::fabs(T(l, l));
+            if (s == 0.0) s = anorm;
+            if (std::fabs(T(l, l - 1)) <= eps * s) {
+                T(l, l - 1) = 0.0;
+                break;
+            }
+        }
+        if (l == hi) { hi -= 1; iter = 0; continue; }          // 1x1 block
+        if (l == hi - 1) { hi -= 2; iter = 0; continue; }      // 2x2 block
+        if (++iter > 60 * n) return false;
+        // Francis double shift: the eigenvalues of the trailing 2x2 block
+        // (an ad hoc shift every tenth sweep breaks cycles)
+        double s, t;
+        if (iter % 10 == 0) {
+            double w = std::fabs(T(hi, hi - 1)) + std::fabs(T(hi - 1, hi - 2));
+            s = 1.5 * w;
+            t = w * w;
+        } else {
+            s = T(hi - 1, hi - 1) + T(hi, hi);
+            t = T(hi - 1, hi - 1) * T(hi, hi) - T(hi - 1, hi) * T(hi, hi - 1);
+        }
+        // first column of (T - a)(T - b) restricted to the active block
+        double x0 = T(l, l) * T(l, l) + T(l, l + 1) * T(l + 1, l) - s * T(l, l) + t;
+        double y0 = T(l + 1, l) * (T(l, l) + T(l + 1, l + 1) - s);
+        double z0 = T(l + 1, l) * T(l + 2, l + 1);
+        for (int k = l; k <= hi - 2; ++k) {
+            const double xs[3] = {x0, y0, z0};
+            if (householder(xs, 3, v)) {
+                const int c0 = std::max(l, k - 1);
+                reflect(T, Q, v, 3, k, c0, n - 1, 0, std::min(k + 3, hi));
+                if (k > l) T(k + 1, k - 1) = T(k + 2, k - 1) = 0.0;
+            }
+            x0 = T(k + 1, k);
+            y0 = T(k + 2, k);
+            if (k < hi - 2) z0 = T(k + 3, k);
+        }
+        const double xs[2] = {x0, y0};
+        if (householder(xs, 2, v)) {
+            reflect(T, Q, v, 2, hi - 1, hi - 2, n - 1, 0, hi);
+            T(hi, hi - 2) = 0.0;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j + 1 < i; ++j) T(i, j) = 0.0;
+    return true;
+}
+
 double cond2(const Mat& A) {
     int n = A.c;
     Mat G(n, n);
@@ -580,6 +687,7 @@ std::string validate(const Problem& p) {
     if (p.nu_pre < 0 || p.nu_post < 0 || p.nu_pre + p.nu_post < 1) os << "nu_pre, nu_post >= 0 with a positive sum; ";
     if (p.prec < 0 || p.prec > 2) os << "transform_prec must be 0, 1 or 2; ";
     if (p.coarse_slabs < 1) os << "coarse_slabs must be >= 1; ";
+    if (p.temporal < 0 || p.temporal > 2) os << "temporal_form must be 0, 1 or 2; ";
     if (os.str().empty() && p.n_elem + p.degree - 2 >= 1) {
         double len = double(p.n_slabs) * (p.n_elem_t + p.degree);
         for (int a = 0; a < p.dim; ++a) len *= (p.n_elem + p.degree - 2);
@@ -588,7 +696,9 @@ std::string validate(const Problem& p) {
     return os.str();
 }
 
-static int temporal_decomposition(TemporalLevel& L, std::string& err) {
+// Eigen form K_t V = M_t V Z (Section 3.3, real 2x2 blocks for conjugate
+// pairs), W = (M_t V)^{-1}; the Re(lambda) > 0 guard of Section 3.2.
+static int eigen_form(TemporalLevel& L, std::string& err) {
     int Nt = L.Kt.r;
     // M_t positivity: every eigenvalue of M_t must have positive real part
     // (the '*' entries of Table 2 violate this).
@@ -680,12 +790,6 @@ static int temporal_decomposition(TemporalLevel& L, std::string& err) {
     }
     if (col != Nt) { err = "temporal eigen decomposition incomplete"; return -5; }
     L.condV = cond2(L.V);
-    if (!(L.condV <= 1e8)) {
-        std::ostringstream os;
-        os << "cond(V) = " << L.condV << " too large for the diagonalisation path";
-        err = os.str();
-        return -5;
-    }
     Mat MV(Nt, Nt);
     for (int i = 0; i < Nt; ++i)
         for (int j = 0; j < Nt; ++j) {
@@ -694,6 +798,87 @@ static int temporal_decomposition(TemporalLevel& L, std::string& err) {
             MV(i, j) = s;
         }
     if (!lu_inverse(MV, L.W)) { err = "M_t V singular"; return -5; }
+    return 0;
+}
+
+// Real Schur form of M_t^{-1} K_t = Q R Q^T (Q orthogonal, R quasi upper
+// triangular), so that A_mu = K_t + mu M_t = M_t Q (R + mu I) Q^T and
+// A_mu^{-1} = Q (R + mu I)^{-1} Q^T M_t^{-1}: V = Q, W = Q^T M_t^{-1} and a
+// block back substitution per spatial mode instead of the diagonal divide.
+// Orthogonal temporal transforms whatever cond(V) (the Schur alternative of
+// Section 3.3).
+static int schur_form(TemporalLevel& L, std::string& err) {
+    const int Nt = L.Kt.r;
+    Mat Minv;
+    if (!lu_inverse(L.Mt, Minv)) { err = "M_t singular"; return -4; }
+    Mat C(Nt, Nt);
+    for (int i = 0; i < Nt; ++i)
+        for (int j = 0; j < Nt; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < Nt; ++k) v += Minv(i, k) * L.Kt(k, j);
+            C(i, j) = v;
+        }
+    Mat T, Q;
+    if (!real_schur(C, T, Q)) { err = "real Schur form did not converge"; return -5; }
+    L.schur = true;
+    L.R = T;
+    L.V = Q;
+    L.W = Mat(Nt, Nt);
+    for (int i = 0; i < Nt; ++i)
+        for (int j = 0; j < Nt; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < Nt; ++k) v += Q(k, i) * Minv(k, j);
+            L.W(i, j) = v;
+        }
+    L.kind.assign(Nt, 0);
+    L.re.assign(Nt, 0.0);
+    L.im.assign(Nt, 0.0);
+    for (int k = 0; k < Nt;) {
+        if (k + 1 < Nt && T(k + 1, k) != 0.0) {
+            // eigenvalues of the 2x2 block
+            const double a = T(k, k), b = T(k, k + 1), c = T(k + 1, k), d = T(k + 1, k + 1);
+            const double tr = 0.5 * (a + d), det = a * d - b * c, disc = tr * tr - det;
+            if (disc < 0) {
+                L.re[k] = L.re[k + 1] = tr;
+                L.im[k] = std::sqrt(-disc);
+                L.im[k + 1] = -L.im[k];
+            } else {
+                L.re[k] = tr + std::sqrt(disc);
+                L.re[k + 1] = tr - std::sqrt(disc);
+            }
+            L.kind[k] = 1;
+            L.kind[k + 1] = 2;
+            k += 2;
+        } else {
+            L.re[k] = T(k, k);
+            k += 1;
+        }
+    }
+    for (int k = 0; k < Nt; ++k)
+        if (L.re[k] <= 0) { err = "temporal eigenvalue with Re <= 0, reduce theta"; return -4; }
+    return 0;
+}
+
+// temporal: 0 diagonalisation (STH_ECOND above cond(V) = 1e8), 1 real
+// Schur, 2 diagonalisation unless cond(V) > 1e6, then real Schur
+static int temporal_decomposition(TemporalLevel& L, int temporal, std::string& err) {
+    int st = eigen_form(L, err);
+    if (st == -4) return st;                       // positivity guard, whatever the form
+    const bool use_schur = temporal == 1 || (temporal == 2 && (st != 0 || !(L.condV <= 1e6)));
+    if (use_schur) {
+        const double condV = st == 0 ? L.condV : INFINITY;
+        err.clear();
+        st = schur_form(L, err);
+        L.condV = condV;
+        return st;
+    }
+    if (st) return st;
+    if (!(L.condV <= 1e8)) {
+        std::ostringstream os;
+        os << "cond(V) = " << L.condV << " too large for the diagonalisation path";
+        err = os.str();
+        return -5;
+    }
     return 0;
 }
 
@@ -760,7 +945,7 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
         L.S = S;
         L.tau = tau;
         time_matrices(tau, p.n_elem_t, p.degree, p.sigma(), L.Kt, L.Mt);
-        int st = temporal_decomposition(L, err);
+        int st = temporal_decomposition(L, p.temporal, err);
         if (st != 0) {
             std::ostringstream os;
             os << "level " << s.levels.size() << ": " << err;

@@ -41,6 +41,9 @@ void sym_eigen(const Mat& A, std::vector<double>& evals, Mat& evecs);   // A sym
 bool nonsym_eigen(const Mat& A, std::vector<std::complex<double>>& lam,
                   std::vector<std::vector<std::complex<double>>>& vecs);
 double cond2(const Mat& A);                                   // sigma_max / sigma_min
+// Real Schur form A = Q T Q^T of a small matrix: Q orthogonal, T upper
+// quasi-triangular (1x1 and 2x2 diagonal blocks).  false if QR stalls.
+bool real_schur(const Mat& A, Mat& T, Mat& Q);
 
 // ---- problem quantities ------------------------------------------------------
 struct Problem {
@@ -49,6 +52,7 @@ struct Problem {
     int nu_pre, nu_post, prec;
     int coarse_slabs;
     int basis;
+    int temporal = 2;      // 0 diagonalisation, 1 real Schur, 2 automatic
     int n() const { return n_elem + degree - 2; }
     int Nt() const { return n_elem_t + degree; }
     double tau() const { return T / n_slabs; }
@@ -60,10 +64,12 @@ struct TemporalLevel {
     double tau = 0;        // slab length
     Mat Kt, Mt;            // eq. TimeMatrices with the finest sigma
     Mat Pt;                // 2Nt x Nt prolongation to the next coarser level
-    Mat V, W;              // real block eigenvectors, W = (Mt V)^{-1}
+    Mat V, W;              // real block eigenvectors, W = (Mt V)^{-1}; Schur: V = Q, W = Q^T Mt^{-1}
     std::vector<double> re, im;   // eigen pairs (im = +b,-b on a pair)
-    std::vector<int> kind;        // 0 real, 1 first of a pair, 2 second
-    double condV = 0;
+    std::vector<int> kind;        // 0 real / 1x1 block, 1 first of a pair / 2x2 block, 2 second
+    double condV = 0;             // of the eigenvector matrix (also computed for the Schur form)
+    bool schur = false;           // W K_t V = R quasi-triangular (else block diagonal)
+    Mat R;                        // Schur form: R = Q^T Mt^{-1} Kt Q
 };
 
 struct Setup {

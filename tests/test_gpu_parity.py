@@ -260,3 +260,41 @@ def test_eigenbasis_solve_matches_direct(name):
     print(f"  eigenbasis: {it} cycles (oracle {it_o}), relres {rr:.2e}")
     assert rr <= 1e-12 and abs(it - it_o) <= 1
     assert np.linalg.norm(host(u) - ud) <= 1e-10 * np.linalg.norm(ud)
+
+
+# ---------------------------------------------------------------------------
+# Real Schur form of the temporal pencil (orthogonal temporal transforms and a
+# block back substitution per spatial mode, the Schur alternative of Section
+# 3.3): the same slab inverse and the same solution as the oracle.
+# ---------------------------------------------------------------------------
+@functools.lru_cache(maxsize=None)
+def schur_solver_for(name, basis):
+    import paper_1802_09277_amd as sth
+    return sth.Solver(**SHAPES[name], temporal="schur", basis=basis)
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+def test_schur_block_solve(name):
+    banner(name, "schur block_solve")
+    prob, mg = oracle_for(name)
+    s = schur_solver_for(name, "nodal")
+    r = W.random_vector(41, prob.n_dof)
+    z = s.new_vector()
+    s.block_solve(dev(r), z)
+    assert rel_max(host(z), mg.levels[0].slab_solve(r)) <= 1e-10
+
+
+@pytest.mark.parametrize("name", list(SHAPES))
+@pytest.mark.parametrize("basis", ["nodal", "eigen"])
+def test_schur_solve_matches_direct(name, basis):
+    banner(name, f"schur solve ({basis})")
+    prob, mg = oracle_for(name)
+    s = schur_solver_for(name, basis)
+    f = assemble_rhs(prob, W.random_modes(7, prob.dim))
+    ud = mg.levels[0].forward_substitution(f)
+    u = s.new_vector()
+    it, rr, _ = s.solve(dev(f), u, rtol=1e-12, maxit=60)
+    _, it_o, _ = mg.solve(f, rtol=1e-12, maxit=60)
+    print(f"  schur/{basis}: {it} cycles (oracle {it_o}), relres {rr:.2e}")
+    assert rr <= 1e-12 and abs(it - it_o) <= 1
+    assert np.linalg.norm(host(u) - ud) <= 1e-10 * np.linalg.norm(ud)

@@ -86,6 +86,40 @@ def test_residual_norm_bound_of_the_eigenbasis(shape):
         assert np.linalg.norm(C @ R @ C.T) >= lam * np.linalg.norm(R) * (1 - 1e-12)
 
 
+SCHUR_SHAPES = [dict(dim=2, n_elem=4, degree=p, n_slabs=4, n_elem_t=net, theta=theta)
+                for p in (1, 2, 3, 4) for net in (1, 2, 8 - p) for theta in (0.0, 0.01, 0.5)
+                if p + net <= 8]
+
+
+@pytest.mark.parametrize("shape", SCHUR_SHAPES)
+def test_real_schur_form_of_the_temporal_pencil(shape):
+    # Schur alternative to the diagonalisation (Section 3.3): M_t^{-1} K_t =
+    # Q R Q^T with Q orthogonal and R quasi upper triangular, W = Q^T M_t^{-1};
+    # then A_mu^{-1} = Q (R + mu I)^{-1} W for every spatial shift mu
+    F = sth.host_factors(level=0, temporal="schur", coarse_slabs=4, **shape)
+    assert F["schur"]
+    Q, W, R, Kt, Mt = F["V"], F["W"], F["R"], F["Kt"], F["Mt"]
+    I = np.eye(len(R))
+    assert np.allclose(Q.T @ Q, I, atol=1e-13)
+    assert np.allclose(W @ Mt @ Q, I, atol=1e-11)
+    assert np.abs(W @ Kt @ Q - R).max() <= 1e-11 * np.abs(R).max()
+    assert np.all(np.tril(R, -2) == 0)
+    sub = np.diag(R, -1)
+    assert not np.any((sub[:-1] != 0) & (sub[1:] != 0))        # blocks of size 1 or 2
+    lam = sl.eigvals(Kt, Mt)
+    lam_h = F["eig_re"] + 1j * F["eig_im"]
+    key = lambda z: (round(z.real, 6), round(abs(z.imag), 6))
+    assert np.allclose(sorted(lam, key=key), sorted(lam_h, key=key), rtol=1e-9)
+    for mu in (0.0, 1.0, 1e3):
+        Ainv = Q @ np.linalg.solve(R + mu * I, W)
+        assert np.abs(Ainv @ (Kt + mu * Mt) - I).max() <= 1e-10
+
+
+def test_automatic_temporal_form_keeps_diagonalisation_when_well_conditioned():
+    F = sth.host_factors(level=0, dim=2, n_elem=4, degree=3, n_slabs=4, n_elem_t=2)
+    assert not F["schur"] and F["cond_V"] < 1e3
+
+
 def test_level_count():
     kw = dict(level=0, dim=2, n_elem=4, degree=2, n_elem_t=2)
     assert sth.host_factors(n_slabs=16, coarse_slabs=1, **kw)["n_levels"] == 5
