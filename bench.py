@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--basis", default="eigen", choices=["nodal", "eigen"],
                     help="iterate on B-spline coefficients or in the spatial eigenbasis (same iterates)")
     ap.add_argument("--coarse-slabs", type=int, default=None,
-                    help="coarsest multigrid level: at most this many slabs (library default 8)")
+                    help="coarsest multigrid level: at most this many slabs (library default 64)")
     ap.add_argument("--cpu-sample-slabs", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB three times first (the reference "

@@ -113,8 +113,10 @@ typedef struct {
 } sth_rhs_modes;
 
 /* Fills p with the defaults of Section 4.4: theta 0.01, omega 1/2, T 1,
- * V(1,1), FP64 transforms, coarse_slabs 8 and the automatic temporal form
- * (the shape fields are left at zero). */
+ * V(1,1), FP64 transforms, the automatic temporal form and coarse_slabs 64:
+ * the exact coarsest-level solve runs parallel in time, so a level of up to
+ * about 256 compute units / N_t slabs is cheaper to solve exactly than to
+ * coarsen further (the shape fields are left at zero). */
 void sth_problem_default(sth_problem* p);
 
 /* Device bytes that sth_setup would allocate for this problem (factors,
@@ -164,6 +166,18 @@ int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream);
  * cycles or when maxit is reached. */
 int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
               int* iters, double* relres, void* stream);
+
+/* The same system solved by flexible GMRES(restart), right-preconditioned
+ * by one V-cycle from a zero initial guess in the handle's iteration basis
+ * (the multigrid used as a preconditioner instead of as the solver, as the
+ * paper's introduction and Section 3.1 allow).  u holds the initial guess;
+ * stops when the true ||f - L_h u||_2 <= rtol ||f||_2 (checked at every
+ * restart and at convergence of the Arnoldi estimate) or after maxit
+ * preconditioned iterations.  restart in 1..31.  The first call allocates
+ * (2 restart + 1) level-0 vectors of workspace, kept by the handle.
+ * Blocks the host (a few scalars per iteration); STH_ENOCONV as sth_solve. */
+int sth_solve_fgmres(sth_handle* h, const double* f, double* u, double rtol, int maxit, int restart,
+                     int* iters, double* relres, void* stream);
 
 /* Graph replay of the solve iterations (default on): on a non-default
  * stream sth_solve captures one iteration (V-cycle, residual, norm, scalar

@@ -87,6 +87,7 @@ def load_library():
         "sth_smooth": (i, [vp, vp, vp, i, vp]),
         "sth_vcycle": (i, [vp, vp, vp, vp]),
         "sth_solve": (i, [vp, vp, vp, d, i, P(i), P(d), vp]),
+        "sth_solve_fgmres": (i, [vp, vp, vp, d, i, i, P(i), P(d), vp]),
         "sth_restrict": (i, [vp, i, vp, vp, vp]),
         "sth_prolong_add": (i, [vp, i, vp, vp, vp]),
         "sth_norm": (i, [vp, vp, P(d), vp]),
@@ -273,6 +274,16 @@ class Solver:
         rr = ctypes.c_double()
         code = self.lib.sth_solve(self.h, _ptr(f), _ptr(u), float(rtol), int(maxit), ctypes.byref(it),
                                   ctypes.byref(rr), _stream(stream))
+        if check:
+            _check(code)
+        return it.value, rr.value, code
+
+    def solve_fgmres(self, f, u, rtol=1e-8, maxit=100, restart=20, stream=None, check=True):
+        """Flexible GMRES(restart) preconditioned by one V-cycle; returns (iterations, relres, code)."""
+        it = ctypes.c_int()
+        rr = ctypes.c_double()
+        code = self.lib.sth_solve_fgmres(self.h, _ptr(f), _ptr(u), float(rtol), int(maxit), int(restart),
+                                         ctypes.byref(it), ctypes.byref(rr), _stream(stream))
         if check:
             _check(code)
         return it.value, rr.value, code

@@ -388,9 +388,7 @@ hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, con
 // Both spatial axes of a 2-D image in one kernel: U (padded to NP x NP) and
 // one image stay in LDS; every block walks over images.  DIR 0 (forward):
 // out = U^T R U.  DIR 1 (inverse): Z = U Y U^T, then the epilogue EPI
-// (0 store, 1 out += alpha Z, 2 out = alpha Z, 3 nothing stored: the block's
-// sum of the squares of Z over its images goes to out[blockIdx.x], in a
-// fixed order).  Eight waves share the
+// (0 store, 1 out += alpha Z, 2 out = alpha Z).  Eight waves share the
 // NT16 x NT16 output tiles of each GEMM; the intermediate product goes back
 // into the image buffer.  CT is the compute type: double (MFMA f64 16x16x4)
 // or float (MFMA f32 16x16x4, FP32 accumulation); global data stay FP64.
@@ -457,7 +455,6 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         }
     };
     if (blockIdx.x < nimg) load_img(blockIdx.x);
-    double ssq = 0.0;                          // EPI 3
     for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
         __syncthreads();
 #pragma unroll
@@ -511,7 +508,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
                 }
             }
         }
-        double* dst = (EPI == 3) ? out : out + img * nn;
+        double* dst = out + img * nn;
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tq = wave + 8 * q;
@@ -523,10 +520,6 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
                     const int i = ti * 16 + M::row(lk, rr);
                     if (i < n && j < n) {
                         double v = (double)acc[q][rr];
-                        if (EPI == 3) {
-                            ssq += v * v;
-                            continue;
-                        }
                         double* o = dst + (long)i * n + j;
                         if (EPI == 0) *o = v;
                         else if (EPI == 1) *o += alpha * v;
@@ -534,20 +527,6 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
                     }
                 }
             }
-        }
-    }
-    if (EPI == 3) {
-        // wave sums by butterfly shuffles, then the eight wave sums in order
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
-        __syncthreads();                        // LDS free: reuse it for the wave sums
-        double* red = sm_raw;
-        if (lane == 0) red[wave] = ssq;
-        __syncthreads();
-        if (tid == 0) {
-            double t = 0.0;
-            for (int w = 0; w < 8; ++w) t += red[w];
-            out[blockIdx.x] = t;
         }
     }
 }
@@ -1048,6 +1027,79 @@ static hipError_t xform2d_bf16_np(const double* in, double* out, const double* M
 
 bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 16 == 0; }
 
+// Sum over nimg n x n images Y of ||C Y C^T||_F^2, written as <Y G, G Y>_F with
+// G = C^T C (symmetric, padded to NP): both MFMA products read the staged
+// image, there is no intermediate product to store, and one barrier pair per
+// image suffices.  Per-block partial sums in a fixed order.
+template <int NT16>
+__global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ in, const double* __restrict__ Gpad,
+                                                     int n, long nimg, double* __restrict__ partial) {
+    constexpr int NP = NT16 * 16, LD = NP + 1;
+    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
+    extern __shared__ double sm_raw[];
+    double* Gs = sm_raw;
+    double* Ys = sm_raw + NP * LD;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int kp = (n + 3) & ~3;
+    for (int i = tid; i < NP * NP; i += 512) Gs[(i / NP) * LD + i % NP] = Gpad[i];
+    const long nn = (long)n * n;
+    constexpr int PER = (NP * NP + 511) / 512;
+    double pre[PER];
+    auto load_img = [&](long img) {
+        const double* src = in + img * nn;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + 512 * k, r = i / NP, c = i % NP;
+            pre[k] = (i < NP * NP && r < n && c < n) ? src[(long)r * n + c] : 0.0;
+        }
+    };
+    if (blockIdx.x < nimg) load_img(blockIdx.x);
+    double ssq = 0.0;
+    for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + 512 * k;
+            if (i < NP * NP) Ys[(i / NP) * LD + i % NP] = pre[k];
+        }
+        if (img + gridDim.x < nimg) load_img(img + gridDim.x);
+        __syncthreads();
+        d4 a1[TPW], a2[TPW];
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) a1[q] = a2[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < kp; k0 += 4) {
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                const int tq = wave + 8 * q;
+                if (tq < NTILE) {
+                    const int ti = tq / NT16, tj = tq % NT16;
+                    a1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ys[(ti * 16 + lr) * LD + k0 + lk],
+                                                                 Gs[(k0 + lk) * LD + tj * 16 + lr], a1[q], 0, 0, 0);
+                    a2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Gs[(ti * 16 + lr) * LD + k0 + lk],
+                                                                 Ys[(k0 + lk) * LD + tj * 16 + lr], a2[q], 0, 0, 0);
+                }
+            }
+        }
+        // padded rows and columns of both products are zero
+#pragma unroll
+        for (int q = 0; q < TPW; ++q)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) ssq += a1[q][rr] * a2[q][rr];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
+    __syncthreads();
+    double* red = sm_raw;
+    if (lane == 0) red[wave] = ssq;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 8; ++w) t += red[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
 // one block: out[0] = sum of the per-block partial sums (fixed order)
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out) {
     __shared__ double sh[256];
@@ -1062,15 +1114,37 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     if (threadIdx.x == 0) out[0] = sh[0];
 }
 
-hipError_t launch_xform2d_norm(const double* in, const double* Cpad, int n, int np, long nimg, double* partial,
-                               int max_blocks, double* out, hipStream_t st) {
-    if (nimg <= 0 || !xform2d_supported(np)) return hipErrorInvalidValue;
-    if (persistent_blocks(sizeof(double) * 2 * (size_t)np * (np + 1), nimg) > max_blocks) return hipErrorInvalidValue;
-    long blocks = 0;
-    hipError_t e = xform2d_np<double, 1, 3>(in, partial, Cpad, n, np, nimg, 0.0, st, &blocks);
-    if (e != hipSuccess) return e;
+template <int NT16>
+static hipError_t gram_norm2d_launch(const double* in, const double* Gpad, int n, long nimg, double* partial,
+                                     int max_blocks, double* out, hipStream_t st) {
+    constexpr int NP = NT16 * 16;
+    const size_t shm = sizeof(double) * 2 * (size_t)NP * (NP + 1);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_gram_norm2d<NT16>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const long blocks = persistent_blocks(shm, nimg);
+    if (blocks > max_blocks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gram_norm2d<NT16>, dim3((unsigned)blocks), dim3(512), shm, st, in, Gpad, n, nimg, partial);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
     return hipGetLastError();
+}
+
+hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
+                              int max_blocks, double* out, hipStream_t st) {
+    if (nimg <= 0 || !xform2d_supported(np)) return hipErrorInvalidValue;
+    switch (np / 16) {
+        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
@@ -1438,41 +1512,59 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
             prev_old = u[NT - 1];
             prev_new = u[NT - 1] + omega * z[NT - 1];
         }
-#pragma unroll 1
-        for (int k = 0; k < chain; k += 2) {
-            double acc[NT];
+        // the next slab's f^ and u^ are loaded while the current one is
+        // processed (software pipelining along the chain)
+        double fnx[NT], unx[NT], acc[NT];
+        {
+            const long b = s0 * NT * Nx + m;
 #pragma unroll
-            for (int c = 0; c < NT; ++c) acc[c] = 0.0;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const long b = (s0 + k + h) * NT * Nx + m;
-                double g[NT], g2[NT], u[NT], z[NT], up[NT];
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    g[t] = fh[b + (long)t * Nx];
-                    u[t] = uin[b + (long)t * Nx];
-                    g2[t] = g[t];
-                }
-                eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) ssq += g[t] * g[t];
-                shifted_solve<NT, SCHUR>(tm, mu, g, z);
-#pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    up[t] = u[t] + omega * z[t];
-                    uout[b + (long)t * Nx] = up[t];
-                }
-                eig_residual_point<NT>(ktmt, mu, up, prev_new, g2);
-#pragma unroll
-                for (int t = 0; t < NT; ++t)
-#pragma unroll
-                    for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g2[t];
-                prev_old = u[NT - 1];
-                prev_new = up[NT - 1];
+            for (int t = 0; t < NT; ++t) {
+                fnx[t] = fh[b + (long)t * Nx];
+                unx[t] = uin[b + (long)t * Nx];
             }
-            const long mc = (s0 + k) / 2;
+        }
+#pragma unroll 1
+        for (int k = 0; k < chain; ++k) {
+            const int h = k & 1;
+            const long b = (s0 + k) * NT * Nx + m;
+            double g[NT], g2[NT], u[NT], z[NT], up[NT];
 #pragma unroll
-            for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+            for (int t = 0; t < NT; ++t) {
+                g[t] = g2[t] = fnx[t];
+                u[t] = unx[t];
+            }
+            if (k + 1 < chain) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    fnx[t] = fh[b + NT * Nx + (long)t * Nx];
+                    unx[t] = uin[b + NT * Nx + (long)t * Nx];
+                }
+            }
+            eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ssq += g[t] * g[t];
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                up[t] = u[t] + omega * z[t];
+                uout[b + (long)t * Nx] = up[t];
+            }
+            eig_residual_point<NT>(ktmt, mu, up, prev_new, g2);
+            if (h == 0) {
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g2[t];
+            if (h == 1) {
+                const long mc = (s0 + k) / 2;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+            }
+            prev_old = u[NT - 1];
+            prev_new = up[NT - 1];
         }
     }
     // block sum: butterfly within each wave, then the four wave sums in order
@@ -1737,6 +1829,82 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
         default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
+    return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// Krylov support (FGMRES outer loop): k <= kMaxKrylov vectors stored one
+// after the other with stride ld.
+// ---------------------------------------------------------------------------
+// partial[b * kMaxKrylov + i] = block b's share of <V_i, w>, i < k; the
+// elements of a block and the lanes of the reduction are visited in a fixed
+// order, so the result does not depend on timing
+__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, long ld, int k,
+                                                  const double* __restrict__ w, long len,
+                                                  double* __restrict__ partial) {
+    double acc[kMaxKrylov];
+#pragma unroll
+    for (int i = 0; i < kMaxKrylov; ++i) acc[i] = 0.0;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < len; e += (long)gridDim.x * 256) {
+        const double we = w[e];
+#pragma unroll
+        for (int i = 0; i < kMaxKrylov; ++i)
+            if (i < k) acc[i] += V[i * ld + e] * we;
+    }
+    __shared__ double red[4][kMaxKrylov];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < kMaxKrylov; ++i) {
+        if (i >= k) break;
+        double v = acc[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) red[wave][i] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k)
+        partial[(long)blockIdx.x * kMaxKrylov + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ __launch_bounds__(64) void k_multidot_final(const double* __restrict__ partial, int blocks, int k,
+                                                       double* __restrict__ out) {
+    const int i = threadIdx.x;
+    if (i >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += partial[(long)b * kMaxKrylov + i];
+    out[i] = s;
+}
+
+// w[e] = alpha w[e] + sum_{i<k} c[i] V_i[e]  (c on the device)
+__global__ __launch_bounds__(256) void k_multiaxpy(const double* __restrict__ V, long ld, int k,
+                                                   const double* __restrict__ c, double alpha,
+                                                   double* __restrict__ w, long len) {
+    __shared__ double cs[kMaxKrylov];
+    if ((int)threadIdx.x < k) cs[threadIdx.x] = c[threadIdx.x];
+    __syncthreads();
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < len; e += (long)gridDim.x * 256) {
+        double v = alpha * w[e];
+        for (int i = 0; i < k; ++i) v += cs[i] * V[i * ld + e];
+        w[e] = v;
+    }
+}
+
+static const int kKrylovBlocks = 1024;
+
+hipError_t launch_multidot(const double* V, long ld, int k, const double* w, long len, double* partial, double* out,
+                           hipStream_t st) {
+    if (k < 1 || k > kMaxKrylov || len <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_multidot, dim3(kKrylovBlocks), dim3(256), 0, st, V, ld, k, w, len, partial);
+    hipLaunchKernelGGL(k_multidot_final, dim3(1), dim3(64), 0, st, partial, kKrylovBlocks, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_multiaxpy(const double* V, long ld, int k, const double* c, double alpha, double* w, long len,
+                            hipStream_t st) {
+    if (k < 0 || k > kMaxKrylov || len <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_multiaxpy, dim3(kKrylovBlocks), dim3(256), 0, st, V, ld, k, c, alpha, w, len);
     return hipGetLastError();
 }
 

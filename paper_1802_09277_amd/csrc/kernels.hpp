@@ -91,11 +91,12 @@ hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const 
                                      int n, const double* fh, const double* uh, double* fc, long Sc,
                                      hipStream_t st);
 
-//  out[0] = sum over the nimg n x n images of ||C Y C^T||_F^2 (2-D, np <= 96;
-//  C padded to np x np): the squared B-spline norm of an eigenbasis vector
-//  without storing the mapped vector; partial needs max_blocks entries
-hipError_t launch_xform2d_norm(const double* in, const double* Cpad, int n, int np, long nimg, double* partial,
-                               int max_blocks, double* out, hipStream_t st);
+//  out[0] = sum over the nimg n x n images Y of ||C Y C^T||_F^2 (2-D, np <= 96),
+//  the squared B-spline norm of an eigenbasis vector without forming it,
+//  computed as <Y G, G Y>_F with Gpad = C^T C (np x np, zero padded); partial
+//  needs max_blocks entries
+hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
+                              int max_blocks, double* out, hipStream_t st);
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,
@@ -105,6 +106,15 @@ hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u
                           long Nx, hipStream_t st);
 
 hipError_t launch_fill(double* v, long len, double val, hipStream_t st);
+
+// Krylov vectors V_i = V + i*ld (i < k <= kMaxKrylov), for the FGMRES loop:
+//  out[i] = <V_i, w> (deterministic; partial needs 1024 * kMaxKrylov entries)
+//  w = alpha w + sum_i c[i] V_i (c: k device values)
+constexpr int kMaxKrylov = 32;
+hipError_t launch_multidot(const double* V, long ld, int k, const double* w, long len, double* partial, double* out,
+                           hipStream_t st);
+hipError_t launch_multiaxpy(const double* V, long ld, int k, const double* c, double alpha, double* w, long len,
+                            hipStream_t st);
 
 // Two-stage deterministic sum of squares: partial sums over a fixed number
 // of blocks, then one block; result in out[0].

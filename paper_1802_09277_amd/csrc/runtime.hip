@@ -62,6 +62,7 @@ struct sth_handle {
     int basis = 0;
     double* Cf = nullptr;               // np x np, C = M_1 U padded (C = U^{-T})
     double* Ci = nullptr;               // np x np, C^T padded
+    double* Gf = nullptr;               // np x np, G = C^T C padded (2-D, np <= 96)
     double* e0 = nullptr;               // f^ on level 0
     double* e1 = nullptr;               // u^ on level 0 (ping-pong with e2)
     double* e2 = nullptr;
@@ -71,6 +72,13 @@ struct sth_handle {
                                         // and lf[1] the restriction of its residual
     double* cpartial = nullptr;         // per-block partial sums of the cycle-end pass
     long n_cpartial = 0;
+    // FGMRES workspace (allocated by the first sth_solve_fgmres)
+    int k_alloc = 0;                    // restart length the workspace holds
+    double* kv = nullptr;               // (restart+1) Krylov vectors
+    double* kz = nullptr;               // restart preconditioned vectors
+    double* kc = nullptr;               // kMaxKrylov coefficients / dot products
+    double* kpart = nullptr;            // 1024 x kMaxKrylov partial sums
+    double* khost = nullptr;            // pinned copy of kc
     double nb_lo = 0.0;                 // ||(I (x) C) r^||^2 >= nb_lo ||r^||^2
     double* buf0 = nullptr;
     double* buf1 = nullptr;
@@ -494,9 +502,9 @@ static int eig_exact_norm(sth_handle* h, hipStream_t st) {
                                    h->buf0, S, st));
     }
     if (h->dim == 2 && xform2d_supported(h->np)) {
-        // r = C r^ C^T per image and the sum of its squares, r not stored
+        // ||C r^ C^T||^2 per image as <r^ G, G r^> (G = C^T C), r not formed
         Timed tm(h, STH_K_RESNORM, dof * 4.0 * h->n, dof * 8.0, st);
-        HIPCHK(launch_xform2d_norm(h->buf0, h->Cf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm, st));
+        HIPCHK(launch_gram_norm2d(h->buf0, h->Gf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm, st));
     } else if (h->dim == 2) {
         // per-axis transforms buf0 -> buf1 -> buf0
         if ((rc = spatial_apply(h, INV_C, h->buf0, h->buf0, rows, h->buf1, st))) return rc;
@@ -543,7 +551,7 @@ void sth_problem_default(sth_problem* p) {
     p->nu_pre = 1;
     p->nu_post = 1;
     p->transform_prec = STH_FP64;
-    p->coarse_slabs = 8;
+    p->coarse_slabs = 64;            // about the compute units per time function (256 / N_t)
     p->iterate_basis = 0;
     p->temporal_form = 2;
 }
@@ -572,7 +580,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     const size_t vecsl = q.basis == 1 ? 3 : 2;               // u, f (+ u^ partner) per coarse level
     total += vecs0 * sizeof(double) * (size_t)q.n_slabs * slab;
     if (q.basis == 1) {
-        total += 2 * sizeof(double) * np * np;                // C, C^T
+        total += 3 * sizeof(double) * np * np;                // C, C^T, G
         total += sizeof(double) * (((size_t)(q.n_slabs / 2) * (size_t)(Nx) + 255) / 256 + 1);   // cycle-end partials
     }
     long S = q.n_slabs;
@@ -698,7 +706,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         if (h->basis == 1 && !dalloc(&h->lu2[l], (size_t)h->lev_S[l] * slab))
             return cleanup(STH_ENOMEM, "device allocation failed");
     }
-    std::vector<double> Cf, Ci;
+    std::vector<double> Cf, Ci, Gf;
     if (h->basis == 1) {
         // C = M_1 U = U^{-T} (from U^T M_1 U = I)
         Cf.assign((size_t)np * np, 0.0);
@@ -719,6 +727,19 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         if (hipMemcpyAsync(h->Cf, Cf.data(), Cf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
             hipMemcpyAsync(h->Ci, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
             return cleanup(STH_EHIP, "upload of the setup failed");
+        if (h->dim == 2 && xform2d_supported(np)) {
+            // G = C^T C for the exact residual norm
+            Gf.assign((size_t)np * np, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double g = 0.0;
+                    for (int k = 0; k < n; ++k) g += Cf[(size_t)k * np + i] * Cf[(size_t)k * np + j];
+                    Gf[(size_t)i * np + j] = g;
+                }
+            if (!dalloc(&h->Gf, (size_t)np * np) ||
+                hipMemcpyAsync(h->Gf, Gf.data(), Gf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+                return cleanup(STH_EHIP, "upload of the setup failed");
+        }
     }
     if (hipHostMalloc((void**)&h->hnorm, 3 * sizeof(double), 0) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
@@ -1027,6 +1048,132 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
     return solve_result(h, iters, relres);
 }
 
+// ---------------------------------------------------------------------------
+// FGMRES(m) outer loop, right-preconditioned by one V-cycle from a zero
+// initial guess (the use of the multigrid as a preconditioner named in the
+// introduction of the paper).  Flexible: the preconditioned vectors are kept,
+// so the preconditioner may change between iterations.  Classical
+// Gram-Schmidt applied twice, Givens rotations on the host.
+// ---------------------------------------------------------------------------
+static int precondition(sth_handle* h, const double* v, double* z, hipStream_t st) {
+    if (h->basis == 0) return vcycle_lvl(h, 0, v, z, true, st);
+    // the same cycle in the spatial eigenbasis: z = (I (x) U) V((I (x) U^T) v)
+    const long rows = h->lev_S[0] * h->Nt;
+    int rc;
+    if ((rc = spatial_apply(h, FWD_U, v, h->e0, rows, h->buf0, st))) return rc;
+    h->ecur[0] = 0;
+    h->presmoothed = false;
+    if ((rc = eig_vcycle(h, 0, true, st))) return rc;
+    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), z, rows, h->buf0, st);
+}
+
+static int krylov_workspace(sth_handle* h, int m) {
+    if (h->k_alloc >= m) return STH_OK;
+    for (double** q : {&h->kv, &h->kz, &h->kc, &h->kpart})
+        if (*q) { (void)hipFree(*q); *q = nullptr; }
+    if (h->khost) { (void)hipHostFree(h->khost); h->khost = nullptr; }
+    h->k_alloc = 0;
+    const size_t len = (size_t)h->lev_S[0] * slab_len(h);
+    if (hipMalloc((void**)&h->kv, sizeof(double) * len * (m + 1)) != hipSuccess ||
+        hipMalloc((void**)&h->kz, sizeof(double) * len * m) != hipSuccess ||
+        hipMalloc((void**)&h->kc, sizeof(double) * kMaxKrylov) != hipSuccess ||
+        hipMalloc((void**)&h->kpart, sizeof(double) * 1024 * kMaxKrylov) != hipSuccess ||
+        hipHostMalloc((void**)&h->khost, sizeof(double) * kMaxKrylov, 0) != hipSuccess)
+        return fail(STH_ENOMEM, "FGMRES workspace allocation failed");
+    h->k_alloc = m;
+    return STH_OK;
+}
+
+int sth_solve_fgmres(sth_handle* h, const double* f, double* u, double rtol, int maxit, int restart, int* iters,
+                     double* relres, void* stream) {
+    if (!h || !f || !u || !(rtol >= 0) || maxit < 0 || restart < 1 || restart >= kMaxKrylov)
+        return fail(STH_EINVAL, "bad argument (restart must be in 1..31)");
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    if ((rc = krylov_workspace(h, restart))) return rc;
+    const long len = h->lev_S[0] * slab_len(h);
+    double* V = h->kv;
+    double* Z = h->kz;
+    double fn = 0.0;
+    if ((rc = read_norm(h, f, len, st, &fn))) return rc;
+    if (fn == 0.0) fn = 1.0;
+    const int m = restart;
+    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), cs(m), sn(m), y(m);
+    auto Hij = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+    int it = 0;
+    double rn = 0.0;
+    for (;;) {
+        // r = f - L u into V_0, beta = ||r||
+        if ((rc = residual(h, 0, f, u, V, 0, h->lev_S[0], 1.0, st))) return rc;
+        double beta = 0.0;
+        if ((rc = read_norm(h, V, len, st, &beta))) return rc;
+        rn = beta;
+        if (!std::isfinite(beta)) break;
+        if (beta <= rtol * fn || it >= maxit) break;
+        h->khost[0] = 1.0 / beta;
+        HIPCHK(hipMemcpyAsync(h->kc, h->khost, sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_multiaxpy(V, len, 0, h->kc, 1.0 / beta, V, len, st));       // V_0 = r / beta
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int jn = 0;                          // columns completed in this cycle
+        for (int j = 0; j < m && it < maxit; ++j) {
+            double* Vj = V + (size_t)j * len;
+            double* Zj = Z + (size_t)j * len;
+            double* w = V + (size_t)(j + 1) * len;
+            if ((rc = precondition(h, Vj, Zj, st))) return rc;
+            if ((rc = residual(h, 0, nullptr, Zj, w, 0, h->lev_S[0], -1.0, st))) return rc;   // w = L z_j
+            for (int i = 0; i <= j; ++i) Hij(i, j) = 0.0;
+            for (int pass = 0; pass < 2; ++pass) {
+                HIPCHK(launch_multidot(V, len, j + 1, w, len, h->kpart, h->kc, st));
+                HIPCHK(hipMemcpyAsync(h->khost, h->kc, sizeof(double) * (j + 1), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                for (int i = 0; i <= j; ++i) {
+                    Hij(i, j) += h->khost[i];
+                    h->khost[i] = -h->khost[i];
+                }
+                HIPCHK(hipMemcpyAsync(h->kc, h->khost, sizeof(double) * (j + 1), hipMemcpyHostToDevice, st));
+                HIPCHK(launch_multiaxpy(V, len, j + 1, h->kc, 1.0, w, len, st));
+            }
+            double hn = 0.0;
+            if ((rc = read_norm(h, w, len, st, &hn))) return rc;
+            Hij(j + 1, j) = hn;
+            if (hn > 0.0) HIPCHK(launch_multiaxpy(V, len, 0, h->kc, 1.0 / hn, w, len, st));
+            // apply the previous rotations to column j, then a new one
+            for (int i = 0; i < j; ++i) {
+                const double a = Hij(i, j), b = Hij(i + 1, j);
+                Hij(i, j) = cs[i] * a + sn[i] * b;
+                Hij(i + 1, j) = -sn[i] * a + cs[i] * b;
+            }
+            const double a = Hij(j, j), b = Hij(j + 1, j);
+            const double r = std::hypot(a, b);
+            cs[j] = r > 0 ? a / r : 1.0;
+            sn[j] = r > 0 ? b / r : 0.0;
+            Hij(j, j) = r;
+            Hij(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            jn = j + 1;
+            if (std::fabs(g[j + 1]) <= rtol * fn || hn == 0.0) break;
+        }
+        // y = R^{-1} g, u += Z y
+        for (int i = jn - 1; i >= 0; --i) {
+            double v = g[i];
+            for (int k = i + 1; k < jn; ++k) v -= Hij(i, k) * y[k];
+            y[i] = v / Hij(i, i);
+        }
+        for (int i = 0; i < jn; ++i) h->khost[i] = y[i];
+        HIPCHK(hipMemcpyAsync(h->kc, h->khost, sizeof(double) * jn, hipMemcpyHostToDevice, st));
+        HIPCHK(launch_multiaxpy(Z, len, jn, h->kc, 1.0, u, len, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    if (iters) *iters = it;
+    if (relres) *relres = rn / fn;
+    if (!std::isfinite(rn)) return fail(STH_ENOCONV, "residual is not finite");
+    if (rn > rtol * fn) return fail(STH_ENOCONV, "maxit reached");
+    return STH_OK;
+}
+
 int sth_use_graphs(sth_handle* h, int enable) {
     if (!h) return fail(STH_EINVAL, "null handle");
     h->use_graph = enable != 0;
@@ -1054,13 +1201,14 @@ int sth_destroy(sth_handle* h) {
     // graph first: its nodes reference the buffers below
     drop_graph(h);
     double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt,
-                      h->Cf, h->Ci, h->e0, h->e1, h->e2, h->cpartial};
+                      h->Cf, h->Ci, h->Gf, h->e0, h->e1, h->e2, h->cpartial, h->kv, h->kz, h->kc, h->kpart};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto* vec : {&h->lu, &h->lf, &h->lu2})
         for (double* q : *vec)
             if (q) (void)hipFree(q);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
+    if (h->khost) (void)hipHostFree(h->khost);
     for (auto e : h->pool) (void)hipEventDestroy(e);
     delete h;
     return STH_OK;

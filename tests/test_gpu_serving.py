@@ -17,16 +17,17 @@ from oracle.solve import SlabSystem
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-# (problem, rhs seed): 2-D and 3-D, both iteration bases, reduced precision
+# (problem, rhs seed): 2-D and 3-D, multilevel and single-level (exact)
+# solves, both iteration bases, reduced precision
 MIX = [
     (dict(dim=2, n_elem=12, degree=2, n_slabs=8, n_elem_t=2, basis="eigen"), 11),
-    (dict(dim=2, n_elem=20, degree=3, n_slabs=16, n_elem_t=2, basis="eigen"), 12),
-    (dict(dim=2, n_elem=16, degree=2, n_slabs=4, n_elem_t=2, basis="nodal"), 13),
+    (dict(dim=2, n_elem=20, degree=3, n_slabs=16, n_elem_t=2, basis="eigen", coarse_slabs=2), 12),
+    (dict(dim=2, n_elem=16, degree=2, n_slabs=4, n_elem_t=2, basis="nodal", coarse_slabs=1), 13),
     (dict(dim=2, n_elem=24, degree=4, n_slabs=8, n_elem_t=2, basis="nodal", prec="fp32"), 14),
-    (dict(dim=3, n_elem=6, degree=2, n_slabs=4, n_elem_t=2, basis="eigen"), 15),
+    (dict(dim=3, n_elem=6, degree=2, n_slabs=4, n_elem_t=2, basis="eigen", coarse_slabs=1), 15),
     (dict(dim=2, n_elem=12, degree=2, n_slabs=8, n_elem_t=2, basis="eigen"), 16),
     (dict(dim=2, n_elem=40, degree=2, n_slabs=32, n_elem_t=1, basis="eigen", coarse_slabs=2), 17),
-    (dict(dim=3, n_elem=5, degree=3, n_slabs=8, n_elem_t=2, basis="nodal"), 18),
+    (dict(dim=3, n_elem=5, degree=3, n_slabs=8, n_elem_t=2, basis="nodal", coarse_slabs=2), 18),
 ]
 RTOL = 1e-11
 

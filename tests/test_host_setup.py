@@ -125,8 +125,8 @@ def test_level_count():
     assert sth.host_factors(n_slabs=16, coarse_slabs=1, **kw)["n_levels"] == 5
     assert sth.host_factors(n_slabs=12, coarse_slabs=1, **kw)["n_levels"] == 3
     assert sth.host_factors(n_slabs=1, coarse_slabs=1, **kw)["n_levels"] == 1
-    assert sth.host_factors(n_slabs=256, **kw)["n_levels"] == 6          # default: coarsest <= 8 slabs
-    assert sth.host_factors(n_slabs=8, **kw)["n_levels"] == 1
+    assert sth.host_factors(n_slabs=256, **kw)["n_levels"] == 3          # default: coarsest <= 64 slabs
+    assert sth.host_factors(n_slabs=64, **kw)["n_levels"] == 1
 
 
 def test_guard_mt_not_positive():
@@ -151,10 +151,13 @@ def test_invalid_problems_rejected(bad):
 
 
 def test_workspace_bytes_grows_with_problem():
-    a = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=16, n_elem_t=2)
-    b = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=32, n_elem_t=2)
+    a = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=16, n_elem_t=2, coarse_slabs=1)
+    b = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=32, n_elem_t=2, coarse_slabs=1)
     vec = 32 * 4 * 16 * 16 * 8
+    # two level-0 work vectors plus u and f on the coarse levels (about one more vector)
     assert b > a and b >= 3 * vec
+    single = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=32, n_elem_t=2)    # one level
+    assert 2 * vec <= single < b
 
 
 @pytest.mark.parametrize("dim", [2, 3])
