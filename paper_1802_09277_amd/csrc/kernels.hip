@@ -1256,21 +1256,22 @@ __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const doub
 // in time.  Per mode the slab systems are A u_s = g_s + e_1 x_{s-1} with the
 // scalar x_{s-1} = u_{s-1}[N_t - 1], so u_s = a_s + x_{s-1} c with
 // a_s = A^{-1} g_s (independent over s) and c = A^{-1} e_1, and the scalars
-// obey x_s = a_s[N_t-1] + gamma x_{s-1}, gamma = c[N_t-1].  A block holds 32
-// modes x 8 slab groups: each thread solves its group's slabs (into out),
-// the groups' recurrences are chained through LDS, and a second sweep adds
-// x_{s-1} c.  in and out must differ.
+// obey x_s = a_s[N_t-1] + gamma x_{s-1}, gamma = c[N_t-1].  A block holds 16
+// modes (one 128-byte line per time row) x 16 slab groups: each thread solves
+// its group's slabs (into out), the groups' recurrences are chained through
+// LDS, and a second sweep adds x_{s-1} c.  in and out must differ.
 template <int NT, bool SCHUR>
 __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
                                                       long Nx, const double* __restrict__ in,
                                                       double* __restrict__ out, long S) {
-    constexpr int MB = 32, G = 8;
+    constexpr int MB = 16, G = 16, LR = 4;      // LR: slabs per group held in registers
     __shared__ double xe_s[G][MB], gl_s[G][MB];
     const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
     const long m = (long)blockIdx.x * MB + ml;
     const long L = (S + G - 1) / G;
     const long sb = g * L, se = (sb + L < S) ? sb + L : S;
-    double c[NT], xe = 0.0, gl = 1.0, gamma = 0.0;
+    const bool inreg = L <= LR;
+    double c[NT], areg[LR][NT], xe = 0.0, gl = 1.0, gamma = 0.0;
     const bool active = m < Nx;
     double mu = 0.0;
     if (active) {
@@ -1280,7 +1281,27 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
         for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
         shifted_solve<NT, SCHUR>(tm, mu, e1, c);
         gamma = c[NT - 1];
-        for (long s = sb; s < se; ++s) {
+        if (inreg) {
+            // all loads of the group first, then the (independent) solves
+#pragma unroll
+            for (int i = 0; i < LR; ++i)
+                if (sb + i < se) {
+                    const double* gp = in + (sb + i) * NT * Nx + m;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) areg[i][t] = gp[(long)t * Nx];
+                }
+#pragma unroll
+            for (int i = 0; i < LR; ++i)
+                if (sb + i < se) {
+                    double a[NT];
+                    shifted_solve<NT, SCHUR>(tm, mu, areg[i], a);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) areg[i][t] = a[t];
+                    xe = a[NT - 1] + gamma * xe;  // group recurrence from x = 0
+                    gl *= gamma;                  // gamma^(slabs so far)
+                }
+        }
+        for (long s = inreg ? se : sb; s < se; ++s) {
             const double* gp = in + s * NT * Nx + m;
             double gv[NT], a[NT];
 #pragma unroll
@@ -1299,6 +1320,20 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
     if (!active) return;
     double x = 0.0;                               // x entering the group
     for (int h = 0; h < g; ++h) x = xe_s[h][ml] + gl_s[h][ml] * x;
+    if (inreg) {
+#pragma unroll
+        for (int i = 0; i < LR; ++i)
+            if (sb + i < se) {
+                double* o = out + (sb + i) * NT * Nx + m;
+                double u[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) u[t] = areg[i][t] + x * c[t];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) o[(long)t * Nx] = u[t];
+                x = u[NT - 1];
+            }
+        return;
+    }
     for (long s = sb; s < se; ++s) {
         double* o = out + s * NT * Nx + m;
         double u[NT];
@@ -1317,7 +1352,7 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
     if (total <= 0) return hipSuccess;
     if (fwdsub && in == out) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
-    dim3 gridm((unsigned)((Nx + 31) / 32));
+    dim3 gridm((unsigned)((Nx + 15) / 16));
 #define STH_TM_LAUNCH(NTV, SC)                                                                           \
     if (fwdsub)                                                                                          \
         hipLaunchKernelGGL((k_timemix_scan<NTV, SC>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in,   \
@@ -1476,6 +1511,10 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
     for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
 }
 
+// change of the coupling value (last time row of the previous slab) made by
+// a smoothing step
+__device__ __forceinline__ double up_prev_delta(double prev_new, double prev_old) { return prev_new - prev_old; }
+
 // End of a cycle on the finest level, for one spatial mode and a chain of
 // `chain` consecutive slabs (chain even, starting at an even slab): the
 // residual r^ = f^ - L u^ of the iterate (its squares summed per block into
@@ -1530,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
             double g[NT], g2[NT], u[NT], z[NT], up[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                g[t] = g2[t] = fnx[t];
+                g[t] = fnx[t];
                 u[t] = unx[t];
             }
             if (k + 1 < chain) {
@@ -1549,7 +1588,11 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                 up[t] = u[t] + omega * z[t];
                 uout[b + (long)t * Nx] = up[t];
             }
-            eig_residual_point<NT>(ktmt, mu, up, prev_new, g2);
+            // residual of u': A z = g (the block of the smoother is the slab
+            // operator), so f - A u' + e_1 u'_prev = (1 - omega) g + e_1 (u'_prev - u_prev)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) g2[t] = (1.0 - omega) * g[t];
+            g2[0] += up_prev_delta(prev_new, prev_old);
             if (h == 0) {
 #pragma unroll
                 for (int c = 0; c < NT; ++c) acc[c] = 0.0;
@@ -1574,6 +1617,73 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ssq;
     __syncthreads();
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Descent on a coarse level with a zero initial guess and one pre-smoothing
+// step, for one spatial mode and a chain of `chain` slabs (chain even,
+// starting at an even slab): u' = omega A^{-1} f (into uout) and the
+// restriction of its residual, fc = (P_t^T (x) I)[f - L u']_{2k, 2k+1}, from one
+// read of f.  The last time row of the previous slab's u' is carried along the
+// chain; a chain after slab 0 first repeats the step for its preceding slab.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                  const double* __restrict__ mu1, int n, long Nx,
+                                                  const double* __restrict__ fl, double* __restrict__ uout,
+                                                  double* __restrict__ fc, Transfer tr, double omega, int chain,
+                                                  long total) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const long q = idx / Nx, m = idx % Nx;
+    const double mu = mode_shift(dim, mu1, n, m);
+    const long s0 = q * chain;
+    double prev = 0.0;
+    if (s0 > 0) {
+        const long b = (s0 - 1) * NT * Nx + m;
+        double g[NT], z[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g[t] = fl[b + (long)t * Nx];
+        shifted_solve<NT, SCHUR>(tm, mu, g, z);
+        prev = omega * z[NT - 1];
+    }
+    double fnx[NT], acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) fnx[t] = fl[s0 * NT * Nx + m + (long)t * Nx];
+#pragma unroll 1
+    for (int k = 0; k < chain; ++k) {
+        const int h = k & 1;
+        const long b = (s0 + k) * NT * Nx + m;
+        double g[NT], g2[NT], z[NT], up[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g[t] = fnx[t];
+        if (k + 1 < chain) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) fnx[t] = fl[b + NT * Nx + (long)t * Nx];
+        }
+        shifted_solve<NT, SCHUR>(tm, mu, g, z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            up[t] = omega * z[t];
+            uout[b + (long)t * Nx] = up[t];
+        }
+        // residual of u' = omega A^{-1} f: f - A u' + e_1 u'_prev = (1 - omega) f + e_1 u'_prev
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g2[t] = (1.0 - omega) * g[t];
+        g2[0] += prev;
+        if (h == 0) {
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g2[t];
+        if (h == 1) {
+            const long mc = (s0 + k) / 2;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+        }
+        prev = up[NT - 1];
+    }
 }
 
 #define STH_NT_SWITCH(KER, GRID, ...)                                                      \
@@ -1856,11 +1966,12 @@ __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < kMaxKrylov; ++i) {
-        if (i >= k) break;
-        double v = acc[i];
+        if (i < k) {
+            double v = acc[i];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        if (lane == 0) red[wave][i] = v;
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+            if (lane == 0) red[wave][i] = v;
+        }
     }
     __syncthreads();
     if ((int)threadIdx.x < k)
@@ -1905,6 +2016,33 @@ hipError_t launch_multiaxpy(const double* V, long ld, int k, const double* c, do
                             hipStream_t st) {
     if (k < 0 || k > kMaxKrylov || len <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_multiaxpy, dim3(kKrylovBlocks), dim3(256), 0, st, V, ld, k, c, alpha, w, len);
+    return hipGetLastError();
+}
+
+
+hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
+                           int chain, hipStream_t st) {
+    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_DN_CASE(NTV)                                                                                  \
+        case NTV:                                                                                          \
+            if (tm.schur)                                                                                  \
+                hipLaunchKernelGGL((k_eig_down<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, \
+                                   fl, uout, fc, tr, omega, chain, total);                                 \
+            else                                                                                           \
+                hipLaunchKernelGGL((k_eig_down<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n,    \
+                                   Nx, fl, uout, fc, tr, omega, chain, total);                             \
+            break;
+        STH_DN_CASE(2) STH_DN_CASE(3) STH_DN_CASE(4) STH_DN_CASE(5) STH_DN_CASE(6) STH_DN_CASE(7) STH_DN_CASE(8)
+#undef STH_DN_CASE
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

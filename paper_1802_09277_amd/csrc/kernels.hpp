@@ -79,6 +79,11 @@ hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* k
 //  `chain` slabs per thread, chain even and dividing S): out[0] = ||fh - L uin||^2,
 //  uout = uin + omega A^{-1}(fh - L uin), fc = (P^T (x) I)(fh - L uout) on slab
 //  pairs; partial needs max_partial >= ceil((S/chain) Nx / 256) entries
+//  descent on a coarse level from a zero guess, one pass over fl (chains as
+//  above): uout = omega A^{-1} fl, fc = (P^T (x) I)(fl - L uout) on slab pairs
+hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
+                           int chain, hipStream_t st);
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, double* partial, long max_partial, double* out,

@@ -407,6 +407,14 @@ static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st, c
     return STH_OK;
 }
 
+// slabs per thread in the chained passes: the longest chain (fewest repeated
+// chain starts) that still leaves min_threads threads
+static int chain_length(const sth_handle* h, long S, long min_threads) {
+    for (int c : {8, 4})
+        if (S % c == 0 && (S / c) * h->Nx >= min_threads) return c;
+    return 2;
+}
+
 static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     h->tlev = lvl;
     if (lvl > 0) h->ecur[lvl] = 0;
@@ -428,6 +436,14 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         // residual) took the pre-smoothing step and restricted its residual
         h->ecur[0] = 1 - h->ecur[0];
         h->presmoothed = false;
+    } else if (zero_guess && h->nu_pre == 1) {
+        // one pass: smoothing step from zero and restriction of its residual
+        double dof = (double)S * slab_len(h);
+        const int c = h->ecur[lvl];
+        Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), 20.0 * dof, st);
+        HIPCHK(launch_eig_down(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
+                               eig_u(h, lvl, 1 - c), eig_f(h, lvl + 1), h->tr, h->omega, S, chain_length(h, S, 262144), st));
+        h->ecur[lvl] = 1 - c;
     } else {
         for (int i = 0; i < h->nu_pre; ++i)
             if ((rc = eig_smooth(h, lvl, zero_guess && i == 0, st))) return rc;
@@ -453,12 +469,6 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
 // cycle-end kernel) also takes the next cycle's smoothing step (into the
 // other buffer of the pair) and restricts the residual of its result into
 // the next level's right-hand side; the next V-cycle adopts both.
-static int chain_length(const sth_handle* h) {
-    const long S = h->lev_S[0];
-    for (int c : {8, 4})
-        if (S % c == 0 && (S / c) * h->Nx >= 65536) return c;
-    return 2;
-}
 
 static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
     h->tlev = 0;
@@ -471,7 +481,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         Timed tm(h, STH_K_EIG_CYCLE_END, dof * (12.0 * Nt + 10.0), 28.0 * dof, st);
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, 1 - c), eig_f(h, 1), h->tr, h->omega, S,
-                                    chain_length(h), h->cpartial, h->n_cpartial, h->dnorm + 2, st));
+                                    chain_length(h, S, 65536), h->cpartial, h->n_cpartial, h->dnorm + 2, st));
         h->presmoothed = true;
     } else {
         {
