@@ -423,24 +423,123 @@ static long persistent_blocks(size_t shm, long nimg) {
     return nimg < blocks ? nimg : blocks;
 }
 
-template <typename CT, int DIR, int NT16, int EPI>
+// The 2-D kernels below may leave the last rows and columns of an image to
+// FP64 dot products (one per thread) instead of a further row and column of
+// MFMA tiles; not for NT16 = 6, which has no registers left for them.
+template <int NT16> constexpr bool kXform2dEdge = NT16 > 1 && NT16 < 6;
+
+// LDS placement of an NP x NP tile (NP = 16 NT16).  FP64: rows of NP words,
+// the column index XOR-ed with the low four bits of the row (and, for an even
+// NT16, bit four with the row parity), so that the MFMA operand reads along a
+// row (16 rows x 2 columns per half-wave) and along a column (2 rows x 16
+// columns) fall into distinct banks.  FP32: rows padded to NP + 1 words.
+template <typename CT, int NT16> struct TileLds {
+    static constexpr int NP = NT16 * 16;
+    static constexpr int SIZE = sizeof(CT) == 8 ? NP * NP : NP * (NP + 1);
+    static __device__ __forceinline__ int at(int r, int c) {
+        if constexpr (sizeof(CT) == 8) {
+            const int s = (r & 15) | ((NT16 % 2 == 0) ? (r & 1) << 4 : 0);
+            return r * NP + (c ^ s);
+        } else {
+            return r * (NP + 1) + c;
+        }
+    }
+};
+
+// Entries of an image outside its MFMA core (the last n - c0 rows, then the
+// last n - c0 columns of the first c0 rows) assigned to groups of g threads
+// (g = 4, 2 or 1 by their count); member `part` of a group sums the k-chunks
+// of 4 with index = part (mod g).  Returns false for threads without one.
+__device__ __forceinline__ bool xform2d_edge(int tid, int n, int c0, int& g, int& part, int& ei, int& ej) {
+    const int tail = n - c0, ne = n * n - c0 * c0;
+    g = ne <= 128 ? 4 : (ne <= 256 ? 2 : 1);
+    part = tid % g;
+    const int e = tid / g;
+    ei = -1;
+    ej = 0;
+    if (tail <= 0 || e >= ne) return false;
+    if (e < tail * n) {
+        ei = c0 + e / n;
+        ej = e % n;
+    } else {
+        const int t = e - tail * n;
+        ej = c0 + t / c0;
+        ei = t % c0;
+    }
+    return true;
+}
+
+// sum over the g members of an edge group (adjacent lanes); all lanes call it
+__device__ __forceinline__ double xform2d_edge_sum(double v, int g) {
+    if (g >= 2) v += __shfl_xor(v, 1);
+    if (g >= 4) v += __shfl_xor(v, 2);
+    return v;
+}
+
+// k loop of the LDS-resident 2-D kernels over [0, kpad) in steps of 4 H
+// (kpad a multiple of 4 H, LDS zero from n on).  With DB the operands of the
+// next step are read into the second buffer before the MFMAs of the current
+// one; the read is always issued (at a clamped, in-range k) so that only the
+// MFMAs are conditional and the LDS counter waits stay exact.
+template <int H, bool DB, typename B, typename LD, typename MM>
+__device__ __forceinline__ void mfma_kloop(int kpad, LD&& ld, MM&& mma) {
+    constexpr int STEP = 4 * H;
+    if constexpr (DB) {
+        B x, y;
+        ld(0, x);
+        for (int k0 = 0; k0 < kpad; k0 += 2 * STEP) {
+            ld(min(k0 + STEP, kpad - STEP), y);
+            mma(x);
+            ld(min(k0 + 2 * STEP, kpad - STEP), x);
+            if (k0 + STEP < kpad) mma(y);
+        }
+    } else {
+        for (int k0 = 0; k0 < kpad; k0 += STEP) {
+            B x;
+            ld(k0, x);
+            mma(x);
+        }
+    }
+}
+
+template <typename CT, int DIR, int NT16, int EPI, bool CORE>
 __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, double* __restrict__ out,
                                                  const double* __restrict__ Upad, int n, long nimg,
                                                  double alpha) {
     using M = Mfma16<CT>;
+    using T = TileLds<CT, NT16>;
     typedef typename M::acc_t acc_t;
-    constexpr int NP = NT16 * 16, LD = NP + 1;
-    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
+    constexpr int NP = NT16 * 16;
+    // CORE: MFMA tiles over the first NT16 - 1 tile rows and columns only
+    constexpr int NC = CORE ? NT16 - 1 : NT16;
+    constexpr int TPW = (NC * NC + 7) / 8;
+    // k-steps per operand buffer and double buffering, as registers allow
+    constexpr int H = TPW <= 2 ? 2 : 1;
+    constexpr bool DB = TPW <= 4;
+    struct Buf { CT a[H][TPW], b[H][TPW]; };
     extern __shared__ double sm_raw[];
-    CT* Us = reinterpret_cast<CT*>(sm_raw);   // U[k][j], row stride LD
-    CT* Is = Us + NP * LD;                    // image / intermediate, row stride LD
+    CT* Us = reinterpret_cast<CT*>(sm_raw);   // U[k][j]
+    CT* Is = Us + T::SIZE;                    // image / intermediate
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int kp = (n + 3) & ~3;
-    for (int i = tid; i < NP * NP; i += 512) {
-        int r = i / NP, c = i % NP;
-        Us[r * LD + c] = (CT)Upad[i];
+    const int kp = (n + 3) & ~3, kpad = (n + 4 * H - 1) / (4 * H) * (4 * H);
+    // MFMA tiles cover the first c0 = 16 NC rows and columns; with CORE the
+    // remaining n^2 - c0^2 <= 512 entries are FP64 dot products.  Tile slots
+    // of a wave past the last tile repeat it and are not stored, so that the
+    // slot loops have no branches.
+    constexpr int NTILE = NC * NC, c0 = 16 * NC;
+    int ti[TPW], tj[TPW];
+    bool own[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tq = wave + 8 * q;
+        own[q] = tq < NTILE;
+        ti[q] = (own[q] ? tq : NTILE - 1) / NC;
+        tj[q] = (own[q] ? tq : NTILE - 1) % NC;
     }
+    int eg = 1, epart = 0, ei = -1, ej = 0;
+    const bool edge = CORE && xform2d_edge(tid, n, c0, eg, epart, ei, ej);
+    for (int i = tid; i < NP * NP; i += 512) Us[T::at(i / NP, i % NP)] = (CT)Upad[i];
     const long nn = (long)n * n;
     // the next image is staged in registers while the current one is in the
     // MFMA products (blocks are persistent over images)
@@ -460,94 +559,133 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k;
-            if (i < NP * NP) Is[(i / NP) * LD + i % NP] = (CT)pre[k];
+            if (i < NP * NP) Is[T::at(i / NP, i % NP)] = (CT)pre[k];
         }
         if (img + gridDim.x < nimg) load_img(img + gridDim.x);
         __syncthreads();
         acc_t acc[TPW];
-        // first product: T1 = R U (forward) or Y U^T (inverse).  The k loop is
-        // outside the tile loop so that the MFMAs of a wave's tiles are
-        // independent and issue back to back.
+        auto mma = [&](const Buf& x) {
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) acc[q] = M::op(x.a[h][q], x.b[h][q], acc[q]);
+        };
+        // first product: T1 = R U (forward) or Y U^T (inverse)
 #pragma unroll
         for (int q = 0; q < TPW; ++q) acc[q] = acc_t{0, 0, 0, 0};
-        for (int k0 = 0; k0 < kp; k0 += 4) {
+        mfma_kloop<H, DB, Buf>(kpad, [&](int k0, Buf& x) {
 #pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                const int tq = wave + 8 * q;
-                if (tq < NTILE) {
-                    const int ti = tq / NT16, tj = tq % NT16;
-                    CT a = Is[(ti * 16 + lr) * LD + k0 + lk];
-                    CT b = (DIR == 0) ? Us[(k0 + lk) * LD + tj * 16 + lr] : Us[(tj * 16 + lr) * LD + k0 + lk];
-                    acc[q] = M::op(a, b, acc[q]);
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    const int k = k0 + 4 * h + lk;
+                    x.a[h][q] = Is[T::at(ti[q] * 16 + lr, k)];
+                    x.b[h][q] = (DIR == 0) ? Us[T::at(k, tj[q] * 16 + lr)] : Us[T::at(tj[q] * 16 + lr, k)];
                 }
+        }, mma);
+        // edge entries of T1 (rows and columns from n on are zero in LDS)
+        double e = 0.0;
+        if (edge) {
+            for (int k0 = 4 * epart; k0 < kp; k0 += 4 * eg) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    e += (double)Is[T::at(ei, k0 + kk)] *
+                         (double)((DIR == 0) ? Us[T::at(k0 + kk, ej)] : Us[T::at(ej, k0 + kk)]);
             }
         }
+        if (CORE) e = xform2d_edge_sum(e, eg);
         __syncthreads();
+        // T1 over the image (rows and columns from n on stay zero)
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
+            if (own[q]) {
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) Is[(ti * 16 + M::row(lk, rr)) * LD + tj * 16 + lr] = acc[q][rr];
+                for (int rr = 0; rr < 4; ++rr)
+                    Is[T::at(ti[q] * 16 + M::row(lk, rr), tj[q] * 16 + lr)] = acc[q][rr];
             }
         }
+        if (edge && epart == 0) Is[T::at(ei, ej)] = (CT)e;
         __syncthreads();
         // second product: U^T T1 (forward) or U T1 (inverse)
 #pragma unroll
         for (int q = 0; q < TPW; ++q) acc[q] = acc_t{0, 0, 0, 0};
-        for (int k0 = 0; k0 < kp; k0 += 4) {
+        mfma_kloop<H, DB, Buf>(kpad, [&](int k0, Buf& x) {
 #pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                const int tq = wave + 8 * q;
-                if (tq < NTILE) {
-                    const int ti = tq / NT16, tj = tq % NT16;
-                    CT a = (DIR == 0) ? Us[(k0 + lk) * LD + ti * 16 + lr] : Us[(ti * 16 + lr) * LD + k0 + lk];
-                    CT b = Is[(k0 + lk) * LD + tj * 16 + lr];
-                    acc[q] = M::op(a, b, acc[q]);
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    const int k = k0 + 4 * h + lk;
+                    x.a[h][q] = (DIR == 0) ? Us[T::at(k, ti[q] * 16 + lr)] : Us[T::at(ti[q] * 16 + lr, k)];
+                    x.b[h][q] = Is[T::at(k, tj[q] * 16 + lr)];
                 }
+        }, mma);
+        e = 0.0;
+        if (edge) {
+            for (int k0 = 4 * epart; k0 < kp; k0 += 4 * eg) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    e += (double)((DIR == 0) ? Us[T::at(k0 + kk, ei)] : Us[T::at(ei, k0 + kk)]) *
+                         (double)Is[T::at(k0 + kk, ej)];
             }
         }
+        if (CORE) e = xform2d_edge_sum(e, eg);
         double* dst = out + img * nn;
+        auto put = [&](int i, int j, double v) {
+            double* o = dst + (long)i * n + j;
+            if (EPI == 0) *o = v;
+            else if (EPI == 1) *o += alpha * v;
+            else *o = alpha * v;
+        };
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
-            const int tq = wave + 8 * q;
-            if (tq < NTILE) {
-                const int ti = tq / NT16, tj = tq % NT16;
-                const int j = tj * 16 + lr;
+            if (own[q]) {
+                const int j = tj[q] * 16 + lr;
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    const int i = ti * 16 + M::row(lk, rr);
-                    if (i < n && j < n) {
-                        double v = (double)acc[q][rr];
-                        double* o = dst + (long)i * n + j;
-                        if (EPI == 0) *o = v;
-                        else if (EPI == 1) *o += alpha * v;
-                        else *o = alpha * v;
-                    }
+                    const int i = ti[q] * 16 + M::row(lk, rr);
+                    if (i < n && j < n) put(i, j, (double)acc[q][rr]);
                 }
             }
         }
+        if (edge && epart == 0) put(ei, ej, e);
     }
 }
 
-template <typename CT, int DIR, int NT16, int EPI>
-static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
-                                 hipStream_t st, long* nblocks = nullptr) {
-    constexpr int NP = NT16 * 16;
-    size_t shm = sizeof(CT) * 2 * (size_t)NP * (NP + 1);
+// MFMA tiles per axis for an n x n image stored in NT16 x NT16 tiles: all of
+// them, or one fewer when the n^2 - (16 (NT16 - 1))^2 entries outside the
+// smaller core fit one per thread of a 512-thread block
+template <int NT16> static int xform2d_core_tiles(int n) {
+    const int c0 = 16 * (NT16 - 1);
+    return (kXform2dEdge<NT16> && n * n - c0 * c0 <= 512) ? NT16 - 1 : NT16;
+}
+
+template <typename CT, int DIR, int NT16, int EPI, bool CORE>
+static hipError_t xform2d_go(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
+                             hipStream_t st, long* nblocks) {
+    size_t shm = sizeof(CT) * 2 * (size_t)TileLds<CT, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI, CORE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     long blocks = persistent_blocks(shm, nimg);
     if (nblocks) *nblocks = blocks;
-    hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Upad,
-                       n, nimg, alpha);
+    hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, out,
+                       Upad, n, nimg, alpha);
     return hipGetLastError();
+}
+
+template <typename CT, int DIR, int NT16, int EPI>
+static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
+                                 hipStream_t st, long* nblocks = nullptr) {
+    if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
+    if constexpr (kXform2dEdge<NT16>) {
+        if (xform2d_core_tiles<NT16>(n) < NT16)
+            return xform2d_go<CT, DIR, NT16, EPI, true>(in, out, Upad, n, nimg, alpha, st, nblocks);
+    }
+    return xform2d_go<CT, DIR, NT16, EPI, false>(in, out, Upad, n, nimg, alpha, st, nblocks);
 }
 
 template <typename CT, int DIR, int EPI>
@@ -613,8 +751,14 @@ __global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, 
                                                  double alpha) {
     using M = Mfma16<CT>;
     typedef typename M::acc_t acc_t;
-    __shared__ CT in_s[64][17];
-    __shared__ CT T_s[16][130];
+    // FP64: rows of 16 (in_s) and 128 (T_s) words with XOR-swizzled columns
+    // (row reads of 16 rows x 2 columns and column reads of 2 rows x 16
+    // columns per half-wave hit distinct banks); FP32: padded rows
+    constexpr bool F64 = sizeof(CT) == 8;
+    __shared__ CT in_s[F64 ? 64 * 16 : 64 * 17];
+    __shared__ CT T_s[F64 ? 16 * 128 : 16 * 130];
+    auto ia = [](int l, int kk) { return F64 ? l * 16 + (kk ^ (l & 15)) : l * 17 + kk; };
+    auto ta = [](int kk, int jj) { return F64 ? kk * 128 + (jj ^ ((kk & 1) << 4)) : kk * 130 + jj; };
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const long line0 = (long)blockIdx.x * 64;
@@ -628,20 +772,20 @@ __global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, 
             int l = i >> 4, kk = i & 15;
             long line = line0 + l;
             int k = k0 + kk;
-            in_s[l][kk] = (CT)((line < lines && k < n) ? in[line * n + k] : 0.0);
+            in_s[ia(l, kk)] = (CT)((line < lines && k < n) ? in[line * n + k] : 0.0);
         }
         for (int i = threadIdx.x; i < 16 * 128; i += 256) {
             int kk = i >> 7, jj = i & 127;
             int j = j0 + jj;
-            T_s[kk][jj] = (CT)((j < np) ? T[(long)(k0 + kk) * np + j] : 0.0);
+            T_s[ta(kk, jj)] = (CT)((j < np) ? T[(long)(k0 + kk) * np + j] : 0.0);
         }
         __syncthreads();
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) {
-            CT a = in_s[wave * 16 + lr][kq * 4 + lk];
+            CT a = in_s[ia(wave * 16 + lr, kq * 4 + lk)];
 #pragma unroll
             for (int jt = 0; jt < 8; ++jt) {
-                if (jt < njt) acc[jt] = M::op(a, T_s[kq * 4 + lk][jt * 16 + lr], acc[jt]);
+                if (jt < njt) acc[jt] = M::op(a, T_s[ta(kq * 4 + lk, jt * 16 + lr)], acc[jt]);
             }
         }
         __syncthreads();
@@ -671,8 +815,12 @@ __global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, 
                                                  int nib, int njb) {
     using M = Mfma16<CT>;
     typedef typename M::acc_t acc_t;
-    __shared__ CT in_s[16][66];
-    __shared__ CT T_s[16][66];
+    // FP64: rows of 64 words, bit four of the column flipped on odd rows (the
+    // column reads of 2 rows x 16 columns per half-wave hit distinct banks)
+    constexpr bool F64 = sizeof(CT) == 8;
+    __shared__ CT in_s[F64 ? 16 * 64 : 16 * 66];
+    __shared__ CT T_s[F64 ? 16 * 64 : 16 * 66];
+    auto sa = [](int kk, int ii) { return F64 ? kk * 64 + (ii ^ ((kk & 1) << 4)) : kk * 66 + ii; };
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     long bid = blockIdx.x;
@@ -693,17 +841,17 @@ __global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, 
             int kk = i >> 6, ii = i & 63;
             int k = k0 + kk;
             long ig = i0 + ii;
-            in_s[kk][ii] = (CT)((k < n && ig < inner) ? inb[(long)k * inner + ig] : 0.0);
+            in_s[sa(kk, ii)] = (CT)((k < n && ig < inner) ? inb[(long)k * inner + ig] : 0.0);
             int j = j0 + ii;
-            T_s[kk][ii] = (CT)((j < np) ? T[(long)k * np + j] : 0.0);
+            T_s[sa(kk, ii)] = (CT)((j < np) ? T[(long)k * np + j] : 0.0);
         }
         __syncthreads();
         if (active) {
 #pragma unroll
             for (int kq = 0; kq < 4; ++kq) {
-                CT a = T_s[kq * 4 + lk][wave * 16 + lr];
+                CT a = T_s[sa(kq * 4 + lk, wave * 16 + lr)];
 #pragma unroll
-                for (int it = 0; it < 4; ++it) acc[it] = M::op(a, in_s[kq * 4 + lk][it * 16 + lr], acc[it]);
+                for (int it = 0; it < 4; ++it) acc[it] = M::op(a, in_s[sa(kq * 4 + lk, it * 16 + lr)], acc[it]);
             }
         }
         __syncthreads();
@@ -1031,18 +1179,37 @@ bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 
 // G = C^T C (symmetric, padded to NP): both MFMA products read the staged
 // image, there is no intermediate product to store, and one barrier pair per
 // image suffices.  Per-block partial sums in a fixed order.
-template <int NT16>
+template <int NT16, bool CORE>
 __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ in, const double* __restrict__ Gpad,
                                                      int n, long nimg, double* __restrict__ partial) {
-    constexpr int NP = NT16 * 16, LD = NP + 1;
-    constexpr int NTILE = NT16 * NT16, TPW = (NTILE + 7) / 8;
+    using T = TileLds<double, NT16>;
+    constexpr int NP = NT16 * 16;
+    constexpr int NC = CORE ? NT16 - 1 : NT16;
+    constexpr int TPW = (NC * NC + 7) / 8;
+    constexpr int H = TPW <= 1 ? 2 : 1;
+    constexpr bool DB = TPW <= 2;
+    struct Buf { double o[H][4][TPW]; };
     extern __shared__ double sm_raw[];
     double* Gs = sm_raw;
-    double* Ys = sm_raw + NP * LD;
+    double* Ys = sm_raw + T::SIZE;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int kp = (n + 3) & ~3;
-    for (int i = tid; i < NP * NP; i += 512) Gs[(i / NP) * LD + i % NP] = Gpad[i];
+    const int kp = (n + 3) & ~3, kpad = (n + 4 * H - 1) / (4 * H) * (4 * H);
+    // MFMA tiles over the first c0 rows and columns (branch-free slots as in
+    // the transform kernel), with CORE FP64 dot products for the rest
+    constexpr int NTILE = NC * NC, c0 = 16 * NC;
+    int ti[TPW], tj[TPW];
+    bool own[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tq = wave + 8 * q;
+        own[q] = tq < NTILE;
+        ti[q] = (own[q] ? tq : NTILE - 1) / NC;
+        tj[q] = (own[q] ? tq : NTILE - 1) % NC;
+    }
+    int eg = 1, epart = 0, ei = -1, ej = 0;
+    const bool edge = CORE && xform2d_edge(tid, n, c0, eg, epart, ei, ej);
+    for (int i = tid; i < NP * NP; i += 512) Gs[T::at(i / NP, i % NP)] = Gpad[i];
     const long nn = (long)n * n;
     constexpr int PER = (NP * NP + 511) / 512;
     double pre[PER];
@@ -1061,31 +1228,54 @@ __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ 
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k;
-            if (i < NP * NP) Ys[(i / NP) * LD + i % NP] = pre[k];
+            if (i < NP * NP) Ys[T::at(i / NP, i % NP)] = pre[k];
         }
         if (img + gridDim.x < nimg) load_img(img + gridDim.x);
         __syncthreads();
         d4 a1[TPW], a2[TPW];
 #pragma unroll
         for (int q = 0; q < TPW; ++q) a1[q] = a2[q] = d4{0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < kp; k0 += 4) {
+        mfma_kloop<H, DB, Buf>(kpad, [&](int k0, Buf& x) {
 #pragma unroll
-            for (int q = 0; q < TPW; ++q) {
-                const int tq = wave + 8 * q;
-                if (tq < NTILE) {
-                    const int ti = tq / NT16, tj = tq % NT16;
-                    a1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Ys[(ti * 16 + lr) * LD + k0 + lk],
-                                                                 Gs[(k0 + lk) * LD + tj * 16 + lr], a1[q], 0, 0, 0);
-                    a2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(Gs[(ti * 16 + lr) * LD + k0 + lk],
-                                                                 Ys[(k0 + lk) * LD + tj * 16 + lr], a2[q], 0, 0, 0);
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    const int k = k0 + 4 * h + lk;
+                    x.o[h][0][q] = Ys[T::at(ti[q] * 16 + lr, k)];
+                    x.o[h][1][q] = Gs[T::at(k, tj[q] * 16 + lr)];
+                    x.o[h][2][q] = Gs[T::at(ti[q] * 16 + lr, k)];
+                    x.o[h][3][q] = Ys[T::at(k, tj[q] * 16 + lr)];
                 }
-            }
-        }
+        }, [&](const Buf& x) {
+#pragma unroll
+            for (int h = 0; h < H; ++h)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    a1[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.o[h][0][q], x.o[h][1][q], a1[q], 0, 0, 0);
+                    a2[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.o[h][2][q], x.o[h][3][q], a2[q], 0, 0, 0);
+                }
+        });
         // padded rows and columns of both products are zero
 #pragma unroll
         for (int q = 0; q < TPW; ++q)
+            if (own[q])
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) ssq += a1[q][rr] * a2[q][rr];
+                for (int rr = 0; rr < 4; ++rr) ssq += a1[q][rr] * a2[q][rr];
+        double e1 = 0.0, e2 = 0.0;
+        if (edge) {
+            for (int k0 = 4 * epart; k0 < kp; k0 += 4 * eg) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    e1 += Ys[T::at(ei, k0 + kk)] * Gs[T::at(k0 + kk, ej)];
+                    e2 += Gs[T::at(ei, k0 + kk)] * Ys[T::at(k0 + kk, ej)];
+                }
+            }
+        }
+        if (CORE) {
+            e1 = xform2d_edge_sum(e1, eg);
+            e2 = xform2d_edge_sum(e2, eg);
+            if (edge && epart == 0) ssq += e1 * e2;
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
@@ -1100,8 +1290,11 @@ __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ 
     }
 }
 
-// one block: out[0] = sum of the per-block partial sums (fixed order)
-__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out) {
+// one block: out[0] = sum of the per-block partial sums (fixed order), also
+// stored to out_host (device address of mapped, coherent pinned host
+// memory) when given, which the host reads once the stream has passed
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out,
+                                                      double* out_host) {
     __shared__ double sh[256];
     double s = 0.0;
     for (int i = threadIdx.x; i < count; i += 256) s += partial[i];
@@ -1111,38 +1304,52 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = sh[0];
+    if (threadIdx.x == 0) {
+        out[0] = sh[0];
+        if (out_host) *out_host = sh[0];
+    }
 }
 
-template <int NT16>
-static hipError_t gram_norm2d_launch(const double* in, const double* Gpad, int n, long nimg, double* partial,
-                                     int max_blocks, double* out, hipStream_t st) {
-    constexpr int NP = NT16 * 16;
-    const size_t shm = sizeof(double) * 2 * (size_t)NP * (NP + 1);
+template <int NT16, bool CORE>
+static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, long nimg, double* partial,
+                                 int max_blocks, double* out, double* out_host, hipStream_t st) {
+    const size_t shm = sizeof(double) * 2 * (size_t)TileLds<double, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_gram_norm2d<NT16>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_gram_norm2d<NT16, CORE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const long blocks = persistent_blocks(shm, nimg);
     if (blocks > max_blocks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_gram_norm2d<NT16>, dim3((unsigned)blocks), dim3(512), shm, st, in, Gpad, n, nimg, partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
+    hipLaunchKernelGGL((k_gram_norm2d<NT16, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, Gpad, n, nimg,
+                       partial);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host);
     return hipGetLastError();
 }
 
+template <int NT16>
+static hipError_t gram_norm2d_launch(const double* in, const double* Gpad, int n, long nimg, double* partial,
+                                     int max_blocks, double* out, double* out_host, hipStream_t st) {
+    if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
+    if constexpr (kXform2dEdge<NT16>) {
+        if (xform2d_core_tiles<NT16>(n) < NT16)
+            return gram_norm2d_go<NT16, true>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+    }
+    return gram_norm2d_go<NT16, false>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+}
+
 hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
-                              int max_blocks, double* out, hipStream_t st) {
+                              int max_blocks, double* out, double* out_host, hipStream_t st) {
     if (nimg <= 0 || !xform2d_supported(np)) return hipErrorInvalidValue;
     switch (np / 16) {
-        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, st);
-        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, st);
-        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, st);
-        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, st);
-        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, st);
-        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, st);
+        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1619,6 +1826,183 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Close of a cycle on the finest level followed by the start of the next
+// one, for one spatial mode and a chain of `chain` consecutive slabs (chain
+// even, starting at an even slab), in one pass over f^, the pre-smoothed
+// iterate u^ and the coarse correction ec:
+//   u1 = u^ + (P_t (x) I) ec                       (prolongation)
+//   u2 = u1 + omega A^{-1} r(u1)  -> uend          (post-smoothing step)
+//   ||r(u2)||^2 summed per block into partial[blockIdx.x] (fixed order)
+//   u3 = u2 + omega A^{-1} r(u2)  -> unext         (next pre-smoothing step)
+//   fc = (P_t^T (x) I)[r(u3)_{2k}; r(u3)_{2k+1}]   (restriction)
+// The residuals after a smoothing step follow from the identity
+// r(u + omega A^{-1} g)_s = (1 - omega) g_s + e_1 (delta of the coupling row
+// of slab s-1), so every slab needs two slab solves.  The coupling rows of
+// the previous slab (u1, u2, u3) are carried along the chain; a chain after
+// slab 0 first repeats the two steps of its two preceding slabs.
+template <int NT>
+__device__ __forceinline__ void prolong_add(const Transfer& tr, int h, const double* c, double* u) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) v += tr.P[(h * NT + t) * kNt + k] * c[k];
+        u[t] += v;
+    }
+}
+
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                         const double* __restrict__ mu1, int n, long Nx,
+                                                         const double* __restrict__ fh,
+                                                         const double* __restrict__ upre,
+                                                         const double* __restrict__ ec, double* __restrict__ uend,
+                                                         double* __restrict__ unext, double* __restrict__ fc,
+                                                         Transfer tr, double omega, int chain, long total,
+                                                         double* __restrict__ partial) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double ssq = 0.0;
+    if (idx < total) {
+        const long q = idx / Nx, m = idx % Nx;
+        const double mu = mode_shift(dim, mu1, n, m);
+        const long s0 = q * chain;
+        const long slab = (long)NT * Nx;
+        // coupling rows of slab s0 - 1: u1, u2 and u3
+        double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        if (s0 > 0) {
+            // slab s0 - 2 (even, so the first half of coarse slab s0/2 - 1),
+            // with the coupling row of slab s0 - 3 from u^ and ec
+            double c[NT], u1[NT], g[NT], z[NT];
+            const long sa = s0 - 2, ba = sa * slab + m, bc = (sa / 2) * slab + m;
+#pragma unroll
+            for (int k = 0; k < NT; ++k) c[k] = ec[bc + (long)k * Nx];
+            double q1 = 0.0;
+            if (sa > 0) {
+                const long bp = (sa - 1) * slab + m, bpc = ((sa - 1) / 2) * slab + m;
+                double v = upre[bp + (long)(NT - 1) * Nx];
+#pragma unroll
+                for (int k = 0; k < NT; ++k) v += tr.P[(NT + NT - 1) * kNt + k] * ec[bpc + (long)k * Nx];
+                q1 = v;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u1[t] = upre[ba + (long)t * Nx];
+                g[t] = fh[ba + (long)t * Nx];
+            }
+            prolong_add<NT>(tr, 0, c, u1);
+            eig_residual_point<NT>(ktmt, mu, u1, q1, g);
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            const double a1 = u1[NT - 1], a2 = u1[NT - 1] + omega * z[NT - 1];
+            // slab s0 - 1 (second half of the same coarse slab): both steps
+            const long bb = (s0 - 1) * slab + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u1[t] = upre[bb + (long)t * Nx];
+                g[t] = fh[bb + (long)t * Nx];
+            }
+            prolong_add<NT>(tr, 1, c, u1);
+            eig_residual_point<NT>(ktmt, mu, u1, a1, g);
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            double u2[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u2[t] = u1[t] + omega * z[t];
+                g[t] *= (1.0 - omega);
+            }
+            g[0] += up_prev_delta(a2, a1);
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            p1 = u1[NT - 1];
+            p2 = u2[NT - 1];
+            p3 = u2[NT - 1] + omega * z[NT - 1];
+        }
+        // the next slab's f^ and u^ (and the next pair's ec) are loaded while
+        // the current one is processed
+        double fnx[NT], unx[NT], cnx[NT], c[NT], acc[NT];
+        {
+            const long b = s0 * slab + m, bc = (s0 / 2) * slab + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                fnx[t] = fh[b + (long)t * Nx];
+                unx[t] = upre[b + (long)t * Nx];
+                cnx[t] = ec[bc + (long)t * Nx];
+            }
+        }
+#pragma unroll 1
+        for (int k = 0; k < chain; ++k) {
+            const int h = k & 1;
+            const long b = (s0 + k) * slab + m;
+            double g[NT], u1[NT], u2[NT], z[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                g[t] = fnx[t];
+                u1[t] = unx[t];
+            }
+            if (h == 0) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) c[t] = cnx[t];
+            }
+            if (k + 1 < chain) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    fnx[t] = fh[b + slab + (long)t * Nx];
+                    unx[t] = upre[b + slab + (long)t * Nx];
+                }
+                if (h == 1) {
+                    const long bc = ((s0 + k + 1) / 2) * slab + m;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) cnx[t] = ec[bc + (long)t * Nx];
+                }
+            }
+            // post-smoothing step from the prolonged iterate
+            prolong_add<NT>(tr, h, c, u1);
+            eig_residual_point<NT>(ktmt, mu, u1, p1, g);
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u2[t] = u1[t] + omega * z[t];
+                uend[b + (long)t * Nx] = u2[t];
+                g[t] *= (1.0 - omega);
+            }
+            g[0] += up_prev_delta(p2, p1);
+            // residual of the cycle's result, then the next smoothing step
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ssq += g[t] * g[t];
+            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            double u3last = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double u3 = u2[t] + omega * z[t];
+                unext[b + (long)t * Nx] = u3;
+                if (t == NT - 1) u3last = u3;
+                g[t] *= (1.0 - omega);
+            }
+            g[0] += up_prev_delta(p3, p2);
+            if (h == 0) {
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) acc[cc] = 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) acc[cc] += tr.P[(h * NT + t) * kNt + cc] * g[t];
+            if (h == 1) {
+                const long mc = (s0 + k) / 2;
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) fc[mc * slab + m + (long)cc * Nx] = acc[cc];
+            }
+            p1 = u1[NT - 1];
+            p2 = u2[NT - 1];
+            p3 = u3last;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ssq;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 // Descent on a coarse level with a zero initial guess and one pre-smoothing
 // step, for one spatial mode and a chain of `chain` slabs (chain even,
 // starting at an even slab): u' = omega A^{-1} f (into uout) and the
@@ -1917,7 +2301,7 @@ hipError_t launch_rhs(int dim, int Nt, int n, int n_modes, const double* Tpart, 
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, double* partial, long max_partial, double* out,
-                                hipStream_t st) {
+                                double* out_host, hipStream_t st) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
@@ -1938,7 +2322,37 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
 #undef STH_CE_CASE
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host);
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                  const double* fh, const double* upre, const double* ec, double* uend,
+                                  double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
+                                  double* partial, long max_partial, double* out, double* out_host,
+                                  hipStream_t st) {
+    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_CC_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (tm.schur)                                                                                     \
+                hipLaunchKernelGGL((k_eig_cycle_close<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,  \
+                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, partial);   \
+            else                                                                                              \
+                hipLaunchKernelGGL((k_eig_cycle_close<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, \
+                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, partial);   \
+            break;
+        STH_CC_CASE(2) STH_CC_CASE(3) STH_CC_CASE(4) STH_CC_CASE(5) STH_CC_CASE(6) STH_CC_CASE(7) STH_CC_CASE(8)
+#undef STH_CC_CASE
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host);
     return hipGetLastError();
 }
 

@@ -79,6 +79,16 @@ hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* k
 //  `chain` slabs per thread, chain even and dividing S): out[0] = ||fh - L uin||^2,
 //  uout = uin + omega A^{-1}(fh - L uin), fc = (P^T (x) I)(fh - L uout) on slab
 //  pairs; partial needs max_partial >= ceil((S/chain) Nx / 256) entries
+//  close of a cycle on the finest level and start of the next in one pass
+//  (chains as above): u1 = upre + (P_t (x) I) ec, uend = u1 + omega
+//  A^{-1}(fh - L u1) (the cycle's result), ||fh - L uend||^2 to out[0] (and
+//  out_host if not null), unext = uend + omega A^{-1}(fh - L uend), fc =
+//  (P^T (x) I)(fh - L unext) on slab pairs; the three iterate buffers differ
+hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                  const double* fh, const double* upre, const double* ec, double* uend,
+                                  double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
+                                  double* partial, long max_partial, double* out, double* out_host,
+                                  hipStream_t st);
 //  descent on a coarse level from a zero guess, one pass over fl (chains as
 //  above): uout = omega A^{-1} fl, fc = (P^T (x) I)(fl - L uout) on slab pairs
 hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
@@ -87,7 +97,7 @@ hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktm
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, double* partial, long max_partial, double* out,
-                                hipStream_t st);
+                                double* out_host, hipStream_t st);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);
@@ -99,9 +109,10 @@ hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const 
 //  out[0] = sum over the nimg n x n images Y of ||C Y C^T||_F^2 (2-D, np <= 96),
 //  the squared B-spline norm of an eigenbasis vector without forming it,
 //  computed as <Y G, G Y>_F with Gpad = C^T C (np x np, zero padded); partial
-//  needs max_blocks entries
+//  needs max_blocks entries; the sum also goes to out_host (mapped pinned host
+//  memory) if not null
 hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
-                              int max_blocks, double* out, hipStream_t st);
+                              int max_blocks, double* out, double* out_host, hipStream_t st);
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,

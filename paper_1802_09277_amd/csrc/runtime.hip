@@ -84,7 +84,8 @@ struct sth_handle {
     double* buf1 = nullptr;
     double* partial = nullptr;
     double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side, [2] eigenbasis residual
-    double* hnorm = nullptr;            // pinned host copies of dnorm
+    double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
+    double* hnorm_dev = nullptr;        // device address of hnorm
     // timing
     bool timing = false;
     unsigned timing_mask = 0;
@@ -481,14 +482,17 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         Timed tm(h, STH_K_EIG_CYCLE_END, dof * (12.0 * Nt + 10.0), 28.0 * dof, st);
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, 1 - c), eig_f(h, 1), h->tr, h->omega, S,
-                                    chain_length(h, S, 65536), h->cpartial, h->n_cpartial, h->dnorm + 2, st));
+                                    chain_length(h, S, 65536), h->cpartial, h->n_cpartial, h->dnorm + 2,
+                                    h->hnorm_dev + 2, st));
         h->presmoothed = true;
-    } else {
-        {
-            Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
-            HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c),
-                                       h->buf0, S, st));
-        }
+        return STH_OK;                  // the pass stored hnorm[2] itself
+    }
+    {
+        Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
+        HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, c),
+                                   h->buf0, S, st));
+    }
+    {
         Timed tm(h, STH_K_NORM, 2.0 * dof, 8.0 * dof, st);
         HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + 2, st));
     }
@@ -514,8 +518,11 @@ static int eig_exact_norm(sth_handle* h, hipStream_t st) {
     if (h->dim == 2 && xform2d_supported(h->np)) {
         // ||C r^ C^T||^2 per image as <r^ G, G r^> (G = C^T C), r not formed
         Timed tm(h, STH_K_RESNORM, dof * 4.0 * h->n, dof * 8.0, st);
-        HIPCHK(launch_gram_norm2d(h->buf0, h->Gf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm, st));
-    } else if (h->dim == 2) {
+        HIPCHK(launch_gram_norm2d(h->buf0, h->Gf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm,
+                                  h->hnorm_dev, st));
+        return STH_OK;                  // stored hnorm[0] itself
+    }
+    if (h->dim == 2) {
         // per-axis transforms buf0 -> buf1 -> buf0
         if ((rc = spatial_apply(h, INV_C, h->buf0, h->buf0, rows, h->buf1, st))) return rc;
         if ((rc = norm2_dev(h, h->buf0, len, st))) return rc;
@@ -751,8 +758,11 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 return cleanup(STH_EHIP, "upload of the setup failed");
         }
     }
-    if (hipHostMalloc((void**)&h->hnorm, 3 * sizeof(double), 0) != hipSuccess)
+    if (hipHostMalloc((void**)&h->hnorm, 3 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
+    if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess)
+        return cleanup(STH_EHIP, "pinned host memory is not mapped");
     if (hipMemcpyAsync(h->Tf, Tf.data(), Tf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->Ti, Ti.data(), Ti.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->mu1, h->S.mu.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess ||

@@ -298,3 +298,42 @@ def test_schur_solve_matches_direct(name, basis):
     print(f"  schur/{basis}: {it} cycles (oracle {it_o}), relres {rr:.2e}")
     assert rr <= 1e-12 and abs(it - it_o) <= 1
     assert np.linalg.norm(host(u) - ud) <= 1e-10 * np.linalg.norm(ud)
+
+
+# ---------------------------------------------------------------------------
+# Image sizes at the tile boundaries of the LDS-resident 2-D transforms and
+# of the Gram-matrix residual norm: n = 33 and 50 (rows and columns past the
+# last whole MFMA tile done as dot products), 64 and 80 (whole tiles), 82
+# (six tiles per axis, no dot products).  One slab inverse in both bases and
+# an eigenbasis solve against the direct solution.
+# ---------------------------------------------------------------------------
+TILE_SHAPES = {f"2d_n{ne + p - 2}": dict(dim=2, n_elem=ne, degree=p, n_slabs=2, n_elem_t=1)
+               for ne, p in ((33, 2), (50, 2), (64, 2), (80, 2), (82, 2))}
+
+
+@functools.lru_cache(maxsize=None)
+def tile_oracle(name):
+    prob = OProblem(**TILE_SHAPES[name])
+    return prob, MultigridOracle(prob, coarse_slabs=1)
+
+
+@pytest.mark.parametrize("name", list(TILE_SHAPES))
+def test_transform_tile_boundaries(name):
+    import paper_1802_09277_amd as sth
+    print(f"[gpu-parity] tile boundaries shape={name} {TILE_SHAPES[name]}", flush=True)
+    prob, mg = tile_oracle(name)
+    r = W.random_vector(22, prob.n_dof)
+    zo = mg.levels[0].slab_solve(r)
+    f = assemble_rhs(prob, W.random_modes(21, prob.dim))
+    ud = mg.levels[0].forward_substitution(f)
+    for basis in ("nodal", "eigen"):
+        s = sth.Solver(**TILE_SHAPES[name], basis=basis, coarse_slabs=1)
+        z = s.new_vector()
+        s.block_solve(dev(r), z)
+        assert rel_max(host(z), zo) <= 1e-11, basis
+        u = s.new_vector()
+        it, rr, _ = s.solve(dev(f), u, rtol=1e-12, maxit=60)
+        print(f"  {basis}: {it} cycles, relres {rr:.2e}")
+        assert rr <= 1e-12
+        assert np.linalg.norm(host(u) - ud) <= 1e-10 * np.linalg.norm(ud), basis
+        s.close()

@@ -99,3 +99,21 @@ def test_mg_iteration_counts_flat_in_h_and_slabs():
     print(counts)
     assert max(counts.values()) - min(counts.values()) <= 2
     assert max(counts.values()) <= 15
+
+
+def test_mg_iteration_counts_flat_down_to_small_tau_over_h2():
+    """Time-only coarsening keeps its count where the slab width is small next
+    to the squared mesh size: tau/h^2 from 8 down to 1/16 (the serving mix
+    reaches 2).  The space-time multigrid of Section 3.1 also coarsens in
+    space; these counts show that the time-only hierarchy does not need it
+    on these shapes (Section 4.4, Table 4: counts independent of the number of
+    slabs)."""
+    counts = {}
+    for ne, S in ((8, 8), (8, 64), (8, 128), (4, 64), (4, 256)):
+        prob = Problem(dim=2, n_elem=ne, degree=2, n_slabs=S, n_elem_t=2)
+        f = assemble_rhs(prob, W.random_modes(1, 2))
+        _, it, _ = MultigridOracle(prob).solve(f, rtol=1e-8)
+        counts[ne * ne / S] = it
+    print(counts)
+    assert max(counts.values()) - min(counts.values()) <= 2
+    assert max(counts.values()) <= 15
