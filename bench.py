@@ -34,7 +34,8 @@ PEAKS = {  # MI355X published peaks
 # dominant-class roofline: which bound applies to each kernel class
 CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "timemix": "hbm",
                "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma",
-               "eig_smooth": "hbm", "eig_resid": "hbm", "resnorm": "mfma", "eig_cycle_end": "hbm"}
+               "eig_smooth": "hbm", "eig_resid": "hbm", "resnorm": "mfma", "eig_cycle_end": "hbm",
+               "eig_cycle_close": "hbm"}
 
 
 def log(*a):

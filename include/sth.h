@@ -225,6 +225,11 @@ typedef struct {
     int schur;          /* 1: real Schur form, V = Q, W = Q^T M_t^{-1} and
                            W K_t V = R (quasi upper triangular, copied to R) */
     double* R;          /* N_t*N_t, may be NULL */
+    double* mode_weights; /* 2n, may be NULL: per 1-D spatial mode j, G_jj and
+                           sum_k |G_jk| of G = C^T C, C = M1 U (interleaved);
+                           the eigenbasis solve bounds the B-spline residual
+                           norm below by sum_m (2 prod G_jj - prod sum_k |G_jk|)
+                           |r^_m|^2 over the modes m = (j_x, j_y[, j_z]) */
 } sth_factors;
 int sth_host_factors(const sth_problem* p, int level, sth_factors* out);
 
@@ -246,7 +251,9 @@ typedef enum {
     STH_K_RESNORM = 11,     /* eigenbasis iteration: residual mapped to B-splines, sum of squares */
     STH_K_EIG_CYCLE_END = 12, /* eigenbasis iteration: residual norm, next smoothing step and
                                restriction in one pass on the finest level */
-    STH_K_COUNT = 13
+    STH_K_EIG_CYCLE_CLOSE = 13, /* the same pass preceded by the prolongation and the
+                                 post-smoothing step of the finest level */
+    STH_K_COUNT = 14
 } sth_kernel_class;
 
 /* Record an event pair around every launch of the kernel classes whose bit

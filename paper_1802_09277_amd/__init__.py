@@ -19,7 +19,7 @@ STATUS = {0: "STH_OK", -1: "STH_EINVAL", -2: "STH_ENOMEM", -3: "STH_EHIP", -4: "
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KCLASS = {"residual": 0, "xform_x": 1, "xform_s": 2, "timemix": 3, "restrict": 4, "prolong": 5,
           "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10, "resnorm": 11,
-          "eig_cycle_end": 12}
+          "eig_cycle_end": 12, "eig_cycle_close": 13}
 
 
 class StatusError(RuntimeError):
@@ -57,7 +57,8 @@ class Factors(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("N_t", ctypes.c_int), ("n_levels", ctypes.c_int),
                 ("cond_V", ctypes.c_double)] + [(nm, _DP) for nm in
                                                 ("M1", "K1", "U", "mu", "Kt", "Mt", "Pt", "V", "W",
-                                                 "eig_re", "eig_im")] + [("schur", ctypes.c_int), ("R", _DP)]
+                                                 "eig_re", "eig_im")] + [("schur", ctypes.c_int), ("R", _DP),
+                                                                         ("mode_weights", _DP)]
 
 
 _lib = None
@@ -154,7 +155,8 @@ def host_factors(level=0, **kw):
     n = kw["n_elem"] + kw["degree"] - 2
     Nt = kw["n_elem_t"] + kw["degree"]
     arrs = {"M1": (n, n), "K1": (n, n), "U": (n, n), "mu": (n,), "Kt": (Nt, Nt), "Mt": (Nt, Nt),
-            "Pt": (2 * Nt, Nt), "V": (Nt, Nt), "W": (Nt, Nt), "eig_re": (Nt,), "eig_im": (Nt,), "R": (Nt, Nt)}
+            "Pt": (2 * Nt, Nt), "V": (Nt, Nt), "W": (Nt, Nt), "eig_re": (Nt,), "eig_im": (Nt,), "R": (Nt, Nt),
+            "mode_weights": (n, 2)}
     buf = {k: np.zeros(s) for k, s in arrs.items()}
     f = Factors()
     for k, a in buf.items():

@@ -1294,19 +1294,57 @@ __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ 
 // stored to out_host (device address of mapped, coherent pinned host
 // memory) when given, which the host reads once the stream has passed
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out,
-                                                      double* out_host) {
+                                                      double* out_host, int nsum = 1) {
     __shared__ double sh[256];
-    double s = 0.0;
-    for (int i = threadIdx.x; i < count; i += 256) s += partial[i];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    for (int j = 0; j < nsum; ++j) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < count; i += 256) s += partial[(long)j * count + i];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            out[j] = sh[0];
+            if (out_host) out_host[j] = sh[0];
+        }
         __syncthreads();
     }
+}
+
+// Weight v of a spatial mode in the lower bound of the B-spline residual norm
+// (vw: per axis and 1-D mode, the diagonal entry d and the absolute row sum a
+// of G = C^T C; v = 2 prod d - prod a over the axes)
+__device__ __forceinline__ double mode_weight(int dim, const double* __restrict__ vw, int n, long m) {
+    const int jx = (int)(m % n);
+    const long rest = m / n;
+    const int jy = (int)(rest % n);
+    double d = vw[2 * jx] * vw[2 * jy], a = vw[2 * jx + 1] * vw[2 * jy + 1];
+    if (dim == 3) {
+        const int jz = (int)(rest / n);
+        d *= vw[2 * jz];
+        a *= vw[2 * jz + 1];
+    }
+    return 2.0 * d - a;
+}
+
+// block sums of two per-thread values into partial[b] and partial[nb + b]
+__device__ __forceinline__ void block_sum2(double x, double y, double* __restrict__ partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_xor(x, off);
+        y += __shfl_xor(y, off);
+    }
+    __shared__ double red[8];
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = x;
+        red[4 + (threadIdx.x >> 6)] = y;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        out[0] = sh[0];
-        if (out_host) *out_host = sh[0];
+        partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+        partial[gridDim.x + blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
     }
 }
 
@@ -1737,12 +1775,14 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                                                        const double* __restrict__ fh, const double* __restrict__ uin,
                                                        double* __restrict__ uout, double* __restrict__ fc,
                                                        Transfer tr, double omega, int chain, long total,
+                                                       const double* __restrict__ vw,
                                                        double* __restrict__ partial) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    double ssq = 0.0;
+    double ssq = 0.0, wsq = 0.0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const double mu = mode_shift(dim, mu1, n, m);
+        const double wm = mode_weight(dim, vw, n, m);
         const long s0 = q * chain;
         double prev_old = 0.0, prev_new = 0.0;
         if (s0 > 0) {
@@ -1787,8 +1827,11 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                 }
             }
             eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
+            double s2 = 0.0;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) ssq += g[t] * g[t];
+            for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
+            ssq += s2;
+            wsq += wm * s2;
             shifted_solve<NT, SCHUR>(tm, mu, g, z);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -1817,13 +1860,8 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
             prev_new = up[NT - 1];
         }
     }
-    // block sum: butterfly within each wave, then the four wave sums in order
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ssq;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    // block sums (fixed order) of ||r^||^2 and its weighted form
+    block_sum2(ssq, wsq, partial);
 }
 
 // Close of a cycle on the finest level followed by the start of the next
@@ -1859,12 +1897,14 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
                                                          const double* __restrict__ ec, double* __restrict__ uend,
                                                          double* __restrict__ unext, double* __restrict__ fc,
                                                          Transfer tr, double omega, int chain, long total,
+                                                         const double* __restrict__ vw,
                                                          double* __restrict__ partial) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    double ssq = 0.0;
+    double ssq = 0.0, wsq = 0.0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const double mu = mode_shift(dim, mu1, n, m);
+        const double wm = mode_weight(dim, vw, n, m);
         const long s0 = q * chain;
         const long slab = (long)NT * Nx;
         // coupling rows of slab s0 - 1: u1, u2 and u3
@@ -1965,8 +2005,11 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             }
             g[0] += up_prev_delta(p2, p1);
             // residual of the cycle's result, then the next smoothing step
+            double s2 = 0.0;
 #pragma unroll
-            for (int t = 0; t < NT; ++t) ssq += g[t] * g[t];
+            for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
+            ssq += s2;
+            wsq += wm * s2;
             shifted_solve<NT, SCHUR>(tm, mu, g, z);
             double u3last = 0.0;
 #pragma unroll
@@ -1995,12 +2038,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             p3 = u3last;
         }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
-    __shared__ double red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ssq;
-    __syncthreads();
-    if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    block_sum2(ssq, wsq, partial);
 }
 
 // Descent on a coarse level with a zero initial guess and one pre-smoothing
@@ -2300,59 +2338,61 @@ hipError_t launch_rhs(int dim, int Nt, int n, int n_modes, const double* Tpart, 
 
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
-                                double omega, long S, int chain, double* partial, long max_partial, double* out,
-                                double* out_host, hipStream_t st) {
+                                double omega, long S, int chain, const double* vw, double* partial,
+                                long max_partial, double* out, double* out_host, hipStream_t st) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
-    if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
-    if (blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks);
     switch (Nt) {
 #define STH_CE_CASE(NTV)                                                                                     \
         case NTV:                                                                                             \
             if (tm.schur)                                                                                     \
                 hipLaunchKernelGGL((k_eig_cycle_end<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, \
-                                   Nx, fh, uin, uout, fc, tr, omega, chain, total, partial);                  \
+                                   Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);              \
             else                                                                                              \
                 hipLaunchKernelGGL((k_eig_cycle_end<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,   \
-                                   n, Nx, fh, uin, uout, fc, tr, omega, chain, total, partial);               \
+                                   n, Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);           \
             break;
         STH_CE_CASE(2) STH_CE_CASE(3) STH_CE_CASE(4) STH_CE_CASE(5) STH_CE_CASE(6) STH_CE_CASE(7) STH_CE_CASE(8)
 #undef STH_CE_CASE
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2);
     return hipGetLastError();
 }
 
 hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                   const double* fh, const double* upre, const double* ec, double* uend,
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
-                                  double* partial, long max_partial, double* out, double* out_host,
-                                  hipStream_t st) {
+                                  const double* vw, double* partial, long max_partial, double* out,
+                                  double* out_host, hipStream_t st) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
-    if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
-    if (blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks);
     switch (Nt) {
 #define STH_CC_CASE(NTV)                                                                                     \
         case NTV:                                                                                             \
             if (tm.schur)                                                                                     \
                 hipLaunchKernelGGL((k_eig_cycle_close<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,  \
-                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, partial);   \
+                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
+                                   partial);                                                                  \
             else                                                                                              \
                 hipLaunchKernelGGL((k_eig_cycle_close<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, \
-                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, partial);   \
+                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
+                                   partial);                                                                  \
             break;
         STH_CC_CASE(2) STH_CC_CASE(3) STH_CC_CASE(4) STH_CC_CASE(5) STH_CC_CASE(6) STH_CC_CASE(7) STH_CC_CASE(8)
 #undef STH_CC_CASE
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2);
     return hipGetLastError();
 }
 

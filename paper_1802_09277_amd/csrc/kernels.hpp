@@ -75,29 +75,33 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
                              bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st);
-//  end of a cycle on the finest level, in one pass over f^ and u^ (chains of
-//  `chain` slabs per thread, chain even and dividing S): out[0] = ||fh - L uin||^2,
-//  uout = uin + omega A^{-1}(fh - L uin), fc = (P^T (x) I)(fh - L uout) on slab
-//  pairs; partial needs max_partial >= ceil((S/chain) Nx / 256) entries
+//  descent on a coarse level from a zero guess, one pass over fl (chains of
+//  `chain` slabs per thread, chain even and dividing S): uout = omega A^{-1} fl,
+//  fc = (P^T (x) I)(fl - L uout) on slab pairs
+hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
+                           int chain, hipStream_t st);
+//  end of a cycle on the finest level, in one pass over f^ and u^ (chains as
+//  above): ||fh - L uin||^2 and its mode-weighted form sum_m v_m |r_m|^2
+//  (weights from the per-axis table vw of the diagonal entries and absolute
+//  row sums of G = C^T C) to out[0..1], and to out_host[0..1] (mapped pinned
+//  host memory) if not null; uout = uin + omega A^{-1}(fh - L uin),
+//  fc = (P^T (x) I)(fh - L uout) on slab pairs.  partial needs
+//  max_partial >= 2 ceil((S/chain) Nx / 256) entries
+hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
+                                double omega, long S, int chain, const double* vw, double* partial,
+                                long max_partial, double* out, double* out_host, hipStream_t st);
 //  close of a cycle on the finest level and start of the next in one pass
-//  (chains as above): u1 = upre + (P_t (x) I) ec, uend = u1 + omega
-//  A^{-1}(fh - L u1) (the cycle's result), ||fh - L uend||^2 to out[0] (and
-//  out_host if not null), unext = uend + omega A^{-1}(fh - L uend), fc =
+//  (chains and sums as above): u1 = upre + (P_t (x) I) ec, uend = u1 +
+//  omega A^{-1}(fh - L u1) (the cycle's result), the two sums of
+//  fh - L uend, unext = uend + omega A^{-1}(fh - L uend), fc =
 //  (P^T (x) I)(fh - L unext) on slab pairs; the three iterate buffers differ
 hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                   const double* fh, const double* upre, const double* ec, double* uend,
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
-                                  double* partial, long max_partial, double* out, double* out_host,
-                                  hipStream_t st);
-//  descent on a coarse level from a zero guess, one pass over fl (chains as
-//  above): uout = omega A^{-1} fl, fc = (P^T (x) I)(fl - L uout) on slab pairs
-hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
-                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
-                           int chain, hipStream_t st);
-hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
-                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
-                                double omega, long S, int chain, double* partial, long max_partial, double* out,
-                                double* out_host, hipStream_t st);
+                                  const double* vw, double* partial, long max_partial, double* out,
+                                  double* out_host, hipStream_t st);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);

@@ -66,9 +66,14 @@ struct sth_handle {
     double* e0 = nullptr;               // f^ on level 0
     double* e1 = nullptr;               // u^ on level 0 (ping-pong with e2)
     double* e2 = nullptr;
+    double* e3 = nullptr;               // third level-0 iterate buffer of the fused cycle close
+    bool fuse_close = false;            // post-smoothing of level 0 fused into the cycle-end pass
+    bool defer_close = false;           // set by a solve iteration: level 0 leaves its post-smoothing
+    const double* pending_ec = nullptr; // coarse correction waiting for the fused cycle close
+    int pre_idx = 1;                    // level-0 buffer of the pre-smoothed iterate
     std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
     std::vector<int> ecur;              // which buffer of the pair holds u^ per level
-    bool presmoothed = false;           // the other level-0 buffer holds u^ after one smoothing step
+    bool presmoothed = false;           // level-0 buffer pre_idx holds u^ after one smoothing step
                                         // and lf[1] the restriction of its residual
     double* cpartial = nullptr;         // per-block partial sums of the cycle-end pass
     long n_cpartial = 0;
@@ -80,10 +85,13 @@ struct sth_handle {
     double* kpart = nullptr;            // 1024 x kMaxKrylov partial sums
     double* khost = nullptr;            // pinned copy of kc
     double nb_lo = 0.0;                 // ||(I (x) C) r^||^2 >= nb_lo ||r^||^2
+    double* vw = nullptr;               // per axis and 1-D mode: G_jj and sum_k |G_jk| (G = C^T C)
+    bool wsum_valid = false;            // hnorm[3] holds the mode-weighted residual sum
     double* buf0 = nullptr;
     double* buf1 = nullptr;
     double* partial = nullptr;
-    double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side, [2] eigenbasis residual
+    double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side, [2] eigenbasis
+                                        // residual, [3] its mode-weighted sum
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
     double* hnorm_dev = nullptr;        // device address of hnorm
     // timing
@@ -98,15 +106,25 @@ struct sth_handle {
     // graph of one solve iteration (V-cycle, residual, norm, scalar read)
     bool use_graph = true;
     bool capturing = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    const double* gf = nullptr;
-    double* gu = nullptr;
-    unsigned gmask = 0;
+    // two cached graphs: the fused cycle close alternates its level-0
+    // buffers, so consecutive iterations start from two different states
+    struct GraphEntry {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        const double* f = nullptr;
+        double* u = nullptr;
+        unsigned mask = 0;
+        int key = -1;                   // level-0 buffer state at entry
+        int ecur0_after = 0, pre_after = 1;
+        bool presm_after = false;
+        std::vector<Rec> recs;          // timed launches inside the graph
+        long last_used = 0;
+    } gent[2];
+    long graph_clock = 0;
+    GraphEntry* glast = nullptr;        // entry of the last replay (its timings)
     bool allow_capture = true;          // cleared by the serving loop while another thread allocates
     bool graph_launched = false;        // the last enqueued iteration was a graph replay
-    int gcur = 0;
-    std::vector<Rec> grecs;
+    std::vector<Rec> grecs;             // timed launches of the graph being captured
     double gms[STH_K_COUNT] = {0}, gfl[STH_K_COUNT] = {0}, gby[STH_K_COUNT] = {0};
     int gcnt[STH_K_COUNT] = {0};
     // state of the solve in progress (sth_solve and the serving loop)
@@ -122,11 +140,15 @@ struct sth_handle {
     } sv;
 };
 
+static void drop_graph_entry(sth_handle::GraphEntry& g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = sth_handle::GraphEntry{};
+}
+
 static void drop_graph(sth_handle* h) {
-    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph) (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    for (auto& g : h->gent) drop_graph_entry(g);
+    h->glast = nullptr;
     h->grecs.clear();
 }
 
@@ -386,7 +408,7 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
 }
 
 static double* eig_u(sth_handle* h, int lvl, int which) {
-    if (lvl == 0) return which ? h->e2 : h->e1;
+    if (lvl == 0) return which == 0 ? h->e1 : (which == 1 ? h->e2 : h->e3);
     return which ? h->lu2[lvl] : h->lu[lvl];
 }
 static double* eig_f(sth_handle* h, int lvl) { return lvl == 0 ? h->e0 : h->lf[lvl]; }
@@ -435,7 +457,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     if (lvl == 0 && h->presmoothed) {
         // the cycle-end pass of the previous cycle (or of the initial
         // residual) took the pre-smoothing step and restricted its residual
-        h->ecur[0] = 1 - h->ecur[0];
+        h->ecur[0] = h->pre_idx;
         h->presmoothed = false;
     } else if (zero_guess && h->nu_pre == 1) {
         // one pass: smoothing step from zero and restriction of its residual
@@ -458,6 +480,11 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     if ((rc = eig_vcycle(h, lvl + 1, true, st))) return rc;
     h->tlev = lvl;
     const double* ec = eig_u(h, lvl + 1, h->ecur[lvl + 1]);
+    if (lvl == 0 && h->defer_close) {
+        // prolongation and post-smoothing go into the fused cycle close
+        h->pending_ec = ec;
+        return STH_OK;
+    }
     if (h->nu_post == 0) return prolong_lvl(h, lvl, ec, eig_u(h, lvl, h->ecur[lvl]), st);
     for (int i = 0; i < h->nu_post; ++i)
         if ((rc = eig_smooth(h, lvl, false, st, i == 0 ? ec : nullptr))) return rc;
@@ -477,13 +504,36 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
     const long len = S * slab_len(h);
     const double dof = (double)len;
     const int c = h->ecur[0];
+    if (h->pending_ec) {
+        // the cycle's prolongation and post-smoothing step, the residual norm
+        // of its result, the next pre-smoothing step and its restriction:
+        // the pre-smoothed iterate is read from buffer c, the result goes to
+        // the buffer that is neither c nor the next pre-smoothed one, so
+        // consecutive cycles alternate between two buffer states
+        const double Nt = h->Nt;
+        const int cur = c == 0 ? 1 : 0, nxt = 3 - c - cur;
+        Timed tm(h, STH_K_EIG_CYCLE_CLOSE, dof * (24.0 * Nt + 20.0), 40.0 * dof, st);
+        HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
+                                      eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
+                                      eig_f(h, 1), h->tr, h->omega, S, chain_length(h, S, 65536), h->vw,
+                                      h->cpartial, h->n_cpartial, h->dnorm + 2, h->hnorm_dev + 2, st));
+        h->pending_ec = nullptr;
+        h->wsum_valid = true;
+        h->ecur[0] = cur;
+        h->pre_idx = nxt;
+        h->presmoothed = true;
+        return STH_OK;
+    }
     if (h->nu_pre == 1 && h->L > 1) {
         const double Nt = h->Nt;
+        const int o = c == 0 ? 1 : 0;   // buffer of the pre-smoothed iterate
         Timed tm(h, STH_K_EIG_CYCLE_END, dof * (12.0 * Nt + 10.0), 28.0 * dof, st);
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
-                                    eig_u(h, 0, c), eig_u(h, 0, 1 - c), eig_f(h, 1), h->tr, h->omega, S,
-                                    chain_length(h, S, 65536), h->cpartial, h->n_cpartial, h->dnorm + 2,
+                                    eig_u(h, 0, c), eig_u(h, 0, o), eig_f(h, 1), h->tr, h->omega, S,
+                                    chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + 2,
                                     h->hnorm_dev + 2, st));
+        h->wsum_valid = true;
+        h->pre_idx = o;
         h->presmoothed = true;
         return STH_OK;                  // the pass stored hnorm[2] itself
     }
@@ -496,6 +546,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         Timed tm(h, STH_K_NORM, 2.0 * dof, 8.0 * dof, st);
         HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + 2, st));
     }
+    h->wsum_valid = false;
     HIPCHK(hipMemcpyAsync(h->hnorm + 2, h->dnorm + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     return STH_OK;
 }
@@ -582,6 +633,13 @@ static size_t level_count(const Problem& q) {
     return L;
 }
 
+// The post-smoothing step of the finest level goes into the cycle-end pass
+// (one more iterate buffer) for V(1,1) cycles in the eigenbasis with a level
+// below and N_t <= 5 (the register budget of the fused pass).
+static bool fused_cycle_close(const Problem& q, size_t levels) {
+    return q.basis == 1 && q.nu_pre == 1 && q.nu_post == 1 && levels > 1 && q.Nt() <= 5;
+}
+
 int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     if (!p || !bytes) return fail(STH_EINVAL, "null argument");
     Problem q = to_problem(p);
@@ -593,12 +651,14 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     size_t total = 0;
     total += 2 * sizeof(double) * np * np;                   // transforms
     total += sizeof(double) * n * (1 + 2 * (2 * q.degree + 1));
-    const size_t vecs0 = q.basis == 1 ? 5 : 2;               // buf0, buf1 (+ f^, u^ pair)
+    const size_t vecs0 = (q.basis == 1 ? 5 : 2) +            // buf0, buf1 (+ f^, u^ pair
+                         (fused_cycle_close(q, level_count(q)) ? 1 : 0);   // and a third u^)
     const size_t vecsl = q.basis == 1 ? 3 : 2;               // u, f (+ u^ partner) per coarse level
     total += vecs0 * sizeof(double) * (size_t)q.n_slabs * slab;
     if (q.basis == 1) {
         total += 3 * sizeof(double) * np * np;                // C, C^T, G
-        total += sizeof(double) * (((size_t)(q.n_slabs / 2) * (size_t)(Nx) + 255) / 256 + 1);   // cycle-end partials
+        total += sizeof(double) * (2 * (((size_t)(q.n_slabs / 2) * (size_t)(Nx) + 255) / 256) + 1);   // cycle-end partials
+        total += sizeof(double) * 2 * n;                                 // mode weights
     }
     long S = q.n_slabs;
     size_t L = level_count(q);
@@ -606,7 +666,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
         S /= 2;
         total += vecsl * sizeof(double) * (size_t)S * slab;
     }
-    total += sizeof(double) * (kNormBlocks + 2 + L * 2 * kNt * kNt);
+    total += sizeof(double) * (kNormBlocks + 4 + L * 2 * kNt * kNt);
     *bytes = total;
     return STH_OK;
 }
@@ -651,6 +711,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     }
     h->L = (int)h->S.levels.size();
     h->nb_lo = std::pow(h->S.m1_min, h->dim);
+    h->fuse_close = fused_cycle_close(q, (size_t)h->L);
     for (auto& lv : h->S.levels) {
         h->lev_S.push_back(lv.S);
         TimeOp op{};
@@ -705,7 +766,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
-        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 3) ||
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 4) ||
         !dalloc(&h->dktmt, (size_t)h->L * 2 * kNt * kNt))
         return cleanup(STH_ENOMEM, "device allocation failed");
     std::vector<double> ktmt((size_t)h->L * 2 * kNt * kNt);
@@ -735,14 +796,20 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 Cf[(size_t)i * np + j] = c;
                 Ci[(size_t)j * np + i] = c;
             }
-        h->n_cpartial = ((q.n_slabs / 2) * h->Nx + 255) / 256;
+        h->n_cpartial = 2 * (((q.n_slabs / 2) * h->Nx + 255) / 256);   // two sums per block
         if (!dalloc(&h->cpartial, (size_t)h->n_cpartial) ||
             !dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
             !dalloc(&h->e0, (size_t)q.n_slabs * slab) || !dalloc(&h->e1, (size_t)q.n_slabs * slab) ||
-            !dalloc(&h->e2, (size_t)q.n_slabs * slab))
+            !dalloc(&h->e2, (size_t)q.n_slabs * slab) ||
+            (h->fuse_close && !dalloc(&h->e3, (size_t)q.n_slabs * slab)))
+            return cleanup(STH_ENOMEM, "device allocation failed");
+        // mode weights of the lower bound of the B-spline residual norm
+        const std::vector<double> vwh = residual_mode_weights(h->S);
+        if (!dalloc(&h->vw, (size_t)2 * n))
             return cleanup(STH_ENOMEM, "device allocation failed");
         if (hipMemcpyAsync(h->Cf, Cf.data(), Cf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(h->Ci, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
+            hipMemcpyAsync(h->Ci, Ci.data(), Ci.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(h->vw, vwh.data(), vwh.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess)
             return cleanup(STH_EHIP, "upload of the setup failed");
         if (h->dim == 2 && xform2d_supported(np)) {
             // G = C^T C for the exact residual norm
@@ -758,7 +825,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 return cleanup(STH_EHIP, "upload of the setup failed");
         }
     }
-    if (hipHostMalloc((void**)&h->hnorm, 3 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
+    if (hipHostMalloc((void**)&h->hnorm, 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
             hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
     if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess)
@@ -857,7 +924,13 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
     int rc;
     long len = h->lev_S[0] * slab_len(h);
     if (h->basis == 1) {
-        if ((rc = eig_vcycle(h, 0, false, st))) return rc;
+        h->defer_close = h->fuse_close;
+        rc = eig_vcycle(h, 0, false, st);
+        h->defer_close = false;
+        if (rc) {
+            h->pending_ec = nullptr;
+            return rc;
+        }
         return eig_residual_cheap(h, st);
     }
     if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
@@ -872,46 +945,65 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
 // on the legacy default stream, where capture is not allowed.  Enqueues one
 // iteration without waiting for it.
 static int graph_launch(sth_handle* h, const double* f, double* u, hipStream_t st) {
-    const int cur0 = h->basis == 1 ? h->ecur[0] : 0;     // eigenbasis iterate buffer at entry
+    // level-0 buffer state at entry (eigenbasis): iterate, pre-smoothed iterate
+    const int key = h->basis == 1 ? h->ecur[0] + 3 * h->pre_idx + 9 * (h->presmoothed ? 1 : 0) : 0;
     const unsigned mask = h->timing ? h->timing_mask : 0u;
-    if (!h->gexec || h->gf != f || h->gu != u || h->gcur != cur0 || h->gmask != mask) {
+    sth_handle::GraphEntry* g = nullptr;
+    for (auto& e : h->gent)
+        if (e.exec && e.f == f && e.u == u && e.key == key && e.mask == mask) g = &e;
+    if (!g) {
         if (!h->allow_capture) {                          // capture later; run this one eagerly
             h->graph_launched = false;
             return solve_iteration(h, f, u, st);
         }
-        drop_graph(h);
-        h->gcur = cur0;
+        // an empty entry, else the least recently used one
+        g = &h->gent[0];
+        for (auto& e : h->gent) {
+            if (!e.exec) { g = &e; break; }
+            if (e.last_used < g->last_used) g = &e;
+        }
+        drop_graph_entry(*g);
+        h->grecs.clear();
         HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         h->capturing = true;
         int rc = solve_iteration(h, f, u, st);
         h->capturing = false;
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(st, &g);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &graph);
         if (rc) {
-            if (g) (void)hipGraphDestroy(g);
+            if (graph) (void)hipGraphDestroy(graph);
             h->grecs.clear();
             return rc;
         }
         HIPCHK(e);
-        h->graph = g;
-        HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
-        h->gf = f;
-        h->gu = u;
-        h->gmask = mask;
+        g->graph = graph;
+        HIPCHK(hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0));
+        g->f = f;
+        g->u = u;
+        g->mask = mask;
+        g->key = key;
+        g->recs.swap(h->grecs);
+        g->ecur0_after = h->basis == 1 ? h->ecur[0] : 0;
+        g->pre_after = h->pre_idx;
+        g->presm_after = h->presmoothed;
+    } else if (h->basis == 1) {
+        // a replay does not run the host-side bookkeeping of the capture:
+        // take the level-0 buffer state the captured iteration left
+        h->ecur[0] = g->ecur0_after;
+        h->pre_idx = g->pre_after;
+        h->presmoothed = g->presm_after;
     }
-    else if (h->basis == 1) {
-        // replaying does not run the host-side bookkeeping of the capture:
-        // advance the eigenbasis buffer index by the smoothing steps of a cycle
-        if ((h->nu_pre + h->nu_post) % 2 == 1) h->ecur[0] = 1 - h->ecur[0];
-    }
-    HIPCHK(hipGraphLaunch(h->gexec, st));
+    g->last_used = ++h->graph_clock;
+    HIPCHK(hipGraphLaunch(g->exec, st));
+    h->glast = g;
     h->graph_launched = true;
     return STH_OK;
 }
 
 // after a replay has completed: add the times of its timed launches
 static int graph_collect(sth_handle* h) {
-    for (auto& r : h->grecs) {
+    if (!h->glast) return STH_OK;
+    for (auto& r : h->glast->recs) {
         float e = 0;
         HIPCHK(hipEventElapsedTime(&e, r.a, r.b));
         h->gms[r.cls] += e;
@@ -982,13 +1074,17 @@ static int enqueue_iteration(sth_handle* h) {
 // the final mapping of the result into u (*more = false).
 //
 // Eigenbasis iteration: every cycle yields ||r^|| of its residual in the
-// eigenbasis; the B-spline residual satisfies ||r||^2 >= nb_lo ||r^||^2
-// (the squared singular values of I (x) C are products of eigenvalues of
-// M_1, nb_lo = lambda_min(M_1)^dim).  While sqrt(nb_lo) ||r^|| > rtol ||f|| the cycle is
-// provably not converged and the next one starts at once; otherwise the
-// exact ||r|| is evaluated and decides, as it would in every cycle, so the
-// cycle count is that of the plain stopping test.  Growth is watched on
-// ||r^||.
+// eigenbasis and a lower bound of the B-spline residual norm: ||r||^2 =
+// r^T (I (x) G (x) G) r^ (G = C^T C) is at least nb_lo ||r^||^2 (the
+// eigenvalues of G are those of M_1, nb_lo = lambda_min(M_1)^dim) and at
+// least sum_m v_m r^_m^2 with v_m = 2 prod d - prod a over the axes (d the
+// diagonal of G, a its absolute row sums: G (x) G - D (x) D is bounded by its
+// row sums).  The second is within a few per cent of ||r||^2 when G is nearly
+// diagonal, as for B-spline mass matrices.  While the bound exceeds
+// rtol ||f|| the cycle is provably not converged and the next one starts at
+// once; otherwise the exact ||r|| is evaluated and decides, as it would in
+// every cycle, so the cycle count is that of the plain stopping test.
+// Growth is watched on ||r^||.
 int solve_continue(sth_handle* h, bool* more) {
     auto& v = h->sv;
     *more = false;
@@ -1016,7 +1112,11 @@ int solve_continue(sth_handle* h, bool* more) {
         }
         v.rn = r;
         if (eig) {
-            v.rn = std::sqrt(h->nb_lo) * r;             // lower bound of ||r||
+            // lower bound of ||r||: the larger of nb_lo ||r^||^2 and the
+            // mode-weighted sum (slightly reduced against rounding)
+            double lo2 = h->nb_lo * r * r;
+            if (h->wsum_valid && std::isfinite(h->hnorm[3])) lo2 = std::max(lo2, (1.0 - 1e-8) * h->hnorm[3]);
+            v.rn = std::sqrt(lo2);
             *more = true;
             if (std::isfinite(r) && v.rn > v.rtol * v.fn && v.it < v.maxit && v.growth < 3)
                 return enqueue_iteration(h);
@@ -1221,7 +1321,8 @@ int sth_destroy(sth_handle* h) {
     // graph first: its nodes reference the buffers below
     drop_graph(h);
     double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt,
-                      h->Cf, h->Ci, h->Gf, h->e0, h->e1, h->e2, h->cpartial, h->kv, h->kz, h->kc, h->kpart};
+                      h->Cf, h->Ci, h->Gf, h->e0, h->e1, h->e2, h->e3, h->cpartial, h->kv, h->kz, h->kc,
+                      h->kpart, h->vw};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
     for (auto* vec : {&h->lu, &h->lf, &h->lu2})
@@ -1310,6 +1411,7 @@ int sth_host_factors(const sth_problem* p, int level, sth_factors* out) {
     cp(out->eig_im, L.im);
     out->schur = L.schur ? 1 : 0;
     if (L.schur) cp(out->R, L.R.a);
+    if (out->mode_weights) cp(out->mode_weights, residual_mode_weights(S));
     return STH_OK;
 }
 

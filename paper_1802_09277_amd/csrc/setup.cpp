@@ -962,4 +962,28 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
     return 0;
 }
 
+// Lower bound of the B-spline norm of an eigenbasis vector, per mode: with
+// G = C^T C = D + E (D its diagonal) and x^T (G (x) G - D (x) D) x bounded by
+// the absolute row sums of G (x) G - D (x) D (symmetric), which are
+// prod a - prod d for the mode (a the absolute row sums of G).
+std::vector<double> residual_mode_weights(const Setup& s) {
+    const int n = s.n;
+    Mat C(n, n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double c = 0.0;
+            for (int k = 0; k < n; ++k) c += s.M1(i, k) * s.U(k, j);
+            C(i, j) = c;
+        }
+    std::vector<double> w((size_t)2 * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double g = 0.0;
+            for (int k = 0; k < n; ++k) g += C(k, i) * C(k, j);
+            if (i == j) w[2 * i] = g;
+            w[2 * i + 1] += std::fabs(g);
+        }
+    return w;
+}
+
 }  // namespace sth

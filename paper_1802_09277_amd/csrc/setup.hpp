@@ -86,6 +86,11 @@ std::string validate(const Problem& p);
 // Full setup.  status: 0 ok, -4 not positive, -5 ill-conditioned, -1 invalid.
 int build_setup(const Problem& p, Setup& s, std::string& err);
 
+// Per 1-D mode j of the spatial eigenbasis: G_jj and sum_k |G_jk| of
+// G = C^T C, C = M1 U (2n entries, interleaved), the weights of the lower
+// bound x^T (G (x) .. (x) G) x >= sum_m (2 prod G_jj - prod sum_k |G_jk|) x_m^2.
+std::vector<double> residual_mode_weights(const Setup& s);
+
 // Spatial 1-D matrices (interior functions), banded with bandwidth p.
 void space_matrices(int n_elem, int p, Mat& M1, Mat& K1);
 // Temporal matrices on a slab of length tau with n_el elements and SUPG sigma.
