@@ -213,6 +213,8 @@ def main():
                     help="run a plain device copy of this many MiB three times first (the reference "
                          "kernel of known size that scales the HBM counters of a --pmc run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-speculate", action="store_true",
+                    help="wait for each cycle's norm before enqueueing the next (library default: speculate)")
     ap.add_argument("--serve", action="store_true", help="serving workload (p50/p99 latency) instead")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=8)
@@ -236,6 +238,8 @@ def main():
     torch.cuda.set_stream(stream)
     s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
                    prec=args.prec, basis=args.basis, coarse_slabs=args.coarse_slabs)
+    if args.no_speculate:
+        s.speculate(False)
     f = s.new_vector()
     s.load_rhs(cfg.modes(), f)
     u = s.new_vector()
@@ -333,6 +337,7 @@ def main():
             "final_relres": relres,
             "levels": s.num_levels,
             "coarse_slabs": s.coarse_slabs,
+            "speculative_cycles": not args.no_speculate,
         },
         "roofline": roof,
     }

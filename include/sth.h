@@ -187,6 +187,18 @@ int sth_solve_fgmres(sth_handle* h, const double* f, double* u, double rtol, int
  * (sth_timing), which needs events around the individual launches. */
 int sth_use_graphs(sth_handle* h, int enable);
 
+/* Speculative cycles (default on; eigenbasis iteration with V(1,1) cycles,
+ * a level below the finest and N_t <= 5): sth_solve enqueues each cycle
+ * before the residual norm of the one ahead of it has reached the host.
+ * The final sum of a cycle stores on the device whether the next cycle
+ * must run (its lower bound of the B-spline residual exceeds rtol ||f||);
+ * when it may have converged every kernel of the next cycle returns at
+ * once and the exact norm decides, so the cycles, iterates and counts are
+ * those of the plain loop (the stopping test of Section 4.4) without a host
+ * round trip between cycles.  enable = 0 waits for each norm first; so does
+ * kernel timing. */
+int sth_speculate(sth_handle* h, int enable);
+
 /* Level transfers (Section 3.1, time coarsening by combining two slabs):
  * rc <- (P_t^T (x) I) r on slab pairs of `level` (rc has the slab count of
  * level+1), and u <- u + (P_t (x) I) ec.  Vectors of a coarse level have

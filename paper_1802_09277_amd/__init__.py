@@ -99,6 +99,7 @@ def load_library():
         "sth_timing": (i, [vp, ctypes.c_uint]),
         "sth_timing_level": (i, [vp, i]),
         "sth_use_graphs": (i, [vp, i]),
+        "sth_speculate": (i, [vp, i]),
         "sth_timing_report": (i, [vp, i, P(i), P(d), P(d), P(d)]),
         "sth_problem_vector_len": (sz, [P(Problem)]),
         "sth_server_create": (i, [sz, i, P(vp)]),
@@ -301,6 +302,10 @@ class Solver:
     def use_graphs(self, enable):
         """Graph replay of solve iterations on non-default streams (default on)."""
         _check(self.lib.sth_use_graphs(self.h, int(enable)))
+
+    def speculate(self, enable):
+        """Cycles enqueued ahead of their predecessor's norm (default on)."""
+        _check(self.lib.sth_speculate(self.h, int(enable)))
 
     def norm(self, v, stream=None):
         out = ctypes.c_double()

@@ -18,6 +18,17 @@
 
 namespace sth {
 
+// Launches of a speculatively enqueued multigrid cycle carry a guard: the
+// cycle before it stored 0 there when it may have converged, and then every
+// kernel of the cycle returns at once (uniformly per block, before any
+// barrier), leaving all buffers untouched.
+// (a uniform read: one scalar load per wave; the flag was stored by an
+// earlier kernel, so the caches are current at this kernel's start)
+__device__ __forceinline__ bool guard_off(const int* __restrict__ guard) {
+    return guard != nullptr && guard[0] == 0;
+}
+
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
@@ -1294,8 +1305,11 @@ __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ 
 // stored to out_host (device address of mapped, coherent pinned host
 // memory) when given, which the host reads once the stream has passed
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out,
-                                                      double* out_host, int nsum = 1) {
+                                                      double* out_host, int nsum = 1, const int* guard = nullptr,
+                                                      CycleFlag flag = CycleFlag{}) {
+    if (guard_off(guard)) return;
     __shared__ double sh[256];
+    __shared__ double res[2];
     for (int j = 0; j < nsum; ++j) {
         double s = 0.0;
         for (int i = threadIdx.x; i < count; i += 256) s += partial[(long)j * count + i];
@@ -1308,9 +1322,31 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         if (threadIdx.x == 0) {
             out[j] = sh[0];
             if (out_host) out_host[j] = sh[0];
+            if (j < 2) res[j] = sh[0];
         }
         __syncthreads();
     }
+    if (flag.dev && threadIdx.x == 0) {
+        const double ssq = res[0], wsq = nsum > 1 ? res[1] : 0.0;
+        const double lo2 = fmax(flag.nb_lo * ssq, (1.0 - 1e-8) * wsq);
+        const int go = (isfinite(ssq) && isfinite(wsq) && lo2 > *flag.thr) ? 1 : 0;
+        *flag.dev = go;
+        *flag.host = go;
+    }
+}
+
+// *flag = value (one thread)
+// and optionally *thr = thr_value (negative: left as it is)
+__global__ void k_set_flag(int* flag, int value, double* thr, double thr_value) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        *flag = value;
+        if (thr && thr_value >= 0.0) *thr = thr_value;
+    }
+}
+
+hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr, double thr_value) {
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flag, value, thr, thr_value);
+    return hipGetLastError();
 }
 
 // Weight v of a spatial mode in the lower bound of the B-spline residual norm
@@ -1482,7 +1518,8 @@ __device__ __forceinline__ double mode_shift(int dim, const double* mu1, int n, 
 template <int NT, bool SCHUR>
 __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
                                                  long Nx, const double* __restrict__ in,
-                                                 double* __restrict__ out, long total) {
+                                                 double* __restrict__ out, long total, const int* guard) {
+    if (guard_off(guard)) return;
     long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     long s = idx / Nx, m = idx % Nx;
@@ -1508,7 +1545,8 @@ __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const doub
 template <int NT, bool SCHUR>
 __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
                                                       long Nx, const double* __restrict__ in,
-                                                      double* __restrict__ out, long S) {
+                                                      double* __restrict__ out, long S, const int* guard) {
+    if (guard_off(guard)) return;
     constexpr int MB = 16, G = 16, LR = 4;      // LR: slabs per group held in registers
     __shared__ double xe_s[G][MB], gl_s[G][MB];
     const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
@@ -1591,7 +1629,7 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
 }
 
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
-                          const double* in, double* out, long S, bool fwdsub, hipStream_t st) {
+                          const double* in, double* out, long S, bool fwdsub, hipStream_t st, const int* guard) {
     long Nx = (long)n * n * (dim == 3 ? n : 1);
     long total = S * Nx;
     if (total <= 0) return hipSuccess;
@@ -1601,10 +1639,10 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 #define STH_TM_LAUNCH(NTV, SC)                                                                           \
     if (fwdsub)                                                                                          \
         hipLaunchKernelGGL((k_timemix_scan<NTV, SC>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in,   \
-                           out, S);                                                                      \
+                           out, S, guard);                                                               \
     else                                                                                                 \
         hipLaunchKernelGGL((k_timemix<NTV, SC>), grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out,    \
-                           total);
+                           total, guard);
 #define STH_TM_CASE(NTV)                 \
     case NTV:                            \
         if (tm.schur) {                  \
@@ -1654,7 +1692,9 @@ __global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const d
                                                     const double* __restrict__ mu1, int n, long Nx,
                                                     const double* __restrict__ fh, const double* __restrict__ uin,
                                                     double* __restrict__ uout, long total, double omega,
-                                                    int zero_guess, const double* __restrict__ ec, Transfer tr) {
+                                                    int zero_guess, const double* __restrict__ ec, Transfer tr,
+                                                    const int* guard) {
+    if (guard_off(guard)) return;
     long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     long s = idx / Nx, m = idx % Nx;
@@ -1898,7 +1938,8 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
                                                          double* __restrict__ unext, double* __restrict__ fc,
                                                          Transfer tr, double omega, int chain, long total,
                                                          const double* __restrict__ vw,
-                                                         double* __restrict__ partial) {
+                                                         double* __restrict__ partial, const int* guard) {
+    if (guard_off(guard)) return;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     double ssq = 0.0, wsq = 0.0;
     if (idx < total) {
@@ -2052,7 +2093,8 @@ __global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const dou
                                                   const double* __restrict__ mu1, int n, long Nx,
                                                   const double* __restrict__ fl, double* __restrict__ uout,
                                                   double* __restrict__ fc, Transfer tr, double omega, int chain,
-                                                  long total) {
+                                                  long total, const int* guard) {
+    if (guard_off(guard)) return;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= total) return;
     const long q = idx / Nx, m = idx % Nx;
@@ -2123,32 +2165,34 @@ __global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const dou
 template <int NT>
 static void eig_smooth_launch(dim3 grid, hipStream_t st, int dim, const TimeMix& tm, const double* ktmt,
                               const double* mu1, int n, long Nx, const double* fh, const double* uin, double* uout,
-                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr) {
+                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr,
+                              const int* guard) {
     const int zg = zero_guess ? 1 : 0;
     if (ec && tm.schur)
         hipLaunchKernelGGL((k_eig_smooth<NT, true, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
-                           uout, total, omega, zg, ec, tr);
+                           uout, total, omega, zg, ec, tr, guard);
     else if (ec)
         hipLaunchKernelGGL((k_eig_smooth<NT, true, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
-                           uin, uout, total, omega, zg, ec, tr);
+                           uin, uout, total, omega, zg, ec, tr, guard);
     else if (tm.schur)
         hipLaunchKernelGGL((k_eig_smooth<NT, false, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
-                           uin, uout, total, omega, zg, ec, tr);
+                           uin, uout, total, omega, zg, ec, tr, guard);
     else
         hipLaunchKernelGGL((k_eig_smooth<NT, false, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
-                           uin, uout, total, omega, zg, ec, tr);
+                           uin, uout, total, omega, zg, ec, tr, guard);
 }
 
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st) {
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st,
+                             const int* guard) {
     long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
     if (total <= 0) return hipSuccess;
     if (ec && zero_guess) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
     switch (Nt) {
 #define STH_ES_CASE(NTV) \
-        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr); break;
+        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr, guard); break;
         STH_ES_CASE(2) STH_ES_CASE(3) STH_ES_CASE(4) STH_ES_CASE(5) STH_ES_CASE(6) STH_ES_CASE(7) STH_ES_CASE(8)
 #undef STH_ES_CASE
         default: return hipErrorInvalidValue;
@@ -2368,10 +2412,11 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const double* fh, const double* upre, const double* ec, double* uend,
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
                                   const double* vw, double* partial, long max_partial, double* out,
-                                  double* out_host, hipStream_t st) {
+                                  double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
+    if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
     if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
@@ -2382,17 +2427,18 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
             if (tm.schur)                                                                                     \
                 hipLaunchKernelGGL((k_eig_cycle_close<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,  \
                                    n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
-                                   partial);                                                                  \
+                                   partial, guard);                                                           \
             else                                                                                              \
                 hipLaunchKernelGGL((k_eig_cycle_close<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, \
                                    n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
-                                   partial);                                                                  \
+                                   partial, guard);                                                           \
             break;
         STH_CC_CASE(2) STH_CC_CASE(3) STH_CC_CASE(4) STH_CC_CASE(5) STH_CC_CASE(6) STH_CC_CASE(7) STH_CC_CASE(8)
 #undef STH_CC_CASE
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2, guard,
+                       flag);
     return hipGetLastError();
 }
 
@@ -2476,7 +2522,7 @@ hipError_t launch_multiaxpy(const double* V, long ld, int k, const double* c, do
 
 hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                            const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
-                           int chain, hipStream_t st) {
+                           int chain, hipStream_t st, const int* guard) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
@@ -2488,10 +2534,10 @@ hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktm
         case NTV:                                                                                          \
             if (tm.schur)                                                                                  \
                 hipLaunchKernelGGL((k_eig_down<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, \
-                                   fl, uout, fc, tr, omega, chain, total);                                 \
+                                   fl, uout, fc, tr, omega, chain, total, guard);                          \
             else                                                                                           \
                 hipLaunchKernelGGL((k_eig_down<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n,    \
-                                   Nx, fl, uout, fc, tr, omega, chain, total);                             \
+                                   Nx, fl, uout, fc, tr, omega, chain, total, guard);                      \
             break;
         STH_DN_CASE(2) STH_DN_CASE(3) STH_DN_CASE(4) STH_DN_CASE(5) STH_DN_CASE(6) STH_DN_CASE(7) STH_DN_CASE(8)
 #undef STH_DN_CASE

@@ -26,6 +26,19 @@ struct Transfer {               // 2Nt x Nt prolongation
     double P[2 * kNt * kNt];
 };
 
+// Guards of speculatively enqueued multigrid cycles: the launches of such a
+// cycle take a device int and return at once when it holds 0.  The final sum
+// of a cycle-close pass with a CycleFlag stores 1 there (and in the mapped
+// host copy) when the lower bound of its B-spline residual,
+// max(nb_lo ||r^||^2, (1 - 1e-8) sum_m v_m r^_m^2), exceeds *thr =
+// (rtol ||f||)^2, and 0 otherwise (possible convergence, or non-finite).
+struct CycleFlag {
+    int* dev = nullptr;
+    int* host = nullptr;           // mapped pinned host memory
+    const double* thr = nullptr;   // device scalar
+    double nb_lo = 0.0;
+};
+
 // r = f + sign * (-(A u)_n + (B u)_{n-1}) for slabs [s0, s0+ns) of a vector
 // with slab length Nt*n^dim; the coupling uses slab s-1 of the same vector
 // when s > 0.  f may be null (treated as zero).  M1b/K1b: bands [n][2p+1];
@@ -65,7 +78,8 @@ hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const d
 // out_s = A_m^{-1}(in_s + e_1 out_{s-1}[Nt-1]) (forward substitution),
 // computed parallel in time (in and out must differ).
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
-                          const double* in, double* out, long S, bool fwdsub, hipStream_t st);
+                          const double* in, double* out, long S, bool fwdsub, hipStream_t st,
+                          const int* guard = nullptr);
 
 // Iteration in the spatial eigenbasis (all pointwise over spatial modes;
 // ktmt = device K_t then M_t of the level):
@@ -74,13 +88,14 @@ hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1,
 //  read when zero_guess (then ec must be null)
 hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                              const double* fh, const double* uin, double* uout, long S, double omega,
-                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st);
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st,
+                             const int* guard = nullptr);
 //  descent on a coarse level from a zero guess, one pass over fl (chains of
 //  `chain` slabs per thread, chain even and dividing S): uout = omega A^{-1} fl,
 //  fc = (P^T (x) I)(fl - L uout) on slab pairs
 hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                            const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
-                           int chain, hipStream_t st);
+                           int chain, hipStream_t st, const int* guard = nullptr);
 //  end of a cycle on the finest level, in one pass over f^ and u^ (chains as
 //  above): ||fh - L uin||^2 and its mode-weighted form sum_m v_m |r_m|^2
 //  (weights from the per-axis table vw of the diagonal entries and absolute
@@ -101,7 +116,10 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const double* fh, const double* upre, const double* ec, double* uend,
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
                                   const double* vw, double* partial, long max_partial, double* out,
-                                  double* out_host, hipStream_t st);
+                                  double* out_host, hipStream_t st, const int* guard = nullptr,
+                                  const CycleFlag& flag = CycleFlag{});
+//  *flag = value, and *thr = thr_value when thr is not null and thr_value >= 0
+hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr = nullptr, double thr_value = -1.0);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);

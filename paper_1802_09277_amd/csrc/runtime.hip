@@ -90,8 +90,8 @@ struct sth_handle {
     double* buf0 = nullptr;
     double* buf1 = nullptr;
     double* partial = nullptr;
-    double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side, [2] eigenbasis
-                                        // residual, [3] its mode-weighted sum
+    double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side; per norm slot
+                                        // s (2 + 2s, 3 + 2s) eigenbasis residual and its weighted sum
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
     double* hnorm_dev = nullptr;        // device address of hnorm
     // timing
@@ -115,7 +115,7 @@ struct sth_handle {
         double* u = nullptr;
         unsigned mask = 0;
         int key = -1;                   // level-0 buffer state at entry
-        int ecur0_after = 0, pre_after = 1;
+        int ecur0_after = 0, pre_after = 1, slot_after = 0;
         bool presm_after = false;
         std::vector<Rec> recs;          // timed launches inside the graph
         long last_used = 0;
@@ -128,6 +128,12 @@ struct sth_handle {
     double gms[STH_K_COUNT] = {0}, gfl[STH_K_COUNT] = {0}, gby[STH_K_COUNT] = {0};
     int gcnt[STH_K_COUNT] = {0};
     // state of the solve in progress (sth_solve and the serving loop)
+    // level-0 buffer state after an enqueued cycle, and its norm slot
+    struct Snap {
+        int ecur0 = 0, pre_idx = 1;
+        bool presmoothed = false;
+        int slot = 0;
+    };
     struct SolveState {
         const double* f = nullptr;
         double* u = nullptr;
@@ -137,7 +143,24 @@ struct sth_handle {
         // 0 initial norms enqueued, 1 iterating, 2 result enqueued, 3 exact
         // B-spline norm of the current eigenbasis iterate enqueued
         int phase = 0;
+        // speculation: the cycle waited for (a) and the guarded one behind it (b)
+        bool spec = false;
+        int pend = 0;
+        bool drain = false;
+        Snap a, b;
+        hipEvent_t ev_a = nullptr, ev_b = nullptr;
     } sv;
+    // speculative cycles (eigenbasis, fused cycle close)
+    bool speculate = true;
+    const int* guard = nullptr;         // guard of the launches of the cycle being enqueued
+    int* dgo = nullptr;                 // per norm slot: continuation flag of the cycle (device)
+    int* hflag = nullptr;               // its mapped host copy
+    int* hflag_dev = nullptr;
+    double* dthr = nullptr;             // (rtol ||f||)^2 of the solve in progress (device)
+    int last_slot = 0;                  // norm slot of the last enqueued cycle end
+    hipEvent_t evring[4] = {nullptr, nullptr, nullptr, nullptr};
+    int evnext = 0;
+    hipEvent_t wait_ev = nullptr;       // event the caller waits for before solve_continue
 };
 
 static void drop_graph_entry(sth_handle::GraphEntry& g) {
@@ -425,7 +448,8 @@ static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st, c
     double bytes = (zero_guess ? 16.0 : 24.0) * dof + (ec ? 4.0 * dof : 0.0);
     Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0 + (ec ? 2.0 * h->Nt : 0.0)), bytes, st);
     HIPCHK(launch_eig_smooth(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
-                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, st));
+                             eig_u(h, lvl, c), eig_u(h, lvl, 1 - c), S, h->omega, zero_guess, ec, h->tr, st,
+                             h->guard));
     h->ecur[lvl] = 1 - c;
     return STH_OK;
 }
@@ -446,7 +470,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         double dof = (double)S * slab_len(h);
         Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
         HIPCHK(launch_timemix(h->dim, h->Nt, h->mixes[lvl], h->mu1, h->n, eig_f(h, lvl),
-                              eig_u(h, lvl, h->ecur[lvl]), S, true, st));
+                              eig_u(h, lvl, h->ecur[lvl]), S, true, st, h->guard));
         return STH_OK;
     }
     int rc;
@@ -465,7 +489,8 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         const int c = h->ecur[lvl];
         Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), 20.0 * dof, st);
         HIPCHK(launch_eig_down(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
-                               eig_u(h, lvl, 1 - c), eig_f(h, lvl + 1), h->tr, h->omega, S, chain_length(h, S, 262144), st));
+                               eig_u(h, lvl, 1 - c), eig_f(h, lvl + 1), h->tr, h->omega, S, chain_length(h, S, 262144), st,
+                               h->guard));
         h->ecur[lvl] = 1 - c;
     } else {
         for (int i = 0; i < h->nu_pre; ++i)
@@ -512,11 +537,18 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         // consecutive cycles alternate between two buffer states
         const double Nt = h->Nt;
         const int cur = c == 0 ? 1 : 0, nxt = 3 - c - cur;
+        // norm slot of this cycle: by its next pre-smoothed buffer, so that
+        // consecutive cycles alternate (the guard of the next cycle reads it)
+        const int slot = nxt == 2 ? 1 : 0;
+        CycleFlag flag;
+        if (h->guard) flag = CycleFlag{h->dgo + slot, h->hflag_dev + slot, h->dthr, h->nb_lo};
         Timed tm(h, STH_K_EIG_CYCLE_CLOSE, dof * (24.0 * Nt + 20.0), 40.0 * dof, st);
         HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                       eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
                                       eig_f(h, 1), h->tr, h->omega, S, chain_length(h, S, 65536), h->vw,
-                                      h->cpartial, h->n_cpartial, h->dnorm + 2, h->hnorm_dev + 2, st));
+                                      h->cpartial, h->n_cpartial, h->dnorm + 2 + 2 * slot,
+                                      h->hnorm_dev + 2 + 2 * slot, st, h->guard, flag));
+        h->last_slot = slot;
         h->pending_ec = nullptr;
         h->wsum_valid = true;
         h->ecur[0] = cur;
@@ -533,6 +565,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
                                     chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + 2,
                                     h->hnorm_dev + 2, st));
         h->wsum_valid = true;
+        h->last_slot = 0;
         h->pre_idx = o;
         h->presmoothed = true;
         return STH_OK;                  // the pass stored hnorm[2] itself
@@ -547,6 +580,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + 2, st));
     }
     h->wsum_valid = false;
+    h->last_slot = 0;
     HIPCHK(hipMemcpyAsync(h->hnorm + 2, h->dnorm + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     return STH_OK;
 }
@@ -766,7 +800,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
-        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 4) ||
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 6) ||
         !dalloc(&h->dktmt, (size_t)h->L * 2 * kNt * kNt))
         return cleanup(STH_ENOMEM, "device allocation failed");
     std::vector<double> ktmt((size_t)h->L * 2 * kNt * kNt);
@@ -825,11 +859,19 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 return cleanup(STH_EHIP, "upload of the setup failed");
         }
     }
-    if (hipHostMalloc((void**)&h->hnorm, 4 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) !=
-            hipSuccess)
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc((void**)&h->hnorm, 6 * sizeof(double), mapped) != hipSuccess ||
+        hipHostMalloc((void**)&h->hflag, 2 * sizeof(int), mapped) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
-    if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess)
+    if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess)
         return cleanup(STH_EHIP, "pinned host memory is not mapped");
+    if (hipMalloc((void**)&h->dgo, 2 * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->dthr, sizeof(double)) != hipSuccess)
+        return cleanup(STH_ENOMEM, "device allocation failed");
+    for (auto& e : h->evring)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return cleanup(STH_EHIP, "event creation failed");
     if (hipMemcpyAsync(h->Tf, Tf.data(), Tf.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->Ti, Ti.data(), Ti.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipMemcpyAsync(h->mu1, h->S.mu.data(), (size_t)n * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
@@ -925,13 +967,15 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
     long len = h->lev_S[0] * slab_len(h);
     if (h->basis == 1) {
         h->defer_close = h->fuse_close;
+        // a speculative solve guards every launch of the cycle with the
+        // continuation flag of the cycle before it (its norm slot)
+        h->guard = h->sv.spec && h->presmoothed ? h->dgo + (h->pre_idx == 2 ? 1 : 0) : nullptr;
         rc = eig_vcycle(h, 0, false, st);
         h->defer_close = false;
-        if (rc) {
-            h->pending_ec = nullptr;
-            return rc;
-        }
-        return eig_residual_cheap(h, st);
+        if (rc == STH_OK) rc = eig_residual_cheap(h, st);
+        h->pending_ec = nullptr;
+        h->guard = nullptr;
+        return rc;
     }
     if ((rc = vcycle_lvl(h, 0, f, u, false, st))) return rc;
     if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
@@ -946,7 +990,9 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
 // iteration without waiting for it.
 static int graph_launch(sth_handle* h, const double* f, double* u, hipStream_t st) {
     // level-0 buffer state at entry (eigenbasis): iterate, pre-smoothed iterate
-    const int key = h->basis == 1 ? h->ecur[0] + 3 * h->pre_idx + 9 * (h->presmoothed ? 1 : 0) : 0;
+    const int key = h->basis == 1 ? h->ecur[0] + 3 * h->pre_idx + 9 * (h->presmoothed ? 1 : 0) +
+                                        18 * (h->sv.spec ? 1 : 0)
+                                  : 0;
     const unsigned mask = h->timing ? h->timing_mask : 0u;
     sth_handle::GraphEntry* g = nullptr;
     for (auto& e : h->gent)
@@ -986,12 +1032,14 @@ static int graph_launch(sth_handle* h, const double* f, double* u, hipStream_t s
         g->ecur0_after = h->basis == 1 ? h->ecur[0] : 0;
         g->pre_after = h->pre_idx;
         g->presm_after = h->presmoothed;
+        g->slot_after = h->last_slot;
     } else if (h->basis == 1) {
         // a replay does not run the host-side bookkeeping of the capture:
         // take the level-0 buffer state the captured iteration left
         h->ecur[0] = g->ecur0_after;
         h->pre_idx = g->pre_after;
         h->presmoothed = g->presm_after;
+        h->last_slot = g->slot_after;
     }
     g->last_used = ++h->graph_clock;
     HIPCHK(hipGraphLaunch(g->exec, st));
@@ -1031,6 +1079,10 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
     v.st = st;
     v.rtol = rtol;
     v.maxit = maxit;
+    // cycles enqueued ahead of their predecessor's norm (eigenbasis with the
+    // fused cycle close; not while kernels are timed one by one)
+    v.spec = h->basis == 1 && h->fuse_close && h->speculate && !h->timing;
+    h->wait_ev = nullptr;
     h->graph_launched = false;
     h->presmoothed = false;
     h->tlev = 0;
@@ -1069,6 +1121,156 @@ static int enqueue_iteration(sth_handle* h) {
     return solve_iteration(h, v.f, v.u, v.st);
 }
 
+static hipEvent_t next_event(sth_handle* h) {
+    hipEvent_t e = h->evring[h->evnext];
+    h->evnext = (h->evnext + 1) % 4;
+    return e;
+}
+
+static sth_handle::Snap take_snap(const sth_handle* h) {
+    return sth_handle::Snap{h->ecur[0], h->pre_idx, h->presmoothed, h->last_slot};
+}
+
+static void put_snap(sth_handle* h, const sth_handle::Snap& s) {
+    h->ecur[0] = s.ecur0;
+    h->pre_idx = s.pre_idx;
+    h->presmoothed = s.presmoothed;
+    h->last_slot = s.slot;
+}
+
+// Enqueues the next cycle (it must run: the flag it is guarded by holds 1)
+// and, while maxit allows, one more behind it guarded by the first one's
+// flag.  The caller then waits for the first.
+static int spec_enqueue(sth_handle* h) {
+    auto& v = h->sv;
+    int rc = enqueue_iteration(h);
+    if (rc) return rc;
+    v.a = take_snap(h);
+    v.ev_a = next_event(h);
+    HIPCHK(hipEventRecord(v.ev_a, v.st));
+    v.pend = 0;
+    if (v.it + 2 <= v.maxit) {
+        if ((rc = enqueue_iteration(h))) return rc;
+        v.b = take_snap(h);
+        v.ev_b = next_event(h);
+        HIPCHK(hipEventRecord(v.ev_b, v.st));
+        v.pend = 1;
+    }
+    h->wait_ev = v.ev_a;
+    return STH_OK;
+}
+
+static int solve_finish(sth_handle* h, bool* more) {
+    auto& v = h->sv;
+    *more = false;
+    v.phase = 2;
+    h->wait_ev = nullptr;
+    // u = (I (x) U_x) u^
+    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st);
+}
+
+// Lower bound of the B-spline residual norm of the cycle whose sums are in
+// norm slot `slot` (the larger of the two bounds of solve_continue)
+static double eig_lower_bound(const sth_handle* h, int slot) {
+    const double ssq = h->hnorm[2 + 2 * slot], wsq = h->hnorm[3 + 2 * slot];
+    double lo2 = h->nb_lo * ssq;
+    if (h->wsum_valid && std::isfinite(wsq)) lo2 = std::max(lo2, (1.0 - 1e-8) * wsq);
+    return std::sqrt(lo2);
+}
+
+// Speculative form of solve_continue: after cycle k's event, its flag (set
+// on the device from the same bound the plain loop tests) says whether cycle
+// k+1, already enqueued behind it, runs; if not, cycle k+1 leaves every
+// buffer as it was, the host state goes back to cycle k's, and the exact
+// norm of cycle k's result decides as in the plain loop.  The cycle count
+// and the iterates are those of the plain loop.
+static int solve_continue_spec(sth_handle* h, bool* more) {
+    auto& v = h->sv;
+    const double target = v.rtol * v.fn;
+    *more = true;
+    if (v.phase == 0) {
+        v.fn = std::sqrt(h->hnorm[1]);
+        if (v.fn == 0.0) v.fn = 1.0;
+        const double r = std::sqrt(h->hnorm[2]);
+        v.prev = r;
+        v.rn = eig_lower_bound(h, 0);
+        if (!std::isfinite(r) || v.maxit == 0) return solve_finish(h, more);
+        if (!(v.rn > v.rtol * v.fn)) {
+            v.phase = 3;
+            int rc = eig_exact_norm(h, v.st);
+            h->wait_ev = nullptr;
+            return rc;
+        }
+        // arm the first cycle and set the threshold of the cycles' flags
+        HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn)));
+        v.phase = 1;
+        return spec_enqueue(h);
+    }
+    if (v.phase == 3) {
+        v.rn = std::sqrt(h->hnorm[0]);
+        if (!std::isfinite(v.rn) || !(v.rn > target) || v.it >= v.maxit || v.growth >= 3)
+            return solve_finish(h, more);
+        // not converged: the next cycle runs after all
+        HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn)));
+        v.phase = 1;
+        return spec_enqueue(h);
+    }
+    // cycle a has completed
+    ++v.it;
+    const int slot = v.a.slot;
+    const double r = std::sqrt(h->hnorm[2 + 2 * slot]);
+    if (std::isfinite(r)) {
+        v.growth = (r > v.prev) ? v.growth + 1 : 0;
+        v.prev = r;
+    }
+    v.rn = eig_lower_bound(h, slot);
+    if (v.drain) return solve_finish(h, more);
+    const bool go = h->hflag[slot] != 0;
+    if (go) {
+        if (v.growth >= 3 && v.pend) {
+            // cycle b runs: take it as the last one
+            v.a = v.b;
+            v.ev_a = v.ev_b;
+            v.pend = 0;
+            v.drain = true;
+            h->wait_ev = v.ev_a;
+            return STH_OK;
+        }
+        if (v.growth >= 3 || v.it >= v.maxit) return solve_finish(h, more);
+        if (v.pend) {
+            // cycle b is real: wait for it, with the next one guarded behind it
+            v.a = v.b;
+            v.ev_a = v.ev_b;
+            v.pend = 0;
+            h->wait_ev = v.ev_a;
+            if (v.it + 2 <= v.maxit) {
+                int rc = enqueue_iteration(h);
+                if (rc) return rc;
+                v.b = take_snap(h);
+                v.ev_b = next_event(h);
+                HIPCHK(hipEventRecord(v.ev_b, v.st));
+                v.pend = 1;
+            }
+            return STH_OK;
+        }
+        return spec_enqueue(h);
+    }
+    // the bound does not exclude convergence (or a sum is not finite):
+    // cycle b, if any, leaves everything untouched
+    if (v.pend) {
+        put_snap(h, v.a);
+        v.pend = 0;
+    }
+    if (!std::isfinite(r)) {
+        v.rn = r;
+        return solve_finish(h, more);
+    }
+    v.phase = 3;
+    int rc = eig_exact_norm(h, v.st);
+    h->wait_ev = nullptr;
+    return rc;
+}
+
 // Once the work enqueued by the previous call has completed: read the
 // residual norm, then enqueue either the next iteration (*more = true) or
 // the final mapping of the result into u (*more = false).
@@ -1094,11 +1296,12 @@ int solve_continue(sth_handle* h, bool* more) {
         if (rc) return rc;
         h->graph_launched = false;
     }
+    if (v.spec) return solve_continue_spec(h, more);
     const bool eig = h->basis == 1;
     if (v.phase == 3) {
         v.rn = std::sqrt(h->hnorm[0]);
     } else {
-        const double r = std::sqrt(h->hnorm[eig ? 2 : 0]);
+        const double r = std::sqrt(h->hnorm[eig ? 2 + 2 * h->last_slot : 0]);
         if (v.phase == 0) {
             v.fn = std::sqrt(h->hnorm[1]);
             if (v.fn == 0.0) v.fn = 1.0;
@@ -1114,9 +1317,7 @@ int solve_continue(sth_handle* h, bool* more) {
         if (eig) {
             // lower bound of ||r||: the larger of nb_lo ||r^||^2 and the
             // mode-weighted sum (slightly reduced against rounding)
-            double lo2 = h->nb_lo * r * r;
-            if (h->wsum_valid && std::isfinite(h->hnorm[3])) lo2 = std::max(lo2, (1.0 - 1e-8) * h->hnorm[3]);
-            v.rn = std::sqrt(lo2);
+            v.rn = eig_lower_bound(h, h->last_slot);
             *more = true;
             if (std::isfinite(r) && v.rn > v.rtol * v.fn && v.it < v.maxit && v.growth < 3)
                 return enqueue_iteration(h);
@@ -1149,6 +1350,8 @@ int solve_result(sth_handle* h, int* iters, double* relres) {
 
 void solve_allow_capture(sth_handle* h, bool allow) { h->allow_capture = allow; }
 
+hipEvent_t solve_wait_event(sth_handle* h) { return h->wait_ev; }
+
 }  // namespace sth
 
 extern "C" {
@@ -1160,7 +1363,8 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
     int rc = solve_begin(h, f, u, rtol, maxit, st);
     bool more = true;
     while (rc == STH_OK && more) {
-        HIPCHK(hipStreamSynchronize(st));
+        if (h->wait_ev) HIPCHK(hipEventSynchronize(h->wait_ev));
+        else HIPCHK(hipStreamSynchronize(st));
         rc = solve_continue(h, &more);
     }
     if (rc) return rc;
@@ -1294,6 +1498,12 @@ int sth_solve_fgmres(sth_handle* h, const double* f, double* u, double rtol, int
     return STH_OK;
 }
 
+int sth_speculate(sth_handle* h, int enable) {
+    if (!h) return fail(STH_EINVAL, "null handle");
+    h->speculate = enable != 0;
+    return STH_OK;
+}
+
 int sth_use_graphs(sth_handle* h, int enable) {
     if (!h) return fail(STH_EINVAL, "null handle");
     h->use_graph = enable != 0;
@@ -1329,6 +1539,11 @@ int sth_destroy(sth_handle* h) {
         for (double* q : *vec)
             if (q) (void)hipFree(q);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
+    if (h->hflag) (void)hipHostFree(h->hflag);
+    if (h->dthr) (void)hipFree(h->dthr);
+    if (h->dgo) (void)hipFree(h->dgo);
+    for (auto e : h->evring)
+        if (e) (void)hipEventDestroy(e);
     if (h->khost) (void)hipHostFree(h->khost);
     for (auto e : h->pool) (void)hipEventDestroy(e);
     delete h;

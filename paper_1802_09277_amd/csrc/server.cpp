@@ -87,6 +87,7 @@ struct Request {
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
+    hipEvent_t wait = nullptr;      // ev, or the solve's own event (a speculative cycle may follow it)
     Request* req = nullptr;
 };
 
@@ -279,7 +280,7 @@ bool advance(sth_server* s, Slot& sl, Request* r, bool* over) {
         return true;
     }
     if (st == St::Running || st == St::Finishing) {
-        hipError_t q = hipEventQuery(sl.ev);
+        hipError_t q = hipEventQuery(sl.wait ? sl.wait : sl.ev);
         if (q == hipErrorNotReady) return false;
         if (q != hipSuccess) {
             r->status = STH_EHIP;
@@ -309,6 +310,11 @@ bool advance(sth_server* s, Slot& sl, Request* r, bool* over) {
             st = St::Running;
         }
         if (rc == STH_OK && hipEventRecord(sl.ev, sl.st) != hipSuccess) rc = STH_EHIP;
+        sl.wait = sl.ev;
+        if (rc == STH_OK && st == St::Running) {
+            hipEvent_t w = sth::solve_wait_event(e->h);
+            if (w) sl.wait = w;
+        }
         if (rc) {
             r->status = rc;
             r->msg = sth_last_error();

@@ -24,4 +24,9 @@ int solve_result(sth_handle* h, int* iters, double* relres);
 // another thread may allocate or free device memory.
 void solve_allow_capture(sth_handle* h, bool allow);
 
+// The event to wait for before the next solve_continue, or nullptr for all
+// work enqueued on the solve's stream (a speculative solve keeps the next
+// cycle queued behind the one whose norm is read).
+hipEvent_t solve_wait_event(sth_handle* h);
+
 }  // namespace sth

@@ -340,3 +340,47 @@ def test_transform_tile_boundaries(name):
         assert rr <= 1e-12
         assert np.linalg.norm(host(u) - ud) <= 1e-10 * np.linalg.norm(ud), basis
         s.close()
+
+
+# ---------------------------------------------------------------------------
+# Speculative cycles (eigenbasis, fused cycle close): each cycle is enqueued
+# before its predecessor's norm has reached the host and is skipped on the
+# device when the predecessor may have converged.  The iterates, counts and
+# results must be those of the plain loop, eager or replayed, and the NaN and
+# maxit exits must behave as there.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["2d_16slabs", "2d_p1_net3", "3d_8slabs", "2d_ragged_p3"])
+def test_speculative_cycles_match_plain_loop(name):
+    banner(name, "speculation")
+    prob, mg = oracle_for(name)
+    s = eigen_solver_for(name)
+    f = dev(assemble_rhs(prob, W.random_modes(13, prob.dim)))
+    ud = mg.levels[0].forward_substitution(host(f))
+    stream = torch.cuda.Stream()
+    results = []
+    for spec, graphs in ((False, False), (True, False), (True, True), (True, True), (False, True)):
+        s.speculate(spec)
+        s.use_graphs(graphs)
+        with torch.cuda.stream(stream):
+            u = s.new_vector()
+            it, rr, _ = s.solve(f, u, rtol=1e-11, maxit=60, stream=stream)
+        stream.synchronize()
+        results.append((it, rr, host(u)))
+        print(f"  speculate={spec} graphs={graphs}: {it} cycles, relres {rr:.3e}")
+    s.speculate(True)
+    s.use_graphs(True)
+    for it, rr, u in results[1:]:
+        assert it == results[0][0] and rr == results[0][1]
+        assert np.array_equal(u, results[0][2])
+    assert results[0][1] <= 1e-11
+    assert np.linalg.norm(results[0][2] - ud) <= 1e-9 * np.linalg.norm(ud)
+    # exits: maxit (no cycle beyond it) and a non-finite right-hand side
+    for maxit in (1, 2, 3):
+        u = s.new_vector()
+        it, rr, code = s.solve(f, u, rtol=1e-30, maxit=maxit, check=False)
+        assert code == -6 and it == maxit
+    g = host(f).copy()
+    g[5] = np.nan
+    u = s.new_vector()
+    it, rr, code = s.solve(dev(g), u, rtol=1e-8, maxit=5, check=False)
+    assert code == -6 and it <= 1
