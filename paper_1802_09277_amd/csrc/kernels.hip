@@ -567,13 +567,22 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
     if (blockIdx.x < nimg) load_img(blockIdx.x);
     for (long img = blockIdx.x; img < nimg; img += gridDim.x) {
         __syncthreads();
+        int nz = 0;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k;
             if (i < NP * NP) Is[T::at(i / NP, i % NP)] = (CT)pre[k];
+            nz |= pre[k] != 0.0;
         }
         if (img + gridDim.x < nimg) load_img(img + gridDim.x);
-        __syncthreads();
+        // an image of zeros (e.g. a zero initial guess) maps to zeros
+        if (!__syncthreads_or(nz)) {
+            if (EPI != 1) {
+                double* dst = out + img * nn;
+                for (long i = tid; i < nn; i += 512) dst[i] = 0.0;
+            }
+            continue;
+        }
         acc_t acc[TPW];
         auto mma = [&](const Buf& x) {
 #pragma unroll
@@ -676,8 +685,9 @@ static hipError_t xform2d_go(const double* in, double* out, const double* Upad, 
     size_t shm = sizeof(CT) * 2 * (size_t)TileLds<CT, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
+        // exactly the dynamic size: the block-wide vote holds a little static LDS
         hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI, CORE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
