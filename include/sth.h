@@ -265,7 +265,8 @@ typedef enum {
                                restriction in one pass on the finest level */
     STH_K_EIG_CYCLE_CLOSE = 13, /* the same pass preceded by the prolongation and the
                                  post-smoothing step of the finest level */
-    STH_K_COUNT = 14
+    STH_K_EIG_COARSE = 14,  /* eigenbasis iteration: the two coarsest levels in one pass */
+    STH_K_COUNT = 15
 } sth_kernel_class;
 
 /* Record an event pair around every launch of the kernel classes whose bit

@@ -2092,6 +2092,146 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
     block_sum2(ssq, wsq, partial);
 }
 
+// The two coarsest levels of a V(1,1) cycle in one pass (a: second-coarsest
+// level with SA slabs, b: coarsest with SA/2 slabs), from the right-hand side
+// fa of level a alone:
+//   u  = omega A_a^{-1} fa                       (smoothing step from zero)
+//   fb = (P_t^T (x) I)(fa - L_a u) on slab pairs  ((1 - omega) fa + e_1 u_{s-1})
+//   ub = L_b^{-1} fb                              (exact, parallel in time)
+//   v  = u + (P_t (x) I) ub,  ua = v + omega A_a^{-1}(fa - L_a v)
+// A block holds 16 modes (one 128-byte line per time row) x G slab groups of
+// LA level-a and LA/2 level-b slabs per thread, kept in registers; the
+// coupling rows between groups, and the recurrence of the exact solve
+// (u_s = A^{-1} g_s + x_{s-1} A^{-1} e_1, x_s = a_s[N_t-1] + gamma x_{s-1}),
+// pass through LDS.  Only ua is written.
+template <int NT, bool SCHUR, int LAM>
+__global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_coarse_tail(int dim, const TimeMix* __restrict__ tma,
+                                                         const TimeMix* __restrict__ tmb,
+                                                         const double* __restrict__ ktmta,
+                                                         const double* __restrict__ mu1, int n, long Nx,
+                                                         const double* __restrict__ fa, double* __restrict__ ua,
+                                                         Transfer tr, double omega, int G, int LA,
+                                                         const int* guard) {
+    if (guard_off(guard)) return;
+    constexpr int MB = 16, LBM = LAM / 2;
+    __shared__ double xch[32][MB], xe_s[32][MB], gl_s[32][MB];
+    const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
+    const long m = (long)blockIdx.x * MB + ml;
+    const bool active = m < Nx;
+    const int LB = LA / 2;
+    const long slab = (long)NT * Nx;
+    const long sa0 = (long)g * LA;                 // first level-a slab of the group (even)
+    double u[LAM][NT], ub[LBM][NT];
+    double mu = 0.0, ulast = 0.0;
+    // (1) smoothing step from zero and restriction of its residual
+    if (active) {
+        mu = mode_shift(dim, mu1, n, m);
+#pragma unroll
+        for (int j = 0; j < LBM; ++j)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ub[j][t] = 0.0;
+#pragma unroll
+        for (int i = 0; i < LAM; ++i) {
+            if (i < LA) {
+                double f[NT], z[NT];
+                const long b = (sa0 + i) * slab + m;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) f[t] = fa[b + (long)t * Nx];
+                shifted_solve<NT, SCHUR>(*tma, mu, f, z);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    u[i][t] = omega * z[t];
+                    f[t] *= (1.0 - omega);
+                }
+                if (i > 0) f[0] += u[i - 1][NT - 1];
+                if (i == LA - 1) ulast = u[i][NT - 1];
+                const int h = i & 1;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) ub[i / 2][c] += tr.P[(h * NT + t) * kNt + c] * f[t];
+            }
+        }
+        xch[g][ml] = ulast;
+    }
+    __syncthreads();
+    if (active && g > 0) {
+        // coupling row of the group's first slab: the previous group's last
+        const double x0 = xch[g - 1][ml];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) ub[0][c] += tr.P[c] * x0;     // P^T row of t = 0, h = 0
+    }
+    // (2) exact solve on level b, parallel in time over the groups
+    double cb[NT], xe = 0.0, gl = 1.0;
+    if (active) {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(*tmb, mu, e1, cb);
+        const double gamma = cb[NT - 1];
+#pragma unroll
+        for (int j = 0; j < LBM; ++j) {
+            if (j < LB) {
+                double a[NT];
+                shifted_solve<NT, SCHUR>(*tmb, mu, ub[j], a);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) ub[j][t] = a[t];
+                xe = a[NT - 1] + gamma * xe;
+                gl *= gamma;
+            }
+        }
+    }
+    xe_s[g][ml] = xe;
+    gl_s[g][ml] = gl;
+    __syncthreads();
+    double vlast = 0.0;
+    if (active) {
+        double x = 0.0;
+        for (int h = 0; h < g; ++h) x = xe_s[h][ml] + gl_s[h][ml] * x;
+#pragma unroll
+        for (int j = 0; j < LBM; ++j) {
+            if (j < LB) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) ub[j][t] += x * cb[t];
+                x = ub[j][NT - 1];
+                if (j == LB - 1) {
+                    // prolonged coupling row of the group's last level-a slab (odd)
+                    vlast = ulast;
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) vlast += tr.P[(NT + NT - 1) * kNt + k] * ub[j][k];
+                }
+            }
+        }
+    }
+    __syncthreads();                               // xch is reused
+    if (active) xch[g][ml] = vlast;
+    __syncthreads();
+    if (!active) return;
+    // (3) prolongation and the post-smoothing step on level a
+    double q = g > 0 ? xch[g - 1][ml] : 0.0;
+#pragma unroll
+    for (int i = 0; i < LAM; ++i) {
+        if (i < LA) {
+            const int h = i & 1;
+            const long b = (sa0 + i) * slab + m;
+            double v[NT], r[NT], z[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double w = u[i][t];
+#pragma unroll
+                for (int k = 0; k < NT; ++k) w += tr.P[(h * NT + t) * kNt + k] * ub[i / 2][k];
+                v[t] = w;
+                r[t] = fa[b + (long)t * Nx];
+            }
+            eig_residual_point<NT>(ktmta, mu, v, q, r);
+            shifted_solve<NT, SCHUR>(*tma, mu, r, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ua[b + (long)t * Nx] = v[t] + omega * z[t];
+            q = v[NT - 1];
+        }
+    }
+}
+
 // Descent on a coarse level with a zero initial guess and one pre-smoothing
 // step, for one spatial mode and a chain of `chain` slabs (chain even,
 // starting at an even slab): u' = omega A^{-1} f (into uout) and the
@@ -2529,6 +2669,48 @@ hipError_t launch_multiaxpy(const double* V, long ld, int k, const double* c, do
     return hipGetLastError();
 }
 
+
+// groups and level-a slabs per thread of the two-level tail pass, or false
+// when the shape does not fit it
+bool coarse_tail_shape(int Nt, long SA, int* G, int* LA) {
+    if (SA < 4 || SA % 4) return false;
+    const long g = SA / 2 < 32 ? SA / 2 : 32;
+    if (SA % (2 * g)) return false;
+    const long la = SA / g;
+    if (la > (Nt <= 5 ? 8 : 4)) return false;
+    *G = (int)g;
+    *LA = (int)la;
+    return true;
+}
+
+hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
+                                  const double* ktmta, const double* mu1, int n, const double* fa, double* ua,
+                                  const Transfer& tr, double omega, long SA, hipStream_t st, const int* guard) {
+    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    int G = 0, LA = 0;
+    if (!coarse_tail_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
+#define STH_CT_GO(NTV, SC, LAMV)                                                                              \
+    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV>), grid, block, 0, st, dim, tma_dev, tmb_dev, ktmta, mu1, \
+                       n, Nx, fa, ua, tr, omega, G, LA, guard)
+#define STH_CT_LAM(NTV, SC)                                                                                  \
+    if (LA <= 2) STH_CT_GO(NTV, SC, 2);                                                                      \
+    else if (LA <= 4) STH_CT_GO(NTV, SC, 4);                                                                 \
+    else if (NTV <= 5) STH_CT_GO(NTV, SC, (NTV <= 5 ? 8 : 4));                                               \
+    else return hipErrorInvalidValue;
+#define STH_CT_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (schur) { STH_CT_LAM(NTV, true) } else { STH_CT_LAM(NTV, false) }                              \
+            break;
+    switch (Nt) {
+        STH_CT_CASE(2) STH_CT_CASE(3) STH_CT_CASE(4) STH_CT_CASE(5) STH_CT_CASE(6) STH_CT_CASE(7) STH_CT_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_CT_CASE
+#undef STH_CT_LAM
+#undef STH_CT_GO
+    return hipGetLastError();
+}
 
 hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                            const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,

@@ -120,6 +120,17 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const CycleFlag& flag = CycleFlag{});
 //  *flag = value, and *thr = thr_value when thr is not null and thr_value >= 0
 hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr = nullptr, double thr_value = -1.0);
+//  the two coarsest levels of a V(1,1) cycle in one pass from level a's
+//  right-hand side fa (SA slabs; level b has SA/2): smoothing step from zero,
+//  restriction of its residual, exact solve of level b, prolongation and the
+//  post-smoothing step; ua = level a's result (fa and ua differ).  The
+//  per-level slab inverses are device copies, both of the same form (schur).
+//  coarse_tail_shape says whether SA fits (slab groups of 2..8 level-a slabs).
+bool coarse_tail_shape(int Nt, long SA, int* G, int* LA);
+hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
+                                  const double* ktmta, const double* mu1, int n, const double* fa, double* ua,
+                                  const Transfer& tr, double omega, long SA, hipStream_t st,
+                                  const int* guard = nullptr);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);

@@ -68,6 +68,8 @@ struct sth_handle {
     double* e2 = nullptr;
     double* e3 = nullptr;               // third level-0 iterate buffer of the fused cycle close
     bool fuse_close = false;            // post-smoothing of level 0 fused into the cycle-end pass
+    bool fuse_tail = false;             // the two coarsest levels in one pass (k_eig_coarse_tail)
+    TimeMix* dmix = nullptr;            // per level slab inverse in device memory
     bool defer_close = false;           // set by a solve iteration: level 0 leaves its post-smoothing
     const double* pending_ec = nullptr; // coarse correction waiting for the fused cycle close
     int pre_idx = 1;                    // level-0 buffer of the pre-smoothed iterate
@@ -474,6 +476,17 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         return STH_OK;
     }
     int rc;
+    if (lvl == h->L - 2 && lvl > 0 && zero_guess && h->fuse_tail) {
+        // descent, exact coarsest solve and post-smoothing of the last two
+        // levels from this level's right-hand side in one pass
+        double dof = (double)S * slab_len(h);
+        Timed tm(h, STH_K_EIG_COARSE, dof * (16.0 * h->Nt + 12.0), 16.0 * dof, st);
+        HIPCHK(launch_eig_coarse_tail(h->dim, h->Nt, h->dmix + lvl, h->dmix + lvl + 1, h->mixes[lvl].schur != 0,
+                                      level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl), eig_u(h, lvl, 0), h->tr,
+                                      h->omega, S, st, h->guard));
+        h->ecur[lvl] = 0;
+        return STH_OK;
+    }
     if (zero_guess && h->nu_pre == 0) {
         HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * slab_len(h), 0.0, st));
         zero_guess = false;
@@ -700,7 +713,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
         S /= 2;
         total += vecsl * sizeof(double) * (size_t)S * slab;
     }
-    total += sizeof(double) * (kNormBlocks + 4 + L * 2 * kNt * kNt);
+    total += sizeof(double) * (kNormBlocks + 6 + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
     *bytes = total;
     return STH_OK;
 }
@@ -746,6 +759,12 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->L = (int)h->S.levels.size();
     h->nb_lo = std::pow(h->S.m1_min, h->dim);
     h->fuse_close = fused_cycle_close(q, (size_t)h->L);
+    {
+        int G = 0, LA = 0;
+        h->fuse_tail = h->basis == 1 && h->nu_pre == 1 && h->nu_post == 1 && h->L >= 3 &&
+                       h->S.levels[h->L - 2].schur == h->S.levels[h->L - 1].schur &&
+                       coarse_tail_shape(h->Nt, h->S.levels[h->L - 2].S, &G, &LA);
+    }
     for (auto& lv : h->S.levels) {
         h->lev_S.push_back(lv.S);
         TimeOp op{};
@@ -818,6 +837,11 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         if (h->basis == 1 && !dalloc(&h->lu2[l], (size_t)h->lev_S[l] * slab))
             return cleanup(STH_ENOMEM, "device allocation failed");
     }
+    if (hipMalloc((void**)&h->dmix, sizeof(TimeMix) * h->mixes.size()) != hipSuccess)
+        return cleanup(STH_ENOMEM, "device allocation failed");
+    if (hipMemcpyAsync(h->dmix, h->mixes.data(), sizeof(TimeMix) * h->mixes.size(), hipMemcpyHostToDevice, s) !=
+        hipSuccess)
+        return cleanup(STH_EHIP, "upload of the setup failed");
     std::vector<double> Cf, Ci, Gf;
     if (h->basis == 1) {
         // C = M_1 U = U^{-T} (from U^T M_1 U = I)
@@ -1541,6 +1565,7 @@ int sth_destroy(sth_handle* h) {
     if (h->hnorm) (void)hipHostFree(h->hnorm);
     if (h->hflag) (void)hipHostFree(h->hflag);
     if (h->dthr) (void)hipFree(h->dthr);
+    if (h->dmix) (void)hipFree(h->dmix);
     if (h->dgo) (void)hipFree(h->dgo);
     for (auto e : h->evring)
         if (e) (void)hipEventDestroy(e);
