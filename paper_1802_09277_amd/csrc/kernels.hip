@@ -1459,8 +1459,52 @@ hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const d
 // ---------------------------------------------------------------------------
 // temporal transform and shifted divide
 // ---------------------------------------------------------------------------
+// Reciprocals of the shifted diagonal blocks of one spatial mode, formed
+// once per mode so that each slab solve of the mode is free of divisions.
+// Eigen form: 1/det(Z_j + mu I) of the fixed 2x2 block j in slot 2j, and
+// 1/(Z_kk + mu) of a trailing 1x1 block.  Schur form: 1/(R_kk + mu) for a
+// 1x1 block, 1/det of the shifted 2x2 block in the slot of its second row.
+template <int NT>
+struct ModeShift {
+    double mu;
+    double rinv[NT];
+};
+
 template <int NT, bool SCHUR>
-__device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, const double* g, double* z) {
+__device__ __forceinline__ ModeShift<NT> mode_shift_inv(const TimeMix& tm, double mu) {
+    ModeShift<NT> s;
+    s.mu = mu;
+    if (SCHUR) {
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            double d = 1.0;
+            if (tm.kind[k] == 0) {
+                d = tm.R[k * kNt + k] + mu;
+            } else if (tm.kind[k] == 2 && k >= 1) {
+                const double a = tm.R[(k - 1) * kNt + k - 1] + mu, b = tm.R[(k - 1) * kNt + k];
+                const double c = tm.R[k * kNt + k - 1], e = tm.R[k * kNt + k] + mu;
+                d = a * e - b * c;
+            }
+            s.rinv[k] = 1.0 / d;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k + 1 < NT; k += 2) {
+            const double det = (tm.zd[k] + mu) * (tm.zd[k + 1] + mu) - tm.zo[k] * tm.zo[k + 1];
+            s.rinv[k] = 1.0 / det;
+            s.rinv[k + 1] = 0.0;
+        }
+        if (NT % 2) s.rinv[NT - 1] = 1.0 / (tm.zd[NT - 1] + mu);
+    }
+    return s;
+}
+
+// z = A_m^{-1} g for one slab and spatial mode: h = W g, the shifted block
+// diagonal (eigen form) or quasi-triangular (Schur form) system, z = V y.
+template <int NT, bool SCHUR>
+__device__ __forceinline__ void shifted_solve(const TimeMix& tm, const ModeShift<NT>& sh, const double* g,
+                                              double* z) {
+    const double mu = sh.mu;
     double h[NT], y[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) h[t] = 0.0;
@@ -1479,7 +1523,7 @@ __device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, cons
                 double r = h[k];
 #pragma unroll
                 for (int j = k + 1; j < NT; ++j) r -= tm.R[k * kNt + j] * y[j];
-                y[k] = r / (tm.R[k * kNt + k] + mu);
+                y[k] = r * sh.rinv[k];
             } else if (k >= 1) {                                 // rows k-1, k
                 double r0 = h[k - 1], r1 = h[k];
 #pragma unroll
@@ -1489,23 +1533,18 @@ __device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, cons
                 }
                 const double a = tm.R[(k - 1) * kNt + k - 1] + mu, b = tm.R[(k - 1) * kNt + k];
                 const double c = tm.R[k * kNt + k - 1], d = tm.R[k * kNt + k] + mu;
-                const double det = a * d - b * c;
-                y[k - 1] = (d * r0 - b * r1) / det;
-                y[k] = (a * r1 - c * r0) / det;
+                y[k - 1] = (d * r0 - b * r1) * sh.rinv[k];
+                y[k] = (a * r1 - c * r0) * sh.rinv[k];
             }
         }
     } else {
+        // fixed 2x2 blocks: [[p + mu, q], [r, s + mu]]^{-1} = [[s + mu, -q], [-r, p + mu]] / det
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (tm.kind[k] == 0) {
-                y[k] = h[k] / (tm.re[k] + mu);
-            } else if (tm.kind[k] == 1 && k + 1 < NT) {
-                double a = tm.re[k] + mu, b = tm.im[k];
-                double det = a * a + b * b;
-                y[k] = (a * h[k] - b * h[k + 1]) / det;
-                y[k + 1] = (b * h[k] + a * h[k + 1]) / det;
-            }
+        for (int k = 0; k + 1 < NT; k += 2) {
+            y[k] = ((tm.zd[k + 1] + mu) * h[k] - tm.zo[k] * h[k + 1]) * sh.rinv[k];
+            y[k + 1] = ((tm.zd[k] + mu) * h[k + 1] - tm.zo[k + 1] * h[k]) * sh.rinv[k];
         }
+        if (NT % 2) y[NT - 1] = h[NT - 1] * sh.rinv[NT - 1];
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -1514,6 +1553,12 @@ __device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, cons
         for (int k = 0; k < NT; ++k) v += tm.V[t * kNt + k] * y[k];
         z[t] = v;
     }
+}
+
+// one solve for a mode: the reciprocals are formed on the spot
+template <int NT, bool SCHUR>
+__device__ __forceinline__ void shifted_solve(const TimeMix& tm, double mu, const double* g, double* z) {
+    shifted_solve<NT, SCHUR>(tm, mode_shift_inv<NT, SCHUR>(tm, mu), g, z);
 }
 
 __device__ __forceinline__ double mode_shift(int dim, const double* mu1, int n, long m) {
@@ -1569,10 +1614,11 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
     double mu = 0.0;
     if (active) {
         mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
         double e1[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
-        shifted_solve<NT, SCHUR>(tm, mu, e1, c);
+        shifted_solve<NT, SCHUR>(tm, sh, e1, c);
         gamma = c[NT - 1];
         if (inreg) {
             // all loads of the group first, then the (independent) solves
@@ -1587,7 +1633,7 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
             for (int i = 0; i < LR; ++i)
                 if (sb + i < se) {
                     double a[NT];
-                    shifted_solve<NT, SCHUR>(tm, mu, areg[i], a);
+                    shifted_solve<NT, SCHUR>(tm, sh, areg[i], a);
 #pragma unroll
                     for (int t = 0; t < NT; ++t) areg[i][t] = a[t];
                     xe = a[NT - 1] + gamma * xe;  // group recurrence from x = 0
@@ -1599,7 +1645,7 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
             double gv[NT], a[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) gv[t] = gp[(long)t * Nx];
-            shifted_solve<NT, SCHUR>(tm, mu, gv, a);
+            shifted_solve<NT, SCHUR>(tm, sh, gv, a);
             double* o = out + s * NT * Nx + m;
 #pragma unroll
             for (int t = 0; t < NT; ++t) o[(long)t * Nx] = a[t];
@@ -1832,6 +1878,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const double mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
         const double wm = mode_weight(dim, vw, n, m);
         const long s0 = q * chain;
         double prev_old = 0.0, prev_new = 0.0;
@@ -1844,7 +1891,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                 u[t] = uin[b + (long)t * Nx];
             }
             eig_residual_point<NT>(ktmt, mu, u, s0 > 1 ? uin[b - Nx] : 0.0, g);
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
             prev_old = u[NT - 1];
             prev_new = u[NT - 1] + omega * z[NT - 1];
         }
@@ -1882,7 +1929,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
             for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
             ssq += s2;
             wsq += wm * s2;
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 up[t] = u[t] + omega * z[t];
@@ -1955,6 +2002,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const double mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
         const double wm = mode_weight(dim, vw, n, m);
         const long s0 = q * chain;
         const long slab = (long)NT * Nx;
@@ -1982,7 +2030,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             }
             prolong_add<NT>(tr, 0, c, u1);
             eig_residual_point<NT>(ktmt, mu, u1, q1, g);
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
             const double a1 = u1[NT - 1], a2 = u1[NT - 1] + omega * z[NT - 1];
             // slab s0 - 1 (second half of the same coarse slab): both steps
             const long bb = (s0 - 1) * slab + m;
@@ -1993,7 +2041,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             }
             prolong_add<NT>(tr, 1, c, u1);
             eig_residual_point<NT>(ktmt, mu, u1, a1, g);
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
             double u2[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -2001,7 +2049,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
                 g[t] *= (1.0 - omega);
             }
             g[0] += up_prev_delta(a2, a1);
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
             p1 = u1[NT - 1];
             p2 = u2[NT - 1];
             p3 = u2[NT - 1] + omega * z[NT - 1];
@@ -2047,7 +2095,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             // post-smoothing step from the prolonged iterate
             prolong_add<NT>(tr, h, c, u1);
             eig_residual_point<NT>(ktmt, mu, u1, p1, g);
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 u2[t] = u1[t] + omega * z[t];
@@ -2061,7 +2109,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
             ssq += s2;
             wsq += wm * s2;
-            shifted_solve<NT, SCHUR>(tm, mu, g, z);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
             double u3last = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -2099,6 +2147,10 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 //   fb = (P_t^T (x) I)(fa - L_a u) on slab pairs  ((1 - omega) fa + e_1 u_{s-1})
 //   ub = L_b^{-1} fb                              (exact, parallel in time)
 //   v  = u + (P_t (x) I) ub,  ua = v + omega A_a^{-1}(fa - L_a v)
+// Since A_a u = omega fa, the last step needs neither fa nor a solve:
+// fa - L_a v = (1 - omega) fa - A_a (P_t ub) + e_1 q with q the last time
+// row of the previous slab of v, so
+//   ua = (2 - omega) u + (1 - omega)(P_t (x) I) ub + omega q A_a^{-1} e_1.
 // A block holds 16 modes (one 128-byte line per time row) x G slab groups of
 // LA level-a and LA/2 level-b slabs per thread, kept in registers; the
 // coupling rows between groups, and the recurrence of the exact solve
@@ -2107,7 +2159,6 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 template <int NT, bool SCHUR, int LAM>
 __global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_coarse_tail(int dim, const TimeMix* __restrict__ tma,
                                                          const TimeMix* __restrict__ tmb,
-                                                         const double* __restrict__ ktmta,
                                                          const double* __restrict__ mu1, int n, long Nx,
                                                          const double* __restrict__ fa, double* __restrict__ ua,
                                                          Transfer tr, double omega, int G, int LA,
@@ -2207,27 +2258,32 @@ __global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_co
     if (active) xch[g][ml] = vlast;
     __syncthreads();
     if (!active) return;
-    // (3) prolongation and the post-smoothing step on level a
+    // (3) prolongation and the post-smoothing step on level a (closed form)
+    double ca[NT];
+    {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(*tma, mu, e1, ca);
+    }
     double q = g > 0 ? xch[g - 1][ml] : 0.0;
 #pragma unroll
     for (int i = 0; i < LAM; ++i) {
         if (i < LA) {
             const int h = i & 1;
             const long b = (sa0 + i) * slab + m;
-            double v[NT], r[NT], z[NT];
+            double pu[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                double w = u[i][t];
+                double w = 0.0;
 #pragma unroll
                 for (int k = 0; k < NT; ++k) w += tr.P[(h * NT + t) * kNt + k] * ub[i / 2][k];
-                v[t] = w;
-                r[t] = fa[b + (long)t * Nx];
+                pu[t] = w;
             }
-            eig_residual_point<NT>(ktmta, mu, v, q, r);
-            shifted_solve<NT, SCHUR>(*tma, mu, r, z);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) ua[b + (long)t * Nx] = v[t] + omega * z[t];
-            q = v[NT - 1];
+            for (int t = 0; t < NT; ++t)
+                ua[b + (long)t * Nx] = (2.0 - omega) * u[i][t] + (1.0 - omega) * pu[t] + omega * q * ca[t];
+            q = u[i][NT - 1] + pu[NT - 1];
         }
     }
 }
@@ -2249,6 +2305,7 @@ __global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const dou
     if (idx >= total) return;
     const long q = idx / Nx, m = idx % Nx;
     const double mu = mode_shift(dim, mu1, n, m);
+    const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
     const long s0 = q * chain;
     double prev = 0.0;
     if (s0 > 0) {
@@ -2256,7 +2313,7 @@ __global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const dou
         double g[NT], z[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) g[t] = fl[b + (long)t * Nx];
-        shifted_solve<NT, SCHUR>(tm, mu, g, z);
+        shifted_solve<NT, SCHUR>(tm, sh, g, z);
         prev = omega * z[NT - 1];
     }
     double fnx[NT], acc[NT];
@@ -2273,7 +2330,7 @@ __global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const dou
 #pragma unroll
             for (int t = 0; t < NT; ++t) fnx[t] = fl[b + NT * Nx + (long)t * Nx];
         }
-        shifted_solve<NT, SCHUR>(tm, mu, g, z);
+        shifted_solve<NT, SCHUR>(tm, sh, g, z);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             up[t] = omega * z[t];
@@ -2684,14 +2741,14 @@ bool coarse_tail_shape(int Nt, long SA, int* G, int* LA) {
 }
 
 hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
-                                  const double* ktmta, const double* mu1, int n, const double* fa, double* ua,
+                                  const double* mu1, int n, const double* fa, double* ua,
                                   const Transfer& tr, double omega, long SA, hipStream_t st, const int* guard) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
     int G = 0, LA = 0;
     if (!coarse_tail_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
     dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
 #define STH_CT_GO(NTV, SC, LAMV)                                                                              \
-    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV>), grid, block, 0, st, dim, tma_dev, tmb_dev, ktmta, mu1, \
+    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV>), grid, block, 0, st, dim, tma_dev, tmb_dev, mu1, \
                        n, Nx, fa, ua, tr, omega, G, LA, guard)
 #define STH_CT_LAM(NTV, SC)                                                                                  \
     if (LA <= 2) STH_CT_GO(NTV, SC, 2);                                                                      \

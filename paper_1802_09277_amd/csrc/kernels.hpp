@@ -16,9 +16,14 @@ struct TimeOp {                 // residual: temporal matrices of the level
 struct TimeMix {                // slab inverse: temporal decomposition of the level
     double W[kNt * kNt];
     double V[kNt * kNt];
-    double re[kNt];
-    double im[kNt];
-    int kind[kNt];              // 0 real / 1x1 block, 1 first of a pair / 2x2 block, 2 second
+    // eigen form (schur == 0): A^{-1} = V (Z + mu I)^{-1} W with Z block
+    // diagonal in fixed 2x2 blocks (rows 2j, 2j+1; a complex pair
+    // [[a, b], [-b, a]] or two real eigenvalues) and a trailing 1x1 block
+    // when Nt is odd; zd[k] = Z[k][k], zo[k] = the other entry of row k in
+    // its block (0 for a 1x1 block)
+    double zd[kNt];
+    double zo[kNt];
+    int kind[kNt];              // Schur form: 0 1x1 block, 1 first row of a 2x2 block, 2 second row
     int schur;                  // 1: (R + mu I) y = W g by block back substitution
     double R[kNt * kNt];        // real Schur form (quasi upper triangular)
 };
@@ -128,7 +133,7 @@ hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr = n
 //  coarse_tail_shape says whether SA fits (slab groups of 2..8 level-a slabs).
 bool coarse_tail_shape(int Nt, long SA, int* G, int* LA);
 hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
-                                  const double* ktmta, const double* mu1, int n, const double* fa, double* ua,
+                                  const double* mu1, int n, const double* fa, double* ua,
                                   const Transfer& tr, double omega, long SA, hipStream_t st,
                                   const int* guard = nullptr);
 //  rh = fh - L uh

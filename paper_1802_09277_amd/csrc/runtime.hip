@@ -480,9 +480,9 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         // descent, exact coarsest solve and post-smoothing of the last two
         // levels from this level's right-hand side in one pass
         double dof = (double)S * slab_len(h);
-        Timed tm(h, STH_K_EIG_COARSE, dof * (16.0 * h->Nt + 12.0), 16.0 * dof, st);
+        Timed tm(h, STH_K_EIG_COARSE, dof * (10.0 * h->Nt + 11.0), 16.0 * dof, st);
         HIPCHK(launch_eig_coarse_tail(h->dim, h->Nt, h->dmix + lvl, h->dmix + lvl + 1, h->mixes[lvl].schur != 0,
-                                      level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl), eig_u(h, lvl, 0), h->tr,
+                                      h->mu1, h->n, eig_f(h, lvl), eig_u(h, lvl, 0), h->tr,
                                       h->omega, S, st, h->guard));
         h->ecur[lvl] = 0;
         return STH_OK;
@@ -769,18 +769,36 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         h->lev_S.push_back(lv.S);
         TimeOp op{};
         TimeMix tm{};
+        // eigen form: complex pairs first, so that each occupies an aligned
+        // 2x2 block, then the real eigenvalues (slot k holds column perm[k])
+        std::vector<int> perm;
+        if (!lv.schur) {
+            for (int i = 0; i < h->Nt; ++i)
+                if (lv.kind[i] == 1) { perm.push_back(i); perm.push_back(i + 1); }
+            for (int i = 0; i < h->Nt; ++i)
+                if (lv.kind[i] == 0) perm.push_back(i);
+        } else {
+            for (int i = 0; i < h->Nt; ++i) perm.push_back(i);
+        }
+        if ((int)perm.size() != h->Nt) {
+            delete h;
+            return fail(STH_ECOND, "temporal eigen form: unpaired complex eigenvalue");
+        }
         for (int i = 0; i < h->Nt; ++i) {
+            const int pi = perm[i];
             for (int j = 0; j < h->Nt; ++j) {
                 op.Kt[i * kNt + j] = lv.Kt(i, j);
                 op.Mt[i * kNt + j] = lv.Mt(i, j);
-                tm.W[i * kNt + j] = lv.W(i, j);
-                tm.V[i * kNt + j] = lv.V(i, j);
+                tm.W[i * kNt + j] = lv.W(pi, j);
+                tm.V[i * kNt + j] = lv.V(i, perm[j]);
             }
-            tm.re[i] = lv.re[i];
-            tm.im[i] = lv.im[i];
-            tm.kind[i] = lv.kind[i];
-            if (lv.schur)
+            if (lv.schur) {
+                tm.kind[i] = lv.kind[i];
                 for (int j = 0; j < h->Nt; ++j) tm.R[i * kNt + j] = lv.R(i, j);
+            } else {
+                tm.zd[i] = lv.re[pi];
+                tm.zo[i] = lv.kind[pi] == 0 ? 0.0 : lv.im[pi];
+            }
         }
         tm.schur = lv.schur ? 1 : 0;
         h->ops.push_back(op);
