@@ -1972,7 +1972,8 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 //   fc = (P_t^T (x) I)[r(u3)_{2k}; r(u3)_{2k+1}]   (restriction)
 // The residuals after a smoothing step follow from the identity
 // r(u + omega A^{-1} g)_s = (1 - omega) g_s + e_1 (delta of the coupling row
-// of slab s-1), so every slab needs two slab solves.  The coupling rows of
+// of slab s-1), and with it A^{-1} r(u2) = (1 - omega) A^{-1} r(u1) +
+// delta A^{-1} e_1, so every slab needs one slab solve.  The coupling rows of
 // the previous slab (u1, u2, u3) are carried along the chain; a chain after
 // slab 0 first repeats the two steps of its two preceding slabs.
 template <int NT>
@@ -2003,6 +2004,14 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
         const long q = idx / Nx, m = idx % Nx;
         const double mu = mode_shift(dim, mu1, n, m);
         const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
+        // ca = A^{-1} e_1: a change of the coupling row moves A^{-1} r by a multiple of it
+        double ca[NT];
+        {
+            double e1[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+            shifted_solve<NT, SCHUR>(tm, sh, e1, ca);
+        }
         const double wm = mode_weight(dim, vw, n, m);
         const long s0 = q * chain;
         const long slab = (long)NT * Nx;
@@ -2042,17 +2051,11 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             prolong_add<NT>(tr, 1, c, u1);
             eig_residual_point<NT>(ktmt, mu, u1, a1, g);
             shifted_solve<NT, SCHUR>(tm, sh, g, z);
-            double u2[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                u2[t] = u1[t] + omega * z[t];
-                g[t] *= (1.0 - omega);
-            }
-            g[0] += up_prev_delta(a2, a1);
-            shifted_solve<NT, SCHUR>(tm, sh, g, z);
+            const double u2last = u1[NT - 1] + omega * z[NT - 1];
+            const double z2last = (1.0 - omega) * z[NT - 1] + up_prev_delta(a2, a1) * ca[NT - 1];
             p1 = u1[NT - 1];
-            p2 = u2[NT - 1];
-            p3 = u2[NT - 1] + omega * z[NT - 1];
+            p2 = u2last;
+            p3 = u2last + omega * z2last;
         }
         // the next slab's f^ and u^ (and the next pair's ec) are loaded while
         // the current one is processed
@@ -2102,18 +2105,19 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
                 uend[b + (long)t * Nx] = u2[t];
                 g[t] *= (1.0 - omega);
             }
-            g[0] += up_prev_delta(p2, p1);
+            const double d2 = up_prev_delta(p2, p1);
+            g[0] += d2;
             // residual of the cycle's result, then the next smoothing step
+            // with A^{-1} r(u2) = (1 - omega) z + d2 ca
             double s2 = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
             ssq += s2;
             wsq += wm * s2;
-            shifted_solve<NT, SCHUR>(tm, sh, g, z);
             double u3last = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                const double u3 = u2[t] + omega * z[t];
+                const double u3 = u2[t] + omega * ((1.0 - omega) * z[t] + d2 * ca[t]);
                 unext[b + (long)t * Nx] = u3;
                 if (t == NT - 1) u3last = u3;
                 g[t] *= (1.0 - omega);
