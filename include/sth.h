@@ -179,7 +179,9 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
 int sth_solve_fgmres(sth_handle* h, const double* f, double* u, double rtol, int maxit, int restart,
                      int* iters, double* relres, void* stream);
 
-/* Graph replay of the solve iterations (default on): on a non-default
+/* Graph replay of the solve iterations (default off: on this hardware the
+ * boundaries between replayed graphs cost more than individual launches
+ * of the few kernels of a cycle): on a non-default
  * stream sth_solve captures one iteration (V-cycle, residual, norm, scalar
  * read) into a HIP graph for the given (f, u) and replays it (on any
  * stream; a new f or u, or a change of the timing mask, recaptures).
@@ -195,8 +197,9 @@ int sth_use_graphs(sth_handle* h, int enable);
  * when it may have converged every kernel of the next cycle returns at
  * once and the exact norm decides, so the cycles, iterates and counts are
  * those of the plain loop (the stopping test of Section 4.4) without a host
- * round trip between cycles.  enable = 0 waits for each norm first; so does
- * kernel timing. */
+ * round trip between cycles.  The first cycles follow the initial residual
+ * pass the same way (its threshold (rtol ||f||)^2 formed on the device).
+ * enable = 0 waits for each norm first; so does kernel timing. */
 int sth_speculate(sth_handle* h, int enable);
 
 /* Level transfers (Section 3.1, time coarsening by combining two slabs):

@@ -300,7 +300,7 @@ class Solver:
         return u
 
     def use_graphs(self, enable):
-        """Graph replay of solve iterations on non-default streams (default on)."""
+        """Graph replay of solve iterations on non-default streams (default off)."""
         _check(self.lib.sth_use_graphs(self.h, int(enable)))
 
     def speculate(self, enable):

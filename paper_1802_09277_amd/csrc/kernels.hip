@@ -1317,7 +1317,14 @@ __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ 
 __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ partial, int count, double* out,
                                                       double* out_host, int nsum = 1, const int* guard = nullptr,
                                                       CycleFlag flag = CycleFlag{}) {
-    if (guard_off(guard)) return;
+    if (guard_off(guard)) {
+        // a skipped cycle stops the cycles guarded by its own flag too
+        if (flag.dev && threadIdx.x == 0) {
+            *flag.dev = 0;
+            *flag.host = 0;
+        }
+        return;
+    }
     __shared__ double sh[256];
     __shared__ double res[2];
     for (int j = 0; j < nsum; ++j) {
@@ -1352,6 +1359,22 @@ __global__ void k_set_flag(int* flag, int value, double* thr, double thr_value) 
         *flag = value;
         if (thr && thr_value >= 0.0) *thr = thr_value;
     }
+}
+
+// *thr = (rtol ||f||)^2 from f2 = ||f||^2, with ||f|| taken as 1 when it is
+// 0 (the same operations as the host's stopping test)
+__global__ void k_spec_threshold(double* thr, const double* f2, double rtol) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double fn = sqrt(f2[0]);
+        if (fn == 0.0) fn = 1.0;
+        const double t = rtol * fn;
+        *thr = t * t;
+    }
+}
+
+hipError_t launch_spec_threshold(double* thr, const double* f2, double rtol, hipStream_t st) {
+    hipLaunchKernelGGL(k_spec_threshold, dim3(1), dim3(64), 0, st, thr, f2, rtol);
+    return hipGetLastError();
 }
 
 hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr, double thr_value) {
@@ -2594,9 +2617,11 @@ hipError_t launch_rhs(int dim, int Nt, int n, int n_modes, const double* Tpart, 
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
-                                long max_partial, double* out, double* out_host, hipStream_t st) {
+                                long max_partial, double* out, double* out_host, hipStream_t st,
+                                const CycleFlag& flag) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
+    if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
     if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
@@ -2615,7 +2640,8 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
 #undef STH_CE_CASE
         default: return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2, nullptr,
+                       flag);
     return hipGetLastError();
 }
 

@@ -36,7 +36,8 @@ struct Transfer {               // 2Nt x Nt prolongation
 // of a cycle-close pass with a CycleFlag stores 1 there (and in the mapped
 // host copy) when the lower bound of its B-spline residual,
 // max(nb_lo ||r^||^2, (1 - 1e-8) sum_m v_m r^_m^2), exceeds *thr =
-// (rtol ||f||)^2, and 0 otherwise (possible convergence, or non-finite).
+// (rtol ||f||)^2, and 0 otherwise (possible convergence, or non-finite); a
+// skipped sum stores 0.
 struct CycleFlag {
     int* dev = nullptr;
     int* host = nullptr;           // mapped pinned host memory
@@ -111,7 +112,8 @@ hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktm
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
-                                long max_partial, double* out, double* out_host, hipStream_t st);
+                                long max_partial, double* out, double* out_host, hipStream_t st,
+                                const CycleFlag& flag = CycleFlag{});
 //  close of a cycle on the finest level and start of the next in one pass
 //  (chains and sums as above): u1 = upre + (P_t (x) I) ec, uend = u1 +
 //  omega A^{-1}(fh - L u1) (the cycle's result), the two sums of
@@ -123,6 +125,8 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const double* vw, double* partial, long max_partial, double* out,
                                   double* out_host, hipStream_t st, const int* guard = nullptr,
                                   const CycleFlag& flag = CycleFlag{});
+//  *thr = (rtol max(||f||, 1 if ||f|| = 0))^2 from f2 = ||f||^2 (device scalars)
+hipError_t launch_spec_threshold(double* thr, const double* f2, double rtol, hipStream_t st);
 //  *flag = value, and *thr = thr_value when thr is not null and thr_value >= 0
 hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr = nullptr, double thr_value = -1.0);
 //  the two coarsest levels of a V(1,1) cycle in one pass from level a's

@@ -106,7 +106,7 @@ struct sth_handle {
     std::vector<hipEvent_t> pool;
     size_t pool_used = 0;
     // graph of one solve iteration (V-cycle, residual, norm, scalar read)
-    bool use_graph = true;
+    bool use_graph = false;
     bool capturing = false;
     // two cached graphs: the fused cycle close alternates its level-0
     // buffers, so consecutive iterations start from two different states
@@ -143,13 +143,14 @@ struct sth_handle {
         double rtol = 0.0, fn = 1.0, rn = 0.0, prev = 0.0;
         int maxit = 0, it = 0, growth = 0;
         // 0 initial norms enqueued, 1 iterating, 2 result enqueued, 3 exact
-        // B-spline norm of the current eigenbasis iterate enqueued
+        // B-spline norm of the current eigenbasis iterate enqueued, 4 initial
+        // norms enqueued with the first cycles behind them (speculation)
         int phase = 0;
         // speculation: the cycle waited for (a) and the guarded one behind it (b)
         bool spec = false;
         int pend = 0;
         bool drain = false;
-        Snap a, b;
+        Snap a, b, s0;                  // s0: state after the initial norms
         hipEvent_t ev_a = nullptr, ev_b = nullptr;
     } sv;
     // speculative cycles (eigenbasis, fused cycle close)
@@ -160,6 +161,7 @@ struct sth_handle {
     int* hflag_dev = nullptr;
     double* dthr = nullptr;             // (rtol ||f||)^2 of the solve in progress (device)
     int last_slot = 0;                  // norm slot of the last enqueued cycle end
+    bool first_flag = false;            // the initial residual pass sets the flag of slot 0
     hipEvent_t evring[4] = {nullptr, nullptr, nullptr, nullptr};
     int evnext = 0;
     hipEvent_t wait_ev = nullptr;       // event the caller waits for before solve_continue
@@ -573,10 +575,12 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         const double Nt = h->Nt;
         const int o = c == 0 ? 1 : 0;   // buffer of the pre-smoothed iterate
         Timed tm(h, STH_K_EIG_CYCLE_END, dof * (12.0 * Nt + 10.0), 28.0 * dof, st);
+        CycleFlag flag;
+        if (h->first_flag) flag = CycleFlag{h->dgo, h->hflag_dev, h->dthr, h->nb_lo};
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, o), eig_f(h, 1), h->tr, h->omega, S,
                                     chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + 2,
-                                    h->hnorm_dev + 2, st));
+                                    h->hnorm_dev + 2, st, flag));
         h->wsum_valid = true;
         h->last_slot = 0;
         h->pre_idx = o;
@@ -1112,6 +1116,9 @@ namespace sth {
 // them the caller waits for the stream (sth_solve) or polls an event (the
 // serving loop).  solve_begin: ||f||^2 and the initial residual norm^2 to
 // the pinned host scalars.
+static sth_handle::Snap take_snap(const sth_handle* h);
+static int spec_enqueue(sth_handle* h);
+
 int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxit, hipStream_t st) {
     if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
     auto& v = h->sv;
@@ -1141,7 +1148,19 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
         h->ecur[0] = 0;
         if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st))) return rc;
         if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) return rc;
-        return eig_residual_cheap(h, st);
+        if (!v.spec || maxit < 1) return eig_residual_cheap(h, st);
+        // speculation from the start: the threshold on the device, the
+        // initial pass sets the flag that guards the first cycle, and the
+        // first cycles go behind it without waiting for the norms
+        HIPCHK(launch_spec_threshold(h->dthr, h->dnorm + 1, rtol, st));
+        h->first_flag = true;
+        rc = eig_residual_cheap(h, st);
+        h->first_flag = false;
+        if (rc) return rc;
+        v.s0 = take_snap(h);
+        if ((rc = spec_enqueue(h))) return rc;
+        v.phase = 4;                    // (enqueue_iteration sets phase 1)
+        return STH_OK;
     }
     if ((rc = residual(h, 0, f, u, h->buf1, 0, h->lev_S[0], 1.0, st))) return rc;
     if ((rc = norm2_dev(h, h->buf1, len, st))) return rc;
@@ -1247,6 +1266,29 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
         HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn)));
         v.phase = 1;
         return spec_enqueue(h);
+    }
+    if (v.phase == 4) {
+        // the initial norms and cycle a are done; the flag of the initial
+        // pass (slot 0) says whether cycle a (and so cycle b) ran
+        v.fn = std::sqrt(h->hnorm[1]);
+        if (v.fn == 0.0) v.fn = 1.0;
+        const double r = std::sqrt(h->hnorm[2]);
+        v.prev = r;
+        v.phase = 1;
+        if (h->hflag[0] == 0) {
+            put_snap(h, v.s0);
+            v.pend = 0;
+            v.rn = eig_lower_bound(h, 0);
+            if (!std::isfinite(r)) {
+                v.rn = r;
+                return solve_finish(h, more);
+            }
+            v.phase = 3;
+            int rc = eig_exact_norm(h, v.st);
+            h->wait_ev = nullptr;
+            return rc;
+        }
+        // cycle a ran: go on as after any completed cycle
     }
     if (v.phase == 3) {
         v.rn = std::sqrt(h->hnorm[0]);
