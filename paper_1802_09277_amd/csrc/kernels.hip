@@ -516,7 +516,8 @@ __device__ __forceinline__ void mfma_kloop(int kpad, LD&& ld, MM&& mma) {
 template <typename CT, int DIR, int NT16, int EPI, bool CORE>
 __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, double* __restrict__ out,
                                                  const double* __restrict__ Upad, int n, long nimg,
-                                                 double alpha) {
+                                                 double alpha, const int* guard) {
+    if (guard_off(guard)) return;
     using M = Mfma16<CT>;
     using T = TileLds<CT, NT16>;
     typedef typename M::acc_t acc_t;
@@ -681,7 +682,7 @@ template <int NT16> static int xform2d_core_tiles(int n) {
 
 template <typename CT, int DIR, int NT16, int EPI, bool CORE>
 static hipError_t xform2d_go(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
-                             hipStream_t st, long* nblocks) {
+                             hipStream_t st, long* nblocks, const int* guard) {
     size_t shm = sizeof(CT) * 2 * (size_t)TileLds<CT, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
@@ -694,42 +695,42 @@ static hipError_t xform2d_go(const double* in, double* out, const double* Upad, 
     long blocks = persistent_blocks(shm, nimg);
     if (nblocks) *nblocks = blocks;
     hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, out,
-                       Upad, n, nimg, alpha);
+                       Upad, n, nimg, alpha, guard);
     return hipGetLastError();
 }
 
 template <typename CT, int DIR, int NT16, int EPI>
 static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
-                                 hipStream_t st, long* nblocks = nullptr) {
+                                 hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr) {
     if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
     if constexpr (kXform2dEdge<NT16>) {
         if (xform2d_core_tiles<NT16>(n) < NT16)
-            return xform2d_go<CT, DIR, NT16, EPI, true>(in, out, Upad, n, nimg, alpha, st, nblocks);
+            return xform2d_go<CT, DIR, NT16, EPI, true>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
     }
-    return xform2d_go<CT, DIR, NT16, EPI, false>(in, out, Upad, n, nimg, alpha, st, nblocks);
+    return xform2d_go<CT, DIR, NT16, EPI, false>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
 }
 
 template <typename CT, int DIR, int EPI>
 static hipError_t xform2d_np(const double* in, double* out, const double* Upad, int n, int np, long nimg,
-                             double alpha, hipStream_t st, long* nblocks = nullptr) {
+                             double alpha, hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr) {
     switch (np / 16) {
-        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
-        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
-        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
-        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
-        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
-        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks);
+        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename CT>
 static hipError_t xform2d_prec(int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
-                               long nimg, double alpha, hipStream_t st) {
-    if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st);
-    if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st);
-    if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st);
-    if (epi == 2) return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st);
+                               long nimg, double alpha, hipStream_t st, const int* guard) {
+    if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st, nullptr, guard);
+    if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard);
+    if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard);
+    if (epi == 2) return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard);
     return hipErrorInvalidValue;
 }
 
@@ -1321,7 +1322,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         // a skipped cycle stops the cycles guarded by its own flag too
         if (flag.dev && threadIdx.x == 0) {
             *flag.dev = 0;
-            *flag.host = 0;
+            if (flag.host) *flag.host = 0;
         }
         return;
     }
@@ -1344,20 +1345,30 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         __syncthreads();
     }
     if (flag.dev && threadIdx.x == 0) {
-        const double ssq = res[0], wsq = nsum > 1 ? res[1] : 0.0;
-        const double lo2 = fmax(flag.nb_lo * ssq, (1.0 - 1e-8) * wsq);
-        const int go = (isfinite(ssq) && isfinite(wsq) && lo2 > *flag.thr) ? 1 : 0;
+        int go;
+        if (flag.exact) {
+            // the host's final test on ||r|| = sqrt(sum) against thr[1] = rtol ||f||
+            const double rn = sqrt(res[0]);
+            go = (!isfinite(rn) || !(rn > flag.thr[1])) ? 1 : 0;
+        } else {
+            const double ssq = res[0], wsq = nsum > 1 ? res[1] : 0.0;
+            const double lo2 = fmax(flag.nb_lo * ssq, (1.0 - 1e-8) * wsq);
+            go = (isfinite(ssq) && isfinite(wsq) && lo2 > flag.thr[0]) ? 1 : 0;
+        }
         *flag.dev = go;
-        *flag.host = go;
+        if (flag.host) *flag.host = go;
     }
 }
 
 // *flag = value (one thread)
 // and optionally *thr = thr_value (negative: left as it is)
-__global__ void k_set_flag(int* flag, int value, double* thr, double thr_value) {
+__global__ void k_set_flag(int* flag, int value, double* thr, double thr_value, double thr_lin) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         *flag = value;
-        if (thr && thr_value >= 0.0) *thr = thr_value;
+        if (thr && thr_value >= 0.0) {
+            thr[0] = thr_value;
+            thr[1] = thr_lin;
+        }
     }
 }
 
@@ -1368,7 +1379,8 @@ __global__ void k_spec_threshold(double* thr, const double* f2, double rtol) {
         double fn = sqrt(f2[0]);
         if (fn == 0.0) fn = 1.0;
         const double t = rtol * fn;
-        *thr = t * t;
+        thr[0] = t * t;
+        thr[1] = t;
     }
 }
 
@@ -1377,8 +1389,8 @@ hipError_t launch_spec_threshold(double* thr, const double* f2, double rtol, hip
     return hipGetLastError();
 }
 
-hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr, double thr_value) {
-    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flag, value, thr, thr_value);
+hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr, double thr_value, double thr_lin) {
+    hipLaunchKernelGGL(k_set_flag, dim3(1), dim3(64), 0, st, flag, value, thr, thr_value, thr_lin);
     return hipGetLastError();
 }
 
@@ -1389,12 +1401,13 @@ __device__ __forceinline__ double mode_weight(int dim, const double* __restrict_
     const int jx = (int)(m % n);
     const long rest = m / n;
     const int jy = (int)(rest % n);
+    // the z entries are read in 2-D too (there rest / n = 0), so that every
+    // load goes out at once; multiplying by 1 leaves the 2-D value exact
+    const int jz = (int)(rest / n);
+    const double dz = vw[2 * jz], az = vw[2 * jz + 1];
     double d = vw[2 * jx] * vw[2 * jy], a = vw[2 * jx + 1] * vw[2 * jy + 1];
-    if (dim == 3) {
-        const int jz = (int)(rest / n);
-        d *= vw[2 * jz];
-        a *= vw[2 * jz + 1];
-    }
+    d *= dim == 3 ? dz : 1.0;
+    a *= dim == 3 ? az : 1.0;
     return 2.0 * d - a;
 }
 
@@ -1419,7 +1432,8 @@ __device__ __forceinline__ void block_sum2(double x, double y, double* __restric
 
 template <int NT16, bool CORE>
 static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, long nimg, double* partial,
-                                 int max_blocks, double* out, double* out_host, hipStream_t st) {
+                                 int max_blocks, double* out, double* out_host, hipStream_t st,
+                                 const CycleFlag& flag) {
     const size_t shm = sizeof(double) * 2 * (size_t)TileLds<double, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
@@ -1432,41 +1446,45 @@ static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, lo
     if (blocks > max_blocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gram_norm2d<NT16, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, Gpad, n, nimg,
                        partial);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 1, nullptr,
+                       flag);
     return hipGetLastError();
 }
 
 template <int NT16>
 static hipError_t gram_norm2d_launch(const double* in, const double* Gpad, int n, long nimg, double* partial,
-                                     int max_blocks, double* out, double* out_host, hipStream_t st) {
+                                     int max_blocks, double* out, double* out_host, hipStream_t st,
+                                     const CycleFlag& flag) {
     if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
     if constexpr (kXform2dEdge<NT16>) {
         if (xform2d_core_tiles<NT16>(n) < NT16)
-            return gram_norm2d_go<NT16, true>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+            return gram_norm2d_go<NT16, true>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
     }
-    return gram_norm2d_go<NT16, false>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+    return gram_norm2d_go<NT16, false>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
 }
 
 hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
-                              int max_blocks, double* out, double* out_host, hipStream_t st) {
+                              int max_blocks, double* out, double* out_host, hipStream_t st,
+                              const CycleFlag& flag) {
     if (nimg <= 0 || !xform2d_supported(np)) return hipErrorInvalidValue;
+    if (flag.dev && !flag.thr) return hipErrorInvalidValue;
     switch (np / 16) {
-        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
-        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
-        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
-        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
-        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
-        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st);
+        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
-                          int np, long nimg, double alpha, hipStream_t st) {
+                          int np, long nimg, double alpha, hipStream_t st, const int* guard) {
     if (nimg <= 0) return hipSuccess;
     if (!xform2d_supported(np)) return hipErrorInvalidValue;
-    if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st);
-    if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st);
+    if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard);
+    if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard);
     return hipErrorInvalidValue;
 }
 
@@ -1588,9 +1606,9 @@ __device__ __forceinline__ double mode_shift(int dim, const double* mu1, int n, 
     int jx = (int)(m % n);
     long rest = m / n;
     int jy = (int)(rest % n);
+    const double muz = mu1[rest / n];                 // in 2-D, rest / n = 0 (read, not used)
     double mu = mu1[jx] + mu1[jy];
-    if (dim == 3) mu += mu1[rest / n];
-    return mu;
+    return dim == 3 ? mu + muz : mu;
 }
 
 template <int NT, bool SCHUR>
@@ -1900,26 +1918,10 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
     double ssq = 0.0, wsq = 0.0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
-        const double mu = mode_shift(dim, mu1, n, m);
-        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
-        const double wm = mode_weight(dim, vw, n, m);
         const long s0 = q * chain;
-        double prev_old = 0.0, prev_new = 0.0;
-        if (s0 > 0) {
-            const long b = (s0 - 1) * NT * Nx + m;
-            double g[NT], u[NT], z[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                g[t] = fh[b + (long)t * Nx];
-                u[t] = uin[b + (long)t * Nx];
-            }
-            eig_residual_point<NT>(ktmt, mu, u, s0 > 1 ? uin[b - Nx] : 0.0, g);
-            shifted_solve<NT, SCHUR>(tm, sh, g, z);
-            prev_old = u[NT - 1];
-            prev_new = u[NT - 1] + omega * z[NT - 1];
-        }
-        // the next slab's f^ and u^ are loaded while the current one is
-        // processed (software pipelining along the chain)
+        // loads first (the chain's first slab, and the slab before it), so
+        // that none waits behind the per-mode setup; the next slab's f^ and
+        // u^ are then loaded while the current one is processed
         double fnx[NT], unx[NT], acc[NT];
         {
             const long b = s0 * NT * Nx + m;
@@ -1928,6 +1930,27 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                 fnx[t] = fh[b + (long)t * Nx];
                 unx[t] = uin[b + (long)t * Nx];
             }
+        }
+        double pg[NT], pu[NT], pq = 0.0;
+        if (s0 > 0) {
+            const long b = (s0 - 1) * NT * Nx + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                pg[t] = fh[b + (long)t * Nx];
+                pu[t] = uin[b + (long)t * Nx];
+            }
+            if (s0 > 1) pq = uin[b - Nx];
+        }
+        const double mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
+        const double wm = mode_weight(dim, vw, n, m);
+        double prev_old = 0.0, prev_new = 0.0;
+        if (s0 > 0) {
+            double z[NT];
+            eig_residual_point<NT>(ktmt, mu, pu, pq, pg);
+            shifted_solve<NT, SCHUR>(tm, sh, pg, z);
+            prev_old = pu[NT - 1];
+            prev_new = pu[NT - 1] + omega * z[NT - 1];
         }
 #pragma unroll 1
         for (int k = 0; k < chain; ++k) {
@@ -2025,6 +2048,41 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
     double ssq = 0.0, wsq = 0.0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
+        const long s0 = q * chain;
+        const long slab = (long)NT * Nx;
+        // loads first: the chain's first slab (f^, u^ and ec) and, after slab
+        // 0, the two slabs before it, so that none waits behind the per-mode
+        // setup below
+        double fnx[NT], unx[NT], cnx[NT], c[NT], acc[NT];
+        {
+            const long b = s0 * slab + m, bc = (s0 / 2) * slab + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                fnx[t] = fh[b + (long)t * Nx];
+                unx[t] = upre[b + (long)t * Nx];
+                cnx[t] = ec[bc + (long)t * Nx];
+            }
+        }
+        const long sa = s0 - 2;                 // slab s0 - 2 (even): first half of coarse slab s0/2 - 1
+        double pc[NT], pua[NT], pfa[NT], pub[NT], pfb[NT], pq[NT], pqu = 0.0;
+        if (s0 > 0) {
+            const long ba = sa * slab + m, bc = (sa / 2) * slab + m, bb = (s0 - 1) * slab + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                pc[t] = ec[bc + (long)t * Nx];
+                pua[t] = upre[ba + (long)t * Nx];
+                pfa[t] = fh[ba + (long)t * Nx];
+                pub[t] = upre[bb + (long)t * Nx];
+                pfb[t] = fh[bb + (long)t * Nx];
+            }
+            if (sa > 0) {
+                // the coupling row of slab s0 - 3 from u^ and ec
+                const long bp = (sa - 1) * slab + m, bpc = ((sa - 1) / 2) * slab + m;
+                pqu = upre[bp + (long)(NT - 1) * Nx];
+#pragma unroll
+                for (int k = 0; k < NT; ++k) pq[k] = ec[bpc + (long)k * Nx];
+            }
+        }
         const double mu = mode_shift(dim, mu1, n, m);
         const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
         // ca = A^{-1} e_1: a change of the coupling row moves A^{-1} r by a multiple of it
@@ -2036,42 +2094,33 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             shifted_solve<NT, SCHUR>(tm, sh, e1, ca);
         }
         const double wm = mode_weight(dim, vw, n, m);
-        const long s0 = q * chain;
-        const long slab = (long)NT * Nx;
         // coupling rows of slab s0 - 1: u1, u2 and u3
         double p1 = 0.0, p2 = 0.0, p3 = 0.0;
         if (s0 > 0) {
-            // slab s0 - 2 (even, so the first half of coarse slab s0/2 - 1),
-            // with the coupling row of slab s0 - 3 from u^ and ec
-            double c[NT], u1[NT], g[NT], z[NT];
-            const long sa = s0 - 2, ba = sa * slab + m, bc = (sa / 2) * slab + m;
-#pragma unroll
-            for (int k = 0; k < NT; ++k) c[k] = ec[bc + (long)k * Nx];
+            double u1[NT], g[NT], z[NT];
             double q1 = 0.0;
             if (sa > 0) {
-                const long bp = (sa - 1) * slab + m, bpc = ((sa - 1) / 2) * slab + m;
-                double v = upre[bp + (long)(NT - 1) * Nx];
+                double v = pqu;
 #pragma unroll
-                for (int k = 0; k < NT; ++k) v += tr.P[(NT + NT - 1) * kNt + k] * ec[bpc + (long)k * Nx];
+                for (int k = 0; k < NT; ++k) v += tr.P[(NT + NT - 1) * kNt + k] * pq[k];
                 q1 = v;
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                u1[t] = upre[ba + (long)t * Nx];
-                g[t] = fh[ba + (long)t * Nx];
+                u1[t] = pua[t];
+                g[t] = pfa[t];
             }
-            prolong_add<NT>(tr, 0, c, u1);
+            prolong_add<NT>(tr, 0, pc, u1);
             eig_residual_point<NT>(ktmt, mu, u1, q1, g);
             shifted_solve<NT, SCHUR>(tm, sh, g, z);
             const double a1 = u1[NT - 1], a2 = u1[NT - 1] + omega * z[NT - 1];
             // slab s0 - 1 (second half of the same coarse slab): both steps
-            const long bb = (s0 - 1) * slab + m;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-                u1[t] = upre[bb + (long)t * Nx];
-                g[t] = fh[bb + (long)t * Nx];
+                u1[t] = pub[t];
+                g[t] = pfb[t];
             }
-            prolong_add<NT>(tr, 1, c, u1);
+            prolong_add<NT>(tr, 1, pc, u1);
             eig_residual_point<NT>(ktmt, mu, u1, a1, g);
             shifted_solve<NT, SCHUR>(tm, sh, g, z);
             const double u2last = u1[NT - 1] + omega * z[NT - 1];
@@ -2079,18 +2128,6 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             p1 = u1[NT - 1];
             p2 = u2last;
             p3 = u2last + omega * z2last;
-        }
-        // the next slab's f^ and u^ (and the next pair's ec) are loaded while
-        // the current one is processed
-        double fnx[NT], unx[NT], cnx[NT], c[NT], acc[NT];
-        {
-            const long b = s0 * slab + m, bc = (s0 / 2) * slab + m;
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                fnx[t] = fh[b + (long)t * Nx];
-                unx[t] = upre[b + (long)t * Nx];
-                cnx[t] = ec[bc + (long)t * Nx];
-            }
         }
 #pragma unroll 1
         for (int k = 0; k < chain; ++k) {

@@ -38,11 +38,15 @@ struct Transfer {               // 2Nt x Nt prolongation
 // max(nb_lo ||r^||^2, (1 - 1e-8) sum_m v_m r^_m^2), exceeds *thr =
 // (rtol ||f||)^2, and 0 otherwise (possible convergence, or non-finite); a
 // skipped sum stores 0.
+// With exact = 1 (sum of an exact B-spline norm) the flag is instead 1 when
+// the host will end the solve on it: ||r|| = sqrt(sum) is not finite or not
+// above thr[1] = rtol ||f||.
 struct CycleFlag {
     int* dev = nullptr;
-    int* host = nullptr;           // mapped pinned host memory
-    const double* thr = nullptr;   // device scalar
+    int* host = nullptr;           // mapped pinned host memory (may be null)
+    const double* thr = nullptr;   // device pair: (rtol ||f||)^2, rtol ||f||
     double nb_lo = 0.0;
+    int exact = 0;
 };
 
 // r = f + sign * (-(A u)_n + (B u)_{n-1}) for slabs [s0, s0+ns) of a vector
@@ -70,7 +74,7 @@ hipError_t launch_xform_s(int prec, const double* in, double* out, const double*
 constexpr int kXform2dMaxNp = 96;
 bool xform2d_supported(int np);
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
-                          long nimg, double alpha, hipStream_t st);
+                          long nimg, double alpha, hipStream_t st, const int* guard = nullptr);
 
 // BF16x3 form of the same: out = M (In M^T) per image with the products
 // accumulated in FP32 from hi*hi + hi*lo + lo*hi bf16 MFMA products; pass
@@ -125,10 +129,11 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const double* vw, double* partial, long max_partial, double* out,
                                   double* out_host, hipStream_t st, const int* guard = nullptr,
                                   const CycleFlag& flag = CycleFlag{});
-//  *thr = (rtol max(||f||, 1 if ||f|| = 0))^2 from f2 = ||f||^2 (device scalars)
+//  thr[0..1] = (rtol F)^2, rtol F with F = ||f|| (1 if ||f|| = 0), from f2 = ||f||^2
 hipError_t launch_spec_threshold(double* thr, const double* f2, double rtol, hipStream_t st);
-//  *flag = value, and *thr = thr_value when thr is not null and thr_value >= 0
-hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr = nullptr, double thr_value = -1.0);
+//  *flag = value, and thr[0..1] = thr_value, thr_lin when thr is not null and thr_value >= 0
+hipError_t launch_set_flag(int* flag, int value, hipStream_t st, double* thr = nullptr, double thr_value = -1.0,
+                           double thr_lin = -1.0);
 //  the two coarsest levels of a V(1,1) cycle in one pass from level a's
 //  right-hand side fa (SA slabs; level b has SA/2): smoothing step from zero,
 //  restriction of its residual, exact solve of level b, prolongation and the
@@ -154,7 +159,8 @@ hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const 
 //  needs max_blocks entries; the sum also goes to out_host (mapped pinned host
 //  memory) if not null
 hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
-                              int max_blocks, double* out, double* out_host, hipStream_t st);
+                              int max_blocks, double* out, double* out_host, hipStream_t st,
+                              const CycleFlag& flag = CycleFlag{});
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,

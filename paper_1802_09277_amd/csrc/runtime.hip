@@ -151,15 +151,19 @@ struct sth_handle {
         int pend = 0;
         bool drain = false;
         Snap a, b, s0;                  // s0: state after the initial norms
+        // the mapping of the result into u was enqueued behind the exact norm
+        // (fin_always: unguarded, as the cycle count or growth ends the solve)
+        bool fin_enq = false, fin_always = false;
         hipEvent_t ev_a = nullptr, ev_b = nullptr;
     } sv;
     // speculative cycles (eigenbasis, fused cycle close)
     bool speculate = true;
     const int* guard = nullptr;         // guard of the launches of the cycle being enqueued
-    int* dgo = nullptr;                 // per norm slot: continuation flag of the cycle (device)
+    int* dgo = nullptr;                 // per norm slot: continuation flag of the cycle (device);
+                                        // [2]: the final exact norm ends the solve
     int* hflag = nullptr;               // its mapped host copy
     int* hflag_dev = nullptr;
-    double* dthr = nullptr;             // (rtol ||f||)^2 of the solve in progress (device)
+    double* dthr = nullptr;             // (rtol ||f||)^2 and rtol ||f|| of the solve in progress (device)
     int last_slot = 0;                  // norm slot of the last enqueued cycle end
     bool first_flag = false;            // the initial residual pass sets the flag of slot 0
     hipEvent_t evring[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -408,7 +412,7 @@ enum SpatialKind { FWD_U, INV_U, FWD_C, INV_C };
 // time row of `rows` rows; A = U or C.  FP64.  in, out and tmp (a level-0
 // sized scratch vector, used by the axis-by-axis path) must be distinct.
 static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, double* out, long rows, double* tmp,
-                         hipStream_t st) {
+                         hipStream_t st, const int* guard = nullptr) {
     const bool fwd = (kind == FWD_U || kind == FWD_C);
     const double* A = (kind == FWD_U || kind == INV_U) ? h->Tf : h->Cf;     // A padded
     const double* At = (kind == FWD_U || kind == INV_U) ? h->Ti : h->Ci;    // A^T padded
@@ -417,7 +421,7 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     h->tlev = 0;
     if (h->dim == 2 && xform2d_supported(h->np)) {
         Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, 16.0 * dof, st);
-        HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st));
+        HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st, guard));
         return STH_OK;
     }
     // axis by axis: x (contiguous), then y (and z), ping-ponging tmp/out
@@ -605,7 +609,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
 // The B-spline residual norm ||(I (x) C_x) r^||^2 (C = M_1 U = U^{-T}) of
 // the current eigenbasis iterate to hnorm[0] (not synchronised); r^ is
 // formed again in buf0.
-static int eig_exact_norm(sth_handle* h, hipStream_t st) {
+static int eig_exact_norm(sth_handle* h, hipStream_t st, const CycleFlag& fin = CycleFlag{}) {
     h->tlev = 0;
     const long S = h->lev_S[0];
     const long len = S * slab_len(h);
@@ -621,7 +625,7 @@ static int eig_exact_norm(sth_handle* h, hipStream_t st) {
         // ||C r^ C^T||^2 per image as <r^ G, G r^> (G = C^T C), r not formed
         Timed tm(h, STH_K_RESNORM, dof * 4.0 * h->n, dof * 8.0, st);
         HIPCHK(launch_gram_norm2d(h->buf0, h->Gf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm,
-                                  h->hnorm_dev, st));
+                                  h->hnorm_dev, st, fin));
         return STH_OK;                  // stored hnorm[0] itself
     }
     if (h->dim == 2) {
@@ -907,13 +911,13 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     }
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc((void**)&h->hnorm, 6 * sizeof(double), mapped) != hipSuccess ||
-        hipHostMalloc((void**)&h->hflag, 2 * sizeof(int), mapped) != hipSuccess)
+        hipHostMalloc((void**)&h->hflag, 3 * sizeof(int), mapped) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
     if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess ||
         hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess)
         return cleanup(STH_EHIP, "pinned host memory is not mapped");
-    if (hipMalloc((void**)&h->dgo, 2 * sizeof(int)) != hipSuccess ||
-        hipMalloc((void**)&h->dthr, sizeof(double)) != hipSuccess)
+    if (hipMalloc((void**)&h->dgo, 3 * sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&h->dthr, 2 * sizeof(double)) != hipSuccess)
         return cleanup(STH_ENOMEM, "device allocation failed");
     for (auto& e : h->evring)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
@@ -1239,6 +1243,29 @@ static double eig_lower_bound(const sth_handle* h, int slot) {
     return std::sqrt(lo2);
 }
 
+// Exact norm of the current iterate in the speculative loop; on the fused
+// 2-D path the mapping of the result into u goes right behind it, guarded by
+// the device's copy of the host's final test (unguarded when the cycle count
+// or growth already ends the solve), so the end of a solve needs no host
+// round trip.  A mapping that runs although the solve goes on is overwritten
+// by the final one.
+static int spec_exact_norm(sth_handle* h) {
+    auto& v = h->sv;
+    v.phase = 3;
+    v.fin_enq = false;
+    h->wait_ev = nullptr;
+    if (!(h->dim == 2 && xform2d_supported(h->np))) return eig_exact_norm(h, v.st);
+    v.fin_always = v.it >= v.maxit || v.growth >= 3;
+    const CycleFlag fin = v.fin_always ? CycleFlag{} : CycleFlag{h->dgo + 2, h->hflag_dev + 2, h->dthr, 0.0, 1};
+    int rc = eig_exact_norm(h, v.st, fin);
+    if (rc) return rc;
+    if ((rc = spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st,
+                            v.fin_always ? nullptr : h->dgo + 2)))
+        return rc;
+    v.fin_enq = true;
+    return STH_OK;
+}
+
 // Speculative form of solve_continue: after cycle k's event, its flag (set
 // on the device from the same bound the plain loop tests) says whether cycle
 // k+1, already enqueued behind it, runs; if not, cycle k+1 leaves every
@@ -1263,7 +1290,8 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
             return rc;
         }
         // arm the first cycle and set the threshold of the cycles' flags
-        HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn)));
+        HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn),
+                                  v.rtol * v.fn));
         v.phase = 1;
         return spec_enqueue(h);
     }
@@ -1283,19 +1311,24 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
                 v.rn = r;
                 return solve_finish(h, more);
             }
-            v.phase = 3;
-            int rc = eig_exact_norm(h, v.st);
-            h->wait_ev = nullptr;
-            return rc;
+            return spec_exact_norm(h);
         }
         // cycle a ran: go on as after any completed cycle
     }
     if (v.phase == 3) {
         v.rn = std::sqrt(h->hnorm[0]);
-        if (!std::isfinite(v.rn) || !(v.rn > target) || v.it >= v.maxit || v.growth >= 3)
+        if (!std::isfinite(v.rn) || !(v.rn > target) || v.it >= v.maxit || v.growth >= 3) {
+            if (v.fin_enq && (v.fin_always || h->hflag[2] != 0)) {
+                // the mapping into u ran behind the norm
+                v.phase = 2;
+                *more = false;
+                return STH_OK;
+            }
             return solve_finish(h, more);
+        }
         // not converged: the next cycle runs after all
-        HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn)));
+        HIPCHK(launch_set_flag(h->dgo + h->last_slot, 1, v.st, h->dthr, (v.rtol * v.fn) * (v.rtol * v.fn),
+                                  v.rtol * v.fn));
         v.phase = 1;
         return spec_enqueue(h);
     }
@@ -1349,10 +1382,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
         v.rn = r;
         return solve_finish(h, more);
     }
-    v.phase = 3;
-    int rc = eig_exact_norm(h, v.st);
-    h->wait_ev = nullptr;
-    return rc;
+    return spec_exact_norm(h);
 }
 
 // Once the work enqueued by the previous call has completed: read the

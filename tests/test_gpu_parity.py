@@ -395,3 +395,22 @@ def test_speculative_cycles_match_plain_loop(name):
     s.speculate(True)
     assert outs[0][:3] == outs[1][:3] and outs[0][0] == 0 and outs[0][2] == 0
     assert np.array_equal(outs[0][3], outs[1][3])
+    # a tolerance between the lower bound and the exact norm after k cycles:
+    # the exact norm says "go on" (so the mapping into u enqueued behind it is
+    # skipped on the device) and the solve continues as in the plain loop
+    k = 2
+    s.speculate(True)
+    _, rb, _ = s.solve(f, s.new_vector(), rtol=0.0, maxit=k, check=False)    # bound / ||f||
+    s.speculate(False)
+    _, re_, _ = s.solve(f, s.new_vector(), rtol=0.0, maxit=k, check=False)   # exact / ||f||
+    assert rb < re_
+    rt = float(np.sqrt(rb * re_))
+    outs = []
+    for spec in (False, True):
+        s.speculate(spec)
+        u = s.new_vector()
+        it, rr, code = s.solve(f, u, rtol=rt, maxit=60, check=False)
+        outs.append((it, rr, code, host(u)))
+    s.speculate(True)
+    assert outs[0][:3] == outs[1][:3] and outs[0][0] > k and outs[0][2] == 0
+    assert np.array_equal(outs[0][3], outs[1][3])
