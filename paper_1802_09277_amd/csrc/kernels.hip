@@ -2686,7 +2686,8 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const double* fh, const double* upre, const double* ec, double* uend,
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
                                   const double* vw, double* partial, long max_partial, double* out,
-                                  double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag) {
+                                  double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag,
+                                  bool sums) {
     const long Nx = (long)n * n * (dim == 3 ? n : 1);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
@@ -2711,6 +2712,16 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
 #undef STH_CC_CASE
         default: return hipErrorInvalidValue;
     }
+    if (!sums) return hipGetLastError();
+    return launch_cycle_sums(dim, n, S, chain, partial, out, out_host, st, guard, flag);
+}
+
+hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial, double* out, double* out_host,
+                             hipStream_t st, const int* guard, const CycleFlag& flag) {
+    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    if (chain < 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    const long blocks = ((S / chain) * Nx + 255) / 256;
+    if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 2, guard,
                        flag);
     return hipGetLastError();

@@ -128,7 +128,11 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
                                   const double* vw, double* partial, long max_partial, double* out,
                                   double* out_host, hipStream_t st, const int* guard = nullptr,
-                                  const CycleFlag& flag = CycleFlag{});
+                                  const CycleFlag& flag = CycleFlag{}, bool sums = true);
+//  the final sums of a cycle-close pass launched with sums = false (same S,
+//  chain, partial, outputs, guard and flag), as a separate launch
+hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial, double* out, double* out_host,
+                             hipStream_t st, const int* guard = nullptr, const CycleFlag& flag = CycleFlag{});
 //  thr[0..1] = (rtol F)^2, rtol F with F = ||f|| (1 if ||f|| = 0), from f2 = ||f||^2
 hipError_t launch_spec_threshold(double* thr, const double* f2, double rtol, hipStream_t st);
 //  *flag = value, and thr[0..1] = thr_value, thr_lin when thr is not null and thr_value >= 0

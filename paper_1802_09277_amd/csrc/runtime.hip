@@ -561,12 +561,18 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         const int slot = nxt == 2 ? 1 : 0;
         CycleFlag flag;
         if (h->guard) flag = CycleFlag{h->dgo + slot, h->hflag_dev + slot, h->dthr, h->nb_lo};
-        Timed tm(h, STH_K_EIG_CYCLE_CLOSE, dof * (12.0 * Nt + 24.0), 40.0 * dof, st);
-        HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
-                                      eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
-                                      eig_f(h, 1), h->tr, h->omega, S, chain_length(h, S, 65536), h->vw,
-                                      h->cpartial, h->n_cpartial, h->dnorm + 2 + 2 * slot,
-                                      h->hnorm_dev + 2 + 2 * slot, st, h->guard, flag));
+        const int chain = chain_length(h, S, 65536);
+        {
+            // the pass alone (its final sums are a launch of their own)
+            Timed tm(h, STH_K_EIG_CYCLE_CLOSE, dof * (12.0 * Nt + 24.0), 40.0 * dof, st);
+            HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
+                                          eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
+                                          eig_f(h, 1), h->tr, h->omega, S, chain, h->vw, h->cpartial,
+                                          h->n_cpartial, h->dnorm + 2 + 2 * slot, h->hnorm_dev + 2 + 2 * slot, st,
+                                          h->guard, flag, false));
+        }
+        HIPCHK(launch_cycle_sums(h->dim, h->n, S, chain, h->cpartial, h->dnorm + 2 + 2 * slot,
+                                 h->hnorm_dev + 2 + 2 * slot, st, h->guard, flag));
         h->last_slot = slot;
         h->pending_ec = nullptr;
         h->wsum_valid = true;
