@@ -198,7 +198,9 @@ int sth_use_graphs(sth_handle* h, int enable);
  * once and the exact norm decides, so the cycles, iterates and counts are
  * those of the plain loop (the stopping test of Section 4.4) without a host
  * round trip between cycles.  The first cycles follow the initial residual
- * pass the same way (its threshold (rtol ||f||)^2 formed on the device).
+ * pass the same way (its threshold (rtol ||f||)^2 formed on the device), and
+ * on the 2-D path the mapping of the result into u goes behind the exact
+ * norm, guarded by the device's copy of the final test.
  * enable = 0 waits for each norm first; so does kernel timing. */
 int sth_speculate(sth_handle* h, int enable);
 
