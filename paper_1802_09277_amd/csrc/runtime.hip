@@ -93,7 +93,8 @@ struct sth_handle {
     double* buf1 = nullptr;
     double* partial = nullptr;
     double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side; per norm slot
-                                        // s (2 + 2s, 3 + 2s) eigenbasis residual and its weighted sum
+                                        // s (2 + 2s, 3 + 2s) eigenbasis residual and its weighted sum;
+                                        // slot 2 (6, 7): the initial pass of a speculative solve
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
     double* hnorm_dev = nullptr;        // device address of hnorm
     // timing
@@ -160,12 +161,14 @@ struct sth_handle {
     bool speculate = true;
     const int* guard = nullptr;         // guard of the launches of the cycle being enqueued
     int* dgo = nullptr;                 // per norm slot: continuation flag of the cycle (device);
-                                        // [2]: the final exact norm ends the solve
+                                        // [2]: the final exact norm ends the solve; [3]: the
+                                        // initial pass of a speculative solve
     int* hflag = nullptr;               // its mapped host copy
     int* hflag_dev = nullptr;
     double* dthr = nullptr;             // (rtol ||f||)^2 and rtol ||f|| of the solve in progress (device)
     int last_slot = 0;                  // norm slot of the last enqueued cycle end
-    bool first_flag = false;            // the initial residual pass sets the flag of slot 0
+    bool first_flag = false;            // the initial residual pass sets its own flag (dgo[3])
+    bool first_guard = false;           // the next cycle is guarded by it
     hipEvent_t evring[4] = {nullptr, nullptr, nullptr, nullptr};
     int evnext = 0;
     hipEvent_t wait_ev = nullptr;       // event the caller waits for before solve_continue
@@ -585,17 +588,21 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         const double Nt = h->Nt;
         const int o = c == 0 ? 1 : 0;   // buffer of the pre-smoothed iterate
         Timed tm(h, STH_K_EIG_CYCLE_END, dof * (12.0 * Nt + 10.0), 28.0 * dof, st);
+        // with the first cycles enqueued behind it, the initial pass keeps its
+        // sums and flag apart from the two alternating cycle slots (the
+        // second cycle writes slot 0 while the host reads these)
         CycleFlag flag;
-        if (h->first_flag) flag = CycleFlag{h->dgo, h->hflag_dev, h->dthr, h->nb_lo};
+        if (h->first_flag) flag = CycleFlag{h->dgo + 3, h->hflag_dev + 3, h->dthr, h->nb_lo};
+        const int at = h->first_flag ? 6 : 2;
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, o), eig_f(h, 1), h->tr, h->omega, S,
-                                    chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + 2,
-                                    h->hnorm_dev + 2, st, flag));
+                                    chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + at,
+                                    h->hnorm_dev + at, st, flag));
         h->wsum_valid = true;
         h->last_slot = 0;
         h->pre_idx = o;
         h->presmoothed = true;
-        return STH_OK;                  // the pass stored hnorm[2] itself
+        return STH_OK;                  // the pass stored its sums to the host itself
     }
     {
         Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
@@ -727,7 +734,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
         S /= 2;
         total += vecsl * sizeof(double) * (size_t)S * slab;
     }
-    total += sizeof(double) * (kNormBlocks + 6 + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
+    total += sizeof(double) * (kNormBlocks + 8 + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
     *bytes = total;
     return STH_OK;
 }
@@ -851,7 +858,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
-        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 6) ||
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 8) ||
         !dalloc(&h->dktmt, (size_t)h->L * 2 * kNt * kNt))
         return cleanup(STH_ENOMEM, "device allocation failed");
     std::vector<double> ktmt((size_t)h->L * 2 * kNt * kNt);
@@ -916,13 +923,13 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         }
     }
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
-    if (hipHostMalloc((void**)&h->hnorm, 6 * sizeof(double), mapped) != hipSuccess ||
-        hipHostMalloc((void**)&h->hflag, 3 * sizeof(int), mapped) != hipSuccess)
+    if (hipHostMalloc((void**)&h->hnorm, 8 * sizeof(double), mapped) != hipSuccess ||
+        hipHostMalloc((void**)&h->hflag, 4 * sizeof(int), mapped) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
     if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess ||
         hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess)
         return cleanup(STH_EHIP, "pinned host memory is not mapped");
-    if (hipMalloc((void**)&h->dgo, 3 * sizeof(int)) != hipSuccess ||
+    if (hipMalloc((void**)&h->dgo, 4 * sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&h->dthr, 2 * sizeof(double)) != hipSuccess)
         return cleanup(STH_ENOMEM, "device allocation failed");
     for (auto& e : h->evring)
@@ -1026,6 +1033,8 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
         // a speculative solve guards every launch of the cycle with the
         // continuation flag of the cycle before it (its norm slot)
         h->guard = h->sv.spec && h->presmoothed ? h->dgo + (h->pre_idx == 2 ? 1 : 0) : nullptr;
+        if (h->guard && h->first_guard) h->guard = h->dgo + 3;   // the initial pass's flag
+        h->first_guard = false;
         rc = eig_vcycle(h, 0, false, st);
         h->defer_close = false;
         if (rc == STH_OK) rc = eig_residual_cheap(h, st);
@@ -1158,7 +1167,9 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
         h->ecur[0] = 0;
         if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st))) return rc;
         if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) return rc;
-        if (!v.spec || maxit < 1) return eig_residual_cheap(h, st);
+        // (with graph replay, whose captured cycles have fixed guards, the
+        // first cycle waits for the initial norms instead)
+        if (!v.spec || maxit < 1 || h->use_graph) return eig_residual_cheap(h, st);
         // speculation from the start: the threshold on the device, the
         // initial pass sets the flag that guards the first cycle, and the
         // first cycles go behind it without waiting for the norms
@@ -1168,6 +1179,7 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
         h->first_flag = false;
         if (rc) return rc;
         v.s0 = take_snap(h);
+        h->first_guard = true;
         if ((rc = spec_enqueue(h))) return rc;
         v.phase = 4;                    // (enqueue_iteration sets phase 1)
         return STH_OK;
@@ -1241,7 +1253,8 @@ static int solve_finish(sth_handle* h, bool* more) {
 }
 
 // Lower bound of the B-spline residual norm of the cycle whose sums are in
-// norm slot `slot` (the larger of the two bounds of solve_continue)
+// norm slot `slot` (the larger of the two bounds of solve_continue); slot 2
+// holds the initial pass of a speculative solve
 static double eig_lower_bound(const sth_handle* h, int slot) {
     const double ssq = h->hnorm[2 + 2 * slot], wsq = h->hnorm[3 + 2 * slot];
     double lo2 = h->nb_lo * ssq;
@@ -1303,16 +1316,17 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
     }
     if (v.phase == 4) {
         // the initial norms and cycle a are done; the flag of the initial
-        // pass (slot 0) says whether cycle a (and so cycle b) ran
+        // pass (its own slot: sums in hnorm[6..7], flag in hflag[3]) says
+        // whether cycle a (and so cycle b) ran
         v.fn = std::sqrt(h->hnorm[1]);
         if (v.fn == 0.0) v.fn = 1.0;
-        const double r = std::sqrt(h->hnorm[2]);
+        const double r = std::sqrt(h->hnorm[6]);
         v.prev = r;
         v.phase = 1;
-        if (h->hflag[0] == 0) {
+        if (h->hflag[3] == 0) {
             put_snap(h, v.s0);
             v.pend = 0;
-            v.rn = eig_lower_bound(h, 0);
+            v.rn = eig_lower_bound(h, 2);
             if (!std::isfinite(r)) {
                 v.rn = r;
                 return solve_finish(h, more);
