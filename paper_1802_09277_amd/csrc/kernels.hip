@@ -1323,6 +1323,10 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         if (flag.dev && threadIdx.x == 0) {
             *flag.dev = 0;
             if (flag.host) *flag.host = 0;
+            if (flag.seq) {
+                __threadfence_system();
+                *flag.seq = flag.seq_val;
+            }
         }
         return;
     }
@@ -1357,6 +1361,10 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
         }
         *flag.dev = go;
         if (flag.host) *flag.host = go;
+        if (flag.seq) {
+            __threadfence_system();
+            *flag.seq = flag.seq_val;
+        }
     }
 }
 

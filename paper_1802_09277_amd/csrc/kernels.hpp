@@ -47,6 +47,11 @@ struct CycleFlag {
     const double* thr = nullptr;   // device pair: (rtol ||f||)^2, rtol ||f||
     double nb_lo = 0.0;
     int exact = 0;
+    // completion mark: after the outputs above, a system-scope fence and
+    // *seq = seq_val (mapped host memory) for a host that polls instead of
+    // waiting for an event
+    int* seq = nullptr;
+    int seq_val = 0;
 };
 
 // r = f + sign * (-(A u)_n + (B u)_{n-1}) for slabs [s0, s0+ns) of a vector

@@ -11,6 +11,8 @@
 // diagonalisation of the 1-D pencils), temporal eigenvector transform and
 // shifted divide, inverse transforms.
 #include <hip/hip_runtime.h>
+#include <atomic>
+#include <chrono>
 
 #include <cmath>
 #include <cstdio>
@@ -136,6 +138,7 @@ struct sth_handle {
         int ecur0 = 0, pre_idx = 1;
         bool presmoothed = false;
         int slot = 0;
+        int seqv = 0;                   // completion mark of the cycle's final sum
     };
     struct SolveState {
         const double* f = nullptr;
@@ -172,6 +175,15 @@ struct sth_handle {
     hipEvent_t evring[4] = {nullptr, nullptr, nullptr, nullptr};
     int evnext = 0;
     hipEvent_t wait_ev = nullptr;       // event the caller waits for before solve_continue
+    // or (wait_slot >= 0) the completion mark wait_seq in hseq[wait_slot]:
+    // the blocking solve with eager launches polls mapped memory instead of
+    // recording an event per cycle (an event record leaves the GPU idle for
+    // a few microseconds at every cycle boundary)
+    int* hseq = nullptr;                // mapped, coherent: per norm slot, last completion mark
+    int* hseq_dev = nullptr;
+    int seq_counter = 0, last_seq = 0;
+    int wait_slot = -1, wait_seq = 0;
+    bool want_poll = false, poll_seq = false;
 };
 
 static void drop_graph_entry(sth_handle::GraphEntry& g) {
@@ -564,6 +576,10 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         const int slot = nxt == 2 ? 1 : 0;
         CycleFlag flag;
         if (h->guard) flag = CycleFlag{h->dgo + slot, h->hflag_dev + slot, h->dthr, h->nb_lo};
+        if (flag.dev && h->poll_seq) {
+            flag.seq = h->hseq_dev + slot;
+            flag.seq_val = h->last_seq = ++h->seq_counter;
+        }
         const int chain = chain_length(h, S, 65536);
         {
             // the pass alone (its final sums are a launch of their own)
@@ -924,10 +940,13 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     }
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc((void**)&h->hnorm, 8 * sizeof(double), mapped) != hipSuccess ||
-        hipHostMalloc((void**)&h->hflag, 4 * sizeof(int), mapped) != hipSuccess)
+        hipHostMalloc((void**)&h->hflag, 4 * sizeof(int), mapped) != hipSuccess ||
+        hipHostMalloc((void**)&h->hseq, 2 * sizeof(int), mapped) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
+    h->hseq[0] = h->hseq[1] = 0;
     if (hipHostGetDevicePointer((void**)&h->hnorm_dev, h->hnorm, 0) != hipSuccess ||
-        hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess)
+        hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&h->hseq_dev, h->hseq, 0) != hipSuccess)
         return cleanup(STH_EHIP, "pinned host memory is not mapped");
     if (hipMalloc((void**)&h->dgo, 4 * sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&h->dthr, 2 * sizeof(double)) != hipSuccess)
@@ -1150,7 +1169,11 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
     // cycles enqueued ahead of their predecessor's norm (eigenbasis with the
     // fused cycle close; not while kernels are timed one by one)
     v.spec = h->basis == 1 && h->fuse_close && h->speculate && !h->timing;
+    // completion marks instead of per-cycle events: the blocking solve with
+    // eager launches (a captured graph would replay fixed marks)
+    h->poll_seq = h->want_poll && v.spec && !h->use_graph;
     h->wait_ev = nullptr;
+    h->wait_slot = -1;
     h->graph_launched = false;
     h->presmoothed = false;
     h->tlev = 0;
@@ -1211,7 +1234,24 @@ static hipEvent_t next_event(sth_handle* h) {
 }
 
 static sth_handle::Snap take_snap(const sth_handle* h) {
-    return sth_handle::Snap{h->ecur[0], h->pre_idx, h->presmoothed, h->last_slot};
+    return sth_handle::Snap{h->ecur[0], h->pre_idx, h->presmoothed, h->last_slot, h->last_seq};
+}
+
+// Completion of the cycle just enqueued: an event, or nothing to record when
+// its final sum leaves a completion mark (poll_seq)
+static int mark_cycle(sth_handle* h, hipEvent_t* ev) {
+    *ev = nullptr;
+    if (h->poll_seq) return STH_OK;
+    *ev = next_event(h);
+    HIPCHK(hipEventRecord(*ev, h->sv.st));
+    return STH_OK;
+}
+
+// the caller's next wait: for cycle s (its event or its completion mark)
+static void wait_for(sth_handle* h, const sth_handle::Snap& s, hipEvent_t ev) {
+    h->wait_ev = ev;
+    h->wait_slot = h->poll_seq ? s.slot : -1;
+    h->wait_seq = s.seqv;
 }
 
 static void put_snap(sth_handle* h, const sth_handle::Snap& s) {
@@ -1229,17 +1269,15 @@ static int spec_enqueue(sth_handle* h) {
     int rc = enqueue_iteration(h);
     if (rc) return rc;
     v.a = take_snap(h);
-    v.ev_a = next_event(h);
-    HIPCHK(hipEventRecord(v.ev_a, v.st));
+    if ((rc = mark_cycle(h, &v.ev_a))) return rc;
     v.pend = 0;
     if (v.it + 2 <= v.maxit) {
         if ((rc = enqueue_iteration(h))) return rc;
         v.b = take_snap(h);
-        v.ev_b = next_event(h);
-        HIPCHK(hipEventRecord(v.ev_b, v.st));
+        if ((rc = mark_cycle(h, &v.ev_b))) return rc;
         v.pend = 1;
     }
-    h->wait_ev = v.ev_a;
+    wait_for(h, v.a, v.ev_a);
     return STH_OK;
 }
 
@@ -1248,6 +1286,7 @@ static int solve_finish(sth_handle* h, bool* more) {
     *more = false;
     v.phase = 2;
     h->wait_ev = nullptr;
+    h->wait_slot = -1;
     // u = (I (x) U_x) u^
     return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st);
 }
@@ -1273,6 +1312,7 @@ static int spec_exact_norm(sth_handle* h) {
     v.phase = 3;
     v.fin_enq = false;
     h->wait_ev = nullptr;
+    h->wait_slot = -1;
     if (!(h->dim == 2 && xform2d_supported(h->np))) return eig_exact_norm(h, v.st);
     v.fin_always = v.it >= v.maxit || v.growth >= 3;
     const CycleFlag fin = v.fin_always ? CycleFlag{} : CycleFlag{h->dgo + 2, h->hflag_dev + 2, h->dthr, 0.0, 1};
@@ -1306,6 +1346,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
             v.phase = 3;
             int rc = eig_exact_norm(h, v.st);
             h->wait_ev = nullptr;
+            h->wait_slot = -1;
             return rc;
         }
         // arm the first cycle and set the threshold of the cycles' flags
@@ -1370,7 +1411,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
             v.ev_a = v.ev_b;
             v.pend = 0;
             v.drain = true;
-            h->wait_ev = v.ev_a;
+            wait_for(h, v.a, v.ev_a);
             return STH_OK;
         }
         if (v.growth >= 3 || v.it >= v.maxit) return solve_finish(h, more);
@@ -1379,13 +1420,12 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
             v.a = v.b;
             v.ev_a = v.ev_b;
             v.pend = 0;
-            h->wait_ev = v.ev_a;
+            wait_for(h, v.a, v.ev_a);
             if (v.it + 2 <= v.maxit) {
                 int rc = enqueue_iteration(h);
                 if (rc) return rc;
                 v.b = take_snap(h);
-                v.ev_b = next_event(h);
-                HIPCHK(hipEventRecord(v.ev_b, v.st));
+                if ((rc = mark_cycle(h, &v.ev_b))) return rc;
                 v.pend = 1;
             }
             return STH_OK;
@@ -1490,17 +1530,48 @@ hipEvent_t solve_wait_event(sth_handle* h) { return h->wait_ev; }
 
 extern "C" {
 
+// Waits until the final sum of the awaited cycle has left its completion
+// mark in mapped memory (it stores the mark after its norms and flag, behind
+// a system-scope fence).  After each millisecond of waiting it checks the
+// stream, so that a failed launch or a missing mark ends the wait with an
+// error; the check is rare because a stream query can itself put work
+// between the kernels.
+static int wait_mark(sth_handle* h, hipStream_t st) {
+    volatile int* p = h->hseq + h->wait_slot;
+    const int want = h->wait_seq;
+    auto last = std::chrono::steady_clock::now();
+    for (long spin = 1; *p != want; ++spin) {
+        if ((spin & 1023) != 0) continue;
+        const auto now = std::chrono::steady_clock::now();
+        if (now - last >= std::chrono::milliseconds(1)) {
+            last = now;
+            const hipError_t q = hipStreamQuery(st);
+            if (q == hipSuccess) {
+                if (*p == want) break;
+                return fail(STH_EHIP, "cycle completion mark not set");
+            }
+            if (q != hipErrorNotReady) return fail(STH_EHIP, std::string("stream work failed: ") + hipGetErrorString(q));
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return STH_OK;
+}
+
 int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit, int* iters, double* relres,
               void* stream) {
     if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
     hipStream_t st = (hipStream_t)stream;
+    h->want_poll = true;
     int rc = solve_begin(h, f, u, rtol, maxit, st);
+    h->want_poll = false;
     bool more = true;
     while (rc == STH_OK && more) {
-        if (h->wait_ev) HIPCHK(hipEventSynchronize(h->wait_ev));
+        if (h->wait_slot >= 0) rc = wait_mark(h, st);
+        else if (h->wait_ev) HIPCHK(hipEventSynchronize(h->wait_ev));
         else HIPCHK(hipStreamSynchronize(st));
-        rc = solve_continue(h, &more);
+        if (rc == STH_OK) rc = solve_continue(h, &more);
     }
+    h->poll_seq = false;
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(st));
     return solve_result(h, iters, relres);
@@ -1674,6 +1745,7 @@ int sth_destroy(sth_handle* h) {
             if (q) (void)hipFree(q);
     if (h->hnorm) (void)hipHostFree(h->hnorm);
     if (h->hflag) (void)hipHostFree(h->hflag);
+    if (h->hseq) (void)hipHostFree(h->hseq);
     if (h->dthr) (void)hipFree(h->dthr);
     if (h->dmix) (void)hipFree(h->dmix);
     if (h->dgo) (void)hipFree(h->dgo);
