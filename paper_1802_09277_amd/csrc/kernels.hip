@@ -516,7 +516,7 @@ __device__ __forceinline__ void mfma_kloop(int kpad, LD&& ld, MM&& mma) {
 template <typename CT, int DIR, int NT16, int EPI, bool CORE>
 __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, double* __restrict__ out,
                                                  const double* __restrict__ Upad, int n, long nimg,
-                                                 double alpha, const int* guard) {
+                                                 double alpha, const int* guard, long ldi, long ldo) {
     if (guard_off(guard)) return;
     using M = Mfma16<CT>;
     using T = TileLds<CT, NT16>;
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
     constexpr int PER = (NP * NP + 511) / 512;
     double pre[PER];
     auto load_img = [&](long img) {
-        const double* src = in + img * nn;
+        const double* src = in + img * ldi;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k, r = i / NP, c = i % NP;
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         // an image of zeros (e.g. a zero initial guess) maps to zeros
         if (!__syncthreads_or(nz)) {
             if (EPI != 1) {
-                double* dst = out + img * nn;
+                double* dst = out + img * ldo;
                 for (long i = tid; i < nn; i += 512) dst[i] = 0.0;
             }
             continue;
@@ -650,7 +650,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
             }
         }
         if (CORE) e = xform2d_edge_sum(e, eg);
-        double* dst = out + img * nn;
+        double* dst = out + img * ldo;
         auto put = [&](int i, int j, double v) {
             double* o = dst + (long)i * n + j;
             if (EPI == 0) *o = v;
@@ -682,7 +682,7 @@ template <int NT16> static int xform2d_core_tiles(int n) {
 
 template <typename CT, int DIR, int NT16, int EPI, bool CORE>
 static hipError_t xform2d_go(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
-                             hipStream_t st, long* nblocks, const int* guard) {
+                             hipStream_t st, long* nblocks, const int* guard, long ldi, long ldo) {
     size_t shm = sizeof(CT) * 2 * (size_t)TileLds<CT, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
@@ -695,42 +695,47 @@ static hipError_t xform2d_go(const double* in, double* out, const double* Upad, 
     long blocks = persistent_blocks(shm, nimg);
     if (nblocks) *nblocks = blocks;
     hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, out,
-                       Upad, n, nimg, alpha, guard);
+                       Upad, n, nimg, alpha, guard, ldi, ldo);
     return hipGetLastError();
 }
 
 template <typename CT, int DIR, int NT16, int EPI>
 static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
-                                 hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr) {
+                                 hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr,
+                                 long ldi = 0, long ldo = 0) {
     if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
+    if (ldi == 0) ldi = (long)n * n;
+    if (ldo == 0) ldo = (long)n * n;
+    if (ldi < (long)n * n || ldo < (long)n * n) return hipErrorInvalidValue;
     if constexpr (kXform2dEdge<NT16>) {
         if (xform2d_core_tiles<NT16>(n) < NT16)
-            return xform2d_go<CT, DIR, NT16, EPI, true>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+            return xform2d_go<CT, DIR, NT16, EPI, true>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
     }
-    return xform2d_go<CT, DIR, NT16, EPI, false>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+    return xform2d_go<CT, DIR, NT16, EPI, false>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
 }
 
 template <typename CT, int DIR, int EPI>
 static hipError_t xform2d_np(const double* in, double* out, const double* Upad, int n, int np, long nimg,
-                             double alpha, hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr) {
+                             double alpha, hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr,
+                             long ldi = 0, long ldo = 0) {
     switch (np / 16) {
-        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
-        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
-        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
-        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
-        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
-        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard);
+        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename CT>
 static hipError_t xform2d_prec(int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
-                               long nimg, double alpha, hipStream_t st, const int* guard) {
-    if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st, nullptr, guard);
-    if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard);
-    if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard);
-    if (epi == 2) return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard);
+                               long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
+    if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st, nullptr, guard, ldi, ldo);
+    if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard, ldi, ldo);
+    if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard, ldi, ldo);
+    if (epi == 2) return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard, ldi, ldo);
     return hipErrorInvalidValue;
 }
 
@@ -1197,13 +1202,19 @@ static hipError_t xform2d_bf16_np(const double* in, double* out, const double* M
 
 bool xform2d_supported(int np) { return np >= 16 && np <= kXform2dMaxNp && np % 16 == 0; }
 
+long eig_modes(int dim, int n) {
+    const long nd = (long)n * n * (dim == 3 ? n : 1);
+    if (dim == 2 && xform2d_supported((n + 15) / 16 * 16)) return (nd + 15) / 16 * 16;
+    return nd;
+}
+
 // Sum over nimg n x n images Y of ||C Y C^T||_F^2, written as <Y G, G Y>_F with
 // G = C^T C (symmetric, padded to NP): both MFMA products read the staged
 // image, there is no intermediate product to store, and one barrier pair per
 // image suffices.  Per-block partial sums in a fixed order.
 template <int NT16, bool CORE>
 __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ in, const double* __restrict__ Gpad,
-                                                     int n, long nimg, double* __restrict__ partial) {
+                                                     int n, long nimg, double* __restrict__ partial, long ldi) {
     using T = TileLds<double, NT16>;
     constexpr int NP = NT16 * 16;
     constexpr int NC = CORE ? NT16 - 1 : NT16;
@@ -1236,7 +1247,7 @@ __global__ __launch_bounds__(512) void k_gram_norm2d(const double* __restrict__ 
     constexpr int PER = (NP * NP + 511) / 512;
     double pre[PER];
     auto load_img = [&](long img) {
-        const double* src = in + img * nn;
+        const double* src = in + img * ldi;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k, r = i / NP, c = i % NP;
@@ -1441,7 +1452,7 @@ __device__ __forceinline__ void block_sum2(double x, double y, double* __restric
 template <int NT16, bool CORE>
 static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, long nimg, double* partial,
                                  int max_blocks, double* out, double* out_host, hipStream_t st,
-                                 const CycleFlag& flag) {
+                                 const CycleFlag& flag, long ldi) {
     const size_t shm = sizeof(double) * 2 * (size_t)TileLds<double, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
@@ -1453,7 +1464,7 @@ static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, lo
     const long blocks = persistent_blocks(shm, nimg);
     if (blocks > max_blocks) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_gram_norm2d<NT16, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, Gpad, n, nimg,
-                       partial);
+                       partial, ldi);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, partial, (int)blocks, out, out_host, 1, nullptr,
                        flag);
     return hipGetLastError();
@@ -1462,37 +1473,39 @@ static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, lo
 template <int NT16>
 static hipError_t gram_norm2d_launch(const double* in, const double* Gpad, int n, long nimg, double* partial,
                                      int max_blocks, double* out, double* out_host, hipStream_t st,
-                                     const CycleFlag& flag) {
+                                     const CycleFlag& flag, long ldi) {
     if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
     if constexpr (kXform2dEdge<NT16>) {
         if (xform2d_core_tiles<NT16>(n) < NT16)
-            return gram_norm2d_go<NT16, true>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+            return gram_norm2d_go<NT16, true>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
     }
-    return gram_norm2d_go<NT16, false>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+    return gram_norm2d_go<NT16, false>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
 }
 
 hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
                               int max_blocks, double* out, double* out_host, hipStream_t st,
-                              const CycleFlag& flag) {
+                              const CycleFlag& flag, long ldi) {
     if (nimg <= 0 || !xform2d_supported(np)) return hipErrorInvalidValue;
     if (flag.dev && !flag.thr) return hipErrorInvalidValue;
+    if (ldi == 0) ldi = (long)n * n;
+    if (ldi < (long)n * n) return hipErrorInvalidValue;
     switch (np / 16) {
-        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
-        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
-        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
-        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
-        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
-        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag);
+        case 1: return gram_norm2d_launch<1>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
+        case 2: return gram_norm2d_launch<2>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
+        case 3: return gram_norm2d_launch<3>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
+        case 4: return gram_norm2d_launch<4>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
+        case 5: return gram_norm2d_launch<5>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
+        case 6: return gram_norm2d_launch<6>(in, Gpad, n, nimg, partial, max_blocks, out, out_host, st, flag, ldi);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
-                          int np, long nimg, double alpha, hipStream_t st, const int* guard) {
+                          int np, long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
     if (nimg <= 0) return hipSuccess;
     if (!xform2d_supported(np)) return hipErrorInvalidValue;
-    if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard);
-    if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard);
+    if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard, ldi, ldo);
+    if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard, ldi, ldo);
     return hipErrorInvalidValue;
 }
 
@@ -1733,9 +1746,9 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
     }
 }
 
-hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
+hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, long nx,
                           const double* in, double* out, long S, bool fwdsub, hipStream_t st, const int* guard) {
-    long Nx = (long)n * n * (dim == 3 ? n : 1);
+    long Nx = nx > 0 ? nx : (long)n * n * (dim == 3 ? n : 1);
     long total = S * Nx;
     if (total <= 0) return hipSuccess;
     if (fwdsub && in == out) return hipErrorInvalidValue;
@@ -2465,7 +2478,7 @@ hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* k
                              const double* fh, const double* uin, double* uout, long S, double omega,
                              bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st,
                              const int* guard) {
-    long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
+    long Nx = eig_modes(dim, n), total = S * Nx;
     if (total <= 0) return hipSuccess;
     if (ec && zero_guess) return hipErrorInvalidValue;
     dim3 grid((unsigned)((total + 255) / 256));
@@ -2481,7 +2494,7 @@ hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* k
 
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st) {
-    long Nx = (long)n * n * (dim == 3 ? n : 1), total = S * Nx;
+    long Nx = eig_modes(dim, n), total = S * Nx;
     if (total <= 0) return hipSuccess;
     dim3 grid((unsigned)((total + 255) / 256));
     STH_NT_SWITCH(k_eig_residual, grid, ktmt, dim, mu1, n, Nx, fh, uh, rh, total)
@@ -2491,7 +2504,7 @@ hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double
 hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const double* ktmt, const double* mu1,
                                      int n, const double* fh, const double* uh, double* fc, long Sc,
                                      hipStream_t st) {
-    long Nx = (long)n * n * (dim == 3 ? n : 1), total = Sc * Nx;
+    long Nx = eig_modes(dim, n), total = Sc * Nx;
     if (total <= 0) return hipSuccess;
     dim3 grid((unsigned)((total + 255) / 256));
     STH_NT_SWITCH(k_eig_resid_restrict, grid, tr, ktmt, dim, mu1, n, Nx, fh, uh, fc, total)
@@ -2664,7 +2677,7 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
                                 double omega, long S, int chain, const double* vw, double* partial,
                                 long max_partial, double* out, double* out_host, hipStream_t st,
                                 const CycleFlag& flag) {
-    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    const long Nx = eig_modes(dim, n);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
@@ -2696,7 +2709,7 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   const double* vw, double* partial, long max_partial, double* out,
                                   double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag,
                                   bool sums) {
-    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    const long Nx = eig_modes(dim, n);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
@@ -2726,7 +2739,7 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
 
 hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial, double* out, double* out_host,
                              hipStream_t st, const int* guard, const CycleFlag& flag) {
-    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    const long Nx = eig_modes(dim, n);
     if (chain < 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
     const long blocks = ((S / chain) * Nx + 255) / 256;
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
@@ -2829,7 +2842,7 @@ bool coarse_tail_shape(int Nt, long SA, int* G, int* LA) {
 hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
                                   const double* mu1, int n, const double* fa, double* ua,
                                   const Transfer& tr, double omega, long SA, hipStream_t st, const int* guard) {
-    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    const long Nx = eig_modes(dim, n);
     int G = 0, LA = 0;
     if (!coarse_tail_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
     dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
@@ -2858,7 +2871,7 @@ hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const
 hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                            const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
                            int chain, hipStream_t st, const int* guard) {
-    const long Nx = (long)n * n * (dim == 3 ? n : 1);
+    const long Nx = eig_modes(dim, n);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;

@@ -72,14 +72,21 @@ hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, cons
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
                           long nbatch, long inner, hipStream_t st);
 
-// Both spatial axes of 2-D images (n x n each, nimg images) in one kernel:
+// Both spatial axes of 2-D images (n x n each, nimg images, image i at
+// in + i ldi and out + i ldo; 0: n^2) in one kernel:
 // dir 0: out = U^T R U; dir 1: Z = U Y U^T with epilogue epi (0 store,
 // 1 out += alpha Z, 2 out = alpha Z).  Upad is U padded to np x np; prec 0
 // computes in FP64 (MFMA f64), 1 in FP32 (MFMA f32, FP32 accumulation).
 constexpr int kXform2dMaxNp = 96;
 bool xform2d_supported(int np);
+// Spatial modes per time row of an eigenbasis vector: n^d, padded to a
+// multiple of 16 (128-byte rows) on the 2-D path of the one-kernel
+// transforms; the padded modes hold zeros (every eigenbasis kernel maps zero
+// data of a mode to zero).  The eigenbasis launchers use this count.
+long eig_modes(int dim, int n);
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
-                          long nimg, double alpha, hipStream_t st, const int* guard = nullptr);
+                          long nimg, double alpha, hipStream_t st, const int* guard = nullptr, long ldi = 0,
+                          long ldo = 0);
 
 // BF16x3 form of the same: out = M (In M^T) per image with the products
 // accumulated in FP32 from hi*hi + hi*lo + lo*hi bf16 MFMA products; pass
@@ -87,12 +94,12 @@ hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* 
 hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
                                  long nimg, double alpha, hipStream_t st);
 
-// Per slab and spatial mode: out[:, m] = A_m^{-1} in[:, m], A_m^{-1} =
+// Per slab and spatial mode (nx modes per time row; 0: n^d): out[:, m] = A_m^{-1} in[:, m], A_m^{-1} =
 // V (Z + mu_m I)^{-1} W (or the real Schur form of the level).  fwdsub:
 // instead the exact solution of the S coupled slabs in the eigenbasis,
 // out_s = A_m^{-1}(in_s + e_1 out_{s-1}[Nt-1]) (forward substitution),
 // computed parallel in time (in and out must differ).
-hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n,
+hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, long nx,
                           const double* in, double* out, long S, bool fwdsub, hipStream_t st,
                           const int* guard = nullptr);
 
@@ -162,14 +169,15 @@ hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const 
                                      int n, const double* fh, const double* uh, double* fc, long Sc,
                                      hipStream_t st);
 
-//  out[0] = sum over the nimg n x n images Y of ||C Y C^T||_F^2 (2-D, np <= 96),
+//  out[0] = sum over the nimg n x n images Y (image i at in + i ldi; 0: n^2)
+//  of ||C Y C^T||_F^2 (2-D, np <= 96),
 //  the squared B-spline norm of an eigenbasis vector without forming it,
 //  computed as <Y G, G Y>_F with Gpad = C^T C (np x np, zero padded); partial
 //  needs max_blocks entries; the sum also goes to out_host (mapped pinned host
 //  memory) if not null
 hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int np, long nimg, double* partial,
                               int max_blocks, double* out, double* out_host, hipStream_t st,
-                              const CycleFlag& flag = CycleFlag{});
+                              const CycleFlag& flag = CycleFlag{}, long ldi = 0);
 
 // rc[m] = (P^T (x) I) [r[2m]; r[2m+1]],  m < Sc
 hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* rc, long Sc,

@@ -45,6 +45,7 @@ struct sth_handle {
     Setup S;
     int dim = 2, n = 0, np = 0, Nt = 0, p = 0, L = 0;
     long Nx = 0;
+    long Nxe = 0;                       // modes per time row of an eigenbasis vector (eig_modes)
     double omega = 0.5;
     int nu_pre = 1, nu_post = 1;
     int prec = 0;                       // sth_prec of the spatial transforms
@@ -199,6 +200,8 @@ static void drop_graph(sth_handle* h) {
 }
 
 static long slab_len(const sth_handle* h) { return (long)h->Nt * h->Nx; }
+// slab length of an eigenbasis vector (time rows padded to eig_modes)
+static long eslab_len(const sth_handle* h) { return (long)h->Nt * h->Nxe; }
 
 // ---------------------------------------------------------------------------
 // timing helpers
@@ -289,7 +292,7 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
         }
         {
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
-            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, fwdsub, st));
+            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, 0, b0, b1, ns, fwdsub, st));
         }
         {
             Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, (epi == 1 ? 24.0 : 16.0) * dof, st);
@@ -305,7 +308,7 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
         {
             double dof = (double)ns * slab_len(h);
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
-            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, b1, b0, ns, fwdsub, st));
+            HIPCHK(launch_timemix(2, h->Nt, h->mixes[lvl], h->mu1, h->n, 0, b1, b0, ns, fwdsub, st));
         }
         if ((rc = xform_s(h, pr, b0, b1, h->Ti, rows, n, st))) return rc;
         if ((rc = xform_x(h, pr, epi, b1, u, h->Ti, rows * n, alpha, st))) return rc;
@@ -317,7 +320,7 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
         {
             double dof = (double)ns * slab_len(h);
             Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
-            HIPCHK(launch_timemix(3, h->Nt, h->mixes[lvl], h->mu1, h->n, b0, b1, ns, fwdsub, st));
+            HIPCHK(launch_timemix(3, h->Nt, h->mixes[lvl], h->mu1, h->n, 0, b0, b1, ns, fwdsub, st));
         }
         if ((rc = xform_s(h, pr, b1, b0, h->Ti, rows, n * n, st))) return rc;      // z
         if ((rc = xform_s(h, pr, b0, b1, h->Ti, rows * n, n, st))) return rc;      // y
@@ -436,7 +439,11 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     h->tlev = 0;
     if (h->dim == 2 && xform2d_supported(h->np)) {
         Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, 16.0 * dof, st);
-        HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st, guard));
+        // eigenbasis rows are eig_modes long: the forward transform writes,
+        // and the inverse reads, images at that stride
+        const long ld = h->Nxe;
+        HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st, guard, fwd ? 0 : ld,
+                              fwd ? ld : 0));
         return STH_OK;
     }
     // axis by axis: x (contiguous), then y (and z), ping-ponging tmp/out
@@ -492,7 +499,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     if (lvl == h->L - 1) {
         double dof = (double)S * slab_len(h);
         Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
-        HIPCHK(launch_timemix(h->dim, h->Nt, h->mixes[lvl], h->mu1, h->n, eig_f(h, lvl),
+        HIPCHK(launch_timemix(h->dim, h->Nt, h->mixes[lvl], h->mu1, h->n, h->Nxe, eig_f(h, lvl),
                               eig_u(h, lvl, h->ecur[lvl]), S, true, st, h->guard));
         return STH_OK;
     }
@@ -509,7 +516,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         return STH_OK;
     }
     if (zero_guess && h->nu_pre == 0) {
-        HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * slab_len(h), 0.0, st));
+        HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * eslab_len(h), 0.0, st));
         zero_guess = false;
     }
     if (lvl == 0 && h->presmoothed) {
@@ -560,8 +567,8 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
 static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
     h->tlev = 0;
     const long S = h->lev_S[0];
-    const long len = S * slab_len(h);
-    const double dof = (double)len;
+    const long len = S * eslab_len(h);             // eigenbasis layout (padded rows)
+    const double dof = (double)S * slab_len(h);
     const int c = h->ecur[0];
     if (h->pending_ec) {
         // the cycle's prolongation and post-smoothing step, the residual norm
@@ -641,8 +648,8 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
 static int eig_exact_norm(sth_handle* h, hipStream_t st, const CycleFlag& fin = CycleFlag{}) {
     h->tlev = 0;
     const long S = h->lev_S[0];
-    const long len = S * slab_len(h);
-    const double dof = (double)len;
+    const long len = S * eslab_len(h);             // eigenbasis layout (padded rows)
+    const double dof = (double)S * slab_len(h);
     const long rows = S * h->Nt;
     int rc;
     {
@@ -654,7 +661,7 @@ static int eig_exact_norm(sth_handle* h, hipStream_t st, const CycleFlag& fin = 
         // ||C r^ C^T||^2 per image as <r^ G, G r^> (G = C^T C), r not formed
         Timed tm(h, STH_K_RESNORM, dof * 4.0 * h->n, dof * 8.0, st);
         HIPCHK(launch_gram_norm2d(h->buf0, h->Gf, h->n, h->np, rows, h->partial, kNormBlocks, h->dnorm,
-                                  h->hnorm_dev, st, fin));
+                                  h->hnorm_dev, st, fin, h->Nxe));
         return STH_OK;                  // stored hnorm[0] itself
     }
     if (h->dim == 2) {
@@ -731,6 +738,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     if (!e.empty()) return fail(STH_EINVAL, e);
     long n = q.n(), np = (n + 15) / 16 * 16;
     long Nx = n * n * (q.dim == 3 ? n : 1);
+    if (q.basis == 1) Nx = std::max(Nx, eig_modes(q.dim, (int)n));   // eigenbasis rows are padded
     long slab = (long)q.Nt() * Nx;
     size_t total = 0;
     total += 2 * sizeof(double) * np * np;                   // transforms
@@ -784,6 +792,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->Nt = h->S.Nt;
     h->p = q.degree;
     h->Nx = (long)h->n * h->n * (q.dim == 3 ? h->n : 1);
+    h->Nxe = eig_modes(q.dim, h->n);
     h->omega = q.omega;
     h->nu_pre = q.nu_pre;
     h->nu_post = q.nu_post;
@@ -870,7 +879,9 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     auto dalloc = [&](double** ptr, size_t count) -> bool {
         return hipMalloc((void**)ptr, std::max<size_t>(count, 1) * sizeof(double)) == hipSuccess;
     };
-    long slab = slab_len(h);
+    // buffers both iterations use hold either layout
+    const long slab = h->basis == 1 ? std::max(slab_len(h), eslab_len(h)) : slab_len(h);
+    const long eslab = eslab_len(h);
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
@@ -909,13 +920,21 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 Cf[(size_t)i * np + j] = c;
                 Ci[(size_t)j * np + i] = c;
             }
-        h->n_cpartial = 2 * (((q.n_slabs / 2) * h->Nx + 255) / 256);   // two sums per block
+        h->n_cpartial = 2 * (((q.n_slabs / 2) * h->Nxe + 255) / 256);   // two sums per block
         if (!dalloc(&h->cpartial, (size_t)h->n_cpartial) ||
             !dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
-            !dalloc(&h->e0, (size_t)q.n_slabs * slab) || !dalloc(&h->e1, (size_t)q.n_slabs * slab) ||
-            !dalloc(&h->e2, (size_t)q.n_slabs * slab) ||
-            (h->fuse_close && !dalloc(&h->e3, (size_t)q.n_slabs * slab)))
+            !dalloc(&h->e0, (size_t)q.n_slabs * eslab) || !dalloc(&h->e1, (size_t)q.n_slabs * eslab) ||
+            !dalloc(&h->e2, (size_t)q.n_slabs * eslab) ||
+            (h->fuse_close && !dalloc(&h->e3, (size_t)q.n_slabs * eslab)))
             return cleanup(STH_ENOMEM, "device allocation failed");
+        // the padded modes of the eigenbasis vectors start (and stay) zero
+        for (double* v : {h->e0, h->e1, h->e2, h->e3})
+            if (v && hipMemsetAsync(v, 0, sizeof(double) * (size_t)q.n_slabs * eslab, s) != hipSuccess)
+                return cleanup(STH_EHIP, "clearing the eigenbasis vectors failed");
+        for (int l = 1; l < h->L; ++l)
+            for (double* v : {h->lu[l], h->lf[l], h->lu2[l]})
+                if (v && hipMemsetAsync(v, 0, sizeof(double) * (size_t)h->lev_S[l] * slab, s) != hipSuccess)
+                    return cleanup(STH_EHIP, "clearing the eigenbasis vectors failed");
         // mode weights of the lower bound of the B-spline residual norm
         const std::vector<double> vwh = residual_mode_weights(h->S);
         if (!dalloc(&h->vw, (size_t)2 * n))
