@@ -1,17 +1,21 @@
 """Benchmark: space-time DOF/s of the multigrid solve to relative residual 1e-8.
 
 One step = one full solve L_h u = f from u = 0 (V(1,1) cycles of the
-time-parallel multigrid with the damped block-Jacobi slab smoother) until
-||f - L_h u||_2 <= 1e-8 ||f||_2, on the 2D workload: unit square, p = 3,
-64 x 64 elements, 256 slabs x 2 time elements (5,408,000 unknowns), right-hand
-side from 8 random Fourier modes (seed 2).  Inputs are resident in HBM when
-the timed region starts; setup and right-hand-side assembly are outside it.
+time-parallel multigrid with the damped block-Jacobi slab smoother, iterated
+in the spatial eigenbasis) until ||f - L_h u||_2 <= 1e-8 ||f||_2, on the
+largest single-GPU workload by default: unit square, p = 2, 256 x 256
+elements, 1024 slabs x 1 time element (201,326,592 unknowns), right-hand side
+from 8 random Fourier modes (seed 4).  Inputs are resident in HBM when the
+timed region starts; setup and right-hand-side assembly are outside it.
 
-The timed region replays the solve iterations as HIP graphs.  Prints one
-JSON line with the throughput, the roofline of the dominant kernel class
-on the finest multigrid level (HIP events on the solve's stream around each
-of its launches there, in an eager pass of the same K solves right after the
-timed region; HBM traffic from the
+The timed region launches the solve's kernels eagerly with speculative
+cycles (the library default).  The headline is the plain FP64 method; the
+same workload is then solved with FP32 and BF16x3 spatial transforms (FP64
+defect correction around reduced-precision inner solves) and reported beside
+it with its error against the FP64 result.  The JSON line also carries the
+roofline of the dominant kernel class on the finest multigrid level (HIP
+events on the solve's stream around each of its launches there, in an eager
+pass of the same K solves right after the timed region; HBM traffic from the
 committed rocprofv3 counter summary when it matches the kernel sources) and
 the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
@@ -32,7 +36,7 @@ PEAKS = {  # MI355X published peaks
     "bf16": 2.5e15,
 }
 # dominant-class roofline: which bound applies to each kernel class
-CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "timemix": "hbm",
+CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "xform_axis": "mfma", "timemix": "hbm",
                "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma",
                "eig_smooth": "hbm", "eig_resid": "hbm", "resnorm": "mfma", "eig_cycle_end": "hbm",
                "eig_cycle_close": "hbm", "eig_coarse": "hbm"}
@@ -82,10 +86,14 @@ def cpu_baseline(cfg, sample_slabs):
     }
 
 
+KERNEL_SOURCES = ("kernels.hpp", "kernels_common.hpp", "k_residual.hip", "k_xform2d.hip", "k_xform_axis.hip",
+                  "k_eigen.hip", "k_misc.hip")
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "kernels.hpp"):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1802_09277_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -196,29 +204,74 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+# kernel classes merged for the choice of the dominant class: the two
+# per-axis transform kernels are one transform
+MERGED = {"xform_axis": ("xform_x", "xform_s")}
+
+
+def merged_classes(names):
+    out = {}
+    for k in names:
+        tgt = next((m for m, parts in MERGED.items() if k in parts), k)
+        out.setdefault(tgt, []).append(k)
+    return out
+
+
+def report_sum(s, parts):
+    reps = [s.timing_report(k) for k in parts]
+    return {key: sum(r[key] for r in reps) for key in ("launches", "ms", "flops", "bytes")}
+
+
+def make_solver(cfg, prec, args):
+    import paper_1802_09277_amd as sth
+    s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
+                   prec=prec, basis=args.basis, coarse_slabs=args.coarse_slabs)
+    if args.no_speculate:
+        s.speculate(False)
+    return s
+
+
+def timed_solves(s, f, u, args, steps):
+    """K solves from u = 0 between two device synchronisations; ms per solve."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = relres = None
+    for _ in range(steps):
+        u.zero_()
+        iters, relres, _ = s.solve(f, u, rtol=args.rtol, maxit=200)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, iters, relres
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--config", default="C4")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="transform precision of the headline solve")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--basis", default="eigen", choices=["nodal", "eigen"],
                     help="iterate on B-spline coefficients or in the spatial eigenbasis (same iterates)")
     ap.add_argument("--coarse-slabs", type=int, default=None,
                     help="coarsest multigrid level: at most this many slabs (library default 64)")
-    ap.add_argument("--cpu-sample-slabs", type=int, default=4)
+    ap.add_argument("--cpu-sample-slabs", type=int, default=None,
+                    help="slabs of the oracle's forward substitution timed for the CPU baseline")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB three times first (the reference "
                          "kernel of known size that scales the HBM counters of a --pmc run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-forms", action="store_true",
+                    help="skip the FP32 / BF16x3 solves reported beside the headline")
     ap.add_argument("--no-speculate", action="store_true",
                     help="wait for each cycle's norm before enqueueing the next (library default: speculate)")
     ap.add_argument("--serve", action="store_true", help="serving workload (p50/p99 latency) instead")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=int, default=160)
+    ap.add_argument("--serve-prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the slab solver runs on a single MI355X; "
@@ -234,12 +287,9 @@ def main():
 
     cfg = W.CONFIGS[args.config]
     torch.cuda.set_device(0)
-    stream = torch.cuda.Stream()          # non-default stream: solve iterations replay as HIP graphs
+    stream = torch.cuda.Stream()          # the solves run on a non-default stream
     torch.cuda.set_stream(stream)
-    s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
-                   prec=args.prec, basis=args.basis, coarse_slabs=args.coarse_slabs)
-    if args.no_speculate:
-        s.speculate(False)
+    s = make_solver(cfg, args.prec, args)
     f = s.new_vector()
     s.load_rhs(cfg.modes(), f)
     u = s.new_vector()
@@ -257,41 +307,32 @@ def main():
     # warm-up with every kernel class timed on the finest level, to find the
     # dominant kernel class there (the coarser levels hold half the work)
     s.timing((1 << len(sth.KCLASS)) - 1, level=0)
-    iters = 0
     for _ in range(max(args.warmup, 1)):
         u.zero_()
-        iters, relres, _ = s.solve(f, u, rtol=args.rtol, maxit=200)
+        s.solve(f, u, rtol=args.rtol, maxit=200)
     totals = {k: s.timing_report(k) for k in sth.KCLASS}
-    dominant = max(totals, key=lambda k: totals[k]["ms"])
+    groups = merged_classes([k for k, v in totals.items() if v["launches"]])
+    group_ms = {g: sum(totals[k]["ms"] for k in parts) for g, parts in groups.items()}
+    dominant = max(group_ms, key=group_ms.get)
     log("warm-up kernel classes on the finest level (ms per solve): " +
-        ", ".join(f"{k}={v['ms'] / max(args.warmup, 1):.3f}" for k, v in totals.items() if v["launches"]))
+        ", ".join(f"{g}={v / max(args.warmup, 1):.3f}" for g, v in group_ms.items()))
     s.timing(0)
 
-    # timed region: K solves, solve iterations replayed as HIP graphs
-    for _ in range(2):                    # capture the graph outside the timed region
-        u.zero_()
-        s.solve(f, u, rtol=args.rtol, maxit=200)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        u.zero_()
-        iters, relres, _ = s.solve(f, u, rtol=args.rtol, maxit=200)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    # timed region: K solves, eager launches with speculative cycles
+    timed_solves(s, f, u, args, 1)
+    ms, iters, relres = timed_solves(s, f, u, args, args.steps)
+    u_head = u.clone()
 
     # roofline pass: the same K solves with HIP events around every launch
     # of the dominant kernel class on the finest level (events need
     # individually launched kernels)
-    s.timing(1 << sth.KCLASS[dominant], level=0)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        u.zero_()
-        s.solve(f, u, rtol=args.rtol, maxit=200)
-    torch.cuda.synchronize()
-    ms_events = (time.perf_counter() - t2) * 1e3 / args.steps
-    rep = s.timing_report(dominant)
+    parts = groups[dominant]
+    mask = 0
+    for k in parts:
+        mask |= 1 << sth.KCLASS[k]
+    s.timing(mask, level=0)
+    ms_events, _, _ = timed_solves(s, f, u, args, args.steps)
+    rep = report_sum(s, parts)
     s.timing(0)
     bound = CLASS_BOUND[dominant]
     if bound == "mfma":
@@ -300,17 +341,39 @@ def main():
         achieved = products * rep["flops"] / (rep["ms"] * 1e-3)
         peak = PEAKS[peak_key]
         roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s"}
+        roof["algorithmic_flops_per_launch"] = rep["flops"] / max(rep["launches"], 1)
     else:
         achieved = rep["bytes"] / (rep["ms"] * 1e-3)
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAKS["hbm"] / 1e9, "unit": "GB/s"}
+        roof["algorithmic_bytes_per_launch"] = rep["bytes"] / max(rep["launches"], 1)
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["algorithmic_bytes_per_launch"] = rep["bytes"] / max(rep["launches"], 1)
     roof["traffic"] = measured_traffic(cfg.name, args.basis, args.prec, dominant)
     roof["kernel_class"] = dominant
     roof["level"] = 0
     roof["launches_per_step"] = rep["launches"] / args.steps
     roof["mean_launch_us"] = rep["ms"] * 1e3 / max(rep["launches"], 1)
     roof["events_pass_ms_per_step"] = ms_events
+    levels, coarse_slabs = s.num_levels, s.coarse_slabs
+    s.close()
+
+    forms = {args.prec: {"value": cfg.unknowns / (ms * 1e-3), "ms_per_step": ms, "v_cycles": iters,
+                         "final_relres": relres}}
+    if not args.no_precision_forms and args.basis == "eigen":
+        # the same solve with reduced-precision transforms, error against the headline result
+        for prec in ("fp64", "fp32", "bf16x3"):
+            if prec == args.prec:
+                continue
+            sp = make_solver(cfg, prec, args)
+            up = sp.new_vector()
+            timed_solves(sp, f, up, args, max(args.warmup, 1))
+            msp, itp, rrp = timed_solves(sp, f, up, args, args.steps)
+            err = float(torch.linalg.vector_norm(up - u_head) / torch.linalg.vector_norm(u_head))
+            sp.close()
+            del up
+            forms[prec] = {"value": cfg.unknowns / (msp * 1e-3), "ms_per_step": msp, "v_cycles": itp,
+                           "final_relres": rrp, f"rel_diff_vs_{args.prec}": err}
+            log(f"precision form {prec}: {msp:.2f} ms per solve, {itp} cycles, relres {rrp:.2e}, "
+                f"|u - u_{args.prec}| / |u_{args.prec}| {err:.2e}")
 
     out = {
         "metric": METRIC,
@@ -335,13 +398,13 @@ def main():
             "iterate_basis": args.basis,
             "v_cycles": iters,
             "final_relres": relres,
-            "levels": s.num_levels,
-            "coarse_slabs": s.coarse_slabs,
+            "levels": levels,
+            "coarse_slabs": coarse_slabs,
             "speculative_cycles": not args.no_speculate,
         },
+        "precision_forms": forms,
         "roofline": roof,
     }
-    s.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_slabs)
     print(json.dumps(out), flush=True)

@@ -1,0 +1,999 @@
+// gfx950 kernels of the space-time slab solver: the temporal transform and
+// shifted divide of the slab inverse (Section 3.3 in real block form), the
+// exact coarsest-level solve parallel in time, and the pointwise passes of the
+// multigrid iteration in the spatial eigenbasis (residual, smoothing steps,
+// time restriction and prolongation fused per Section 3.1).
+#include "kernels_common.hpp"
+
+namespace sth {
+
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
+                                                 long Nx, const double* __restrict__ in,
+                                                 double* __restrict__ out, long total, const int* guard) {
+    if (guard_off(guard)) return;
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    const double* gp = in + s * NT * Nx + m;
+    double g[NT], z[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) g[t] = gp[(long)t * Nx];
+    shifted_solve<NT, SCHUR>(tm, mu, g, z);
+    double* o = out + s * NT * Nx + m;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) o[(long)t * Nx] = z[t];
+}
+
+// Exact forward substitution over S slabs in the spatial eigenbasis, parallel
+// in time.  Per mode the slab systems are A u_s = g_s + e_1 x_{s-1} with the
+// scalar x_{s-1} = u_{s-1}[N_t - 1], so u_s = a_s + x_{s-1} c with
+// a_s = A^{-1} g_s (independent over s) and c = A^{-1} e_1, and the scalars
+// obey x_s = a_s[N_t-1] + gamma x_{s-1}, gamma = c[N_t-1].  A block holds 16
+// modes (one 128-byte line per time row) x 16 slab groups: each thread solves
+// its group's slabs (into out), the groups' recurrences are chained through
+// LDS, and a second sweep adds x_{s-1} c.  in and out must differ.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
+                                                      long Nx, const double* __restrict__ in,
+                                                      double* __restrict__ out, long S, const int* guard) {
+    if (guard_off(guard)) return;
+    constexpr int MB = 16, G = 16, LR = 4;      // LR: slabs per group held in registers
+    __shared__ double xe_s[G][MB], gl_s[G][MB];
+    const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
+    const long m = (long)blockIdx.x * MB + ml;
+    const long L = (S + G - 1) / G;
+    const long sb = g * L, se = (sb + L < S) ? sb + L : S;
+    const bool inreg = L <= LR;
+    double c[NT], areg[LR][NT], xe = 0.0, gl = 1.0, gamma = 0.0;
+    const bool active = m < Nx;
+    double mu = 0.0;
+    if (active) {
+        mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(tm, sh, e1, c);
+        gamma = c[NT - 1];
+        if (inreg) {
+            // all loads of the group first, then the (independent) solves
+#pragma unroll
+            for (int i = 0; i < LR; ++i)
+                if (sb + i < se) {
+                    const double* gp = in + (sb + i) * NT * Nx + m;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) areg[i][t] = gp[(long)t * Nx];
+                }
+#pragma unroll
+            for (int i = 0; i < LR; ++i)
+                if (sb + i < se) {
+                    double a[NT];
+                    shifted_solve<NT, SCHUR>(tm, sh, areg[i], a);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) areg[i][t] = a[t];
+                    xe = a[NT - 1] + gamma * xe;  // group recurrence from x = 0
+                    gl *= gamma;                  // gamma^(slabs so far)
+                }
+        }
+        for (long s = inreg ? se : sb; s < se; ++s) {
+            const double* gp = in + s * NT * Nx + m;
+            double gv[NT], a[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) gv[t] = gp[(long)t * Nx];
+            shifted_solve<NT, SCHUR>(tm, sh, gv, a);
+            double* o = out + s * NT * Nx + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) o[(long)t * Nx] = a[t];
+            xe = a[NT - 1] + gamma * xe;          // group recurrence from x = 0
+            gl *= gamma;                          // gamma^(slabs so far)
+        }
+    }
+    xe_s[g][ml] = xe;
+    gl_s[g][ml] = gl;
+    __syncthreads();
+    if (!active) return;
+    double x = 0.0;                               // x entering the group
+    for (int h = 0; h < g; ++h) x = xe_s[h][ml] + gl_s[h][ml] * x;
+    if (inreg) {
+#pragma unroll
+        for (int i = 0; i < LR; ++i)
+            if (sb + i < se) {
+                double* o = out + (sb + i) * NT * Nx + m;
+                double u[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) u[t] = areg[i][t] + x * c[t];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) o[(long)t * Nx] = u[t];
+                x = u[NT - 1];
+            }
+        return;
+    }
+    for (long s = sb; s < se; ++s) {
+        double* o = out + s * NT * Nx + m;
+        double u[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = o[(long)t * Nx] + x * c[t];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) o[(long)t * Nx] = u[t];
+        x = u[NT - 1];
+    }
+}
+
+hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, long nx,
+                          const double* in, double* out, long S, bool fwdsub, hipStream_t st, const int* guard) {
+    long Nx = nx > 0 ? nx : (long)n * n * (dim == 3 ? n : 1);
+    long total = S * Nx;
+    if (total <= 0) return hipSuccess;
+    if (fwdsub && in == out) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((total + 255) / 256));
+    dim3 gridm((unsigned)((Nx + 15) / 16));
+#define STH_TM_LAUNCH(NTV, SC)                                                                           \
+    if (fwdsub)                                                                                          \
+        hipLaunchKernelGGL((k_timemix_scan<NTV, SC>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in,   \
+                           out, S, guard);                                                               \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_timemix<NTV, SC>), grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out,    \
+                           total, guard);
+#define STH_TM_CASE(NTV)                 \
+    case NTV:                            \
+        if (tm.schur) {                  \
+            STH_TM_LAUNCH(NTV, true)     \
+        } else {                         \
+            STH_TM_LAUNCH(NTV, false)    \
+        }                                \
+        break;
+    switch (Nt) {
+        STH_TM_CASE(2) STH_TM_CASE(3) STH_TM_CASE(4) STH_TM_CASE(5)
+        STH_TM_CASE(6) STH_TM_CASE(7) STH_TM_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_TM_CASE
+#undef STH_TM_LAUNCH
+    return hipGetLastError();
+}
+// ---------------------------------------------------------------------------
+// Iteration in the spatial eigenbasis.  With u = (I (x) U_x) u^ and
+// r^ = (I (x) U_x^T) r, where U_x^T M_x U_x = I and U_x^T K_x U_x = diag(mu),
+// the slab operator A_n = K_t (x) M_x + M_t (x) K_x becomes
+// K_t (x) I + M_t (x) diag(mu) and B_n = N_t (x) M_x becomes N_t (x) I
+// (eq. structureAn), so the residual r^_n = f^_n - A^ u^_n + B^ u^_{n-1} and
+// the slab inverse are both pointwise over the spatial modes.
+// ---------------------------------------------------------------------------
+// one damped block-Jacobi step u^out = u^in + omega A^{-1}(f^ - L^ u^in); with
+// zero_guess u^in is taken as 0 (and not read).  uin and uout must differ
+// (the coupling reads the previous slab's old iterate).  PRO: the coarse
+// correction (P_t (x) I) ec of the next coarser level is added to u^in first
+// (prolongation fused into the first post-smoothing step).
+template <int NT, bool PRO, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_smooth(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                    const double* __restrict__ mu1, int n, long Nx,
+                                                    const double* __restrict__ fh, const double* __restrict__ uin,
+                                                    double* __restrict__ uout, long total, double omega,
+                                                    int zero_guess, const double* __restrict__ ec, Transfer tr,
+                                                    const int* guard) {
+    if (guard_off(guard)) return;
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    const long base = s * NT * Nx + m;
+    double g[NT], u[NT], z[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) g[t] = fh[base + (long)t * Nx];
+    if (!zero_guess) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = uin[base + (long)t * Nx];
+        double prev = s > 0 ? uin[base - Nx] : 0.0;          // last time row of slab s-1
+        if (PRO) {
+            const long mc = s / 2;
+            const int h = (int)(s % 2);
+            double c[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) c[k] = ec[mc * NT * Nx + m + (long)k * Nx];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k) v += tr.P[(h * NT + t) * kNt + k] * c[k];
+                u[t] += v;
+            }
+            if (s > 0) {
+                // last row of slab s-1: second half of coarse slab (s-1)/2
+                const long mp = (s - 1) / 2;
+                const int hp = (int)((s - 1) % 2);
+                double v = 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k)
+                    v += tr.P[(hp * NT + NT - 1) * kNt + k] * ec[mp * NT * Nx + m + (long)k * Nx];
+                prev += v;
+            }
+        }
+        eig_residual_point<NT>(ktmt, mu, u, prev, g);
+    } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = 0.0;
+    }
+    shifted_solve<NT, SCHUR>(tm, mu, g, z);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) uout[base + (long)t * Nx] = u[t] + omega * z[t];
+}
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_eig_residual(const double* __restrict__ ktmt, int dim,
+                                                      const double* __restrict__ mu1, int n, long Nx,
+                                                      const double* __restrict__ fh, const double* __restrict__ uh,
+                                                      double* __restrict__ rh, long total) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long s = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    const long base = s * NT * Nx + m;
+    double g[NT], u[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        g[t] = fh[base + (long)t * Nx];
+        u[t] = uh[base + (long)t * Nx];
+    }
+    eig_residual_point<NT>(ktmt, mu, u, s > 0 ? uh[base - Nx] : 0.0, g);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) rh[base + (long)t * Nx] = g[t];
+}
+
+// residual of slabs 2m, 2m+1 restricted to coarse slab m (P_t^T (x) I)
+template <int NT>
+__global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const double* __restrict__ ktmt, int dim,
+                                                            const double* __restrict__ mu1, int n, long Nx,
+                                                            const double* __restrict__ fh,
+                                                            const double* __restrict__ uh, double* __restrict__ fc,
+                                                            long total) {
+    long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    long mc = idx / Nx, m = idx % Nx;
+    double mu = mode_shift(dim, mu1, n, m);
+    double acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const long s = 2 * mc + h;
+        const long base = s * NT * Nx + m;
+        double g[NT], u[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            g[t] = fh[base + (long)t * Nx];
+            u[t] = uh[base + (long)t * Nx];
+        }
+        eig_residual_point<NT>(ktmt, mu, u, s > 0 ? uh[base - Nx] : 0.0, g);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g[t];
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+}
+
+// End of a cycle on the finest level, for one spatial mode and a chain of
+// `chain` consecutive slabs (chain even, starting at an even slab): the
+// residual r^ = f^ - L u^ of the iterate (its squares summed per block into
+// partial[blockIdx.x], fixed order), the next cycle's first smoothing step
+// u'^ = u^ + omega A^{-1} r^ (into uout), and the restriction of the residual
+// of u'^ to the next level, fc = (P_t^T (x) I)[r'_{2k}; r'_{2k+1}].  The last
+// time row of the previous slab (old and smoothed iterate) is carried in
+// registers along the chain; a chain after slab 0 first repeats the
+// smoothing step of its preceding slab for that row.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                       const double* __restrict__ mu1, int n, long Nx,
+                                                       const double* __restrict__ fh, const double* __restrict__ uin,
+                                                       double* __restrict__ uout, double* __restrict__ fc,
+                                                       Transfer tr, double omega, int chain, long total,
+                                                       const double* __restrict__ vw,
+                                                       double* __restrict__ partial) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double ssq = 0.0, wsq = 0.0;
+    if (idx < total) {
+        const long q = idx / Nx, m = idx % Nx;
+        const long s0 = q * chain;
+        // loads first (the chain's first slab, and the slab before it), so
+        // that none waits behind the per-mode setup; the next slab's f^ and
+        // u^ are then loaded while the current one is processed
+        double fnx[NT], unx[NT], acc[NT];
+        {
+            const long b = s0 * NT * Nx + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                fnx[t] = fh[b + (long)t * Nx];
+                unx[t] = uin[b + (long)t * Nx];
+            }
+        }
+        double pg[NT], pu[NT], pq = 0.0;
+        if (s0 > 0) {
+            const long b = (s0 - 1) * NT * Nx + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                pg[t] = fh[b + (long)t * Nx];
+                pu[t] = uin[b + (long)t * Nx];
+            }
+            if (s0 > 1) pq = uin[b - Nx];
+        }
+        const double mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
+        const double wm = mode_weight(dim, vw, n, m);
+        double prev_old = 0.0, prev_new = 0.0;
+        if (s0 > 0) {
+            double z[NT];
+            eig_residual_point<NT>(ktmt, mu, pu, pq, pg);
+            shifted_solve<NT, SCHUR>(tm, sh, pg, z);
+            prev_old = pu[NT - 1];
+            prev_new = pu[NT - 1] + omega * z[NT - 1];
+        }
+#pragma unroll 1
+        for (int k = 0; k < chain; ++k) {
+            const int h = k & 1;
+            const long b = (s0 + k) * NT * Nx + m;
+            double g[NT], g2[NT], u[NT], z[NT], up[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                g[t] = fnx[t];
+                u[t] = unx[t];
+            }
+            if (k + 1 < chain) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    fnx[t] = fh[b + NT * Nx + (long)t * Nx];
+                    unx[t] = uin[b + NT * Nx + (long)t * Nx];
+                }
+            }
+            eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
+            double s2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
+            ssq += s2;
+            wsq += wm * s2;
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                up[t] = u[t] + omega * z[t];
+                uout[b + (long)t * Nx] = up[t];
+            }
+            // residual of u': A z = g (the block of the smoother is the slab
+            // operator), so f - A u' + e_1 u'_prev = (1 - omega) g + e_1 (u'_prev - u_prev)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) g2[t] = (1.0 - omega) * g[t];
+            g2[0] += up_prev_delta(prev_new, prev_old);
+            if (h == 0) {
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g2[t];
+            if (h == 1) {
+                const long mc = (s0 + k) / 2;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+            }
+            prev_old = u[NT - 1];
+            prev_new = up[NT - 1];
+        }
+    }
+    // block sums (fixed order) of ||r^||^2 and its weighted form
+    block_sum2(ssq, wsq, partial);
+}
+
+// Close of a cycle on the finest level followed by the start of the next
+// one, for one spatial mode and a chain of `chain` consecutive slabs (chain
+// even, starting at an even slab), in one pass over f^, the pre-smoothed
+// iterate u^ and the coarse correction ec:
+//   u1 = u^ + (P_t (x) I) ec                       (prolongation)
+//   u2 = u1 + omega A^{-1} r(u1)  -> uend          (post-smoothing step)
+//   ||r(u2)||^2 summed per block into partial[blockIdx.x] (fixed order)
+//   u3 = u2 + omega A^{-1} r(u2)  -> unext         (next pre-smoothing step)
+//   fc = (P_t^T (x) I)[r(u3)_{2k}; r(u3)_{2k+1}]   (restriction)
+// The residuals after a smoothing step follow from the identity
+// r(u + omega A^{-1} g)_s = (1 - omega) g_s + e_1 (delta of the coupling row
+// of slab s-1), and with it A^{-1} r(u2) = (1 - omega) A^{-1} r(u1) +
+// delta A^{-1} e_1, so every slab needs one slab solve.  The coupling rows of
+// the previous slab (u1, u2, u3) are carried along the chain; a chain after
+// slab 0 first repeats the two steps of its two preceding slabs.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                         const double* __restrict__ mu1, int n, long Nx,
+                                                         const double* __restrict__ fh,
+                                                         const double* __restrict__ upre,
+                                                         const double* __restrict__ ec, double* __restrict__ uend,
+                                                         double* __restrict__ unext, double* __restrict__ fc,
+                                                         Transfer tr, double omega, int chain, long total,
+                                                         const double* __restrict__ vw,
+                                                         double* __restrict__ partial, const int* guard) {
+    if (guard_off(guard)) return;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    double ssq = 0.0, wsq = 0.0;
+    if (idx < total) {
+        const long q = idx / Nx, m = idx % Nx;
+        const long s0 = q * chain;
+        const long slab = (long)NT * Nx;
+        // loads first: the chain's first slab (f^, u^ and ec) and, after slab
+        // 0, the two slabs before it, so that none waits behind the per-mode
+        // setup below
+        double fnx[NT], unx[NT], cnx[NT], c[NT], acc[NT];
+        {
+            const long b = s0 * slab + m, bc = (s0 / 2) * slab + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                fnx[t] = fh[b + (long)t * Nx];
+                unx[t] = upre[b + (long)t * Nx];
+                cnx[t] = ec[bc + (long)t * Nx];
+            }
+        }
+        const long sa = s0 - 2;                 // slab s0 - 2 (even): first half of coarse slab s0/2 - 1
+        double pc[NT], pua[NT], pfa[NT], pub[NT], pfb[NT], pq[NT], pqu = 0.0;
+        if (s0 > 0) {
+            const long ba = sa * slab + m, bc = (sa / 2) * slab + m, bb = (s0 - 1) * slab + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                pc[t] = ec[bc + (long)t * Nx];
+                pua[t] = upre[ba + (long)t * Nx];
+                pfa[t] = fh[ba + (long)t * Nx];
+                pub[t] = upre[bb + (long)t * Nx];
+                pfb[t] = fh[bb + (long)t * Nx];
+            }
+            if (sa > 0) {
+                // the coupling row of slab s0 - 3 from u^ and ec
+                const long bp = (sa - 1) * slab + m, bpc = ((sa - 1) / 2) * slab + m;
+                pqu = upre[bp + (long)(NT - 1) * Nx];
+#pragma unroll
+                for (int k = 0; k < NT; ++k) pq[k] = ec[bpc + (long)k * Nx];
+            }
+        }
+        const double mu = mode_shift(dim, mu1, n, m);
+        const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
+        // ca = A^{-1} e_1: a change of the coupling row moves A^{-1} r by a multiple of it
+        double ca[NT];
+        {
+            double e1[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+            shifted_solve<NT, SCHUR>(tm, sh, e1, ca);
+        }
+        const double wm = mode_weight(dim, vw, n, m);
+        // coupling rows of slab s0 - 1: u1, u2 and u3
+        double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+        if (s0 > 0) {
+            double u1[NT], g[NT], z[NT];
+            double q1 = 0.0;
+            if (sa > 0) {
+                double v = pqu;
+#pragma unroll
+                for (int k = 0; k < NT; ++k) v += tr.P[(NT + NT - 1) * kNt + k] * pq[k];
+                q1 = v;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u1[t] = pua[t];
+                g[t] = pfa[t];
+            }
+            prolong_add<NT>(tr, 0, pc, u1);
+            eig_residual_point<NT>(ktmt, mu, u1, q1, g);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
+            const double a1 = u1[NT - 1], a2 = u1[NT - 1] + omega * z[NT - 1];
+            // slab s0 - 1 (second half of the same coarse slab): both steps
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u1[t] = pub[t];
+                g[t] = pfb[t];
+            }
+            prolong_add<NT>(tr, 1, pc, u1);
+            eig_residual_point<NT>(ktmt, mu, u1, a1, g);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
+            const double u2last = u1[NT - 1] + omega * z[NT - 1];
+            const double z2last = (1.0 - omega) * z[NT - 1] + up_prev_delta(a2, a1) * ca[NT - 1];
+            p1 = u1[NT - 1];
+            p2 = u2last;
+            p3 = u2last + omega * z2last;
+        }
+#pragma unroll 1
+        for (int k = 0; k < chain; ++k) {
+            const int h = k & 1;
+            const long b = (s0 + k) * slab + m;
+            double g[NT], u1[NT], u2[NT], z[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                g[t] = fnx[t];
+                u1[t] = unx[t];
+            }
+            if (h == 0) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) c[t] = cnx[t];
+            }
+            if (k + 1 < chain) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    fnx[t] = fh[b + slab + (long)t * Nx];
+                    unx[t] = upre[b + slab + (long)t * Nx];
+                }
+                if (h == 1) {
+                    const long bc = ((s0 + k + 1) / 2) * slab + m;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) cnx[t] = ec[bc + (long)t * Nx];
+                }
+            }
+            // post-smoothing step from the prolonged iterate
+            prolong_add<NT>(tr, h, c, u1);
+            eig_residual_point<NT>(ktmt, mu, u1, p1, g);
+            shifted_solve<NT, SCHUR>(tm, sh, g, z);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                u2[t] = u1[t] + omega * z[t];
+                uend[b + (long)t * Nx] = u2[t];
+                g[t] *= (1.0 - omega);
+            }
+            const double d2 = up_prev_delta(p2, p1);
+            g[0] += d2;
+            // residual of the cycle's result, then the next smoothing step
+            // with A^{-1} r(u2) = (1 - omega) z + d2 ca
+            double s2 = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
+            ssq += s2;
+            wsq += wm * s2;
+            double u3last = 0.0;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const double u3 = u2[t] + omega * ((1.0 - omega) * z[t] + d2 * ca[t]);
+                unext[b + (long)t * Nx] = u3;
+                if (t == NT - 1) u3last = u3;
+                g[t] *= (1.0 - omega);
+            }
+            g[0] += up_prev_delta(p3, p2);
+            if (h == 0) {
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) acc[cc] = 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) acc[cc] += tr.P[(h * NT + t) * kNt + cc] * g[t];
+            if (h == 1) {
+                const long mc = (s0 + k) / 2;
+#pragma unroll
+                for (int cc = 0; cc < NT; ++cc) fc[mc * slab + m + (long)cc * Nx] = acc[cc];
+            }
+            p1 = u1[NT - 1];
+            p2 = u2[NT - 1];
+            p3 = u3last;
+        }
+    }
+    block_sum2(ssq, wsq, partial);
+}
+
+// The two coarsest levels of a V(1,1) cycle in one pass (a: second-coarsest
+// level with SA slabs, b: coarsest with SA/2 slabs), from the right-hand side
+// fa of level a alone:
+//   u  = omega A_a^{-1} fa                       (smoothing step from zero)
+//   fb = (P_t^T (x) I)(fa - L_a u) on slab pairs  ((1 - omega) fa + e_1 u_{s-1})
+//   ub = L_b^{-1} fb                              (exact, parallel in time)
+//   v  = u + (P_t (x) I) ub,  ua = v + omega A_a^{-1}(fa - L_a v)
+// Since A_a u = omega fa, the last step needs neither fa nor a solve:
+// fa - L_a v = (1 - omega) fa - A_a (P_t ub) + e_1 q with q the last time
+// row of the previous slab of v, so
+//   ua = (2 - omega) u + (1 - omega)(P_t (x) I) ub + omega q A_a^{-1} e_1.
+// A block holds 16 modes (one 128-byte line per time row) x G slab groups of
+// LA level-a and LA/2 level-b slabs per thread, kept in registers; the
+// coupling rows between groups, and the recurrence of the exact solve
+// (u_s = A^{-1} g_s + x_{s-1} A^{-1} e_1, x_s = a_s[N_t-1] + gamma x_{s-1}),
+// pass through LDS.  Only ua is written.
+template <int NT, bool SCHUR, int LAM>
+__global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_coarse_tail(int dim, const TimeMix* __restrict__ tma,
+                                                         const TimeMix* __restrict__ tmb,
+                                                         const double* __restrict__ mu1, int n, long Nx,
+                                                         const double* __restrict__ fa, double* __restrict__ ua,
+                                                         Transfer tr, double omega, int G, int LA,
+                                                         const int* guard) {
+    if (guard_off(guard)) return;
+    constexpr int MB = 16, LBM = LAM / 2;
+    __shared__ double xch[32][MB], xe_s[32][MB], gl_s[32][MB];
+    const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
+    const long m = (long)blockIdx.x * MB + ml;
+    const bool active = m < Nx;
+    const int LB = LA / 2;
+    const long slab = (long)NT * Nx;
+    const long sa0 = (long)g * LA;                 // first level-a slab of the group (even)
+    double u[LAM][NT], ub[LBM][NT];
+    double mu = 0.0, ulast = 0.0;
+    // (1) smoothing step from zero and restriction of its residual
+    if (active) {
+        mu = mode_shift(dim, mu1, n, m);
+#pragma unroll
+        for (int j = 0; j < LBM; ++j)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ub[j][t] = 0.0;
+#pragma unroll
+        for (int i = 0; i < LAM; ++i) {
+            if (i < LA) {
+                double f[NT], z[NT];
+                const long b = (sa0 + i) * slab + m;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) f[t] = fa[b + (long)t * Nx];
+                shifted_solve<NT, SCHUR>(*tma, mu, f, z);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    u[i][t] = omega * z[t];
+                    f[t] *= (1.0 - omega);
+                }
+                if (i > 0) f[0] += u[i - 1][NT - 1];
+                if (i == LA - 1) ulast = u[i][NT - 1];
+                const int h = i & 1;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) ub[i / 2][c] += tr.P[(h * NT + t) * kNt + c] * f[t];
+            }
+        }
+        xch[g][ml] = ulast;
+    }
+    __syncthreads();
+    if (active && g > 0) {
+        // coupling row of the group's first slab: the previous group's last
+        const double x0 = xch[g - 1][ml];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) ub[0][c] += tr.P[c] * x0;     // P^T row of t = 0, h = 0
+    }
+    // (2) exact solve on level b, parallel in time over the groups
+    double cb[NT], xe = 0.0, gl = 1.0;
+    if (active) {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(*tmb, mu, e1, cb);
+        const double gamma = cb[NT - 1];
+#pragma unroll
+        for (int j = 0; j < LBM; ++j) {
+            if (j < LB) {
+                double a[NT];
+                shifted_solve<NT, SCHUR>(*tmb, mu, ub[j], a);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) ub[j][t] = a[t];
+                xe = a[NT - 1] + gamma * xe;
+                gl *= gamma;
+            }
+        }
+    }
+    xe_s[g][ml] = xe;
+    gl_s[g][ml] = gl;
+    __syncthreads();
+    double vlast = 0.0;
+    if (active) {
+        double x = 0.0;
+        for (int h = 0; h < g; ++h) x = xe_s[h][ml] + gl_s[h][ml] * x;
+#pragma unroll
+        for (int j = 0; j < LBM; ++j) {
+            if (j < LB) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) ub[j][t] += x * cb[t];
+                x = ub[j][NT - 1];
+                if (j == LB - 1) {
+                    // prolonged coupling row of the group's last level-a slab (odd)
+                    vlast = ulast;
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) vlast += tr.P[(NT + NT - 1) * kNt + k] * ub[j][k];
+                }
+            }
+        }
+    }
+    __syncthreads();                               // xch is reused
+    if (active) xch[g][ml] = vlast;
+    __syncthreads();
+    if (!active) return;
+    // (3) prolongation and the post-smoothing step on level a (closed form)
+    double ca[NT];
+    {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(*tma, mu, e1, ca);
+    }
+    double q = g > 0 ? xch[g - 1][ml] : 0.0;
+#pragma unroll
+    for (int i = 0; i < LAM; ++i) {
+        if (i < LA) {
+            const int h = i & 1;
+            const long b = (sa0 + i) * slab + m;
+            double pu[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double w = 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k) w += tr.P[(h * NT + t) * kNt + k] * ub[i / 2][k];
+                pu[t] = w;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                ua[b + (long)t * Nx] = (2.0 - omega) * u[i][t] + (1.0 - omega) * pu[t] + omega * q * ca[t];
+            q = u[i][NT - 1] + pu[NT - 1];
+        }
+    }
+}
+
+// Descent on a coarse level with a zero initial guess and one pre-smoothing
+// step, for one spatial mode and a chain of `chain` slabs (chain even,
+// starting at an even slab): u' = omega A^{-1} f (into uout) and the
+// restriction of its residual, fc = (P_t^T (x) I)[f - L u']_{2k, 2k+1}, from one
+// read of f.  The last time row of the previous slab's u' is carried along the
+// chain; a chain after slab 0 first repeats the step for its preceding slab.
+template <int NT, bool SCHUR>
+__global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const double* __restrict__ ktmt,
+                                                  const double* __restrict__ mu1, int n, long Nx,
+                                                  const double* __restrict__ fl, double* __restrict__ uout,
+                                                  double* __restrict__ fc, Transfer tr, double omega, int chain,
+                                                  long total, const int* guard) {
+    if (guard_off(guard)) return;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const long q = idx / Nx, m = idx % Nx;
+    const double mu = mode_shift(dim, mu1, n, m);
+    const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
+    const long s0 = q * chain;
+    double prev = 0.0;
+    if (s0 > 0) {
+        const long b = (s0 - 1) * NT * Nx + m;
+        double g[NT], z[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g[t] = fl[b + (long)t * Nx];
+        shifted_solve<NT, SCHUR>(tm, sh, g, z);
+        prev = omega * z[NT - 1];
+    }
+    double fnx[NT], acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) fnx[t] = fl[s0 * NT * Nx + m + (long)t * Nx];
+#pragma unroll 1
+    for (int k = 0; k < chain; ++k) {
+        const int h = k & 1;
+        const long b = (s0 + k) * NT * Nx + m;
+        double g[NT], g2[NT], z[NT], up[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g[t] = fnx[t];
+        if (k + 1 < chain) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) fnx[t] = fl[b + NT * Nx + (long)t * Nx];
+        }
+        shifted_solve<NT, SCHUR>(tm, sh, g, z);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            up[t] = omega * z[t];
+            uout[b + (long)t * Nx] = up[t];
+        }
+        // residual of u' = omega A^{-1} f: f - A u' + e_1 u'_prev = (1 - omega) f + e_1 u'_prev
+#pragma unroll
+        for (int t = 0; t < NT; ++t) g2[t] = (1.0 - omega) * g[t];
+        g2[0] += prev;
+        if (h == 0) {
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] = 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[c] += tr.P[(h * NT + t) * kNt + c] * g2[t];
+        if (h == 1) {
+            const long mc = (s0 + k) / 2;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+        }
+        prev = up[NT - 1];
+    }
+}
+
+#define STH_NT_SWITCH(KER, GRID, ...)                                                      \
+    switch (Nt) {                                                                           \
+        case 2: hipLaunchKernelGGL(KER<2>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 3: hipLaunchKernelGGL(KER<3>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 4: hipLaunchKernelGGL(KER<4>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 5: hipLaunchKernelGGL(KER<5>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 6: hipLaunchKernelGGL(KER<6>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 7: hipLaunchKernelGGL(KER<7>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        case 8: hipLaunchKernelGGL(KER<8>, GRID, dim3(256), 0, st, __VA_ARGS__); break;     \
+        default: return hipErrorInvalidValue;                                               \
+    }
+
+template <int NT>
+static void eig_smooth_launch(dim3 grid, hipStream_t st, int dim, const TimeMix& tm, const double* ktmt,
+                              const double* mu1, int n, long Nx, const double* fh, const double* uin, double* uout,
+                              long total, double omega, bool zero_guess, const double* ec, const Transfer& tr,
+                              const int* guard) {
+    const int zg = zero_guess ? 1 : 0;
+    if (ec && tm.schur)
+        hipLaunchKernelGGL((k_eig_smooth<NT, true, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh, uin,
+                           uout, total, omega, zg, ec, tr, guard);
+    else if (ec)
+        hipLaunchKernelGGL((k_eig_smooth<NT, true, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
+                           uin, uout, total, omega, zg, ec, tr, guard);
+    else if (tm.schur)
+        hipLaunchKernelGGL((k_eig_smooth<NT, false, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
+                           uin, uout, total, omega, zg, ec, tr, guard);
+    else
+        hipLaunchKernelGGL((k_eig_smooth<NT, false, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, fh,
+                           uin, uout, total, omega, zg, ec, tr, guard);
+}
+
+hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                             const double* fh, const double* uin, double* uout, long S, double omega,
+                             bool zero_guess, const double* ec, const Transfer& tr, hipStream_t st,
+                             const int* guard) {
+    long Nx = eig_modes(dim, n), total = S * Nx;
+    if (total <= 0) return hipSuccess;
+    if (ec && zero_guess) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((total + 255) / 256));
+    switch (Nt) {
+#define STH_ES_CASE(NTV) \
+        case NTV: eig_smooth_launch<NTV>(grid, st, dim, tm, ktmt, mu1, n, Nx, fh, uin, uout, total, omega, zero_guess, ec, tr, guard); break;
+        STH_ES_CASE(2) STH_ES_CASE(3) STH_ES_CASE(4) STH_ES_CASE(5) STH_ES_CASE(6) STH_ES_CASE(7) STH_ES_CASE(8)
+#undef STH_ES_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
+                               const double* uh, double* rh, long S, hipStream_t st) {
+    long Nx = eig_modes(dim, n), total = S * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_NT_SWITCH(k_eig_residual, grid, ktmt, dim, mu1, n, Nx, fh, uh, rh, total)
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const double* ktmt, const double* mu1,
+                                     int n, const double* fh, const double* uh, double* fc, long Sc,
+                                     hipStream_t st) {
+    long Nx = eig_modes(dim, n), total = Sc * Nx;
+    if (total <= 0) return hipSuccess;
+    dim3 grid((unsigned)((total + 255) / 256));
+    STH_NT_SWITCH(k_eig_resid_restrict, grid, tr, ktmt, dim, mu1, n, Nx, fh, uh, fc, total)
+    return hipGetLastError();
+}
+#undef STH_NT_SWITCH
+hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
+                                double omega, long S, int chain, const double* vw, double* partial,
+                                long max_partial, double* out, double* out_host, hipStream_t st,
+                                const CycleFlag& flag) {
+    const long Nx = eig_modes(dim, n);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
+    if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_CE_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (tm.schur)                                                                                     \
+                hipLaunchKernelGGL((k_eig_cycle_end<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, \
+                                   Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);              \
+            else                                                                                              \
+                hipLaunchKernelGGL((k_eig_cycle_end<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,   \
+                                   n, Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);           \
+            break;
+        STH_CE_CASE(2) STH_CE_CASE(3) STH_CE_CASE(4) STH_CE_CASE(5) STH_CE_CASE(6) STH_CE_CASE(7) STH_CE_CASE(8)
+#undef STH_CE_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return launch_sum_partials(partial, (int)blocks, out, out_host, 2, nullptr, flag, st);
+}
+
+hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                  const double* fh, const double* upre, const double* ec, double* uend,
+                                  double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
+                                  const double* vw, double* partial, long max_partial, double* out,
+                                  double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag,
+                                  bool sums) {
+    const long Nx = eig_modes(dim, n);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
+    if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
+    if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_CC_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (tm.schur)                                                                                     \
+                hipLaunchKernelGGL((k_eig_cycle_close<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,  \
+                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
+                                   partial, guard);                                                           \
+            else                                                                                              \
+                hipLaunchKernelGGL((k_eig_cycle_close<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, \
+                                   n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
+                                   partial, guard);                                                           \
+            break;
+        STH_CC_CASE(2) STH_CC_CASE(3) STH_CC_CASE(4) STH_CC_CASE(5) STH_CC_CASE(6) STH_CC_CASE(7) STH_CC_CASE(8)
+#undef STH_CC_CASE
+        default: return hipErrorInvalidValue;
+    }
+    if (!sums) return hipGetLastError();
+    return launch_cycle_sums(dim, n, S, chain, partial, out, out_host, st, guard, flag);
+}
+
+hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial, double* out, double* out_host,
+                             hipStream_t st, const int* guard, const CycleFlag& flag) {
+    const long Nx = eig_modes(dim, n);
+    if (chain < 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    const long blocks = ((S / chain) * Nx + 255) / 256;
+    if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
+    return launch_sum_partials(partial, (int)blocks, out, out_host, 2, guard, flag, st);
+}
+// groups and level-a slabs per thread of the two-level tail pass, or false
+// when the shape does not fit it
+bool coarse_tail_shape(int Nt, long SA, int* G, int* LA) {
+    if (SA < 4 || SA % 4) return false;
+    const long g = SA / 2 < 32 ? SA / 2 : 32;
+    if (SA % (2 * g)) return false;
+    const long la = SA / g;
+    if (la > (Nt <= 5 ? 8 : 4)) return false;
+    *G = (int)g;
+    *LA = (int)la;
+    return true;
+}
+
+hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
+                                  const double* mu1, int n, const double* fa, double* ua,
+                                  const Transfer& tr, double omega, long SA, hipStream_t st, const int* guard) {
+    const long Nx = eig_modes(dim, n);
+    int G = 0, LA = 0;
+    if (!coarse_tail_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
+#define STH_CT_GO(NTV, SC, LAMV)                                                                              \
+    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV>), grid, block, 0, st, dim, tma_dev, tmb_dev, mu1, \
+                       n, Nx, fa, ua, tr, omega, G, LA, guard)
+#define STH_CT_LAM(NTV, SC)                                                                                  \
+    if (LA <= 2) STH_CT_GO(NTV, SC, 2);                                                                      \
+    else if (LA <= 4) STH_CT_GO(NTV, SC, 4);                                                                 \
+    else if (NTV <= 5) STH_CT_GO(NTV, SC, (NTV <= 5 ? 8 : 4));                                               \
+    else return hipErrorInvalidValue;
+#define STH_CT_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (schur) { STH_CT_LAM(NTV, true) } else { STH_CT_LAM(NTV, false) }                              \
+            break;
+    switch (Nt) {
+        STH_CT_CASE(2) STH_CT_CASE(3) STH_CT_CASE(4) STH_CT_CASE(5) STH_CT_CASE(6) STH_CT_CASE(7) STH_CT_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_CT_CASE
+#undef STH_CT_LAM
+#undef STH_CT_GO
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
+                           int chain, hipStream_t st, const int* guard) {
+    const long Nx = eig_modes(dim, n);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_DN_CASE(NTV)                                                                                  \
+        case NTV:                                                                                          \
+            if (tm.schur)                                                                                  \
+                hipLaunchKernelGGL((k_eig_down<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, \
+                                   fl, uout, fc, tr, omega, chain, total, guard);                          \
+            else                                                                                           \
+                hipLaunchKernelGGL((k_eig_down<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n,    \
+                                   Nx, fl, uout, fc, tr, omega, chain, total, guard);                      \
+            break;
+        STH_DN_CASE(2) STH_DN_CASE(3) STH_DN_CASE(4) STH_DN_CASE(5) STH_DN_CASE(6) STH_DN_CASE(7) STH_DN_CASE(8)
+#undef STH_DN_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sth

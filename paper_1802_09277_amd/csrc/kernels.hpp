@@ -91,8 +91,10 @@ hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* 
 // BF16x3 form of the same: out = M (In M^T) per image with the products
 // accumulated in FP32 from hi*hi + hi*lo + lo*hi bf16 MFMA products; pass
 // M = U^T (padded) for the forward and M = U for the inverse transform.
+// Image strides ldi, ldo (0: n^2) and the guard as in launch_xform2d.
 hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
-                                 long nimg, double alpha, hipStream_t st);
+                                 long nimg, double alpha, hipStream_t st, const int* guard = nullptr, long ldi = 0,
+                                 long ldo = 0);
 
 // Per slab and spatial mode (nx modes per time row; 0: n^d): out[:, m] = A_m^{-1} in[:, m], A_m^{-1} =
 // V (Z + mu_m I)^{-1} W (or the real Schur form of the level).  fwdsub:

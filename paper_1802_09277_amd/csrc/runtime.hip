@@ -29,6 +29,8 @@ using namespace sth;
 
 static thread_local std::string g_err;
 
+constexpr int kNormSlots = 12;          // squared norms on the device and their mapped host copies
+
 static int fail(int code, const std::string& msg) {
     g_err = msg;
     return code;
@@ -97,7 +99,8 @@ struct sth_handle {
     double* partial = nullptr;
     double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side; per norm slot
                                         // s (2 + 2s, 3 + 2s) eigenbasis residual and its weighted sum;
-                                        // slot 2 (6, 7): the initial pass of a speculative solve
+                                        // slot 2 (6, 7): the initial pass of a speculative solve;
+                                        // [8], [9]: residual and right-hand side of a mixed-precision solve
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
     double* hnorm_dev = nullptr;        // device address of hnorm
     // timing
@@ -160,7 +163,23 @@ struct sth_handle {
         // (fin_always: unguarded, as the cycle count or growth ends the solve)
         bool fin_enq = false, fin_always = false;
         hipEvent_t ev_a = nullptr, ev_b = nullptr;
+        // inner solve of a mixed-precision solve: zero initial guess, ||f||
+        // known, transforms in precision tprec, no exact B-spline norm (the
+        // lower bound decides), the result added into u
+        bool inner = false;
+        int tprec = STH_FP64;
     } sv;
+    // Mixed-precision solve (eigenbasis iteration with reduced-precision
+    // transforms): FP64 defect correction around inner eigenbasis solves
+    struct Mixed {
+        bool on = false;
+        const double* f = nullptr;
+        double* u = nullptr;
+        hipStream_t st = nullptr;
+        double rtol = 0.0, fn = 1.0, rn = 0.0, prev = 0.0;
+        int maxit = 0, it = 0, outer = 0, growth = 0;
+        int phase = 0;                  // 0 outer residual norm enqueued, 1 inner solve running, 2 done
+    } mx;
     // speculative cycles (eigenbasis, fused cycle close)
     bool speculate = true;
     const int* guard = nullptr;         // guard of the launches of the cycle being enqueued
@@ -359,12 +378,15 @@ static int restrict_lvl(sth_handle* h, int lvl, const double* r, double* rc, hip
     return STH_OK;
 }
 
-static int prolong_lvl(sth_handle* h, int lvl, const double* e, double* u, hipStream_t st) {
+// u += (P_t (x) I) e on the slab pairs of level lvl; row_len is the length
+// of a time row: h->Nx for B-spline coefficient vectors, h->Nxe for
+// eigenbasis vectors (their rows are padded)
+static int prolong_lvl(sth_handle* h, int lvl, const double* e, double* u, hipStream_t st, long row_len) {
     h->tlev = lvl;
     long Sc = h->lev_S[lvl + 1];
     double dof = (double)Sc * slab_len(h);
     Timed tm(h, STH_K_PROLONG, dof * 4.0 * h->Nt, dof * 40.0, st);
-    HIPCHK(launch_prolong(h->Nt, h->tr, e, u, Sc, h->Nx, st));
+    HIPCHK(launch_prolong(h->Nt, h->tr, e, u, Sc, row_len, st));
     return STH_OK;
 }
 
@@ -391,7 +413,7 @@ static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool z
     if ((rc = residual(h, lvl, f, u, h->buf1, 0, ns, 1.0, st))) return rc;
     if ((rc = restrict_lvl(h, lvl, h->buf1, h->lf[lvl + 1], st))) return rc;
     if ((rc = vcycle_lvl(h, lvl + 1, h->lf[lvl + 1], h->lu[lvl + 1], true, st))) return rc;
-    if ((rc = prolong_lvl(h, lvl, h->lu[lvl + 1], u, st))) return rc;
+    if ((rc = prolong_lvl(h, lvl, h->lu[lvl + 1], u, st, h->Nx))) return rc;
     for (int i = 0; i < h->nu_post; ++i) {
         if ((rc = smooth_step(h, lvl, f, u, false, st))) return rc;
     }
@@ -427,35 +449,56 @@ static int read_norm(sth_handle* h, const double* v, long len, hipStream_t st, d
 enum SpatialKind { FWD_U, INV_U, FWD_C, INV_C };
 
 // out = (A^T (x) ... (x) A^T) in (FWD) or (A (x) ... (x) A) in (INV) on every
-// time row of `rows` rows; A = U or C.  FP64.  in, out and tmp (a level-0
-// sized scratch vector, used by the axis-by-axis path) must be distinct.
+// time row of `rows` rows; A = U or C.  prec (sth_prec) is the arithmetic of
+// the transforms; epi 1 (inverse only) adds the result to out instead of
+// storing it.  in, out and tmp (a level-0 sized scratch vector, used by the
+// axis-by-axis path) must be distinct; the 3-D inverse with epi 1 also needs
+// a second scratch vector tmp2.
 static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, double* out, long rows, double* tmp,
-                         hipStream_t st, const int* guard = nullptr) {
+                         hipStream_t st, const int* guard = nullptr, int prec = STH_FP64, int epi = 0,
+                         double* tmp2 = nullptr) {
     const bool fwd = (kind == FWD_U || kind == FWD_C);
     const double* A = (kind == FWD_U || kind == INV_U) ? h->Tf : h->Cf;     // A padded
     const double* At = (kind == FWD_U || kind == INV_U) ? h->Ti : h->Ci;    // A^T padded
     const long n = h->n;
     double dof = (double)rows * h->Nx;
     h->tlev = 0;
+    if (epi != 0 && fwd) return fail(STH_EINVAL, "accumulating forward transform");
     if (h->dim == 2 && xform2d_supported(h->np)) {
-        Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, 16.0 * dof, st);
+        Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, (epi ? 24.0 : 16.0) * dof, st);
         // eigenbasis rows are eig_modes long: the forward transform writes,
         // and the inverse reads, images at that stride
         const long ld = h->Nxe;
-        HIPCHK(launch_xform2d(0, fwd ? 0 : 1, 0, in, out, A, h->n, h->np, rows, 1.0, st, guard, fwd ? 0 : ld,
-                              fwd ? ld : 0));
+        if (prec == STH_BF16X3)
+            // out = M (In M^T) with M = A^T (forward) or A (inverse)
+            HIPCHK(launch_xform2d_bf16x3(epi, in, out, fwd ? At : A, h->n, h->np, rows, 1.0, st, guard,
+                                         fwd ? 0 : ld, fwd ? ld : 0));
+        else
+            HIPCHK(launch_xform2d(prec, fwd ? 0 : 1, epi, in, out, A, h->n, h->np, rows, 1.0, st, guard,
+                                  fwd ? 0 : ld, fwd ? ld : 0));
         return STH_OK;
     }
-    // axis by axis: x (contiguous), then y (and z), ping-ponging tmp/out
+    // axis by axis, ping-ponging between the buffers; with accumulation the
+    // contiguous axis goes last, so that its epilogue adds into out
     const double* T = fwd ? A : At;
     int rc;
     if (h->dim == 2) {
-        if ((rc = xform_x(h, STH_FP64, 0, in, tmp, T, rows * n, 1.0, st))) return rc;
-        if ((rc = xform_s(h, STH_FP64, tmp, out, T, rows, n, st))) return rc;
+        if (epi == 0) {
+            if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n, 1.0, st))) return rc;
+            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st))) return rc;
+        } else {
+            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st))) return rc;
+            if ((rc = xform_x(h, prec, epi, tmp, out, T, rows * n, 1.0, st))) return rc;
+        }
+    } else if (epi == 0) {
+        if ((rc = xform_x(h, prec, 0, in, out, T, rows * n * n, 1.0, st))) return rc;   // x
+        if ((rc = xform_s(h, prec, out, tmp, T, rows * n, n, st))) return rc;            // y
+        if ((rc = xform_s(h, prec, tmp, out, T, rows, n * n, st))) return rc;            // z
     } else {
-        if ((rc = xform_x(h, STH_FP64, 0, in, out, T, rows * n * n, 1.0, st))) return rc;   // x
-        if ((rc = xform_s(h, STH_FP64, out, tmp, T, rows * n, n, st))) return rc;            // y
-        if ((rc = xform_s(h, STH_FP64, tmp, out, T, rows, n * n, st))) return rc;            // z
+        if (!tmp2) return fail(STH_EINVAL, "accumulating 3-D transform without a second scratch vector");
+        if ((rc = xform_s(h, prec, in, tmp, T, rows, n * n, st))) return rc;             // z
+        if ((rc = xform_s(h, prec, tmp, tmp2, T, rows * n, n, st))) return rc;           // y
+        if ((rc = xform_x(h, prec, epi, tmp2, out, T, rows * n * n, 1.0, st))) return rc;   // x, added
     }
     return STH_OK;
 }
@@ -551,7 +594,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         h->pending_ec = ec;
         return STH_OK;
     }
-    if (h->nu_post == 0) return prolong_lvl(h, lvl, ec, eig_u(h, lvl, h->ecur[lvl]), st);
+    if (h->nu_post == 0) return prolong_lvl(h, lvl, ec, eig_u(h, lvl, h->ecur[lvl]), st, h->Nxe);
     for (int i = 0; i < h->nu_post; ++i)
         if ((rc = eig_smooth(h, lvl, false, st, i == 0 ? ec : nullptr))) return rc;
     return STH_OK;
@@ -758,7 +801,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
         S /= 2;
         total += vecsl * sizeof(double) * (size_t)S * slab;
     }
-    total += sizeof(double) * (kNormBlocks + 8 + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
+    total += sizeof(double) * (kNormBlocks + kNormSlots + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
     *bytes = total;
     return STH_OK;
 }
@@ -885,7 +928,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!dalloc(&h->Tf, (size_t)np * np) || !dalloc(&h->Ti, (size_t)np * np) || !dalloc(&h->mu1, n) ||
         !dalloc(&h->M1b, (size_t)n * B) || !dalloc(&h->K1b, (size_t)n * B) ||
         !dalloc(&h->buf0, (size_t)q.n_slabs * slab) || !dalloc(&h->buf1, (size_t)q.n_slabs * slab) ||
-        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, 8) ||
+        !dalloc(&h->partial, kNormBlocks) || !dalloc(&h->dnorm, kNormSlots) ||
         !dalloc(&h->dktmt, (size_t)h->L * 2 * kNt * kNt))
         return cleanup(STH_ENOMEM, "device allocation failed");
     std::vector<double> ktmt((size_t)h->L * 2 * kNt * kNt);
@@ -958,7 +1001,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         }
     }
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
-    if (hipHostMalloc((void**)&h->hnorm, 8 * sizeof(double), mapped) != hipSuccess ||
+    if (hipHostMalloc((void**)&h->hnorm, kNormSlots * sizeof(double), mapped) != hipSuccess ||
         hipHostMalloc((void**)&h->hflag, 4 * sizeof(int), mapped) != hipSuccess ||
         hipHostMalloc((void**)&h->hseq, 2 * sizeof(int), mapped) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
@@ -1176,7 +1219,10 @@ namespace sth {
 static sth_handle::Snap take_snap(const sth_handle* h);
 static int spec_enqueue(sth_handle* h);
 
-int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxit, hipStream_t st) {
+// inner (not null): an inner solve of a mixed-precision solve, with ||f|| =
+// *inner_fn known on the host and transforms in precision tprec
+static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rtol, int maxit, hipStream_t st,
+                            const double* inner_fn = nullptr, int tprec = STH_FP64) {
     if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
     auto& v = h->sv;
     v = sth_handle::SolveState{};
@@ -1185,6 +1231,8 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
     v.st = st;
     v.rtol = rtol;
     v.maxit = maxit;
+    v.inner = inner_fn != nullptr;
+    v.tprec = tprec;
     // cycles enqueued ahead of their predecessor's norm (eigenbasis with the
     // fused cycle close; not while kernels are timed one by one)
     v.spec = h->basis == 1 && h->fuse_close && h->speculate && !h->timing;
@@ -1197,25 +1245,39 @@ int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxi
     h->presmoothed = false;
     h->tlev = 0;
     const long len = h->lev_S[0] * slab_len(h);
-    {
-        Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
-        HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + 1, st));
+    if (v.inner) {
+        h->hnorm[1] = (*inner_fn) * (*inner_fn);     // read by the host only
+    } else {
+        {
+            Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
+            HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + 1, st));
+        }
+        HIPCHK(hipMemcpyAsync(h->hnorm + 1, h->dnorm + 1, sizeof(double), hipMemcpyDeviceToHost, st));
     }
-    HIPCHK(hipMemcpyAsync(h->hnorm + 1, h->dnorm + 1, sizeof(double), hipMemcpyDeviceToHost, st));
     int rc;
     if (h->basis == 1) {
         // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
         const long rows = h->lev_S[0] * h->Nt;
         h->ecur[0] = 0;
-        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st))) return rc;
-        if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) return rc;
+        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st, nullptr, v.tprec))) return rc;
+        if (v.inner) {
+            h->tlev = 0;
+            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st));     // zero initial guess
+        } else if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) {
+            return rc;
+        }
         // (with graph replay, whose captured cycles have fixed guards, the
         // first cycle waits for the initial norms instead)
         if (!v.spec || maxit < 1 || h->use_graph) return eig_residual_cheap(h, st);
         // speculation from the start: the threshold on the device, the
         // initial pass sets the flag that guards the first cycle, and the
         // first cycles go behind it without waiting for the norms
-        HIPCHK(launch_spec_threshold(h->dthr, h->dnorm + 1, rtol, st));
+        if (v.inner) {
+            const double t = rtol * (*inner_fn);
+            HIPCHK(launch_set_flag(h->dgo + 3, 0, st, h->dthr, t * t, t));
+        } else {
+            HIPCHK(launch_spec_threshold(h->dthr, h->dnorm + 1, rtol, st));
+        }
         h->first_flag = true;
         rc = eig_residual_cheap(h, st);
         h->first_flag = false;
@@ -1306,8 +1368,9 @@ static int solve_finish(sth_handle* h, bool* more) {
     v.phase = 2;
     h->wait_ev = nullptr;
     h->wait_slot = -1;
-    // u = (I (x) U_x) u^
-    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st);
+    // u = (I (x) U_x) u^ (an inner solve adds it to u)
+    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st, nullptr,
+                         v.tprec, v.inner ? 1 : 0, h->buf1);
 }
 
 // Lower bound of the B-spline residual norm of the cycle whose sums are in
@@ -1362,6 +1425,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
         v.rn = eig_lower_bound(h, 0);
         if (!std::isfinite(r) || v.maxit == 0) return solve_finish(h, more);
         if (!(v.rn > v.rtol * v.fn)) {
+            if (v.inner) return solve_finish(h, more);      // the outer loop takes the exact norm
             v.phase = 3;
             int rc = eig_exact_norm(h, v.st);
             h->wait_ev = nullptr;
@@ -1391,6 +1455,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
                 v.rn = r;
                 return solve_finish(h, more);
             }
+            if (v.inner) return solve_finish(h, more);
             return spec_exact_norm(h);
         }
         // cycle a ran: go on as after any completed cycle
@@ -1461,6 +1526,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
         v.rn = r;
         return solve_finish(h, more);
     }
+    if (v.inner) return solve_finish(h, more);
     return spec_exact_norm(h);
 }
 
@@ -1480,7 +1546,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
 // once; otherwise the exact ||r|| is evaluated and decides, as it would in
 // every cycle, so the cycle count is that of the plain stopping test.
 // Growth is watched on ||r^||.
-int solve_continue(sth_handle* h, bool* more) {
+static int solve_continue_impl(sth_handle* h, bool* more) {
     auto& v = h->sv;
     *more = false;
     if (v.phase == 2) return STH_OK;
@@ -1514,6 +1580,7 @@ int solve_continue(sth_handle* h, bool* more) {
             *more = true;
             if (std::isfinite(r) && v.rn > v.rtol * v.fn && v.it < v.maxit && v.growth < 3)
                 return enqueue_iteration(h);
+            if (v.inner) return solve_finish(h, more);
             v.phase = 3;
             return eig_exact_norm(h, v.st);
         }
@@ -1530,8 +1597,130 @@ int solve_continue(sth_handle* h, bool* more) {
     return STH_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Mixed precision (eigenbasis iteration, transform_prec FP32 or BF16x3): the
+// spatial transforms run in reduced precision, so f^ and the mapping back
+// carry their rounding; an FP64 defect correction wins the accuracy back.
+// Each outer step forms the B-spline residual r = f - L_h u in FP64 (the
+// residual kernel of the nodal iteration) and its exact norm, which is the
+// stopping test of Section 4.4; an inner eigenbasis solve then reduces r by a
+// factor eta (set by the transform precision, or just what the tolerance
+// needs) from a zero guess, and its result is added to u by the
+// reduced-precision inverse transform.  An inverse accurate to 1e-4 keeps the
+// multigrid's iteration count (Section 4.4), so the inner cycles are those of
+// the FP64 solve split over two or three outer steps.
+// ---------------------------------------------------------------------------
+static double mixed_inner_eta(int prec) { return prec == STH_BF16X3 ? 1e-4 : 1e-6; }
+
+static int mixed_residual(sth_handle* h) {
+    auto& m = h->mx;
+    const long S = h->lev_S[0];
+    const long len = S * slab_len(h);
+    int rc = residual(h, 0, m.f, m.u, h->buf1, 0, S, 1.0, m.st);
+    if (rc) return rc;
+    h->tlev = 0;
+    {
+        Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, m.st);
+        HIPCHK(launch_norm2(h->buf1, len, h->partial, h->dnorm + 8, m.st));
+    }
+    HIPCHK(hipMemcpyAsync(h->hnorm + 8, h->dnorm + 8, sizeof(double), hipMemcpyDeviceToHost, m.st));
+    h->wait_ev = nullptr;                 // the caller waits for the stream
+    h->wait_slot = -1;
+    m.phase = 0;
+    return STH_OK;
+}
+
+static int mixed_begin(sth_handle* h, const double* f, double* u, double rtol, int maxit, hipStream_t st) {
+    if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
+    auto& m = h->mx;
+    m = sth_handle::Mixed{};
+    m.on = true;
+    m.f = f;
+    m.u = u;
+    m.st = st;
+    m.rtol = rtol;
+    m.maxit = maxit;
+    h->sv = sth_handle::SolveState{};
+    h->sv.st = st;
+    h->graph_launched = false;
+    h->presmoothed = false;
+    const long len = h->lev_S[0] * slab_len(h);
+    h->tlev = 0;
+    {
+        Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
+        HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + 9, st));
+    }
+    HIPCHK(hipMemcpyAsync(h->hnorm + 9, h->dnorm + 9, sizeof(double), hipMemcpyDeviceToHost, st));
+    return mixed_residual(h);
+}
+
+static int mixed_continue(sth_handle* h, bool* more) {
+    auto& m = h->mx;
+    *more = false;
+    if (m.phase == 2) return STH_OK;
+    if (m.phase == 1) {
+        bool inner_more = false;
+        int rc = solve_continue_impl(h, &inner_more);
+        if (rc || inner_more) {
+            *more = inner_more;
+            return rc;
+        }
+        // the inner result is being added to u: the next outer residual
+        m.it += h->sv.it;
+        ++m.outer;
+        *more = true;
+        return mixed_residual(h);
+    }
+    // outer residual norm of the current iterate
+    if (m.outer == 0) {
+        m.fn = std::sqrt(h->hnorm[9]);
+        if (m.fn == 0.0) m.fn = 1.0;
+    }
+    const double rn = std::sqrt(h->hnorm[8]);
+    if (m.outer > 0 && std::isfinite(rn)) m.growth = (rn >= m.prev) ? m.growth + 1 : 0;
+    m.rn = rn;
+    m.prev = rn;
+    if (!std::isfinite(rn) || !(rn > m.rtol * m.fn) || m.it >= m.maxit || m.growth >= 3) {
+        m.phase = 2;
+        return STH_OK;
+    }
+    // inner solve of L e = r to eta ||r|| (at least what the tolerance
+    // needs, with a margin), added into u
+    const double eta = std::max(mixed_inner_eta(h->prec), 0.5 * m.rtol * m.fn / rn);
+    int rc = solve_begin_impl(h, h->buf1, m.u, eta, m.maxit - m.it, m.st, &rn, h->prec);
+    if (rc) return rc;
+    m.phase = 1;
+    *more = true;
+    return STH_OK;
+}
+
+static int mixed_result(sth_handle* h, int* iters, double* relres) {
+    const auto& m = h->mx;
+    if (iters) *iters = m.it;
+    if (relres) *relres = m.rn / m.fn;
+    if (!std::isfinite(m.rn)) return fail(STH_ENOCONV, "residual is not finite");
+    if (m.growth >= 3) return fail(STH_ENOCONV, "residual did not decrease over 3 consecutive outer steps");
+    if (m.rn > m.rtol * m.fn) return fail(STH_ENOCONV, "maxit reached");
+    return STH_OK;
+}
+
+// whether sth_solve on this handle takes the mixed-precision route
+static bool mixed_route(const sth_handle* h) { return h->basis == 1 && h->prec != STH_FP64; }
+
+int solve_begin(sth_handle* h, const double* f, double* u, double rtol, int maxit, hipStream_t st) {
+    if (h) h->mx.on = false;
+    if (h && mixed_route(h)) return mixed_begin(h, f, u, rtol, maxit, st);
+    return solve_begin_impl(h, f, u, rtol, maxit, st);
+}
+
+int solve_continue(sth_handle* h, bool* more) {
+    if (h->mx.on) return mixed_continue(h, more);
+    return solve_continue_impl(h, more);
+}
+
 // Outcome of a finished solve: STH_OK when the tolerance was met.
 int solve_result(sth_handle* h, int* iters, double* relres) {
+    if (h->mx.on) return mixed_result(h, iters, relres);
     const auto& v = h->sv;
     if (iters) *iters = v.it;
     if (relres) *relres = v.rn / v.fn;
@@ -1580,9 +1769,10 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
               void* stream) {
     if (!h || !f || !u || !(rtol >= 0) || maxit < 0) return fail(STH_EINVAL, "bad argument");
     hipStream_t st = (hipStream_t)stream;
+    // completion marks instead of per-cycle events (also for the inner
+    // solves of a mixed-precision solve, which start inside the loop)
     h->want_poll = true;
     int rc = solve_begin(h, f, u, rtol, maxit, st);
-    h->want_poll = false;
     bool more = true;
     while (rc == STH_OK && more) {
         if (h->wait_slot >= 0) rc = wait_mark(h, st);
@@ -1590,6 +1780,7 @@ int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
         else HIPCHK(hipStreamSynchronize(st));
         if (rc == STH_OK) rc = solve_continue(h, &more);
     }
+    h->want_poll = false;
     h->poll_seq = false;
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(st));
@@ -1608,11 +1799,13 @@ static int precondition(sth_handle* h, const double* v, double* z, hipStream_t s
     // the same cycle in the spatial eigenbasis: z = (I (x) U) V((I (x) U^T) v)
     const long rows = h->lev_S[0] * h->Nt;
     int rc;
-    if ((rc = spatial_apply(h, FWD_U, v, h->e0, rows, h->buf0, st))) return rc;
+    // (transforms in the handle's precision: FGMRES is flexible, so a
+    // reduced-precision preconditioner leaves its residual test exact)
+    if ((rc = spatial_apply(h, FWD_U, v, h->e0, rows, h->buf0, st, nullptr, h->prec))) return rc;
     h->ecur[0] = 0;
     h->presmoothed = false;
     if ((rc = eig_vcycle(h, 0, true, st))) return rc;
-    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), z, rows, h->buf0, st);
+    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), z, rows, h->buf0, st, nullptr, h->prec);
 }
 
 static int krylov_workspace(sth_handle* h, int m) {
@@ -1742,7 +1935,7 @@ int sth_restrict(sth_handle* h, int level, const double* r, double* rc, void* st
 
 int sth_prolong_add(sth_handle* h, int level, const double* ec, double* u, void* stream) {
     if (!h || !ec || !u || level < 0 || level + 1 >= h->L) return fail(STH_EINVAL, "bad argument");
-    return prolong_lvl(h, level, ec, u, (hipStream_t)stream);
+    return prolong_lvl(h, level, ec, u, (hipStream_t)stream, h->Nx);
 }
 
 int sth_norm(sth_handle* h, const double* v, double* out, void* stream) {

@@ -7,7 +7,7 @@ Checked against oracle values sampled at 4000 seeded indices
 (tests/golden/c2_direct_samples.txt, written by make_fullsize_samples.py
 from the oracle's SuperLU forward substitution):
   * load vector: 1e-13 relative to the largest sampled entry;
-  * FP64 solve to relative residual 1e-12: 1e-9 relative;
+  * FP64 solve to relative residual 1e-12: 1e-10 relative;
   * solves to relative residual 1e-8 (FP64, FP32 and BF16x3 transforms):
     1e-6 relative (the accuracy a 1e-8 residual allows here), and the
     relative residual itself.
@@ -65,7 +65,7 @@ def test_fullsize_fp64_tight():
     assert abs(nf - meta["norm_f"]) <= 1e-12 * meta["norm_f"]
     err = np.abs(u[idx] - us).max() / np.abs(us).max()
     print(f"  sampled max rel error vs direct {err:.2e}")
-    assert rr <= 1e-12 and err <= 1e-9
+    assert rr <= 1e-12 and err <= 1e-10
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -82,7 +82,7 @@ def test_fullsize_eigenbasis():
     it, rr, f, u, nf = _run("fp64", 1e-12, basis="eigen")
     err = np.abs(u[idx] - us).max() / np.abs(us).max()
     print(f"  eigenbasis: {it} cycles, relres {rr:.2e}, sampled max rel error vs direct {err:.2e}")
-    assert rr <= 1e-12 and err <= 1e-9
+    assert rr <= 1e-12 and err <= 1e-10
 
 
 # ---------------------------------------------------------------------------
@@ -92,42 +92,70 @@ def test_fullsize_eigenbasis():
 # element, 8 random modes seed 4; 201,326,592 unknowns), in the bench launch
 # configuration.  The oracle cannot solve these directly; it supplies the
 # load vector on three slabs (tests/golden/c3_rhs_samples.txt,
-# c4_rhs_samples.txt, written by make_fullsize_samples.py) and its slab
-# operators, eq. structureAn, built from its 1-D matrices (pinned to the
-# quadrature-assembled slab matrix by the Kronecker identity tests).  On the
-# first, a middle and the last slab the GPU solution must satisfy the
-# oracle's equations r_n = f_n - A_n u_n + B_n u_{n-1} to the solve tolerance.
+# c4_rhs_samples.txt, written by make_fullsize_samples.py) and its 1-D
+# matrices, from which the residual of eq. equ_linear_system,
+# r_n = f_n - (K_t (x) M_x + M_t (x) K_x) u_n + (N_t (x) M_x) u_{n-1}
+# (eq. structureAn; pinned to the quadrature-assembled slab matrix by the
+# Kronecker identity tests), is formed on every slab of the GPU solution on
+# the host (PyTorch CPU ops, banded 1-D factors).  Its norm must meet the
+# solve tolerance and agree with the relative residual the library reports.
 # Each reduced-precision result is reported against the FP64 one.
 # ---------------------------------------------------------------------------
 from oracle.spacetime import Problem as OProblem, time_matrices, space_matrices_1d   # noqa: E402
 
 
-def _along(mat, v, axis):
-    return np.moveaxis(np.tensordot(mat, v, axes=([1], [axis])), 0, axis)
+def _band(mat, v, axis, p):
+    """mat (banded, half-bandwidth p) applied along `axis` of the CPU tensor v."""
+    n = mat.shape[0]
+    out = torch.zeros_like(v)
+    for k in range(-p, p + 1):
+        d = torch.from_numpy(np.ascontiguousarray(np.diagonal(mat, k)))
+        shape = [1] * v.dim()
+        shape[axis] = n - abs(k)
+        lo_o, lo_i = max(0, -k), max(0, k)
+        out.narrow(axis, lo_o, n - abs(k)).add_(v.narrow(axis, lo_i, n - abs(k)) * d.reshape(shape))
+    return out
 
 
-def _oracle_slab_residual(prob, f_s, u_s, u_prev):
+def _oracle_residual(prob, f, u):
+    """r = f - L_h u on every slab with the oracle's 1-D and temporal matrices;
+    returns the per-slab squared norms."""
     Kt, Mt = time_matrices(0.0, prob.tau, prob.n_elem_t, prob.degree, prob.sigma)
     M1, K1 = space_matrices_1d(prob.n_elem, prob.degree)
-    shape = (prob.N_t,) + (prob.n,) * prob.dim
-    u = u_s.reshape(shape)
-    axes = range(1, 1 + prob.dim)
-    Mu = u
-    for a in axes:
-        Mu = _along(M1, Mu, a)
-    Ku = np.zeros_like(u)
-    for a in axes:
-        w = u
-        for b in axes:
-            w = _along(K1 if b == a else M1, w, b)
-        Ku += w
-    r = f_s.reshape(shape) - _along(Kt, Mu, 0) - _along(Mt, Ku, 0)
-    if u_prev is not None:
-        up = u_prev.reshape(shape)[-1]                 # B_n = (e_1 e_{N_t}^T) (x) M_x
-        for a in range(prob.dim):
-            up = _along(M1, up, a)
-        r[0] += up
-    return r.ravel()
+    p = prob.degree
+    assert np.abs(np.triu(M1, p + 1)).max() == 0 and np.abs(np.triu(K1, p + 1)).max() == 0
+    shape = (prob.n_slabs, prob.N_t) + (prob.n,) * prob.dim
+    with torch.no_grad():
+        uu = torch.from_numpy(u).view(shape)
+        if prob.dim == 2:                                   # axes: 2 = y, 3 = x
+            A = _band(M1, uu, 2, p)
+            Mu = _band(M1, A, 3, p)
+            Ku = _band(K1, A, 3, p)
+            del A
+            B = _band(K1, uu, 2, p)
+            Ku += _band(M1, B, 3, p)
+            del B
+        else:                                               # axes: 2 = z, 3 = y, 4 = x
+            X = _band(M1, uu, 4, p)
+            KX = _band(K1, uu, 4, p)
+            Y = _band(M1, X, 3, p)
+            YK = _band(K1, X, 3, p)
+            del X
+            YK += _band(M1, KX, 3, p)
+            del KX
+            Mu = _band(M1, Y, 2, p)
+            Ku = _band(K1, Y, 2, p)
+            del Y
+            Ku += _band(M1, YK, 2, p)
+            del YK
+        r = torch.from_numpy(f).view(shape).clone()
+        Ktt, Mtt = torch.from_numpy(Kt), torch.from_numpy(Mt)
+        for t in range(prob.N_t):
+            for t2 in range(prob.N_t):
+                r[:, t].sub_(Mu[:, t2], alpha=float(Ktt[t, t2])).sub_(Ku[:, t2], alpha=float(Mtt[t, t2]))
+        r[1:, 0] += Mu[:-1, prob.N_t - 1]                  # B_n u_{n-1} = (e_1 e_{N_t}^T (x) M_x) u_{n-1}
+        del Mu, Ku
+        return (r * r).flatten(1).sum(1).numpy()
 
 
 def _rhs_samples(name):
@@ -157,31 +185,31 @@ def _solve_large(cfg, basis, prec, rtol):
     return out
 
 
-@pytest.mark.parametrize("name,variants", [
-    ("C3", [("eigen", "fp64"), ("nodal", "fp64"), ("nodal", "fp32"), ("nodal", "bf16x3")]),
-    ("C4", [("eigen", "fp64"), ("nodal", "fp64"), ("nodal", "fp32"), ("nodal", "bf16x3")]),
+_FP64_RESULT = {}
+
+
+@pytest.mark.parametrize("name,basis,prec", [
+    ("C3", "eigen", "fp64"), ("C3", "nodal", "fp64"), ("C3", "nodal", "fp32"), ("C3", "nodal", "bf16x3"),
+    ("C4", "eigen", "fp64"), ("C4", "nodal", "fp64"), ("C4", "nodal", "fp32"), ("C4", "nodal", "bf16x3"),
 ])
-def test_fullsize_large_workloads(name, variants):
+def test_fullsize_large_workloads(name, basis, prec):
     cfg = W.CONFIGS[name]
     prob = OProblem(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta)
     idx, fs = _rhs_samples(name)
     rtol = 1e-8
-    u64 = None
-    for basis, prec in variants:
-        print(f"[gpu-fullsize] {name} basis={basis} prec={prec} rtol={rtol}", flush=True)
-        it, rr, f, u, nf = _solve_large(cfg, basis, prec, rtol)
-        assert np.abs(f[idx] - fs).max() <= 1e-13 * np.abs(fs).max()
-        worst = 0.0
-        L = prob.slab_size
-        for s_ in (0, prob.n_slabs // 2, prob.n_slabs - 1):
-            r = _oracle_slab_residual(prob, f[s_ * L:(s_ + 1) * L], u[s_ * L:(s_ + 1) * L],
-                                      u[(s_ - 1) * L:s_ * L] if s_ > 0 else None)
-            worst = max(worst, np.linalg.norm(r) / nf)
-        msg = f"  {name} {basis}/{prec}: {it} cycles, relres {rr:.2e}, oracle slab residual / |f| {worst:.2e}"
-        if u64 is None:
-            u64 = u
-        else:
-            msg += f", |u-u_fp64|/|u_fp64| {np.linalg.norm(u - u64) / np.linalg.norm(u64):.2e}"
-        print(msg, flush=True)
-        assert rr <= rtol and worst <= 1.05 * rtol
-        del f, u
+    print(f"[gpu-fullsize] {name} basis={basis} prec={prec} rtol={rtol}", flush=True)
+    it, rr, f, u, nf = _solve_large(cfg, basis, prec, rtol)
+    assert np.abs(f[idx] - fs).max() <= 1e-13 * np.abs(fs).max()
+    r2 = _oracle_residual(prob, f, u)
+    rel = float(np.sqrt(r2.sum())) / nf
+    worst = float(np.sqrt(r2.max())) / nf
+    msg = (f"  {name} {basis}/{prec}: {it} cycles, relres {rr:.3e}, oracle residual over all "
+           f"{prob.n_slabs} slabs / |f| {rel:.3e} (worst slab {worst:.2e})")
+    if prec == "fp64" and basis == "eigen":
+        _FP64_RESULT[name] = u
+    elif name in _FP64_RESULT:
+        u64 = _FP64_RESULT[name]
+        msg += f", |u-u_fp64|/|u_fp64| {np.linalg.norm(u - u64) / np.linalg.norm(u64):.2e}"
+    print(msg, flush=True)
+    assert rr <= rtol and rel <= 1.05 * rtol
+    assert abs(rel - rr) <= 0.05 * rr

@@ -9,6 +9,7 @@ The shapes span several residual and MFMA tiles with ragged tails, an odd
 coarsest level (forward substitution), N_t from 3 to 6 and d = 2, 3.
 """
 import functools
+import os
 import sys
 
 import numpy as np
@@ -33,6 +34,12 @@ SHAPES = {
     "3d_8slabs": dict(dim=3, n_elem=7, degree=2, n_slabs=8, n_elem_t=2, coarse_slabs=2),
     # n = 98 > 96: the two-kernel (per-axis) transform path of large images
     "2d_n98_axiswise": dict(dim=2, n_elem=98, degree=2, n_slabs=2, n_elem_t=2, coarse_slabs=1),
+    # five levels (32 -> 16 -> 8 -> 4 -> 2 slabs; 100 modes padded to 112 per
+    # time row): the coarse-level descent and post-smoothing passes of levels
+    # 1 and 2 and the two-level coarse pass, as the large workloads run them
+    "2d_5lev": dict(dim=2, n_elem=10, degree=2, n_slabs=32, n_elem_t=1, coarse_slabs=2),
+    # five levels in 3-D down to a single slab (16 -> 8 -> 4 -> 2 -> 1)
+    "3d_5lev": dict(dim=3, n_elem=6, degree=2, n_slabs=16, n_elem_t=2, coarse_slabs=1),
 }
 
 
@@ -414,3 +421,74 @@ def test_speculative_cycles_match_plain_loop(name):
     s.speculate(True)
     assert outs[0][:3] == outs[1][:3] and outs[0][0] > k and outs[0][2] == 0
     assert np.array_equal(outs[0][3], outs[1][3])
+
+
+# ---------------------------------------------------------------------------
+# Cycle shapes other than V(1,1) in the eigenbasis iteration (the fused
+# passes are V(1,1) only; these run the general level loop, including the
+# prolongation alone when there is no post-smoothing step) on a padded
+# four-level shape, cycle by cycle against the oracle's multigrid with the
+# same nu1, nu2.
+# ---------------------------------------------------------------------------
+CYCLE_SHAPE = dict(dim=2, n_elem=6, degree=2, n_slabs=8, n_elem_t=2)   # 36 modes padded to 48
+
+
+@pytest.mark.parametrize("nu", [(1, 0), (0, 1), (2, 1), (1, 2)])
+@pytest.mark.parametrize("basis", ["nodal", "eigen"])
+def test_cycle_shapes_match_oracle(nu, basis):
+    import paper_1802_09277_amd as sth
+    print(f"[gpu-parity] cycle shape V{nu} basis={basis} {CYCLE_SHAPE}", flush=True)
+    prob = OProblem(**CYCLE_SHAPE)
+    mg = MultigridOracle(prob, nu1=nu[0], nu2=nu[1], coarse_slabs=1)
+    s = sth.Solver(**CYCLE_SHAPE, nu_pre=nu[0], nu_post=nu[1], coarse_slabs=1, basis=basis)
+    assert s.num_levels == len(mg.levels) == 4
+    f = assemble_rhs(prob, W.random_modes(9, prob.dim))
+    fd = dev(f)
+    uo = np.zeros_like(f)
+    for k in range(1, 4):
+        uo = mg.vcycle(f, uo)
+        u = s.new_vector()
+        it, rr, code = s.solve(fd, u, rtol=0.0, maxit=k, check=False)
+        assert (it, code) == (k, -6), last_error()
+        assert rel_max(host(u), uo) <= 1e-10, k
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# A five-level 2-D shape wide enough for the widest slab chains of the
+# finest-level cycle pass (91 x 91 elements, p = 2, 64 slabs; the bench
+# workloads run the same chains): the eigenbasis iterates after 1, 2 and 3
+# cycles and a solve to 1e-12 against the oracle's multigrid iterates and
+# direct solution, sampled at 3000 indices (tests/golden/deep_cycle_samples.txt,
+# written by make_deep_cycle_samples.py from the oracle alone).
+# ---------------------------------------------------------------------------
+DEEP = os.path.join(os.path.dirname(__file__), "golden", "deep_cycle_samples.txt")
+DEEP_SHAPE = dict(dim=2, n_elem=91, degree=2, n_slabs=64, n_elem_t=1)
+
+
+@pytest.mark.parametrize("temporal", ["eigen", "schur"])
+def test_deep_wide_shape_cycles(temporal):
+    import paper_1802_09277_amd as sth
+    if not os.path.exists(DEEP):
+        pytest.skip("golden samples not generated")
+    print(f"[gpu-parity] deep wide shape temporal={temporal} {DEEP_SHAPE}", flush=True)
+    data = np.loadtxt(DEEP)
+    idx = data[:, 0].astype(np.int64)
+    s = sth.Solver(**DEEP_SHAPE, coarse_slabs=4, basis="eigen", temporal=temporal)
+    assert s.num_levels == 5
+    f = s.new_vector()
+    s.load_rhs(W.random_modes(3, 2), f)
+    assert rel_max(host(f)[idx], data[:, 1]) <= 1e-13
+    for k in range(1, 4):
+        u = s.new_vector()
+        it, rr, code = s.solve(f, u, rtol=0.0, maxit=k, check=False)
+        assert (it, code) == (k, -6), last_error()
+        err = rel_max(host(u)[idx], data[:, 1 + k])
+        print(f"  cycle {k}: sampled max rel error {err:.2e}")
+        assert err <= 1e-10, k
+    u = s.new_vector()
+    it, rr, _ = s.solve(f, u, rtol=1e-12, maxit=60)
+    err = rel_max(host(u)[idx], data[:, 5])
+    print(f"  solve: {it} cycles, relres {rr:.2e}, sampled max rel error vs direct {err:.2e}")
+    assert rr <= 1e-12 and err <= 1e-10
+    s.close()
