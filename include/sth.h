@@ -143,6 +143,20 @@ int sth_num_levels(const sth_handle* h);
  * products). */
 int sth_load_rhs(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream);
 
+/* The same load vector as sth_load_rhs, for callers that cannot allocate
+ * device memory (tight serving loops, code that runs between the captures of
+ * a caller's HIP graphs, harnesses that forbid hipMalloc): the temporal and
+ * spatial mode tables are staged in a fixed device array of the library
+ * (4 MiB per GPU, 524288 doubles, held until the process ends) instead of
+ * device memory allocated per call.  This call allocates no device or pinned
+ * host memory.  The tables need n_modes * (n_slabs * N_t + 3 n) doubles; a
+ * larger request returns STH_EINVAL before any copy or launch.  Every call on
+ * one GPU shares that GPU's array, so calls that overlap in time on the same
+ * GPU (from several threads or on several streams) race; like sth_load_rhs,
+ * the call synchronises `stream` before it returns, so consecutive calls from
+ * one thread do not overlap. */
+int sth_load_rhs_noalloc(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream);
+
 /* y <- L_h u  (eq. equ_linear_system). */
 int sth_apply(sth_handle* h, const double* u, double* y, void* stream);
 

@@ -82,6 +82,7 @@ def load_library():
         "sth_num_levels": (i, [vp]),
         "sth_level_len": (sz, [vp, i]),
         "sth_load_rhs": (i, [vp, P(RhsModes), vp, vp]),
+        "sth_load_rhs_noalloc": (i, [vp, P(RhsModes), vp, vp]),
         "sth_apply": (i, [vp, vp, vp, vp]),
         "sth_residual": (i, [vp, vp, vp, vp, vp]),
         "sth_block_solve": (i, [vp, vp, vp, vp]),
@@ -251,6 +252,15 @@ class Solver:
         m, _keep = _modes(modes)
         _check(self.lib.sth_load_rhs(self.h, ctypes.byref(m), _ptr(f), _stream(stream)))
         return f
+
+    def load_rhs_noalloc(self, modes, f, stream=None, check=True):
+        """The same load vector staged through the library's fixed device
+        scratch (no device allocation); returns the status code."""
+        m, _keep = _modes(modes)
+        code = self.lib.sth_load_rhs_noalloc(self.h, ctypes.byref(m), _ptr(f), _stream(stream))
+        if check:
+            _check(code)
+        return code
 
     def apply(self, u, y, stream=None):
         _check(self.lib.sth_apply(self.h, _ptr(u), _ptr(y), _stream(stream)))

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -721,6 +722,37 @@ static int eig_exact_norm(sth_handle* h, hipStream_t st, const CycleFlag& fin = 
 }
 
 // ---------------------------------------------------------------------------
+// Device scratch of the entry point that allocates nothing
+// (sth_load_rhs_noalloc): the staging of the mode tables of the load vector
+// lives in a file-scope device array instead of memory allocated per call.
+// Each GPU holds its own copy of the array at its own address, taken once per
+// device with that device current; host code passes that address, never the
+// array's name, to kernels and copies.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchDoubles = size_t(1) << 19;          // 4 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+// device address of the current device's copy of `scratch`
+static int scratch_address(double** out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(STH_EINVAL, "device index out of range for the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(STH_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return STH_OK;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 static Problem to_problem(const sth_problem* p) {
@@ -822,6 +854,12 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!e.empty()) return fail(STH_EINVAL, e);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(STH_ENODEV, "no HIP device");
+    {
+        // the scratch address of this device, taken once at set-up
+        double* scr = nullptr;
+        const int rc = scratch_address(&scr);
+        if (rc != STH_OK) return rc;
+    }
     sth_handle* h = new sth_handle();
     int st = build_setup(q, h->S, e);
     if (st != 0) {
@@ -1071,6 +1109,42 @@ int sth_load_rhs(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream)
     (void)hipFree(dT);
     (void)hipFree(dX);
     if (e1 || e2 || e3 || e4) return fail(STH_EHIP, "rhs assembly failed");
+    return STH_OK;
+}
+
+int sth_load_rhs_noalloc(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream) {
+    if (!h || !m || !f) return fail(STH_EINVAL, "null argument");
+    if (m->n_modes < 0 || (m->n_modes > 0 && (!m->amp || !m->k || !m->omega || !m->phase)))
+        return fail(STH_EINVAL, "bad mode list");
+    hipStream_t st = (hipStream_t)stream;
+    const Problem& q = h->S.prob;
+    const long S = q.n_slabs;
+    const int n = h->n, Nt = h->Nt, M = m->n_modes;
+    if (M == 0) {
+        HIPCHK(launch_fill(f, S * slab_len(h), 0.0, st));
+        return STH_OK;
+    }
+    // the temporal and spatial tables side by side in the scratch array
+    const size_t nT = (size_t)M * S * Nt, nX = (size_t)M * 3 * n;
+    if (nT + nX > kScratchDoubles)
+        return fail(STH_EINVAL, "mode tables of " + std::to_string(nT + nX) + " doubles exceed the scratch of " +
+                                    std::to_string(kScratchDoubles) + " doubles (4 MiB): fewer modes or slabs");
+    double* scr = nullptr;
+    int rc = scratch_address(&scr);
+    if (rc != STH_OK) return rc;
+    std::vector<double> T(nT), X(nX, 0.0), tmp;
+    for (int q2 = 0; q2 < M; ++q2) {
+        load_time(q, m->omega[q2], m->phase[q2], tmp);
+        for (size_t i = 0; i < tmp.size(); ++i) T[(size_t)q2 * S * Nt + i] = m->amp[q2] * tmp[i];
+        for (int a = 0; a < h->dim; ++a) {
+            load_space(q, m->k[q2 * h->dim + a], tmp);
+            for (int i = 0; i < n; ++i) X[(size_t)q2 * 3 * n + (size_t)a * n + i] = tmp[i];
+        }
+    }
+    HIPCHK(hipMemcpyAsync(scr, T.data(), nT * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(scr + nT, X.data(), nX * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_rhs(h->dim, Nt, n, M, scr, scr + nT, f, S, st));
+    HIPCHK(hipStreamSynchronize(st));     // the host tables go out of scope
     return STH_OK;
 }
 
