@@ -293,7 +293,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                                                        const double* __restrict__ vw,
                                                        double* __restrict__ partial) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    double ssq = 0.0, wsq = 0.0;
+    double ssq = 0.0, wsq = 0.0, usq = 0.0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const long s0 = q * chain;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
         }
         const double mu = mode_shift(dim, mu1, n, m);
         const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
-        const double wm = mode_weight(dim, vw, n, m);
+        const ModeWeights wm = mode_weights(dim, vw, n, m);
         double prev_old = 0.0, prev_new = 0.0;
         if (s0 > 0) {
             double z[NT];
@@ -352,7 +352,8 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 #pragma unroll
             for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
             ssq += s2;
-            wsq += wm * s2;
+            wsq += wm.lo * s2;
+            usq += wm.up * s2;
             shifted_solve<NT, SCHUR>(tm, sh, g, z);
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
         }
     }
     // block sums (fixed order) of ||r^||^2 and its weighted form
-    block_sum2(ssq, wsq, partial);
+    block_sum3(ssq, wsq, usq, partial);
 }
 
 // Close of a cycle on the finest level followed by the start of the next
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
                                                          double* __restrict__ partial, const int* guard) {
     if (guard_off(guard)) return;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    double ssq = 0.0, wsq = 0.0;
+    double ssq = 0.0, wsq = 0.0, usq = 0.0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const long s0 = q * chain;
@@ -460,7 +461,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
             shifted_solve<NT, SCHUR>(tm, sh, e1, ca);
         }
-        const double wm = mode_weight(dim, vw, n, m);
+        const ModeWeights wm = mode_weights(dim, vw, n, m);
         // coupling rows of slab s0 - 1: u1, u2 and u3
         double p1 = 0.0, p2 = 0.0, p3 = 0.0;
         if (s0 > 0) {
@@ -540,7 +541,8 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 #pragma unroll
             for (int t = 0; t < NT; ++t) s2 += g[t] * g[t];
             ssq += s2;
-            wsq += wm * s2;
+            wsq += wm.lo * s2;
+            usq += wm.up * s2;
             double u3last = 0.0;
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             p3 = u3last;
         }
     }
-    block_sum2(ssq, wsq, partial);
+    block_sum3(ssq, wsq, usq, partial);
 }
 
 // The two coarsest levels of a V(1,1) cycle in one pass (a: second-coarsest
@@ -867,7 +869,7 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
-    if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if (3 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks);
     switch (Nt) {
 #define STH_CE_CASE(NTV)                                                                                     \
@@ -883,7 +885,7 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
 #undef STH_CE_CASE
         default: return hipErrorInvalidValue;
     }
-    return launch_sum_partials(partial, (int)blocks, out, out_host, 2, nullptr, flag, st);
+    return launch_sum_partials(partial, (int)blocks, out, out_host, 3, nullptr, flag, st);
 }
 
 hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
@@ -898,7 +900,7 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
-    if (2 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if (3 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks);
     switch (Nt) {
 #define STH_CC_CASE(NTV)                                                                                     \
@@ -926,7 +928,7 @@ hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial,
     if (chain < 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
     const long blocks = ((S / chain) * Nx + 255) / 256;
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
-    return launch_sum_partials(partial, (int)blocks, out, out_host, 2, guard, flag, st);
+    return launch_sum_partials(partial, (int)blocks, out, out_host, 3, guard, flag, st);
 }
 // groups and level-a slabs per thread of the two-level tail pass, or false
 // when the shape does not fit it

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_partials(const double* __re
     }
     constexpr int NW = kSumThreads / 64, NA = 8;
     __shared__ double red[NW];
-    __shared__ double res[2];
+    __shared__ double res[3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = 0; j < nsum; ++j) {
         // NA independent accumulators per thread (loads in flight together),
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kSumThreads) void k_sum_partials(const double* __re
             for (int w = 0; w < NW; ++w) t += red[w];
             out[j] = t;
             if (out_host) out_host[j] = t;
-            if (j < 2) res[j] = t;
+            if (j < 3) res[j] = t;
         }
         __syncthreads();
     }
@@ -193,16 +193,40 @@ hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u
 // ---------------------------------------------------------------------------
 // misc
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_fill(double* v, long len, double val) {
+__global__ void k_set_int(int* p, int value) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = value;
+}
+
+__global__ __launch_bounds__(256) void k_fill(double* v, long len, double val, const int* skip) {
+    if (skip != nullptr && skip[0] != 0) return;
     long stride = (long)gridDim.x * 256;
     for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) v[i] = val;
 }
 
-hipError_t launch_fill(double* v, long len, double val, hipStream_t st) {
+hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip) {
     if (len <= 0) return hipSuccess;
     long blocks = (len + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, v, len, val);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, v, len, val, skip);
+    return hipGetLastError();
+}
+
+// *flag |= 1 when some entry of v is not zero (NaN included); the caller
+// clears *flag first.  One atomic per wave that saw such an entry.
+__global__ __launch_bounds__(256) void k_any_nonzero(const double* __restrict__ v, long len, int* flag) {
+    int nz = 0;
+    const long stride = (long)gridDim.x * 256;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) nz |= !(v[i] == 0.0);
+    if (__any(nz) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_any_nonzero(const double* v, long len, int* flag, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, st, flag, 0);
+    if (len > 0) {
+        long blocks = (len + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_any_nonzero, dim3((unsigned)blocks), dim3(256), 0, st, v, len, flag);
+    }
     return hipGetLastError();
 }
 

@@ -15,7 +15,8 @@ namespace sth {
 template <typename CT, int EPI>
 __global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, double* __restrict__ out,
                                                  const double* __restrict__ T, int n, int np, long lines,
-                                                 double alpha) {
+                                                 double alpha, const int* guard) {
+    if (guard_off(guard)) return;
     using M = Mfma16<CT>;
     typedef typename M::acc_t acc_t;
     // FP64: rows of 16 (in_s) and 128 (T_s) words with XOR-swizzled columns
@@ -85,7 +86,8 @@ __global__ __launch_bounds__(256) void k_xform_x(const double* __restrict__ in, 
 template <typename CT>
 __global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, double* __restrict__ out,
                                                  const double* __restrict__ T, int n, int np, long inner,
-                                                 int nib, int njb) {
+                                                 int nib, int njb, const int* guard) {
+    if (guard_off(guard)) return;
     using M = Mfma16<CT>;
     typedef typename M::acc_t acc_t;
     // FP64: rows of 64 words, bit four of the column flipped on odd rows (the
@@ -151,7 +153,8 @@ __global__ __launch_bounds__(256) void k_xform_s(const double* __restrict__ in, 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_xform_x_bf16x3(const double* __restrict__ in, double* __restrict__ out,
                                                         const double* __restrict__ T, int n, int np, long lines,
-                                                        double alpha) {
+                                                        double alpha, const int* guard) {
+    if (guard_off(guard)) return;
     __shared__ unsigned short ih[64][20], il[64][20];      // [line][k]
     __shared__ unsigned short th[128][20], tl[128][20];    // [j][k]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -215,7 +218,8 @@ __global__ __launch_bounds__(256) void k_xform_x_bf16x3(const double* __restrict
 
 __global__ __launch_bounds__(256) void k_xform_s_bf16x3(const double* __restrict__ in, double* __restrict__ out,
                                                         const double* __restrict__ T, int n, int np, long inner,
-                                                        int nib, int njb) {
+                                                        int nib, int njb, const int* guard) {
+    if (guard_off(guard)) return;
     __shared__ unsigned short ih[64][20], il[64][20];      // [i][k]
     __shared__ unsigned short th[64][20], tl[64][20];      // [j][k]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -274,27 +278,33 @@ __global__ __launch_bounds__(256) void k_xform_s_bf16x3(const double* __restrict
 
 template <typename CT>
 static void xform_x_ct(int epi, dim3 grid, hipStream_t st, const double* in, double* out, const double* T, int n,
-                       int np, long lines, double alpha) {
-    if (epi == 0) hipLaunchKernelGGL((k_xform_x<CT, 0>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    else if (epi == 1) hipLaunchKernelGGL((k_xform_x<CT, 1>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    else hipLaunchKernelGGL((k_xform_x<CT, 2>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+                       int np, long lines, double alpha, const int* guard) {
+    if (epi == 0)
+        hipLaunchKernelGGL((k_xform_x<CT, 0>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
+    else if (epi == 1)
+        hipLaunchKernelGGL((k_xform_x<CT, 1>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
+    else
+        hipLaunchKernelGGL((k_xform_x<CT, 2>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
 }
 
 hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st) {
+                          long lines, double alpha, hipStream_t st, const int* guard) {
     if (lines <= 0) return hipSuccess;
     if (epi < 0 || epi > 2 || prec < 0 || prec > 2) return hipErrorInvalidValue;
     dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
-    if (prec == 0) xform_x_ct<double>(epi, grid, st, in, out, T, n, np, lines, alpha);
-    else if (prec == 1) xform_x_ct<float>(epi, grid, st, in, out, T, n, np, lines, alpha);
-    else if (epi == 0) hipLaunchKernelGGL(k_xform_x_bf16x3<0>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    else if (epi == 1) hipLaunchKernelGGL(k_xform_x_bf16x3<1>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
-    else hipLaunchKernelGGL(k_xform_x_bf16x3<2>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha);
+    if (prec == 0) xform_x_ct<double>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
+    else if (prec == 1) xform_x_ct<float>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
+    else if (epi == 0)
+        hipLaunchKernelGGL(k_xform_x_bf16x3<0>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
+    else if (epi == 1)
+        hipLaunchKernelGGL(k_xform_x_bf16x3<1>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
+    else
+        hipLaunchKernelGGL(k_xform_x_bf16x3<2>, grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
     return hipGetLastError();
 }
 
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st) {
+                          long nbatch, long inner, hipStream_t st, const int* guard) {
     if (nbatch <= 0) return hipSuccess;
     if (prec < 0 || prec > 2) return hipErrorInvalidValue;
     int nib = (int)((inner + 63) / 64), njb = (np + 63) / 64;
@@ -302,13 +312,13 @@ hipError_t launch_xform_s(int prec, const double* in, double* out, const double*
     if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
     if (prec == 0)
         hipLaunchKernelGGL(k_xform_s<double>, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner,
-                           nib, njb);
+                           nib, njb, guard);
     else if (prec == 1)
         hipLaunchKernelGGL(k_xform_s<float>, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner,
-                           nib, njb);
+                           nib, njb, guard);
     else
         hipLaunchKernelGGL(k_xform_s_bf16x3, dim3((unsigned)blocks), dim3(256), 0, st, in, out, T, n, np, inner,
-                           nib, njb);
+                           nib, njb, guard);
     return hipGetLastError();
 }
 

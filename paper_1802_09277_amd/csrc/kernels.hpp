@@ -66,11 +66,13 @@ hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, con
 // of length n.  EPI 0: store, 1: out += alpha*acc, 2: out = alpha*acc.
 // prec (sth_prec): 0 MFMA f64, 1 MFMA f32 (FP32 accumulation), 2 BF16x3.
 hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st);
+                          long lines, double alpha, hipStream_t st, const int* guard = nullptr);
 
 // Strided axis: in[b][k][i] (k stride `inner`), out[b][j][i] = sum_k T[k][j] in[b][k][i].
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st);
+                          long nbatch, long inner, hipStream_t st, const int* guard = nullptr);
+// (both per-axis launchers: every block returns at once when guard is given
+// and *guard == 0, as in the guards of speculative cycles)
 
 // Both spatial axes of 2-D images (n x n each, nimg images, image i at
 // in + i ldi and out + i ldo; 0: n^2) in one kernel:
@@ -121,12 +123,13 @@ hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktm
                            const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
                            int chain, hipStream_t st, const int* guard = nullptr);
 //  end of a cycle on the finest level, in one pass over f^ and u^ (chains as
-//  above): ||fh - L uin||^2 and its mode-weighted form sum_m v_m |r_m|^2
-//  (weights from the per-axis table vw of the diagonal entries and absolute
-//  row sums of G = C^T C) to out[0..1], and to out_host[0..1] (mapped pinned
-//  host memory) if not null; uout = uin + omega A^{-1}(fh - L uin),
-//  fc = (P^T (x) I)(fh - L uout) on slab pairs.  partial needs
-//  max_partial >= 2 ceil((S/chain) Nx / 256) entries
+//  above): ||fh - L uin||^2 and its lower and upper mode-weighted forms
+//  sum_m v_m |r_m|^2, sum_m w_m |r_m|^2 (weights from the per-axis table vw
+//  of the diagonal entries and absolute row sums of G = C^T C) to
+//  out[0..2], and to out_host[0..2] (mapped pinned host memory) if not null;
+//  uout = uin + omega A^{-1}(fh - L uin), fc = (P^T (x) I)(fh - L uout) on
+//  slab pairs.  partial needs max_partial >= 3 ceil((S/chain) Nx / 256)
+//  entries
 hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
@@ -134,7 +137,7 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
                                 const CycleFlag& flag = CycleFlag{});
 //  close of a cycle on the finest level and start of the next in one pass
 //  (chains and sums as above): u1 = upre + (P_t (x) I) ec, uend = u1 +
-//  omega A^{-1}(fh - L u1) (the cycle's result), the two sums of
+//  omega A^{-1}(fh - L u1) (the cycle's result), the three sums of
 //  fh - L uend, unext = uend + omega A^{-1}(fh - L uend), fc =
 //  (P^T (x) I)(fh - L unext) on slab pairs; the three iterate buffers differ
 hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
@@ -188,7 +191,10 @@ hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* 
 hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u, long Sc,
                           long Nx, hipStream_t st);
 
-hipError_t launch_fill(double* v, long len, double val, hipStream_t st);
+// v[0..len) = val, skipped when skip is given and *skip != 0
+hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip = nullptr);
+// *flag = 1 if some entry of v[0..len) is not zero (NaN included), else 0
+hipError_t launch_any_nonzero(const double* v, long len, int* flag, hipStream_t st);
 
 // Krylov vectors V_i = V + i*ld (i < k <= kMaxKrylov), for the FGMRES loop:
 //  out[i] = <V_i, w> (deterministic; partial needs 1024 * kMaxKrylov entries)

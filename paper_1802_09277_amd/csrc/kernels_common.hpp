@@ -279,10 +279,14 @@ __device__ __forceinline__ double mode_shift(int dim, const double* mu1, int n, 
 }
 
 
-// Weight v of a spatial mode in the lower bound of the B-spline residual norm
-// (vw: per axis and 1-D mode, the diagonal entry d and the absolute row sum a
-// of G = C^T C; v = 2 prod d - prod a over the axes)
-__device__ __forceinline__ double mode_weight(int dim, const double* __restrict__ vw, int n, long m) {
+// Weights of a spatial mode in the two-sided bounds of the B-spline residual
+// norm (vw: per axis and 1-D mode, the diagonal entry d and the absolute row
+// sum a of G = C^T C): lower v = 2 prod d - prod a, upper w = prod a over the
+// axes, so that sum_m v_m r^_m^2 <= ||r||^2 <= sum_m w_m r^_m^2
+struct ModeWeights {
+    double lo, up;
+};
+__device__ __forceinline__ ModeWeights mode_weights(int dim, const double* __restrict__ vw, int n, long m) {
     const int jx = (int)(m % n);
     const long rest = m / n;
     const int jy = (int)(rest % n);
@@ -294,25 +298,29 @@ __device__ __forceinline__ double mode_weight(int dim, const double* __restrict_
     double d = vw[2 * jx] * vw[2 * jy], a = vw[2 * jx + 1] * vw[2 * jy + 1];
     d *= dim == 3 ? dz : 1.0;
     a *= dim == 3 ? az : 1.0;
-    return 2.0 * d - a;
+    return ModeWeights{2.0 * d - a, a};
 }
 
-// block sums of two per-thread values into partial[b] and partial[nb + b]
-__device__ __forceinline__ void block_sum2(double x, double y, double* __restrict__ partial) {
+// block sums of three per-thread values into partial[b], partial[nb + b]
+// and partial[2 nb + b] (nb blocks; fixed order)
+__device__ __forceinline__ void block_sum3(double x, double y, double z, double* __restrict__ partial) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         x += __shfl_xor(x, off);
         y += __shfl_xor(y, off);
+        z += __shfl_xor(z, off);
     }
-    __shared__ double red[8];
+    __shared__ double red[12];
     if ((threadIdx.x & 63) == 0) {
         red[threadIdx.x >> 6] = x;
         red[4 + (threadIdx.x >> 6)] = y;
+        red[8 + (threadIdx.x >> 6)] = z;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
         partial[gridDim.x + blockIdx.x] = (red[4] + red[5]) + (red[6] + red[7]);
+        partial[2 * gridDim.x + blockIdx.x] = (red[8] + red[9]) + (red[10] + red[11]);
     }
 }
 

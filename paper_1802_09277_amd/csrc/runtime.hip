@@ -30,7 +30,15 @@ using namespace sth;
 
 static thread_local std::string g_err;
 
-constexpr int kNormSlots = 12;          // squared norms on the device and their mapped host copies
+// squared norms on the device and their mapped host copies: [0] exact
+// residual, [1] right-hand side, then three cycle slots of three sums each
+// (eigenbasis residual, its lower and its upper mode-weighted sums; slots 0
+// and 1 alternate between cycles, slot 2 is the initial pass of a
+// speculative solve), then the outer residual and right-hand side of a
+// mixed-precision solve
+constexpr int kNormSlots = 14;
+constexpr int slot_base(int slot) { return 2 + 3 * slot; }
+constexpr int kMixR = 11, kMixF = 12;
 
 static int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -93,15 +101,13 @@ struct sth_handle {
     double* kpart = nullptr;            // 1024 x kMaxKrylov partial sums
     double* khost = nullptr;            // pinned copy of kc
     double nb_lo = 0.0;                 // ||(I (x) C) r^||^2 >= nb_lo ||r^||^2
+    double nb_hi = 0.0;                 // ||(I (x) C) r^||^2 <= nb_hi ||r^||^2
     double* vw = nullptr;               // per axis and 1-D mode: G_jj and sum_k |G_jk| (G = C^T C)
-    bool wsum_valid = false;            // hnorm[3] holds the mode-weighted residual sum
+    bool wsum_valid = false;            // the norm slots hold the mode-weighted residual sums
     double* buf0 = nullptr;
     double* buf1 = nullptr;
     double* partial = nullptr;
-    double* dnorm = nullptr;            // squared norms: [0] residual, [1] right-hand side; per norm slot
-                                        // s (2 + 2s, 3 + 2s) eigenbasis residual and its weighted sum;
-                                        // slot 2 (6, 7): the initial pass of a speculative solve;
-                                        // [8], [9]: residual and right-hand side of a mixed-precision solve
+    double* dnorm = nullptr;            // squared norms (layout at kNormSlots)
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
     double* hnorm_dev = nullptr;        // device address of hnorm
     // timing
@@ -186,7 +192,8 @@ struct sth_handle {
     const int* guard = nullptr;         // guard of the launches of the cycle being enqueued
     int* dgo = nullptr;                 // per norm slot: continuation flag of the cycle (device);
                                         // [2]: the final exact norm ends the solve; [3]: the
-                                        // initial pass of a speculative solve
+                                        // initial pass of a speculative solve; [4]: the initial
+                                        // guess of the solve has a nonzero entry
     int* hflag = nullptr;               // its mapped host copy
     int* hflag_dev = nullptr;
     double* dthr = nullptr;             // (rtol ||f||)^2 and rtol ||f|| of the solve in progress (device)
@@ -273,18 +280,18 @@ static int residual(sth_handle* h, int lvl, const double* f, const double* u, do
 
 // per-axis transforms in the precision `prec` (sth_prec)
 static int xform_x(sth_handle* h, int prec, int epi, const double* in, double* out, const double* T, long lines,
-                   double alpha, hipStream_t st) {
+                   double alpha, hipStream_t st, const int* guard = nullptr) {
     double dof = (double)lines * h->n;
     Timed tm(h, STH_K_XFORM_X, 2.0 * h->n * dof, dof * (epi == 1 ? 24.0 : 16.0), st);
-    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st));
+    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st, guard));
     return STH_OK;
 }
 
 static int xform_s(sth_handle* h, int prec, const double* in, double* out, const double* T, long nbatch,
-                   long inner, hipStream_t st) {
+                   long inner, hipStream_t st, const int* guard = nullptr) {
     double dof = (double)nbatch * h->n * inner;
     Timed tm(h, STH_K_XFORM_S, 2.0 * h->n * dof, 16.0 * dof, st);
-    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st));
+    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st, guard));
     return STH_OK;
 }
 
@@ -482,24 +489,25 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     // axis by axis, ping-ponging between the buffers; with accumulation the
     // contiguous axis goes last, so that its epilogue adds into out
     const double* T = fwd ? A : At;
+    const int* g = guard;
     int rc;
     if (h->dim == 2) {
         if (epi == 0) {
-            if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n, 1.0, st))) return rc;
-            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st))) return rc;
+            if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n, 1.0, st, g))) return rc;
+            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st, g))) return rc;
         } else {
-            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st))) return rc;
-            if ((rc = xform_x(h, prec, epi, tmp, out, T, rows * n, 1.0, st))) return rc;
+            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st, g))) return rc;
+            if ((rc = xform_x(h, prec, epi, tmp, out, T, rows * n, 1.0, st, g))) return rc;
         }
     } else if (epi == 0) {
-        if ((rc = xform_x(h, prec, 0, in, out, T, rows * n * n, 1.0, st))) return rc;   // x
-        if ((rc = xform_s(h, prec, out, tmp, T, rows * n, n, st))) return rc;            // y
-        if ((rc = xform_s(h, prec, tmp, out, T, rows, n * n, st))) return rc;            // z
+        if ((rc = xform_x(h, prec, 0, in, out, T, rows * n * n, 1.0, st, g))) return rc;   // x
+        if ((rc = xform_s(h, prec, out, tmp, T, rows * n, n, st, g))) return rc;            // y
+        if ((rc = xform_s(h, prec, tmp, out, T, rows, n * n, st, g))) return rc;            // z
     } else {
         if (!tmp2) return fail(STH_EINVAL, "accumulating 3-D transform without a second scratch vector");
-        if ((rc = xform_s(h, prec, in, tmp, T, rows, n * n, st))) return rc;             // z
-        if ((rc = xform_s(h, prec, tmp, tmp2, T, rows * n, n, st))) return rc;           // y
-        if ((rc = xform_x(h, prec, epi, tmp2, out, T, rows * n * n, 1.0, st))) return rc;   // x, added
+        if ((rc = xform_s(h, prec, in, tmp, T, rows, n * n, st, g))) return rc;             // z
+        if ((rc = xform_s(h, prec, tmp, tmp2, T, rows * n, n, st, g))) return rc;           // y
+        if ((rc = xform_x(h, prec, epi, tmp2, out, T, rows * n * n, 1.0, st, g))) return rc;   // x, added
     }
     return STH_OK;
 }
@@ -529,8 +537,13 @@ static int eig_smooth(sth_handle* h, int lvl, bool zero_guess, hipStream_t st, c
 }
 
 // slabs per thread in the chained passes: the longest chain (fewest repeated
-// chain starts) that still leaves min_threads threads
+// chain starts) that still leaves min_threads threads; chains of 16 and 32
+// slabs only where four times as many threads remain (large levels, where
+// the repeated starts of shorter chains cost a measurable share of the
+// traffic)
 static int chain_length(const sth_handle* h, long S, long min_threads) {
+    for (int c : {32, 16})
+        if (S % c == 0 && (S / c) * h->Nx >= 4 * min_threads) return c;
     for (int c : {8, 4})
         if (S % c == 0 && (S / c) * h->Nx >= min_threads) return c;
     return 2;
@@ -602,7 +615,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
 }
 
 // ||r^||^2 of the residual r^ = f^ - L u^ of the current eigenbasis iterate
-// to the pinned host scalar hnorm[2] (not synchronised).  With one
+// to the pinned host scalars of a norm slot (not synchronised).  With one
 // pre-smoothing step in the cycle and a level below, a single pass (the
 // cycle-end kernel) also takes the next cycle's smoothing step (into the
 // other buffer of the pair) and restricts the residual of its result into
@@ -638,11 +651,11 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
             HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                           eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
                                           eig_f(h, 1), h->tr, h->omega, S, chain, h->vw, h->cpartial,
-                                          h->n_cpartial, h->dnorm + 2 + 2 * slot, h->hnorm_dev + 2 + 2 * slot, st,
+                                          h->n_cpartial, h->dnorm + slot_base(slot), h->hnorm_dev + slot_base(slot), st,
                                           h->guard, flag, false));
         }
-        HIPCHK(launch_cycle_sums(h->dim, h->n, S, chain, h->cpartial, h->dnorm + 2 + 2 * slot,
-                                 h->hnorm_dev + 2 + 2 * slot, st, h->guard, flag));
+        HIPCHK(launch_cycle_sums(h->dim, h->n, S, chain, h->cpartial, h->dnorm + slot_base(slot),
+                                 h->hnorm_dev + slot_base(slot), st, h->guard, flag));
         h->last_slot = slot;
         h->pending_ec = nullptr;
         h->wsum_valid = true;
@@ -660,7 +673,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         // second cycle writes slot 0 while the host reads these)
         CycleFlag flag;
         if (h->first_flag) flag = CycleFlag{h->dgo + 3, h->hflag_dev + 3, h->dthr, h->nb_lo};
-        const int at = h->first_flag ? 6 : 2;
+        const int at = slot_base(h->first_flag ? 2 : 0);
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, o), eig_f(h, 1), h->tr, h->omega, S,
                                     chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + at,
@@ -678,11 +691,12 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
     }
     {
         Timed tm(h, STH_K_NORM, 2.0 * dof, 8.0 * dof, st);
-        HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + 2, st));
+        HIPCHK(launch_norm2(h->buf0, len, h->partial, h->dnorm + slot_base(0), st));
     }
     h->wsum_valid = false;
     h->last_slot = 0;
-    HIPCHK(hipMemcpyAsync(h->hnorm + 2, h->dnorm + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->hnorm + slot_base(0), h->dnorm + slot_base(0), sizeof(double), hipMemcpyDeviceToHost,
+                          st));
     return STH_OK;
 }
 
@@ -885,6 +899,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     }
     h->L = (int)h->S.levels.size();
     h->nb_lo = std::pow(h->S.m1_min, h->dim);
+    h->nb_hi = std::pow(h->S.m1_max, h->dim);
     h->fuse_close = fused_cycle_close(q, (size_t)h->L);
     {
         int G = 0, LA = 0;
@@ -1001,7 +1016,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
                 Cf[(size_t)i * np + j] = c;
                 Ci[(size_t)j * np + i] = c;
             }
-        h->n_cpartial = 2 * (((q.n_slabs / 2) * h->Nxe + 255) / 256);   // two sums per block
+        h->n_cpartial = 3 * (((q.n_slabs / 2) * h->Nxe + 255) / 256);   // three sums per block
         if (!dalloc(&h->cpartial, (size_t)h->n_cpartial) ||
             !dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
             !dalloc(&h->e0, (size_t)q.n_slabs * eslab) || !dalloc(&h->e1, (size_t)q.n_slabs * eslab) ||
@@ -1048,7 +1063,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess ||
         hipHostGetDevicePointer((void**)&h->hseq_dev, h->hseq, 0) != hipSuccess)
         return cleanup(STH_EHIP, "pinned host memory is not mapped");
-    if (hipMalloc((void**)&h->dgo, 4 * sizeof(int)) != hipSuccess ||
+    if (hipMalloc((void**)&h->dgo, 5 * sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&h->dthr, 2 * sizeof(double)) != hipSuccess)
         return cleanup(STH_ENOMEM, "device allocation failed");
     for (auto& e : h->evring)
@@ -1334,11 +1349,17 @@ static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rt
         const long rows = h->lev_S[0] * h->Nt;
         h->ecur[0] = 0;
         if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st, nullptr, v.tprec))) return rc;
+        h->tlev = 0;
         if (v.inner) {
-            h->tlev = 0;
             HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st));     // zero initial guess
-        } else if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st))) {
-            return rc;
+        } else {
+            // an initial guess of zeros (the usual start) needs no transform:
+            // a device flag says whether u has a nonzero entry; the transform
+            // runs only then, the fill of zeros only otherwise
+            int* nz = h->dgo + 4;
+            HIPCHK(launch_any_nonzero(u, len, nz, st));
+            if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st, nz))) return rc;
+            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nz));
         }
         // (with graph replay, whose captured cycles have fixed guards, the
         // first cycle waits for the initial norms instead)
@@ -1451,10 +1472,25 @@ static int solve_finish(sth_handle* h, bool* more) {
 // norm slot `slot` (the larger of the two bounds of solve_continue); slot 2
 // holds the initial pass of a speculative solve
 static double eig_lower_bound(const sth_handle* h, int slot) {
-    const double ssq = h->hnorm[2 + 2 * slot], wsq = h->hnorm[3 + 2 * slot];
+    const double ssq = h->hnorm[slot_base(slot)], wsq = h->hnorm[slot_base(slot) + 1];
     double lo2 = h->nb_lo * ssq;
     if (h->wsum_valid && std::isfinite(wsq)) lo2 = std::max(lo2, (1.0 - 1e-8) * wsq);
     return std::sqrt(lo2);
+}
+
+// Upper bound of the B-spline residual norm of the same cycle: the smaller
+// of nb_hi ||r^||^2 (the eigenvalues of G = C^T C are those of M_1) and
+// sum_m w_m r^_m^2 with w_m = prod a over the axes of mode m (a the absolute
+// row sums of G; the Schur test bounds x^T (G (x) G) x by the absolute row
+// sums of G (x) G), slightly enlarged against rounding.  When it meets the
+// tolerance the cycle has converged without the exact norm; with the lower
+// bound above the tolerance it provably has not, so the cycle count is that
+// of the plain stopping test either way.
+static double eig_upper_bound(const sth_handle* h, int slot) {
+    const double ssq = h->hnorm[slot_base(slot)], usq = h->hnorm[slot_base(slot) + 2];
+    double up2 = h->nb_hi * ssq;
+    if (h->wsum_valid && std::isfinite(usq)) up2 = std::min(up2, (1.0 + 1e-8) * usq);
+    return std::sqrt(up2);
 }
 
 // Exact norm of the current iterate in the speculative loop; on the fused
@@ -1494,12 +1530,17 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
     if (v.phase == 0) {
         v.fn = std::sqrt(h->hnorm[1]);
         if (v.fn == 0.0) v.fn = 1.0;
-        const double r = std::sqrt(h->hnorm[2]);
+        const double r = std::sqrt(h->hnorm[slot_base(0)]);
         v.prev = r;
         v.rn = eig_lower_bound(h, 0);
         if (!std::isfinite(r) || v.maxit == 0) return solve_finish(h, more);
         if (!(v.rn > v.rtol * v.fn)) {
             if (v.inner) return solve_finish(h, more);      // the outer loop takes the exact norm
+            const double up = eig_upper_bound(h, 0);
+            if (up <= v.rtol * v.fn) {
+                v.rn = up;
+                return solve_finish(h, more);
+            }
             v.phase = 3;
             int rc = eig_exact_norm(h, v.st);
             h->wait_ev = nullptr;
@@ -1514,11 +1555,11 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
     }
     if (v.phase == 4) {
         // the initial norms and cycle a are done; the flag of the initial
-        // pass (its own slot: sums in hnorm[6..7], flag in hflag[3]) says
+        // pass (its own norm slot 2 and flag hflag[3]) says
         // whether cycle a (and so cycle b) ran
         v.fn = std::sqrt(h->hnorm[1]);
         if (v.fn == 0.0) v.fn = 1.0;
-        const double r = std::sqrt(h->hnorm[6]);
+        const double r = std::sqrt(h->hnorm[slot_base(2)]);
         v.prev = r;
         v.phase = 1;
         if (h->hflag[3] == 0) {
@@ -1530,6 +1571,11 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
                 return solve_finish(h, more);
             }
             if (v.inner) return solve_finish(h, more);
+            const double up = eig_upper_bound(h, 2);
+            if (up <= v.rtol * v.fn) {
+                v.rn = up;
+                return solve_finish(h, more);
+            }
             return spec_exact_norm(h);
         }
         // cycle a ran: go on as after any completed cycle
@@ -1554,7 +1600,7 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
     // cycle a has completed
     ++v.it;
     const int slot = v.a.slot;
-    const double r = std::sqrt(h->hnorm[2 + 2 * slot]);
+    const double r = std::sqrt(h->hnorm[slot_base(slot)]);
     if (std::isfinite(r)) {
         v.growth = (r > v.prev) ? v.growth + 1 : 0;
         v.prev = r;
@@ -1601,6 +1647,11 @@ static int solve_continue_spec(sth_handle* h, bool* more) {
         return solve_finish(h, more);
     }
     if (v.inner) return solve_finish(h, more);
+    const double up = eig_upper_bound(h, slot);
+    if (up <= target) {
+        v.rn = up;
+        return solve_finish(h, more);
+    }
     return spec_exact_norm(h);
 }
 
@@ -1634,7 +1685,7 @@ static int solve_continue_impl(sth_handle* h, bool* more) {
     if (v.phase == 3) {
         v.rn = std::sqrt(h->hnorm[0]);
     } else {
-        const double r = std::sqrt(h->hnorm[eig ? 2 + 2 * h->last_slot : 0]);
+        const double r = std::sqrt(h->hnorm[eig ? slot_base(h->last_slot) : 0]);
         if (v.phase == 0) {
             v.fn = std::sqrt(h->hnorm[1]);
             if (v.fn == 0.0) v.fn = 1.0;
@@ -1655,6 +1706,11 @@ static int solve_continue_impl(sth_handle* h, bool* more) {
             if (std::isfinite(r) && v.rn > v.rtol * v.fn && v.it < v.maxit && v.growth < 3)
                 return enqueue_iteration(h);
             if (v.inner) return solve_finish(h, more);
+            const double up = eig_upper_bound(h, h->last_slot);
+            if (std::isfinite(r) && up <= v.rtol * v.fn) {
+                v.rn = up;
+                return solve_finish(h, more);
+            }
             v.phase = 3;
             return eig_exact_norm(h, v.st);
         }
@@ -1695,9 +1751,9 @@ static int mixed_residual(sth_handle* h) {
     h->tlev = 0;
     {
         Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, m.st);
-        HIPCHK(launch_norm2(h->buf1, len, h->partial, h->dnorm + 8, m.st));
+        HIPCHK(launch_norm2(h->buf1, len, h->partial, h->dnorm + kMixR, m.st));
     }
-    HIPCHK(hipMemcpyAsync(h->hnorm + 8, h->dnorm + 8, sizeof(double), hipMemcpyDeviceToHost, m.st));
+    HIPCHK(hipMemcpyAsync(h->hnorm + kMixR, h->dnorm + kMixR, sizeof(double), hipMemcpyDeviceToHost, m.st));
     h->wait_ev = nullptr;                 // the caller waits for the stream
     h->wait_slot = -1;
     m.phase = 0;
@@ -1722,9 +1778,9 @@ static int mixed_begin(sth_handle* h, const double* f, double* u, double rtol, i
     h->tlev = 0;
     {
         Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, st);
-        HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + 9, st));
+        HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + kMixF, st));
     }
-    HIPCHK(hipMemcpyAsync(h->hnorm + 9, h->dnorm + 9, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->hnorm + kMixF, h->dnorm + kMixF, sizeof(double), hipMemcpyDeviceToHost, st));
     return mixed_residual(h);
 }
 
@@ -1747,10 +1803,10 @@ static int mixed_continue(sth_handle* h, bool* more) {
     }
     // outer residual norm of the current iterate
     if (m.outer == 0) {
-        m.fn = std::sqrt(h->hnorm[9]);
+        m.fn = std::sqrt(h->hnorm[kMixF]);
         if (m.fn == 0.0) m.fn = 1.0;
     }
-    const double rn = std::sqrt(h->hnorm[8]);
+    const double rn = std::sqrt(h->hnorm[kMixR]);
     if (m.outer > 0 && std::isfinite(rn)) m.growth = (rn >= m.prev) ? m.growth + 1 : 0;
     m.rn = rn;
     m.prev = rn;
