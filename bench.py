@@ -143,7 +143,7 @@ def finish_cpu_baseline(cfg, sample_slabs, started, limit_s):
 
 
 KERNEL_SOURCES = ("kernels.hpp", "kernels_common.hpp", "k_residual.hip", "k_xform2d.hip", "k_xform_axis.hip",
-                  "k_eigen.hip", "k_misc.hip")
+                  "k_xform_panel.hip", "k_eigen.hip", "k_misc.hip")
 
 
 def kernel_source_hash():

@@ -124,10 +124,16 @@ void sth_problem_default(sth_problem* p);
  * only, no allocation: used for admission by memory footprint. */
 int sth_workspace_bytes(const sth_problem* p, size_t* bytes);
 
-/* Host FP64 setup (1-D spline matrices, temporal pencils of every level,
- * their eigen decompositions with the Re(lambda) > 0 and cond(V) guards,
- * spatial fast-diagonalisation factors) and upload on `stream`.  On success
- * *out owns device memory until sth_destroy.  Synchronises `stream`. */
+/* Host FP64 setup and upload on `stream`: the 1-D spatial mass and stiffness
+ * matrices and the temporal matrices K_t, M_t of eq. TimeMatrices on every
+ * level (Section 2.3, the slab operators of eq. structureAn), the temporal
+ * pencil of every level in the eigen form of Section 3.3 (real 2x2 blocks,
+ * the Re(lambda) > 0 check of Section 3.2 -> STH_ENOTPOS, the cond(V) guard
+ * -> STH_ECOND) or its real Schur form, the spatial fast-diagonalisation
+ * factors, and the time prolongation of Section 3.1.  Arguments: the problem
+ * (host, read only), a hipStream_t (NULL = default stream), *out receives the
+ * handle.  On success *out owns device memory until sth_destroy; on failure
+ * *out is NULL and nothing stays allocated.  Synchronises `stream`. */
 int sth_setup(const sth_problem* p, void* stream, sth_handle** out);
 
 /* n_slabs * N_t * n^dim (n = n_elem + degree - 2), or 0 for NULL. */
@@ -160,24 +166,41 @@ int sth_load_rhs_noalloc(sth_handle* h, const sth_rhs_modes* m, double* f, void*
 /* y <- L_h u  (eq. equ_linear_system). */
 int sth_apply(sth_handle* h, const double* u, double* y, void* stream);
 
-/* r <- f - L_h u, i.e. r_n = f_n - A_n u_n + B_n u_{n-1} for all slabs. */
+/* r <- f - L_h u, i.e. r_n = f_n - A_n u_n + B_n u_{n-1} for all slabs
+ * (eq. equ_linear_system with A_n, B_n of eq. structureAn).  f, u, r: device
+ * vectors of sth_vector_len(h) doubles; r must not alias f or u. */
 int sth_residual(sth_handle* h, const double* f, const double* u, double* r, void* stream);
 
 /* z <- D^{-1} r with D = diag(A_n): every slab inverted independently by
  * eq. equ:ST:generalDecompA (exact up to rounding for FP64 transforms). */
 int sth_block_solve(sth_handle* h, const double* r, double* z, void* stream);
 
-/* `steps` damped block-Jacobi steps u <- u + omega D^{-1}(f - L_h u). */
+/* `steps` damped block-Jacobi steps u <- u + omega D^{-1}(f - L_h u) with
+ * D = diag(A_n), the smoother of the time-parallel multigrid (Section 3.1);
+ * u (device, sth_vector_len(h) doubles) is updated in place. */
 int sth_smooth(sth_handle* h, const double* f, double* u, int steps, void* stream);
 
-/* One V(nu_pre, nu_post) cycle on the finest level, u updated in place. */
+/* One V(nu_pre, nu_post) cycle of the time-parallel multigrid (Section 3.1:
+ * the slab smoother, restriction and prolongation in time between pairs of
+ * slabs and one coarse slab, an exact solve on the coarsest level) on the
+ * finest level; u (device) is updated in place.  Iterates on the B-spline
+ * coefficients, whatever iterate_basis says. */
 int sth_vcycle(sth_handle* h, const double* f, double* u, void* stream);
 
 /* V-cycles from the initial guess in u until ||f - L_h u||_2 <= rtol ||f||_2
- * or maxit cycles.  Blocks the host (one scalar read per cycle).  iters and
- * relres (may be NULL) receive the cycle count and the final relative
- * residual.  Returns STH_ENOCONV on NaN, on growth over 3 consecutive
- * cycles or when maxit is reached. */
+ * (the stopping test of Section 4.4: Euclidean norm of the coefficient
+ * vector relative to the right-hand side) or maxit cycles.  f, u: device
+ * vectors of sth_vector_len(h) doubles (u holds the initial guess and
+ * receives the result).  Blocks the host until the result is in u.  iters
+ * and relres (may be NULL) receive the cycle count and the final relative
+ * residual (in the eigenbasis iteration an upper bound of it when the
+ * two-sided bound decides the test, else the exact value).  With
+ * iterate_basis 1 and transform_prec FP32 or BF16x3 the solve is an FP64
+ * defect correction: each outer step forms the FP64 residual and its exact
+ * norm, and an eigenbasis solve with reduced-precision transforms reduces
+ * it; iters is then the sum of the inner cycles.  Returns STH_ENOCONV on
+ * NaN, on growth over 3 consecutive cycles (outer steps) or when maxit is
+ * reached. */
 int sth_solve(sth_handle* h, const double* f, double* u, double rtol, int maxit,
               int* iters, double* relres, void* stream);
 

@@ -34,10 +34,10 @@ __global__ __launch_bounds__(256) void k_timemix(int dim, TimeMix tm, const doub
 // modes (one 128-byte line per time row) x 16 slab groups: each thread solves
 // its group's slabs (into out), the groups' recurrences are chained through
 // LDS, and a second sweep adds x_{s-1} c.  in and out must differ.
-template <int NT, bool SCHUR>
+template <int NT, bool SCHUR, typename VT>
 __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
-                                                      long Nx, const double* __restrict__ in,
-                                                      double* __restrict__ out, long S, const int* guard) {
+                                                      long Nx, const VT* __restrict__ in,
+                                                      VT* __restrict__ out, long S, const int* guard) {
     if (guard_off(guard)) return;
     constexpr int MB = 16, G = 16, LR = 4;      // LR: slabs per group held in registers
     __shared__ double xe_s[G][MB], gl_s[G][MB];
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
 #pragma unroll
             for (int i = 0; i < LR; ++i)
                 if (sb + i < se) {
-                    const double* gp = in + (sb + i) * NT * Nx + m;
+                    const VT* gp = in + (sb + i) * NT * Nx + m;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) areg[i][t] = gp[(long)t * Nx];
                 }
@@ -78,12 +78,12 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
                 }
         }
         for (long s = inreg ? se : sb; s < se; ++s) {
-            const double* gp = in + s * NT * Nx + m;
+            const VT* gp = in + s * NT * Nx + m;
             double gv[NT], a[NT];
 #pragma unroll
             for (int t = 0; t < NT; ++t) gv[t] = gp[(long)t * Nx];
             shifted_solve<NT, SCHUR>(tm, sh, gv, a);
-            double* o = out + s * NT * Nx + m;
+            VT* o = out + s * NT * Nx + m;
 #pragma unroll
             for (int t = 0; t < NT; ++t) o[(long)t * Nx] = a[t];
             xe = a[NT - 1] + gamma * xe;          // group recurrence from x = 0
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
 #pragma unroll
         for (int i = 0; i < LR; ++i)
             if (sb + i < se) {
-                double* o = out + (sb + i) * NT * Nx + m;
+                VT* o = out + (sb + i) * NT * Nx + m;
                 double u[NT];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) u[t] = areg[i][t] + x * c[t];
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
         return;
     }
     for (long s = sb; s < se; ++s) {
-        double* o = out + s * NT * Nx + m;
+        VT* o = out + s * NT * Nx + m;
         double u[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) u[t] = o[(long)t * Nx] + x * c[t];
@@ -122,17 +122,24 @@ __global__ __launch_bounds__(256) void k_timemix_scan(int dim, TimeMix tm, const
 }
 
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, long nx,
-                          const double* in, double* out, long S, bool fwdsub, hipStream_t st, const int* guard) {
+                          const double* in, double* out, long S, bool fwdsub, hipStream_t st, const int* guard,
+                          int vt) {
     long Nx = nx > 0 ? nx : (long)n * n * (dim == 3 ? n : 1);
     long total = S * Nx;
     if (total <= 0) return hipSuccess;
     if (fwdsub && in == out) return hipErrorInvalidValue;
+    if (vt && !fwdsub) return hipErrorInvalidValue;       // float storage: the exact coarsest solve only
+    const float* inf = reinterpret_cast<const float*>(in);
+    float* outf = reinterpret_cast<float*>(out);
     dim3 grid((unsigned)((total + 255) / 256));
     dim3 gridm((unsigned)((Nx + 15) / 16));
 #define STH_TM_LAUNCH(NTV, SC)                                                                           \
-    if (fwdsub)                                                                                          \
-        hipLaunchKernelGGL((k_timemix_scan<NTV, SC>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, in,   \
-                           out, S, guard);                                                               \
+    if (fwdsub && vt)                                                                                    \
+        hipLaunchKernelGGL((k_timemix_scan<NTV, SC, float>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx,  \
+                           inf, outf, S, guard);                                                         \
+    else if (fwdsub)                                                                                     \
+        hipLaunchKernelGGL((k_timemix_scan<NTV, SC, double>), gridm, dim3(256), 0, st, dim, tm, mu1, n, Nx, \
+                           in, out, S, guard);                                                           \
     else                                                                                                 \
         hipLaunchKernelGGL((k_timemix<NTV, SC>), grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, in, out,    \
                            total, guard);
@@ -284,11 +291,11 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
 // time row of the previous slab (old and smoothed iterate) is carried in
 // registers along the chain; a chain after slab 0 first repeats the
 // smoothing step of its preceding slab for that row.
-template <int NT, bool SCHUR>
+template <int NT, bool SCHUR, typename VT>
 __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                        const double* __restrict__ mu1, int n, long Nx,
-                                                       const double* __restrict__ fh, const double* __restrict__ uin,
-                                                       double* __restrict__ uout, double* __restrict__ fc,
+                                                       const VT* __restrict__ fh, const VT* __restrict__ uin,
+                                                       VT* __restrict__ uout, VT* __restrict__ fc,
                                                        Transfer tr, double omega, int chain, long total,
                                                        const double* __restrict__ vw,
                                                        double* __restrict__ partial) {
@@ -401,13 +408,13 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 // delta A^{-1} e_1, so every slab needs one slab solve.  The coupling rows of
 // the previous slab (u1, u2, u3) are carried along the chain; a chain after
 // slab 0 first repeats the two steps of its two preceding slabs.
-template <int NT, bool SCHUR>
+template <int NT, bool SCHUR, typename VT>
 __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                          const double* __restrict__ mu1, int n, long Nx,
-                                                         const double* __restrict__ fh,
-                                                         const double* __restrict__ upre,
-                                                         const double* __restrict__ ec, double* __restrict__ uend,
-                                                         double* __restrict__ unext, double* __restrict__ fc,
+                                                         const VT* __restrict__ fh,
+                                                         const VT* __restrict__ upre,
+                                                         const VT* __restrict__ ec, VT* __restrict__ uend,
+                                                         VT* __restrict__ unext, VT* __restrict__ fc,
                                                          Transfer tr, double omega, int chain, long total,
                                                          const double* __restrict__ vw,
                                                          double* __restrict__ partial, const int* guard) {
@@ -589,11 +596,11 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 // coupling rows between groups, and the recurrence of the exact solve
 // (u_s = A^{-1} g_s + x_{s-1} A^{-1} e_1, x_s = a_s[N_t-1] + gamma x_{s-1}),
 // pass through LDS.  Only ua is written.
-template <int NT, bool SCHUR, int LAM>
+template <int NT, bool SCHUR, int LAM, typename VT>
 __global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_coarse_tail(int dim, const TimeMix* __restrict__ tma,
                                                          const TimeMix* __restrict__ tmb,
                                                          const double* __restrict__ mu1, int n, long Nx,
-                                                         const double* __restrict__ fa, double* __restrict__ ua,
+                                                         const VT* __restrict__ fa, VT* __restrict__ ua,
                                                          Transfer tr, double omega, int G, int LA,
                                                          const int* guard) {
     if (guard_off(guard)) return;
@@ -721,17 +728,103 @@ __global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_co
     }
 }
 
+// Post-smoothing step of a level whose pre-smoothing step started from zero
+// (u = omega A^{-1} f slab by slab, so A u = omega f), with the prolonged
+// coarse correction added first, for one spatial mode and a chain of
+// `chain` slabs (chain even, starting at an even slab).  With v = u +
+// (P_t (x) I) ec the residual of slab s is (1 - omega) f - A (P_t ec)_s +
+// e_1 q, q the last time row of v in slab s - 1, so the step needs neither f
+// nor a slab solve:
+//   u' = (2 - omega) u + (1 - omega) (P_t (x) I) ec + omega q A^{-1} e_1.
+// A chain after slab 0 reads the last row of u and the coarse correction of
+// the slab before it for q.  uin and uout must differ.
+template <int NT, bool SCHUR, typename VT>
+__global__ __launch_bounds__(256) void k_eig_post(int dim, TimeMix tm, const double* __restrict__ mu1, int n,
+                                                  long Nx, const VT* __restrict__ uin,
+                                                  const VT* __restrict__ ec, VT* __restrict__ uout,
+                                                  Transfer tr, double omega, int chain, long total,
+                                                  const int* guard) {
+    if (guard_off(guard)) return;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const long q = idx / Nx, m = idx % Nx;
+    const long s0 = q * chain;
+    const long slab = (long)NT * Nx;
+    // loads first: the chain's first slab and coarse correction, and the
+    // coupling row of the slab before it
+    double unx[NT], cnx[NT], c[NT], pc[NT];
+    double prev = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        unx[t] = uin[s0 * slab + m + (long)t * Nx];
+        cnx[t] = ec[(s0 / 2) * slab + m + (long)t * Nx];
+    }
+    if (s0 > 0) {
+        prev = uin[(s0 - 1) * slab + m + (long)(NT - 1) * Nx];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) pc[t] = ec[((s0 - 1) / 2) * slab + m + (long)t * Nx];
+    }
+    const double mu = mode_shift(dim, mu1, n, m);
+    double ca[NT];
+    {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(tm, mu, e1, ca);
+    }
+    double qv = 0.0;
+    if (s0 > 0) {
+        // slab s0 - 1 is the second half of its coarse slab
+        double v = prev;
+#pragma unroll
+        for (int k = 0; k < NT; ++k) v += tr.P[(NT + NT - 1) * kNt + k] * pc[k];
+        qv = v;
+    }
+#pragma unroll 1
+    for (int k = 0; k < chain; ++k) {
+        const int h = k & 1;
+        const long b = (s0 + k) * slab + m;
+        double u[NT], pu[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) u[t] = unx[t];
+        if (h == 0) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) c[t] = cnx[t];
+        }
+        if (k + 1 < chain) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) unx[t] = uin[b + slab + (long)t * Nx];
+            if (h == 1) {
+                const long bc = ((s0 + k + 1) / 2) * slab + m;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) cnx[t] = ec[bc + (long)t * Nx];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            double w = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < NT; ++kk) w += tr.P[(h * NT + t) * kNt + kk] * c[kk];
+            pu[t] = w;
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+            uout[b + (long)t * Nx] = (2.0 - omega) * u[t] + (1.0 - omega) * pu[t] + omega * qv * ca[t];
+        qv = u[NT - 1] + pu[NT - 1];
+    }
+}
+
 // Descent on a coarse level with a zero initial guess and one pre-smoothing
 // step, for one spatial mode and a chain of `chain` slabs (chain even,
 // starting at an even slab): u' = omega A^{-1} f (into uout) and the
 // restriction of its residual, fc = (P_t^T (x) I)[f - L u']_{2k, 2k+1}, from one
 // read of f.  The last time row of the previous slab's u' is carried along the
 // chain; a chain after slab 0 first repeats the step for its preceding slab.
-template <int NT, bool SCHUR>
+template <int NT, bool SCHUR, typename VT>
 __global__ __launch_bounds__(256) void k_eig_down(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                   const double* __restrict__ mu1, int n, long Nx,
-                                                  const double* __restrict__ fl, double* __restrict__ uout,
-                                                  double* __restrict__ fc, Transfer tr, double omega, int chain,
+                                                  const VT* __restrict__ fl, VT* __restrict__ uout,
+                                                  VT* __restrict__ fc, Transfer tr, double omega, int chain,
                                                   long total, const int* guard) {
     if (guard_off(guard)) return;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -859,8 +952,9 @@ hipError_t launch_eig_resid_restrict(int dim, int Nt, const Transfer& tr, const 
     return hipGetLastError();
 }
 #undef STH_NT_SWITCH
-hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
-                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
+template <typename VT>
+static hipError_t launch_eig_cycle_end_vt(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                const VT* fh, const VT* uin, VT* uout, VT* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
                                 long max_partial, double* out, double* out_host, hipStream_t st,
                                 const CycleFlag& flag) {
@@ -875,10 +969,10 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
 #define STH_CE_CASE(NTV)                                                                                     \
         case NTV:                                                                                             \
             if (tm.schur)                                                                                     \
-                hipLaunchKernelGGL((k_eig_cycle_end<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, \
+                hipLaunchKernelGGL((k_eig_cycle_end<NTV, true, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, \
                                    Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);              \
             else                                                                                              \
-                hipLaunchKernelGGL((k_eig_cycle_end<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,   \
+                hipLaunchKernelGGL((k_eig_cycle_end<NTV, false, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,   \
                                    n, Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);           \
             break;
         STH_CE_CASE(2) STH_CE_CASE(3) STH_CE_CASE(4) STH_CE_CASE(5) STH_CE_CASE(6) STH_CE_CASE(7) STH_CE_CASE(8)
@@ -888,9 +982,23 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
     return launch_sum_partials(partial, (int)blocks, out, out_host, 3, nullptr, flag, st);
 }
 
-hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
-                                  const double* fh, const double* upre, const double* ec, double* uend,
-                                  double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
+hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
+                                double omega, long S, int chain, const double* vw, double* partial,
+                                long max_partial, double* out, double* out_host, hipStream_t st,
+                                const CycleFlag& flag, int vt) {
+    if (vt)
+        return launch_eig_cycle_end_vt<float>(dim, Nt, tm, ktmt, mu1, n, (const float*)fh, (const float*)uin,
+                                              (float*)uout, (float*)fc, tr, omega, S, chain, vw, partial,
+                                              max_partial, out, out_host, st, flag);
+    return launch_eig_cycle_end_vt<double>(dim, Nt, tm, ktmt, mu1, n, fh, uin, uout, fc, tr, omega, S, chain, vw,
+                                           partial, max_partial, out, out_host, st, flag);
+}
+
+template <typename VT>
+static hipError_t launch_eig_cycle_close_vt(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                  const VT* fh, const VT* upre, const VT* ec, VT* uend,
+                                  VT* unext, VT* fc, const Transfer& tr, double omega, long S, int chain,
                                   const double* vw, double* partial, long max_partial, double* out,
                                   double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag,
                                   bool sums) {
@@ -906,11 +1014,11 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
 #define STH_CC_CASE(NTV)                                                                                     \
         case NTV:                                                                                             \
             if (tm.schur)                                                                                     \
-                hipLaunchKernelGGL((k_eig_cycle_close<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,  \
+                hipLaunchKernelGGL((k_eig_cycle_close<NTV, true, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,  \
                                    n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
                                    partial, guard);                                                           \
             else                                                                                              \
-                hipLaunchKernelGGL((k_eig_cycle_close<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, \
+                hipLaunchKernelGGL((k_eig_cycle_close<NTV, false, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, \
                                    n, Nx, fh, upre, ec, uend, unext, fc, tr, omega, chain, total, vw,         \
                                    partial, guard);                                                           \
             break;
@@ -920,6 +1028,21 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
     }
     if (!sums) return hipGetLastError();
     return launch_cycle_sums(dim, n, S, chain, partial, out, out_host, st, guard, flag);
+}
+
+hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                                  const double* fh, const double* upre, const double* ec, double* uend,
+                                  double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
+                                  const double* vw, double* partial, long max_partial, double* out,
+                                  double* out_host, hipStream_t st, const int* guard, const CycleFlag& flag,
+                                  bool sums, int vt) {
+    if (vt)
+        return launch_eig_cycle_close_vt<float>(dim, Nt, tm, ktmt, mu1, n, (const float*)fh, (const float*)upre,
+                                                (const float*)ec, (float*)uend, (float*)unext, (float*)fc, tr, omega,
+                                                S, chain, vw, partial, max_partial, out, out_host, st, guard, flag,
+                                                sums);
+    return launch_eig_cycle_close_vt<double>(dim, Nt, tm, ktmt, mu1, n, fh, upre, ec, uend, unext, fc, tr, omega, S,
+                                             chain, vw, partial, max_partial, out, out_host, st, guard, flag, sums);
 }
 
 hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial, double* out, double* out_host,
@@ -943,15 +1066,16 @@ bool coarse_tail_shape(int Nt, long SA, int* G, int* LA) {
     return true;
 }
 
-hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
-                                  const double* mu1, int n, const double* fa, double* ua,
+template <typename VT>
+static hipError_t launch_eig_coarse_tail_vt(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
+                                  const double* mu1, int n, const VT* fa, VT* ua,
                                   const Transfer& tr, double omega, long SA, hipStream_t st, const int* guard) {
     const long Nx = eig_modes(dim, n);
     int G = 0, LA = 0;
     if (!coarse_tail_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
     dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
 #define STH_CT_GO(NTV, SC, LAMV)                                                                              \
-    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV>), grid, block, 0, st, dim, tma_dev, tmb_dev, mu1, \
+    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV, VT>), grid, block, 0, st, dim, tma_dev, tmb_dev, mu1, \
                        n, Nx, fa, ua, tr, omega, G, LA, guard)
 #define STH_CT_LAM(NTV, SC)                                                                                  \
     if (LA <= 2) STH_CT_GO(NTV, SC, 2);                                                                      \
@@ -972,8 +1096,20 @@ hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const
     return hipGetLastError();
 }
 
-hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
-                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
+hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
+                                  const double* mu1, int n, const double* fa, double* ua,
+                                  const Transfer& tr, double omega, long SA, hipStream_t st, const int* guard,
+                                  int vt) {
+    if (vt)
+        return launch_eig_coarse_tail_vt<float>(dim, Nt, tma_dev, tmb_dev, schur, mu1, n, (const float*)fa,
+                                                (float*)ua, tr, omega, SA, st, guard);
+    return launch_eig_coarse_tail_vt<double>(dim, Nt, tma_dev, tmb_dev, schur, mu1, n, fa, ua, tr, omega, SA, st,
+                                             guard);
+}
+
+template <typename VT>
+static hipError_t launch_eig_down_vt(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                           const VT* fl, VT* uout, VT* fc, const Transfer& tr, double omega, long S,
                            int chain, hipStream_t st, const int* guard) {
     const long Nx = eig_modes(dim, n);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain) return hipErrorInvalidValue;
@@ -985,10 +1121,10 @@ hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktm
 #define STH_DN_CASE(NTV)                                                                                  \
         case NTV:                                                                                          \
             if (tm.schur)                                                                                  \
-                hipLaunchKernelGGL((k_eig_down<NTV, true>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, \
+                hipLaunchKernelGGL((k_eig_down<NTV, true, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, Nx, \
                                    fl, uout, fc, tr, omega, chain, total, guard);                          \
             else                                                                                           \
-                hipLaunchKernelGGL((k_eig_down<NTV, false>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n,    \
+                hipLaunchKernelGGL((k_eig_down<NTV, false, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n,    \
                                    Nx, fl, uout, fc, tr, omega, chain, total, guard);                      \
             break;
         STH_DN_CASE(2) STH_DN_CASE(3) STH_DN_CASE(4) STH_DN_CASE(5) STH_DN_CASE(6) STH_DN_CASE(7) STH_DN_CASE(8)
@@ -996,6 +1132,51 @@ hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktm
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
+                           const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
+                           int chain, hipStream_t st, const int* guard, int vt) {
+    if (vt)
+        return launch_eig_down_vt<float>(dim, Nt, tm, ktmt, mu1, n, (const float*)fl, (float*)uout, (float*)fc, tr,
+                                         omega, S, chain, st, guard);
+    return launch_eig_down_vt<double>(dim, Nt, tm, ktmt, mu1, n, fl, uout, fc, tr, omega, S, chain, st, guard);
+}
+
+template <typename VT>
+static hipError_t launch_eig_post_vt(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, const VT* uin,
+                           const VT* ec, VT* uout, const Transfer& tr, double omega, long S, int chain,
+                           hipStream_t st, const int* guard) {
+    const long Nx = eig_modes(dim, n);
+    if (chain < 2 || chain % 2 || S <= 0 || S % chain || uin == uout) return hipErrorInvalidValue;
+    const long total = (S / chain) * Nx;
+    const long blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    dim3 grid((unsigned)blocks);
+    switch (Nt) {
+#define STH_PO_CASE(NTV)                                                                                  \
+        case NTV:                                                                                          \
+            if (tm.schur)                                                                                  \
+                hipLaunchKernelGGL((k_eig_post<NTV, true, VT>), grid, dim3(256), 0, st, dim, tm, mu1, n, Nx, uin, \
+                                   ec, uout, tr, omega, chain, total, guard);                              \
+            else                                                                                           \
+                hipLaunchKernelGGL((k_eig_post<NTV, false, VT>), grid, dim3(256), 0, st, dim, tm, mu1, n, Nx,     \
+                                   uin, ec, uout, tr, omega, chain, total, guard);                         \
+            break;
+        STH_PO_CASE(2) STH_PO_CASE(3) STH_PO_CASE(4) STH_PO_CASE(5) STH_PO_CASE(6) STH_PO_CASE(7) STH_PO_CASE(8)
+#undef STH_PO_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_post(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, const double* uin,
+                           const double* ec, double* uout, const Transfer& tr, double omega, long S, int chain,
+                           hipStream_t st, const int* guard, int vt) {
+    if (vt)
+        return launch_eig_post_vt<float>(dim, Nt, tm, mu1, n, (const float*)uin, (const float*)ec, (float*)uout, tr,
+                                         omega, S, chain, st, guard);
+    return launch_eig_post_vt<double>(dim, Nt, tm, mu1, n, uin, ec, uout, tr, omega, S, chain, st, guard);
 }
 
 }  // namespace sth

@@ -197,17 +197,22 @@ __global__ void k_set_int(int* p, int value) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = value;
 }
 
-__global__ __launch_bounds__(256) void k_fill(double* v, long len, double val, const int* skip) {
+template <typename VT>
+__global__ __launch_bounds__(256) void k_fill(VT* v, long len, double val, const int* skip) {
     if (skip != nullptr && skip[0] != 0) return;
     long stride = (long)gridDim.x * 256;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) v[i] = val;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < len; i += stride) v[i] = (VT)val;
 }
 
-hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip) {
+hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip, int f32) {
     if (len <= 0) return hipSuccess;
     long blocks = (len + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, st, v, len, val, skip);
+    if (f32)
+        hipLaunchKernelGGL(k_fill<float>, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<float*>(v), len,
+                           val, skip);
+    else
+        hipLaunchKernelGGL(k_fill<double>, dim3((unsigned)blocks), dim3(256), 0, st, v, len, val, skip);
     return hipGetLastError();
 }
 

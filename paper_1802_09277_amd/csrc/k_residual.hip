@@ -350,11 +350,216 @@ static hipError_t residual2d_nt(int Nt, int n, const double* M1b, const double* 
     return hipErrorInvalidValue;
 }
 
+// 2-D residual for large images: one wave per (slab, range of columns of x,
+// range of YR rows of y), with no LDS and no barrier.  A wave's 64 lanes
+// hold 64 consecutive columns; the P lanes at either end only supply the
+// neighbours of the others (chunks of 64 - 2P output columns overlap by 2P).
+// The wave marches along y: for each input row and time row it applies M_1
+// and K_1 along x (neighbours by cross-lane reads), keeps the last 2P+1
+// results per time row in registers, and completes each output row with the
+// y pass and the temporal contraction.  The next input row is loaded while
+// the current one is processed.  With `partial` the block's sum of squares
+// of r goes to partial[blockIdx.x] (fixed order).
+template <int NT, int P>
+__global__ __launch_bounds__(256) void k_residual2d_march(int n, int nxc, int nyr, int YR, long nwaves,
+                                                          const double* __restrict__ M1b,
+                                                          const double* __restrict__ K1b,
+                                                          const double* __restrict__ ktmt,
+                                                          const double* __restrict__ f,
+                                                          const double* __restrict__ u, double* __restrict__ r,
+                                                          long s0, double sign, double* __restrict__ partial) {
+    constexpr int B = 2 * P + 1, NR = NT + 1;   // band width; time rows with the coupling row
+    constexpr int XS = 64 - 2 * P;              // output columns per wave
+    const int lane = threadIdx.x & 63;
+    const long w = (long)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double ssq = 0.0;
+    if (w < nwaves) {
+        const long per_slab = (long)nxc * nyr;
+        const long s = s0 + w / per_slab;
+        const int rem = (int)(w % per_slab);
+        const int x = (rem % nxc) * XS - P + lane;
+        const bool xin = x >= 0 && x < n;
+        const bool xout = xin && lane >= P && lane < 64 - P;
+        const int yb = (rem / nxc) * YR, ye = min(n, yb + YR);
+        const long Nx = (long)n * n, slab = NT * Nx;
+        const bool has_prev = s > 0;
+        double bm[B], bk[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+            bm[k] = xin ? M1b[(long)x * B + k] : 0.0;
+            bk[k] = xin ? K1b[(long)x * B + k] : 0.0;
+        }
+        // input row y of time row tr (tr = NT: the last time row of slab s - 1)
+        double v[NR];
+        auto load = [&](int y) {
+            const bool yin = y >= 0 && y < n;
+#pragma unroll
+            for (int tr = 0; tr < NR; ++tr) {
+                const bool ok = yin && xin && (tr < NT || has_prev);
+                const long base = tr < NT ? s * slab + (long)tr * Nx : (s - 1) * slab + (long)(NT - 1) * Nx;
+                v[tr] = ok ? u[base + (long)y * n + x] : 0.0;
+            }
+        };
+        double wa[NR][B], wb[NR][B];
+#pragma unroll
+        for (int tr = 0; tr < NR; ++tr)
+#pragma unroll
+            for (int k = 0; k < B; ++k) wa[tr][k] = wb[tr][k] = 0.0;
+        load(yb - P);
+#pragma unroll 1
+        for (int y = yb - P; y < ye + P; ++y) {
+            double cv[NR];
+#pragma unroll
+            for (int tr = 0; tr < NR; ++tr) cv[tr] = v[tr];
+            if (y + 1 < ye + P) load(y + 1);
+            // x pass of input row y for every time row, into the windows
+            // (lanes whose neighbours fall outside the wave are not output)
+#pragma unroll
+            for (int tr = 0; tr < NR; ++tr) {
+                double a = bm[P] * cv[tr], b = bk[P] * cv[tr];
+#pragma unroll
+                for (int d = 1; d <= P; ++d) {
+                    const double up = __shfl_down(cv[tr], d);    // column x + d
+                    const double dn = __shfl_up(cv[tr], d);      // column x - d
+                    a += bm[P + d] * up + bm[P - d] * dn;
+                    b += bk[P + d] * up + bk[P - d] * dn;
+                }
+#pragma unroll
+                for (int k = 0; k + 1 < B; ++k) {
+                    wa[tr][k] = wa[tr][k + 1];
+                    wb[tr][k] = wb[tr][k + 1];
+                }
+                wa[tr][B - 1] = a;
+                wb[tr][B - 1] = b;
+            }
+            // output row y - P: y pass and temporal contraction
+            const int yo = y - P;
+            if (yo >= yb) {
+                double cm[B], ck[B];
+#pragma unroll
+                for (int k = 0; k < B; ++k) {
+                    cm[k] = M1b[(long)yo * B + k];
+                    ck[k] = K1b[(long)yo * B + k];
+                }
+                double acc[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+#pragma unroll
+                for (int tr = 0; tr < NT; ++tr) {
+                    double Mu = 0.0, Ku = 0.0;
+#pragma unroll
+                    for (int k = 0; k < B; ++k) {
+                        Mu += cm[k] * wa[tr][k];
+                        Ku += ck[k] * wa[tr][k] + cm[k] * wb[tr][k];
+                    }
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[t] -= ktmt[t * kNt + tr] * Mu + ktmt[kNt * kNt + t * kNt + tr] * Ku;
+                }
+                double Mc = 0.0;                         // B_n u_{n-1}: M_x on the coupling row
+#pragma unroll
+                for (int k = 0; k < B; ++k) Mc += cm[k] * wa[NT][k];
+                acc[0] += Mc;
+                if (xout) {
+                    const long off = s * slab + (long)yo * n + x;
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) {
+                        const double val = (f ? f[off + (long)t * Nx] : 0.0) + sign * acc[t];
+                        r[off + (long)t * Nx] = val;
+                        ssq += val * val;
+                    }
+                }
+            }
+        }
+    }
+    if (partial) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) ssq += __shfl_xor(ssq, off);
+        __shared__ double red[4];
+        if (lane == 0) red[threadIdx.x >> 6] = ssq;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+// rows of y per wave of the marching kernel: the longest range that still
+// gives at least 8192 waves (halo rows: 2P per range)
+static int march_rows(int n, int p, long ns) {
+    const long nxc = (n + 63 - 2 * p) / (64 - 2 * p);
+    for (int yr : {128, 64, 32})
+        if (ns * nxc * ((n + yr - 1) / yr) >= 8192) return yr;
+    return 16;
+}
+
+template <int NT, int P>
+static hipError_t residual2d_march_launch(int n, const double* M1b, const double* K1b, const double* ktmt,
+                                          const double* f, const double* u, double* r, long s0, long ns, double sign,
+                                          double* partial, long* nblocks, hipStream_t st) {
+    const int nxc = (n + 63 - 2 * P) / (64 - 2 * P), YR = march_rows(n, P, ns), nyr = (n + YR - 1) / YR;
+    const long nwaves = ns * nxc * nyr, blocks = (nwaves + 3) / 4;
+    if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if (nblocks) *nblocks = blocks;
+    hipLaunchKernelGGL((k_residual2d_march<NT, P>), dim3((unsigned)blocks), dim3(256), 0, st, n, nxc, nyr, YR, nwaves,
+                       M1b, K1b, ktmt, f, u, r, s0, sign, partial);
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t residual2d_march_nt(int Nt, int n, const double* M1b, const double* K1b, const double* ktmt,
+                                      const double* f, const double* u, double* r, long s0, long ns, double sign,
+                                      double* partial, long* nblocks, hipStream_t st) {
+#define STH_RM_CASE(NTV)                                                                                    \
+    case NTV:                                                                                                \
+        if constexpr (2 * (NTV + 1) * (2 * P + 1) <= 64)                                                     \
+            return residual2d_march_launch<NTV, P>(n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, partial, nblocks, st); \
+        return hipErrorInvalidValue;
+    switch (Nt) {
+        STH_RM_CASE(2) STH_RM_CASE(3) STH_RM_CASE(4) STH_RM_CASE(5) STH_RM_CASE(6) STH_RM_CASE(7) STH_RM_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_RM_CASE
+}
+
+// the marching kernel serves 2-D images of 128 or more columns where its
+// windows (2 (N_t + 1)(2p + 1) doubles per lane) fit the registers
+static bool residual_marches(int dim, int n, int p, int Nt) {
+    return dim == 2 && n >= 128 && p >= 1 && p <= kMaxP && 2 * (Nt + 1) * (2 * p + 1) <= 64;
+}
+
+hipError_t launch_residual_norm(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
+                                const double* ktmt, const double* f, const double* u, double* r, long ns,
+                                double* partial, long max_partial, double* out, double* out_host, hipStream_t st) {
+    if (ns <= 0) return hipSuccess;
+    if (!residual_marches(dim, n, p, Nt)) return hipErrorInvalidValue;
+    const int nxc = (n + 63 - 2 * p) / (64 - 2 * p), YR = march_rows(n, p, ns), nyr = (n + YR - 1) / YR;
+    if ((ns * nxc * nyr + 3) / 4 > max_partial) return hipErrorInvalidValue;
+    long blocks = 0;
+    hipError_t e;
+    switch (p) {
+        case 1: e = residual2d_march_nt<1>(Nt, n, M1b, K1b, ktmt, f, u, r, 0, ns, 1.0, partial, &blocks, st); break;
+        case 2: e = residual2d_march_nt<2>(Nt, n, M1b, K1b, ktmt, f, u, r, 0, ns, 1.0, partial, &blocks, st); break;
+        case 3: e = residual2d_march_nt<3>(Nt, n, M1b, K1b, ktmt, f, u, r, 0, ns, 1.0, partial, &blocks, st); break;
+        default: e = residual2d_march_nt<4>(Nt, n, M1b, K1b, ktmt, f, u, r, 0, ns, 1.0, partial, &blocks, st); break;
+    }
+    if (e != hipSuccess) return e;
+    return launch_sum_partials(partial, (int)blocks, out, out_host, 1, nullptr, CycleFlag{}, st);
+}
+
+bool residual_norm_fused(int dim, int n, int p, int Nt) { return residual_marches(dim, n, p, Nt); }
+
 hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
                            const TimeOp& op, const double* ktmt, const double* f, const double* u, double* r,
                            long s0, long ns, double sign, hipStream_t st) {
     if (ns <= 0) return hipSuccess;
     if (p < 1 || p > kMaxP) return hipErrorInvalidValue;
+    if (residual_marches(dim, n, p, Nt)) {
+        switch (p) {
+            case 1: return residual2d_march_nt<1>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, nullptr, nullptr, st);
+            case 2: return residual2d_march_nt<2>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, nullptr, nullptr, st);
+            case 3: return residual2d_march_nt<3>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, nullptr, nullptr, st);
+            case 4: return residual2d_march_nt<4>(Nt, n, M1b, K1b, ktmt, f, u, r, s0, ns, sign, nullptr, nullptr, st);
+        }
+    }
     if (dim == 2) {
         int TXT = (n + 7) / 8 * 8, RT = TXT >= 256 ? 1 : 256 / TXT;
         int TY = RT * kRY, HY = TY + 2 * p;

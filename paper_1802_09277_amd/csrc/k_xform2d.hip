@@ -3,6 +3,8 @@
 // equ:ST:generalDecompA with fast diagonalisation of K_x + lambda M_x), in
 // FP64, FP32 and BF16x3 MFMA, and the exact B-spline residual norm of an
 // eigenbasis vector through the Gram matrix G = C^T C.
+#include <type_traits>
+
 #include "kernels_common.hpp"
 
 namespace sth {
@@ -16,8 +18,8 @@ namespace sth {
 // into the image buffer.  CT is the compute type: double (MFMA f64 16x16x4)
 // or float (MFMA f32 16x16x4, FP32 accumulation); global data stay FP64.
 // ---------------------------------------------------------------------------
-template <typename CT, int DIR, int NT16, int EPI, bool CORE>
-__global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, double* __restrict__ out,
+template <typename CT, int DIR, int NT16, int EPI, bool CORE, typename TI, typename TO>
+__global__ __launch_bounds__(512) void k_xform2d(const TI* __restrict__ in, TO* __restrict__ out,
                                                  const double* __restrict__ Upad, int n, long nimg,
                                                  double alpha, const int* guard, long ldi, long ldo) {
     if (guard_off(guard)) return;
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
     constexpr int PER = (NP * NP + 511) / 512;
     double pre[PER];
     auto load_img = [&](long img) {
-        const double* src = in + img * ldi;
+        const TI* src = in + img * ldi;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k, r = i / NP, c = i % NP;
@@ -82,7 +84,7 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         // an image of zeros (e.g. a zero initial guess) maps to zeros
         if (!__syncthreads_or(nz)) {
             if (EPI != 1) {
-                double* dst = out + img * ldo;
+                TO* dst = out + img * ldo;
                 for (long i = tid; i < nn; i += 512) dst[i] = 0.0;
             }
             continue;
@@ -153,9 +155,9 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
             }
         }
         if (CORE) e = xform2d_edge_sum(e, eg);
-        double* dst = out + img * ldo;
+        TO* dst = out + img * ldo;
         auto put = [&](int i, int j, double v) {
-            double* o = dst + (long)i * n + j;
+            TO* o = dst + (long)i * n + j;
             if (EPI == 0) *o = v;
             else if (EPI == 1) *o += alpha * v;
             else *o = alpha * v;
@@ -174,27 +176,27 @@ __global__ __launch_bounds__(512) void k_xform2d(const double* __restrict__ in, 
         if (edge && epart == 0) put(ei, ej, e);
     }
 }
-template <typename CT, int DIR, int NT16, int EPI, bool CORE>
-static hipError_t xform2d_go(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
+template <typename CT, int DIR, int NT16, int EPI, bool CORE, typename TI, typename TO>
+static hipError_t xform2d_go(const TI* in, TO* out, const double* Upad, int n, long nimg, double alpha,
                              hipStream_t st, long* nblocks, const int* guard, long ldi, long ldo) {
     size_t shm = sizeof(CT) * 2 * (size_t)TileLds<CT, NT16>::SIZE;
     static bool attr_set = false;
     if (!attr_set) {
         // exactly the dynamic size: the block-wide vote holds a little static LDS
-        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI, CORE>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI, CORE, TI, TO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     long blocks = persistent_blocks(shm, nimg);
     if (nblocks) *nblocks = blocks;
-    hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI, CORE>), dim3((unsigned)blocks), dim3(512), shm, st, in, out,
+    hipLaunchKernelGGL((k_xform2d<CT, DIR, NT16, EPI, CORE, TI, TO>), dim3((unsigned)blocks), dim3(512), shm, st, in, out,
                        Upad, n, nimg, alpha, guard, ldi, ldo);
     return hipGetLastError();
 }
 
-template <typename CT, int DIR, int NT16, int EPI>
-static hipError_t xform2d_launch(const double* in, double* out, const double* Upad, int n, long nimg, double alpha,
+template <typename CT, int DIR, int NT16, int EPI, typename TI, typename TO>
+static hipError_t xform2d_launch(const TI* in, TO* out, const double* Upad, int n, long nimg, double alpha,
                                  hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr,
                                  long ldi = 0, long ldo = 0) {
     if (n > 16 * NT16 || n <= 16 * (NT16 - 1)) return hipErrorInvalidValue;
@@ -203,37 +205,53 @@ static hipError_t xform2d_launch(const double* in, double* out, const double* Up
     if (ldi < (long)n * n || ldo < (long)n * n) return hipErrorInvalidValue;
     if constexpr (kXform2dEdge<NT16>) {
         if (xform2d_core_tiles<NT16>(n) < NT16)
-            return xform2d_go<CT, DIR, NT16, EPI, true>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+            return xform2d_go<CT, DIR, NT16, EPI, true, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
     }
-    return xform2d_go<CT, DIR, NT16, EPI, false>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+    return xform2d_go<CT, DIR, NT16, EPI, false, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
 }
 
-template <typename CT, int DIR, int EPI>
-static hipError_t xform2d_np(const double* in, double* out, const double* Upad, int n, int np, long nimg,
+template <typename CT, int DIR, int EPI, typename TI = double, typename TO = double>
+static hipError_t xform2d_np(const TI* in, TO* out, const double* Upad, int n, int np, long nimg,
                              double alpha, hipStream_t st, long* nblocks = nullptr, const int* guard = nullptr,
                              long ldi = 0, long ldo = 0) {
     switch (np / 16) {
-        case 1: return xform2d_launch<CT, DIR, 1, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
-        case 2: return xform2d_launch<CT, DIR, 2, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
-        case 3: return xform2d_launch<CT, DIR, 3, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
-        case 4: return xform2d_launch<CT, DIR, 4, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
-        case 5: return xform2d_launch<CT, DIR, 5, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
-        case 6: return xform2d_launch<CT, DIR, 6, EPI>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 1: return xform2d_launch<CT, DIR, 1, EPI, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 2: return xform2d_launch<CT, DIR, 2, EPI, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 3: return xform2d_launch<CT, DIR, 3, EPI, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 4: return xform2d_launch<CT, DIR, 4, EPI, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 5: return xform2d_launch<CT, DIR, 5, EPI, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
+        case 6: return xform2d_launch<CT, DIR, 6, EPI, TI, TO>(in, out, Upad, n, nimg, alpha, st, nblocks, guard, ldi, ldo);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename CT>
 static hipError_t xform2d_prec(int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
-                               long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
+                               long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo,
+                               int io_f32) {
+    if (io_f32) {
+        // FP32 eigenbasis vectors (FP32 transforms only): the forward
+        // transform writes them, the inverse reads them
+        if (!std::is_same<CT, float>::value) return hipErrorInvalidValue;
+        if (dir == 0 && io_f32 == 2)
+            return xform2d_np<CT, 0, 0, double, float>(in, (float*)out, Upad, n, np, nimg, 1.0, st, nullptr, guard,
+                                                       ldi, ldo);
+        if (dir == 1 && io_f32 == 1 && epi == 0)
+            return xform2d_np<CT, 1, 0, float, double>((const float*)in, out, Upad, n, np, nimg, alpha, st, nullptr,
+                                                       guard, ldi, ldo);
+        if (dir == 1 && io_f32 == 1 && epi == 1)
+            return xform2d_np<CT, 1, 1, float, double>((const float*)in, out, Upad, n, np, nimg, alpha, st, nullptr,
+                                                       guard, ldi, ldo);
+        return hipErrorInvalidValue;
+    }
     if (dir == 0) return xform2d_np<CT, 0, 0>(in, out, Upad, n, np, nimg, 1.0, st, nullptr, guard, ldi, ldo);
     if (epi == 0) return xform2d_np<CT, 1, 0>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard, ldi, ldo);
     if (epi == 1) return xform2d_np<CT, 1, 1>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard, ldi, ldo);
     if (epi == 2) return xform2d_np<CT, 1, 2>(in, out, Upad, n, np, nimg, alpha, st, nullptr, guard, ldi, ldo);
     return hipErrorInvalidValue;
 }
-template <int NT16, int EPI>
-__global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict__ in, double* __restrict__ out,
+template <int NT16, int EPI, typename TI, typename TO>
+__global__ __launch_bounds__(512) void k_xform2d_bf16x3(const TI* __restrict__ in, TO* __restrict__ out,
                                                         const double* __restrict__ Mpad, int n, long nimg,
                                                         double alpha, const int* guard, long ldi, long ldo) {
     if (guard_off(guard)) return;
@@ -254,7 +272,7 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
     constexpr int PER = (NP * NP + 511) / 512;
     double pre[PER];
     auto load_img = [&](long img) {
-        const double* src = in + img * ldi;
+        const TI* src = in + img * ldi;
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int i = tid + 512 * k, r = i / NP, c = i % NP;
@@ -275,7 +293,7 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
         // an image of zeros maps to zeros
         if (!__syncthreads_or(nz)) {
             if (EPI != 1) {
-                double* dst = out + img * ldo;
+                TO* dst = out + img * ldo;
                 for (long i = tid; i < nn; i += 512) dst[i] = 0.0;
             }
             continue;
@@ -332,7 +350,7 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
                 }
             }
         }
-        double* dst = out + img * ldo;
+        TO* dst = out + img * ldo;
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tq = wave + 8 * q;
@@ -344,7 +362,7 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
                     const int i = ti * 16 + 4 * lk + rr;
                     if (i < n && j < n) {
                         double v = (double)acc[q][rr];
-                        double* o = dst + (long)i * n + j;
+                        TO* o = dst + (long)i * n + j;
                         if (EPI == 0) *o = v;
                         else if (EPI == 1) *o += alpha * v;
                         else *o = alpha * v;
@@ -355,35 +373,35 @@ __global__ __launch_bounds__(512) void k_xform2d_bf16x3(const double* __restrict
     }
 }
 
-template <int NT16, int EPI>
-static hipError_t xform2d_bf16_launch(const double* in, double* out, const double* Mpad, int n, long nimg,
+template <int NT16, int EPI, typename TI, typename TO>
+static hipError_t xform2d_bf16_launch(const TI* in, TO* out, const double* Mpad, int n, long nimg,
                                       double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
     constexpr int NP = NT16 * 16;
     size_t shm = sizeof(unsigned short) * 4 * (size_t)NP * (NP + 8);
     static bool attr_set = false;
     if (!attr_set) {
         // exactly the dynamic size: the block-wide vote holds a little static LDS
-        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d_bf16x3<NT16, EPI>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform2d_bf16x3<NT16, EPI, TI, TO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     long blocks = persistent_blocks(shm, nimg);
-    hipLaunchKernelGGL((k_xform2d_bf16x3<NT16, EPI>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Mpad,
+    hipLaunchKernelGGL((k_xform2d_bf16x3<NT16, EPI, TI, TO>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Mpad,
                        n, nimg, alpha, guard, ldi, ldo);
     return hipGetLastError();
 }
 
-template <int EPI>
-static hipError_t xform2d_bf16_np(const double* in, double* out, const double* Mpad, int n, int np, long nimg,
+template <int EPI, typename TI = double, typename TO = double>
+static hipError_t xform2d_bf16_np(const TI* in, TO* out, const double* Mpad, int n, int np, long nimg,
                                   double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
     switch (np / 16) {
-        case 1: return xform2d_bf16_launch<1, EPI>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
-        case 2: return xform2d_bf16_launch<2, EPI>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
-        case 3: return xform2d_bf16_launch<3, EPI>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
-        case 4: return xform2d_bf16_launch<4, EPI>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
-        case 5: return xform2d_bf16_launch<5, EPI>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
-        case 6: return xform2d_bf16_launch<6, EPI>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
+        case 1: return xform2d_bf16_launch<1, EPI, TI, TO>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
+        case 2: return xform2d_bf16_launch<2, EPI, TI, TO>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
+        case 3: return xform2d_bf16_launch<3, EPI, TI, TO>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
+        case 4: return xform2d_bf16_launch<4, EPI, TI, TO>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
+        case 5: return xform2d_bf16_launch<5, EPI, TI, TO>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
+        case 6: return xform2d_bf16_launch<6, EPI, TI, TO>(in, out, Mpad, n, nimg, alpha, st, guard, ldi, ldo);
         default: return hipErrorInvalidValue;
     }
 }
@@ -559,21 +577,33 @@ hipError_t launch_gram_norm2d(const double* in, const double* Gpad, int n, int n
 }
 
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n,
-                          int np, long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
+                          int np, long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo,
+                          int io_f32) {
     if (nimg <= 0) return hipSuccess;
     if (!xform2d_supported(np)) return hipErrorInvalidValue;
-    if (prec == 0) return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard, ldi, ldo);
-    if (prec == 1) return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard, ldi, ldo);
+    if (prec == 0)
+        return xform2d_prec<double>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard, ldi, ldo, io_f32);
+    if (prec == 1)
+        return xform2d_prec<float>(dir, epi, in, out, Upad, n, np, nimg, alpha, st, guard, ldi, ldo, io_f32);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
-                                 long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
+                                 long nimg, double alpha, hipStream_t st, const int* guard, long ldi, long ldo,
+                                 int io_f32) {
     if (nimg <= 0) return hipSuccess;
     if (!xform2d_supported(np) || n > np || n <= np - 16) return hipErrorInvalidValue;
     if (ldi == 0) ldi = (long)n * n;
     if (ldo == 0) ldo = (long)n * n;
     if (ldi < (long)n * n || ldo < (long)n * n) return hipErrorInvalidValue;
+    if (io_f32 == 2 && epi == 0)             // forward transform into FP32 eigenbasis vectors
+        return xform2d_bf16_np<0, double, float>(in, (float*)out, Mpad, n, np, nimg, 1.0, st, guard, ldi, ldo);
+    if (io_f32 == 1 && epi == 0)             // inverse transform from FP32 eigenbasis vectors
+        return xform2d_bf16_np<0, float, double>((const float*)in, out, Mpad, n, np, nimg, 1.0, st, guard, ldi, ldo);
+    if (io_f32 == 1 && epi == 1)
+        return xform2d_bf16_np<1, float, double>((const float*)in, out, Mpad, n, np, nimg, alpha, st, guard, ldi,
+                                                 ldo);
+    if (io_f32) return hipErrorInvalidValue;
     if (epi == 0) return xform2d_bf16_np<0>(in, out, Mpad, n, np, nimg, 1.0, st, guard, ldi, ldo);
     if (epi == 1) return xform2d_bf16_np<1>(in, out, Mpad, n, np, nimg, alpha, st, guard, ldi, ldo);
     if (epi == 2) return xform2d_bf16_np<2>(in, out, Mpad, n, np, nimg, alpha, st, guard, ldi, ldo);

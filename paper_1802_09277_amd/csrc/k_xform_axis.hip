@@ -1,6 +1,8 @@
 // gfx950 kernels of the space-time slab solver: the spatial eigenbasis
 // transforms one axis at a time (3-D, and 2-D images too large for the
-// LDS-resident kernels) as MFMA GEMMs in FP64, FP32 and BF16x3.
+// LDS-resident kernels) as MFMA GEMMs in FP64, FP32 and BF16x3.  The
+// launchers take the panel kernels (transform matrix in LDS) for np <= 256;
+// the kernels here serve larger n.
 #include "kernels_common.hpp"
 
 namespace sth {
@@ -291,6 +293,7 @@ hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, cons
                           long lines, double alpha, hipStream_t st, const int* guard) {
     if (lines <= 0) return hipSuccess;
     if (epi < 0 || epi > 2 || prec < 0 || prec > 2) return hipErrorInvalidValue;
+    if (xform_panel_supported(np)) return launch_xform_panel_x(prec, epi, in, out, T, n, np, lines, alpha, st, guard);
     dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
     if (prec == 0) xform_x_ct<double>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
     else if (prec == 1) xform_x_ct<float>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
@@ -304,9 +307,12 @@ hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, cons
 }
 
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st, const int* guard) {
+                          long nbatch, long inner, hipStream_t st, const int* guard, int io_f32) {
     if (nbatch <= 0) return hipSuccess;
     if (prec < 0 || prec > 2) return hipErrorInvalidValue;
+    if (xform_panel_supported(np))
+        return launch_xform_panel_s(prec, in, out, T, n, np, nbatch, inner, st, guard, io_f32);
+    if (io_f32) return hipErrorInvalidValue;      // FP32 storage: the panel kernels only
     int nib = (int)((inner + 63) / 64), njb = (np + 63) / 64;
     long blocks = nbatch * nib * njb;
     if (blocks > 0x7fffffffL) return hipErrorInvalidValue;

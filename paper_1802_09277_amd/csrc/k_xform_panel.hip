@@ -1,0 +1,354 @@
+// gfx950 kernels of the space-time slab solver: the spatial eigenbasis
+// transforms one axis at a time (eq. equ:ST:generalDecompA with fast
+// diagonalisation of K_x + lambda M_x) for np <= 256 (a multiple of 32), as
+// MFMA GEMMs with the
+// transform matrix held in LDS and the data streamed through registers.
+//
+// A block stages one panel of PW output columns of the (padded) transform
+// matrix T, all of its rows, in LDS once; then each wave works on its own
+// 16-row tiles of the data with no further barrier.  A tile's data (16 rows
+// x np) goes through registers in groups of 64 k (four consecutive k per
+// lane and chunk of 16); the loads of the next group are in flight while the
+// current one is in the MFMAs.  Inside a chunk of 16, MFMA step s of lane
+// group g (lanes 16g..16g+15) takes k = 16c + 4g + s: every lane supplies
+// four consecutive k of its row, and the panel rows are read in the same
+// order, which leaves the sum over k unchanged.
+//
+//  x axis (contiguous): out[line][j] (EPI) sum_k in[line][k] T[k][j];
+//    MFMA A = data (rows = lines), B = panel (columns = j).
+//  strided axis: out[b][j][i] = sum_k T[k][j] in[b][k][i];
+//    MFMA A = panel^T (rows = j), B = data (columns = i), so that the
+//    results of a lane group are 16 consecutive i (coalesced stores).
+//
+// Blocks are persistent.  With P panels (np / PW), the P blocks that handle
+// the same data tiles have block ids b, b + 8, b + 16, ... so that they sit
+// on the same XCD (block ids go round-robin over the eight XCDs) and share
+// the data in its L2.
+#include <algorithm>
+#include <type_traits>
+
+#include "kernels_common.hpp"
+
+namespace sth {
+
+constexpr int kPanelThreads = 512;              // eight waves
+constexpr int kPanelWaves = kPanelThreads / 64;
+
+// compute types of the panel kernels
+struct PanelF64 {};
+struct PanelF32 {};
+struct PanelBf16x3 {};
+
+template <typename C> struct PanelTraits;
+template <> struct PanelTraits<PanelF64> { static constexpr int PW = 64; };
+template <> struct PanelTraits<PanelF32> { static constexpr int PW = 128; };
+template <> struct PanelTraits<PanelBf16x3> { static constexpr int PW = 128; };
+
+// LDS bytes of a panel of pw columns and kp rows
+template <typename C> static size_t panel_lds(int kp, int pw) {
+    if constexpr (std::is_same<C, PanelF64>::value) return sizeof(double) * (size_t)kp * pw;
+    else if constexpr (std::is_same<C, PanelF32>::value) return sizeof(float) * (size_t)kp * pw;
+    else return 2 * sizeof(unsigned short) * (size_t)pw * (kp + 4);
+}
+
+template <typename C, int PW, bool XAXIS, int EPI, typename TI, typename TO>
+__global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restrict__ in, TO* __restrict__ out,
+                                                               const double* __restrict__ T, int n, int np,
+                                                               int npanel, long nrows, long inner, long ntiles,
+                                                               double alpha, const int* guard) {
+    if (guard_off(guard)) return;
+    constexpr int pw = PW;                       // panel width (output columns)
+    constexpr int NJT = PW / 16;                 // column tiles per wave
+    constexpr bool F64 = std::is_same<C, PanelF64>::value;
+    constexpr bool BF = std::is_same<C, PanelBf16x3>::value;
+    const int ngroups = (np + 63) / 64;          // groups of four chunks of 16 k
+    const int KP = 64 * ngroups;                 // panel rows (k), zero from np on
+    extern __shared__ double sm_raw[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    // persistent block -> (panel, tile stream); see the file comment
+    const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
+    const int panel = q % npanel;
+    const long stream = (long)(q / npanel) * 8 + xcd;
+    const long nstream = (long)gridDim.x / npanel;
+    const int j0 = panel * pw;
+    // stage the panel: T[k][j0 + jj], k < KP (rows from np on are zero)
+    if constexpr (BF) {
+        unsigned short* th = reinterpret_cast<unsigned short*>(sm_raw);
+        unsigned short* tl = th + (size_t)pw * (KP + 4);
+        for (int i = tid; i < KP * pw; i += kPanelThreads) {
+            const int k = i / pw, jj = i % pw;
+            split_bf16(k < np ? T[(long)k * np + j0 + jj] : 0.0, &th[jj * (KP + 4) + k], &tl[jj * (KP + 4) + k]);
+        }
+    } else {
+        using CT = typename std::conditional<F64, double, float>::type;
+        CT* tp = reinterpret_cast<CT*>(sm_raw);
+        for (int i = tid; i < KP * pw; i += kPanelThreads) {
+            const int k = i / pw, jj = i % pw;
+            tp[k * pw + jj] = (CT)(k < np ? T[(long)k * np + j0 + jj] : 0.0);
+        }
+    }
+    __syncthreads();
+    // tiles: x axis, tile t = lines 16t..16t+15; strided axis, tile t =
+    // (batch t / itb, columns 16 (t % itb) .. +15) with itb = ceil(inner / 16)
+    const long itb = XAXIS ? 1 : (inner + 15) / 16;
+    for (long grp = stream;; grp += nstream) {
+        const long t = grp * kPanelWaves + wave;
+        if (t >= ntiles) break;
+        long rbase;                              // element (row lr, k) at in + rbase + lr * rs + k * ks
+        long rows_left;
+        long bbase = 0, i0 = 0;
+        if (XAXIS) {
+            rbase = t * 16 * (long)n;
+            rows_left = nrows - t * 16;
+        } else {
+            const long bt = t / itb;
+            i0 = (t % itb) * 16;
+            bbase = bt * (long)n * inner;
+            rbase = bbase + i0;
+            rows_left = inner - i0;
+        }
+        const long rs = XAXIS ? n : 1, ks = XAXIS ? 1 : inner;
+        const bool row_ok = lr < rows_left;
+        // lane (lr, lg) holds k = 64 gi + 16 c + 4 lg + e of row lr; the loads
+        // of group gi + 1 are in flight while group gi is in the MFMAs
+        auto load = [&](int gi, double (&a)[4][4]) {
+            const int kb = 64 * gi + 4 * lg;
+            const TI* p = in + rbase + lr * rs + (long)kb * ks;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    // (16 c + e) ks is the same for every lane
+                    a[c][e] = (row_ok && kb + 16 * c + e < n) ? p[(long)(16 * c + e) * ks] : 0.0;
+                }
+        };
+        double cur[4][4], nxt[4][4];
+        load(0, cur);
+        if constexpr (BF) {
+            const unsigned short* th = reinterpret_cast<const unsigned short*>(sm_raw);
+            const unsigned short* tl = th + (size_t)pw * (KP + 4);
+            f4 acc[NJT];
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt) acc[jt] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+            for (int gi = 0; gi < ngroups; ++gi) {
+                if (gi + 1 < ngroups) load(gi + 1, nxt);
+                int nz = 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) nz |= cur[c][e] != 0.0;
+                if (__any(nz)) {                 // a group of zeros adds nothing
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        s4 dh, dl;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            unsigned short hi, lo;
+                            split_bf16(cur[c][e], &hi, &lo);
+                            dh[e] = (short)hi;
+                            dl[e] = (short)lo;
+                        }
+#pragma unroll
+                        for (int jt = 0; jt < NJT; ++jt) {
+                            {
+                                const int o = (jt * 16 + lr) * (KP + 4) + 64 * gi + 16 * c + 4 * lg;
+                                const s4 bh = *reinterpret_cast<const s4*>(&th[o]);
+                                const s4 bl = *reinterpret_cast<const s4*>(&tl[o]);
+                                if (XAXIS) {
+                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, bh, acc[jt], 0, 0, 0);
+                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, bl, acc[jt], 0, 0, 0);
+                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dl, bh, acc[jt], 0, 0, 0);
+                                } else {
+                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, dh, acc[jt], 0, 0, 0);
+                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bl, dh, acc[jt], 0, 0, 0);
+                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, dl, acc[jt], 0, 0, 0);
+                                }
+                            }
+                        }
+                        // keep each chunk's operand reads with its MFMAs
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) cur[c][e] = nxt[c][e];
+            }
+            // D[4 lg + r][lr]: x axis (line, j), strided axis (j, i)
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = 4 * lg + r;
+                    if (XAXIS) {
+                        const int j = j0 + jt * 16 + lr;
+                        if (m < rows_left && j < n) {
+                            TO* o = out + (t * 16 + m) * (long)n + j;
+                            const double v = (double)acc[jt][r];
+                            if (EPI == 0) *o = v;
+                            else if (EPI == 1) *o += alpha * v;
+                            else *o = alpha * v;
+                        }
+                    } else {
+                        const int j = j0 + jt * 16 + m;
+                        if (j < n && lr < rows_left) out[bbase + (long)j * inner + i0 + lr] = (double)acc[jt][r];
+                    }
+                }
+            }
+        } else {
+            using CT = typename std::conditional<F64, double, float>::type;
+            using M = Mfma16<CT>;
+            typedef typename M::acc_t acc_t;
+            const CT* tp = reinterpret_cast<const CT*>(sm_raw);
+            acc_t acc[NJT];
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+#pragma unroll 1
+            for (int gi = 0; gi < ngroups; ++gi) {
+                if (gi + 1 < ngroups) load(gi + 1, nxt);
+                int nz = 0;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) nz |= cur[c][e] != 0.0;
+                if (__any(nz)) {                 // a group of zeros adds nothing
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) {
+                            const CT d = (CT)cur[c][s];
+                            const CT* row = tp + (64 * gi + 16 * c + 4 * lg + s) * pw + lr;
+#pragma unroll
+                            for (int jt = 0; jt < NJT; ++jt) {
+                                {
+                                    const CT w = row[jt * 16];
+                                    acc[jt] = XAXIS ? M::op(d, w, acc[jt]) : M::op(w, d, acc[jt]);
+                                }
+                            }
+                        }
+                        // keep each chunk's operand reads with its MFMAs
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) cur[c][e] = nxt[c][e];
+            }
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = M::row(lg, r);
+                    if (XAXIS) {
+                        const int j = j0 + jt * 16 + lr;
+                        if (m < rows_left && j < n) {
+                            TO* o = out + (t * 16 + m) * (long)n + j;
+                            const double v = (double)acc[jt][r];
+                            if (EPI == 0) *o = v;
+                            else if (EPI == 1) *o += alpha * v;
+                            else *o = alpha * v;
+                        }
+                    } else {
+                        const int j = j0 + jt * 16 + m;
+                        if (j < n && lr < rows_left) out[bbase + (long)j * inner + i0 + lr] = (double)acc[jt][r];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename C, int PW, bool XAXIS, int EPI, typename TI, typename TO>
+static hipError_t panel_go(const TI* in, TO* out, const double* T, int n, int np, long nrows, long inner,
+                           long ntiles, double alpha, hipStream_t st, const int* guard) {
+    const int npanel = np / PW;
+    if (npanel * PW != np) return hipErrorInvalidValue;
+    const size_t shm = panel_lds<C>(64 * ((np + 63) / 64), PW);
+    if (shm > 160 * 1024) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform_panel<C, PW, XAXIS, EPI, TI, TO>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const long fit = (long)((160 * 1024) / shm);
+    // 1, 2 or 4 blocks per compute unit (4 x 8 waves = 32 waves): a power of
+    // two, so that halving below keeps a multiple of 8 npanel blocks
+    const long per_cu = fit >= 4 ? 4 : (fit >= 2 ? 2 : 1);
+    // persistent blocks: a multiple of 8 npanel, no more than the tiles need
+    long blocks = 256 * per_cu;
+    const long need = ((ntiles + kPanelWaves - 1) / kPanelWaves) * npanel;
+    while (blocks > 8 * npanel && blocks / 2 >= need) blocks /= 2;
+    hipLaunchKernelGGL((k_xform_panel<C, PW, XAXIS, EPI, TI, TO>), dim3((unsigned)blocks), dim3(kPanelThreads), shm, st, in,
+                       out, T, n, np, npanel, nrows, inner, ntiles, alpha, guard);
+    return hipGetLastError();
+}
+
+// panel width: the widest of 128 (64 in FP64), 64, 32 that divides np
+template <typename C> static int panel_width(int np) {
+    for (int pw : {128, 64, 32})
+        if (pw <= PanelTraits<C>::PW && np % pw == 0) return pw;
+    return 0;
+}
+
+template <typename C, bool XAXIS, int EPI, typename TI = double, typename TO = double>
+static hipError_t panel_pw(const TI* in, TO* out, const double* T, int n, int np, long nrows, long inner,
+                           long ntiles, double alpha, hipStream_t st, const int* guard) {
+    switch (panel_width<C>(np)) {
+        case 32: return panel_go<C, 32, XAXIS, EPI, TI, TO>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        case 64: return panel_go<C, 64, XAXIS, EPI, TI, TO>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        case 128:
+            if constexpr (PanelTraits<C>::PW >= 128)
+                return panel_go<C, 128, XAXIS, EPI, TI, TO>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename C>
+static hipError_t panel_x_epi(int epi, const double* in, double* out, const double* T, int n, int np, long lines,
+                              double alpha, hipStream_t st, const int* guard) {
+    const long ntiles = (lines + 15) / 16;
+    if (epi == 0) return panel_pw<C, true, 0>(in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    if (epi == 1) return panel_pw<C, true, 1>(in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    return panel_pw<C, true, 2>(in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+}
+
+bool xform_panel_supported(int np) { return np >= 32 && np <= 256 && np % 32 == 0; }
+
+bool xform_panel_f32_io(int np) { return xform_panel_supported(np); }
+
+hipError_t launch_xform_panel_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
+                                long lines, double alpha, hipStream_t st, const int* guard) {
+    if (lines <= 0) return hipSuccess;
+    if (!xform_panel_supported(np) || epi < 0 || epi > 2) return hipErrorInvalidValue;
+    if (prec == 0) return panel_x_epi<PanelF64>(epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 1) return panel_x_epi<PanelF32>(epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 2) return panel_x_epi<PanelBf16x3>(epi, in, out, T, n, np, lines, alpha, st, guard);
+    return hipErrorInvalidValue;
+}
+
+template <typename C>
+static hipError_t panel_s_io(const double* in, double* out, const double* T, int n, int np, long inner, long ntiles,
+                             hipStream_t st, const int* guard, int io_f32) {
+    if (io_f32 == 2) return panel_pw<C, false, 0, double, float>(in, (float*)out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
+    if (io_f32 == 1) return panel_pw<C, false, 0, float, double>((const float*)in, out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
+    return panel_pw<C, false, 0>(in, out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
+}
+
+hipError_t launch_xform_panel_s(int prec, const double* in, double* out, const double* T, int n, int np, long nbatch,
+                                long inner, hipStream_t st, const int* guard, int io_f32) {
+    if (nbatch <= 0 || inner <= 0) return hipSuccess;
+    if (!xform_panel_supported(np) || io_f32 < 0 || io_f32 > 2) return hipErrorInvalidValue;
+    const long ntiles = nbatch * ((inner + 15) / 16);
+    if (prec == 0) return panel_s_io<PanelF64>(in, out, T, n, np, inner, ntiles, st, guard, io_f32);
+    if (prec == 1) return panel_s_io<PanelF32>(in, out, T, n, np, inner, ntiles, st, guard, io_f32);
+    if (prec == 2) return panel_s_io<PanelBf16x3>(in, out, T, n, np, inner, ntiles, st, guard, io_f32);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace sth

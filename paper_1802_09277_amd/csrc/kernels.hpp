@@ -62,6 +62,17 @@ hipError_t launch_residual(int dim, int Nt, int p, int n, const double* M1b, con
                            const TimeOp& op, const double* ktmt, const double* f, const double* u, double* r,
                            long s0, long ns, double sign, hipStream_t st);
 
+// The residual with its squared norm (2-D images of 128 or more columns and
+// small degrees: residual_norm_fused): r = f - L u over all ns slabs, and
+// sum r^2 to out[0]
+// (and out_host, mapped pinned host memory, if not null) in a fixed order;
+// partial needs as many entries as the residual kernel has blocks (at most
+// max_partial).
+bool residual_norm_fused(int dim, int n, int p, int Nt);
+hipError_t launch_residual_norm(int dim, int Nt, int p, int n, const double* M1b, const double* K1b,
+                                const double* ktmt, const double* f, const double* u, double* r, long ns,
+                                double* partial, long max_partial, double* out, double* out_host, hipStream_t st);
+
 // out[line][j] (EPI) sum_k in[line][k] T[k][j] for `lines` contiguous lines
 // of length n.  EPI 0: store, 1: out += alpha*acc, 2: out = alpha*acc.
 // prec (sth_prec): 0 MFMA f64, 1 MFMA f32 (FP32 accumulation), 2 BF16x3.
@@ -70,9 +81,12 @@ hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, cons
 
 // Strided axis: in[b][k][i] (k stride `inner`), out[b][j][i] = sum_k T[k][j] in[b][k][i].
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st, const int* guard = nullptr);
+                          long nbatch, long inner, hipStream_t st, const int* guard = nullptr, int io_f32 = 0);
 // (both per-axis launchers: every block returns at once when guard is given
-// and *guard == 0, as in the guards of speculative cycles)
+// and *guard == 0, as in the guards of speculative cycles; launch_xform_s
+// with io_f32 2 writes float output, 1 reads float input, for np <= 256 a
+// multiple of 32: xform_panel_f32_io(np))
+bool xform_panel_f32_io(int np);
 
 // Both spatial axes of 2-D images (n x n each, nimg images, image i at
 // in + i ldi and out + i ldo; 0: n^2) in one kernel:
@@ -86,9 +100,11 @@ bool xform2d_supported(int np);
 // transforms; the padded modes hold zeros (every eigenbasis kernel maps zero
 // data of a mode to zero).  The eigenbasis launchers use this count.
 long eig_modes(int dim, int n);
+// io_f32 (FP32 transforms only): 2 writes float output (out addresses float
+// data), 1 reads float input
 hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* out, const double* Upad, int n, int np,
                           long nimg, double alpha, hipStream_t st, const int* guard = nullptr, long ldi = 0,
-                          long ldo = 0);
+                          long ldo = 0, int io_f32 = 0);
 
 // BF16x3 form of the same: out = M (In M^T) per image with the products
 // accumulated in FP32 from hi*hi + hi*lo + lo*hi bf16 MFMA products; pass
@@ -96,7 +112,7 @@ hipError_t launch_xform2d(int prec, int dir, int epi, const double* in, double* 
 // Image strides ldi, ldo (0: n^2) and the guard as in launch_xform2d.
 hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const double* Mpad, int n, int np,
                                  long nimg, double alpha, hipStream_t st, const int* guard = nullptr, long ldi = 0,
-                                 long ldo = 0);
+                                 long ldo = 0, int io_f32 = 0);
 
 // Per slab and spatial mode (nx modes per time row; 0: n^d): out[:, m] = A_m^{-1} in[:, m], A_m^{-1} =
 // V (Z + mu_m I)^{-1} W (or the real Schur form of the level).  fwdsub:
@@ -105,10 +121,13 @@ hipError_t launch_xform2d_bf16x3(int epi, const double* in, double* out, const d
 // computed parallel in time (in and out must differ).
 hipError_t launch_timemix(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, long nx,
                           const double* in, double* out, long S, bool fwdsub, hipStream_t st,
-                          const int* guard = nullptr);
+                          const int* guard = nullptr, int vt = 0);
 
 // Iteration in the spatial eigenbasis (all pointwise over spatial modes;
-// ktmt = device K_t then M_t of the level):
+// ktmt = device K_t then M_t of the level).  The launchers with a `vt`
+// argument take eigenbasis vectors stored in FP64 (vt = 0) or FP32 (vt = 1:
+// the vector pointers then address float data); the arithmetic is FP64
+// either way:
 //  uout = v + omega A^{-1}(fh - L v) with v = uin (+ (P (x) I) ec when ec is
 //  not null: the prolonged coarse correction, S/2 coarse slabs); uin is not
 //  read when zero_guess (then ec must be null)
@@ -121,7 +140,15 @@ hipError_t launch_eig_smooth(int dim, int Nt, const TimeMix& tm, const double* k
 //  fc = (P^T (x) I)(fl - L uout) on slab pairs
 hipError_t launch_eig_down(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                            const double* fl, double* uout, double* fc, const Transfer& tr, double omega, long S,
-                           int chain, hipStream_t st, const int* guard = nullptr);
+                           int chain, hipStream_t st, const int* guard = nullptr, int vt = 0);
+//  post-smoothing step of a level whose pre-smoothing step started from zero
+//  (so A u = omega f slab by slab), with the prolonged coarse correction
+//  (S/2 coarse slabs) added first, in closed form without f or a slab solve:
+//  uout = (2 - omega) uin + (1 - omega)(P (x) I) ec + omega q A^{-1} e_1 (q the
+//  coupling row of the previous slab of uin + (P (x) I) ec); chains as above
+hipError_t launch_eig_post(int dim, int Nt, const TimeMix& tm, const double* mu1, int n, const double* uin,
+                           const double* ec, double* uout, const Transfer& tr, double omega, long S, int chain,
+                           hipStream_t st, const int* guard = nullptr, int vt = 0);
 //  end of a cycle on the finest level, in one pass over f^ and u^ (chains as
 //  above): ||fh - L uin||^2 and its lower and upper mode-weighted forms
 //  sum_m v_m |r_m|^2, sum_m w_m |r_m|^2 (weights from the per-axis table vw
@@ -134,7 +161,7 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
                                 long max_partial, double* out, double* out_host, hipStream_t st,
-                                const CycleFlag& flag = CycleFlag{});
+                                const CycleFlag& flag = CycleFlag{}, int vt = 0);
 //  close of a cycle on the finest level and start of the next in one pass
 //  (chains and sums as above): u1 = upre + (P_t (x) I) ec, uend = u1 +
 //  omega A^{-1}(fh - L u1) (the cycle's result), the three sums of
@@ -145,7 +172,7 @@ hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const doub
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,
                                   const double* vw, double* partial, long max_partial, double* out,
                                   double* out_host, hipStream_t st, const int* guard = nullptr,
-                                  const CycleFlag& flag = CycleFlag{}, bool sums = true);
+                                  const CycleFlag& flag = CycleFlag{}, bool sums = true, int vt = 0);
 //  the final sums of a cycle-close pass launched with sums = false (same S,
 //  chain, partial, outputs, guard and flag), as a separate launch
 hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial, double* out, double* out_host,
@@ -165,7 +192,7 @@ bool coarse_tail_shape(int Nt, long SA, int* G, int* LA);
 hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev, bool schur,
                                   const double* mu1, int n, const double* fa, double* ua,
                                   const Transfer& tr, double omega, long SA, hipStream_t st,
-                                  const int* guard = nullptr);
+                                  const int* guard = nullptr, int vt = 0);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);
@@ -191,8 +218,9 @@ hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* 
 hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u, long Sc,
                           long Nx, hipStream_t st);
 
-// v[0..len) = val, skipped when skip is given and *skip != 0
-hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip = nullptr);
+// v[0..len) = val, skipped when skip is given and *skip != 0 (f32: v
+// addresses float data)
+hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip = nullptr, int f32 = 0);
 // *flag = 1 if some entry of v[0..len) is not zero (NaN included), else 0
 hipError_t launch_any_nonzero(const double* v, long len, int* flag, hipStream_t st);
 

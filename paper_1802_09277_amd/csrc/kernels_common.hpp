@@ -358,4 +358,12 @@ __device__ __forceinline__ void prolong_add(const Transfer& tr, int h, const dou
 hipError_t launch_sum_partials(const double* partial, int count, double* out, double* out_host, int nsum,
                                const int* guard, const CycleFlag& flag, hipStream_t st);
 
+// Per-axis transforms with the transform matrix in LDS (np <= 256, a
+// multiple of 32), the same operations as launch_xform_x / launch_xform_s
+bool xform_panel_supported(int np);
+hipError_t launch_xform_panel_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
+                                long lines, double alpha, hipStream_t st, const int* guard);
+hipError_t launch_xform_panel_s(int prec, const double* in, double* out, const double* T, int n, int np, long nbatch,
+                                long inner, hipStream_t st, const int* guard, int io_f32 = 0);
+
 }  // namespace sth

@@ -88,6 +88,11 @@ struct sth_handle {
     const double* pending_ec = nullptr; // coarse correction waiting for the fused cycle close
     int pre_idx = 1;                    // level-0 buffer of the pre-smoothed iterate
     std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
+    // FP32 storage of the eigenbasis vectors (the inner solves of the mixed
+    // precision form): e0..e3 and the coarse-level eu, ef, eu2 hold floats
+    // (the pointers then address float data; arithmetic stays FP64)
+    bool f32 = false;
+    std::vector<double*> eu, ef, eu2;
     std::vector<int> ecur;              // which buffer of the pair holds u^ per level
     bool presmoothed = false;           // level-0 buffer pre_idx holds u^ after one smoothing step
                                         // and lf[1] the restriction of its residual
@@ -288,10 +293,10 @@ static int xform_x(sth_handle* h, int prec, int epi, const double* in, double* o
 }
 
 static int xform_s(sth_handle* h, int prec, const double* in, double* out, const double* T, long nbatch,
-                   long inner, hipStream_t st, const int* guard = nullptr) {
+                   long inner, hipStream_t st, const int* guard = nullptr, int io_f32 = 0) {
     double dof = (double)nbatch * h->n * inner;
-    Timed tm(h, STH_K_XFORM_S, 2.0 * h->n * dof, 16.0 * dof, st);
-    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st, guard));
+    Timed tm(h, STH_K_XFORM_S, 2.0 * h->n * dof, (io_f32 ? 12.0 : 16.0) * dof, st);
+    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st, guard, io_f32));
     return STH_OK;
 }
 
@@ -459,12 +464,14 @@ enum SpatialKind { FWD_U, INV_U, FWD_C, INV_C };
 // out = (A^T (x) ... (x) A^T) in (FWD) or (A (x) ... (x) A) in (INV) on every
 // time row of `rows` rows; A = U or C.  prec (sth_prec) is the arithmetic of
 // the transforms; epi 1 (inverse only) adds the result to out instead of
-// storing it.  in, out and tmp (a level-0 sized scratch vector, used by the
-// axis-by-axis path) must be distinct; the 3-D inverse with epi 1 also needs
-// a second scratch vector tmp2.
+// storing it; io_f32 2 (forward) writes out as float, 1 (inverse) reads in
+// as float (FP32 eigenbasis vectors).  in, out and tmp (a level-0 sized
+// scratch vector, used by the axis-by-axis path) must be distinct; the 3-D
+// inverse with epi 1 and the 3-D transforms with float data also need a
+// second scratch vector tmp2 (which may be `in` for a forward transform).
 static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, double* out, long rows, double* tmp,
                          hipStream_t st, const int* guard = nullptr, int prec = STH_FP64, int epi = 0,
-                         double* tmp2 = nullptr) {
+                         double* tmp2 = nullptr, int io_f32 = 0) {
     const bool fwd = (kind == FWD_U || kind == FWD_C);
     const double* A = (kind == FWD_U || kind == INV_U) ? h->Tf : h->Cf;     // A padded
     const double* At = (kind == FWD_U || kind == INV_U) ? h->Ti : h->Ci;    // A^T padded
@@ -472,6 +479,7 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     double dof = (double)rows * h->Nx;
     h->tlev = 0;
     if (epi != 0 && fwd) return fail(STH_EINVAL, "accumulating forward transform");
+    if (io_f32 && io_f32 != (fwd ? 2 : 1)) return fail(STH_EINVAL, "float data on the wrong side of a transform");
     if (h->dim == 2 && xform2d_supported(h->np)) {
         Timed tm(h, STH_K_XFORM_2D, 4.0 * n * dof, (epi ? 24.0 : 16.0) * dof, st);
         // eigenbasis rows are eig_modes long: the forward transform writes,
@@ -480,43 +488,53 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
         if (prec == STH_BF16X3)
             // out = M (In M^T) with M = A^T (forward) or A (inverse)
             HIPCHK(launch_xform2d_bf16x3(epi, in, out, fwd ? At : A, h->n, h->np, rows, 1.0, st, guard,
-                                         fwd ? 0 : ld, fwd ? ld : 0));
+                                         fwd ? 0 : ld, fwd ? ld : 0, io_f32));
         else
             HIPCHK(launch_xform2d(prec, fwd ? 0 : 1, epi, in, out, A, h->n, h->np, rows, 1.0, st, guard,
-                                  fwd ? 0 : ld, fwd ? ld : 0));
+                                  fwd ? 0 : ld, fwd ? ld : 0, io_f32));
         return STH_OK;
     }
-    // axis by axis, ping-ponging between the buffers; with accumulation the
-    // contiguous axis goes last, so that its epilogue adds into out
+    // axis by axis, ping-ponging between the buffers; with accumulation (or
+    // float input) the inverse takes the contiguous axis last, so that its
+    // epilogue adds into out; float data go through the strided axis only
     const double* T = fwd ? A : At;
     const int* g = guard;
     int rc;
     if (h->dim == 2) {
-        if (epi == 0) {
+        if (fwd || (epi == 0 && io_f32 == 0)) {
             if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n, 1.0, st, g))) return rc;
-            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st, g))) return rc;
+            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st, g, io_f32))) return rc;
         } else {
-            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st, g))) return rc;
+            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st, g, io_f32))) return rc;
             if ((rc = xform_x(h, prec, epi, tmp, out, T, rows * n, 1.0, st, g))) return rc;
         }
-    } else if (epi == 0) {
+    } else if (epi == 0 && io_f32 == 0) {
         if ((rc = xform_x(h, prec, 0, in, out, T, rows * n * n, 1.0, st, g))) return rc;   // x
         if ((rc = xform_s(h, prec, out, tmp, T, rows * n, n, st, g))) return rc;            // y
         if ((rc = xform_s(h, prec, tmp, out, T, rows, n * n, st, g))) return rc;            // z
-    } else {
-        if (!tmp2) return fail(STH_EINVAL, "accumulating 3-D transform without a second scratch vector");
-        if ((rc = xform_s(h, prec, in, tmp, T, rows, n * n, st, g))) return rc;             // z
+    } else if (fwd) {
+        if (!tmp2) return fail(STH_EINVAL, "3-D transform into float data without a second scratch vector");
+        if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n * n, 1.0, st, g))) return rc;   // x
         if ((rc = xform_s(h, prec, tmp, tmp2, T, rows * n, n, st, g))) return rc;           // y
-        if ((rc = xform_x(h, prec, epi, tmp2, out, T, rows * n * n, 1.0, st, g))) return rc;   // x, added
+        if ((rc = xform_s(h, prec, tmp2, out, T, rows, n * n, st, g, io_f32))) return rc;   // z, float out
+    } else {
+        if (!tmp2) return fail(STH_EINVAL, "3-D inverse transform without a second scratch vector");
+        if ((rc = xform_s(h, prec, in, tmp, T, rows, n * n, st, g, io_f32))) return rc;     // z
+        if ((rc = xform_s(h, prec, tmp, tmp2, T, rows * n, n, st, g))) return rc;           // y
+        if ((rc = xform_x(h, prec, epi, tmp2, out, T, rows * n * n, 1.0, st, g))) return rc;   // x
     }
     return STH_OK;
 }
 
 static double* eig_u(sth_handle* h, int lvl, int which) {
     if (lvl == 0) return which == 0 ? h->e1 : (which == 1 ? h->e2 : h->e3);
+    if (h->f32) return which ? h->eu2[lvl] : h->eu[lvl];
     return which ? h->lu2[lvl] : h->lu[lvl];
 }
-static double* eig_f(sth_handle* h, int lvl) { return lvl == 0 ? h->e0 : h->lf[lvl]; }
+static double* eig_f(sth_handle* h, int lvl) {
+    if (lvl == 0) return h->e0;
+    return h->f32 ? h->ef[lvl] : h->lf[lvl];
+}
 
 static const double* level_ktmt(sth_handle* h, int lvl) { return h->dktmt + (size_t)lvl * 2 * kNt * kNt; }
 
@@ -557,7 +575,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         double dof = (double)S * slab_len(h);
         Timed tm(h, STH_K_TIMEMIX, dof * (4.0 * h->Nt + 4.0), 16.0 * dof, st);
         HIPCHK(launch_timemix(h->dim, h->Nt, h->mixes[lvl], h->mu1, h->n, h->Nxe, eig_f(h, lvl),
-                              eig_u(h, lvl, h->ecur[lvl]), S, true, st, h->guard));
+                              eig_u(h, lvl, h->ecur[lvl]), S, true, st, h->guard, h->f32));
         return STH_OK;
     }
     int rc;
@@ -568,7 +586,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         Timed tm(h, STH_K_EIG_COARSE, dof * (10.0 * h->Nt + 11.0), 16.0 * dof, st);
         HIPCHK(launch_eig_coarse_tail(h->dim, h->Nt, h->dmix + lvl, h->dmix + lvl + 1, h->mixes[lvl].schur != 0,
                                       h->mu1, h->n, eig_f(h, lvl), eig_u(h, lvl, 0), h->tr,
-                                      h->omega, S, st, h->guard));
+                                      h->omega, S, st, h->guard, h->f32));
         h->ecur[lvl] = 0;
         return STH_OK;
     }
@@ -576,6 +594,7 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         HIPCHK(launch_fill(eig_u(h, lvl, h->ecur[lvl]), S * eslab_len(h), 0.0, st));
         zero_guess = false;
     }
+    bool from_zero = false;             // the pre-smoothing step started from zero (A u = omega f)
     if (lvl == 0 && h->presmoothed) {
         // the cycle-end pass of the previous cycle (or of the initial
         // residual) took the pre-smoothing step and restricted its residual
@@ -583,12 +602,13 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         h->presmoothed = false;
     } else if (zero_guess && h->nu_pre == 1) {
         // one pass: smoothing step from zero and restriction of its residual
+        from_zero = true;
         double dof = (double)S * slab_len(h);
         const int c = h->ecur[lvl];
         Timed tm(h, STH_K_EIG_SMOOTH, dof * (8.0 * h->Nt + 8.0), 20.0 * dof, st);
         HIPCHK(launch_eig_down(h->dim, h->Nt, h->mixes[lvl], level_ktmt(h, lvl), h->mu1, h->n, eig_f(h, lvl),
                                eig_u(h, lvl, 1 - c), eig_f(h, lvl + 1), h->tr, h->omega, S, chain_length(h, S, 262144), st,
-                               h->guard));
+                               h->guard, h->f32));
         h->ecur[lvl] = 1 - c;
     } else {
         for (int i = 0; i < h->nu_pre; ++i)
@@ -609,7 +629,19 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         return STH_OK;
     }
     if (h->nu_post == 0) return prolong_lvl(h, lvl, ec, eig_u(h, lvl, h->ecur[lvl]), st, h->Nxe);
-    for (int i = 0; i < h->nu_post; ++i)
+    int first = 0;
+    if (from_zero) {
+        // the first post-smoothing step in closed form (A u = omega f):
+        // reads u and the coarse correction only
+        double dof = (double)S * slab_len(h);
+        const int c = h->ecur[lvl];
+        Timed tm(h, STH_K_EIG_SMOOTH, dof * (4.0 * h->Nt + 4.0), 20.0 * dof, st);
+        HIPCHK(launch_eig_post(h->dim, h->Nt, h->mixes[lvl], h->mu1, h->n, eig_u(h, lvl, c), ec, eig_u(h, lvl, 1 - c),
+                               h->tr, h->omega, S, chain_length(h, S, 262144), st, h->guard, h->f32));
+        h->ecur[lvl] = 1 - c;
+        first = 1;
+    }
+    for (int i = first; i < h->nu_post; ++i)
         if ((rc = eig_smooth(h, lvl, false, st, i == 0 ? ec : nullptr))) return rc;
     return STH_OK;
 }
@@ -652,7 +684,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
                                           eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
                                           eig_f(h, 1), h->tr, h->omega, S, chain, h->vw, h->cpartial,
                                           h->n_cpartial, h->dnorm + slot_base(slot), h->hnorm_dev + slot_base(slot), st,
-                                          h->guard, flag, false));
+                                          h->guard, flag, false, h->f32));
         }
         HIPCHK(launch_cycle_sums(h->dim, h->n, S, chain, h->cpartial, h->dnorm + slot_base(slot),
                                  h->hnorm_dev + slot_base(slot), st, h->guard, flag));
@@ -677,7 +709,7 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, o), eig_f(h, 1), h->tr, h->omega, S,
                                     chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + at,
-                                    h->hnorm_dev + at, st, flag));
+                                    h->hnorm_dev + at, st, flag, h->f32));
         h->wsum_valid = true;
         h->last_slot = 0;
         h->pre_idx = o;
@@ -820,6 +852,15 @@ static bool fused_cycle_close(const Problem& q, size_t levels) {
     return q.basis == 1 && q.nu_pre == 1 && q.nu_post == 1 && levels > 1 && q.Nt() <= 5;
 }
 
+// Eigenbasis vectors in FP32 (arithmetic in FP64): the mixed precision form
+// (eigenbasis iteration, reduced-precision transforms) with the fused V(1,1)
+// passes and a transform path that reads and writes float data
+static bool f32_storage(const Problem& q, size_t levels) {
+    const int n = q.n(), np = (n + 15) / 16 * 16;
+    return q.basis == 1 && q.prec != STH_FP64 && fused_cycle_close(q, levels) &&
+           ((q.dim == 2 && xform2d_supported(np)) || xform_panel_f32_io(np));
+}
+
 int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     if (!p || !bytes) return fail(STH_EINVAL, "null argument");
     Problem q = to_problem(p);
@@ -832,10 +873,13 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     size_t total = 0;
     total += 2 * sizeof(double) * np * np;                   // transforms
     total += sizeof(double) * n * (1 + 2 * (2 * q.degree + 1));
-    const size_t vecs0 = (q.basis == 1 ? 5 : 2) +            // buf0, buf1 (+ f^, u^ pair
-                         (fused_cycle_close(q, level_count(q)) ? 1 : 0);   // and a third u^)
-    const size_t vecsl = q.basis == 1 ? 3 : 2;               // u, f (+ u^ partner) per coarse level
-    total += vecs0 * sizeof(double) * (size_t)q.n_slabs * slab;
+    const bool f32 = f32_storage(q, level_count(q));
+    const size_t evecs0 = q.basis == 1 ? 3 + (fused_cycle_close(q, level_count(q)) ? 1 : 0) : 0;   // f^, u^ (x2 or 3)
+    total += 2 * sizeof(double) * (size_t)q.n_slabs * slab;                            // buf0, buf1
+    total += evecs0 * (f32 ? sizeof(float) : sizeof(double)) * (size_t)q.n_slabs * slab;
+    // per coarse level: u, f (nodal), and the eigenbasis u^, its partner and
+    // f^ (the u, f pair shared unless the eigenbasis vectors are float)
+    const size_t vecsl_bytes = 2 * sizeof(double) + (q.basis == 1 ? (f32 ? 3 * sizeof(float) : sizeof(double)) : 0);
     if (q.basis == 1) {
         total += 3 * sizeof(double) * np * np;                // C, C^T, G
         total += sizeof(double) * (2 * (((size_t)(q.n_slabs / 2) * (size_t)(Nx) + 255) / 256) + 1);   // cycle-end partials
@@ -845,7 +889,7 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     size_t L = level_count(q);
     for (size_t l = 1; l < L; ++l) {
         S /= 2;
-        total += vecsl * sizeof(double) * (size_t)S * slab;
+        total += vecsl_bytes * (size_t)S * slab;
     }
     total += sizeof(double) * (kNormBlocks + kNormSlots + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
     *bytes = total;
@@ -901,6 +945,7 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->nb_lo = std::pow(h->S.m1_min, h->dim);
     h->nb_hi = std::pow(h->S.m1_max, h->dim);
     h->fuse_close = fused_cycle_close(q, (size_t)h->L);
+    h->f32 = f32_storage(q, (size_t)h->L);
     {
         int G = 0, LA = 0;
         h->fuse_tail = h->basis == 1 && h->nu_pre == 1 && h->nu_post == 1 && h->L >= 3 &&
@@ -993,11 +1038,22 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     h->lf.assign(h->L, nullptr);
     h->lu2.assign(h->L, nullptr);
     h->ecur.assign(h->L, 0);
+    // doubles that hold `count` eigenbasis values (floats with FP32 storage)
+    auto ecount = [&](size_t count) { return h->f32 ? (count + 1) / 2 : count; };
+    const size_t ebytes = h->f32 ? sizeof(float) : sizeof(double);
+    h->eu.assign(h->L, nullptr);
+    h->ef.assign(h->L, nullptr);
+    h->eu2.assign(h->L, nullptr);
     for (int l = 1; l < h->L; ++l) {
         if (!dalloc(&h->lu[l], (size_t)h->lev_S[l] * slab) || !dalloc(&h->lf[l], (size_t)h->lev_S[l] * slab))
             return cleanup(STH_ENOMEM, "device allocation failed");
-        if (h->basis == 1 && !dalloc(&h->lu2[l], (size_t)h->lev_S[l] * slab))
+        if (h->basis == 1 && !h->f32 && !dalloc(&h->lu2[l], (size_t)h->lev_S[l] * slab))
             return cleanup(STH_ENOMEM, "device allocation failed");
+        if (h->f32) {
+            const size_t c = ecount((size_t)h->lev_S[l] * slab);
+            if (!dalloc(&h->eu[l], c) || !dalloc(&h->ef[l], c) || !dalloc(&h->eu2[l], c))
+                return cleanup(STH_ENOMEM, "device allocation failed");
+        }
     }
     if (hipMalloc((void**)&h->dmix, sizeof(TimeMix) * h->mixes.size()) != hipSuccess)
         return cleanup(STH_ENOMEM, "device allocation failed");
@@ -1019,18 +1075,22 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         h->n_cpartial = 3 * (((q.n_slabs / 2) * h->Nxe + 255) / 256);   // three sums per block
         if (!dalloc(&h->cpartial, (size_t)h->n_cpartial) ||
             !dalloc(&h->Cf, (size_t)np * np) || !dalloc(&h->Ci, (size_t)np * np) ||
-            !dalloc(&h->e0, (size_t)q.n_slabs * eslab) || !dalloc(&h->e1, (size_t)q.n_slabs * eslab) ||
-            !dalloc(&h->e2, (size_t)q.n_slabs * eslab) ||
-            (h->fuse_close && !dalloc(&h->e3, (size_t)q.n_slabs * eslab)))
+            !dalloc(&h->e0, ecount((size_t)q.n_slabs * eslab)) || !dalloc(&h->e1, ecount((size_t)q.n_slabs * eslab)) ||
+            !dalloc(&h->e2, ecount((size_t)q.n_slabs * eslab)) ||
+            (h->fuse_close && !dalloc(&h->e3, ecount((size_t)q.n_slabs * eslab))))
             return cleanup(STH_ENOMEM, "device allocation failed");
         // the padded modes of the eigenbasis vectors start (and stay) zero
         for (double* v : {h->e0, h->e1, h->e2, h->e3})
-            if (v && hipMemsetAsync(v, 0, sizeof(double) * (size_t)q.n_slabs * eslab, s) != hipSuccess)
+            if (v && hipMemsetAsync(v, 0, ebytes * (size_t)q.n_slabs * eslab, s) != hipSuccess)
                 return cleanup(STH_EHIP, "clearing the eigenbasis vectors failed");
-        for (int l = 1; l < h->L; ++l)
+        for (int l = 1; l < h->L; ++l) {
             for (double* v : {h->lu[l], h->lf[l], h->lu2[l]})
                 if (v && hipMemsetAsync(v, 0, sizeof(double) * (size_t)h->lev_S[l] * slab, s) != hipSuccess)
                     return cleanup(STH_EHIP, "clearing the eigenbasis vectors failed");
+            for (double* v : {h->eu[l], h->ef[l], h->eu2[l]})
+                if (v && hipMemsetAsync(v, 0, ebytes * (size_t)h->lev_S[l] * slab, s) != hipSuccess)
+                    return cleanup(STH_EHIP, "clearing the eigenbasis vectors failed");
+        }
         // mode weights of the lower bound of the B-spline residual norm
         const std::vector<double> vwh = residual_mode_weights(h->S);
         if (!dalloc(&h->vw, (size_t)2 * n))
@@ -1348,10 +1408,13 @@ static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rt
         // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
         const long rows = h->lev_S[0] * h->Nt;
         h->ecur[0] = 0;
-        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st, nullptr, v.tprec))) return rc;
+        // (FP32 eigenbasis vectors: only in inner solves, whose f is buf1)
+        if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st, nullptr, v.tprec, 0,
+                                h->f32 ? h->buf1 : nullptr, h->f32 ? 2 : 0)))
+            return rc;
         h->tlev = 0;
         if (v.inner) {
-            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st));     // zero initial guess
+            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nullptr, h->f32));   // zero guess
         } else {
             // an initial guess of zeros (the usual start) needs no transform:
             // a device flag says whether u has a nonzero entry; the transform
@@ -1359,7 +1422,7 @@ static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rt
             int* nz = h->dgo + 4;
             HIPCHK(launch_any_nonzero(u, len, nz, st));
             if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st, nz))) return rc;
-            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nz));
+            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nz, h->f32));
         }
         // (with graph replay, whose captured cycles have fixed guards, the
         // first cycle waits for the initial norms instead)
@@ -1465,7 +1528,7 @@ static int solve_finish(sth_handle* h, bool* more) {
     h->wait_slot = -1;
     // u = (I (x) U_x) u^ (an inner solve adds it to u)
     return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st, nullptr,
-                         v.tprec, v.inner ? 1 : 0, h->buf1);
+                         v.tprec, v.inner ? 1 : 0, h->buf1, h->f32 ? 1 : 0);
 }
 
 // Lower bound of the B-spline residual norm of the cycle whose sums are in
@@ -1746,14 +1809,23 @@ static int mixed_residual(sth_handle* h) {
     auto& m = h->mx;
     const long S = h->lev_S[0];
     const long len = S * slab_len(h);
-    int rc = residual(h, 0, m.f, m.u, h->buf1, 0, S, 1.0, m.st);
-    if (rc) return rc;
     h->tlev = 0;
-    {
-        Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, m.st);
-        HIPCHK(launch_norm2(h->buf1, len, h->partial, h->dnorm + kMixR, m.st));
+    if (residual_norm_fused(h->dim, h->n, h->p, h->Nt)) {
+        // the residual kernel sums the squares of its output itself
+        const double dof = (double)len;
+        Timed tm(h, STH_K_RESIDUAL, dof * (10.0 * (2 * h->p + 1) + 4.0 * h->Nt + 4.0), dof * 24.0, m.st);
+        HIPCHK(launch_residual_norm(h->dim, h->Nt, h->p, h->n, h->M1b, h->K1b, level_ktmt(h, 0), m.f, m.u, h->buf1,
+                                    S, h->cpartial, h->n_cpartial, h->dnorm + kMixR, h->hnorm_dev + kMixR, m.st));
+    } else {
+        int rc = residual(h, 0, m.f, m.u, h->buf1, 0, S, 1.0, m.st);
+        if (rc) return rc;
+        h->tlev = 0;
+        {
+            Timed tm(h, STH_K_NORM, 2.0 * len, 8.0 * len, m.st);
+            HIPCHK(launch_norm2(h->buf1, len, h->partial, h->dnorm + kMixR, m.st));
+        }
+        HIPCHK(hipMemcpyAsync(h->hnorm + kMixR, h->dnorm + kMixR, sizeof(double), hipMemcpyDeviceToHost, m.st));
     }
-    HIPCHK(hipMemcpyAsync(h->hnorm + kMixR, h->dnorm + kMixR, sizeof(double), hipMemcpyDeviceToHost, m.st));
     h->wait_ev = nullptr;                 // the caller waits for the stream
     h->wait_slot = -1;
     m.phase = 0;
@@ -1931,11 +2003,13 @@ static int precondition(sth_handle* h, const double* v, double* z, hipStream_t s
     int rc;
     // (transforms in the handle's precision: FGMRES is flexible, so a
     // reduced-precision preconditioner leaves its residual test exact)
-    if ((rc = spatial_apply(h, FWD_U, v, h->e0, rows, h->buf0, st, nullptr, h->prec))) return rc;
+    if ((rc = spatial_apply(h, FWD_U, v, h->e0, rows, h->buf0, st, nullptr, h->prec, 0, h->buf1, h->f32 ? 2 : 0)))
+        return rc;
     h->ecur[0] = 0;
     h->presmoothed = false;
     if ((rc = eig_vcycle(h, 0, true, st))) return rc;
-    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), z, rows, h->buf0, st, nullptr, h->prec);
+    return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), z, rows, h->buf0, st, nullptr, h->prec, 0, h->buf1,
+                         h->f32 ? 1 : 0);
 }
 
 static int krylov_workspace(sth_handle* h, int m) {
@@ -2082,7 +2156,7 @@ int sth_destroy(sth_handle* h) {
                       h->kpart, h->vw};
     for (double* q : ptrs)
         if (q) (void)hipFree(q);
-    for (auto* vec : {&h->lu, &h->lf, &h->lu2})
+    for (auto* vec : {&h->lu, &h->lf, &h->lu2, &h->eu, &h->ef, &h->eu2})
         for (double* q : *vec)
             if (q) (void)hipFree(q);
     if (h->hnorm) (void)hipHostFree(h->hnorm);

@@ -191,6 +191,9 @@ _FP64_RESULT = {}
 @pytest.mark.parametrize("name,basis,prec", [
     ("C3", "eigen", "fp64"), ("C3", "nodal", "fp64"), ("C3", "nodal", "fp32"), ("C3", "nodal", "bf16x3"),
     ("C4", "eigen", "fp64"), ("C4", "nodal", "fp64"), ("C4", "nodal", "fp32"), ("C4", "nodal", "bf16x3"),
+    # the FP64 defect correction around inner eigenbasis solves (eigenbasis
+    # vectors in FP32 on both workloads)
+    ("C3", "eigen", "fp32"), ("C3", "eigen", "bf16x3"), ("C4", "eigen", "fp32"), ("C4", "eigen", "bf16x3"),
 ])
 def test_fullsize_large_workloads(name, basis, prec):
     cfg = W.CONFIGS[name]

@@ -40,6 +40,9 @@ SHAPES = {
     "2d_5lev": dict(dim=2, n_elem=10, degree=2, n_slabs=32, n_elem_t=1, coarse_slabs=2),
     # five levels in 3-D down to a single slab (16 -> 8 -> 4 -> 2 -> 1)
     "3d_5lev": dict(dim=3, n_elem=6, degree=2, n_slabs=16, n_elem_t=2, coarse_slabs=1),
+    # n = 113 (np = 128): the per-axis transforms with the transform matrix in
+    # LDS (two 64-column panels in FP64), a ragged last tile of k and rows
+    "2d_n113_panel": dict(dim=2, n_elem=113, degree=2, n_slabs=2, n_elem_t=1, coarse_slabs=1),
 }
 
 
@@ -491,4 +494,37 @@ def test_deep_wide_shape_cycles(temporal):
     err = rel_max(host(u)[idx], data[:, 5])
     print(f"  solve: {it} cycles, relres {rr:.2e}, sampled max rel error vs direct {err:.2e}")
     assert rr <= 1e-12 and err <= 1e-10
+    s.close()
+
+
+# ---------------------------------------------------------------------------
+# The residual kernel of large 2-D images (n >= 128: one wave per column
+# range and row range, marching along y; overlapping column chunks) on
+# ragged shapes, element-wise against the oracle's assembled L_h.
+# ---------------------------------------------------------------------------
+MARCH_SHAPES = {
+    "2d_n128_p1": dict(dim=2, n_elem=129, degree=1, n_slabs=3, n_elem_t=2),
+    "2d_n130_p2": dict(dim=2, n_elem=130, degree=2, n_slabs=3, n_elem_t=2),
+    "2d_n181_p3": dict(dim=2, n_elem=180, degree=3, n_slabs=2, n_elem_t=1),
+}
+
+
+@pytest.mark.parametrize("name", list(MARCH_SHAPES))
+def test_residual_large_images(name):
+    import paper_1802_09277_amd as sth
+    from oracle.solve import SlabSystem
+    shape = MARCH_SHAPES[name]
+    print(f"[gpu-parity] large-image residual shape={name} {shape}", flush=True)
+    prob = OProblem(**shape)
+    sysm = SlabSystem.assemble(prob)
+    s = sth.Solver(**shape)
+    u = W.random_vector(40, prob.n_dof)
+    f = W.random_vector(41, prob.n_dof)
+    y = s.new_vector()
+    s.apply(dev(u), y)
+    ref = sysm.apply(u)
+    assert rel_max(host(y), ref) <= 1e-12
+    r = s.new_vector()
+    s.residual(dev(f), dev(u), r)
+    assert rel_max(host(r), f - ref) <= 1e-12
     s.close()

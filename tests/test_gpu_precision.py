@@ -18,11 +18,18 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 # the LDS-resident 2-D transform (n <= 96), the per-axis transforms of a
-# large 2-D image (n = 100) and of a 3-D problem
+# large 2-D image (n = 100, np = 112: the kernels that stage both operands),
+# of a 3-D problem and of n = 113 (np = 128: the transform matrix in LDS)
 SHAPES = {
     "2d_fused": (dict(dim=2, n_elem=30, degree=3, n_slabs=16, n_elem_t=2), 4),
     "2d_axiswise": (dict(dim=2, n_elem=100, degree=2, n_slabs=4, n_elem_t=2), 2),
     "3d": (dict(dim=3, n_elem=10, degree=2, n_slabs=8, n_elem_t=2), 2),
+    # n = 113 (np = 128): the per-axis transforms with the matrix in LDS
+    "2d_panel": (dict(dim=2, n_elem=113, degree=2, n_slabs=4, n_elem_t=1), 2),
+    # three time basis functions per slab (the fused V(1,1) passes): the
+    # eigenbasis vectors of the mixed form are stored in FP32 (here through
+    # the LDS-resident 2-D transform; "2d_panel" through the per-axis panels)
+    "2d_fused_f32": (dict(dim=2, n_elem=40, degree=2, n_slabs=8, n_elem_t=1), 2),
 }
 
 
