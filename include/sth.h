@@ -337,7 +337,8 @@ int sth_timing_report(sth_handle* h, int kclass, int* launches, double* ms,
  * f and u) fits into hbm_budget_bytes together with every cached setup;
  * idle cached setups are evicted, least recently used first, to make room.
  * Admitted requests run concurrently: each solve is driven one V-cycle at a
- * time (graph replays on its own stream), so a request that arrives while
+ * time (individual launches on its own stream, each cycle enqueued behind
+ * the device flag of the cycle before it), so a request that arrives while
  * others run starts as soon as it is admitted.  The result is copied into
  * the caller's device buffer u_out (sth_problem_vector_len elements, valid
  * until the request finishes); the kernels are deterministic, so a result

@@ -3,6 +3,8 @@
 //   + M_t (x) K_x, B_n = N_t (x) M_x with N_t = e_1 e_{N_t}^T, eq. structureAn)
 // by sum factorisation: banded 1-D passes of M_1/K_1, then the dense
 // N_t x N_t contraction in registers.
+#include <atomic>
+
 #include "kernels_common.hpp"
 
 namespace sth {
@@ -313,15 +315,15 @@ static hipError_t residual2d_launch(int n, const double* M1b, const double* K1b,
     int RT = TXT >= 256 ? 1 : 256 / TXT;
     int TY = RT * kRY, HY = TY + 2 * P;
     size_t shm = sizeof(double) * ((size_t)HY * (n + 2 * P) + 2 * (size_t)HY * n + 2 * (size_t)TY * (2 * P + 1));
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::atomic<bool> attr_set{false};       // set once; the attribute call is idempotent
+    if (!attr_set.load(std::memory_order_acquire)) {
         hipError_t e = hipFuncSetAttribute((const void*)k_residual2d<NT, P, kRY + 2 * P>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)k_residual2d<NT, P, kRY + P>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.store(true, std::memory_order_release);
     }
     dim3 grid((unsigned)((n + TY - 1) / TY), (unsigned)ns);
     if (RT == 1)

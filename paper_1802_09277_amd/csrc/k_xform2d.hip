@@ -3,6 +3,7 @@
 // equ:ST:generalDecompA with fast diagonalisation of K_x + lambda M_x), in
 // FP64, FP32 and BF16x3 MFMA, and the exact B-spline residual norm of an
 // eigenbasis vector through the Gram matrix G = C^T C.
+#include <atomic>
 #include <type_traits>
 
 #include "kernels_common.hpp"
@@ -180,13 +181,13 @@ template <typename CT, int DIR, int NT16, int EPI, bool CORE, typename TI, typen
 static hipError_t xform2d_go(const TI* in, TO* out, const double* Upad, int n, long nimg, double alpha,
                              hipStream_t st, long* nblocks, const int* guard, long ldi, long ldo) {
     size_t shm = sizeof(CT) * 2 * (size_t)TileLds<CT, NT16>::SIZE;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::atomic<bool> attr_set{false};       // set once; the attribute call is idempotent
+    if (!attr_set.load(std::memory_order_acquire)) {
         // exactly the dynamic size: the block-wide vote holds a little static LDS
         hipError_t e = hipFuncSetAttribute((const void*)k_xform2d<CT, DIR, NT16, EPI, CORE, TI, TO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.store(true, std::memory_order_release);
     }
     long blocks = persistent_blocks(shm, nimg);
     if (nblocks) *nblocks = blocks;
@@ -378,13 +379,13 @@ static hipError_t xform2d_bf16_launch(const TI* in, TO* out, const double* Mpad,
                                       double alpha, hipStream_t st, const int* guard, long ldi, long ldo) {
     constexpr int NP = NT16 * 16;
     size_t shm = sizeof(unsigned short) * 4 * (size_t)NP * (NP + 8);
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::atomic<bool> attr_set{false};       // set once; the attribute call is idempotent
+    if (!attr_set.load(std::memory_order_acquire)) {
         // exactly the dynamic size: the block-wide vote holds a little static LDS
         hipError_t e = hipFuncSetAttribute((const void*)k_xform2d_bf16x3<NT16, EPI, TI, TO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.store(true, std::memory_order_release);
     }
     long blocks = persistent_blocks(shm, nimg);
     hipLaunchKernelGGL((k_xform2d_bf16x3<NT16, EPI, TI, TO>), dim3((unsigned)blocks), dim3(512), shm, st, in, out, Mpad,
@@ -532,12 +533,12 @@ static hipError_t gram_norm2d_go(const double* in, const double* Gpad, int n, lo
                                  int max_blocks, double* out, double* out_host, hipStream_t st,
                                  const CycleFlag& flag, long ldi) {
     const size_t shm = sizeof(double) * 2 * (size_t)TileLds<double, NT16>::SIZE;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::atomic<bool> attr_set{false};       // set once; the attribute call is idempotent
+    if (!attr_set.load(std::memory_order_acquire)) {
         hipError_t e = hipFuncSetAttribute((const void*)k_gram_norm2d<NT16, CORE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.store(true, std::memory_order_release);
     }
     const long blocks = persistent_blocks(shm, nimg);
     if (blocks > max_blocks) return hipErrorInvalidValue;

@@ -25,6 +25,7 @@
 // on the same XCD (block ids go round-robin over the eight XCDs) and share
 // the data in its L2.
 #include <algorithm>
+#include <atomic>
 #include <type_traits>
 
 #include "kernels_common.hpp"
@@ -268,12 +269,12 @@ static hipError_t panel_go(const TI* in, TO* out, const double* T, int n, int np
     if (npanel * PW != np) return hipErrorInvalidValue;
     const size_t shm = panel_lds<C>(64 * ((np + 63) / 64), PW);
     if (shm > 160 * 1024) return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static std::atomic<bool> attr_set{false};       // set once; the attribute call is idempotent
+    if (!attr_set.load(std::memory_order_acquire)) {
         hipError_t e = hipFuncSetAttribute((const void*)k_xform_panel<C, PW, XAXIS, EPI, TI, TO>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set.store(true, std::memory_order_release);
     }
     const long fit = (long)((160 * 1024) / shm);
     // 1, 2 or 4 blocks per compute unit (4 x 8 waves = 32 waves): a power of

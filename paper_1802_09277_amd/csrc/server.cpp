@@ -6,7 +6,8 @@
 // problem shape (sth_setup), the right-hand side (sth_load_rhs) and the
 // release of evicted setups.  The scheduler thread admits requests and
 // drives every admitted solve one V-cycle at a time on the request's own
-// stream (graph replays), polling one event per request, so the solves of
+// stream (individual launches, speculative cycles guarded by device flags),
+// polling one event per request, so the solves of
 // different requests overlap on the device and a request that arrives while
 // others run starts as soon as a stream and memory are free.  Admission is
 // first come, first served, by device footprint against a fixed budget;
@@ -48,8 +49,8 @@ std::string problem_key(const sth_problem& p) {
     return buf;
 }
 
-// a cached setup with its own right-hand side and iterate (so that the
-// captured iteration graph stays valid across requests)
+// a cached setup with its own right-hand side and iterate (the request's
+// result is copied out of u when its solve ends)
 struct Entry {
     std::string key;
     sth_handle* h = nullptr;
@@ -114,7 +115,7 @@ struct sth_server {
     bool stop = false;
     std::mutex mu;                                  // everything above
     std::condition_variable cv_sched, cv_setup, cv_done;
-    std::mutex alloc_mu;                            // device (de)allocation vs graph capture
+    std::mutex alloc_mu;                            // device (de)allocation vs graph capture (handles with graphs on)
     hipStream_t setup_st = nullptr;
     std::thread sched, setup;
 };

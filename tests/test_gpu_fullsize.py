@@ -1,7 +1,7 @@
 """Full-size parity for the benchmark workload (unit square, p = 3, 64 x 64
 elements, 256 slabs x 2 time elements, 8 random modes seed 2; 5,408,000
 unknowns), in the launch configuration bench.py times (non-default stream,
-graph replay of the solve iterations, default coarsest level).
+individual launches with speculative cycles, default coarsest level).
 
 Checked against oracle values sampled at 4000 seeded indices
 (tests/golden/c2_direct_samples.txt, written by make_fullsize_samples.py
