@@ -98,6 +98,20 @@ typedef struct {
                            M_t^{-1} K_t = Q R Q^T (orthogonal Q, a block back
                            substitution per spatial mode); 2 diagonalisation
                            unless cond(V) > 1e6, then real Schur (default) */
+    double space_ratio; /* coarsening in space (Section 4.4, the multigrid
+                           coarsens in space as well as in time): 0 (default)
+                           time only; > 0 a level transition also halves the
+                           spatial elements per axis when the level's
+                           tau / h_x^2 >= space_ratio (h_x = 1 / n_elem) and
+                           its element count is even and at least 4 (the
+                           ratio halves on such a step and doubles on a time
+                           step; 2 keeps the cycle counts of time-only
+                           coarsening).  The prolongation in space is the
+                           embedding of the coarse spline space (knot
+                           insertion), the coarse operators the Galerkin
+                           ones, i.e. the rediscretisations on the coarse
+                           mesh with the finest sigma.  Requires
+                           iterate_basis 0 (STH_EINVAL otherwise). */
 } sth_problem;
 
 /* Right-hand side as a sum of separable modes (host arrays):
@@ -142,8 +156,12 @@ size_t sth_vector_len(const sth_handle* h);
 /* The same for a problem description, without a setup (0 if invalid). */
 size_t sth_problem_vector_len(const sth_problem* p);
 
-/* Number of multigrid levels (1 + number of time coarsenings). */
+/* Number of multigrid levels (1 + number of coarsenings). */
 int sth_num_levels(const sth_handle* h);
+
+/* Spatial elements per axis on a multigrid level (0 for a bad level):
+ * n_elem halved once per space-time coarsening step above it. */
+int sth_level_elems(const sth_handle* h, int level);
 
 /* f <- load vector of the given modes (host 1-D quadrature, device outer
  * products). */
@@ -243,8 +261,11 @@ int sth_speculate(sth_handle* h, int enable);
 
 /* Level transfers (Section 3.1, time coarsening by combining two slabs):
  * rc <- (P_t^T (x) I) r on slab pairs of `level` (rc has the slab count of
- * level+1), and u <- u + (P_t (x) I) ec.  Vectors of a coarse level have
- * sth_level_len(h, level) elements. */
+ * level+1), and u <- u + (P_t (x) I) ec; where the transition below `level`
+ * coarsens in space too, I is replaced by P_x (x) .. (x) P_x (P_x^T in the
+ * restriction; see space_ratio), and neither vector may be one of the
+ * handle's own workspaces.  Vectors of a level have sth_level_len(h, level)
+ * elements. */
 int sth_restrict(sth_handle* h, int level, const double* r, double* rc, void* stream);
 int sth_prolong_add(sth_handle* h, int level, const double* ec, double* u, void* stream);
 size_t sth_level_len(const sth_handle* h, int level);
@@ -292,6 +313,12 @@ int sth_host_factors(const sth_problem* p, int level, sth_factors* out);
  * (n, interior functions). */
 int sth_host_load_1d(const sth_problem* p, double omega, double phase, int k,
                      double* time_part, double* space_part);
+
+/* The prolongation of the interior spatial functions from a mesh of
+ * n_elem_c elements on (0,1) to the mesh of 2 n_elem_c elements (degree p,
+ * Boehm knot insertion of every element midpoint): out is row-major
+ * (n_f x n_c), n_f = 2 n_elem_c + p - 2, n_c = n_elem_c + p - 2. */
+int sth_host_space_prolongation(int n_elem_c, int degree, double* out);
 
 /* ---- kernel timing (measurement support) ----------------------------- */
 

@@ -20,6 +20,19 @@ readings used (and listed as such in the design notes):
   * D^{-1} is applied exactly by sparse LU (the paper's "Direct" variant).
 The residual norm is the Euclidean norm of the coefficient vector, relative
 to ||f|| (zero initial guess), stopping at 1e-8 as in Section 4.4.
+
+Coarsening in space (Section 4.4 states that the multigrid coarsens in
+space as well as in time, again without the details): a level transition
+either coarsens in time only (two slabs into one) or in space and time
+together (also halving the spatial elements per axis).  The reading used
+follows the space-time multigrid of the paper's reference on block Jacobi
+smoothing (Gander and Neumueller): space and time are coarsened together
+when the discrete parabolic ratio lambda = tau / h_x^2 of the level is at
+least a critical value, in time only otherwise.  A space-time step halves
+lambda, a time step doubles it.  The spatial prolongation P_x is the exact
+embedding of the coarse spline space into the fine one (an L2 projection,
+exact because the spaces are nested), on the interior functions; the
+space-time prolongation of a coupled step is P_t (x) P_x (x) ... (x) P_x.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -52,6 +65,49 @@ def time_prolongation(tau, n_el, p):
     return np.vstack(blocks)
 
 
+def space_prolongation(n_elem_c, p):
+    """P_x (n_f x n_c) on the interior functions: coarse mesh of n_elem_c
+    elements on (0, 1) -> fine mesh of 2 n_elem_c elements, degree p.
+    Column j holds the fine coefficients of coarse function j, found by
+    solving M_f c = (fine, coarse) with Gauss quadrature on the fine
+    elements (exact: coarse functions are polynomials there).  Coarse
+    interior functions vanish on the boundary, so their first and last fine
+    coefficients are zero and the interior block is the whole map."""
+    q = p + 2
+    coarse = bs.open_uniform_knots(0.0, 1.0, n_elem_c, p)
+    ax = Axis(0.0, 1.0, 2 * n_elem_c, p, q)
+    N = ax.N
+    Mf = np.zeros((N, N))
+    rhs = np.zeros((N, bs.n_basis(coarse, p)))
+    for e in range(ax.n_el):
+        g = ax.gidx[e]
+        Mf[np.ix_(g, g)] += np.einsum("q,qi,qj->ij", ax.W[e], ax.V[e], ax.V[e])
+        cvals = bs.basis_all(coarse, p, ax.X[e], 0)
+        rhs[g] += np.einsum("q,qi,qj->ij", ax.W[e], ax.V[e], cvals)
+    P = np.linalg.solve(Mf, rhs)
+    return P[1:-1, 1:-1]
+
+
+def coarsening_schedule(prob, coarse_slabs=1, lam_crit=None, min_elem=2):
+    """Kinds of the level transitions from the finest level down: "t" (time
+    only) or "xt" (space and time).  Without lam_crit, time only.  A level
+    is coarsened while its slab count is even and above coarse_slabs; in
+    space too when tau_l / h_l^2 >= lam_crit and its element count halves
+    to at least min_elem."""
+    kinds = []
+    S, ne, tau = prob.n_slabs, prob.n_elem, prob.tau
+    while S > coarse_slabs and S % 2 == 0:
+        lam = tau * ne * ne
+        if lam_crit is not None and lam >= lam_crit and ne % 2 == 0 and ne // 2 >= min_elem:
+            kinds.append("xt")
+            ne //= 2
+        else:
+            kinds.append("t")
+        S //= 2
+        tau *= 2
+    return kinds
+
+
 class Level:
     def __init__(self, system):
         self.sys = system
@@ -62,18 +118,30 @@ class Level:
 
 
 class MultigridOracle:
-    def __init__(self, prob, nu1=1, nu2=1, omega=0.5, system=None, coarse_slabs=1):
+    def __init__(self, prob, nu1=1, nu2=1, omega=0.5, system=None, coarse_slabs=1, lam_crit=None,
+                 min_elem=2):
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
         fine = system if system is not None else SlabSystem.assemble(prob)
         self.levels = [fine]
         self.P = []
+        self.kinds = coarsening_schedule(prob, coarse_slabs, lam_crit, min_elem)
+        self.n_elem = [prob.n_elem]
         tau = prob.tau
-        Nx = prob.N_x
-        while self.levels[-1].S > coarse_slabs and self.levels[-1].S % 2 == 0:
+        ne = prob.n_elem
+        for kind in self.kinds:
             lev = self.levels[-1]
             Pt = time_prolongation(tau, prob.n_elem_t, prob.degree)
-            P = sp.kron(sp.csr_matrix(Pt), sp.identity(Nx), format="csr")
+            n_f = ne + prob.degree - 2
+            if kind == "xt":
+                ne //= 2
+                Px = space_prolongation(ne, prob.degree)
+                Pxd = np.ones((1, 1))
+                for _ in range(prob.dim):
+                    Pxd = np.kron(Pxd, Px)
+                P = sp.kron(sp.csr_matrix(Pt), sp.csr_matrix(Pxd), format="csr")
+            else:
+                P = sp.kron(sp.csr_matrix(Pt), sp.identity(n_f ** prob.dim), format="csr")
             A, B = lev.A, lev.B
             Z = sp.csr_matrix(A.shape)
             Lpair = sp.bmat([[A, Z], [-B, A]], format="csr")
@@ -82,6 +150,7 @@ class MultigridOracle:
             Bc = (P.T @ Epair @ P).tocsr()
             self.levels.append(SlabSystem(Ac, Bc, lev.S // 2))
             self.P.append(P)
+            self.n_elem.append(ne)
             tau *= 2
 
     # grid transfers --------------------------------------------------

@@ -34,7 +34,7 @@ class Problem(ctypes.Structure):
                 ("n_slabs", ctypes.c_int), ("n_elem_t", ctypes.c_int), ("T", ctypes.c_double),
                 ("theta", ctypes.c_double), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int), ("coarse_slabs", ctypes.c_int),
-                ("iterate_basis", ctypes.c_int), ("temporal_form", ctypes.c_int)]
+                ("iterate_basis", ctypes.c_int), ("temporal_form", ctypes.c_int), ("space_ratio", ctypes.c_double)]
 
 
 class RhsModes(ctypes.Structure):
@@ -81,6 +81,7 @@ def load_library():
         "sth_vector_len": (sz, [vp]),
         "sth_num_levels": (i, [vp]),
         "sth_level_len": (sz, [vp, i]),
+        "sth_level_elems": (i, [vp, i]),
         "sth_load_rhs": (i, [vp, P(RhsModes), vp, vp]),
         "sth_load_rhs_noalloc": (i, [vp, P(RhsModes), vp, vp]),
         "sth_apply": (i, [vp, vp, vp, vp]),
@@ -97,6 +98,7 @@ def load_library():
         "sth_last_error": (ctypes.c_char_p, []),
         "sth_host_factors": (i, [P(Problem), i, P(Factors)]),
         "sth_host_load_1d": (i, [P(Problem), d, d, i, _DP, _DP]),
+        "sth_host_space_prolongation": (i, [i, i, _DP]),
         "sth_timing": (i, [vp, ctypes.c_uint]),
         "sth_timing_level": (i, [vp, i]),
         "sth_use_graphs": (i, [vp, i]),
@@ -131,7 +133,7 @@ TEMPORAL = {"eigen": 0, "schur": 1, "auto": 2}
 
 
 def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto"):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", space_ratio=0.0):
     p = Problem()
     load_library().sth_problem_default(ctypes.byref(p))
     p.dim, p.n_elem, p.degree, p.n_slabs, p.n_elem_t = dim, n_elem, degree, n_slabs, n_elem_t
@@ -141,6 +143,7 @@ def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omeg
         p.coarse_slabs = int(coarse_slabs)
     p.iterate_basis = BASIS[basis] if isinstance(basis, str) else int(basis)
     p.temporal_form = TEMPORAL[temporal] if isinstance(temporal, str) else int(temporal)
+    p.space_ratio = float(space_ratio)
     return p
 
 
@@ -168,6 +171,15 @@ def host_factors(level=0, **kw):
     buf["n_levels"] = f.n_levels
     buf["schur"] = bool(f.schur)
     return buf
+
+
+def host_space_prolongation(n_elem_c, degree):
+    """The library's P_x (n_f x n_c) from n_elem_c to 2 n_elem_c elements."""
+    import numpy as np
+    nf, nc = 2 * n_elem_c + degree - 2, n_elem_c + degree - 2
+    out = np.zeros((nf, nc))
+    _check(load_library().sth_host_space_prolongation(int(n_elem_c), int(degree), out.ctypes.data_as(_DP)))
+    return out
 
 
 def host_load_1d(omega, phase, k, **kw):
@@ -215,13 +227,14 @@ class Solver:
     """One discrete problem on the GPU (setup factors and workspaces)."""
 
     def __init__(self, dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", stream=None):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", space_ratio=0.0,
+                 stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP slab solver needs a gfx950 device")
         self.lib = load_library()
         self.problem = make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T, theta, omega, nu_pre,
-                                    nu_post, prec, coarse_slabs, basis, temporal)
+                                    nu_post, prec, coarse_slabs, basis, temporal, space_ratio)
         self.shape = dict(dim=dim, n_elem=n_elem, degree=degree, n_slabs=n_slabs, n_elem_t=n_elem_t)
         self.coarse_slabs = self.problem.coarse_slabs
         h = ctypes.c_void_p()
@@ -242,6 +255,10 @@ class Solver:
 
     def level_len(self, level):
         return self.lib.sth_level_len(self.h, level)
+
+    def level_elems(self, level):
+        """spatial elements per axis on a level (halved by each space-time coarsening)"""
+        return self.lib.sth_level_elems(self.h, level)
 
     def new_vector(self, level=0):
         import torch

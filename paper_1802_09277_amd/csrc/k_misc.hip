@@ -1,6 +1,9 @@
 // gfx950 kernels of the space-time slab solver: fixed-order sums and the
 // flags of speculative cycles, time restriction and prolongation (Section
-// 3.1), fills, norms, the load vector and the Krylov vector operations.
+// 3.1), the banded spatial transfers of a space-time coarsening step, fills,
+// norms, the load vector and the Krylov vector operations.
+#include <algorithm>
+
 #include "kernels_common.hpp"
 
 namespace sth {
@@ -187,6 +190,39 @@ hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u
     if (total <= 0) return hipSuccess;
     dim3 grid((unsigned)((total + 255) / 256));
     STH_TR_SWITCH(k_prolong, tr, e, u, Sc, Nx)
+    return hipGetLastError();
+}
+
+// Banded operator along one axis of a row-major tensor [outer][n_in][inner]
+// (the spatial transfers between meshes of a space-time coarsening step,
+// P_x^T for the restriction, P_x for the prolongation, one axis at a time):
+//   out[o][i][c] = sum_{k < W} coef[i W + k] in[o][j0[i] + k][c],
+// j0[i] + W <= n_in for every i (the host pads the coefficients with zeros).
+__global__ __launch_bounds__(256) void k_band_axis(const double* __restrict__ in, double* __restrict__ out, long outer,
+                                                   int n_in, int n_out, long inner, const int* __restrict__ j0,
+                                                   const double* __restrict__ coef, int W) {
+    const long total = outer * n_out * inner;
+    for (long g = (long)blockIdx.x * 256 + threadIdx.x; g < total; g += (long)gridDim.x * 256) {
+        const long c = g % inner;
+        const long t = g / inner;
+        const int i = (int)(t % n_out);
+        const long o = t / n_out;
+        const double* src = in + ((o * n_in + j0[i]) * inner + c);
+        const double* cf = coef + (long)i * W;
+        double acc = 0.0;
+        for (int k = 0; k < W; ++k) acc += cf[k] * src[(long)k * inner];
+        out[g] = acc;
+    }
+}
+
+hipError_t launch_band_axis(const double* in, double* out, long outer, int n_in, int n_out, long inner,
+                            const int* j0, const double* coef, int W, hipStream_t st) {
+    if (outer <= 0 || n_out <= 0 || inner <= 0) return hipSuccess;
+    if (n_in <= 0 || W <= 0 || W > n_in) return hipErrorInvalidValue;
+    const long total = outer * n_out * inner;
+    const long blocks = std::min<long>((total + 255) / 256, 1L << 20);
+    hipLaunchKernelGGL(k_band_axis, dim3((unsigned)blocks), dim3(256), 0, st, in, out, outer, n_in, n_out, inner, j0,
+                       coef, W);
     return hipGetLastError();
 }
 

@@ -217,6 +217,9 @@ hipError_t launch_restrict(int Nt, const Transfer& tr, const double* r, double* 
 // u[2m..2m+1] += (P (x) I) e[m]
 hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u, long Sc,
                           long Nx, hipStream_t st);
+// out[o][i][c] = sum_{k<W} coef[i W + k] in[o][j0[i] + k][c] over [outer][n_in][inner]
+hipError_t launch_band_axis(const double* in, double* out, long outer, int n_in, int n_out, long inner,
+                            const int* j0, const double* coef, int W, hipStream_t st);
 
 // v[0..len) = val, skipped when skip is given and *skip != 0 (f32: v
 // addresses float data)

@@ -111,6 +111,18 @@ struct sth_handle {
     bool wsum_valid = false;            // the norm slots hold the mode-weighted residual sums
     double* buf0 = nullptr;
     double* buf1 = nullptr;
+    // coarsening in space (Section 4.4): the transition below the last
+    // level of this handle halves the spatial mesh as well; the levels from
+    // there on belong to `child`, the problem on the halved mesh
+    sth_handle* child = nullptr;
+    int n_c = 0;                        // interior functions per axis of the child's mesh
+    int rW = 0, pW = 0;                 // band widths of P_x^T and P_x
+    int* rj0 = nullptr;                 // P_x^T: first fine function of each coarse one
+    double* rco = nullptr;              //   and its rW coefficients
+    int* pj0 = nullptr;                 // P_x: first coarse function of each fine one
+    double* pco = nullptr;              //   and its pW coefficients
+    double* cf = nullptr;               // right-hand side and iterate of the child's finest level
+    double* cu = nullptr;
     double* partial = nullptr;
     double* dnorm = nullptr;            // squared norms (layout at kNormSlots)
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
@@ -403,10 +415,68 @@ static int prolong_lvl(sth_handle* h, int lvl, const double* e, double* u, hipSt
     return STH_OK;
 }
 
+// Space-time restriction from the last level of h to the child's finest
+// level: r_c = (P_t^T (x) P_x^T (x) .. (x) P_x^T) on each slab pair, in time
+// first (into buf0), then along x, y (and z), alternating buf1 and buf0.
+// Neither r nor rc may be buf0 or buf1 of h, except r == buf1.
+static int restrict_space(sth_handle* h, const double* r, double* rc, hipStream_t st) {
+    const int lvl = h->L - 1;
+    h->tlev = lvl;
+    const long Sc = h->child->lev_S[0];
+    const long nf = h->n, nc = h->n_c, rows = Sc * h->Nt;
+    const double dof = (double)Sc * slab_len(h);
+    Timed tm(h, STH_K_RESTRICT, dof * 4.0 * h->Nt + dof * 2.0 * h->rW * (h->dim == 2 ? 1.5 : 1.75),
+             dof * 24.0, st);
+    HIPCHK(launch_restrict(h->Nt, h->tr, r, h->buf0, Sc, h->Nx, st));
+    if (h->dim == 2) {
+        HIPCHK(launch_band_axis(h->buf0, h->buf1, rows * nf, nf, nc, 1, h->rj0, h->rco, h->rW, st));     // x
+        HIPCHK(launch_band_axis(h->buf1, rc, rows, nf, nc, nc, h->rj0, h->rco, h->rW, st));               // y
+    } else {
+        HIPCHK(launch_band_axis(h->buf0, h->buf1, rows * nf * nf, nf, nc, 1, h->rj0, h->rco, h->rW, st));  // x
+        HIPCHK(launch_band_axis(h->buf1, h->buf0, rows * nf, nf, nc, nc, h->rj0, h->rco, h->rW, st));      // y
+        HIPCHK(launch_band_axis(h->buf0, rc, rows, nf, nc, nc * nc, h->rj0, h->rco, h->rW, st));           // z
+    }
+    return STH_OK;
+}
+
+// u += (P_t (x) P_x (x) .. (x) P_x) e on the slab pairs of the last level of h
+// (e on the child's finest level): along z, y, x into the buffers, then the
+// time prolongation adds into u.  Neither e nor u may be buf0 or buf1 of h.
+static int prolong_space(sth_handle* h, const double* e, double* u, hipStream_t st) {
+    const int lvl = h->L - 1;
+    h->tlev = lvl;
+    const long Sc = h->child->lev_S[0];
+    const long nf = h->n, nc = h->n_c, rows = Sc * h->Nt;
+    const double dof = (double)Sc * slab_len(h);
+    Timed tm(h, STH_K_PROLONG, dof * 4.0 * h->Nt + dof * 2.0 * h->pW * 2.0, dof * 40.0, st);
+    const double* fine;
+    if (h->dim == 2) {
+        HIPCHK(launch_band_axis(e, h->buf0, rows, nc, nf, nc, h->pj0, h->pco, h->pW, st));                 // y
+        HIPCHK(launch_band_axis(h->buf0, h->buf1, rows * nf, nc, nf, 1, h->pj0, h->pco, h->pW, st));       // x
+        fine = h->buf1;
+    } else {
+        HIPCHK(launch_band_axis(e, h->buf0, rows, nc, nf, nc * nc, h->pj0, h->pco, h->pW, st));            // z
+        HIPCHK(launch_band_axis(h->buf0, h->buf1, rows * nf, nc, nf, nc, h->pj0, h->pco, h->pW, st));      // y
+        HIPCHK(launch_band_axis(h->buf1, h->buf0, rows * nf * nf, nc, nf, 1, h->pj0, h->pco, h->pW, st));  // x
+        fine = h->buf0;
+    }
+    HIPCHK(launch_prolong(h->Nt, h->tr, fine, u, Sc, h->Nx, st));
+    return STH_OK;
+}
+
+static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool zero_guess, hipStream_t st);
+
+// the coarse-grid correction below the last level of h: V-cycle of the
+// child from a zero guess (its exact solve when it has one level)
+static int child_cycle(sth_handle* c, const double* f, double* u, hipStream_t st) {
+    if (c->L == 1 && !c->child) return coarse_solve(c, 0, f, u, st);
+    return vcycle_lvl(c, 0, f, u, true, st);
+}
+
 static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool zero_guess, hipStream_t st) {
     h->tlev = lvl;
     int rc;
-    if (lvl == h->L - 1) {
+    if (lvl == h->L - 1 && !h->child) {
         if (lvl > 0) return coarse_solve(h, lvl, f, u, st);      // zero initial guess on coarse levels
         // a single level: correct the iterate, u += L^{-1}(f - L u), so that
         // an inexact (reduced-precision) forward substitution still converges
@@ -424,9 +494,17 @@ static int vcycle_lvl(sth_handle* h, int lvl, const double* f, double* u, bool z
         if ((rc = smooth_step(h, lvl, f, u, zero_guess && i == 0, st))) return rc;
     }
     if ((rc = residual(h, lvl, f, u, h->buf1, 0, ns, 1.0, st))) return rc;
-    if ((rc = restrict_lvl(h, lvl, h->buf1, h->lf[lvl + 1], st))) return rc;
-    if ((rc = vcycle_lvl(h, lvl + 1, h->lf[lvl + 1], h->lu[lvl + 1], true, st))) return rc;
-    if ((rc = prolong_lvl(h, lvl, h->lu[lvl + 1], u, st, h->Nx))) return rc;
+    if (lvl == h->L - 1) {
+        // coarsening in space and time: the child's hierarchy below
+        if ((rc = restrict_space(h, h->buf1, h->cf, st))) return rc;
+        if ((rc = child_cycle(h->child, h->cf, h->cu, st))) return rc;
+        h->tlev = lvl;
+        if ((rc = prolong_space(h, h->cu, u, st))) return rc;
+    } else {
+        if ((rc = restrict_lvl(h, lvl, h->buf1, h->lf[lvl + 1], st))) return rc;
+        if ((rc = vcycle_lvl(h, lvl + 1, h->lf[lvl + 1], h->lu[lvl + 1], true, st))) return rc;
+        if ((rc = prolong_lvl(h, lvl, h->lu[lvl + 1], u, st, h->Nx))) return rc;
+    }
     for (int i = 0; i < h->nu_post; ++i) {
         if ((rc = smooth_step(h, lvl, f, u, false, st))) return rc;
     }
@@ -817,6 +895,7 @@ static Problem to_problem(const sth_problem* p) {
     q.coarse_slabs = p->coarse_slabs;
     q.basis = p->iterate_basis;
     q.temporal = p->temporal_form;
+    q.space_ratio = p->space_ratio;
     return q;
 }
 
@@ -841,7 +920,7 @@ const char* sth_last_error(void) { return g_err.c_str(); }
 static size_t level_count(const Problem& q) {
     size_t L = 1;
     long S = q.n_slabs;
-    while (S > q.coarse_slabs && S % 2 == 0) { S /= 2; ++L; }
+    while (S > q.coarse_slabs && S % 2 == 0 && (q.level_cap <= 0 || (int)L < q.level_cap)) { S /= 2; ++L; }
     return L;
 }
 
@@ -861,11 +940,24 @@ static bool f32_storage(const Problem& q, size_t levels) {
            ((q.dim == 2 && xform2d_supported(np)) || xform_panel_f32_io(np));
 }
 
+static size_t workspace_of(Problem q);
+
 int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
     if (!p || !bytes) return fail(STH_EINVAL, "null argument");
     Problem q = to_problem(p);
     std::string e = validate(q);
     if (!e.empty()) return fail(STH_EINVAL, e);
+    *bytes = workspace_of(q);
+    return STH_OK;
+}
+
+}  // extern "C"
+
+// device bytes of the setup of q and of the problems below it on coarser
+// spatial meshes (the same allocations as setup_problem)
+static size_t workspace_of(Problem q) {
+    const int own = space_transition(q);
+    if (own > 0) q.level_cap = own;
     long n = q.n(), np = (n + 15) / 16 * 16;
     long Nx = n * n * (q.dim == 3 ? n : 1);
     if (q.basis == 1) Nx = std::max(Nx, eig_modes(q.dim, (int)n));   // eigenbasis rows are padded
@@ -892,9 +984,23 @@ int sth_workspace_bytes(const sth_problem* p, size_t* bytes) {
         total += vecsl_bytes * (size_t)S * slab;
     }
     total += sizeof(double) * (kNormBlocks + kNormSlots + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
-    *bytes = total;
-    return STH_OK;
+    if (own > 0) {
+        // the coarse-mesh problem, its finest right-hand side and iterate,
+        // and the band tables of P_x
+        Problem c = q;
+        c.n_elem = q.n_elem / 2;
+        c.n_slabs = (int)(S / 2);
+        c.theta = q.theta * ((double)c.n_slabs / q.n_slabs);
+        c.level_cap = 0;
+        total += workspace_of(c);
+        const long nc = c.n();
+        total += 2 * sizeof(double) * (size_t)c.n_slabs * q.Nt() * nc * nc * (q.dim == 3 ? nc : 1);
+        total += (size_t)(n + nc) * (sizeof(int) + sizeof(double) * (q.degree + 2));
+    }
+    return total;
 }
+
+extern "C" {
 
 size_t sth_problem_vector_len(const sth_problem* p) {
     if (!p) return 0;
@@ -903,6 +1009,12 @@ size_t sth_problem_vector_len(const sth_problem* p) {
     long n = q.n();
     return (size_t)q.n_slabs * q.Nt() * n * n * (q.dim == 3 ? n : 1);
 }
+
+}  // extern "C"
+
+static int setup_problem(Problem q, hipStream_t s, sth_handle** out);
+
+extern "C" {
 
 int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
     if (!p || !out) return fail(STH_EINVAL, "null argument");
@@ -918,13 +1030,86 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         const int rc = scratch_address(&scr);
         if (rc != STH_OK) return rc;
     }
+    return setup_problem(q, (hipStream_t)stream, out);
+}
+
+}  // extern "C"
+
+// The problem on the halved spatial mesh below the last level of h (a
+// space-time coarsening step): n_elem / 2 elements per axis, half the slabs
+// of that level on the same (0, T), and theta scaled by a power of two so
+// that sigma is the finest one (the Galerkin coarse operators are the
+// rediscretisations with the finest sigma), then P_x as two band tables.
+static int attach_coarse_space(sth_handle* h, const Problem& q, hipStream_t s) {
+    Problem c = q;
+    c.n_elem = q.n_elem / 2;
+    c.n_slabs = (int)(h->lev_S[h->L - 1] / 2);
+    c.theta = q.theta * ((double)c.n_slabs / q.n_slabs);
+    c.level_cap = 0;
+    int rc = setup_problem(c, s, &h->child);
+    if (rc) return rc;
+    const int nf = h->n, nc = h->child->n;
+    h->n_c = nc;
+    Mat Px;
+    space_prolongation(c.n_elem, q.degree, Px);
+    if (Px.r != nf || Px.c != nc) return fail(STH_EINVAL, "spatial prolongation has the wrong shape");
+    // band of output o: the inputs with a nonzero coefficient, shifted to
+    // stay inside [0, n_in) at the common width W (zeros fill the rest)
+    auto band = [&](bool restr, std::vector<int>& j0, std::vector<double>& co, int& W) {
+        const int nout = restr ? nc : nf, nin = restr ? nf : nc;
+        auto at = [&](int o, int i) { return restr ? Px(i, o) : Px(o, i); };
+        std::vector<int> lo(nout, nin), hi(nout, -1);
+        for (int o = 0; o < nout; ++o)
+            for (int i = 0; i < nin; ++i)
+                if (at(o, i) != 0.0) {
+                    lo[o] = std::min(lo[o], i);
+                    hi[o] = std::max(hi[o], i);
+                }
+        W = 1;
+        for (int o = 0; o < nout; ++o)
+            if (hi[o] >= lo[o]) W = std::max(W, hi[o] - lo[o] + 1);
+        j0.assign(nout, 0);
+        co.assign((size_t)nout * W, 0.0);
+        for (int o = 0; o < nout; ++o) {
+            const int a = std::max(0, std::min(hi[o] >= lo[o] ? lo[o] : 0, nin - W));
+            j0[o] = a;
+            for (int k = 0; k < W; ++k) co[(size_t)o * W + k] = at(o, a + k);
+        }
+    };
+    std::vector<int> rj0, pj0;
+    std::vector<double> rco, pco;
+    band(true, rj0, rco, h->rW);
+    band(false, pj0, pco, h->pW);
+    const size_t clen = (size_t)h->child->lev_S[0] * slab_len(h->child);
+    if (hipMalloc((void**)&h->rj0, sizeof(int) * rj0.size()) != hipSuccess ||
+        hipMalloc((void**)&h->pj0, sizeof(int) * pj0.size()) != hipSuccess ||
+        hipMalloc((void**)&h->rco, sizeof(double) * rco.size()) != hipSuccess ||
+        hipMalloc((void**)&h->pco, sizeof(double) * pco.size()) != hipSuccess ||
+        hipMalloc((void**)&h->cf, sizeof(double) * clen) != hipSuccess ||
+        hipMalloc((void**)&h->cu, sizeof(double) * clen) != hipSuccess)
+        return fail(STH_ENOMEM, "device allocation failed");
+    if (hipMemcpyAsync(h->rj0, rj0.data(), sizeof(int) * rj0.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->pj0, pj0.data(), sizeof(int) * pj0.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->rco, rco.data(), sizeof(double) * rco.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->pco, pco.data(), sizeof(double) * pco.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return fail(STH_EHIP, "upload of the spatial prolongation failed");
+    return STH_OK;
+}
+
+static int setup_problem(Problem q, hipStream_t s, sth_handle** out) {
+    *out = nullptr;
+    // levels on this spatial mesh (all of them unless the hierarchy
+    // coarsens in space below one of them)
+    const int own = space_transition(q);
+    if (own > 0) q.level_cap = own;
+    std::string e;
     sth_handle* h = new sth_handle();
     int st = build_setup(q, h->S, e);
     if (st != 0) {
         delete h;
         return fail(st, e);
     }
-    hipStream_t s = (hipStream_t)stream;
     h->dim = q.dim;
     h->n = h->S.n;
     h->np = (h->n + 15) / 16 * 16;
@@ -991,8 +1176,11 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         h->ops.push_back(op);
         h->mixes.push_back(tm);
     }
-    if (h->L > 1) {
-        const Mat& P = h->S.levels[0].Pt;
+    if (h->L > 1 || own > 0) {
+        // P_t of every time step of this handle, also of a space-time step
+        // below its last level (the map does not depend on the slab length)
+        Mat P;
+        time_prolongation(q.n_elem_t, q.degree, P);
         for (int i = 0; i < 2 * h->Nt; ++i)
             for (int j = 0; j < h->Nt; ++j) h->tr.P[i * kNt + j] = P(i, j);
     }
@@ -1137,18 +1325,54 @@ int sth_setup(const sth_problem* p, void* stream, sth_handle** out) {
         hipMemcpyAsync(h->dktmt, ktmt.data(), ktmt.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(STH_EHIP, "upload of the setup failed");
+    if (own > 0) {
+        if ((h->L != own)) return cleanup(STH_EINVAL, "level count of the spatial mesh");
+        const int rc = attach_coarse_space(h, q, s);
+        if (rc) {
+            const std::string msg = g_err;
+            return cleanup(rc, msg);
+        }
+    }
     *out = h;
     return STH_OK;
 }
 
+extern "C" {
+
 size_t sth_vector_len(const sth_handle* h) { return h ? (size_t)h->lev_S[0] * slab_len(h) : 0; }
 
-size_t sth_level_len(const sth_handle* h, int level) {
-    if (!h || level < 0 || level >= h->L) return 0;
-    return (size_t)h->lev_S[level] * slab_len(h);
+}  // extern "C"
+
+// The handle of the chain (h, its child, ...) that holds multigrid level
+// `level`, with `level` made local to it; null past the coarsest level.
+static sth_handle* level_owner(const sth_handle* h, int& level) {
+    sth_handle* o = const_cast<sth_handle*>(h);
+    if (level < 0) return nullptr;
+    while (o && level >= o->L) {
+        level -= o->L;
+        o = o->child;
+    }
+    return o;
 }
 
-int sth_num_levels(const sth_handle* h) { return h ? h->L : 0; }
+extern "C" {
+
+size_t sth_level_len(const sth_handle* h, int level) {
+    const sth_handle* o = level_owner(h, level);
+    if (!o) return 0;
+    return (size_t)o->lev_S[level] * slab_len(o);
+}
+
+int sth_num_levels(const sth_handle* h) {
+    int L = 0;
+    for (; h; h = h->child) L += h->L;
+    return L;
+}
+
+int sth_level_elems(const sth_handle* h, int level) {
+    const sth_handle* o = level_owner(h, level);
+    return o ? o->S.prob.n_elem : 0;
+}
 
 int sth_load_rhs(sth_handle* h, const sth_rhs_modes* m, double* f, void* stream) {
     if (!h || !m || !f) return fail(STH_EINVAL, "null argument");
@@ -2133,13 +2357,20 @@ int sth_use_graphs(sth_handle* h, int enable) {
 }
 
 int sth_restrict(sth_handle* h, int level, const double* r, double* rc, void* stream) {
-    if (!h || !r || !rc || level < 0 || level + 1 >= h->L) return fail(STH_EINVAL, "bad argument");
-    return restrict_lvl(h, level, r, rc, (hipStream_t)stream);
+    sth_handle* o = h && r && rc ? level_owner(h, level) : nullptr;
+    if (!o || (level + 1 >= o->L && !o->child)) return fail(STH_EINVAL, "bad argument");
+    if (level + 1 == o->L) {
+        if (r == o->buf0 || rc == o->buf0 || rc == o->buf1) return fail(STH_EINVAL, "vector aliases a workspace");
+        return restrict_space(o, r, rc, (hipStream_t)stream);
+    }
+    return restrict_lvl(o, level, r, rc, (hipStream_t)stream);
 }
 
 int sth_prolong_add(sth_handle* h, int level, const double* ec, double* u, void* stream) {
-    if (!h || !ec || !u || level < 0 || level + 1 >= h->L) return fail(STH_EINVAL, "bad argument");
-    return prolong_lvl(h, level, ec, u, (hipStream_t)stream, h->Nx);
+    sth_handle* o = h && ec && u ? level_owner(h, level) : nullptr;
+    if (!o || (level + 1 >= o->L && !o->child)) return fail(STH_EINVAL, "bad argument");
+    if (level + 1 == o->L) return prolong_space(o, ec, u, (hipStream_t)stream);
+    return prolong_lvl(o, level, ec, u, (hipStream_t)stream, o->Nx);
 }
 
 int sth_norm(sth_handle* h, const double* v, double* out, void* stream) {
@@ -2151,6 +2382,9 @@ int sth_destroy(sth_handle* h) {
     if (!h) return STH_OK;
     // graph first: its nodes reference the buffers below
     drop_graph(h);
+    if (h->child) sth_destroy(h->child);
+    for (void* q : {(void*)h->rj0, (void*)h->pj0, (void*)h->rco, (void*)h->pco, (void*)h->cf, (void*)h->cu})
+        if (q) (void)hipFree(q);
     double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt,
                       h->Cf, h->Ci, h->Gf, h->e0, h->e1, h->e2, h->e3, h->cpartial, h->kv, h->kz, h->kc,
                       h->kpart, h->vw};
@@ -2188,12 +2422,25 @@ int sth_timing(sth_handle* h, unsigned class_mask) {
     }
     h->timing = class_mask != 0;
     h->timing_mask = class_mask;
-    return STH_OK;
+    return h->child ? sth_timing(h->child, class_mask) : STH_OK;
 }
 
 int sth_timing_level(sth_handle* h, int level) {
-    if (!h || level < -1 || level >= h->L) return fail(STH_EINVAL, "bad argument");
-    h->timing_level = level;
+    if (!h || level < -1 || level >= sth_num_levels(h)) return fail(STH_EINVAL, "bad argument");
+    // level made local to the handle of the chain that holds it; the others
+    // record nothing
+    int rest = level;                   // local to the current handle; -1 once placed
+    for (sth_handle* o = h; o; o = o->child) {
+        if (level < 0) {
+            o->timing_level = -1;
+        } else if (rest >= 0 && rest < o->L) {
+            o->timing_level = rest;
+            rest = -1;
+        } else {
+            o->timing_level = 1 << 30;
+            if (rest >= 0) rest -= o->L;
+        }
+    }
     return STH_OK;
 }
 
@@ -2210,6 +2457,16 @@ int sth_timing_report(sth_handle* h, int kclass, int* launches, double* ms, doub
         t += e;
         fl += r.flops;
         by += r.bytes;
+    }
+    if (h->child) {
+        int c2 = 0;
+        double t2 = 0, f2 = 0, b2 = 0;
+        const int rc = sth_timing_report(h->child, kclass, &c2, &t2, &f2, &b2);
+        if (rc) return rc;
+        cnt += c2;
+        t += t2;
+        fl += f2;
+        by += b2;
     }
     if (launches) *launches = cnt;
     if (ms) *ms = t;
@@ -2250,6 +2507,15 @@ int sth_host_factors(const sth_problem* p, int level, sth_factors* out) {
     out->schur = L.schur ? 1 : 0;
     if (L.schur) cp(out->R, L.R.a);
     if (out->mode_weights) cp(out->mode_weights, residual_mode_weights(S));
+    return STH_OK;
+}
+
+int sth_host_space_prolongation(int n_elem_c, int degree, double* out) {
+    if (!out || n_elem_c < 1 || degree < 1 || degree > kMaxDeg || n_elem_c + degree - 2 < 1)
+        return fail(STH_EINVAL, "bad argument");
+    Mat Px;
+    space_prolongation(n_elem_c, degree, Px);
+    std::memcpy(out, Px.a.data(), sizeof(double) * Px.a.size());
     return STH_OK;
 }
 

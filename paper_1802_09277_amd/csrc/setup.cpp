@@ -572,31 +572,13 @@ void time_matrices(double tau, int n_el, int p, double sigma, Mat& Kt, Mat& Mt) 
         for (int j = 0; j <= p; ++j) Kt(i, j) += v[i] * v[j];
 }
 
-void time_prolongation(int n_el, int p, Mat& Pt) {
-    // Coarse slab [0,2] (n_el elements, degree p) represented in the two
-    // fine slabs [0,1], [1,2] by Boehm knot insertion: insert every fine
-    // knot that is missing, and the slab interface 1 up to multiplicity p+1,
-    // which splits the basis into the two fine slab bases.  (The map does
-    // not depend on the slab length, so unit slabs are used.)
-    std::vector<double> t = open_knots(0.0, 2.0, n_el, p);
-    int Nc = n_el + p;
-    std::vector<std::vector<double>> C(Nc, std::vector<double>(Nc, 0.0));  // rows: coefficients
+// Boehm knot insertion: inserts the knots `ins` (one at a time) into the
+// knot vector t of degree p and returns the coefficients of every original
+// basis function in the refined basis (row i: refined function i).
+static std::vector<std::vector<double>> insert_knots(std::vector<double> t, int p, const std::vector<double>& ins) {
+    const int Nc = int(t.size()) - p - 1;
+    std::vector<std::vector<double>> C(Nc, std::vector<double>(Nc, 0.0));
     for (int i = 0; i < Nc; ++i) C[i][i] = 1.0;
-    std::vector<double> target;
-    for (int i = 0; i <= p; ++i) target.push_back(0.0);
-    for (int k = 1; k < n_el; ++k) target.push_back(double(k) / n_el);
-    for (int i = 0; i <= p; ++i) target.push_back(1.0);
-    for (int k = 1; k < n_el; ++k) target.push_back(1.0 + double(k) / n_el);
-    for (int i = 0; i <= p; ++i) target.push_back(2.0);
-    // insert target knots not yet present (multiset difference)
-    std::vector<double> ins;
-    {
-        std::vector<double> have = t;
-        for (double x : target) {
-            auto it = std::find_if(have.begin(), have.end(), [&](double y) { return std::fabs(y - x) < 1e-14; });
-            if (it != have.end()) have.erase(it); else ins.push_back(x);
-        }
-    }
     for (double x : ins) {
         int N = int(t.size()) - p - 1;
         int k = find_span(t, p, x);
@@ -616,10 +598,50 @@ void time_prolongation(int n_el, int p, Mat& Pt) {
         C.swap(Cn);
         t.insert(t.begin() + k + 1, x);
     }
+    return C;
+}
+
+void time_prolongation(int n_el, int p, Mat& Pt) {
+    // Coarse slab [0,2] (n_el elements, degree p) represented in the two
+    // fine slabs [0,1], [1,2] by Boehm knot insertion: insert every fine
+    // knot that is missing, and the slab interface 1 up to multiplicity p+1,
+    // which splits the basis into the two fine slab bases.  (The map does
+    // not depend on the slab length, so unit slabs are used.)
+    std::vector<double> t = open_knots(0.0, 2.0, n_el, p);
+    std::vector<double> target;
+    for (int i = 0; i <= p; ++i) target.push_back(0.0);
+    for (int k = 1; k < n_el; ++k) target.push_back(double(k) / n_el);
+    for (int i = 0; i <= p; ++i) target.push_back(1.0);
+    for (int k = 1; k < n_el; ++k) target.push_back(1.0 + double(k) / n_el);
+    for (int i = 0; i <= p; ++i) target.push_back(2.0);
+    // insert target knots not yet present (multiset difference)
+    std::vector<double> ins;
+    {
+        std::vector<double> have = t;
+        for (double x : target) {
+            auto it = std::find_if(have.begin(), have.end(), [&](double y) { return std::fabs(y - x) < 1e-14; });
+            if (it != have.end()) have.erase(it); else ins.push_back(x);
+        }
+    }
+    std::vector<std::vector<double>> C = insert_knots(t, p, ins);
     int Nt = n_el + p;
     Pt = Mat(2 * Nt, Nt);
     for (int i = 0; i < 2 * Nt; ++i)
         for (int j = 0; j < Nt; ++j) Pt(i, j) = C[i][j];
+}
+
+void space_prolongation(int n_elem_c, int p, Mat& Px) {
+    // Coarse mesh of n_elem_c elements on (0,1) refined by inserting every
+    // element midpoint (Boehm); the interior block, since coarse interior
+    // functions vanish on the boundary and so have no weight on the first
+    // and last fine function
+    std::vector<double> ins;
+    for (int k = 0; k < n_elem_c; ++k) ins.push_back((2.0 * k + 1.0) / (2.0 * n_elem_c));
+    std::vector<std::vector<double>> C = insert_knots(open_knots(0.0, 1.0, n_elem_c, p), p, ins);
+    const int nc = n_elem_c + p - 2, nf = 2 * n_elem_c + p - 2;
+    Px = Mat(nf, nc);
+    for (int i = 0; i < nf; ++i)
+        for (int j = 0; j < nc; ++j) Px(i, j) = C[i + 1][j + 1];
 }
 
 void load_time(const Problem& pr, double omega, double phase, std::vector<double>& out) {
@@ -672,6 +694,21 @@ void load_space(const Problem& pr, int k, std::vector<double>& out) {
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
+int space_transition(const Problem& p) {
+    if (!(p.space_ratio > 0.0)) return 0;
+    long S = p.n_slabs;
+    double tau = p.tau();
+    const double ne = p.n_elem;            // h = 1 / n_elem: tau / h^2 = tau n_elem^2
+    int lvl = 0;
+    while (S > p.coarse_slabs && S % 2 == 0) {
+        if (p.n_elem % 2 == 0 && p.n_elem / 2 >= 2 && tau * ne * ne >= p.space_ratio) return lvl + 1;
+        S /= 2;
+        tau *= 2.0;
+        ++lvl;
+    }
+    return 0;
+}
+
 std::string validate(const Problem& p) {
     std::ostringstream os;
     if (p.dim != 2 && p.dim != 3) os << "dim must be 2 or 3; ";
@@ -688,6 +725,9 @@ std::string validate(const Problem& p) {
     if (p.prec < 0 || p.prec > 2) os << "transform_prec must be 0, 1 or 2; ";
     if (p.coarse_slabs < 1) os << "coarse_slabs must be >= 1; ";
     if (p.temporal < 0 || p.temporal > 2) os << "temporal_form must be 0, 1 or 2; ";
+    if (!(p.space_ratio >= 0.0) || !std::isfinite(p.space_ratio)) os << "space_ratio must be finite and >= 0; ";
+    if (p.space_ratio > 0.0 && p.basis != 0)
+        os << "coarsening in space runs in the B-spline coefficient iteration (iterate_basis 0); ";
     if (os.str().empty() && p.n_elem + p.degree - 2 >= 1) {
         double len = double(p.n_slabs) * (p.n_elem_t + p.degree);
         for (int a = 0; a < p.dim; ++a) len *= (p.n_elem + p.degree - 2);
@@ -952,7 +992,8 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
             err = os.str();
             return st;
         }
-        bool coarsen = (S > p.coarse_slabs && S % 2 == 0);
+        bool coarsen = (S > p.coarse_slabs && S % 2 == 0) &&
+                       (p.level_cap <= 0 || (int)s.levels.size() + 1 < p.level_cap);
         if (coarsen) L.Pt = Pt;
         s.levels.push_back(L);
         if (!coarsen) break;

@@ -53,6 +53,8 @@ struct Problem {
     int coarse_slabs;
     int basis;
     int temporal = 2;      // 0 diagonalisation, 1 real Schur, 2 automatic
+    double space_ratio = 0.0;   // > 0: coarsen in space too where tau_l / h_l^2 >= space_ratio
+    int level_cap = 0;     // > 0: at most this many levels of this spatial mesh
     int n() const { return n_elem + degree - 2; }
     int Nt() const { return n_elem_t + degree; }
     double tau() const { return T / n_slabs; }
@@ -81,6 +83,12 @@ struct Setup {
     std::vector<TemporalLevel> levels;
 };
 
+// Levels of the finest spatial mesh when the hierarchy coarsens in space
+// and time at their last transition (tau_l / h_l^2 >= space_ratio with an
+// even number of elements, at least 4, per axis); 0 when it coarsens in time
+// only.  The levels below belong to the problem on the halved mesh.
+int space_transition(const Problem& p);
+
 // Validates the problem; returns an error message or "".
 std::string validate(const Problem& p);
 // Full setup.  status: 0 ok, -4 not positive, -5 ill-conditioned, -1 invalid.
@@ -97,6 +105,10 @@ void space_matrices(int n_elem, int p, Mat& M1, Mat& K1);
 void time_matrices(double tau, int n_el, int p, double sigma, Mat& Kt, Mat& Mt);
 // Prolongation coarse slab (length 2 tau) -> two fine slabs by knot insertion.
 void time_prolongation(int n_el, int p, Mat& Pt);
+// Prolongation of the interior spatial functions, coarse mesh of n_elem_c
+// elements -> fine mesh of 2 n_elem_c elements on (0,1), by knot insertion
+// ((n_f x n_c), banded: p+2 fine functions per coarse one).
+void space_prolongation(int n_elem_c, int p, Mat& Px);
 // 1-D load vectors of one separable mode.
 void load_time(const Problem& p, double omega, double phase, std::vector<double>& out);
 void load_space(const Problem& p, int k, std::vector<double>& out);

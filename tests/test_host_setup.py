@@ -9,7 +9,7 @@ import pytest
 
 import paper_1802_09277_amd as sth
 from oracle.spacetime import time_matrices, space_matrices_1d, Problem as OProblem, assemble_rhs
-from oracle.mg import time_prolongation, MultigridOracle
+from oracle.mg import time_prolongation, space_prolongation, MultigridOracle
 import workloads as W
 
 HDR = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "sth.h")
@@ -202,7 +202,8 @@ def test_guard_mt_not_positive():
 
 @pytest.mark.parametrize("bad", [dict(dim=1), dict(degree=5), dict(n_elem=1), dict(n_slabs=0),
                                  dict(n_elem_t=7), dict(omega=0.0), dict(nu_pre=0, nu_post=0),
-                                 dict(prec=3), dict(theta=-1.0), dict(coarse_slabs=0)])
+                                 dict(prec=3), dict(theta=-1.0), dict(coarse_slabs=0), dict(space_ratio=-1.0),
+                                 dict(space_ratio=2.0, basis="eigen")])
 def test_invalid_problems_rejected(bad):
     kw = dict(dim=2, n_elem=4, degree=2, n_slabs=4, n_elem_t=2)
     kw.update(bad)
@@ -219,6 +220,27 @@ def test_workspace_bytes_grows_with_problem():
     assert b > a and b >= 3 * vec
     single = sth.workspace_bytes(dim=2, n_elem=16, degree=2, n_slabs=32, n_elem_t=2)    # one level
     assert 2 * vec <= single < b
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+@pytest.mark.parametrize("nec", [2, 3, 5, 8])
+def test_space_prolongation_matches_oracle(p, nec):
+    """The library's P_x (Boehm knot insertion of the element midpoints)
+    against the oracle's (L2 projection on the fine mesh)."""
+    if nec + p - 2 < 1:
+        pytest.skip("no interior function")
+    P = sth.host_space_prolongation(nec, p)
+    assert P.shape == (2 * nec + p - 2, nec + p - 2)
+    assert np.abs(P - space_prolongation(nec, p)).max() <= 1e-14
+
+
+def test_workspace_with_coarsening_in_space():
+    """Space-time steps shrink the coarse levels by 2^(d+1) instead of 2: the
+    whole chain of setups needs less device memory than time-only levels."""
+    kw = dict(dim=2, n_elem=32, degree=2, n_slabs=32, n_elem_t=1, coarse_slabs=1)
+    assert sth.workspace_bytes(space_ratio=2.0, **kw) < sth.workspace_bytes(**kw)
+    # a ratio no level reaches keeps the time-only hierarchy
+    assert sth.workspace_bytes(space_ratio=1e9, **kw) == sth.workspace_bytes(**kw)
 
 
 @pytest.mark.parametrize("dim", [2, 3])
