@@ -291,7 +291,7 @@ def report_sum(s, parts):
 def make_solver(cfg, prec, args):
     import paper_1802_09277_amd as sth
     s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
-                   prec=prec, basis=args.basis, coarse_slabs=args.coarse_slabs)
+                   prec=prec, basis=args.basis, coarse_slabs=args.coarse_slabs, space_ratio=args.space_ratio)
     if args.no_speculate:
         s.speculate(False)
     return s
@@ -333,6 +333,12 @@ def main():
                     help="time the CPU oracle may take (it runs beside the GPU part)")
     ap.add_argument("--no-precision-forms", action="store_true",
                     help="skip the FP32 / BF16x3 solves reported beside the headline")
+    ap.add_argument("--slabs", type=int, default=None,
+                    help="profiling runs only: override the workload's slab count (the line then names a "
+                         "different workload)")
+    ap.add_argument("--space-ratio", type=float, default=0.0,
+                    help="coarsen in space too where tau/h^2 >= this (B-spline coefficient iteration only; "
+                         "0: time only)")
     ap.add_argument("--no-speculate", action="store_true",
                     help="wait for each cycle's norm before enqueueing the next (library default: speculate)")
     ap.add_argument("--serve", action="store_true", help="serving workload (p50/p99 latency) instead")
@@ -354,6 +360,12 @@ def main():
     import workloads as W
 
     cfg = W.CONFIGS[args.config]
+    if args.slabs:
+        # the same slab length and slab problem on fewer (or more) slabs
+        import dataclasses
+        cfg = dataclasses.replace(cfg, name=f"{cfg.name}-{args.slabs}slabs", n_slabs=args.slabs,
+                                  T=cfg.T * args.slabs / cfg.n_slabs,
+                                  note=f"{cfg.note}; cut to {args.slabs} slabs of the same length")
     sample_slabs = args.cpu_sample_slabs or min(4, cfg.n_slabs)
     # the CPU oracle runs in its own process beside the GPU part
     cpu_job = None if args.no_cpu_baseline else start_cpu_baseline(cfg, sample_slabs)
@@ -375,6 +387,11 @@ def main():
         log(f"copy calibration: 3 copies of {n * 8} bytes")
         del src, dst
 
+    # one untimed solve first: the first launch of each kernel loads its code,
+    # which the per-class times below must not include
+    u.zero_()
+    s.solve(f, u, rtol=args.rtol, maxit=200)
+    torch.cuda.synchronize()
     # warm-up with every kernel class timed on the finest level, to find the
     # dominant kernel class there (the coarser levels hold half the work)
     s.timing((1 << len(sth.KCLASS)) - 1, level=0)
@@ -425,6 +442,7 @@ def main():
     roof["mean_launch_us"] = rep["ms"] * 1e3 / max(rep["launches"], 1)
     roof["events_pass_ms_per_step"] = ms_events
     levels, coarse_slabs = s.num_levels, s.coarse_slabs
+    level_elems = [s.level_elems(l) for l in range(levels)]
     s.close()
 
     forms = {args.prec: {"value": cfg.unknowns / (ms * 1e-3), "ms_per_step": ms, "v_cycles": iters,
@@ -471,6 +489,8 @@ def main():
             "final_relres": relres,
             "levels": levels,
             "coarse_slabs": coarse_slabs,
+            "space_ratio": args.space_ratio,
+            "level_elems": level_elems,
             "speculative_cycles": not args.no_speculate,
         },
         "precision_forms": forms,

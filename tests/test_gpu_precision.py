@@ -13,6 +13,8 @@ import pytest
 import workloads as W
 from oracle.spacetime import Problem as OProblem, assemble_rhs
 from oracle.mg import MultigridOracle
+from oracle.norms import errors, ExactSolution
+from oracle.solve import SlabSystem
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -98,3 +100,39 @@ def test_reduced_precision_solve(name, prec, basis):
         assert abs(rr_check - rr) <= 1e-6 * rr
     s.close()
     s64.close()
+
+
+# a C3-shaped manufactured problem (3-D, p = 2, two time elements per slab,
+# u = prod sin(pi x_a) sin(pi t)) small enough for the oracle's quadrature of
+# the error over every slab
+C3_SHAPED = dict(dim=3, n_elem=6, degree=2, n_slabs=8, n_elem_t=2)
+
+
+@functools.lru_cache(maxsize=None)
+def _c3_shaped_direct():
+    prob = OProblem(**C3_SHAPED)
+    f = assemble_rhs(prob, W.manufactured_modes(3))
+    ud = SlabSystem.assemble(prob).forward_substitution(f)
+    return prob, f, errors(prob, ud, ExactSolution(*W.manufactured_exact(3)))
+
+
+@pytest.mark.parametrize("basis,prec", [("eigen", "fp64"), ("eigen", "fp32"), ("eigen", "bf16x3"),
+                                        ("nodal", "bf16x3")])
+def test_c3_shaped_l2_error_against_exact_solution(basis, prec):
+    """The L2(Q) and dG errors against u_exact of a solve to rtol 1e-10 equal
+    those of the oracle's direct solution: the precision form changes the
+    discrete solution far below the discretisation error."""
+    import paper_1802_09277_amd as sth
+    print(f"[gpu-precision] C3-shaped L2 error basis={basis} prec={prec} {C3_SHAPED}", flush=True)
+    prob, f, e_direct = _c3_shaped_direct()
+    s = sth.Solver(**C3_SHAPED, prec=prec, basis=basis, coarse_slabs=2)
+    u = s.new_vector()
+    it, rr, _ = s.solve(torch.from_numpy(f).cuda(), u, rtol=1e-10, maxit=80)
+    torch.cuda.synchronize()
+    e = errors(prob, u.cpu().numpy(), ExactSolution(*W.manufactured_exact(3)))
+    print(f"  {basis}/{prec}: {it} cycles, relres {rr:.2e}, L2 error {e['L2']:.6e} (direct {e_direct['L2']:.6e}), "
+          f"dG error {e['dG']:.6e} (direct {e_direct['dG']:.6e})")
+    assert rr <= 1e-10
+    assert abs(e["L2"] - e_direct["L2"]) <= 1e-5 * e_direct["L2"]
+    assert abs(e["dG"] - e_direct["dG"]) <= 1e-5 * e_direct["dG"]
+    s.close()
