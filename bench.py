@@ -16,8 +16,10 @@ it with its error against the FP64 result.  The JSON line also carries the
 roofline of the dominant kernel class on the finest multigrid level (HIP
 events on the solve's stream around each of its launches there, in an eager
 pass of the same K solves right after the timed region; HBM traffic from the
-committed rocprofv3 counter summary when it matches the kernel sources) and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+committed rocprofv3 counter summary when it matches the kernel sources), a
+short serving leg (the serving request mix through the library's server: its
+saturation rate and p50/p99 latency at 0.8 of it) and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -184,7 +186,7 @@ def measured_traffic(cfg_name, basis, prec, kclass):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def serve_bench(args):
+def serve_measure(n_requests, slots, budget_gib, basis, loads, graphs, prec):
     """Serving workload: 2-D requests with n_elem in {32..256}, p in {2,3,4},
     slabs in {16..512}, random-mode right-hand sides seeded by the request id,
     rtol 1e-8.  A closed burst measures the saturation rate (after a cold
@@ -197,8 +199,10 @@ def serve_bench(args):
     import workloads as W
 
     torch.cuda.set_device(0)
-    reqs = W.serving_requests(args.serve_requests, seed=0)
-    srv = sth.Server(args.serve_budget_gib << 30, args.serve_slots)
+    reqs = W.serving_requests(n_requests, seed=0)
+    srv = sth.Server(budget_gib << 30, slots)
+    if graphs:
+        srv.use_graphs(True)
     shape = lambda c: dict(dim=c.dim, n_elem=c.n_elem, degree=c.degree, n_slabs=c.n_slabs, n_elem_t=c.n_elem_t)
 
     def burst():
@@ -207,7 +211,7 @@ def serve_bench(args):
         for c in reqs:
             u = torch.empty(sth.problem_vector_len(**shape(c)), dtype=torch.float64, device="cuda")
             outs.append(u)
-            tickets.append(srv.submit(c.modes(), u, rtol=1e-8, maxit=100, basis=args.basis, **shape(c)))
+            tickets.append(srv.submit(c.modes(), u, rtol=1e-8, maxit=100, basis=basis, prec=prec, **shape(c)))
         stats = [srv.wait(t) for t in tickets]
         torch.cuda.synchronize()
         return time.perf_counter() - t0, stats
@@ -222,7 +226,7 @@ def serve_bench(args):
     log(f"serve: cold burst {t_cold:.2f} s, warm burst {t_warm:.2f} s, {sat_rps:.1f} requests/s")
     rng = np.random.default_rng(1)
     rates = []
-    for load in (0.5, 0.8, 0.95):
+    for load in loads:
         lam = load * sat_rps
         arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
         tickets, outs = [None] * len(reqs), [None] * len(reqs)
@@ -234,7 +238,8 @@ def serve_bench(args):
                 if delay > 0:
                     time.sleep(delay)
                 outs[i] = torch.empty(sth.problem_vector_len(**shape(c)), dtype=torch.float64, device="cuda")
-                tickets[i] = srv.submit(c.modes(), outs[i], rtol=1e-8, maxit=100, basis=args.basis, **shape(c))
+                tickets[i] = srv.submit(c.modes(), outs[i], rtol=1e-8, maxit=100, basis=basis, prec=prec,
+                                        **shape(c))
 
         t0 = time.perf_counter()
         th = threading.Thread(target=client)
@@ -249,9 +254,19 @@ def serve_bench(args):
         log(f"serve: load {load}: p50 {rates[-1]['p50_ms']:.1f} ms, p99 {rates[-1]['p99_ms']:.1f} ms")
     resident, setups = srv.resident()
     srv.close()
+    return {"requests": len(reqs), "streams": slots, "graphs": bool(graphs), "transform_prec": prec,
+            "saturation_rps": sat_rps,
+            "saturation_dof_per_s": total_dof / t_warm, "unknowns_total": total_dof, "cold_burst_s": t_cold,
+            "warm_burst_s": t_warm, "mean_cycles": float(np.mean([st["iters"] for st in stats])),
+            "cached_setups": setups, "resident_gib": resident / 2 ** 30, "poisson": rates}
+
+
+def serve_bench(args):
+    sv = serve_measure(args.serve_requests, args.serve_slots, args.serve_budget_gib, args.basis,
+                       (0.5, 0.8, 0.95), args.serve_graphs, args.serve_prec)
     out = {
         "metric": METRIC,
-        "value": total_dof / t_warm,
+        "value": sv["saturation_dof_per_s"],
         "unit": "DOF/s",
         "n_gpus": 1,
         "higher_is_better": True,
@@ -259,13 +274,11 @@ def serve_bench(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"serving: {len(reqs)} 2D requests, n_elem 32-256, p 2-4, 16-512 slabs x 2 "
+        "config": {"workload": f"serving: {sv['requests']} 2D requests, n_elem 32-256, p 2-4, 16-512 slabs x 2 "
                                f"time elems, random modes seeded by request id, rtol 1e-8",
                    "iterate_basis": args.basis, "streams": args.serve_slots,
-                   "hbm_budget_gib": args.serve_budget_gib, "unknowns_total": total_dof},
-        "serving": {"saturation_rps": sat_rps, "cold_burst_s": t_cold, "warm_burst_s": t_warm,
-                    "mean_cycles": float(np.mean([st["iters"] for st in stats])),
-                    "cached_setups": setups, "resident_gib": resident / 2 ** 30, "poisson": rates},
+                   "hbm_budget_gib": args.serve_budget_gib, "unknowns_total": sv["unknowns_total"]},
+        "serving": sv,
     }
     print(json.dumps(out), flush=True)
 
@@ -345,7 +358,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-budget-gib", type=int, default=160)
-    ap.add_argument("--serve-prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--serve-prec", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="transform precision of the serving requests (FP64 is the faster on this mix)")
+    ap.add_argument("--serve-graphs", action="store_true",
+                    help="serving: replay captured solve iterations instead of eager launches")
+    ap.add_argument("--serve-leg-requests", type=int, default=48,
+                    help="requests of the short serving leg of the default run (0: none)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the slab solver runs on a single MI355X; "
@@ -496,6 +514,13 @@ def main():
         "precision_forms": forms,
         "roofline": roof,
     }
+    if args.serve_leg_requests > 0:
+        # a short serving leg (the C5 request mix, one Poisson load at 0.8 of
+        # the measured saturation rate): p50/p99 latency beside the throughput
+        torch.cuda.synchronize()
+        sv = serve_measure(args.serve_leg_requests, args.serve_slots, args.serve_budget_gib, args.basis, (0.8,),
+                           args.serve_graphs, args.serve_prec)
+        out["serving"] = sv
     if cpu_job is not None:
         out["cpu_baseline"] = finish_cpu_baseline(cfg, sample_slabs, cpu_job, args.cpu_limit_s)
     print(json.dumps(out), flush=True)

@@ -403,6 +403,13 @@ int sth_server_poll(sth_server* s, long long ticket, sth_request_stats* stats);
 /* Blocks until the request has finished, then as sth_server_poll. */
 int sth_server_wait(sth_server* s, long long ticket, sth_request_stats* stats);
 
+/* Setups made from now on replay each solve iteration from a captured HIP
+ * graph (sth_use_graphs) on their request's stream, instead of launching
+ * its kernels one by one: one graph launch per cycle for the scheduler
+ * thread.  A cached setup keeps the mode it was made with.  Results are
+ * bitwise those of eager launches. */
+int sth_server_use_graphs(sth_server* s, int enable);
+
 /* Device bytes held by cached setups (busy or idle) and their count. */
 int sth_server_resident(sth_server* s, size_t* bytes, int* setups);
 

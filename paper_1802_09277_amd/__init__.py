@@ -110,6 +110,7 @@ def load_library():
         "sth_server_poll": (i, [vp, ctypes.c_longlong, P(RequestStats)]),
         "sth_server_wait": (i, [vp, ctypes.c_longlong, P(RequestStats)]),
         "sth_server_resident": (i, [vp, P(sz), P(i)]),
+        "sth_server_use_graphs": (i, [vp, i]),
         "sth_server_destroy": (i, [vp]),
     }
     for name, (res, args) in sigs.items():
@@ -409,6 +410,10 @@ class Server:
         st = RequestStats()
         _check(self.lib.sth_server_wait(self.h, ticket, ctypes.byref(st)))
         return self._stats(st)
+
+    def use_graphs(self, enable=True):
+        """setups made from now on replay captured solve iterations"""
+        _check(self.lib.sth_server_use_graphs(self.h, 1 if enable else 0))
 
     def resident(self):
         b, n = ctypes.c_size_t(), ctypes.c_int()

@@ -113,6 +113,7 @@ struct sth_server {
     long long next_ticket = 1;
     int in_flight = 0;                              // admitted and not finished
     bool stop = false;
+    bool graphs = false;                            // new setups replay captured iterations
     std::mutex mu;                                  // everything above
     std::condition_variable cv_sched, cv_setup, cv_done;
     std::mutex alloc_mu;                            // device (de)allocation vs graph capture (handles with graphs on)
@@ -181,6 +182,15 @@ int prepare(sth_server* s, Request* r, std::string& msg) {
     int rc;
     if (!e->h) {
         if ((rc = sth_setup(&r->prob, (void*)s->setup_st, &e->h))) {
+            msg = sth_last_error();
+            return rc;
+        }
+        bool graphs;
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            graphs = s->graphs;
+        }
+        if (graphs && (rc = sth_use_graphs(e->h, 1))) {
             msg = sth_last_error();
             return rc;
         }
@@ -475,6 +485,13 @@ int sth_server_wait(sth_server* s, long long ticket, sth_request_stats* stats) {
     s->cv_done.wait(lk, [&] { return r->state.load() == St::Done; });
     fill_stats(r, stats);
     s->reqs.erase(ticket);
+    return STH_OK;
+}
+
+int sth_server_use_graphs(sth_server* s, int enable) {
+    if (!s) return STH_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->graphs = enable != 0;
     return STH_OK;
 }
 

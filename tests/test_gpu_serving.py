@@ -92,6 +92,28 @@ def test_every_mix_member_matches_oracle(k):
     assert err <= 1e-8
 
 
+def test_graph_replay_serving_matches_eager():
+    """Setups made with graph replay on (sth_server_use_graphs) give the
+    vectors of eager launches bitwise, also when a cached setup replays its
+    captured iterations for a later request; a mixed-precision eigenbasis
+    request (FP64 defect correction, FP32 storage) is in the mix."""
+    print("[gpu-serving] graph replay vs eager", flush=True)
+    mixed = (dict(dim=2, n_elem=40, degree=2, n_slabs=32, n_elem_t=1, basis="eigen", prec="fp32", coarse_slabs=2), 19)
+    items = MIX + [mixed]
+    srv = _server()
+    eager, st_e = _run_all(srv, items)
+    srv.close()
+    srv = _server()
+    srv.use_graphs(True)
+    first, st_1 = _run_all(srv, items)
+    again, st_2 = _run_all(srv, items)
+    srv.close()
+    for a, b, c, s1, s2 in zip(eager, first, again, st_1, st_2):
+        assert s1["status"] == 0 and s2["status"] == 0, (s1["message"], s2["message"])
+        assert s2["setup_reused"]
+        assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
 def test_same_shape_reuses_setup_and_results_are_repeatable():
     print("[gpu-serving] setup cache", flush=True)
     srv = _server()
