@@ -119,7 +119,7 @@ class Level:
 
 class MultigridOracle:
     def __init__(self, prob, nu1=1, nu2=1, omega=0.5, system=None, coarse_slabs=1, lam_crit=None,
-                 min_elem=2):
+                 min_elem=2, minres_iters=None):
         self.prob = prob
         self.nu1, self.nu2, self.omega = nu1, nu2, omega
         fine = system if system is not None else SlabSystem.assemble(prob)
@@ -152,6 +152,23 @@ class MultigridOracle:
             self.P.append(P)
             self.n_elem.append(ne)
             tau *= 2
+        # smoother: D^{-1} by sparse LU, or (minres_iters) through the
+        # temporal block form with MinRes on the 2x2 blocks (Theorem 3.10);
+        # the temporal matrices of a coarse level are those of its slab
+        # length with the finest sigma (the Galerkin blocks), time-only
+        # coarsening
+        self.minres = None
+        if minres_iters is not None:
+            from .minres import MinresSlabInverse
+            from .spacetime import time_matrices, space_matrices
+            if "xt" in self.kinds:
+                raise ValueError("the MinRes smoother is set up for coarsening in time only")
+            Mx, Kx = space_matrices(prob)
+            self.minres = []
+            for lvl in range(len(self.levels)):
+                t = prob.tau * 2 ** lvl
+                Kt, Mt = time_matrices(0.0, t, prob.n_elem_t, prob.degree, prob.sigma)
+                self.minres.append(MinresSlabInverse(Kt, Mt, Kx, Mx, minres_iters))
 
     # grid transfers --------------------------------------------------
     def restrict(self, lvl, r):
@@ -167,10 +184,18 @@ class MultigridOracle:
         return (P @ E.T).T.ravel()
 
     # smoother -----------------------------------------------------------
+    def slab_inverse(self, lvl, r):
+        """D^{-1} r on level lvl (every slab independently)."""
+        sysl = self.levels[lvl]
+        if self.minres is None:
+            return sysl.slab_solve(r)
+        R = r.reshape(sysl.S, sysl.m)
+        return np.concatenate([self.minres[lvl].apply(R[s]) for s in range(sysl.S)])
+
     def smooth(self, lvl, f, u, steps):
         sysl = self.levels[lvl]
         for _ in range(steps):
-            u = u + self.omega * sysl.slab_solve(sysl.residual(f, u))
+            u = u + self.omega * self.slab_inverse(lvl, sysl.residual(f, u))
         return u
 
     def vcycle(self, f, u, lvl=0):
