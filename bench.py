@@ -147,7 +147,7 @@ def finish_cpu_baseline(cfg, sample_slabs, started, limit_s):
 # the sources a kernel class compiles from (the committed HBM counters of a
 # class stay valid while these are unchanged); other classes: every kernel file
 KERNEL_FILES = ("kernels.hpp", "kernels_common.hpp", "k_residual.hip", "k_xform2d.hip", "k_xform_axis.hip",
-                "k_xform_panel.hip", "k_eigen.hip", "k_misc.hip")
+                "k_xform_panel.hip", "k_eigen.hip", "k_misc.hip", "k_minres.hip")
 CLASS_SOURCES = {
     "eig_cycle_close": ("kernels_common.hpp", "k_eigen.hip"),
     "eig_cycle_end": ("kernels_common.hpp", "k_eigen.hip"),
@@ -304,7 +304,8 @@ def report_sum(s, parts):
 def make_solver(cfg, prec, args):
     import paper_1802_09277_amd as sth
     s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta,
-                   prec=prec, basis=args.basis, coarse_slabs=args.coarse_slabs, space_ratio=args.space_ratio)
+                   prec=prec, basis=args.basis, coarse_slabs=args.coarse_slabs, space_ratio=args.space_ratio,
+                   minres_iters=args.minres_iters)
     if args.no_speculate:
         s.speculate(False)
     return s
@@ -349,6 +350,9 @@ def main():
     ap.add_argument("--slabs", type=int, default=None,
                     help="profiling runs only: override the workload's slab count (the line then names a "
                          "different workload)")
+    ap.add_argument("--minres-iters", type=int, default=0,
+                    help="smoother slab inverse by this many MinRes iterations per temporal pair (Theorem 3.10 "
+                         "preconditioner; B-spline coefficient iteration only; 0: exact)")
     ap.add_argument("--space-ratio", type=float, default=0.0,
                     help="coarsen in space too where tau/h^2 >= this (B-spline coefficient iteration only; "
                          "0: time only)")
@@ -508,6 +512,7 @@ def main():
             "levels": levels,
             "coarse_slabs": coarse_slabs,
             "space_ratio": args.space_ratio,
+            "minres_iters": args.minres_iters,
             "level_elems": level_elems,
             "speculative_cycles": not args.no_speculate,
         },

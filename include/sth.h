@@ -112,6 +112,21 @@ typedef struct {
                            ones, i.e. the rediscretisations on the coarse
                            mesh with the finest sigma.  Requires
                            iterate_basis 0 (STH_EINVAL otherwise). */
+    int minres_iters;   /* slab inverse of the smoother (Section 3.3,
+                           Theorems 3.8 and 3.10): 0 (default) exact by fast
+                           diagonalisation; k > 0: through the temporal eigen
+                           form, each real eigenvalue's spatial system solved
+                           exactly and each conjugate pair's 2x2 block system
+                           by k iterations of MinRes (zero start) on the
+                           symmetric form of Theorem 3.10 with its block
+                           diagonal preconditioner P (applied exactly).  The
+                           preconditioned spectrum lies in [-1, -1/sqrt 2] u
+                           [1/sqrt 2, 1], so k = 12 reduces each block residual
+                           (P^{-1} norm) by 1e-4, the accuracy of Section 4.4,
+                           and k = 28 by 1e-10.  The coarsest level stays
+                           exact.  Requires iterate_basis 0 and the eigen
+                           form on every level (STH_EINVAL otherwise); at most
+                           200. */
 } sth_problem;
 
 /* Right-hand side as a sum of separable modes (host arrays):
@@ -190,7 +205,8 @@ int sth_apply(sth_handle* h, const double* u, double* y, void* stream);
 int sth_residual(sth_handle* h, const double* f, const double* u, double* r, void* stream);
 
 /* z <- D^{-1} r with D = diag(A_n): every slab inverted independently by
- * eq. equ:ST:generalDecompA (exact up to rounding for FP64 transforms). */
+ * eq. equ:ST:generalDecompA (exact up to rounding for FP64 transforms), or
+ * with minres_iters > 0 by the MinRes slab inverse of the smoother. */
 int sth_block_solve(sth_handle* h, const double* r, double* z, void* stream);
 
 /* `steps` damped block-Jacobi steps u <- u + omega D^{-1}(f - L_h u) with

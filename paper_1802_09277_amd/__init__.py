@@ -34,7 +34,8 @@ class Problem(ctypes.Structure):
                 ("n_slabs", ctypes.c_int), ("n_elem_t", ctypes.c_int), ("T", ctypes.c_double),
                 ("theta", ctypes.c_double), ("omega", ctypes.c_double), ("nu_pre", ctypes.c_int),
                 ("nu_post", ctypes.c_int), ("transform_prec", ctypes.c_int), ("coarse_slabs", ctypes.c_int),
-                ("iterate_basis", ctypes.c_int), ("temporal_form", ctypes.c_int), ("space_ratio", ctypes.c_double)]
+                ("iterate_basis", ctypes.c_int), ("temporal_form", ctypes.c_int), ("space_ratio", ctypes.c_double),
+                ("minres_iters", ctypes.c_int)]
 
 
 class RhsModes(ctypes.Structure):
@@ -134,7 +135,8 @@ TEMPORAL = {"eigen": 0, "schur": 1, "auto": 2}
 
 
 def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
-                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", space_ratio=0.0):
+                 nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", space_ratio=0.0,
+                 minres_iters=0):
     p = Problem()
     load_library().sth_problem_default(ctypes.byref(p))
     p.dim, p.n_elem, p.degree, p.n_slabs, p.n_elem_t = dim, n_elem, degree, n_slabs, n_elem_t
@@ -145,6 +147,7 @@ def make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omeg
     p.iterate_basis = BASIS[basis] if isinstance(basis, str) else int(basis)
     p.temporal_form = TEMPORAL[temporal] if isinstance(temporal, str) else int(temporal)
     p.space_ratio = float(space_ratio)
+    p.minres_iters = int(minres_iters)
     return p
 
 
@@ -229,13 +232,13 @@ class Solver:
 
     def __init__(self, dim, n_elem, degree, n_slabs, n_elem_t, T=1.0, theta=0.01, omega=0.5, nu_pre=1,
                  nu_post=1, prec="fp64", coarse_slabs=None, basis="nodal", temporal="auto", space_ratio=0.0,
-                 stream=None):
+                 minres_iters=0, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the HIP slab solver needs a gfx950 device")
         self.lib = load_library()
         self.problem = make_problem(dim, n_elem, degree, n_slabs, n_elem_t, T, theta, omega, nu_pre,
-                                    nu_post, prec, coarse_slabs, basis, temporal, space_ratio)
+                                    nu_post, prec, coarse_slabs, basis, temporal, space_ratio, minres_iters)
         self.shape = dict(dim=dim, n_elem=n_elem, degree=degree, n_slabs=n_slabs, n_elem_t=n_elem_t)
         self.coarse_slabs = self.problem.coarse_slabs
         h = ctypes.c_void_p()

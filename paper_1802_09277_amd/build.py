@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsth.so")
-SOURCES = ["setup.cpp", "k_residual.hip", "k_xform2d.hip", "k_xform_axis.hip", "k_xform_panel.hip", "k_eigen.hip", "k_misc.hip",
+SOURCES = ["setup.cpp", "k_residual.hip", "k_xform2d.hip", "k_xform_axis.hip", "k_xform_panel.hip", "k_eigen.hip", "k_misc.hip", "k_minres.hip",
            "runtime.hip", "server.cpp"]
 
 HIPCC_FLAGS = [

@@ -221,6 +221,40 @@ hipError_t launch_prolong(int Nt, const Transfer& tr, const double* e, double* u
 hipError_t launch_band_axis(const double* in, double* out, long outer, int n_in, int n_out, long inner,
                             const int* j0, const double* coef, int W, hipStream_t st);
 
+// ---- MinRes slab inverse (Theorems 3.8, 3.10) ------------------------------
+constexpr int kMrState = 13;    // doubles of MinRes state per (slab, pair) system
+struct TimeRowMix {             // out row t = sout[t] sum_t' M[t][t'] sin[t'] in row t'
+    double M[kNt * kNt];
+    double sin[kNt];
+    double sout[kNt];
+};
+struct PairOps {                // A_bar of the pairs (rows 2k, 2k+1 of a slab)
+    int npairs;
+    double alpha[kNt / 2];
+    double a11[kNt / 2], a12[kNt / 2], a21[kNt / 2], a22[kNt / 2];
+};
+struct PinvRows {               // P^{-1} per time row: scale / (mu + shift) in the eigenbasis
+    double scale[kNt];
+    double shift[kNt];
+};
+hipError_t launch_time_mix(const double* in, double* out, const TimeRowMix& m, long ns, int nt, long nx, int epi,
+                           double alpha, hipStream_t st);
+hipError_t launch_pair_apply(int dim, const double* z, double* q, const double* M1b, const double* K1b, int n, int p,
+                             long ns, int nt, const PairOps& ops, hipStream_t st);
+hipError_t launch_pinv_scale(double* t, long ns, int nt, long nx, int dim, const double* mu1, int n,
+                             const PinvRows& pr, hipStream_t st);
+// which 0: q.z into the state's slot, 1: v.z
+hipError_t launch_pair_dot(const double* a, const double* b, double* state, int which, long ns, int nt, int npairs,
+                           long nx, hipStream_t st);
+hipError_t launch_minres_init(double* state, long nsys, hipStream_t st);
+hipError_t launch_lanczos(const double* q, const double* vc, const double* vp, double* vn, const double* state,
+                          long ns, int nt, int npairs, long nx, hipStream_t st);
+hipError_t launch_minres_scalars(double* state, long nsys, hipStream_t st);
+hipError_t launch_minres_update(const double* zc, const double* w1, double* w2, double* y, const double* state,
+                                long ns, int nt, int npairs, long nx, hipStream_t st);
+hipError_t launch_pair_split(double* y, double* zc, double* w1, double* w2, double* vp, long ns, int nt, int npairs,
+                             long nx, hipStream_t st);
+
 // v[0..len) = val, skipped when skip is given and *skip != 0 (f32: v
 // addresses float data)
 hipError_t launch_fill(double* v, long len, double val, hipStream_t st, const int* skip = nullptr, int f32 = 0);

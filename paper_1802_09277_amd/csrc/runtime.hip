@@ -123,6 +123,18 @@ struct sth_handle {
     double* pco = nullptr;              //   and its pW coefficients
     double* cf = nullptr;               // right-hand side and iterate of the child's finest level
     double* cu = nullptr;
+    // MinRes slab inverse of the smoother (minres_iters > 0): per level the
+    // mixing into the temporal blocks (W, the pair rows scaled as in
+    // Theorem 3.10), back (V, the second row of a pair negated), the 2x2
+    // operators and the preconditioner's per-row shifts; level-0-sized
+    // vectors v_{j-1}, v_j, v_{j+1}, z_j, z_{j+1}, w_{j-1}, w_{j-2}, y and the
+    // per-system scalars
+    int minres = 0;
+    std::vector<TimeRowMix> mr_win, mr_vout;
+    std::vector<PairOps> mr_ops;
+    std::vector<PinvRows> mr_pinv;
+    double* mr[8] = {};
+    double* mrst = nullptr;
     double* partial = nullptr;
     double* dnorm = nullptr;            // squared norms (layout at kNormSlots)
     double* hnorm = nullptr;            // pinned, mapped, coherent host copies of dnorm
@@ -373,13 +385,129 @@ static int slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int
     return STH_OK;
 }
 
+// out = P^{-1} in per time row: the spatial transforms of the slab inverse
+// around a per-row scale / (mu + shift) in the eigenbasis (the exact inverse
+// of K_x + shift M_x, times scale); buf0 and buf1 are the work vectors
+static int pinv_apply(sth_handle* h, int lvl, const double* in, double* out, long ns, hipStream_t st) {
+    h->tlev = lvl;
+    const long n = h->n, rows = ns * h->Nt;
+    double* b0 = h->buf0;
+    double* b1 = h->buf1;
+    const double dof = (double)ns * slab_len(h);
+    int rc;
+    auto scale = [&](double* t) -> int {
+        Timed tm(h, STH_K_TIMEMIX, 2.0 * dof, 16.0 * dof, st);
+        HIPCHK(launch_pinv_scale(t, ns, h->Nt, h->Nx, h->dim, h->mu1, h->n, h->mr_pinv[lvl], st));
+        return STH_OK;
+    };
+    if (h->dim == 2 && xform2d_supported(h->np)) {
+        {
+            Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, 16.0 * dof, st);
+            if (h->prec == STH_BF16X3)
+                HIPCHK(launch_xform2d_bf16x3(0, in, b0, h->Ti, h->n, h->np, rows, 1.0, st));
+            else
+                HIPCHK(launch_xform2d(h->prec, 0, 0, in, b0, h->Tf, h->n, h->np, rows, 1.0, st));
+        }
+        if ((rc = scale(b0))) return rc;
+        Timed tm(h, STH_K_XFORM_2D, 4.0 * h->n * dof, 16.0 * dof, st);
+        if (h->prec == STH_BF16X3)
+            HIPCHK(launch_xform2d_bf16x3(0, b0, out, h->Tf, h->n, h->np, rows, 1.0, st));
+        else
+            HIPCHK(launch_xform2d(h->prec, 1, 0, b0, out, h->Tf, h->n, h->np, rows, 1.0, st));
+    } else if (h->dim == 2) {
+        const int pr = h->prec;
+        if ((rc = xform_x(h, pr, 0, in, b0, h->Tf, rows * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, pr, b0, b1, h->Tf, rows, n, st))) return rc;
+        if ((rc = scale(b1))) return rc;
+        if ((rc = xform_s(h, pr, b1, b0, h->Ti, rows, n, st))) return rc;
+        if ((rc = xform_x(h, pr, 0, b0, out, h->Ti, rows * n, 1.0, st))) return rc;
+    } else {
+        const int pr = h->prec;
+        if ((rc = xform_x(h, pr, 0, in, b0, h->Tf, rows * n * n, 1.0, st))) return rc;
+        if ((rc = xform_s(h, pr, b0, b1, h->Tf, rows * n, n, st))) return rc;      // y
+        if ((rc = xform_s(h, pr, b1, b0, h->Tf, rows, n * n, st))) return rc;      // z
+        if ((rc = scale(b0))) return rc;
+        if ((rc = xform_s(h, pr, b0, b1, h->Ti, rows, n * n, st))) return rc;      // z
+        if ((rc = xform_s(h, pr, b1, b0, h->Ti, rows * n, n, st))) return rc;      // y
+        if ((rc = xform_x(h, pr, 0, b0, out, h->Ti, rows * n * n, 1.0, st))) return rc;
+    }
+    return STH_OK;
+}
+
+// u = alpha A^{-1} in (epi 2) or u += alpha A^{-1} in (epi 1) on the ns slabs
+// of level lvl, A^{-1} through the temporal eigen form: g = W in (pair rows
+// scaled by |b2|, |b1|), the real rows' systems solved exactly by P^{-1},
+// each pair's symmetric system of Theorem 3.10 by h->minres MinRes
+// iterations preconditioned by P (all (slab, pair) systems together, each
+// with its own scalars), then u (+)= alpha V y with the second row of each
+// pair negated (the substitution of the theorem).  `in` may be buf1.
+static int minres_slab_inverse(sth_handle* h, int lvl, const double* in, double* u, int epi, double alpha, long ns,
+                               hipStream_t st) {
+    h->tlev = lvl;
+    const int nt = h->Nt, npairs = h->mr_ops[lvl].npairs;
+    const long nx = h->Nx, nsys = ns * npairs;
+    const double dof = (double)ns * slab_len(h);
+    double *vp = h->mr[0], *vc = h->mr[1], *vn = h->mr[2], *zc = h->mr[3], *zn = h->mr[4];
+    double *w1 = h->mr[5], *w2 = h->mr[6], *y = h->mr[7];
+    double* q = h->buf0;
+    int rc;
+    {
+        Timed tm(h, STH_K_TIMEMIX, 2.0 * nt * dof, 16.0 * dof, st);
+        HIPCHK(launch_time_mix(in, vc, h->mr_win[lvl], ns, nt, nx, 0, 1.0, st));
+    }
+    if ((rc = pinv_apply(h, lvl, vc, y, ns, st))) return rc;
+    if (npairs > 0) {
+        h->tlev = lvl;
+        const double pdof = (double)nsys * 2 * nx;
+        {
+            Timed tm(h, STH_K_OTHER, 0.0, 40.0 * pdof, st);
+            HIPCHK(launch_pair_split(y, zc, w1, w2, vp, ns, nt, npairs, nx, st));
+            HIPCHK(launch_pair_dot(vc, zc, h->mrst, 1, ns, nt, npairs, nx, st));
+            HIPCHK(launch_minres_init(h->mrst, nsys, st));
+        }
+        for (int it = 0; it < h->minres; ++it) {
+            h->tlev = lvl;
+            {
+                const double st_pts = std::pow(2.0 * h->p + 1.0, h->dim);
+                Timed tm(h, STH_K_RESIDUAL, pdof * 4.0 * st_pts, 16.0 * pdof, st);
+                HIPCHK(launch_pair_apply(h->dim, zc, q, h->M1b, h->K1b, h->n, h->p, ns, nt, h->mr_ops[lvl], st));
+            }
+            {
+                Timed tm(h, STH_K_OTHER, 8.0 * pdof, 56.0 * pdof, st);
+                HIPCHK(launch_pair_dot(q, zc, h->mrst, 0, ns, nt, npairs, nx, st));
+                HIPCHK(launch_lanczos(q, vc, vp, vn, h->mrst, ns, nt, npairs, nx, st));
+            }
+            if ((rc = pinv_apply(h, lvl, vn, zn, ns, st))) return rc;
+            h->tlev = lvl;
+            {
+                Timed tm(h, STH_K_OTHER, 8.0 * pdof, 56.0 * pdof, st);
+                HIPCHK(launch_pair_dot(vn, zn, h->mrst, 1, ns, nt, npairs, nx, st));
+                HIPCHK(launch_minres_scalars(h->mrst, nsys, st));
+                HIPCHK(launch_minres_update(zc, w1, w2, y, h->mrst, ns, nt, npairs, nx, st));
+            }
+            std::swap(w1, w2);          // w_{j-1} <- w_j, w_{j-2} <- w_{j-1}
+            double* t = vp;             // v_{j-1} <- v_j, v_j <- v_{j+1}
+            vp = vc;
+            vc = vn;
+            vn = t;
+            std::swap(zc, zn);
+        }
+    }
+    Timed tm(h, STH_K_TIMEMIX, 2.0 * nt * dof, (epi == 1 ? 24.0 : 16.0) * dof, st);
+    HIPCHK(launch_time_mix(y, u, h->mr_vout[lvl], ns, nt, nx, epi == 1 ? 1 : 0, alpha, st));
+    return STH_OK;
+}
+
 // one damped block-Jacobi step on level lvl; zero_guess: u is taken as 0
 static int smooth_step(sth_handle* h, int lvl, const double* f, double* u, bool zero_guess, hipStream_t st) {
     long ns = h->lev_S[lvl];
-    if (zero_guess) return slab_inverse(h, lvl, f, u, 2, h->omega, 0, ns, st);
+    if (zero_guess)
+        return h->minres ? minres_slab_inverse(h, lvl, f, u, 2, h->omega, ns, st)
+                         : slab_inverse(h, lvl, f, u, 2, h->omega, 0, ns, st);
     int rc = residual(h, lvl, f, u, h->buf1, 0, ns, 1.0, st);
     if (rc) return rc;
-    return slab_inverse(h, lvl, h->buf1, u, 1, h->omega, 0, ns, st);
+    return h->minres ? minres_slab_inverse(h, lvl, h->buf1, u, 1, h->omega, ns, st)
+                     : slab_inverse(h, lvl, h->buf1, u, 1, h->omega, 0, ns, st);
 }
 
 // exact solve of the coarsest level: slab-wise forward substitution
@@ -896,6 +1024,7 @@ static Problem to_problem(const sth_problem* p) {
     q.basis = p->iterate_basis;
     q.temporal = p->temporal_form;
     q.space_ratio = p->space_ratio;
+    q.minres_iters = p->minres_iters;
     return q;
 }
 
@@ -984,6 +1113,8 @@ static size_t workspace_of(Problem q) {
         total += vecsl_bytes * (size_t)S * slab;
     }
     total += sizeof(double) * (kNormBlocks + kNormSlots + L * 2 * kNt * kNt) + sizeof(TimeMix) * L;
+    if (q.minres_iters > 0)   // eight MinRes vectors of the finest level and the per-system scalars
+        total += sizeof(double) * (size_t)q.n_slabs * slab * 8 + sizeof(double) * q.n_slabs * (kNt / 2) * kMrState;
     if (own > 0) {
         // the coarse-mesh problem, its finest right-hand side and iterate,
         // and the band tables of P_x
@@ -1325,6 +1456,64 @@ static int setup_problem(Problem q, hipStream_t s, sth_handle** out) {
         hipMemcpyAsync(h->dktmt, ktmt.data(), ktmt.size() * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(STH_EHIP, "upload of the setup failed");
+    if (q.minres_iters > 0) {
+        // the temporal blocks of every level: pairs (alpha, beta_1, beta_2)
+        // in the leading 2x2 blocks, real eigenvalues after them
+        h->minres = q.minres_iters;
+        int max_pairs = 0;
+        for (int l = 0; l < h->L; ++l) {
+            const TimeMix& tm = h->mixes[l];
+            if (tm.schur)
+                return cleanup(STH_EINVAL, "the MinRes slab inverse needs the temporal eigen form on every level "
+                                           "(the automatic form chose the real Schur form)");
+            PairOps ops{};
+            TimeRowMix win{}, vout{};
+            PinvRows pr{};
+            int np = 0;
+            while (2 * np + 1 < h->Nt && tm.zo[2 * np] != 0.0) ++np;
+            for (int k = np; 2 * k + 1 < h->Nt; ++k)
+                if (tm.zo[2 * k] != 0.0 || tm.zo[2 * k + 1] != 0.0)
+                    return cleanup(STH_EINVAL, "temporal eigen form: complex pairs are not the leading blocks");
+            ops.npairs = np;
+            for (int t = 0; t < h->Nt; ++t) {
+                win.sin[t] = 1.0;
+                win.sout[t] = 1.0;
+                vout.sin[t] = 1.0;
+                vout.sout[t] = 1.0;
+                pr.scale[t] = 1.0;
+                pr.shift[t] = tm.zd[t];              // a real eigenvalue: K_x + lambda M_x
+                for (int j = 0; j < h->Nt; ++j) {
+                    win.M[t * kNt + j] = tm.W[t * kNt + j];
+                    vout.M[t * kNt + j] = tm.V[t * kNt + j];
+                }
+            }
+            for (int k = 0; k < np; ++k) {
+                const double a = tm.zd[2 * k], b1 = tm.zo[2 * k], b2 = tm.zo[2 * k + 1];
+                const double s = std::sqrt(std::fabs(b1 * b2));
+                ops.alpha[k] = a;
+                ops.a11[k] = std::fabs(b2);
+                ops.a12[k] = -b1 * std::fabs(b2);
+                ops.a21[k] = std::fabs(b1) * b2;
+                ops.a22[k] = -std::fabs(b1);
+                win.sout[2 * k] = std::fabs(b2);
+                win.sout[2 * k + 1] = std::fabs(b1);
+                pr.scale[2 * k] = 1.0 / std::fabs(b2);
+                pr.scale[2 * k + 1] = 1.0 / std::fabs(b1);
+                pr.shift[2 * k] = pr.shift[2 * k + 1] = a + s;
+                vout.sin[2 * k + 1] = -1.0;
+            }
+            h->mr_ops.push_back(ops);
+            h->mr_win.push_back(win);
+            h->mr_vout.push_back(vout);
+            h->mr_pinv.push_back(pr);
+            max_pairs = std::max(max_pairs, np);
+        }
+        const size_t vlen = (size_t)h->lev_S[0] * slab_len(h);
+        for (double*& v : h->mr)
+            if (!dalloc(&v, vlen)) return cleanup(STH_ENOMEM, "device allocation failed");
+        if (!dalloc(&h->mrst, (size_t)h->lev_S[0] * std::max(max_pairs, 1) * kMrState))
+            return cleanup(STH_ENOMEM, "device allocation failed");
+    }
     if (own > 0) {
         if ((h->L != own)) return cleanup(STH_EINVAL, "level count of the spatial mesh");
         const int rc = attach_coarse_space(h, q, s);
@@ -1460,6 +1649,7 @@ int sth_residual(sth_handle* h, const double* f, const double* u, double* r, voi
 int sth_block_solve(sth_handle* h, const double* r, double* z, void* stream) {
     if (!h || !r || !z) return fail(STH_EINVAL, "null argument");
     if (r == h->buf0 || z == h->buf0) return fail(STH_EINVAL, "aliasing");
+    if (h->minres) return minres_slab_inverse(h, 0, r, z, 2, 1.0, h->lev_S[0], (hipStream_t)stream);
     return slab_inverse(h, 0, r, z, 2, 1.0, 0, h->lev_S[0], (hipStream_t)stream);
 }
 
@@ -2383,7 +2573,10 @@ int sth_destroy(sth_handle* h) {
     // graph first: its nodes reference the buffers below
     drop_graph(h);
     if (h->child) sth_destroy(h->child);
-    for (void* q : {(void*)h->rj0, (void*)h->pj0, (void*)h->rco, (void*)h->pco, (void*)h->cf, (void*)h->cu})
+    for (void* q : {(void*)h->rj0, (void*)h->pj0, (void*)h->rco, (void*)h->pco, (void*)h->cf, (void*)h->cu,
+                    (void*)h->mrst})
+        if (q) (void)hipFree(q);
+    for (double* q : h->mr)
         if (q) (void)hipFree(q);
     double* ptrs[] = {h->Tf, h->Ti, h->mu1, h->M1b, h->K1b, h->buf0, h->buf1, h->partial, h->dnorm, h->dktmt,
                       h->Cf, h->Ci, h->Gf, h->e0, h->e1, h->e2, h->e3, h->cpartial, h->kv, h->kz, h->kc,

@@ -43,9 +43,9 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 std::string problem_key(const sth_problem& p) {
     char buf[384];
-    std::snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%d|%d|%d|%.17g", p.dim, p.n_elem,
+    std::snprintf(buf, sizeof buf, "%d|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%d|%d|%d|%.17g|%d", p.dim, p.n_elem,
                   p.degree, p.n_slabs, p.n_elem_t, p.T, p.theta, p.omega, p.nu_pre, p.nu_post, (int)p.transform_prec,
-                  p.coarse_slabs, p.iterate_basis, p.temporal_form, p.space_ratio);
+                  p.coarse_slabs, p.iterate_basis, p.temporal_form, p.space_ratio, p.minres_iters);
     return buf;
 }
 

@@ -728,6 +728,11 @@ std::string validate(const Problem& p) {
     if (!(p.space_ratio >= 0.0) || !std::isfinite(p.space_ratio)) os << "space_ratio must be finite and >= 0; ";
     if (p.space_ratio > 0.0 && p.basis != 0)
         os << "coarsening in space runs in the B-spline coefficient iteration (iterate_basis 0); ";
+    if (p.minres_iters < 0 || p.minres_iters > 200) os << "minres_iters must be in 0..200; ";
+    if (p.minres_iters > 0 && p.basis != 0)
+        os << "the MinRes slab inverse runs in the B-spline coefficient iteration (iterate_basis 0); ";
+    if (p.minres_iters > 0 && p.temporal == 1)
+        os << "the MinRes slab inverse needs the temporal eigen form (temporal_form 0 or 2); ";
     if (os.str().empty() && p.n_elem + p.degree - 2 >= 1) {
         double len = double(p.n_slabs) * (p.n_elem_t + p.degree);
         for (int a = 0; a < p.dim; ++a) len *= (p.n_elem + p.degree - 2);
@@ -813,7 +818,22 @@ static int eigen_form(TemporalLevel& L, std::string& err) {
             }
             used[i] = used[j] = 1;
             int ip = lam[i].imag() > 0 ? i : j;       // a + ib with b > 0
-            std::vector<cd>& x = vec[ip];
+            // canonical eigenvector: unit 2-norm, its largest-modulus entry
+            // real and positive (the first of equal ones), so that the 2x2
+            // spatial block systems of the pair depend on the pencil alone
+            std::vector<cd> x = vec[ip];
+            {
+                int imax = 0;
+                for (int r = 1; r < Nt; ++r) if (std::abs(x[r]) > std::abs(x[imax])) imax = r;
+                const cd ph = std::conj(x[imax]) / std::abs(x[imax]);
+                double nn = 0.0;
+                for (int r = 0; r < Nt; ++r) {
+                    x[r] *= ph;
+                    nn += std::norm(x[r]);
+                }
+                nn = std::sqrt(nn);
+                for (int r = 0; r < Nt; ++r) x[r] /= nn;
+            }
             double a = lam[ip].real(), b = lam[ip].imag();
             // K (xr + i xi) = (a + ib) M (xr + i xi)  =>  K V = M V [[a, b], [-b, a]]
             for (int r = 0; r < Nt; ++r) {

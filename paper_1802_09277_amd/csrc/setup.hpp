@@ -55,6 +55,7 @@ struct Problem {
     int temporal = 2;      // 0 diagonalisation, 1 real Schur, 2 automatic
     double space_ratio = 0.0;   // > 0: coarsen in space too where tau_l / h_l^2 >= space_ratio
     int level_cap = 0;     // > 0: at most this many levels of this spatial mesh
+    int minres_iters = 0;  // > 0: smoother slab inverse by this many MinRes iterations per pair
     int n() const { return n_elem + degree - 2; }
     int Nt() const { return n_elem_t + degree; }
     double tau() const { return T / n_slabs; }

@@ -262,3 +262,19 @@ def test_load_vectors_match_oracle(dim):
             outer = np.multiply.outer(parts[a], outer)
         f = f + amp[m] * np.multiply.outer(tpr, outer).ravel()
     assert np.allclose(f, f_or, rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("bad", [dict(minres_iters=-1), dict(minres_iters=201), dict(minres_iters=12, basis="eigen"),
+                                 dict(minres_iters=12, temporal="schur")])
+def test_minres_options_rejected(bad):
+    kw = dict(dim=2, n_elem=4, degree=2, n_slabs=4, n_elem_t=2)
+    kw.update(bad)
+    with pytest.raises(sth.StatusError) as ei:
+        sth.workspace_bytes(**kw)
+    assert ei.value.name == "STH_EINVAL"
+
+
+def test_workspace_with_minres_slab_inverse():
+    kw = dict(dim=2, n_elem=16, degree=2, n_slabs=16, n_elem_t=2, coarse_slabs=1)
+    vec = 16 * 4 * 16 * 16 * 8
+    assert sth.workspace_bytes(minres_iters=12, **kw) >= sth.workspace_bytes(**kw) + 8 * vec
