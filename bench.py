@@ -41,7 +41,7 @@ PEAKS = {  # MI355X published peaks
 CLASS_BOUND = {"residual": "hbm", "xform_x": "mfma", "xform_s": "mfma", "xform_axis": "mfma", "timemix": "hbm",
                "restrict": "hbm", "prolong": "hbm", "norm": "hbm", "other": "hbm", "xform_2d": "mfma",
                "eig_smooth": "hbm", "eig_resid": "hbm", "resnorm": "mfma", "eig_cycle_end": "hbm",
-               "eig_cycle_close": "hbm", "eig_coarse": "hbm"}
+               "eig_cycle_close": "hbm", "eig_coarse": "hbm", "minres": "hbm"}
 
 
 def log(*a):

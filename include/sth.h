@@ -351,7 +351,8 @@ typedef enum {
     STH_K_EIG_CYCLE_CLOSE = 13, /* the same pass preceded by the prolongation and the
                                  post-smoothing step of the finest level */
     STH_K_EIG_COARSE = 14,  /* eigenbasis iteration: the two coarsest levels in one pass */
-    STH_K_COUNT = 15
+    STH_K_MINRES = 15,      /* MinRes slab inverse: the 2x2 block operator (tensor stencils) */
+    STH_K_COUNT = 16
 } sth_kernel_class;
 
 /* Record an event pair around every launch of the kernel classes whose bit

@@ -19,7 +19,7 @@ STATUS = {0: "STH_OK", -1: "STH_EINVAL", -2: "STH_ENOMEM", -3: "STH_EHIP", -4: "
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 KCLASS = {"residual": 0, "xform_x": 1, "xform_s": 2, "timemix": 3, "restrict": 4, "prolong": 5,
           "norm": 6, "other": 7, "xform_2d": 8, "eig_smooth": 9, "eig_resid": 10, "resnorm": 11,
-          "eig_cycle_end": 12, "eig_cycle_close": 13, "eig_coarse": 14}
+          "eig_cycle_end": 12, "eig_cycle_close": 13, "eig_coarse": 14, "minres": 15}
 
 
 class StatusError(RuntimeError):

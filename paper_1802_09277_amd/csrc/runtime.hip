@@ -469,7 +469,7 @@ static int minres_slab_inverse(sth_handle* h, int lvl, const double* in, double*
             h->tlev = lvl;
             {
                 const double st_pts = std::pow(2.0 * h->p + 1.0, h->dim);
-                Timed tm(h, STH_K_RESIDUAL, pdof * 4.0 * st_pts, 16.0 * pdof, st);
+                Timed tm(h, STH_K_MINRES, pdof * 4.0 * st_pts, 16.0 * pdof, st);
                 HIPCHK(launch_pair_apply(h->dim, zc, q, h->M1b, h->K1b, h->n, h->p, ns, nt, h->mr_ops[lvl], st));
             }
             {
