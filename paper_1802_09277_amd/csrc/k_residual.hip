@@ -362,8 +362,15 @@ static hipError_t residual2d_nt(int Nt, int n, const double* M1b, const double* 
 // y pass and the temporal contraction.  The next input row is loaded while
 // the current one is processed.  With `partial` the block's sum of squares
 // of r goes to partial[blockIdx.x] (fixed order).
+// waves per SIMD the marching kernel asks for: 4 (at most 128 VGPRs) where
+// its windows and time rows are small enough to fit them without spilling
+// more than a few registers, else what the compiler picks
 template <int NT, int P>
-__global__ __launch_bounds__(256) void k_residual2d_march(int n, int nxc, int nyr, int YR, long nwaves,
+constexpr int march_waves() { return NT <= 4 && (NT + 1) * (2 * P + 1) <= 20 ? 4 : 1; }
+
+template <int NT, int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(march_waves<NT, P>())))
+void k_residual2d_march(int n, int nxc, int nyr, int YR, long nwaves,
                                                           const double* __restrict__ M1b,
                                                           const double* __restrict__ K1b,
                                                           const double* __restrict__ ktmt,
@@ -407,13 +414,27 @@ __global__ __launch_bounds__(256) void k_residual2d_march(int n, int nxc, int ny
         for (int tr = 0; tr < NR; ++tr)
 #pragma unroll
             for (int k = 0; k < B; ++k) wa[tr][k] = wb[tr][k] = 0.0;
+        // f of output row yo, loaded one input row ahead of its use
+        double fv[NT];
+        auto load_f = [&](int yo) {
+            const bool ok = f && xout && yo >= yb && yo < ye;
+            const long off = s * slab + (long)yo * n + x;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) fv[t] = ok ? f[off + (long)t * Nx] : 0.0;
+        };
         load(yb - P);
+        load_f(yb - 2 * P);
 #pragma unroll 1
         for (int y = yb - P; y < ye + P; ++y) {
-            double cv[NR];
+            double cv[NR], fc[NT];
 #pragma unroll
             for (int tr = 0; tr < NR; ++tr) cv[tr] = v[tr];
-            if (y + 1 < ye + P) load(y + 1);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) fc[t] = fv[t];
+            if (y + 1 < ye + P) {
+                load(y + 1);
+                load_f(y + 1 - P);
+            }
             // x pass of input row y for every time row, into the windows
             // (lanes whose neighbours fall outside the wave are not output)
 #pragma unroll
@@ -466,7 +487,7 @@ __global__ __launch_bounds__(256) void k_residual2d_march(int n, int nxc, int ny
                     const long off = s * slab + (long)yo * n + x;
 #pragma unroll
                     for (int t = 0; t < NT; ++t) {
-                        const double val = (f ? f[off + (long)t * Nx] : 0.0) + sign * acc[t];
+                        const double val = fc[t] + sign * acc[t];
                         r[off + (long)t * Nx] = val;
                         ssq += val * val;
                     }

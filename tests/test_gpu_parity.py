@@ -505,6 +505,8 @@ def test_deep_wide_shape_cycles(temporal):
 MARCH_SHAPES = {
     "2d_n128_p1": dict(dim=2, n_elem=129, degree=1, n_slabs=3, n_elem_t=2),
     "2d_n130_p2": dict(dim=2, n_elem=130, degree=2, n_slabs=3, n_elem_t=2),
+    # N_t = 3, p = 2: the instantiation of the 2-D p = 2 one-time-element workloads
+    "2d_n128_p2_nt3": dict(dim=2, n_elem=128, degree=2, n_slabs=3, n_elem_t=1),
     "2d_n181_p3": dict(dim=2, n_elem=180, degree=3, n_slabs=2, n_elem_t=1),
 }
 
