@@ -336,7 +336,7 @@ def main():
     ap.add_argument("--basis", default="eigen", choices=["nodal", "eigen"],
                     help="iterate on B-spline coefficients or in the spatial eigenbasis (same iterates)")
     ap.add_argument("--coarse-slabs", type=int, default=None,
-                    help="coarsest multigrid level: at most this many slabs (library default 64)")
+                    help="coarsest multigrid level: at most this many slabs (library default 128)")
     ap.add_argument("--cpu-sample-slabs", type=int, default=None,
                     help="slabs of the oracle's forward substitution timed for the CPU baseline")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,

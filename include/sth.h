@@ -142,10 +142,11 @@ typedef struct {
 } sth_rhs_modes;
 
 /* Fills p with the defaults of Section 4.4: theta 0.01, omega 1/2, T 1,
- * V(1,1), FP64 transforms, the automatic temporal form and coarse_slabs 64:
+ * V(1,1), FP64 transforms, the automatic temporal form and coarse_slabs 128:
  * the exact coarsest-level solve runs parallel in time, so a level of up to
- * about 256 compute units / N_t slabs is cheaper to solve exactly than to
- * coarsen further (the shape fields are left at zero). */
+ * 128 slabs is cheaper to solve exactly than to coarsen further, and the
+ * eigenbasis iteration then takes it together with the level above it in one
+ * pass (the shape fields are left at zero). */
 void sth_problem_default(sth_problem* p);
 
 /* Device bytes that sth_setup would allocate for this problem (factors,

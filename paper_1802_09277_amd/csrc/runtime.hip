@@ -1039,7 +1039,7 @@ void sth_problem_default(sth_problem* p) {
     p->nu_pre = 1;
     p->nu_post = 1;
     p->transform_prec = STH_FP64;
-    p->coarse_slabs = 64;            // about the compute units per time function (256 / N_t)
+    p->coarse_slabs = 128;           // exact parallel-in-time solve; with the level above: one pass
     p->iterate_basis = 0;
     p->temporal_form = 2;
 }

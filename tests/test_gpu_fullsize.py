@@ -166,12 +166,18 @@ def _rhs_samples(name):
     return data[:, 0].astype(np.int64), data[:, 1]
 
 
+# coarsest level per workload: the library default (128 slabs) except for
+# C3, whose 128 slabs would then be a single exact solve; 64 keeps its two
+# multigrid levels
+COARSE = {"C3": 64}
+
+
 def _solve_large(cfg, basis, prec, rtol):
     import paper_1802_09277_amd as sth
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         s = sth.Solver(cfg.dim, cfg.n_elem, cfg.degree, cfg.n_slabs, cfg.n_elem_t, cfg.T, cfg.theta, prec=prec,
-                       basis=basis, stream=stream)
+                       basis=basis, coarse_slabs=COARSE.get(cfg.name), stream=stream)
         f = s.new_vector()
         s.load_rhs(cfg.modes(), f, stream=stream)
         u = s.new_vector()

@@ -186,8 +186,9 @@ def test_level_count():
     assert sth.host_factors(n_slabs=16, coarse_slabs=1, **kw)["n_levels"] == 5
     assert sth.host_factors(n_slabs=12, coarse_slabs=1, **kw)["n_levels"] == 3
     assert sth.host_factors(n_slabs=1, coarse_slabs=1, **kw)["n_levels"] == 1
-    assert sth.host_factors(n_slabs=256, **kw)["n_levels"] == 3          # default: coarsest <= 64 slabs
-    assert sth.host_factors(n_slabs=64, **kw)["n_levels"] == 1
+    assert sth.host_factors(n_slabs=256, **kw)["n_levels"] == 2          # default: coarsest <= 128 slabs
+    assert sth.host_factors(n_slabs=1024, **kw)["n_levels"] == 4
+    assert sth.host_factors(n_slabs=128, **kw)["n_levels"] == 1
 
 
 def test_guard_mt_not_positive():
