@@ -214,7 +214,8 @@ struct sth_handle {
         hipStream_t st = nullptr;
         double rtol = 0.0, fn = 1.0, rn = 0.0, prev = 0.0;
         int maxit = 0, it = 0, outer = 0, growth = 0;
-        int phase = 0;                  // 0 outer residual norm enqueued, 1 inner solve running, 2 done
+        int phase = 0;                  // 0 outer residual norm enqueued, 1 inner solve running, 2 done,
+                                        // 3 ||f|| and whether u is nonzero enqueued
     } mx;
     // speculative cycles (eigenbasis, fused cycle close)
     bool speculate = true;
@@ -1434,7 +1435,7 @@ static int setup_problem(Problem q, hipStream_t s, sth_handle** out) {
     }
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc((void**)&h->hnorm, kNormSlots * sizeof(double), mapped) != hipSuccess ||
-        hipHostMalloc((void**)&h->hflag, 4 * sizeof(int), mapped) != hipSuccess ||
+        hipHostMalloc((void**)&h->hflag, 5 * sizeof(int), mapped) != hipSuccess ||
         hipHostMalloc((void**)&h->hseq, 2 * sizeof(int), mapped) != hipSuccess)
         return cleanup(STH_ENOMEM, "pinned host allocation failed");
     h->hseq[0] = h->hseq[1] = 0;
@@ -1822,7 +1823,10 @@ static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rt
         // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
         const long rows = h->lev_S[0] * h->Nt;
         h->ecur[0] = 0;
-        // (FP32 eigenbasis vectors: only in inner solves, whose f is buf1)
+        // (FP32 eigenbasis vectors: only in inner solves, whose f is the
+        // outer residual in buf1 or the caller's f; a 3-D forward transform
+        // into float data uses buf1 as its second work vector after its
+        // first step has read f)
         if ((rc = spatial_apply(h, FWD_U, f, h->e0, rows, h->buf0, st, nullptr, v.tprec, 0,
                                 h->f32 ? h->buf1 : nullptr, h->f32 ? 2 : 0)))
             return rc;
@@ -2267,13 +2271,50 @@ static int mixed_begin(sth_handle* h, const double* f, double* u, double rtol, i
         HIPCHK(launch_norm2(f, len, h->partial, h->dnorm + kMixF, st));
     }
     HIPCHK(hipMemcpyAsync(h->hnorm + kMixF, h->dnorm + kMixF, sizeof(double), hipMemcpyDeviceToHost, st));
-    return mixed_residual(h);
+    // whether u has a nonzero entry: from zero (the usual start) the first
+    // outer residual is f itself, and the first inner solve starts on f
+    {
+        Timed tm(h, STH_K_OTHER, 0.0, 8.0 * len, st);
+        HIPCHK(launch_any_nonzero(u, len, h->dgo + 4, st));
+    }
+    HIPCHK(hipMemcpyAsync(h->hflag + 4, h->dgo + 4, sizeof(int), hipMemcpyDeviceToHost, st));
+    m.phase = 3;
+    return STH_OK;
+}
+
+// the inner solve of L e = r to eta ||r|| (at least what the tolerance needs,
+// with a margin), added into u; r is the outer residual (buf1) or f
+static int mixed_inner(sth_handle* h, const double* r, double rn) {
+    auto& m = h->mx;
+    const double eta = std::max(mixed_inner_eta(h->prec), 0.5 * m.rtol * m.fn / rn);
+    int rc = solve_begin_impl(h, r, m.u, eta, m.maxit - m.it, m.st, &rn, h->prec);
+    if (rc) return rc;
+    m.phase = 1;
+    return STH_OK;
 }
 
 static int mixed_continue(sth_handle* h, bool* more) {
     auto& m = h->mx;
     *more = false;
     if (m.phase == 2) return STH_OK;
+    if (m.phase == 3) {
+        m.fn = std::sqrt(h->hnorm[kMixF]);
+        if (m.fn == 0.0) m.fn = 1.0;
+        if (h->hflag[4] != 0) {
+            // nonzero initial guess: its residual first
+            m.phase = 0;
+            *more = true;
+            return mixed_residual(h);
+        }
+        const double rn = std::sqrt(h->hnorm[kMixF]);
+        m.rn = m.prev = rn;
+        if (!std::isfinite(rn) || !(rn > m.rtol * m.fn) || m.maxit < 1) {
+            m.phase = 2;
+            return STH_OK;
+        }
+        *more = true;
+        return mixed_inner(h, m.f, rn);
+    }
     if (m.phase == 1) {
         bool inner_more = false;
         int rc = solve_continue_impl(h, &inner_more);
@@ -2300,14 +2341,8 @@ static int mixed_continue(sth_handle* h, bool* more) {
         m.phase = 2;
         return STH_OK;
     }
-    // inner solve of L e = r to eta ||r|| (at least what the tolerance
-    // needs, with a margin), added into u
-    const double eta = std::max(mixed_inner_eta(h->prec), 0.5 * m.rtol * m.fn / rn);
-    int rc = solve_begin_impl(h, h->buf1, m.u, eta, m.maxit - m.it, m.st, &rn, h->prec);
-    if (rc) return rc;
-    m.phase = 1;
     *more = true;
-    return STH_OK;
+    return mixed_inner(h, h->buf1, rn);
 }
 
 static int mixed_result(sth_handle* h, int* iters, double* relres) {

@@ -136,3 +136,27 @@ def test_c3_shaped_l2_error_against_exact_solution(basis, prec):
     assert abs(e["L2"] - e_direct["L2"]) <= 1e-5 * e_direct["L2"]
     assert abs(e["dG"] - e_direct["dG"]) <= 1e-5 * e_direct["dG"]
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_solve_from_nonzero_guess(prec):
+    """The defect correction from a nonzero initial guess (its residual
+    first) reaches the FP64 tolerance and the direct solution; from zero the
+    first outer residual is f itself."""
+    import paper_1802_09277_amd as sth
+    name = "2d_fused_f32"
+    shape, cs = SHAPES[name]
+    print(f"[gpu-precision] {prec} mixed solve from a nonzero guess {shape}", flush=True)
+    prob, mg = oracle(name)
+    f = assemble_rhs(prob, W.random_modes(8, prob.dim))
+    ud = mg.levels[0].forward_substitution(f)
+    s = sth.Solver(**shape, prec=prec, coarse_slabs=cs, basis="eigen")
+    fd = torch.from_numpy(f).cuda()
+    for u0 in (np.zeros_like(f), W.random_vector(9, prob.n_dof)):
+        u = torch.from_numpy(u0.copy()).cuda()
+        it, rr, _ = s.solve(fd, u, rtol=1e-10, maxit=80)
+        torch.cuda.synchronize()
+        err = np.linalg.norm(u.cpu().numpy() - ud) / np.linalg.norm(ud)
+        print(f"  |u0| {np.linalg.norm(u0):.2e}: {it} cycles, relres {rr:.2e}, error {err:.2e}")
+        assert rr <= 1e-10 and err <= 1e-7
+    s.close()
