@@ -289,11 +289,15 @@ static void xform_x_ct(int epi, dim3 grid, hipStream_t st, const double* in, dou
         hipLaunchKernelGGL((k_xform_x<CT, 2>), grid, dim3(256), 0, st, in, out, T, n, np, lines, alpha, guard);
 }
 
+bool xform_split_supported(int n) { return xform_panel_split_supported(n); }
+
 hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st, const int* guard) {
+                          long lines, double alpha, hipStream_t st, const int* guard, int sym) {
     if (lines <= 0) return hipSuccess;
     if (epi < 0 || epi > 2 || prec < 0 || prec > 2) return hipErrorInvalidValue;
-    if (xform_panel_supported(np)) return launch_xform_panel_x(prec, epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (xform_panel_supported(np))
+        return launch_xform_panel_x(prec, epi, in, out, T, n, np, lines, alpha, st, guard, sym);
+    if (sym) return hipErrorInvalidValue;
     dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
     if (prec == 0) xform_x_ct<double>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
     else if (prec == 1) xform_x_ct<float>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
@@ -307,11 +311,12 @@ hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, cons
 }
 
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st, const int* guard, int io_f32) {
+                          long nbatch, long inner, hipStream_t st, const int* guard, int io_f32, int sym) {
     if (nbatch <= 0) return hipSuccess;
     if (prec < 0 || prec > 2) return hipErrorInvalidValue;
     if (xform_panel_supported(np))
-        return launch_xform_panel_s(prec, in, out, T, n, np, nbatch, inner, st, guard, io_f32);
+        return launch_xform_panel_s(prec, in, out, T, n, np, nbatch, inner, st, guard, io_f32, sym);
+    if (sym) return hipErrorInvalidValue;
     if (io_f32) return hipErrorInvalidValue;      // FP32 storage: the panel kernels only
     int nib = (int)((inner + 63) / 64), njb = (np + 63) / 64;
     long blocks = nbatch * nib * njb;

@@ -52,7 +52,7 @@ template <typename C> static size_t panel_lds(int kp, int pw) {
     else return 2 * sizeof(unsigned short) * (size_t)pw * (kp + 4);
 }
 
-template <typename C, int PW, bool XAXIS, int EPI, typename TI, typename TO>
+template <typename C, int PW, bool XAXIS, int EPI, typename TI, typename TO, int SYM>
 __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restrict__ in, TO* __restrict__ out,
                                                                const double* __restrict__ T, int n, int np,
                                                                int npanel, long nrows, long inner, long ntiles,
@@ -62,8 +62,11 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
     constexpr int NJT = PW / 16;                 // column tiles per wave
     constexpr bool F64 = std::is_same<C, PanelF64>::value;
     constexpr bool BF = std::is_same<C, PanelBf16x3>::value;
-    const int ngroups = (np + 63) / 64;          // groups of four chunks of 16 k
-    const int KP = 64 * ngroups;                 // panel rows (k), zero from np on
+    const int hn = n / 2;
+    // panel rows (k), zero from np on; with the even/odd split (np = n,
+    // n / 2 a multiple of 64) the forward transform sums over k < n / 2
+    const int KP = SYM == 1 ? hn : (SYM == 2 ? n : 64 * ((np + 63) / 64));
+    const int ngroups = KP / 64;                 // groups of four chunks of 16 k
     extern __shared__ double sm_raw[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lg = lane >> 4;
@@ -90,6 +93,9 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
         }
     }
     __syncthreads();
+    // forward split: columns [0, n / 2) are even modes, fed x_k + x_{n-1-k};
+    // columns [n / 2, n) odd modes, fed x_k - x_{n-1-k}
+    const double sgn = (SYM == 1 && j0 >= hn) ? -1.0 : 1.0;
     // tiles: x axis, tile t = lines 16t..16t+15; strided axis, tile t =
     // (batch t / itb, columns 16 (t % itb) .. +15) with itb = ceil(inner / 16)
     const long itb = XAXIS ? 1 : (inner + 15) / 16;
@@ -111,167 +117,201 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
         }
         const long rs = XAXIS ? n : 1, ks = XAXIS ? 1 : inner;
         const bool row_ok = lr < rows_left;
-        // lane (lr, lg) holds k = 64 gi + 16 c + 4 lg + e of row lr; the loads
-        // of group gi + 1 are in flight while group gi is in the MFMAs
-        auto load = [&](int gi, double (&a)[4][4]) {
+        // lane (lr, lg) holds k = 64 gi + 16 c + 4 lg + e of row lr.  The
+        // loads of group gi + 1 go to ra (and, folding, rb: x_{n-1-k}) and
+        // are in flight while group gi is in the MFMAs; only then are they
+        // converted (and folded) into cur, held in the compute precision
+        // (FP32 for the FP32 and BF16x3 kernels).
+        using DT = typename std::conditional<F64, double, float>::type;
+        TI ra[4][4], rb[SYM == 1 ? 4 : 1][4];
+        auto load = [&](int gi) {
             const int kb = 64 * gi + 4 * lg;
+            const int kend = SYM == 1 ? hn : n;
             const TI* p = in + rbase + lr * rs + (long)kb * ks;
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     // (16 c + e) ks is the same for every lane
-                    a[c][e] = (row_ok && kb + 16 * c + e < n) ? p[(long)(16 * c + e) * ks] : 0.0;
+                    const bool ok = row_ok && kb + 16 * c + e < kend;
+                    ra[c][e] = ok ? p[(long)(16 * c + e) * ks] : (TI)0;
+                    if constexpr (SYM == 1) {
+                        const TI* pm = in + rbase + lr * rs + (long)(n - 1 - kb) * ks;
+                        rb[c][e] = ok ? pm[-(long)(16 * c + e) * ks] : (TI)0;
+                    }
                 }
         };
-        double cur[4][4], nxt[4][4];
-        load(0, cur);
+        DT cur[4][4];
+        auto settle = [&]() {
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if constexpr (SYM == 1) cur[c][e] = (DT)((double)ra[c][e] + sgn * (double)rb[c][e]);
+                    else cur[c][e] = (DT)ra[c][e];
+                }
+        };
+        // output j0 + jl of tile row il (x axis: line 16 t + il; strided
+        // axis: column i0 + il) from v; with the inverse split v + w there and
+        // v - w at the mirrored output n - 1 - j
+        auto put = [&](TO* o, double v) {
+            if (EPI == 0) *o = v;
+            else if (EPI == 1) *o += alpha * v;
+            else *o = alpha * v;
+        };
+        auto emit = [&](int jl, int il, double v, double w) {
+            const int j = j0 + jl;
+            if (il >= rows_left || j >= n) return;
+            TO* o = XAXIS ? out + (t * 16 + il) * (long)n : out + bbase + i0 + il;
+            const long js = XAXIS ? 1 : inner;
+            if (SYM == 2) {
+                put(o + j * js, v + w);
+                put(o + (n - 1 - j) * js, v - w);
+            } else {
+                put(o + j * js, v);
+            }
+        };
+        load(0);
+        settle();
         if constexpr (BF) {
             const unsigned short* th = reinterpret_cast<const unsigned short*>(sm_raw);
             const unsigned short* tl = th + (size_t)pw * (KP + 4);
-            f4 acc[NJT];
+            f4 acc[NJT], acc2[SYM == 2 ? NJT : 1];
 #pragma unroll
             for (int jt = 0; jt < NJT; ++jt) acc[jt] = f4{0.f, 0.f, 0.f, 0.f};
+            if constexpr (SYM == 2) {
+#pragma unroll
+                for (int jt = 0; jt < NJT; ++jt) acc2[jt] = f4{0.f, 0.f, 0.f, 0.f};
+            }
+            auto mma = [&](int gi, auto& A) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    s4 dh, dl;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        unsigned short hi, lo;
+                        split_bf16(cur[c][e], &hi, &lo);
+                        dh[e] = (short)hi;
+                        dl[e] = (short)lo;
+                    }
+#pragma unroll
+                    for (int jt = 0; jt < NJT; ++jt) {
+                        const int o = (jt * 16 + lr) * (KP + 4) + 64 * gi + 16 * c + 4 * lg;
+                        const s4 bh = *reinterpret_cast<const s4*>(&th[o]);
+                        const s4 bl = *reinterpret_cast<const s4*>(&tl[o]);
+                        if (XAXIS) {
+                            A[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, bh, A[jt], 0, 0, 0);
+                            A[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, bl, A[jt], 0, 0, 0);
+                            A[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dl, bh, A[jt], 0, 0, 0);
+                        } else {
+                            A[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, dh, A[jt], 0, 0, 0);
+                            A[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bl, dh, A[jt], 0, 0, 0);
+                            A[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, dl, A[jt], 0, 0, 0);
+                        }
+                    }
+                    // keep each chunk's operand reads with its MFMAs
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
 #pragma unroll 1
             for (int gi = 0; gi < ngroups; ++gi) {
-                if (gi + 1 < ngroups) load(gi + 1, nxt);
+                if (gi + 1 < ngroups) load(gi + 1);
                 int nz = 0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) nz |= cur[c][e] != 0.0;
+                    for (int e = 0; e < 4; ++e) nz |= cur[c][e] != (DT)0;
                 if (__any(nz)) {                 // a group of zeros adds nothing
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        s4 dh, dl;
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            unsigned short hi, lo;
-                            split_bf16(cur[c][e], &hi, &lo);
-                            dh[e] = (short)hi;
-                            dl[e] = (short)lo;
-                        }
-#pragma unroll
-                        for (int jt = 0; jt < NJT; ++jt) {
-                            {
-                                const int o = (jt * 16 + lr) * (KP + 4) + 64 * gi + 16 * c + 4 * lg;
-                                const s4 bh = *reinterpret_cast<const s4*>(&th[o]);
-                                const s4 bl = *reinterpret_cast<const s4*>(&tl[o]);
-                                if (XAXIS) {
-                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, bh, acc[jt], 0, 0, 0);
-                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dh, bl, acc[jt], 0, 0, 0);
-                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(dl, bh, acc[jt], 0, 0, 0);
-                                } else {
-                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, dh, acc[jt], 0, 0, 0);
-                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bl, dh, acc[jt], 0, 0, 0);
-                                    acc[jt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(bh, dl, acc[jt], 0, 0, 0);
-                                }
-                            }
-                        }
-                        // keep each chunk's operand reads with its MFMAs
-                        __builtin_amdgcn_sched_barrier(0);
+                    if constexpr (SYM == 2) {
+                        // inverse split: even modes (k < n / 2) into acc, odd into acc2
+                        if (gi < ngroups / 2) mma(gi, acc);
+                        else mma(gi, acc2);
+                    } else {
+                        mma(gi, acc);
                     }
                 }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) cur[c][e] = nxt[c][e];
+                if (gi + 1 < ngroups) settle();
             }
             // D[4 lg + r][lr]: x axis (line, j), strided axis (j, i)
 #pragma unroll
-            for (int jt = 0; jt < NJT; ++jt) {
+            for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = 4 * lg + r;
-                    if (XAXIS) {
-                        const int j = j0 + jt * 16 + lr;
-                        if (m < rows_left && j < n) {
-                            TO* o = out + (t * 16 + m) * (long)n + j;
-                            const double v = (double)acc[jt][r];
-                            if (EPI == 0) *o = v;
-                            else if (EPI == 1) *o += alpha * v;
-                            else *o = alpha * v;
-                        }
-                    } else {
-                        const int j = j0 + jt * 16 + m;
-                        if (j < n && lr < rows_left) out[bbase + (long)j * inner + i0 + lr] = (double)acc[jt][r];
-                    }
-                }
-            }
+                for (int r = 0; r < 4; ++r)
+                    emit(XAXIS ? jt * 16 + lr : jt * 16 + 4 * lg + r, XAXIS ? 4 * lg + r : lr, (double)acc[jt][r],
+                         SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0);
+            (void)acc2;
         } else {
             using CT = typename std::conditional<F64, double, float>::type;
             using M = Mfma16<CT>;
             typedef typename M::acc_t acc_t;
             const CT* tp = reinterpret_cast<const CT*>(sm_raw);
-            acc_t acc[NJT];
+            acc_t acc[NJT], acc2[SYM == 2 ? NJT : 1];
 #pragma unroll
             for (int jt = 0; jt < NJT; ++jt) acc[jt] = acc_t{0, 0, 0, 0};
+            if constexpr (SYM == 2) {
+#pragma unroll
+                for (int jt = 0; jt < NJT; ++jt) acc2[jt] = acc_t{0, 0, 0, 0};
+            }
+            auto mma = [&](int gi, auto& A) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const CT d = (CT)cur[c][s];
+                        const CT* row = tp + (64 * gi + 16 * c + 4 * lg + s) * pw + lr;
+#pragma unroll
+                        for (int jt = 0; jt < NJT; ++jt) {
+                            const CT w = row[jt * 16];
+                            A[jt] = XAXIS ? M::op(d, w, A[jt]) : M::op(w, d, A[jt]);
+                        }
+                    }
+                    // keep each chunk's operand reads with its MFMAs
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
 #pragma unroll 1
             for (int gi = 0; gi < ngroups; ++gi) {
-                if (gi + 1 < ngroups) load(gi + 1, nxt);
+                if (gi + 1 < ngroups) load(gi + 1);
                 int nz = 0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) nz |= cur[c][e] != 0.0;
+                    for (int e = 0; e < 4; ++e) nz |= cur[c][e] != (DT)0;
                 if (__any(nz)) {                 // a group of zeros adds nothing
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) {
-                            const CT d = (CT)cur[c][s];
-                            const CT* row = tp + (64 * gi + 16 * c + 4 * lg + s) * pw + lr;
-#pragma unroll
-                            for (int jt = 0; jt < NJT; ++jt) {
-                                {
-                                    const CT w = row[jt * 16];
-                                    acc[jt] = XAXIS ? M::op(d, w, acc[jt]) : M::op(w, d, acc[jt]);
-                                }
-                            }
-                        }
-                        // keep each chunk's operand reads with its MFMAs
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) cur[c][e] = nxt[c][e];
-            }
-#pragma unroll
-            for (int jt = 0; jt < NJT; ++jt) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int m = M::row(lg, r);
-                    if (XAXIS) {
-                        const int j = j0 + jt * 16 + lr;
-                        if (m < rows_left && j < n) {
-                            TO* o = out + (t * 16 + m) * (long)n + j;
-                            const double v = (double)acc[jt][r];
-                            if (EPI == 0) *o = v;
-                            else if (EPI == 1) *o += alpha * v;
-                            else *o = alpha * v;
-                        }
+                    if constexpr (SYM == 2) {
+                        // inverse split: even modes (k < n / 2) into acc, odd into acc2
+                        if (gi < ngroups / 2) mma(gi, acc);
+                        else mma(gi, acc2);
                     } else {
-                        const int j = j0 + jt * 16 + m;
-                        if (j < n && lr < rows_left) out[bbase + (long)j * inner + i0 + lr] = (double)acc[jt][r];
+                        mma(gi, acc);
                     }
                 }
+                if (gi + 1 < ngroups) settle();
             }
+#pragma unroll
+            for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    emit(XAXIS ? jt * 16 + lr : jt * 16 + M::row(lg, r), XAXIS ? M::row(lg, r) : lr,
+                         (double)acc[jt][r], SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0);
+            (void)acc2;
         }
     }
 }
 
-template <typename C, int PW, bool XAXIS, int EPI, typename TI, typename TO>
+template <typename C, int PW, bool XAXIS, int EPI, typename TI, typename TO, int SYM>
 static hipError_t panel_go(const TI* in, TO* out, const double* T, int n, int np, long nrows, long inner,
                            long ntiles, double alpha, hipStream_t st, const int* guard) {
-    const int npanel = np / PW;
-    if (npanel * PW != np) return hipErrorInvalidValue;
-    const size_t shm = panel_lds<C>(64 * ((np + 63) / 64), PW);
+    // the inverse split computes the outputs j < n / 2 (and their mirrors)
+    const int ncols = SYM == 2 ? n / 2 : np;
+    const int npanel = ncols / PW;
+    if (npanel * PW != ncols) return hipErrorInvalidValue;
+    const int kp = SYM == 1 ? n / 2 : (SYM == 2 ? n : 64 * ((np + 63) / 64));
+    const size_t shm = panel_lds<C>(kp, PW);
     if (shm > 160 * 1024) return hipErrorInvalidValue;
     static std::atomic<bool> attr_set{false};       // set once; the attribute call is idempotent
     if (!attr_set.load(std::memory_order_acquire)) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_xform_panel<C, PW, XAXIS, EPI, TI, TO>,
+        hipError_t e = hipFuncSetAttribute((const void*)k_xform_panel<C, PW, XAXIS, EPI, TI, TO, SYM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set.store(true, std::memory_order_release);
@@ -284,12 +324,13 @@ static hipError_t panel_go(const TI* in, TO* out, const double* T, int n, int np
     long blocks = 256 * per_cu;
     const long need = ((ntiles + kPanelWaves - 1) / kPanelWaves) * npanel;
     while (blocks > 8 * npanel && blocks / 2 >= need) blocks /= 2;
-    hipLaunchKernelGGL((k_xform_panel<C, PW, XAXIS, EPI, TI, TO>), dim3((unsigned)blocks), dim3(kPanelThreads), shm, st, in,
-                       out, T, n, np, npanel, nrows, inner, ntiles, alpha, guard);
+    hipLaunchKernelGGL((k_xform_panel<C, PW, XAXIS, EPI, TI, TO, SYM>), dim3((unsigned)blocks), dim3(kPanelThreads),
+                       shm, st, in, out, T, n, np, npanel, nrows, inner, ntiles, alpha, guard);
     return hipGetLastError();
 }
 
-// panel width: the widest of 128 (64 in FP64), 64, 32 that divides np
+// panel width: the widest of 128 (64 in FP64), 64, 32 that divides np (the
+// split transforms: n / 2)
 template <typename C> static int panel_width(int np) {
     for (int pw : {128, 64, 32})
         if (pw <= PanelTraits<C>::PW && np % pw == 0) return pw;
@@ -297,58 +338,92 @@ template <typename C> static int panel_width(int np) {
 }
 
 template <typename C, bool XAXIS, int EPI, typename TI = double, typename TO = double>
-static hipError_t panel_pw(const TI* in, TO* out, const double* T, int n, int np, long nrows, long inner,
+static hipError_t panel_pw(int sym, const TI* in, TO* out, const double* T, int n, int np, long nrows, long inner,
                            long ntiles, double alpha, hipStream_t st, const int* guard) {
+    if (sym == 1) {
+        // the folding loads take a second set of registers: width 128 on the
+        // x axis only (n / 2 is 64 or 128)
+        if (EPI != 0) return hipErrorInvalidValue;
+        if constexpr (PanelTraits<C>::PW >= 128 && XAXIS)
+            if (n == 256) return panel_go<C, 128, XAXIS, EPI, TI, TO, 1>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        return panel_go<C, 64, XAXIS, EPI, TI, TO, 1>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+    }
+    if (sym == 2) {
+        // two accumulator sets (even and odd modes): on the strided axis,
+        // whose addressing takes more registers, at half the width
+        if constexpr (XAXIS) {
+            if constexpr (PanelTraits<C>::PW >= 128)
+                if (n == 256) return panel_go<C, 128, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+            return panel_go<C, 64, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        } else {
+            if constexpr (PanelTraits<C>::PW >= 128)
+                if (n == 256) return panel_go<C, 64, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+            return panel_go<C, 32, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        }
+    }
     switch (panel_width<C>(np)) {
-        case 32: return panel_go<C, 32, XAXIS, EPI, TI, TO>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
-        case 64: return panel_go<C, 64, XAXIS, EPI, TI, TO>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        case 32: return panel_go<C, 32, XAXIS, EPI, TI, TO, 0>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+        case 64: return panel_go<C, 64, XAXIS, EPI, TI, TO, 0>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
         case 128:
             if constexpr (PanelTraits<C>::PW >= 128)
-                return panel_go<C, 128, XAXIS, EPI, TI, TO>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
+                return panel_go<C, 128, XAXIS, EPI, TI, TO, 0>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename C>
-static hipError_t panel_x_epi(int epi, const double* in, double* out, const double* T, int n, int np, long lines,
-                              double alpha, hipStream_t st, const int* guard) {
+static hipError_t panel_x_epi(int sym, int epi, const double* in, double* out, const double* T, int n, int np,
+                              long lines, double alpha, hipStream_t st, const int* guard) {
     const long ntiles = (lines + 15) / 16;
-    if (epi == 0) return panel_pw<C, true, 0>(in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
-    if (epi == 1) return panel_pw<C, true, 1>(in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
-    return panel_pw<C, true, 2>(in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    if (epi == 0) return panel_pw<C, true, 0>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    if (sym == 1) return hipErrorInvalidValue;
+    if (epi == 1) return panel_pw<C, true, 1>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    return panel_pw<C, true, 2>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
 }
 
 bool xform_panel_supported(int np) { return np >= 32 && np <= 256 && np % 32 == 0; }
 
+bool xform_panel_split_supported(int n) { return n == 128 || n == 256; }
+
 bool xform_panel_f32_io(int np) { return xform_panel_supported(np); }
 
 hipError_t launch_xform_panel_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                                long lines, double alpha, hipStream_t st, const int* guard) {
+                                long lines, double alpha, hipStream_t st, const int* guard, int sym) {
     if (lines <= 0) return hipSuccess;
-    if (!xform_panel_supported(np) || epi < 0 || epi > 2) return hipErrorInvalidValue;
-    if (prec == 0) return panel_x_epi<PanelF64>(epi, in, out, T, n, np, lines, alpha, st, guard);
-    if (prec == 1) return panel_x_epi<PanelF32>(epi, in, out, T, n, np, lines, alpha, st, guard);
-    if (prec == 2) return panel_x_epi<PanelBf16x3>(epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (!xform_panel_supported(np) || epi < 0 || epi > 2 || sym < 0 || sym > 2) return hipErrorInvalidValue;
+    if (sym != 0 && !(xform_panel_split_supported(n) && np == n)) return hipErrorInvalidValue;
+    if (prec == 0) return panel_x_epi<PanelF64>(sym, epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 1) return panel_x_epi<PanelF32>(sym, epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 2) return panel_x_epi<PanelBf16x3>(sym, epi, in, out, T, n, np, lines, alpha, st, guard);
     return hipErrorInvalidValue;
 }
 
 template <typename C>
-static hipError_t panel_s_io(const double* in, double* out, const double* T, int n, int np, long inner, long ntiles,
-                             hipStream_t st, const int* guard, int io_f32) {
-    if (io_f32 == 2) return panel_pw<C, false, 0, double, float>(in, (float*)out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
-    if (io_f32 == 1) return panel_pw<C, false, 0, float, double>((const float*)in, out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
-    return panel_pw<C, false, 0>(in, out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
+static hipError_t panel_s_io(int sym, const double* in, double* out, const double* T, int n, int np, long inner,
+                             long ntiles, hipStream_t st, const int* guard, int io_f32) {
+    // float data: written by a forward transform, read by an inverse one
+    if (io_f32 == 2) {
+        if (sym == 2) return hipErrorInvalidValue;
+        return panel_pw<C, false, 0, double, float>(sym, in, (float*)out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
+    }
+    if (io_f32 == 1) {
+        if (sym == 1) return hipErrorInvalidValue;
+        return panel_pw<C, false, 0, float, double>(sym, (const float*)in, out, T, n, np, 0, inner, ntiles, 1.0, st,
+                                                    guard);
+    }
+    return panel_pw<C, false, 0>(sym, in, out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
 }
 
 hipError_t launch_xform_panel_s(int prec, const double* in, double* out, const double* T, int n, int np, long nbatch,
-                                long inner, hipStream_t st, const int* guard, int io_f32) {
+                                long inner, hipStream_t st, const int* guard, int io_f32, int sym) {
     if (nbatch <= 0 || inner <= 0) return hipSuccess;
-    if (!xform_panel_supported(np) || io_f32 < 0 || io_f32 > 2) return hipErrorInvalidValue;
+    if (!xform_panel_supported(np) || io_f32 < 0 || io_f32 > 2 || sym < 0 || sym > 2) return hipErrorInvalidValue;
+    if (sym != 0 && !(xform_panel_split_supported(n) && np == n)) return hipErrorInvalidValue;
     const long ntiles = nbatch * ((inner + 15) / 16);
-    if (prec == 0) return panel_s_io<PanelF64>(in, out, T, n, np, inner, ntiles, st, guard, io_f32);
-    if (prec == 1) return panel_s_io<PanelF32>(in, out, T, n, np, inner, ntiles, st, guard, io_f32);
-    if (prec == 2) return panel_s_io<PanelBf16x3>(in, out, T, n, np, inner, ntiles, st, guard, io_f32);
+    if (prec == 0) return panel_s_io<PanelF64>(sym, in, out, T, n, np, inner, ntiles, st, guard, io_f32);
+    if (prec == 1) return panel_s_io<PanelF32>(sym, in, out, T, n, np, inner, ntiles, st, guard, io_f32);
+    if (prec == 2) return panel_s_io<PanelBf16x3>(sym, in, out, T, n, np, inner, ntiles, st, guard, io_f32);
     return hipErrorInvalidValue;
 }
 

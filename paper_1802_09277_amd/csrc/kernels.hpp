@@ -77,11 +77,16 @@ hipError_t launch_residual_norm(int dim, int Nt, int p, int n, const double* M1b
 // of length n.  EPI 0: store, 1: out += alpha*acc, 2: out = alpha*acc.
 // prec (sth_prec): 0 MFMA f64, 1 MFMA f32 (FP32 accumulation), 2 BF16x3.
 hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st, const int* guard = nullptr);
+                          long lines, double alpha, hipStream_t st, const int* guard = nullptr, int sym = 0);
 
 // Strided axis: in[b][k][i] (k stride `inner`), out[b][j][i] = sum_k T[k][j] in[b][k][i].
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
-                          long nbatch, long inner, hipStream_t st, const int* guard = nullptr, int io_f32 = 0);
+                          long nbatch, long inner, hipStream_t st, const int* guard = nullptr, int io_f32 = 0,
+                          int sym = 0);
+// sym 1 (forward) and 2 (inverse): T's modes split into even ones [0, n/2)
+// and odd ones [n/2, n) under the reflection i -> n-1-i, which halves the
+// multiply-adds; only for n = np with xform_split_supported(n)
+bool xform_split_supported(int n);
 // (both per-axis launchers: every block returns at once when guard is given
 // and *guard == 0, as in the guards of speculative cycles; launch_xform_s
 // with io_f32 2 writes float output, 1 reads float input, for np <= 256 a

@@ -359,11 +359,17 @@ hipError_t launch_sum_partials(const double* partial, int count, double* out, do
                                const int* guard, const CycleFlag& flag, hipStream_t st);
 
 // Per-axis transforms with the transform matrix in LDS (np <= 256, a
-// multiple of 32), the same operations as launch_xform_x / launch_xform_s
+// multiple of 32), the same operations as launch_xform_x / launch_xform_s.
+// sym 1 and 2 (n = np = 128 or 256: xform_panel_split_supported(n)) take a
+// T whose columns (forward, sym 1: T = U) or rows (inverse, sym 2: T = U^T)
+// [0, n/2) are even and [n/2, n) odd under the reflection i -> n-1-i, and
+// compute the same result with half the multiply-adds: the forward transform
+// reads only rows k < n/2 of T, the inverse only columns j < n/2.
 bool xform_panel_supported(int np);
+bool xform_panel_split_supported(int n);
 hipError_t launch_xform_panel_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                                long lines, double alpha, hipStream_t st, const int* guard);
+                                long lines, double alpha, hipStream_t st, const int* guard, int sym = 0);
 hipError_t launch_xform_panel_s(int prec, const double* in, double* out, const double* T, int n, int np, long nbatch,
-                                long inner, hipStream_t st, const int* guard, int io_f32 = 0);
+                                long inner, hipStream_t st, const int* guard, int io_f32 = 0, int sym = 0);
 
 }  // namespace sth

@@ -57,6 +57,9 @@ struct sth_handle {
     int dim = 2, n = 0, np = 0, Nt = 0, p = 0, L = 0;
     long Nx = 0;
     long Nxe = 0;                       // modes per time row of an eigenbasis vector (eig_modes)
+    // the spatial modes are ordered [even | odd] under the reflection
+    // i -> n-1-i and the per-axis transforms use the split kernels
+    bool split = false;
     double omega = 0.5;
     int nu_pre = 1, nu_post = 1;
     int prec = 0;                       // sth_prec of the spatial transforms
@@ -308,20 +311,33 @@ static int residual(sth_handle* h, int lvl, const double* f, const double* u, do
     return STH_OK;
 }
 
-// per-axis transforms in the precision `prec` (sth_prec)
+// Split form of a per-axis transform with matrix T: 1 for the forward
+// matrices (U, C = M_1 U: out = T^T in), 2 for the inverse ones (their
+// transposes), 0 without the even/odd mode order
+static int split_of(const sth_handle* h, const double* T) {
+    if (!h->split) return 0;
+    if (T == h->Tf || (h->Cf && T == h->Cf)) return 1;
+    if (T == h->Ti || (h->Ci && T == h->Ci)) return 2;
+    return 0;
+}
+
+// per-axis transforms in the precision `prec` (sth_prec); the split forms
+// take n / 2 multiply-adds per output instead of n
 static int xform_x(sth_handle* h, int prec, int epi, const double* in, double* out, const double* T, long lines,
                    double alpha, hipStream_t st, const int* guard = nullptr) {
-    double dof = (double)lines * h->n;
-    Timed tm(h, STH_K_XFORM_X, 2.0 * h->n * dof, dof * (epi == 1 ? 24.0 : 16.0), st);
-    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st, guard));
+    const double dof = (double)lines * h->n;
+    const int sym = split_of(h, T);
+    Timed tm(h, STH_K_XFORM_X, (sym ? 1.0 : 2.0) * h->n * dof, dof * (epi == 1 ? 24.0 : 16.0), st);
+    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st, guard, sym));
     return STH_OK;
 }
 
 static int xform_s(sth_handle* h, int prec, const double* in, double* out, const double* T, long nbatch,
                    long inner, hipStream_t st, const int* guard = nullptr, int io_f32 = 0) {
-    double dof = (double)nbatch * h->n * inner;
-    Timed tm(h, STH_K_XFORM_S, 2.0 * h->n * dof, (io_f32 ? 12.0 : 16.0) * dof, st);
-    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st, guard, io_f32));
+    const double dof = (double)nbatch * h->n * inner;
+    const int sym = split_of(h, T);
+    Timed tm(h, STH_K_XFORM_S, (sym ? 1.0 : 2.0) * h->n * dof, (io_f32 ? 12.0 : 16.0) * dof, st);
+    HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st, guard, io_f32, sym));
     return STH_OK;
 }
 
@@ -1245,6 +1261,7 @@ static int setup_problem(Problem q, hipStream_t s, sth_handle** out) {
     h->dim = q.dim;
     h->n = h->S.n;
     h->np = (h->n + 15) / 16 * 16;
+    h->split = h->S.half > 0 && h->np == h->n && xform_split_supported(h->n);
     h->Nt = h->S.Nt;
     h->p = q.degree;
     h->Nx = (long)h->n * h->n * (q.dim == 3 ? h->n : 1);

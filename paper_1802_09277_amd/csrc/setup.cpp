@@ -942,17 +942,13 @@ static int temporal_decomposition(TemporalLevel& L, int temporal, std::string& e
     return 0;
 }
 
-int build_setup(const Problem& p, Setup& s, std::string& err) {
-    err = validate(p);
-    if (!err.empty()) return -1;
-    s.prob = p;
-    s.n = p.n();
-    s.Nt = p.Nt();
-    space_matrices(p.n_elem, p.degree, s.M1, s.K1);
-    // spatial pencil: M1 = L L^T, C = L^{-1} K1 L^{-T} = Q diag(mu) Q^T, U = L^{-T} Q
+// Eigenpairs of the symmetric pencil (K, M), M positive definite:
+// M = L L^T, L^{-1} K L^{-T} = Q diag(mu) Q^T, U = L^{-T} Q (U^T M U = I),
+// mu ascending.
+static bool pencil_eigen(const Mat& K, const Mat& M, std::vector<double>& mu, Mat& U) {
     Mat Lc;
-    if (!cholesky(s.M1, Lc)) { err = "M1 not positive definite"; return -5; }
-    int n = s.n;
+    if (!cholesky(M, Lc)) return false;
+    const int n = M.r;
     Mat Linv(n, n);
     for (int j = 0; j < n; ++j) {
         for (int i = 0; i < n; ++i) {
@@ -965,7 +961,7 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             double v = 0.0;
-            for (int k = 0; k <= i; ++k) v += Linv(i, k) * s.K1(k, j);
+            for (int k = 0; k <= i; ++k) v += Linv(i, k) * K(k, j);
             T1(i, j) = v;
         }
     for (int i = 0; i < n; ++i)
@@ -977,15 +973,89 @@ int build_setup(const Problem& p, Setup& s, std::string& err) {
     for (int i = 0; i < n; ++i)
         for (int j = i + 1; j < n; ++j) C(i, j) = C(j, i) = 0.5 * (C(i, j) + C(j, i));
     Mat Q;
-    sym_eigen(C, s.mu, Q);
-    s.U = Mat(n, n);
+    sym_eigen(C, mu, Q);
+    U = Mat(n, n);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             double v = 0.0;
             for (int k = i; k < n; ++k) v += Linv(k, i) * Q(k, j);
-            s.U(i, j) = v;
+            U(i, j) = v;
         }
-    if (p.basis == 1) {
+    return true;
+}
+
+// A(i, j) = A(n-1-i, n-1-j) to rounding
+static bool reflection_symmetric(const Mat& A) {
+    const int n = A.r;
+    double amax = 0.0, d = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            amax = std::max(amax, std::fabs(A(i, j)));
+            d = std::max(d, std::fabs(A(i, j) - A(n - 1 - i, n - 1 - j)));
+        }
+    return d <= 1e-12 * amax;
+}
+
+int build_setup(const Problem& p, Setup& s, std::string& err) {
+    err = validate(p);
+    if (!err.empty()) return -1;
+    s.prob = p;
+    s.n = p.n();
+    s.Nt = p.Nt();
+    space_matrices(p.n_elem, p.degree, s.M1, s.K1);
+    const int n = s.n;
+    const int h = n / 2;
+    if (n % 2 == 0 && reflection_symmetric(s.M1) && reflection_symmetric(s.K1)) {
+        // The reflection J (i -> n - 1 - i) commutes with M1 and K1, so the
+        // eigenvectors split into even ones, v = [w; J w], and odd ones,
+        // v = [w; -J w], where w solves the half pencil (K11 +- K12 J,
+        // M11 +- M12 J) of order n / 2.  With w^T (M11 +- M12 J) w = 1,
+        // v / sqrt 2 is M1-orthonormal.
+        Mat U(n, n);
+        s.mu.assign(n, 0.0);
+        for (int sg = 0; sg < 2; ++sg) {
+            const double sign = sg == 0 ? 1.0 : -1.0;
+            Mat Kh(h, h), Mh(h, h);
+            for (int i = 0; i < h; ++i)
+                for (int j = 0; j < h; ++j) {
+                    Kh(i, j) = s.K1(i, j) + sign * s.K1(i, n - 1 - j);
+                    Mh(i, j) = s.M1(i, j) + sign * s.M1(i, n - 1 - j);
+                }
+            std::vector<double> mh;
+            Mat Uh;
+            if (!pencil_eigen(Kh, Mh, mh, Uh)) {
+                err = "half mass matrix not positive definite";
+                return -5;
+            }
+            if (p.basis == 1) {
+                // the eigenvalues of M1 are those of its two half matrices
+                std::vector<double> ev;
+                Mat Qm;
+                sym_eigen(Mh, ev, Qm);
+                const double lo = *std::min_element(ev.begin(), ev.end());
+                const double hi = *std::max_element(ev.begin(), ev.end());
+                s.m1_min = sg == 0 ? lo : std::min(s.m1_min, lo);
+                s.m1_max = sg == 0 ? hi : std::max(s.m1_max, hi);
+            }
+            const double r2 = std::sqrt(0.5);
+            for (int j = 0; j < h; ++j) {
+                s.mu[sg * h + j] = mh[j];
+                for (int i = 0; i < h; ++i) {
+                    U(i, sg * h + j) = r2 * Uh(i, j);
+                    U(n - 1 - i, sg * h + j) = sign * r2 * Uh(i, j);
+                }
+            }
+        }
+        s.U = U;
+        s.half = h;
+    } else {
+        if (!pencil_eigen(s.K1, s.M1, s.mu, s.U)) {
+            err = "M1 not positive definite";
+            return -5;
+        }
+        s.half = 0;
+    }
+    if (p.basis == 1 && s.half == 0) {
         // C = M1 U satisfies C C^T = M1 (U U^T = M1^{-1}), so the squared
         // singular values of C are the eigenvalues of M1
         std::vector<double> ev;

@@ -80,6 +80,10 @@ struct Setup {
     int n = 0, Nt = 0;
     Mat M1, K1, U;         // 1-D spatial matrices (interior), eigenvectors
     std::vector<double> mu;
+    // n / 2 when n is even and the pencil is symmetric under the reflection
+    // i -> n - 1 - i: then columns [0, half) of U are even and [half, n) odd
+    // (each block in ascending mu); 0 otherwise
+    int half = 0;
     double m1_min = 0, m1_max = 0;   // extreme eigenvalues of M1 (eigenbasis iteration only)
     std::vector<TemporalLevel> levels;
 };

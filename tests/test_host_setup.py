@@ -279,3 +279,26 @@ def test_workspace_with_minres_slab_inverse():
     kw = dict(dim=2, n_elem=16, degree=2, n_slabs=16, n_elem_t=2, coarse_slabs=1)
     vec = 16 * 4 * 16 * 16 * 8
     assert sth.workspace_bytes(minres_iters=12, **kw) >= sth.workspace_bytes(**kw) + 8 * vec
+
+
+@pytest.mark.parametrize("n_elem,degree", [(6, 2), (128, 2), (9, 3), (7, 4)])
+def test_spatial_modes_even_then_odd(n_elem, degree):
+    """For an even number n of interior functions the library orders the
+    generalised eigenvectors of (K_1, M_1) [even | odd] under the reflection
+    i -> n-1-i (each half in ascending eigenvalue), which its split
+    transforms rely on; the eigenpairs themselves are those of the oracle's
+    pencil (dense symmetric-definite solver)."""
+    F = sth.host_factors(level=0, dim=2, n_elem=n_elem, degree=degree, n_slabs=2, n_elem_t=1)
+    U, mu = F["U"], F["mu"]
+    M1o, K1o = space_matrices_1d(n_elem, degree)
+    n = len(mu)
+    assert np.allclose(U.T @ M1o @ U, np.eye(n), atol=1e-12)
+    assert np.allclose(K1o @ U, M1o @ U @ np.diag(mu), atol=1e-9 * mu.max())
+    assert np.allclose(np.sort(mu), sl.eigh(K1o, M1o, eigvals_only=True), rtol=1e-10)
+    if n % 2:
+        return
+    h = n // 2
+    J = U[::-1]
+    assert np.abs(J[:, :h] - U[:, :h]).max() <= 1e-13 * np.abs(U).max()
+    assert np.abs(J[:, h:] + U[:, h:]).max() <= 1e-13 * np.abs(U).max()
+    assert np.all(np.diff(mu[:h]) > 0) and np.all(np.diff(mu[h:]) > 0)
