@@ -408,6 +408,9 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 // delta A^{-1} e_1, so every slab needs one slab solve.  The coupling rows of
 // the previous slab (u1, u2, u3) are carried along the chain; a chain after
 // slab 0 first repeats the two steps of its two preceding slabs.
+// With uend null the result is not stored (it is formed again only if it is
+// needed: the solve keeps iterating from unext); with unext null the pass
+// only forms and stores the result (uend), bitwise as the full pass would.
 template <int NT, bool SCHUR, typename VT>
 __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, const double* __restrict__ ktmt,
                                                          const double* __restrict__ mu1, int n, long Nx,
@@ -537,8 +540,12 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 u2[t] = u1[t] + omega * z[t];
-                uend[b + (long)t * Nx] = u2[t];
+                if (uend) uend[b + (long)t * Nx] = u2[t];
                 g[t] *= (1.0 - omega);
+            }
+            if (!unext) {                       // the result alone
+                p1 = u1[NT - 1];
+                continue;
             }
             const double d2 = up_prev_delta(p2, p1);
             g[0] += d2;
@@ -577,7 +584,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             p3 = u3last;
         }
     }
-    block_sum3(ssq, wsq, usq, partial);
+    if (partial) block_sum3(ssq, wsq, usq, partial);
 }
 
 // The two coarsest levels of a V(1,1) cycle in one pass (a: second-coarsest
@@ -1004,11 +1011,14 @@ static hipError_t launch_eig_cycle_close_vt(int dim, int Nt, const TimeMix& tm, 
                                   bool sums) {
     const long Nx = eig_modes(dim, n);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
-    if (upre == uend || upre == unext || uend == unext) return hipErrorInvalidValue;
+    // a full pass (unext, fc, partial), stored result optional; or the result alone
+    const bool full = unext != nullptr;
+    if (full ? (!fc || !partial) : (!uend || fc || partial || sums)) return hipErrorInvalidValue;
+    if (upre == uend || upre == unext || (uend && uend == unext)) return hipErrorInvalidValue;
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
     const long total = (S / chain) * Nx;
     const long blocks = (total + 255) / 256;
-    if (3 * blocks > max_partial || blocks > 0x7fffffffL) return hipErrorInvalidValue;
+    if ((full && 3 * blocks > max_partial) || blocks > 0x7fffffffL) return hipErrorInvalidValue;
     dim3 grid((unsigned)blocks);
     switch (Nt) {
 #define STH_CC_CASE(NTV)                                                                                     \

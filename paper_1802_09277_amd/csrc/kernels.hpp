@@ -171,7 +171,9 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
 //  (chains and sums as above): u1 = upre + (P_t (x) I) ec, uend = u1 +
 //  omega A^{-1}(fh - L u1) (the cycle's result), the three sums of
 //  fh - L uend, unext = uend + omega A^{-1}(fh - L uend), fc =
-//  (P^T (x) I)(fh - L unext) on slab pairs; the three iterate buffers differ
+//  (P^T (x) I)(fh - L unext) on slab pairs; the three iterate buffers differ.
+//  uend null: the result is not stored.  unext null (fc and partial null,
+//  sums false): the pass stores uend alone, bitwise as the full pass does.
 hipError_t launch_eig_cycle_close(int dim, int Nt, const TimeMix& tm, const double* ktmt, const double* mu1, int n,
                                   const double* fh, const double* upre, const double* ec, double* uend,
                                   double* unext, double* fc, const Transfer& tr, double omega, long S, int chain,

@@ -89,6 +89,17 @@ struct sth_handle {
     TimeMix* dmix = nullptr;            // per level slab inverse in device memory
     bool defer_close = false;           // set by a solve iteration: level 0 leaves its post-smoothing
     const double* pending_ec = nullptr; // coarse correction waiting for the fused cycle close
+    // The solve loop's fused cycle closes do not store the cycle's result
+    // (level-0 buffer dst): it is formed from the close's inputs (the
+    // pre-smoothed buffer c and the coarse correction ec, which stay intact
+    // until the next cycle runs) only when it is read (form_result).
+    struct Unformed {
+        bool on = false;
+        int c = 0, dst = 0;
+        const double* ec = nullptr;
+    };
+    Unformed unformed;
+    bool lazy_close = false;            // set by the solve loop around its cycles
     int pre_idx = 1;                    // level-0 buffer of the pre-smoothed iterate
     std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
     // FP32 storage of the eigenbasis vectors (the inner solves of the mixed
@@ -165,6 +176,7 @@ struct sth_handle {
         int key = -1;                   // level-0 buffer state at entry
         int ecur0_after = 0, pre_after = 1, slot_after = 0;
         bool presm_after = false;
+        Unformed unf_after;
         std::vector<Rec> recs;          // timed launches inside the graph
         long last_used = 0;
     } gent[2];
@@ -182,6 +194,7 @@ struct sth_handle {
         bool presmoothed = false;
         int slot = 0;
         int seqv = 0;                   // completion mark of the cycle's final sum
+        Unformed unf;
     };
     struct SolveState {
         const double* f = nullptr;
@@ -820,9 +833,11 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
     bool from_zero = false;             // the pre-smoothing step started from zero (A u = omega f)
     if (lvl == 0 && h->presmoothed) {
         // the cycle-end pass of the previous cycle (or of the initial
-        // residual) took the pre-smoothing step and restricted its residual
+        // residual) took the pre-smoothing step and restricted its residual;
+        // the previous cycle's result, if unformed, is not needed any more
         h->ecur[0] = h->pre_idx;
         h->presmoothed = false;
+        h->unformed = sth_handle::Unformed{};
     } else if (zero_guess && h->nu_pre == 1) {
         // one pass: smoothing step from zero and restriction of its residual
         from_zero = true;
@@ -900,15 +915,18 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
             flag.seq_val = h->last_seq = ++h->seq_counter;
         }
         const int chain = chain_length(h, S, 65536);
+        // in the solve loop the result is formed only if it is read
+        const bool lazy = h->lazy_close;
         {
             // the pass alone (its final sums are a launch of their own)
-            Timed tm(h, STH_K_EIG_CYCLE_CLOSE, dof * (12.0 * Nt + 24.0), 40.0 * dof, st);
+            Timed tm(h, STH_K_EIG_CYCLE_CLOSE, dof * (12.0 * Nt + 24.0), (lazy ? 32.0 : 40.0) * dof, st);
             HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
-                                          eig_u(h, 0, c), h->pending_ec, eig_u(h, 0, cur), eig_u(h, 0, nxt),
-                                          eig_f(h, 1), h->tr, h->omega, S, chain, h->vw, h->cpartial,
-                                          h->n_cpartial, h->dnorm + slot_base(slot), h->hnorm_dev + slot_base(slot), st,
-                                          h->guard, flag, false, h->f32));
+                                          eig_u(h, 0, c), h->pending_ec, lazy ? nullptr : eig_u(h, 0, cur),
+                                          eig_u(h, 0, nxt), eig_f(h, 1), h->tr, h->omega, S, chain, h->vw,
+                                          h->cpartial, h->n_cpartial, h->dnorm + slot_base(slot),
+                                          h->hnorm_dev + slot_base(slot), st, h->guard, flag, false, h->f32));
         }
+        h->unformed = lazy ? sth_handle::Unformed{true, c, cur, h->pending_ec} : sth_handle::Unformed{};
         HIPCHK(launch_cycle_sums(h->dim, h->n, S, chain, h->cpartial, h->dnorm + slot_base(slot),
                                  h->hnorm_dev + slot_base(slot), st, h->guard, flag));
         h->last_slot = slot;
@@ -955,16 +973,36 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
     return STH_OK;
 }
 
+// The result of the last cycle when its close left it unformed: the
+// post-smoothing step of that close again, from the same inputs, stored
+// alone (bitwise the value the close would have stored).
+static int form_result(sth_handle* h, hipStream_t st) {
+    if (!h->unformed.on) return STH_OK;
+    const sth_handle::Unformed uf = h->unformed;
+    h->unformed = sth_handle::Unformed{};
+    if (uf.dst != h->ecur[0]) return fail(STH_EINVAL, "unformed result in a buffer that is not the iterate");
+    h->tlev = 0;
+    const long S = h->lev_S[0];
+    const double dof = (double)S * slab_len(h);
+    Timed tm(h, STH_K_EIG_SMOOTH, dof * (10.0 * h->Nt + 8.0), 28.0 * dof, st);
+    HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
+                                  eig_u(h, 0, uf.c), uf.ec, eig_u(h, 0, uf.dst), nullptr, nullptr, h->tr, h->omega,
+                                  S, chain_length(h, S, 65536), h->vw, nullptr, 0, nullptr, nullptr, st, nullptr,
+                                  CycleFlag{}, false, h->f32));
+    return STH_OK;
+}
+
 // The B-spline residual norm ||(I (x) C_x) r^||^2 (C = M_1 U = U^{-T}) of
 // the current eigenbasis iterate to hnorm[0] (not synchronised); r^ is
 // formed again in buf0.
 static int eig_exact_norm(sth_handle* h, hipStream_t st, const CycleFlag& fin = CycleFlag{}) {
+    int rc = form_result(h, st);
+    if (rc) return rc;
     h->tlev = 0;
     const long S = h->lev_S[0];
     const long len = S * eslab_len(h);             // eigenbasis layout (padded rows)
     const double dof = (double)S * slab_len(h);
     const long rows = S * h->Nt;
-    int rc;
     {
         Timed tm(h, STH_K_EIG_RESID, dof * 4.0 * h->Nt, dof * 24.0, st);
         HIPCHK(launch_eig_residual(h->dim, h->Nt, level_ktmt(h, 0), h->mu1, h->n, h->e0, eig_u(h, 0, h->ecur[0]),
@@ -1699,7 +1737,9 @@ static int solve_iteration(sth_handle* h, const double* f, double* u, hipStream_
         h->first_guard = false;
         rc = eig_vcycle(h, 0, false, st);
         h->defer_close = false;
+        h->lazy_close = true;
         if (rc == STH_OK) rc = eig_residual_cheap(h, st);
+        h->lazy_close = false;
         h->pending_ec = nullptr;
         h->guard = nullptr;
         return rc;
@@ -1760,6 +1800,7 @@ static int graph_launch(sth_handle* h, const double* f, double* u, hipStream_t s
         g->pre_after = h->pre_idx;
         g->presm_after = h->presmoothed;
         g->slot_after = h->last_slot;
+        g->unf_after = h->unformed;
     } else if (h->basis == 1) {
         // a replay does not run the host-side bookkeeping of the capture:
         // take the level-0 buffer state the captured iteration left
@@ -1767,6 +1808,7 @@ static int graph_launch(sth_handle* h, const double* f, double* u, hipStream_t s
         h->pre_idx = g->pre_after;
         h->presmoothed = g->presm_after;
         h->last_slot = g->slot_after;
+        h->unformed = g->unf_after;
     }
     g->last_used = ++h->graph_clock;
     HIPCHK(hipGraphLaunch(g->exec, st));
@@ -1840,6 +1882,7 @@ static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rt
         // f^ = (I (x) U_x^T) f, u^ = (I (x) C_x^T) u (C^T = U^{-1}), then the residual
         const long rows = h->lev_S[0] * h->Nt;
         h->ecur[0] = 0;
+        h->unformed = sth_handle::Unformed{};
         // (FP32 eigenbasis vectors: only in inner solves, whose f is the
         // outer residual in buf1 or the caller's f; a 3-D forward transform
         // into float data uses buf1 as its second work vector after its
@@ -1908,7 +1951,7 @@ static hipEvent_t next_event(sth_handle* h) {
 }
 
 static sth_handle::Snap take_snap(const sth_handle* h) {
-    return sth_handle::Snap{h->ecur[0], h->pre_idx, h->presmoothed, h->last_slot, h->last_seq};
+    return sth_handle::Snap{h->ecur[0], h->pre_idx, h->presmoothed, h->last_slot, h->last_seq, h->unformed};
 }
 
 // Completion of the cycle just enqueued: an event, or nothing to record when
@@ -1933,6 +1976,7 @@ static void put_snap(sth_handle* h, const sth_handle::Snap& s) {
     h->pre_idx = s.pre_idx;
     h->presmoothed = s.presmoothed;
     h->last_slot = s.slot;
+    h->unformed = s.unf;
 }
 
 // Enqueues the next cycle (it must run: the flag it is guarded by holds 1)
@@ -1961,6 +2005,8 @@ static int solve_finish(sth_handle* h, bool* more) {
     v.phase = 2;
     h->wait_ev = nullptr;
     h->wait_slot = -1;
+    int rc = form_result(h, v.st);
+    if (rc) return rc;
     // u = (I (x) U_x) u^ (an inner solve adds it to u)
     return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st, nullptr,
                          v.tprec, v.inner ? 1 : 0, h->buf1, h->f32 ? 1 : 0);
@@ -2220,6 +2266,8 @@ static int solve_continue_impl(sth_handle* h, bool* more) {
     v.phase = 2;
     if (eig) {
         // u = (I (x) U_x) u^
+        int rc = form_result(h, v.st);
+        if (rc) return rc;
         return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st);
     }
     return STH_OK;
@@ -2473,6 +2521,7 @@ static int precondition(sth_handle* h, const double* v, double* z, hipStream_t s
         return rc;
     h->ecur[0] = 0;
     h->presmoothed = false;
+    h->unformed = sth_handle::Unformed{};
     if ((rc = eig_vcycle(h, 0, true, st))) return rc;
     return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), z, rows, h->buf0, st, nullptr, h->prec, 0, h->buf1,
                          h->f32 ? 1 : 0);
