@@ -598,13 +598,14 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 // fa - L_a v = (1 - omega) fa - A_a (P_t ub) + e_1 q with q the last time
 // row of the previous slab of v, so
 //   ua = (2 - omega) u + (1 - omega)(P_t (x) I) ub + omega q A_a^{-1} e_1.
-// A block holds 16 modes (one 128-byte line per time row) x G slab groups of
-// LA level-a and LA/2 level-b slabs per thread, kept in registers; the
+// A block holds 16 modes (one 128-byte line per time row) x G slab groups
+// (G <= GM: 32, or 64 in the 1024-thread form for N_t <= 3) of LA level-a
+// and LA/2 level-b slabs per thread, kept in registers; the
 // coupling rows between groups, and the recurrence of the exact solve
 // (u_s = A^{-1} g_s + x_{s-1} A^{-1} e_1, x_s = a_s[N_t-1] + gamma x_{s-1}),
 // pass through LDS.  Only ua is written.
-template <int NT, bool SCHUR, int LAM, typename VT>
-__global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_coarse_tail(int dim, const TimeMix* __restrict__ tma,
+template <int NT, bool SCHUR, int LAM, typename VT, int GM>
+__global__ __launch_bounds__(16 * GM, (GM > 32 ? 1 : ((NT <= 5 && LAM <= 4) ? 4 : 2))) void k_eig_coarse_tail(int dim, const TimeMix* __restrict__ tma,
                                                          const TimeMix* __restrict__ tmb,
                                                          const double* __restrict__ mu1, int n, long Nx,
                                                          const VT* __restrict__ fa, VT* __restrict__ ua,
@@ -612,7 +613,7 @@ __global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_co
                                                          const int* guard) {
     if (guard_off(guard)) return;
     constexpr int MB = 16, LBM = LAM / 2;
-    __shared__ double xch[32][MB], xe_s[32][MB], gl_s[32][MB];
+    __shared__ double xch[GM][MB], xe_s[GM][MB], gl_s[GM][MB];
     const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
     const long m = (long)blockIdx.x * MB + ml;
     const bool active = m < Nx;
@@ -706,6 +707,224 @@ __global__ __launch_bounds__(512, ((NT <= 5 && LAM <= 4) ? 4 : 2)) void k_eig_co
     __syncthreads();
     if (!active) return;
     // (3) prolongation and the post-smoothing step on level a (closed form)
+    double ca[NT];
+    {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(*tma, mu, e1, ca);
+    }
+    double q = g > 0 ? xch[g - 1][ml] : 0.0;
+#pragma unroll
+    for (int i = 0; i < LAM; ++i) {
+        if (i < LA) {
+            const int h = i & 1;
+            const long b = (sa0 + i) * slab + m;
+            double pu[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                double w = 0.0;
+#pragma unroll
+                for (int k = 0; k < NT; ++k) w += tr.P[(h * NT + t) * kNt + k] * ub[i / 2][k];
+                pu[t] = w;
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+                ua[b + (long)t * Nx] = (2.0 - omega) * u[i][t] + (1.0 - omega) * pu[t] + omega * q * ca[t];
+            q = u[i][NT - 1] + pu[NT - 1];
+        }
+    }
+}
+
+// The three coarsest levels of a V(1,1) cycle in one pass (a, b with SA and
+// SA/2 slabs, c the coarsest with SA/4), from the right-hand side fa of level
+// a alone: the descent of the two-level pass taken twice (smoothing step
+// from zero and restriction of its residual, on a and then on b), the exact
+// solve on c, and the closed-form post-smoothing step (prolonged correction
+// added first) on b and then on a:
+//   ub' = (2 - omega) ub + (1 - omega)(P_t (x) I) uc + omega q_b A_b^{-1} e_1,
+//   ua' = (2 - omega) ua + (1 - omega)(P_t (x) I) ub' + omega q_a A_a^{-1} e_1,
+// q the last time row of the previous slab of the prolonged iterate.  A block
+// holds 16 modes x G slab groups of LA level-a, LA/2 level-b and LA/4
+// level-c slabs per thread, all in registers; the coupling rows between
+// groups (twice on the way down, twice on the way up) and the recurrence of
+// the exact solve pass through LDS.  Only ua is written.
+template <int NT, bool SCHUR, int LAM, typename VT, int GM>
+__global__ __launch_bounds__(16 * GM) void k_eig_coarse_tail3(int dim, const TimeMix* __restrict__ tma,
+                                                             const TimeMix* __restrict__ tmb,
+                                                             const TimeMix* __restrict__ tmc,
+                                                             const double* __restrict__ mu1, int n, long Nx,
+                                                             const VT* __restrict__ fa, VT* __restrict__ ua,
+                                                             Transfer tr, double omega, int G, int LA,
+                                                             const int* guard) {
+    if (guard_off(guard)) return;
+    constexpr int MB = 16, LBM = LAM / 2, LCM = LAM / 4;
+    __shared__ double xch[GM][MB], xe_s[GM][MB], gl_s[GM][MB];
+    const int ml = threadIdx.x % MB, g = threadIdx.x / MB;
+    const long m = (long)blockIdx.x * MB + ml;
+    const bool active = m < Nx;
+    const int LB = LA / 2, LC = LA / 4;
+    const long slab = (long)NT * Nx;
+    const long sa0 = (long)g * LA;                 // first level-a slab of the group (a multiple of 4)
+    double u[LAM][NT], ub[LBM][NT], uc[LCM][NT];
+    double mu = 0.0, ulast = 0.0, blast = 0.0;
+    // (1) level a: smoothing step from zero, restriction of its residual into ub (f_b)
+    if (active) {
+        mu = mode_shift(dim, mu1, n, m);
+#pragma unroll
+        for (int j = 0; j < LBM; ++j)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) ub[j][t] = 0.0;
+#pragma unroll
+        for (int i = 0; i < LAM; ++i) {
+            if (i < LA) {
+                double f[NT], z[NT];
+                const long b = (sa0 + i) * slab + m;
+#pragma unroll
+                for (int t = 0; t < NT; ++t) f[t] = fa[b + (long)t * Nx];
+                shifted_solve<NT, SCHUR>(*tma, mu, f, z);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    u[i][t] = omega * z[t];
+                    f[t] *= (1.0 - omega);
+                }
+                if (i > 0) f[0] += u[i - 1][NT - 1];
+                if (i == LA - 1) ulast = u[i][NT - 1];
+                const int h = i & 1;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) ub[i / 2][c] += tr.P[(h * NT + t) * kNt + c] * f[t];
+            }
+        }
+        xch[g][ml] = ulast;
+    }
+    __syncthreads();
+    if (active && g > 0) {
+        const double x0 = xch[g - 1][ml];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) ub[0][c] += tr.P[c] * x0;     // P^T row of t = 0, h = 0
+    }
+    __syncthreads();                               // xch is reused
+    // (2) level b: smoothing step from zero (ub becomes u_b), restriction into uc (f_c)
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < LCM; ++k)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) uc[k][t] = 0.0;
+#pragma unroll
+        for (int j = 0; j < LBM; ++j) {
+            if (j < LB) {
+                double r[NT], z[NT];
+                shifted_solve<NT, SCHUR>(*tmb, mu, ub[j], z);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    r[t] = (1.0 - omega) * ub[j][t];
+                    ub[j][t] = omega * z[t];
+                }
+                if (j > 0) r[0] += ub[j - 1][NT - 1];
+                if (j == LB - 1) blast = ub[j][NT - 1];
+                const int h = j & 1;
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) uc[j / 2][c] += tr.P[(h * NT + t) * kNt + c] * r[t];
+            }
+        }
+        xch[g][ml] = blast;
+    }
+    __syncthreads();
+    if (active && g > 0) {
+        const double x0 = xch[g - 1][ml];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) uc[0][c] += tr.P[c] * x0;
+    }
+    // (3) exact solve on level c, parallel in time over the groups
+    double cc[NT], xe = 0.0, gl = 1.0;
+    if (active) {
+        double e1[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+        shifted_solve<NT, SCHUR>(*tmc, mu, e1, cc);
+        const double gamma = cc[NT - 1];
+#pragma unroll
+        for (int k = 0; k < LCM; ++k) {
+            if (k < LC) {
+                double a[NT];
+                shifted_solve<NT, SCHUR>(*tmc, mu, uc[k], a);
+#pragma unroll
+                for (int t = 0; t < NT; ++t) uc[k][t] = a[t];
+                xe = a[NT - 1] + gamma * xe;
+                gl *= gamma;
+            }
+        }
+    }
+    xe_s[g][ml] = xe;
+    gl_s[g][ml] = gl;
+    __syncthreads();
+    double vlast = 0.0;
+    if (active) {
+        double x = 0.0;
+        for (int h = 0; h < g; ++h) x = xe_s[h][ml] + gl_s[h][ml] * x;
+#pragma unroll
+        for (int k = 0; k < LCM; ++k) {
+            if (k < LC) {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) uc[k][t] += x * cc[t];
+                x = uc[k][NT - 1];
+                if (k == LC - 1) {
+                    // prolonged coupling row of the group's last level-b slab (odd)
+                    vlast = blast;
+#pragma unroll
+                    for (int q = 0; q < NT; ++q) vlast += tr.P[(NT + NT - 1) * kNt + q] * uc[k][q];
+                }
+            }
+        }
+    }
+    __syncthreads();                               // xch is reused
+    if (active) xch[g][ml] = vlast;
+    __syncthreads();
+    // (4) level b: prolongation and the post-smoothing step (closed form)
+    if (active) {
+        double cbv[NT];
+        {
+            double e1[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) e1[t] = (t == 0) ? 1.0 : 0.0;
+            shifted_solve<NT, SCHUR>(*tmb, mu, e1, cbv);
+        }
+        double q = g > 0 ? xch[g - 1][ml] : 0.0;
+#pragma unroll
+        for (int j = 0; j < LBM; ++j) {
+            if (j < LB) {
+                const int h = j & 1;
+                double pu[NT];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    double w = 0.0;
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) w += tr.P[(h * NT + t) * kNt + k] * uc[j / 2][k];
+                    pu[t] = w;
+                }
+                const double qn = ub[j][NT - 1] + pu[NT - 1];
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                    ub[j][t] = (2.0 - omega) * ub[j][t] + (1.0 - omega) * pu[t] + omega * q * cbv[t];
+                q = qn;
+                if (j == LB - 1) {
+                    // prolonged coupling row of the group's last level-a slab (odd)
+                    vlast = ulast;
+#pragma unroll
+                    for (int k = 0; k < NT; ++k) vlast += tr.P[(NT + NT - 1) * kNt + k] * ub[j][k];
+                }
+            }
+        }
+    }
+    __syncthreads();                               // xch is reused
+    if (active) xch[g][ml] = vlast;
+    __syncthreads();
+    if (!active) return;
+    // (5) level a: prolongation and the post-smoothing step (closed form)
     double ca[NT];
     {
         double e1[NT];
@@ -1067,10 +1286,13 @@ hipError_t launch_cycle_sums(int dim, int n, long S, int chain, double* partial,
 // when the shape does not fit it
 bool coarse_tail_shape(int Nt, long SA, int* G, int* LA) {
     if (SA < 4 || SA % 4) return false;
-    const long g = SA / 2 < 32 ? SA / 2 : 32;
+    const long lamax = Nt <= 5 ? 8 : 4;
+    long g = SA / 2 < 32 ? SA / 2 : 32;
+    // beyond 32 groups of lamax slabs: 64 groups (1024 threads), N_t <= 3
+    if (SA / g > lamax && g == 32 && Nt <= 3) g = 64;
     if (SA % (2 * g)) return false;
     const long la = SA / g;
-    if (la > (Nt <= 5 ? 8 : 4)) return false;
+    if (la > lamax) return false;
     *G = (int)g;
     *LA = (int)la;
     return true;
@@ -1084,13 +1306,16 @@ static hipError_t launch_eig_coarse_tail_vt(int dim, int Nt, const TimeMix* tma_
     int G = 0, LA = 0;
     if (!coarse_tail_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
     dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
-#define STH_CT_GO(NTV, SC, LAMV)                                                                              \
-    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV, VT>), grid, block, 0, st, dim, tma_dev, tmb_dev, mu1, \
-                       n, Nx, fa, ua, tr, omega, G, LA, guard)
+#define STH_CT_GO(NTV, SC, LAMV, GMV)                                                                         \
+    hipLaunchKernelGGL((k_eig_coarse_tail<NTV, SC, LAMV, VT, GMV>), grid, block, 0, st, dim, tma_dev, tmb_dev, \
+                       mu1, n, Nx, fa, ua, tr, omega, G, LA, guard)
 #define STH_CT_LAM(NTV, SC)                                                                                  \
-    if (LA <= 2) STH_CT_GO(NTV, SC, 2);                                                                      \
-    else if (LA <= 4) STH_CT_GO(NTV, SC, 4);                                                                 \
-    else if (NTV <= 5) STH_CT_GO(NTV, SC, (NTV <= 5 ? 8 : 4));                                               \
+    if (G > 32) {                                                                                            \
+        if (NTV <= 3 && LA == 8) STH_CT_GO(NTV, SC, 8, (NTV <= 3 ? 64 : 32));                                  \
+        else return hipErrorInvalidValue;                                                                    \
+    } else if (LA <= 2) STH_CT_GO(NTV, SC, 2, 32);                                                           \
+    else if (LA <= 4) STH_CT_GO(NTV, SC, 4, 32);                                                             \
+    else if (NTV <= 5) STH_CT_GO(NTV, SC, (NTV <= 5 ? 8 : 4), 32);                                           \
     else return hipErrorInvalidValue;
 #define STH_CT_CASE(NTV)                                                                                     \
         case NTV:                                                                                             \
@@ -1115,6 +1340,64 @@ hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const
                                                 (float*)ua, tr, omega, SA, st, guard);
     return launch_eig_coarse_tail_vt<double>(dim, Nt, tma_dev, tmb_dev, schur, mu1, n, fa, ua, tr, omega, SA, st,
                                              guard);
+}
+
+bool coarse_tail3_shape(int Nt, long SA, int* G, int* LA) {
+    if (SA < 8 || SA % 8) return false;
+    const long lamax = Nt <= 5 ? 8 : 4;
+    long g = SA / 4 < 32 ? SA / 4 : 32;
+    // beyond 32 groups of lamax slabs: 64 groups (1024 threads), N_t <= 3
+    if (SA / g > lamax && g == 32 && Nt <= 3) g = 64;
+    if (SA % (4 * g)) return false;
+    const long la = SA / g;
+    if (la > lamax || (la != 4 && la != 8)) return false;
+    *G = (int)g;
+    *LA = (int)la;
+    return true;
+}
+
+template <typename VT>
+static hipError_t launch_eig_coarse_tail3_vt(int dim, int Nt, const TimeMix* tma, const TimeMix* tmb,
+                                             const TimeMix* tmc, bool schur, const double* mu1, int n, const VT* fa,
+                                             VT* ua, const Transfer& tr, double omega, long SA, hipStream_t st,
+                                             const int* guard) {
+    const long Nx = eig_modes(dim, n);
+    int G = 0, LA = 0;
+    if (!coarse_tail3_shape(Nt, SA, &G, &LA) || fa == ua) return hipErrorInvalidValue;
+    dim3 grid((unsigned)((Nx + 15) / 16)), block((unsigned)(16 * G));
+#define STH_T3_GO(NTV, SC, LAMV, GMV)                                                                         \
+    hipLaunchKernelGGL((k_eig_coarse_tail3<NTV, SC, LAMV, VT, GMV>), grid, block, 0, st, dim, tma, tmb, tmc,  \
+                       mu1, n, Nx, fa, ua, tr, omega, G, LA, guard)
+#define STH_T3_LAM(NTV, SC)                                                                                  \
+    if (G > 32) {                                                                                            \
+        if (NTV <= 3 && LA == 8) STH_T3_GO(NTV, SC, 8, (NTV <= 3 ? 64 : 32));                                  \
+        else return hipErrorInvalidValue;                                                                    \
+    } else if (LA == 4) STH_T3_GO(NTV, SC, 4, 32);                                                           \
+    else if (NTV <= 5) STH_T3_GO(NTV, SC, (NTV <= 5 ? 8 : 4), 32);                                           \
+    else return hipErrorInvalidValue;
+#define STH_T3_CASE(NTV)                                                                                     \
+        case NTV:                                                                                             \
+            if (schur) { STH_T3_LAM(NTV, true) } else { STH_T3_LAM(NTV, false) }                              \
+            break;
+    switch (Nt) {
+        STH_T3_CASE(2) STH_T3_CASE(3) STH_T3_CASE(4) STH_T3_CASE(5) STH_T3_CASE(6) STH_T3_CASE(7) STH_T3_CASE(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef STH_T3_CASE
+#undef STH_T3_LAM
+#undef STH_T3_GO
+    return hipGetLastError();
+}
+
+hipError_t launch_eig_coarse_tail3(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev,
+                                   const TimeMix* tmc_dev, bool schur, const double* mu1, int n, const double* fa,
+                                   double* ua, const Transfer& tr, double omega, long SA, hipStream_t st,
+                                   const int* guard, int vt) {
+    if (vt)
+        return launch_eig_coarse_tail3_vt<float>(dim, Nt, tma_dev, tmb_dev, tmc_dev, schur, mu1, n, (const float*)fa,
+                                                 (float*)ua, tr, omega, SA, st, guard);
+    return launch_eig_coarse_tail3_vt<double>(dim, Nt, tma_dev, tmb_dev, tmc_dev, schur, mu1, n, fa, ua, tr, omega,
+                                              SA, st, guard);
 }
 
 template <typename VT>

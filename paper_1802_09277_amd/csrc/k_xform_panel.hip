@@ -68,7 +68,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
     const int KP = SYM == 1 ? hn : (SYM == 2 ? n : 64 * ((np + 63) / 64));
     const int ngroups = KP / 64;                 // groups of four chunks of 16 k
     extern __shared__ double sm_raw[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: tile bookkeeping in scalars
     const int lr = lane & 15, lg = lane >> 4;
     // persistent block -> (panel, tile stream); see the file comment
     const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
@@ -99,80 +100,101 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
     // tiles: x axis, tile t = lines 16t..16t+15; strided axis, tile t =
     // (batch t / itb, columns 16 (t % itb) .. +15) with itb = ceil(inner / 16)
     const long itb = XAXIS ? 1 : (inner + 15) / 16;
-    for (long grp = stream;; grp += nstream) {
-        const long t = grp * kPanelWaves + wave;
-        if (t >= ntiles) break;
-        long rbase;                              // element (row lr, k) at in + rbase + lr * rs + k * ks
-        long rows_left;
-        long bbase = 0, i0 = 0;
+    // a wave's tile: element (row lr, k) at in + rbase + lr * rs + k * ks
+    struct Tile {
+        long t, rbase, rows_left, bbase, i0;
+        bool ok, row_ok;                         // the tile exists; row lr of it does
+    };
+    const long rs = XAXIS ? n : 1, ks = XAXIS ? 1 : inner;
+    auto tile_of = [&](long grp) {
+        Tile c;
+        c.t = grp * kPanelWaves + wave;
+        c.ok = c.t < ntiles;
+        c.bbase = 0;
+        c.i0 = 0;
         if (XAXIS) {
-            rbase = t * 16 * (long)n;
-            rows_left = nrows - t * 16;
+            c.rbase = c.t * 16 * (long)n;
+            c.rows_left = nrows - c.t * 16;
         } else {
-            const long bt = t / itb;
-            i0 = (t % itb) * 16;
-            bbase = bt * (long)n * inner;
-            rbase = bbase + i0;
-            rows_left = inner - i0;
+            const long bt = c.t / itb;
+            c.i0 = (c.t % itb) * 16;
+            c.bbase = bt * (long)n * inner;
+            c.rbase = c.bbase + c.i0;
+            c.rows_left = inner - c.i0;
         }
-        const long rs = XAXIS ? n : 1, ks = XAXIS ? 1 : inner;
-        const bool row_ok = lr < rows_left;
-        // lane (lr, lg) holds k = 64 gi + 16 c + 4 lg + e of row lr.  The
-        // loads of group gi + 1 go to ra (and, folding, rb: x_{n-1-k}) and
-        // are in flight while group gi is in the MFMAs; only then are they
-        // converted (and folded) into cur, held in the compute precision
-        // (FP32 for the FP32 and BF16x3 kernels).
-        using DT = typename std::conditional<F64, double, float>::type;
-        TI ra[4][4], rb[SYM == 1 ? 4 : 1][4];
-        auto load = [&](int gi) {
-            const int kb = 64 * gi + 4 * lg;
-            const int kend = SYM == 1 ? hn : n;
-            const TI* p = in + rbase + lr * rs + (long)kb * ks;
+        c.row_ok = c.ok && lr < c.rows_left;
+        return c;
+    };
+    // lane (lr, lg) holds k = 64 gi + 16 c + 4 lg + e of row lr.  The
+    // loads of group gi + 1 go to ra (and, folding, rb: x_{n-1-k}) and
+    // are in flight while group gi is in the MFMAs; only then are they
+    // converted (and folded) into cur, held in the compute precision
+    // (FP32 for the FP32 and BF16x3 kernels).
+    using DT = typename std::conditional<F64, double, float>::type;
+    TI ra[4][4], rb[SYM == 1 ? 4 : 1][4];
+    // addresses: a wave-uniform base (scalar registers) plus a 32-bit lane
+    // offset, the same for all sixteen loads of a group
+    const unsigned loff = (unsigned)(lr * rs + 4 * lg * ks);
+    const unsigned loff_m = (unsigned)(lr * rs + (12 - 4 * lg) * ks);   // mirrored rows, from k + 12
+    auto load = [&](const Tile& tl_, int gi) {
+        const int kb = 64 * gi + 4 * lg;
+        const int kend = SYM == 1 ? hn : n;
+        const bool row_ok = tl_.row_ok;
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    // (16 c + e) ks is the same for every lane
-                    const bool ok = row_ok && kb + 16 * c + e < kend;
-                    ra[c][e] = ok ? p[(long)(16 * c + e) * ks] : (TI)0;
-                    if constexpr (SYM == 1) {
-                        const TI* pm = in + rbase + lr * rs + (long)(n - 1 - kb) * ks;
-                        rb[c][e] = ok ? pm[-(long)(16 * c + e) * ks] : (TI)0;
-                    }
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = row_ok && kb + 16 * c + e < kend;
+                // element k = 64 gi + 16 c + e + 4 lg of row lr
+                const TI* pu = in + tl_.rbase + (long)(64 * gi + 16 * c + e) * ks;
+                ra[c][e] = ok ? pu[loff] : (TI)0;
+                if constexpr (SYM == 1) {
+                    // element n - 1 - k
+                    const TI* pm = in + tl_.rbase + (long)(n - 1 - 12 - 64 * gi - 16 * c - e) * ks;
+                    rb[c][e] = ok ? pm[loff_m] : (TI)0;
                 }
-        };
-        DT cur[4][4];
-        auto settle = [&]() {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if constexpr (SYM == 1) cur[c][e] = (DT)((double)ra[c][e] + sgn * (double)rb[c][e]);
-                    else cur[c][e] = (DT)ra[c][e];
-                }
-        };
-        // output j0 + jl of tile row il (x axis: line 16 t + il; strided
-        // axis: column i0 + il) from v; with the inverse split v + w there and
-        // v - w at the mirrored output n - 1 - j
-        auto put = [&](TO* o, double v) {
-            if (EPI == 0) *o = v;
-            else if (EPI == 1) *o += alpha * v;
-            else *o = alpha * v;
-        };
-        auto emit = [&](int jl, int il, double v, double w) {
-            const int j = j0 + jl;
-            if (il >= rows_left || j >= n) return;
-            TO* o = XAXIS ? out + (t * 16 + il) * (long)n : out + bbase + i0 + il;
-            const long js = XAXIS ? 1 : inner;
-            if (SYM == 2) {
-                put(o + j * js, v + w);
-                put(o + (n - 1 - j) * js, v - w);
-            } else {
-                put(o + j * js, v);
             }
-        };
-        load(0);
+    };
+    DT cur[4][4];
+    auto settle = [&]() {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if constexpr (SYM == 1) cur[c][e] = (DT)((double)ra[c][e] + sgn * (double)rb[c][e]);
+                else cur[c][e] = (DT)ra[c][e];
+            }
+    };
+    // output j0 + jl of tile row il (x axis: line 16 t + il; strided
+    // axis: column i0 + il) from v; with the inverse split v + w there and
+    // v - w at the mirrored output n - 1 - j
+    auto put = [&](TO* o, double v) {
+        if (EPI == 0) *o = v;
+        else if (EPI == 1) *o += alpha * v;
+        else *o = alpha * v;
+    };
+    auto emit = [&](const Tile& tc, int jl, int il, double v, double w) {
+        const int j = j0 + jl;
+        if (il >= tc.rows_left || j >= n) return;
+        TO* o = XAXIS ? out + (tc.t * 16 + il) * (long)n : out + tc.bbase + tc.i0 + il;
+        const long js = XAXIS ? 1 : inner;
+        if (SYM == 2) {
+            put(o + j * js, v + w);
+            put(o + (n - 1 - j) * js, v - w);
+        } else {
+            put(o + j * js, v);
+        }
+    };
+    // the first group of a wave's next tile is loaded during the last group
+    // of its current one
+    long grp = stream;
+    Tile tn = tile_of(grp);
+    if (tn.ok) load(tn, 0);
+    for (;; grp += nstream) {
+        const Tile tc = tn;
+        if (!tc.ok) break;
         settle();
+        tn = tile_of(grp + nstream);
         if constexpr (BF) {
             const unsigned short* th = reinterpret_cast<const unsigned short*>(sm_raw);
             const unsigned short* tl = th + (size_t)pw * (KP + 4);
@@ -215,7 +237,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
             };
 #pragma unroll 1
             for (int gi = 0; gi < ngroups; ++gi) {
-                if (gi + 1 < ngroups) load(gi + 1);
+                if (gi + 1 < ngroups) load(tc, gi + 1);
+                else if (tn.ok) load(tn, 0);
                 int nz = 0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
@@ -237,7 +260,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
             for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    emit(XAXIS ? jt * 16 + lr : jt * 16 + 4 * lg + r, XAXIS ? 4 * lg + r : lr, (double)acc[jt][r],
+                    emit(tc, XAXIS ? jt * 16 + lr : jt * 16 + 4 * lg + r, XAXIS ? 4 * lg + r : lr, (double)acc[jt][r],
                          SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0);
             (void)acc2;
         } else {
@@ -271,7 +294,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
             };
 #pragma unroll 1
             for (int gi = 0; gi < ngroups; ++gi) {
-                if (gi + 1 < ngroups) load(gi + 1);
+                if (gi + 1 < ngroups) load(tc, gi + 1);
+                else if (tn.ok) load(tn, 0);
                 int nz = 0;
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
@@ -292,7 +316,7 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
             for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    emit(XAXIS ? jt * 16 + lr : jt * 16 + M::row(lg, r), XAXIS ? M::row(lg, r) : lr,
+                    emit(tc, XAXIS ? jt * 16 + lr : jt * 16 + M::row(lg, r), XAXIS ? M::row(lg, r) : lr,
                          (double)acc[jt][r], SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0);
             (void)acc2;
         }
@@ -344,7 +368,8 @@ static hipError_t panel_pw(int sym, const TI* in, TO* out, const double* T, int 
         // the folding loads take a second set of registers: width 128 on the
         // x axis only (n / 2 is 64 or 128)
         if (EPI != 0) return hipErrorInvalidValue;
-        if constexpr (PanelTraits<C>::PW >= 128 && XAXIS)
+        // (in FP64 too: half as many panels re-read each line)
+        if constexpr (XAXIS)
             if (n == 256) return panel_go<C, 128, XAXIS, EPI, TI, TO, 1>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
         return panel_go<C, 64, XAXIS, EPI, TI, TO, 1>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
     }
@@ -356,7 +381,7 @@ static hipError_t panel_pw(int sym, const TI* in, TO* out, const double* T, int 
                 if (n == 256) return panel_go<C, 128, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
             return panel_go<C, 64, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
         } else {
-            if constexpr (PanelTraits<C>::PW >= 128)
+            if constexpr (std::is_same<C, PanelF32>::value)
                 if (n == 256) return panel_go<C, 64, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
             return panel_go<C, 32, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
         }

@@ -200,6 +200,16 @@ hipError_t launch_eig_coarse_tail(int dim, int Nt, const TimeMix* tma_dev, const
                                   const double* mu1, int n, const double* fa, double* ua,
                                   const Transfer& tr, double omega, long SA, hipStream_t st,
                                   const int* guard = nullptr, int vt = 0);
+//  the three coarsest levels in one pass (a, b, c with SA, SA/2, SA/4
+//  slabs): the descent of the two-level pass on a and on b, the exact solve
+//  of c, and the closed-form post-smoothing step on b and then on a; ua =
+//  level a's result.  coarse_tail3_shape says whether SA fits (slab groups
+//  of 4 or 8 level-a slabs; 64 groups for N_t <= 3).
+bool coarse_tail3_shape(int Nt, long SA, int* G, int* LA);
+hipError_t launch_eig_coarse_tail3(int dim, int Nt, const TimeMix* tma_dev, const TimeMix* tmb_dev,
+                                   const TimeMix* tmc_dev, bool schur, const double* mu1, int n, const double* fa,
+                                   double* ua, const Transfer& tr, double omega, long SA, hipStream_t st,
+                                   const int* guard = nullptr, int vt = 0);
 //  rh = fh - L uh
 hipError_t launch_eig_residual(int dim, int Nt, const double* ktmt, const double* mu1, int n, const double* fh,
                                const double* uh, double* rh, long S, hipStream_t st);

@@ -86,6 +86,7 @@ struct sth_handle {
     double* e3 = nullptr;               // third level-0 iterate buffer of the fused cycle close
     bool fuse_close = false;            // post-smoothing of level 0 fused into the cycle-end pass
     bool fuse_tail = false;             // the two coarsest levels in one pass (k_eig_coarse_tail)
+    bool fuse_tail3 = false;            // the three coarsest levels in one pass (k_eig_coarse_tail3)
     TimeMix* dmix = nullptr;            // per level slab inverse in device memory
     bool defer_close = false;           // set by a solve iteration: level 0 leaves its post-smoothing
     const double* pending_ec = nullptr; // coarse correction waiting for the fused cycle close
@@ -815,6 +816,17 @@ static int eig_vcycle(sth_handle* h, int lvl, bool zero_guess, hipStream_t st) {
         return STH_OK;
     }
     int rc;
+    if (lvl == h->L - 3 && lvl > 0 && zero_guess && h->fuse_tail3) {
+        // descent over two levels, exact coarsest solve and post-smoothing of
+        // the last three levels from this level's right-hand side in one pass
+        double dof = (double)S * slab_len(h);
+        Timed tm(h, STH_K_EIG_COARSE, dof * (12.0 * h->Nt + 14.0), 16.0 * dof, st);
+        HIPCHK(launch_eig_coarse_tail3(h->dim, h->Nt, h->dmix + lvl, h->dmix + lvl + 1, h->dmix + lvl + 2,
+                                       h->mixes[lvl].schur != 0, h->mu1, h->n, eig_f(h, lvl), eig_u(h, lvl, 0),
+                                       h->tr, h->omega, S, st, h->guard, h->f32));
+        h->ecur[lvl] = 0;
+        return STH_OK;
+    }
     if (lvl == h->L - 2 && lvl > 0 && zero_guess && h->fuse_tail) {
         // descent, exact coarsest solve and post-smoothing of the last two
         // levels from this level's right-hand side in one pass
@@ -1323,6 +1335,10 @@ static int setup_problem(Problem q, hipStream_t s, sth_handle** out) {
         h->fuse_tail = h->basis == 1 && h->nu_pre == 1 && h->nu_post == 1 && h->L >= 3 &&
                        h->S.levels[h->L - 2].schur == h->S.levels[h->L - 1].schur &&
                        coarse_tail_shape(h->Nt, h->S.levels[h->L - 2].S, &G, &LA);
+        h->fuse_tail3 = h->basis == 1 && h->nu_pre == 1 && h->nu_post == 1 && h->L >= 4 &&
+                        h->S.levels[h->L - 3].schur == h->S.levels[h->L - 1].schur &&
+                        h->S.levels[h->L - 2].schur == h->S.levels[h->L - 1].schur &&
+                        coarse_tail3_shape(h->Nt, h->S.levels[h->L - 3].S, &G, &LA);
     }
     for (auto& lv : h->S.levels) {
         h->lev_S.push_back(lv.S);

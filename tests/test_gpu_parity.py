@@ -43,6 +43,15 @@ SHAPES = {
     # n = 113 (np = 128): the per-axis transforms with the transform matrix in
     # LDS (two 64-column panels in FP64), a ragged last tile of k and rows
     "2d_n113_panel": dict(dim=2, n_elem=113, degree=2, n_slabs=2, n_elem_t=1, coarse_slabs=1),
+    # 1024 -> 512 -> 256 slabs, N_t = 3: the two coarsest levels in one pass
+    # with 64 slab groups of 8 level-a slabs (1024-thread blocks)
+    "2d_wide_tail": dict(dim=2, n_elem=4, degree=1, n_slabs=1024, n_elem_t=2, coarse_slabs=256),
+    # 1024 -> 512 -> 256 -> 128 slabs, N_t = 3 (the level structure of the
+    # large 2-D workload): the three coarsest levels in one pass, 64 groups
+    "2d_wide_tail3": dict(dim=2, n_elem=4, degree=1, n_slabs=1024, n_elem_t=2, coarse_slabs=128),
+    # 64 -> 32 -> 16 -> 8 slabs, N_t = 5: the three-level pass with 8 groups
+    # of 4 level-a slabs
+    "2d_p3_tail3": dict(dim=2, n_elem=6, degree=3, n_slabs=64, n_elem_t=2, coarse_slabs=8),
 }
 
 
