@@ -298,9 +298,12 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
                                                        VT* __restrict__ uout, VT* __restrict__ fc,
                                                        Transfer tr, double omega, int chain, long total,
                                                        const double* __restrict__ vw,
-                                                       double* __restrict__ partial) {
+                                                       double* __restrict__ partial,
+                                                       const int* __restrict__ unz) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     double ssq = 0.0, wsq = 0.0, usq = 0.0;
+    // with unz given and *unz == 0 the input iterate is zero and not read
+    const bool zin = unz && *unz == 0;
     if (idx < total) {
         const long q = idx / Nx, m = idx % Nx;
         const long s0 = q * chain;
@@ -313,7 +316,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 fnx[t] = fh[b + (long)t * Nx];
-                unx[t] = uin[b + (long)t * Nx];
+                unx[t] = zin ? 0.0 : (double)uin[b + (long)t * Nx];
             }
         }
         double pg[NT], pu[NT], pq = 0.0;
@@ -322,9 +325,9 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 pg[t] = fh[b + (long)t * Nx];
-                pu[t] = uin[b + (long)t * Nx];
+                pu[t] = zin ? 0.0 : (double)uin[b + (long)t * Nx];
             }
-            if (s0 > 1) pq = uin[b - Nx];
+            if (s0 > 1 && !zin) pq = uin[b - Nx];
         }
         const double mu = mode_shift(dim, mu1, n, m);
         const ModeShift<NT> sh = mode_shift_inv<NT, SCHUR>(tm, mu);
@@ -351,7 +354,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     fnx[t] = fh[b + NT * Nx + (long)t * Nx];
-                    unx[t] = uin[b + NT * Nx + (long)t * Nx];
+                    unx[t] = zin ? 0.0 : (double)uin[b + NT * Nx + (long)t * Nx];
                 }
             }
             eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
@@ -1183,7 +1186,7 @@ static hipError_t launch_eig_cycle_end_vt(int dim, int Nt, const TimeMix& tm, co
                                 const VT* fh, const VT* uin, VT* uout, VT* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
                                 long max_partial, double* out, double* out_host, hipStream_t st,
-                                const CycleFlag& flag) {
+                                const CycleFlag& flag, const int* unz) {
     const long Nx = eig_modes(dim, n);
     if (chain < 2 || chain % 2 || S <= 0 || S % chain || !vw) return hipErrorInvalidValue;
     if (flag.dev && (!flag.host || !flag.thr)) return hipErrorInvalidValue;
@@ -1196,10 +1199,10 @@ static hipError_t launch_eig_cycle_end_vt(int dim, int Nt, const TimeMix& tm, co
         case NTV:                                                                                             \
             if (tm.schur)                                                                                     \
                 hipLaunchKernelGGL((k_eig_cycle_end<NTV, true, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1, n, \
-                                   Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);              \
+                                   Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial, unz);         \
             else                                                                                              \
                 hipLaunchKernelGGL((k_eig_cycle_end<NTV, false, VT>), grid, dim3(256), 0, st, dim, tm, ktmt, mu1,   \
-                                   n, Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial);           \
+                                   n, Nx, fh, uin, uout, fc, tr, omega, chain, total, vw, partial, unz);      \
             break;
         STH_CE_CASE(2) STH_CE_CASE(3) STH_CE_CASE(4) STH_CE_CASE(5) STH_CE_CASE(6) STH_CE_CASE(7) STH_CE_CASE(8)
 #undef STH_CE_CASE
@@ -1212,13 +1215,13 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
                                 long max_partial, double* out, double* out_host, hipStream_t st,
-                                const CycleFlag& flag, int vt) {
+                                const CycleFlag& flag, int vt, const int* unz) {
     if (vt)
         return launch_eig_cycle_end_vt<float>(dim, Nt, tm, ktmt, mu1, n, (const float*)fh, (const float*)uin,
                                               (float*)uout, (float*)fc, tr, omega, S, chain, vw, partial,
-                                              max_partial, out, out_host, st, flag);
+                                              max_partial, out, out_host, st, flag, unz);
     return launch_eig_cycle_end_vt<double>(dim, Nt, tm, ktmt, mu1, n, fh, uin, uout, fc, tr, omega, S, chain, vw,
-                                           partial, max_partial, out, out_host, st, flag);
+                                           partial, max_partial, out, out_host, st, flag, unz);
 }
 
 template <typename VT>

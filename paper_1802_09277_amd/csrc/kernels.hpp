@@ -166,7 +166,8 @@ hipError_t launch_eig_cycle_end(int dim, int Nt, const TimeMix& tm, const double
                                 const double* fh, const double* uin, double* uout, double* fc, const Transfer& tr,
                                 double omega, long S, int chain, const double* vw, double* partial,
                                 long max_partial, double* out, double* out_host, hipStream_t st,
-                                const CycleFlag& flag = CycleFlag{}, int vt = 0);
+                                const CycleFlag& flag = CycleFlag{}, int vt = 0, const int* unz = nullptr);
+//  (unz given and *unz == 0 on the device: uin is zero and is not read)
 //  close of a cycle on the finest level and start of the next in one pass
 //  (chains and sums as above): u1 = upre + (P_t (x) I) ec, uend = u1 +
 //  omega A^{-1}(fh - L u1) (the cycle's result), the three sums of

@@ -94,13 +94,19 @@ struct sth_handle {
     // (level-0 buffer dst): it is formed from the close's inputs (the
     // pre-smoothed buffer c and the coarse correction ec, which stay intact
     // until the next cycle runs) only when it is read (form_result).
+    // A zero initial guess is likewise left unwritten (zero): buffer dst is
+    // filled with zeros when read, where the device flag zguard is 0 (always
+    // without one); the initial pass reads that flag instead of the buffer.
     struct Unformed {
         bool on = false;
         int c = 0, dst = 0;
         const double* ec = nullptr;
+        bool zero = false;
+        const int* zguard = nullptr;
     };
     Unformed unformed;
     bool lazy_close = false;            // set by the solve loop around its cycles
+    const int* zero_in = nullptr;       // device flag of an unwritten zero guess (Unformed::zero)
     int pre_idx = 1;                    // level-0 buffer of the pre-smoothed iterate
     std::vector<double*> lu2;           // ping-pong partner of lu on levels >= 1
     // FP32 storage of the eigenbasis vectors (the inner solves of the mixed
@@ -240,7 +246,7 @@ struct sth_handle {
     int* dgo = nullptr;                 // per norm slot: continuation flag of the cycle (device);
                                         // [2]: the final exact norm ends the solve; [3]: the
                                         // initial pass of a speculative solve; [4]: the initial
-                                        // guess of the solve has a nonzero entry
+                                        // guess of the solve has a nonzero entry; [5]: always 0
     int* hflag = nullptr;               // its mapped host copy
     int* hflag_dev = nullptr;
     double* dthr = nullptr;             // (rtol ||f||)^2 and rtol ||f|| of the solve in progress (device)
@@ -959,10 +965,12 @@ static int eig_residual_cheap(sth_handle* h, hipStream_t st) {
         CycleFlag flag;
         if (h->first_flag) flag = CycleFlag{h->dgo + 3, h->hflag_dev + 3, h->dthr, h->nb_lo};
         const int at = slot_base(h->first_flag ? 2 : 0);
+        // the zero guess of a solve's start is read through its device flag
+        const int* unz = (h->unformed.on && h->unformed.zero && h->unformed.dst == c) ? h->zero_in : nullptr;
         HIPCHK(launch_eig_cycle_end(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                     eig_u(h, 0, c), eig_u(h, 0, o), eig_f(h, 1), h->tr, h->omega, S,
                                     chain_length(h, S, 65536), h->vw, h->cpartial, h->n_cpartial, h->dnorm + at,
-                                    h->hnorm_dev + at, st, flag, h->f32));
+                                    h->hnorm_dev + at, st, flag, h->f32, unz));
         h->wsum_valid = true;
         h->last_slot = 0;
         h->pre_idx = o;
@@ -996,6 +1004,10 @@ static int form_result(sth_handle* h, hipStream_t st) {
     h->tlev = 0;
     const long S = h->lev_S[0];
     const double dof = (double)S * slab_len(h);
+    if (uf.zero) {
+        HIPCHK(launch_fill(eig_u(h, 0, uf.dst), S * eslab_len(h), 0.0, st, uf.zguard, h->f32));
+        return STH_OK;
+    }
     Timed tm(h, STH_K_EIG_SMOOTH, dof * (10.0 * h->Nt + 8.0), 28.0 * dof, st);
     HIPCHK(launch_eig_cycle_close(h->dim, h->Nt, h->mixes[0], level_ktmt(h, 0), h->mu1, h->n, h->e0,
                                   eig_u(h, 0, uf.c), uf.ec, eig_u(h, 0, uf.dst), nullptr, nullptr, h->tr, h->omega,
@@ -1514,9 +1526,12 @@ static int setup_problem(Problem q, hipStream_t s, sth_handle** out) {
         hipHostGetDevicePointer((void**)&h->hflag_dev, h->hflag, 0) != hipSuccess ||
         hipHostGetDevicePointer((void**)&h->hseq_dev, h->hseq, 0) != hipSuccess)
         return cleanup(STH_EHIP, "pinned host memory is not mapped");
-    if (hipMalloc((void**)&h->dgo, 5 * sizeof(int)) != hipSuccess ||
+    if (hipMalloc((void**)&h->dgo, 6 * sizeof(int)) != hipSuccess ||
         hipMalloc((void**)&h->dthr, 2 * sizeof(double)) != hipSuccess)
         return cleanup(STH_ENOMEM, "device allocation failed");
+    // dgo[5] stays 0: the flag of an inner solve's zero guess
+    if (hipMemsetAsync(h->dgo, 0, 6 * sizeof(int), s) != hipSuccess)
+        return cleanup(STH_EHIP, "clearing the device flags failed");
     for (auto& e : h->evring)
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
             return cleanup(STH_EHIP, "event creation failed");
@@ -1907,16 +1922,31 @@ static int solve_begin_impl(sth_handle* h, const double* f, double* u, double rt
                                 h->f32 ? h->buf1 : nullptr, h->f32 ? 2 : 0)))
             return rc;
         h->tlev = 0;
+        // with the initial pass next (cycle-end kernel), a zero guess is not
+        // written: that pass reads the device flag instead, and the buffer is
+        // filled only if it is read as the iterate (form_result)
+        const bool lazy_zero = h->nu_pre == 1 && h->L > 1;
+        const int* zg = nullptr;
         if (v.inner) {
-            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nullptr, h->f32));   // zero guess
+            zg = h->dgo + 5;                            // holds 0: the guess is zero
+            if (!lazy_zero) HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nullptr, h->f32));
         } else {
             // an initial guess of zeros (the usual start) needs no transform:
             // a device flag says whether u has a nonzero entry; the transform
             // runs only then, the fill of zeros only otherwise
             int* nz = h->dgo + 4;
+            zg = nz;
             HIPCHK(launch_any_nonzero(u, len, nz, st));
             if ((rc = spatial_apply(h, FWD_C, u, h->e1, rows, h->buf0, st, nz))) return rc;
-            HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nz, h->f32));
+            if (!lazy_zero) HIPCHK(launch_fill(h->e1, h->lev_S[0] * eslab_len(h), 0.0, st, nz, h->f32));
+        }
+        if (lazy_zero) {
+            h->unformed = sth_handle::Unformed{};
+            h->unformed.on = true;
+            h->unformed.zero = true;
+            h->unformed.dst = 0;
+            h->unformed.zguard = zg;
+            h->zero_in = zg;
         }
         // (with graph replay, whose captured cycles have fixed guards, the
         // first cycle waits for the initial norms instead)
