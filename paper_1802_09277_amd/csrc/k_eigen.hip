@@ -282,6 +282,14 @@ __global__ __launch_bounds__(256) void k_eig_resid_restrict(Transfer tr, const d
     for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
 }
 
+// Streaming accesses of data touched once per pass (nontemporal hint)
+template <typename T> __device__ __forceinline__ double stream_load(const T* p) {
+    return (double)__builtin_nontemporal_load(p);
+}
+template <typename T> __device__ __forceinline__ void stream_store(T* p, double v) {
+    __builtin_nontemporal_store((T)v, p);
+}
+
 // End of a cycle on the finest level, for one spatial mode and a chain of
 // `chain` consecutive slabs (chain even, starting at an even slab): the
 // residual r^ = f^ - L u^ of the iterate (its squares summed per block into
@@ -353,8 +361,8 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
             if (k + 1 < chain) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    fnx[t] = fh[b + NT * Nx + (long)t * Nx];
-                    unx[t] = zin ? 0.0 : (double)uin[b + NT * Nx + (long)t * Nx];
+                    fnx[t] = stream_load(fh + b + NT * Nx + (long)t * Nx);
+                    unx[t] = zin ? 0.0 : stream_load(uin + b + NT * Nx + (long)t * Nx);
                 }
             }
             eig_residual_point<NT>(ktmt, mu, u, prev_old, g);
@@ -368,7 +376,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 up[t] = u[t] + omega * z[t];
-                uout[b + (long)t * Nx] = up[t];
+                stream_store(uout + b + (long)t * Nx, up[t]);
             }
             // residual of u': A z = g (the block of the smoother is the slab
             // operator), so f - A u' + e_1 u'_prev = (1 - omega) g + e_1 (u'_prev - u_prev)
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_end(int dim, TimeMix tm, cons
             if (h == 1) {
                 const long mc = (s0 + k) / 2;
 #pragma unroll
-                for (int c = 0; c < NT; ++c) fc[mc * NT * Nx + m + (long)c * Nx] = acc[c];
+                for (int c = 0; c < NT; ++c) stream_store(fc + mc * NT * Nx + m + (long)c * Nx, acc[c]);
             }
             prev_old = u[NT - 1];
             prev_new = up[NT - 1];
@@ -527,13 +535,13 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             if (k + 1 < chain) {
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
-                    fnx[t] = fh[b + slab + (long)t * Nx];
-                    unx[t] = upre[b + slab + (long)t * Nx];
+                    fnx[t] = stream_load(fh + b + slab + (long)t * Nx);
+                    unx[t] = stream_load(upre + b + slab + (long)t * Nx);
                 }
                 if (h == 1) {
                     const long bc = ((s0 + k + 1) / 2) * slab + m;
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) cnx[t] = ec[bc + (long)t * Nx];
+                    for (int t = 0; t < NT; ++t) cnx[t] = stream_load(ec + bc + (long)t * Nx);
                 }
             }
             // post-smoothing step from the prolonged iterate
@@ -543,7 +551,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 u2[t] = u1[t] + omega * z[t];
-                if (uend) uend[b + (long)t * Nx] = u2[t];
+                if (uend) stream_store(uend + b + (long)t * Nx, u2[t]);
                 g[t] *= (1.0 - omega);
             }
             if (!unext) {                       // the result alone
@@ -564,7 +572,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const double u3 = u2[t] + omega * ((1.0 - omega) * z[t] + d2 * ca[t]);
-                unext[b + (long)t * Nx] = u3;
+                stream_store(unext + b + (long)t * Nx, u3);
                 if (t == NT - 1) u3last = u3;
                 g[t] *= (1.0 - omega);
             }
@@ -580,7 +588,7 @@ __global__ __launch_bounds__(256) void k_eig_cycle_close(int dim, TimeMix tm, co
             if (h == 1) {
                 const long mc = (s0 + k) / 2;
 #pragma unroll
-                for (int cc = 0; cc < NT; ++cc) fc[mc * slab + m + (long)cc * Nx] = acc[cc];
+                for (int cc = 0; cc < NT; ++cc) stream_store(fc + mc * slab + m + (long)cc * Nx, acc[cc]);
             }
             p1 = u1[NT - 1];
             p2 = u2[NT - 1];
@@ -784,7 +792,7 @@ __global__ __launch_bounds__(16 * GM) void k_eig_coarse_tail3(int dim, const Tim
                 double f[NT], z[NT];
                 const long b = (sa0 + i) * slab + m;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) f[t] = fa[b + (long)t * Nx];
+                for (int t = 0; t < NT; ++t) f[t] = stream_load(fa + b + (long)t * Nx);
                 shifted_solve<NT, SCHUR>(*tma, mu, f, z);
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
@@ -951,7 +959,7 @@ __global__ __launch_bounds__(16 * GM) void k_eig_coarse_tail3(int dim, const Tim
             }
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-                ua[b + (long)t * Nx] = (2.0 - omega) * u[i][t] + (1.0 - omega) * pu[t] + omega * q * ca[t];
+                stream_store(ua + b + (long)t * Nx, (2.0 - omega) * u[i][t] + (1.0 - omega) * pu[t] + omega * q * ca[t]);
             q = u[i][NT - 1] + pu[NT - 1];
         }
     }

@@ -286,9 +286,20 @@ __global__ __launch_bounds__(256) void k_norm2_partial(const double* __restrict_
     __shared__ double sh[256];
     long beg = (long)blockIdx.x * chunk;
     long end = beg + chunk < len ? beg + chunk : len;
-    double s = 0.0;
-    for (long i = beg + threadIdx.x; i < end; i += 256) s += v[i] * v[i];
-    double tot = block_sum_256(s, sh);
+    // four independent sums (four loads in flight per thread), combined in a
+    // fixed order; streaming loads (each entry is read once)
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    long i = beg + threadIdx.x;
+    for (; i + 768 < end; i += 1024) {
+        const double a0 = __builtin_nontemporal_load(v + i), a1 = __builtin_nontemporal_load(v + i + 256);
+        const double a2 = __builtin_nontemporal_load(v + i + 512), a3 = __builtin_nontemporal_load(v + i + 768);
+        s0 += a0 * a0;
+        s1 += a1 * a1;
+        s2 += a2 * a2;
+        s3 += a3 * a3;
+    }
+    for (; i < end; i += 256) s0 += v[i] * v[i];
+    double tot = block_sum_256((s0 + s1) + (s2 + s3), sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
