@@ -435,6 +435,31 @@ def test_speculative_cycles_match_plain_loop(name):
     assert np.array_equal(outs[0][3], outs[1][3])
 
 
+@pytest.mark.parametrize("spec", [False, True])
+def test_zero_guess_start_without_cycles(spec):
+    """A zero initial guess is not written to the eigenbasis buffer (the
+    initial pass reads its device flag); a solve that ends before any cycle
+    must still return exactly the zero guess, also after an earlier solve
+    has left other values in that buffer: maxit = 0, and f = 0 (converged at
+    the start)."""
+    name = "2d_16slabs"
+    banner(name, f"zero guess, no cycles, speculate={spec}")
+    prob, _ = oracle_for(name)
+    s = eigen_solver_for(name)
+    s.speculate(spec)
+    f = dev(assemble_rhs(prob, W.random_modes(8, prob.dim)))
+    u = s.new_vector()
+    it, rr, _ = s.solve(f, u, rtol=1e-10, maxit=60)        # leaves the eigenbasis buffers nonzero
+    assert it > 0 and np.abs(host(u)).max() > 0
+    u = s.new_vector()
+    it, rr, code = s.solve(f, u, rtol=1e-10, maxit=0, check=False)
+    assert it == 0 and not host(u).any(), (it, code)
+    u = s.new_vector()
+    it, rr, code = s.solve(s.new_vector(), u, rtol=1e-8, maxit=10, check=False)
+    assert (it, code) == (0, 0) and not host(u).any()
+    s.speculate(True)
+
+
 # ---------------------------------------------------------------------------
 # Cycle shapes other than V(1,1) in the eigenbasis iteration (the fused
 # passes are V(1,1) only; these run the general level loop, including the
