@@ -226,6 +226,7 @@ struct sth_handle {
         // known, transforms in precision tprec, no exact B-spline norm (the
         // lower bound decides), the result added into u
         bool inner = false;
+        bool inner_store = false;       // the inner result is stored into u (u was zero), not added
         int tprec = STH_FP64;
     } sv;
     // Mixed-precision solve (eigenbasis iteration with reduced-precision
@@ -2053,9 +2054,9 @@ static int solve_finish(sth_handle* h, bool* more) {
     h->wait_slot = -1;
     int rc = form_result(h, v.st);
     if (rc) return rc;
-    // u = (I (x) U_x) u^ (an inner solve adds it to u)
+    // u = (I (x) U_x) u^ (an inner solve adds it to u, unless u is zero)
     return spatial_apply(h, INV_U, eig_u(h, 0, h->ecur[0]), v.u, h->lev_S[0] * h->Nt, h->buf0, v.st, nullptr,
-                         v.tprec, v.inner ? 1 : 0, h->buf1, h->f32 ? 1 : 0);
+                         v.tprec, (v.inner && !v.inner_store) ? 1 : 0, h->buf1, h->f32 ? 1 : 0);
 }
 
 // Lower bound of the B-spline residual norm of the cycle whose sums are in
@@ -2394,12 +2395,14 @@ static int mixed_begin(sth_handle* h, const double* f, double* u, double rtol, i
 }
 
 // the inner solve of L e = r to eta ||r|| (at least what the tolerance needs,
-// with a margin), added into u; r is the outer residual (buf1) or f
-static int mixed_inner(sth_handle* h, const double* r, double rn) {
+// with a margin), added into u (stored, when u is zero); r is the outer
+// residual (buf1) or f
+static int mixed_inner(sth_handle* h, const double* r, double rn, bool u_zero = false) {
     auto& m = h->mx;
     const double eta = std::max(mixed_inner_eta(h->prec), 0.5 * m.rtol * m.fn / rn);
     int rc = solve_begin_impl(h, r, m.u, eta, m.maxit - m.it, m.st, &rn, h->prec);
     if (rc) return rc;
+    h->sv.inner_store = u_zero;
     m.phase = 1;
     return STH_OK;
 }
@@ -2424,7 +2427,7 @@ static int mixed_continue(sth_handle* h, bool* more) {
             return STH_OK;
         }
         *more = true;
-        return mixed_inner(h, m.f, rn);
+        return mixed_inner(h, m.f, rn, true);
     }
     if (m.phase == 1) {
         bool inner_more = false;
