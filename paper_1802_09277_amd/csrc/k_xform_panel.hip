@@ -168,22 +168,33 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
     // output j0 + jl of tile row il (x axis: line 16 t + il; strided
     // axis: column i0 + il) from v; with the inverse split v + w there and
     // v - w at the mirrored output n - 1 - j
-    auto put = [&](TO* o, double v) {
+    // The update epilogue (EPI 1) reads the tile's old outputs first, all of
+    // them, so that their loads overlap (old[0], and old[1] at the mirror).
+    constexpr int NS = SYM == 2 ? 2 : 1;
+    auto put = [&](TO* o, double v, double old) {
         if (EPI == 0) *o = v;
-        else if (EPI == 1) *o += alpha * v;
+        else if (EPI == 1) *o = old + alpha * v;
         else *o = alpha * v;
     };
-    auto emit = [&](const Tile& tc, int jl, int il, double v, double w) {
+    auto emit = [&](const Tile& tc, int jl, int il, double v, double w, const double* old) {
         const int j = j0 + jl;
         if (il >= tc.rows_left || j >= n) return;
         TO* o = XAXIS ? out + (tc.t * 16 + il) * (long)n : out + tc.bbase + tc.i0 + il;
         const long js = XAXIS ? 1 : inner;
         if (SYM == 2) {
-            put(o + j * js, v + w);
-            put(o + (n - 1 - j) * js, v - w);
+            put(o + j * js, v + w, old[0]);
+            put(o + (n - 1 - j) * js, v - w, old[NS - 1]);
         } else {
-            put(o + j * js, v);
+            put(o + j * js, v, old[0]);
         }
+    };
+    auto gather = [&](const Tile& tc, int jl, int il, double* old) {
+        const int j = j0 + jl;
+        if (il >= tc.rows_left || j >= n) return;
+        const TO* o = XAXIS ? out + (tc.t * 16 + il) * (long)n : out + tc.bbase + tc.i0 + il;
+        const long js = XAXIS ? 1 : inner;
+        old[0] = o[j * js];
+        if (SYM == 2) old[NS - 1] = o[(n - 1 - j) * js];
     };
     // the first group of a wave's next tile is loaded during the last group
     // of its current one
@@ -256,12 +267,20 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
                 if (gi + 1 < ngroups) settle();
             }
             // D[4 lg + r][lr]: x axis (line, j), strided axis (j, i)
+            double old[EPI == 1 ? NJT : 1][4][NS] = {};
+            if constexpr (EPI == 1) {
+#pragma unroll
+                for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        gather(tc, XAXIS ? jt * 16 + lr : jt * 16 + 4 * lg + r, XAXIS ? 4 * lg + r : lr, old[jt][r]);
+            }
 #pragma unroll
             for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     emit(tc, XAXIS ? jt * 16 + lr : jt * 16 + 4 * lg + r, XAXIS ? 4 * lg + r : lr, (double)acc[jt][r],
-                         SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0);
+                         SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0, old[EPI == 1 ? jt : 0][r]);
             (void)acc2;
         } else {
             using CT = typename std::conditional<F64, double, float>::type;
@@ -312,12 +331,22 @@ __global__ __launch_bounds__(kPanelThreads) void k_xform_panel(const TI* __restr
                 }
                 if (gi + 1 < ngroups) settle();
             }
+            double old[EPI == 1 ? NJT : 1][4][NS] = {};
+            if constexpr (EPI == 1) {
+#pragma unroll
+                for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        gather(tc, XAXIS ? jt * 16 + lr : jt * 16 + M::row(lg, r), XAXIS ? M::row(lg, r) : lr,
+                               old[jt][r]);
+            }
 #pragma unroll
             for (int jt = 0; jt < NJT; ++jt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     emit(tc, XAXIS ? jt * 16 + lr : jt * 16 + M::row(lg, r), XAXIS ? M::row(lg, r) : lr,
-                         (double)acc[jt][r], SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0);
+                         (double)acc[jt][r], SYM == 2 ? (double)acc2[SYM == 2 ? jt : 0][r] : 0.0,
+                         old[EPI == 1 ? jt : 0][r]);
             (void)acc2;
         }
     }
@@ -377,7 +406,8 @@ static hipError_t panel_pw(int sym, const TI* in, TO* out, const double* T, int 
         // two accumulator sets (even and odd modes): on the strided axis,
         // whose addressing takes more registers, at half the width
         if constexpr (XAXIS) {
-            if constexpr (PanelTraits<C>::PW >= 128)
+            // (the update epilogue holds the old outputs too: width 64)
+            if constexpr (PanelTraits<C>::PW >= 128 && EPI != 1)
                 if (n == 256) return panel_go<C, 128, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
             return panel_go<C, 64, XAXIS, EPI, TI, TO, 2>(in, out, T, n, np, nrows, inner, ntiles, alpha, st, guard);
         } else {
