@@ -292,12 +292,12 @@ static void xform_x_ct(int epi, dim3 grid, hipStream_t st, const double* in, dou
 bool xform_split_supported(int n) { return xform_panel_split_supported(n); }
 
 hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st, const int* guard, int sym) {
+                          long lines, double alpha, hipStream_t st, const int* guard, int sym, int io) {
     if (lines <= 0) return hipSuccess;
     if (epi < 0 || epi > 2 || prec < 0 || prec > 2) return hipErrorInvalidValue;
     if (xform_panel_supported(np))
-        return launch_xform_panel_x(prec, epi, in, out, T, n, np, lines, alpha, st, guard, sym);
-    if (sym) return hipErrorInvalidValue;
+        return launch_xform_panel_x_io(prec, epi, in, out, T, n, np, lines, alpha, st, guard, sym, io);
+    if (sym || io) return hipErrorInvalidValue;
     dim3 grid((unsigned)((lines + 63) / 64), (unsigned)((np + 127) / 128));
     if (prec == 0) xform_x_ct<double>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);
     else if (prec == 1) xform_x_ct<float>(epi, grid, st, in, out, T, n, np, lines, alpha, guard);

@@ -427,14 +427,34 @@ static hipError_t panel_pw(int sym, const TI* in, TO* out, const double* T, int 
     }
 }
 
+// io 0: double data; 2: float output (a forward transform's intermediate);
+// 1: float input (an inverse transform's intermediate); float data only in
+// the reduced precisions
 template <typename C>
-static hipError_t panel_x_epi(int sym, int epi, const double* in, double* out, const double* T, int n, int np,
-                              long lines, double alpha, hipStream_t st, const int* guard) {
+static hipError_t panel_x_epi(int sym, int epi, int io, const double* in, double* out, const double* T, int n,
+                              int np, long lines, double alpha, hipStream_t st, const int* guard) {
     const long ntiles = (lines + 15) / 16;
-    if (epi == 0) return panel_pw<C, true, 0>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
-    if (sym == 1) return hipErrorInvalidValue;
-    if (epi == 1) return panel_pw<C, true, 1>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
-    return panel_pw<C, true, 2>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    if (io == 0) {
+        if (epi == 0) return panel_pw<C, true, 0>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+        if (sym == 1) return hipErrorInvalidValue;
+        if (epi == 1) return panel_pw<C, true, 1>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+        return panel_pw<C, true, 2>(sym, in, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+    }
+    if constexpr (!std::is_same<C, PanelF64>::value) {
+        if (io == 2) {
+            if (epi != 0 || sym == 2) return hipErrorInvalidValue;
+            return panel_pw<C, true, 0, double, float>(sym, in, (float*)out, T, n, np, lines, 0, ntiles, alpha, st,
+                                                       guard);
+        }
+        if (io == 1) {
+            if (sym == 1) return hipErrorInvalidValue;
+            const float* fin = (const float*)in;
+            if (epi == 0) return panel_pw<C, true, 0, float, double>(sym, fin, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+            if (epi == 1) return panel_pw<C, true, 1, float, double>(sym, fin, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+            return panel_pw<C, true, 2, float, double>(sym, fin, out, T, n, np, lines, 0, ntiles, alpha, st, guard);
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 bool xform_panel_supported(int np) { return np >= 32 && np <= 256 && np % 32 == 0; }
@@ -445,12 +465,18 @@ bool xform_panel_f32_io(int np) { return xform_panel_supported(np); }
 
 hipError_t launch_xform_panel_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
                                 long lines, double alpha, hipStream_t st, const int* guard, int sym) {
+    return launch_xform_panel_x_io(prec, epi, in, out, T, n, np, lines, alpha, st, guard, sym, 0);
+}
+
+hipError_t launch_xform_panel_x_io(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
+                                   long lines, double alpha, hipStream_t st, const int* guard, int sym, int io) {
     if (lines <= 0) return hipSuccess;
-    if (!xform_panel_supported(np) || epi < 0 || epi > 2 || sym < 0 || sym > 2) return hipErrorInvalidValue;
+    if (!xform_panel_supported(np) || epi < 0 || epi > 2 || sym < 0 || sym > 2 || io < 0 || io > 2)
+        return hipErrorInvalidValue;
     if (sym != 0 && !(xform_panel_split_supported(n) && np == n)) return hipErrorInvalidValue;
-    if (prec == 0) return panel_x_epi<PanelF64>(sym, epi, in, out, T, n, np, lines, alpha, st, guard);
-    if (prec == 1) return panel_x_epi<PanelF32>(sym, epi, in, out, T, n, np, lines, alpha, st, guard);
-    if (prec == 2) return panel_x_epi<PanelBf16x3>(sym, epi, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 0) return panel_x_epi<PanelF64>(sym, epi, io, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 1) return panel_x_epi<PanelF32>(sym, epi, io, in, out, T, n, np, lines, alpha, st, guard);
+    if (prec == 2) return panel_x_epi<PanelBf16x3>(sym, epi, io, in, out, T, n, np, lines, alpha, st, guard);
     return hipErrorInvalidValue;
 }
 
@@ -467,13 +493,20 @@ static hipError_t panel_s_io(int sym, const double* in, double* out, const doubl
         return panel_pw<C, false, 0, float, double>(sym, (const float*)in, out, T, n, np, 0, inner, ntiles, 1.0, st,
                                                     guard);
     }
+    if (io_f32 == 3) {
+        // float on both sides (the intermediate of a reduced-precision transform)
+        if constexpr (!std::is_same<C, PanelF64>::value)
+            return panel_pw<C, false, 0, float, float>(sym, (const float*)in, (float*)out, T, n, np, 0, inner, ntiles,
+                                                       1.0, st, guard);
+        return hipErrorInvalidValue;
+    }
     return panel_pw<C, false, 0>(sym, in, out, T, n, np, 0, inner, ntiles, 1.0, st, guard);
 }
 
 hipError_t launch_xform_panel_s(int prec, const double* in, double* out, const double* T, int n, int np, long nbatch,
                                 long inner, hipStream_t st, const int* guard, int io_f32, int sym) {
     if (nbatch <= 0 || inner <= 0) return hipSuccess;
-    if (!xform_panel_supported(np) || io_f32 < 0 || io_f32 > 2 || sym < 0 || sym > 2) return hipErrorInvalidValue;
+    if (!xform_panel_supported(np) || io_f32 < 0 || io_f32 > 3 || sym < 0 || sym > 2) return hipErrorInvalidValue;
     if (sym != 0 && !(xform_panel_split_supported(n) && np == n)) return hipErrorInvalidValue;
     const long ntiles = nbatch * ((inner + 15) / 16);
     if (prec == 0) return panel_s_io<PanelF64>(sym, in, out, T, n, np, inner, ntiles, st, guard, io_f32);

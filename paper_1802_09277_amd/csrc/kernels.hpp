@@ -77,7 +77,13 @@ hipError_t launch_residual_norm(int dim, int Nt, int p, int n, const double* M1b
 // of length n.  EPI 0: store, 1: out += alpha*acc, 2: out = alpha*acc.
 // prec (sth_prec): 0 MFMA f64, 1 MFMA f32 (FP32 accumulation), 2 BF16x3.
 hipError_t launch_xform_x(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
-                          long lines, double alpha, hipStream_t st, const int* guard = nullptr, int sym = 0);
+                          long lines, double alpha, hipStream_t st, const int* guard = nullptr, int sym = 0,
+                          int io = 0);
+// the panel form of launch_xform_x with float data on one side (reduced
+// precisions, np <= 256): io 2 writes float output (the intermediate of a
+// forward transform), 1 reads float input (that of an inverse transform)
+hipError_t launch_xform_panel_x_io(int prec, int epi, const double* in, double* out, const double* T, int n, int np,
+                                   long lines, double alpha, hipStream_t st, const int* guard, int sym, int io);
 
 // Strided axis: in[b][k][i] (k stride `inner`), out[b][j][i] = sum_k T[k][j] in[b][k][i].
 hipError_t launch_xform_s(int prec, const double* in, double* out, const double* T, int n, int np,
@@ -89,8 +95,8 @@ hipError_t launch_xform_s(int prec, const double* in, double* out, const double*
 bool xform_split_supported(int n);
 // (both per-axis launchers: every block returns at once when guard is given
 // and *guard == 0, as in the guards of speculative cycles; launch_xform_s
-// with io_f32 2 writes float output, 1 reads float input, for np <= 256 a
-// multiple of 32: xform_panel_f32_io(np))
+// with io_f32 2 writes float output, 1 reads float input, 3 both (reduced
+// precisions), for np <= 256 a multiple of 32: xform_panel_f32_io(np))
 bool xform_panel_f32_io(int np);
 
 // Both spatial axes of 2-D images (n x n each, nimg images, image i at

@@ -344,12 +344,14 @@ static int split_of(const sth_handle* h, const double* T) {
 
 // per-axis transforms in the precision `prec` (sth_prec); the split forms
 // take n / 2 multiply-adds per output instead of n
+// io (reduced precisions): 2 float output, 1 float input
 static int xform_x(sth_handle* h, int prec, int epi, const double* in, double* out, const double* T, long lines,
-                   double alpha, hipStream_t st, const int* guard = nullptr) {
+                   double alpha, hipStream_t st, const int* guard = nullptr, int io = 0) {
     const double dof = (double)lines * h->n;
     const int sym = split_of(h, T);
-    Timed tm(h, STH_K_XFORM_X, (sym ? 1.0 : 2.0) * h->n * dof, dof * (epi == 1 ? 24.0 : 16.0), st);
-    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st, guard, sym));
+    Timed tm(h, STH_K_XFORM_X, (sym ? 1.0 : 2.0) * h->n * dof, dof * ((epi == 1 ? 24.0 : 16.0) - (io ? 4.0 : 0.0)),
+             st);
+    HIPCHK(launch_xform_x(prec, epi, in, out, T, h->n, h->np, lines, alpha, st, guard, sym, io));
     return STH_OK;
 }
 
@@ -357,7 +359,7 @@ static int xform_s(sth_handle* h, int prec, const double* in, double* out, const
                    long inner, hipStream_t st, const int* guard = nullptr, int io_f32 = 0) {
     const double dof = (double)nbatch * h->n * inner;
     const int sym = split_of(h, T);
-    Timed tm(h, STH_K_XFORM_S, (sym ? 1.0 : 2.0) * h->n * dof, (io_f32 ? 12.0 : 16.0) * dof, st);
+    Timed tm(h, STH_K_XFORM_S, (sym ? 1.0 : 2.0) * h->n * dof, (io_f32 == 3 ? 8.0 : (io_f32 ? 12.0 : 16.0)) * dof, st);
     HIPCHK(launch_xform_s(prec, in, out, T, h->n, h->np, nbatch, inner, st, guard, io_f32, sym));
     return STH_OK;
 }
@@ -745,12 +747,15 @@ static int spatial_apply(sth_handle* h, SpatialKind kind, const double* in, doub
     const int* g = guard;
     int rc;
     if (h->dim == 2) {
+        // float eigenbasis data with reduced-precision transforms: the
+        // intermediate between the two axes is float as well
+        const bool fmid = io_f32 != 0 && prec != STH_FP64;
         if (fwd || (epi == 0 && io_f32 == 0)) {
-            if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n, 1.0, st, g))) return rc;
-            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st, g, io_f32))) return rc;
+            if ((rc = xform_x(h, prec, 0, in, tmp, T, rows * n, 1.0, st, g, fmid ? 2 : 0))) return rc;
+            if ((rc = xform_s(h, prec, tmp, out, T, rows, n, st, g, fmid ? 3 : io_f32))) return rc;
         } else {
-            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st, g, io_f32))) return rc;
-            if ((rc = xform_x(h, prec, epi, tmp, out, T, rows * n, 1.0, st, g))) return rc;
+            if ((rc = xform_s(h, prec, in, tmp, T, rows, n, st, g, fmid ? 3 : io_f32))) return rc;
+            if ((rc = xform_x(h, prec, epi, tmp, out, T, rows * n, 1.0, st, g, fmid ? 1 : 0))) return rc;
         }
     } else if (epi == 0 && io_f32 == 0) {
         if ((rc = xform_x(h, prec, 0, in, out, T, rows * n * n, 1.0, st, g))) return rc;   // x
